@@ -1,0 +1,200 @@
+"""BiCGSTAB with the block-diagonal right preconditioner (Sec. II-B).
+
+Test infrastructure (see ``oracle/__init__``).
+
+The outer solve is BiCGSTAB (van der Vorst, ref. [18] of the paper) applied
+to the right-preconditioned system A K2^{-1} (K2 x) = b, K1 = I, as the
+paper states in Sec. II-B; each iteration needs the two extra solves
+y = K2^{-1} p and z = K2^{-1} s.  K2 is the block-diagonal part of A for a
+partition of the scatterer into geometric blocks (eq. (10)); every block
+matrix A_k keeps all x/y/z couplings (eq. (11)) and is itself solved by
+BiCGSTAB with FFT products to a loose ("softened") tolerance.  The block
+solutions are written back into one vector for the outer iteration.
+
+Readings where the paper is silent (listed in the design doc):
+
+* inner products are conjugated in the first argument; the shadow vector is
+  the initial residual; x0 = 0 for the outer and for every inner solve;
+* stopping uses the recursive residual, ||r|| / ||b|| in the 2-norm, and is
+  also tested after the half step (s);
+* an inner solve that reaches its iteration cap (or breaks down) returns its
+  last iterate; a block whose right-hand side is zero returns zero;
+* one "step" is one pass of the loop below.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional
+
+import numpy as np
+import scipy.linalg
+
+from .operator import FFTOperator, Grid, dense_matrix, from_support, to_support
+
+
+@dataclasses.dataclass
+class KrylovInfo:
+    iterations: int = 0
+    status: str = "not_converged"     # converged | not_converged | breakdown
+    relres: float = float("nan")
+    history: List[float] = dataclasses.field(default_factory=list)
+    half_step: bool = False
+
+
+def _dot(a, b) -> complex:
+    """<a, b> = sum conj(a) b."""
+    return complex(np.vdot(a.ravel(), b.ravel()))
+
+
+def _norm(a) -> float:
+    return float(np.linalg.norm(a.ravel()))
+
+
+def bicgstab(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float,
+             maxit: int, precond: Optional[Callable[[np.ndarray], np.ndarray]] = None):
+    """Right-preconditioned BiCGSTAB; returns (x, KrylovInfo).
+
+    With ``precond`` None the preconditioner is the identity.
+    """
+    M = precond if precond is not None else (lambda w: w)
+    x = np.zeros_like(b)
+    r = b.copy()
+    rhat = r.copy()
+    nb = _norm(b)
+    info = KrylovInfo()
+    if nb == 0.0:
+        info.status, info.relres = "converged", 0.0
+        return x, info
+    rho_old = alpha = omega = 1.0 + 0.0j
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    for it in range(1, maxit + 1):
+        info.iterations = it
+        rho = _dot(rhat, r)
+        if rho == 0:
+            info.status = "breakdown"
+            break
+        if it == 1:
+            p = r.copy()
+        else:
+            beta = (rho / rho_old) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+        y = M(p)
+        v = apply_A(y)
+        den = _dot(rhat, v)
+        if den == 0:
+            info.status = "breakdown"
+            break
+        alpha = rho / den
+        s = r - alpha * v
+        ns = _norm(s) / nb
+        if ns <= tol:
+            x = x + alpha * y
+            info.status, info.relres, info.half_step = "converged", ns, True
+            info.history.append(ns)
+            return x, info
+        z = M(s)
+        t = apply_A(z)
+        tt = _dot(t, t)
+        if tt == 0:
+            info.status = "breakdown"
+            break
+        omega = _dot(t, s) / tt
+        x = x + alpha * y + omega * z
+        r = s - omega * t
+        nr = _norm(r) / nb
+        info.history.append(nr)
+        info.relres = nr
+        if nr <= tol:
+            info.status = "converged"
+            return x, info
+        if omega == 0:
+            info.status = "breakdown"
+            break
+        rho_old = rho
+    return x, info
+
+
+@dataclasses.dataclass
+class _Block:
+    index: int
+    sl: tuple                  # slices (z, y, x) of the bounding box
+    member: np.ndarray         # bool [bz, by, bx]
+    op: FFTOperator
+
+
+class BlockPreconditioner:
+    """y = K2^{-1} w with K2 = blockdiag(A_1, ..., A_N) (eq. (10)).
+
+    Block k is the set of voxels with ``block_id == k``.  Its matrix A_k is
+    A restricted to those voxels, applied with the FFT product on the block's
+    bounding box with every other voxel masked as vacuum.
+    """
+
+    def __init__(self, grid: Grid, block_id: np.ndarray, n_blocks: int, tol: float, maxit: int):
+        self.tol = tol
+        self.maxit = maxit
+        self.blocks: List[_Block] = []
+        self.inner_counts: List[List[int]] = []
+        for k in range(n_blocks):
+            kk, jj, ii = np.nonzero(block_id == k)
+            if ii.size == 0:
+                continue
+            sl = (slice(kk.min(), kk.max() + 1), slice(jj.min(), jj.max() + 1),
+                  slice(ii.min(), ii.max() + 1))
+            member = block_id[sl] == k
+            sub_eps = np.where(member, grid.eps[sl], 1.0 + 0.0j)
+            sub = Grid(sub_eps.shape[2], sub_eps.shape[1], sub_eps.shape[0],
+                       grid.dx, grid.dy, grid.dz, grid.wavelength, sub_eps)
+            self.blocks.append(_Block(k, sl, member, FFTOperator(sub)))
+
+    def __call__(self, w: np.ndarray) -> np.ndarray:
+        y = np.zeros_like(w)
+        counts = []
+        for blk in self.blocks:
+            bk = w[(slice(None),) + blk.sl] * blk.member
+            if _norm(bk) == 0.0:
+                counts.append(0)
+                continue
+            yk, info = bicgstab(blk.op, bk, self.tol, self.maxit)
+            y[(slice(None),) + blk.sl] += yk * blk.member
+            counts.append(info.iterations)
+        self.inner_counts.append(counts)
+        return y
+
+
+@dataclasses.dataclass
+class Solution:
+    P: np.ndarray              # [3, nz, ny, nx], P = J / (j omega eps0)
+    E_tot: np.ndarray          # P / chi on S, 0 in vacuum (eq. (2))
+    info: KrylovInfo
+    inner_counts: List[List[int]]
+
+
+def masked_rhs(grid: Grid, e_inc: np.ndarray) -> np.ndarray:
+    return e_inc * grid.mask
+
+
+def total_field(grid: Grid, P: np.ndarray) -> np.ndarray:
+    return P * grid.chi_inv
+
+
+def solve(grid: Grid, e_inc: np.ndarray, tol_outer: float, maxit_outer: int = 1000,
+          block_id: Optional[np.ndarray] = None, n_blocks: int = 0,
+          tol_inner: float = 1e-2, maxit_inner: int = 500) -> Solution:
+    """Solve A P = E_inc on S; block preconditioner if ``block_id`` is given."""
+    A = FFTOperator(grid)
+    b = masked_rhs(grid, e_inc)
+    pre = None
+    if block_id is not None:
+        pre = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner)
+    P, info = bicgstab(A, b, tol_outer, maxit_outer, pre)
+    return Solution(P, total_field(grid, P), info, pre.inner_counts if pre is not None else [])
+
+
+def solve_dense(grid: Grid, e_inc: np.ndarray) -> np.ndarray:
+    """Reference solution of A P = E_inc by dense LU (tiny grids only)."""
+    Z, idx = dense_matrix(grid)
+    b = to_support(grid, masked_rhs(grid, e_inc), idx)
+    x = scipy.linalg.solve(Z, b)
+    return from_support(grid, x, idx)

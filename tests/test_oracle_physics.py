@@ -1,0 +1,137 @@
+"""Physical pins of the oracle (Sec. III).
+
+* Mie series: the textbook worked example (golden file), the Rayleigh
+  limit, the optical theorem and angular integration of |S1|^2 + |S2|^2.
+* The VIE solution of a voxelised sphere agrees with the Mie series
+  (Sec. III, Figs. 1-2: dielectric eps 2.25 and metal eps -1.05 - j5.62),
+  within a stated discretisation tolerance that shrinks with refinement.
+* Power balance P_ext = P_abs + P_sca holds for the discrete solution; the
+  scattering term computed from Im(T) equals an independent far-field
+  quadrature of the radiated power.
+* Mirror symmetries of the field in a symmetric cube under x-polarised
+  normal incidence.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import krylov, operator as op, physics
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_mie_textbook_example():
+    ref = json.load(open(os.path.join(GOLDEN, "mie_bohren_huffman.json")))
+    x = 2 * np.pi * ref["radius"] / ref["wavelength"]
+    m = complex(*ref["m"])
+    qext, qsca = physics.mie_efficiencies(m, x)
+    assert round(qext, 5) == pytest.approx(ref["qext"], abs=1.5e-5)
+    assert round(qsca, 5) == pytest.approx(ref["qsca"], abs=1.5e-5)
+    a, b = physics.mie_coefficients(m, x)
+    n = np.arange(1, a.size + 1)
+    qback = abs(np.sum((2 * n + 1) * (-1.0) ** n * (a - b))) ** 2 / x ** 2
+    assert qback == pytest.approx(ref["qback"], abs=1.5e-5)
+
+
+@pytest.mark.parametrize("m", [1.5 + 0.1j, 2.0 + 0.0j, 0.3 + 2.4j])
+def test_mie_rayleigh_limit(m):
+    x = 1e-2
+    qext, qsca = physics.mie_efficiencies(m, x)
+    K = (m * m - 1) / (m * m + 2)
+    assert qsca == pytest.approx(8 / 3 * x ** 4 * abs(K) ** 2, rel=1e-3)
+    assert qext - qsca == pytest.approx(4 * x * K.imag, rel=1e-3, abs=1e-12)
+
+
+@pytest.mark.parametrize("m,x", [(1.5 + 0.0j, 1.3), (0.4 + 2.3j, 1.26), (1.33 + 0.01j, 4.0)])
+def test_mie_optical_theorem_and_angular_integral(m, x):
+    qext, qsca = physics.mie_efficiencies(m, x)
+    S1, S2 = physics.mie_amplitudes(m, x, np.array([0.0]))
+    assert S1[0] == pytest.approx(S2[0], rel=1e-12)
+    assert qext == pytest.approx(4 / x ** 2 * S1[0].real, rel=1e-10)
+    mu, w = np.polynomial.legendre.leggauss(200)
+    S1, S2 = physics.mie_amplitudes(m, x, np.arccos(mu))
+    # C_sca = (pi / k^2) int (|S1|^2 + |S2|^2) d(mu) ; Q = C / (pi a^2)
+    qsca_int = np.sum(w * (np.abs(S1) ** 2 + np.abs(S2) ** 2)) / x ** 2
+    assert qsca_int == pytest.approx(qsca, rel=1e-9)
+    if m.imag == 0:
+        assert qext == pytest.approx(qsca, rel=1e-10)
+
+
+def _solve_sphere(r, eps, tol=1e-10):
+    lam = r * 40 / 8          # fixed size parameter k a = 2 pi / 5
+    case = W.sphere(r, lam, eps)
+    g = op.Grid.from_case(case)
+    e = physics.plane_wave(g)
+    s = krylov.solve(g, e, tol, 3000)
+    assert s.info.status == "converged"
+    return case, g, e, s, lam
+
+
+def _mie_errors(r, eps):
+    case, g, e, s, lam = _solve_sphere(r, eps)
+    se, sa, ss = physics.cross_sections(g, s.P, e)
+    m = np.sqrt(np.conj(eps))
+    qe, qs = physics.mie_efficiencies(m, 2 * np.pi * r / lam)
+    area = np.pi * r * r
+    th = np.radians(np.arange(0, 181))
+    rv = physics.rcs_eplane(g, s.P, th)
+    rm = physics.mie_rcs_eplane(eps, r, lam, th)
+    return (abs(se / area - qe) / qe, abs(ss / area - qs) / qs,
+            np.linalg.norm(rv - rm) / np.linalg.norm(rm))
+
+
+@pytest.mark.parametrize("eps,tol_q,tol_rcs", [(2.25, 0.05, 0.05), (-1.05 - 5.62j, 0.10, 0.10)])
+def test_vie_sphere_matches_mie(eps, tol_q, tol_rcs):
+    """Sphere of radius 8 voxels at lambda = 40 voxels (k a = 1.257)."""
+    eq_ext, eq_sca, e_rcs = _mie_errors(8, eps)
+    assert eq_ext <= tol_q and eq_sca <= tol_q and e_rcs <= tol_rcs
+
+
+@pytest.mark.parametrize("eps,tol_fine", [(2.25, 0.02), (-1.05 - 5.62j, 0.05)])
+def test_vie_sphere_converges_to_mie(eps, tol_fine):
+    """Refining 6 -> 8 -> 12 voxels per radius at fixed k a: the finest grid
+    has the smallest E-plane RCS error and is within ``tol_fine``."""
+    errs = [_mie_errors(r, eps)[2] for r in (6, 8, 12)]
+    assert errs[2] < errs[0] and errs[2] < errs[1]
+    assert errs[2] <= tol_fine
+
+
+@pytest.mark.parametrize("eps", [2.25, 4.0 - 1.0j])
+def test_power_balance_and_far_field(eps):
+    case, g, e, s, lam = _solve_sphere(5, eps, tol=1e-12)
+    ext, absn, sca = physics.power_terms(g, s.P, e)
+    assert abs(ext - absn - sca) <= 1e-9 * abs(ext)
+    if np.imag(eps) == 0:
+        assert absn == 0.0
+    else:
+        assert absn > 0
+    assert sca > 0
+    far = physics.scattered_power_far(g, s.P)
+    # point-sampled far field vs Im(T) with the finite-sphere self term:
+    # differ by O((k0 a)^2) of the self part only
+    assert abs(far - sca) <= 1e-3 * sca
+
+
+def test_lossy_materials_of_the_cases_absorb():
+    """The loss signs chosen for the plasmonic case absorb power (P_abs > 0)."""
+    for eps in (3.0 - 0.3j, -15.0 - 1.0j, 12.0 - 0.5j):
+        chi_inv = 1.0 / (eps - 1.0)
+        assert chi_inv.imag > 0
+
+
+def test_cube_mirror_symmetries():
+    n = 8
+    g = op.Grid(n, n, n, 0.05, 0.05, 0.05, 1.0, np.full((n, n, n), 4.0 + 0j))
+    e = physics.plane_wave(g)
+    s = krylov.solve(g, e, 1e-12, 500)
+    P = s.P
+    Py = np.flip(P, axis=2)      # y -> -y  (array axes: comp, z, y, x)
+    Px = np.flip(P, axis=3)      # x -> -x
+    sc = np.abs(P).max()
+    assert np.allclose(Py[0], P[0], atol=1e-9 * sc) and np.allclose(Py[2], P[2], atol=1e-9 * sc)
+    assert np.allclose(Py[1], -P[1], atol=1e-9 * sc)
+    assert np.allclose(Px[0], P[0], atol=1e-9 * sc)
+    assert np.allclose(Px[1], -P[1], atol=1e-9 * sc) and np.allclose(Px[2], -P[2], atol=1e-9 * sc)

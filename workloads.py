@@ -1,0 +1,278 @@
+"""Seeded synthetic inputs for the block-preconditioned VIE-FFT solver.
+
+This module builds problem *inputs* only: a voxel grid, the relative
+permittivity of every voxel, the partition of the scatterer into blocks and
+the solver settings of each benchmark case.  It holds none of the method's
+arithmetic (no Green's function, no FFT, no Krylov step) and imports nothing
+from the oracle or from the GPU package, so both sides can take their inputs
+from it.
+
+Conventions (shared by both sides):
+
+* arrays are indexed ``[z, y, x]`` (x fastest in memory);
+* voxel ``(i, j, k)`` has its centre at ``((i+1/2)dx, (j+1/2)dy, (k+1/2)dz)``
+  measured from the grid corner; a voxel belongs to an object iff its centre
+  lies inside the object, boundary included (staircase approximation of the
+  paper's uniform hexahedral mesh, Sec. II-A);
+* the paper writes fields with the ``exp(+j omega t)`` convention, so a lossy
+  permittivity has a *negative* imaginary part (the metal of Fig. 2 is
+  -1.05 - j5.62);
+* ``block_id`` is ``-1`` on vacuum voxels and in ``[0, n_blocks)`` elsewhere;
+  blocks partition the non-vacuum voxels (Sec. II-B, eq. (10)).
+
+Cases (each is a synthetic stand-in shaped like a structure of Sec. III; the
+paper's own geometries depend on figures and data that are not published):
+
+* ``cube16``       dielectric cube, 16^3, lambda/20, 2x2x2 blocks, FP64.
+* ``metasurface``  8x8 nanopillars on a slab, 128x128x32, lambda/40.
+* ``plasmonic``    4x4 metal spheres in an absorbing layer over a slab,
+                   96x96x64, lambda/40.
+* ``sweep``        64 independent pillar/sphere solves of assorted grids.
+* ``sphere``       voxelised sphere for the Mie comparison (Sec. III).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Case", "cube16", "metasurface", "plasmonic", "sweep_case", "sweep",
+    "sphere", "random_tiny", "CASES", "by_name",
+]
+
+
+@dataclasses.dataclass
+class Case:
+    """One solve: grid, materials, partition, excitation and tolerances."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    wavelength: float
+    eps: np.ndarray            # complex128 [nz, ny, nx]
+    block_id: np.ndarray       # int32 [nz, ny, nx], -1 on vacuum
+    n_blocks: int
+    tol_outer: float
+    tol_inner: float
+    maxit_outer: int = 1000
+    maxit_inner: int = 500
+    precision: str = "fp64"    # "fp64" or "mixed"
+    kdir: Tuple[float, float, float] = (0.0, 0.0, 1.0)
+    pol: Tuple[complex, complex, complex] = (1.0, 0.0, 0.0)
+    note: str = ""
+
+    @property
+    def nvox(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        return (self.nz, self.ny, self.nx)
+
+    def unpartitioned(self) -> "Case":
+        """The same case with every non-vacuum voxel in a single block."""
+        bid = np.where(self.block_id >= 0, 0, -1).astype(np.int32)
+        return dataclasses.replace(self, block_id=bid, n_blocks=1)
+
+
+def _centres(n: int) -> np.ndarray:
+    """Voxel-centre coordinates in units of the spacing, from the corner."""
+    return np.arange(n, dtype=np.float64) + 0.5
+
+
+def cube16() -> Case:
+    """Dielectric cube, eps_r = 4, filling a 16^3 grid at lambda/20.
+
+    Blocks: 2x2x2 equal octants, id = [i>=8] + 2[j>=8] + 4[k>=8].
+    """
+    n = 16
+    eps = np.full((n, n, n), 4.0 + 0.0j, dtype=np.complex128)
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    bid = ((i >= 8).astype(np.int32) + 2 * (j >= 8) + 4 * (k >= 8)).astype(np.int32)
+    lam = 1.0
+    d = lam / 20.0
+    return Case("cube16", n, n, n, d, d, d, lam, eps, bid, 8,
+                tol_outer=1e-6, tol_inner=1e-3, precision="fp64",
+                note="dielectric cube eps 4, 16^3 at lambda/20, 8 blocks")
+
+
+def metasurface() -> Case:
+    """8x8 cylindrical pillars (eps 5.8) on a slab (eps 2.25), 128x128x32.
+
+    Spacing lambda/40.  Slab occupies z-voxels [0, 8); pillars z-voxels
+    [8, 32).  Cell (ix, iy) is 16x16 voxels with centre (16 ix + 8, 16 iy + 8)
+    in voxel units; its radius is ``default_rng(2).uniform(0.1, 0.2, (8, 8))
+    [iy, ix]`` wavelengths.  Blocks: pillar (ix, iy) -> id 8*iy + ix, slab ->
+    64.
+    """
+    nx, ny, nz = 128, 128, 32
+    lam = 1.0
+    d = lam / 40.0
+    radii = np.random.default_rng(2).uniform(0.1, 0.2, (8, 8))  # [iy, ix], wavelengths
+    eps = np.ones((nz, ny, nx), dtype=np.complex128)
+    bid = np.full((nz, ny, nx), -1, dtype=np.int32)
+    eps[0:8] = 2.25
+    bid[0:8] = 64
+    xc = _centres(nx)
+    yc = _centres(ny)
+    for iy in range(8):
+        for ix in range(8):
+            r_vox = radii[iy, ix] * lam / d
+            cx, cy = 16 * ix + 8.0, 16 * iy + 8.0
+            inside = ((xc[None, :] - cx) ** 2 + (yc[:, None] - cy) ** 2) <= r_vox ** 2
+            eps[8:32][:, inside] = 5.8
+            bid[8:32][:, inside] = 8 * iy + ix
+    return Case("metasurface", nx, ny, nz, d, d, d, lam, eps, bid, 65,
+                tol_outer=1e-5, tol_inner=1e-2, precision="mixed",
+                note="8x8 pillars eps 5.8 on slab eps 2.25, 128x128x32 at lambda/40, 65 blocks")
+
+
+def plasmonic() -> Case:
+    """Metal spheres in an absorbing layer over a lossy slab, 96x96x64.
+
+    Spacing lambda/40.  Slab z-voxels [0, 24): eps 12 - 0.5j.  Layer z-voxels
+    [24, 64): eps 3.0 - 0.3j.  4x4 spheres, eps -15 - 1.0j, centre
+    (24 ix + 12, 24 iy + 12, 44) voxel units, radius
+    ``default_rng(3).integers(6, 11, (4, 4))[iy, ix]`` voxels.  The lossy
+    values are the conjugates of ``3.0+0.3i``, ``-15+1.0i``, ``12+0.5i`` so
+    that they are lossy in the paper's exp(+j omega t) convention.
+    Blocks: sphere (ix, iy) -> 4*iy + ix, layer (minus spheres) -> 16,
+    slab -> 17.
+    """
+    nx, ny, nz = 96, 96, 64
+    lam = 1.0
+    d = lam / 40.0
+    radii = np.random.default_rng(3).integers(6, 11, (4, 4))
+    eps = np.ones((nz, ny, nx), dtype=np.complex128)
+    bid = np.full((nz, ny, nx), -1, dtype=np.int32)
+    eps[0:24] = 12.0 - 0.5j
+    bid[0:24] = 17
+    eps[24:64] = 3.0 - 0.3j
+    bid[24:64] = 16
+    zc, yc, xc = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    for iy in range(4):
+        for ix in range(4):
+            cx, cy, cz = 24 * ix + 12.0, 24 * iy + 12.0, 44.0
+            r = float(radii[iy, ix])
+            inside = (xc - cx) ** 2 + (yc - cy) ** 2 + (zc - cz) ** 2 <= r * r
+            eps[inside] = -15.0 - 1.0j
+            bid[inside] = 4 * iy + ix
+    return Case("plasmonic", nx, ny, nz, d, d, d, lam, eps, bid, 18,
+                tol_outer=1e-6, tol_inner=3e-2, precision="mixed",
+                note="4x4 metal spheres in absorbing layer over slab, 96x96x64 at lambda/40, 18 blocks")
+
+
+SWEEP_GRIDS = [(32, 32, 32), (48, 48, 48), (64, 64, 32), (96, 96, 32)]
+
+
+def sweep_case(b: int) -> Case:
+    """Solve ``b`` (0..63) of the batched sweep.
+
+    ``rng = default_rng(4000 + b)``; draws in this order: grid index
+    ``rng.integers(4)`` into (32^3, 48^3, 64x64x32, 96x96x32); wavelength
+    ``rng.uniform(400, 800)`` nm with spacing 20 nm; kind ``rng.integers(2)``
+    (0 pillars, 1 spheres).  Objects sit on a 16x16-voxel xy lattice, visited
+    row by row (iy outer, ix inner).  Per object: eps ``rng.uniform(2, 6)``;
+    pillars: radius ``rng.uniform(0.25, 0.45) * 16`` voxels, then height
+    ``rng.uniform(0.5, 1) * nz`` voxels from z = 0; spheres: radius
+    ``rng.uniform(0.25, 0.45) * min(16, nz)`` voxels, centre at z = nz/2.
+    One block per object.
+    """
+    rng = np.random.default_rng(4000 + b)
+    nx, ny, nz = SWEEP_GRIDS[int(rng.integers(4))]
+    lam = float(rng.uniform(400.0, 800.0))
+    kind = int(rng.integers(2))
+    d = 20.0
+    eps = np.ones((nz, ny, nx), dtype=np.complex128)
+    bid = np.full((nz, ny, nx), -1, dtype=np.int32)
+    zc, yc, xc = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    nb = 0
+    for iy in range(ny // 16):
+        for ix in range(nx // 16):
+            e = float(rng.uniform(2.0, 6.0))
+            cx, cy = 16 * ix + 8.0, 16 * iy + 8.0
+            if kind == 0:
+                r = float(rng.uniform(0.25, 0.45)) * 16.0
+                h = float(rng.uniform(0.5, 1.0)) * nz
+                inside = ((xc - cx) ** 2 + (yc - cy) ** 2 <= r * r) & (zc <= h)
+            else:
+                r = float(rng.uniform(0.25, 0.45)) * min(16, nz)
+                cz = nz / 2.0
+                inside = (xc - cx) ** 2 + (yc - cy) ** 2 + (zc - cz) ** 2 <= r * r
+            eps[inside] = e
+            bid[inside] = nb
+            nb += 1
+    return Case(f"sweep{b}", nx, ny, nz, d, d, d, lam, eps, bid, nb,
+                tol_outer=1e-6, tol_inner=1e-2, precision="mixed",
+                note=f"sweep solve {b}: {'pillars' if kind == 0 else 'spheres'} {nx}x{ny}x{nz}, lambda {lam:.1f} nm")
+
+
+def sweep(n: int = 64) -> List[Case]:
+    return [sweep_case(b) for b in range(n)]
+
+
+def sphere(radius_vox: int, wavelength_vox: float, eps_r: complex,
+           pad: int = 0) -> Case:
+    """Voxelised sphere of ``radius_vox`` voxels, spacing 1, centred in the grid.
+
+    The grid is ``2*radius_vox + 2*pad`` voxels per side; the sphere centre is
+    the grid centre.  A single block holds the whole sphere.
+    """
+    n = 2 * radius_vox + 2 * pad
+    c = n / 2.0
+    zc, yc, xc = np.meshgrid(_centres(n), _centres(n), _centres(n), indexing="ij")
+    inside = (xc - c) ** 2 + (yc - c) ** 2 + (zc - c) ** 2 <= radius_vox ** 2
+    eps = np.where(inside, complex(eps_r), 1.0 + 0.0j).astype(np.complex128)
+    bid = np.where(inside, 0, -1).astype(np.int32)
+    return Case(f"sphere_r{radius_vox}", n, n, n, 1.0, 1.0, 1.0, float(wavelength_vox),
+                eps, bid, 1, tol_outer=1e-10, tol_inner=1e-2, precision="fp64",
+                note=f"voxelised sphere radius {radius_vox} voxels, lambda {wavelength_vox} voxels, eps {eps_r}")
+
+
+def random_tiny(seed: int, shape: Tuple[int, int, int], fill: float = 0.7,
+                spacing: Optional[Tuple[float, float, float]] = None,
+                wavelength: float = 1.0, n_blocks: int = 2, lossy: bool = True) -> Case:
+    """Random small problem: random mask, random complex eps, random blocks.
+
+    ``rng = default_rng(seed)``; draws in order: spacing (if not given)
+    ``rng.uniform(0.03, 0.08, 3)`` wavelengths; mask ``rng.random(shape) <
+    fill``; eps real part ``rng.uniform(1.5, 6, shape)``; eps imaginary part
+    ``-rng.uniform(0, 0.5, shape)`` if ``lossy`` (else 0); block id
+    ``rng.integers(n_blocks, size=shape)``.  Blocks are re-numbered so every
+    id in ``[0, n_blocks')`` is used.
+    """
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    if spacing is None:
+        spacing = tuple(float(v) for v in rng.uniform(0.03, 0.08, 3))
+    mask = rng.random(shape) < fill
+    er = rng.uniform(1.5, 6.0, shape)
+    ei = -rng.uniform(0.0, 0.5, shape) if lossy else np.zeros(shape)
+    raw_bid = rng.integers(n_blocks, size=shape)
+    eps = np.where(mask, er + 1j * ei, 1.0 + 0.0j).astype(np.complex128)
+    used = sorted(set(int(v) for v in raw_bid[mask]))
+    remap = {v: i for i, v in enumerate(used)}
+    bid = np.full(shape, -1, dtype=np.int32)
+    for v, i in remap.items():
+        bid[mask & (raw_bid == v)] = i
+    dx, dy, dz = spacing
+    return Case(f"tiny{seed}_{nx}x{ny}x{nz}", nx, ny, nz, dx, dy, dz, wavelength, eps, bid,
+                max(len(used), 0), tol_outer=1e-10, tol_inner=1e-2, precision="fp64",
+                note="random tiny problem")
+
+
+CASES = {"cube16": cube16, "metasurface": metasurface, "plasmonic": plasmonic}
+
+
+def by_name(name: str) -> Case:
+    if name in CASES:
+        return CASES[name]()
+    if name.startswith("sweep"):
+        return sweep_case(int(name[5:]))
+    raise KeyError(name)
