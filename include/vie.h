@@ -1,0 +1,193 @@
+/*
+ * libvie — block-preconditioned VIE-FFT solver on one AMD Instinct MI355X.
+ *
+ * Solves the volume integral equation of Huang & Sha, "A Parallel Block
+ * Preconditioner Based VIE-FFT Algorithm for Modeling Electromagnetic
+ * Response from Nanostructures" (arXiv 2501.13512), Sec. II:
+ *
+ *   eq. (2)  E_tot = J / (j omega (eps - eps0))
+ *   eq. (3)  E_tot = E_inc + E_s,   E_s from eq. (1) with the dyadic
+ *            Green's function G = (I + grad grad / k0^2) g,
+ *            g = exp(-j k0 R) / (4 pi R)   (exp(+j omega t) convention)
+ *   eq. (4)  the resulting equation for J, discretised on a uniform voxel
+ *            grid into the 3x3-block system A x = b of eq. (6).
+ *
+ * The library works with P = J / (j omega eps0) (same Krylov iterates as J
+ * up to a constant), so with chi = eps_r - 1 and S = non-vacuum voxels:
+ *   (A P)_m = P_m / chi_m - sum_{n in S} T(m - n) P_n = E_inc(r_m),  m in S,
+ * T(m) = k0^2 dV G(r_m - r_0) for m != 0 (voxel-centre sampling), and for
+ * m = 0 the integral of k0^2 G over the sphere of the voxel's volume.  The
+ * product A x is the paper's FFT acceleration (Sec. I: Toeplitz structure of
+ * the uniform grid, zero-padded 3-D FFT).  The system is solved by BiCGSTAB
+ * (Sec. II-B) with the block-diagonal right preconditioner of eq. (10): the
+ * scatterer is partitioned into blocks, each block matrix A_k (all x/y/z
+ * couplings, eq. (11)) is solved by an inner BiCGSTAB-FFT to a loose
+ * tolerance, and the block solutions are merged into one vector.
+ *
+ * Conventions
+ *  - Fields and currents are complex double, interleaved (re, im), stored
+ *    component-major [3][nz][ny][nx] with x fastest (same bytes as
+ *    C99 double _Complex and torch.complex128).
+ *  - Voxel (i, j, k) has its centre at ((i+1/2)dx, (j+1/2)dy, (k+1/2)dz)
+ *    from the grid corner; phases are referred to the grid centre.
+ *  - eps_r == 1 (exactly) marks vacuum: no unknown there, outputs are 0.
+ *  - Lossy media have Im(eps_r) < 0 (exp(+j omega t)).
+ *  - Length units are arbitrary but common to spacing and wavelength;
+ *    k0 = 2 pi / wavelength.
+ *  - Grid sizes: 1 <= n <= 256 per axis (FFT lengths up to 512).
+ *
+ * Errors: every call returns vie_status.  0 = success, > 0 = warning with
+ * results written, < 0 = error.  vie_last_error() gives a message for the
+ * calling thread's last non-OK status.  No C++ exception crosses this ABI.
+ *
+ * Ownership: handles are created and freed by the library (matching
+ * _create/_destroy).  Host arrays passed in are owned by the caller and only
+ * read during the call.  Device pointers ("_dev") are borrowed for the call:
+ * they must be device memory of the context's GPU, are accessed in order on
+ * the given HIP stream (hipStream_t passed as void*, NULL = default stream),
+ * and must stay valid until that stream reaches the end of the call's work.
+ * Calls on one problem are serialised by the library; a problem holds the
+ * Krylov state of one solve at a time.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VIE_ABI_VERSION 1
+
+typedef enum {
+  VIE_OK = 0,
+  VIE_NOT_CONVERGED = 1,   /* iteration cap reached; best iterate and stats written */
+  VIE_EINVAL = -1,         /* invalid argument (sizes, non-finite values, block ids, ...) */
+  VIE_ENOMEM = -2,         /* device or host allocation failed */
+  VIE_EDEVICE = -3,        /* no usable HIP device, or a HIP runtime error */
+  VIE_EBREAKDOWN = -4,     /* BiCGSTAB breakdown (rho, <rhat,v> or <t,t> = 0, or non-finite); last iterate written */
+  VIE_EBUSY = -5,          /* resource budget exceeded */
+  VIE_ECANCELLED = -6,
+  VIE_EINTERNAL = -7
+} vie_status;
+
+typedef struct vie_context vie_context;
+typedef struct vie_problem vie_problem;
+
+/* Uniform grid (Sec. II-A: hexahedral mesh, staircase geometry). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx, dy, dz;
+  double wavelength;
+} vie_grid;
+
+typedef enum {
+  VIE_FP64 = 0,   /* every product, vector and reduction in FP64 */
+  VIE_MIXED = 1   /* FFT products in complex FP32; vectors, inner products and
+                     the iterative-refinement residual in FP64 */
+} vie_precision;
+
+/* Solver settings (Sec. II-B and III: outer/inner residual tolerances). */
+typedef struct {
+  double tol_outer;     /* stop when ||r|| / ||b|| <= tol_outer (recursive residual) */
+  double tol_inner;     /* inner block solves: ||r_k|| / ||b_k|| <= tol_inner */
+  int32_t maxit_outer;  /* outer BiCGSTAB steps (paper: 1000) */
+  int32_t maxit_inner;  /* per inner solve */
+  int32_t max_refine;   /* VIE_MIXED: iterative-refinement corrections (FP64 true residual) */
+  int32_t precondition; /* 1: block-diagonal preconditioner (needs block ids), 0: none */
+  int32_t precision;    /* vie_precision */
+  int32_t poll_lag;     /* convergence checks trail the enqueued work by this many steps (>= 0) */
+} vie_opts;
+
+/* Statistics of one solve. */
+typedef struct {
+  int32_t outer_iters;        /* BiCGSTAB steps of the main solve */
+  int32_t refine_steps;       /* VIE_MIXED correction solves */
+  int32_t refine_iters;       /* BiCGSTAB steps spent in correction solves */
+  int32_t final_state;        /* 1 converged, 3 breakdown, 4 iteration cap */
+  int64_t inner_iters_total;  /* sum over preconditioner applications and blocks */
+  int64_t precond_applies;
+  double relres_recursive;    /* ||r|| / ||b|| of the recursion at exit */
+  double relres_true;         /* ||b - A x|| / ||b|| with an FP64 product */
+  double seconds;             /* wall time of the call */
+  int32_t* inner_hist;        /* optional (caller-owned, may be NULL): inner iteration
+                                 count of every non-empty block (ascending id) for each
+                                 preconditioner application, application-major */
+  int64_t inner_hist_cap;     /* capacity of inner_hist in entries */
+  int64_t inner_hist_len;     /* entries written */
+} vie_stats;
+
+/* Block plan summary of a problem. */
+typedef struct {
+  int32_t lx, ly, lz;         /* circulant FFT lengths of the full grid */
+  int32_t n_blocks;           /* non-empty blocks */
+  int32_t n_groups;           /* equally-shaped block batches */
+  int64_t footprint_bytes;    /* device memory held by the problem */
+} vie_problem_info;
+
+/* ABI version (VIE_ABI_VERSION). */
+int32_t vie_abi_version(void);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* vie_last_error(void);
+
+/* Open device `device`.  hbm_budget_bytes bounds the device memory the
+ * context may hold for problems (0 = no limit); problem creation beyond it
+ * returns VIE_EBUSY.  Returns VIE_EDEVICE when no such HIP device exists. */
+vie_status vie_context_create(int32_t device, size_t hbm_budget_bytes, vie_context** out);
+vie_status vie_context_destroy(vie_context* ctx);
+
+/* Set up a problem (Sec. II-A and II-B): uploads 1/chi, computes (or reuses
+ * from the context's cache) the Green-tensor spectra of the grid and of every
+ * block shape, and allocates the Krylov state.
+ *   eps_r:    nx*ny*nz complex (2 doubles each), x fastest; finite.
+ *   block_id: nx*ny*nz int32 or NULL.  Voxel's block in [0, n_blocks) for
+ *             non-vacuum voxels; ignored (should be -1) on vacuum voxels.
+ *             Every non-vacuum voxel must have a valid id when given.
+ *             Blocks partition the scatterer (eq. (10)); a block need not
+ *             be a box (its product runs on its bounding box, masked).
+ * VIE_EINVAL on bad sizes, non-finite values or ids out of range. */
+vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
+                              int32_t n_blocks, vie_problem** out);
+vie_status vie_problem_destroy(vie_problem* p);
+vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info);
+
+/* Incident plane wave E_inc = pol * exp(-j k0 khat . r) at every voxel centre
+ * (Sec. III: x-polarised wave along z).  kdir: unit vector (|kdir| = 1 within
+ * 1e-12, else VIE_EINVAL); pol: 3 complex (6 doubles); e_inc: 3*nx*ny*nz
+ * complex written.  Host helper, no device needed. */
+vie_status vie_plane_wave(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc);
+
+/* y = A x on the device (the hot path's product; eqs. (2)-(4), (6)).
+ * x_dev, y_dev: 3*nx*ny*nz complex double.  x is masked to the scatterer
+ * on input; y is 0 on vacuum voxels.  x_dev and y_dev must not overlap. */
+vie_status vie_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream);
+
+/* y = K2 x with K2 = blockdiag(A_1, ..., A_N) (eq. (10)): every block's
+ * matrix applied to the block's part of x.  Needs block ids. */
+vie_status vie_block_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream);
+
+/* y = K2^{-1} w by inner BiCGSTAB-FFT solves of every block to tol_inner
+ * (x0 = 0, at most maxit_inner steps, last iterate kept), all blocks batched
+ * (Sec. II-B).  inner_iters (optional) receives the total inner steps. */
+vie_status vie_precond_apply(vie_problem* p, int32_t precision, double tol_inner, int32_t maxit_inner,
+                             const void* w_dev, void* y_dev, void* stream, int64_t* inner_iters);
+
+/* Solve A P = E_inc (host arrays).  e_inc: 3*nvox complex; e_tot_out:
+ * 3*nvox complex, E_tot = P / chi on the scatterer, 0 in vacuum (eq. (2));
+ * pol_out: optional (NULL) P.  Returns VIE_OK, VIE_NOT_CONVERGED (best
+ * iterate written) or an error. */
+vie_status vie_solve(vie_problem* p, const double* e_inc, const vie_opts* opts, double* e_tot_out, double* pol_out,
+                     vie_stats* stats);
+
+/* Same with device buffers on `stream` (inputs already in HBM). */
+vie_status vie_solve_device(vie_problem* p, const void* e_inc_dev, const vie_opts* opts, void* e_tot_dev,
+                            void* pol_dev, vie_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIE_H */

@@ -1,0 +1,144 @@
+// Internal interface between the host orchestration (vie_api.cpp) and the
+// HIP kernels.  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "cx.h"
+
+namespace vie {
+
+// Per-system solver status, shared by every kernel that gates on it.
+enum SysStatus : int {
+  ST_ACTIVE = 0,      // iterating
+  ST_CONVERGED = 1,   // done, x final
+  ST_HALF = 2,        // converged at the half step; x += alpha y still pending
+  ST_BREAKDOWN = 3,   // rho, <rhat, v> or omega vanished; x = last iterate
+  ST_MAXIT = 4,       // iteration cap reached; x = last iterate
+  ST_IDLE = 5,        // not started / skipped (zero right-hand side)
+};
+
+// FFT lengths with compiled kernels (2^a 3^b, up to 512).
+constexpr int kFftLengths[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+int smallest_fft_length(int min_len);   // smallest supported L >= min_len, or -1
+
+// Twiddle tables exp(-2 pi i t / L), one per supported L, for one precision.
+template <typename R>
+struct TwiddleSet {
+  const cx<R>* table[513];   // indexed by L (null where unsupported)
+};
+
+// A batch of `nsys` equally-shaped systems (outer grid or a group of blocks).
+// Vectors are c128 [nsys][3][nz][ny][nx]; the work buffer holds the
+// partially transformed components [nsys][3][nz][ly][lx] in precision R.
+template <typename R>
+struct MvmBatch {
+  int nx, ny, nz;          // voxel box
+  int lx, ly, lz;          // circulant lengths (>= 2n - 1)
+  int nsys;
+  int64_t vstride;         // c128 elements between systems' vectors (3 nx ny nz)
+  int64_t cstride;         // c128 elements between systems' 1/chi arrays (nx ny nz)
+  int64_t wstride;         // elements between systems' work buffers
+  int64_t sstride;         // elements between systems' spectra (0 = shared)
+  const c128* chi_inv;     // [nsys][nz][ny][nx], 0 on voxels outside the system
+  const cx<R>* spec;       // [6][lz/2+1][ly/2+1][lx/2+1] per system
+  cx<R>* work;
+  const int* status;       // per system; null = always active
+  const TwiddleSet<R>* tw; // host-side pointer table (values are device pointers)
+};
+
+// y = A x for every active system of the batch (Sec. I Toeplitz + FFT;
+// eqs. (2)-(4)).  `mask_input` zeroes x where 1/chi = 0 before transforming.
+template <typename R>
+void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s);
+
+// Octant spectra of the 6 Green-tensor components for one box shape:
+// evaluates T(m) on the (lz, ly, lx) circulant grid in FP64, transforms it
+// with the device FFT and keeps q in [0, L/2] per axis.  `scratch` holds
+// 6 lx ly lz c128.  Writes both precisions if the pointers are non-null.
+void green_spectra(int nx, int ny, int nz, int lx, int ly, int lz, double dx, double dy, double dz, double k0,
+                   c128* scratch, c128* spec64, c64* spec32, const TwiddleSet<double>& tw, hipStream_t s);
+
+}  // namespace vie
+
+namespace vie {
+
+// ------------------------------------------------------------------ Krylov
+// Scalars of one BiCGSTAB system (outer solve, or one block's inner solve).
+struct KState {
+  c128 rho, rho_old, alpha, omega, beta;
+  double nb;        // ||b||
+  double rnorm;     // ||r|| / ||b|| after the last full step
+  double snorm;     // ||s|| / ||b|| after the last half step
+  double tol;
+  int iters, maxit;
+  int pad0, pad1;
+};
+
+// A batch of `nsys` systems with vectors of `n` c128 each (contiguous,
+// system-major).  `status`/`st` point at this batch's entries.
+struct KBatch {
+  int nsys;
+  int64_t n;
+  int* status;
+  KState* st;
+  double* partials;   // >= nsys * chunks(n) * 4 doubles
+};
+
+int64_t krylov_chunks(int64_t n);   // reduction chunks per system
+
+// x = 0, r = rhat = b, ||b||; status ACTIVE if ||b|| > 0 and the gate (if
+// any) is ACTIVE, CONVERGED (x = 0) if ||b|| = 0, IDLE if gated off.
+void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, double tol, int maxit, const int* gate,
+            hipStream_t s);
+// p = r (first step) or p = r + beta (p - omega v)
+void k_update_p(const KBatch& k, const c128* r, const c128* v, c128* p, hipStream_t s);
+// alpha = rho / <rhat, v>
+void k_alpha(const KBatch& k, const c128* rhat, const c128* v, hipStream_t s);
+// s = r - alpha v; half-step convergence test on ||s||
+void k_update_s(const KBatch& k, const c128* r, const c128* v, c128* sv, hipStream_t s);
+// omega = <t, s> / <t, t>
+void k_omega(const KBatch& k, const c128* t, const c128* sv, hipStream_t s);
+// x += alpha y + omega z, r = s - omega t, new rho and ||r||; or, after a
+// half-step convergence, x += alpha y only.
+void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv, const c128* t,
+                 const c128* rhat, hipStream_t s);
+// After one preconditioner application (skipped when the gate is not
+// ACTIVE): acc[0] += sum of the inner iteration counts of `slots`,
+// acc[1] += 1, and the counts are appended to hist at acc[2] (if they fit).
+void record_inner(const int* gate, const KState* st, const int* slots, int nslots, int64_t* acc, int32_t* hist,
+                  int64_t hist_cap, hipStream_t s);
+// number of ACTIVE entries of status[0..n) into *out (device int)
+void count_active(const int* status, int n, int* out, hipStream_t s);
+// y = x * chi_inv (E_tot = P / chi on the scatterer, 0 in vacuum), batched
+void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int ncomp, hipStream_t s);
+// b = e * mask (mask: chi_inv != 0), 3 components of nv voxels
+void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s);
+// r = b - a (c128, n elements) ; partial-free helper for refinement
+void sub_vec(const c128* b, const c128* a, c128* r, int64_t n, hipStream_t s);
+// x += d
+void add_vec(c128* x, const c128* d, int64_t n, hipStream_t s);
+// ||v||^2 of one vector into *out (device double), deterministic
+void norm2(const c128* v, int64_t n, double* partials, double* out, hipStream_t s);
+
+// ------------------------------------------------------------------ blocks
+// Block k of the partition lives in group block_group[k] as system
+// block_sys[k] with box origin block_origin[k] (voxel coordinates of the
+// outer grid); the group's box is gbox[g].  Group vectors are passed as a
+// device array of per-group base pointers.
+struct BlockMap {
+  int nblocks, ngroups;
+  const int* block_id;      // outer grid [nz][ny][nx], -1 vacuum
+  const int* block_group;   // [nblocks]
+  const int* block_sys;     // [nblocks]
+  const int4* block_origin; // [nblocks] (x, y, z, unused)
+  const int4* gbox;         // [ngroups] (bx, by, bz, unused)
+  int nx, ny, nz;
+};
+// gvec_k[c][local] = w[c][v] for every scatterer voxel v (members only; the
+// other entries of the group vectors are left untouched, i.e. zero)
+void block_gather(const BlockMap& m, const c128* w, c128* const* gdst, hipStream_t s);
+// y[c][v] = gsrc_k[c][local(v)] for scatterer voxels, 0 for vacuum
+void block_scatter(const BlockMap& m, c128* const* gsrc, c128* y, hipStream_t s);
+
+}  // namespace vie

@@ -1,0 +1,543 @@
+// BiCGSTAB vector operations and reductions for batches of independent
+// systems, and the gather/scatter between the outer vector and the blocks of
+// the block-diagonal preconditioner (Sec. II-B, eqs. (10)-(11)).
+//
+// Every reduction is two-stage and deterministic: each workgroup reduces a
+// fixed chunk of 2048 elements (wavefront shuffles, then LDS) into a partial,
+// and one workgroup per system sums the partials in a fixed order and applies
+// the scalar step of the iteration.  No floating-point atomics.
+//
+// BiCGSTAB (van der Vorst), right-preconditioned, per system:
+//   rho = <rhat, r>; p = r + beta (p - omega v); y = K^{-1} p; v = A y;
+//   alpha = rho / <rhat, v>; s = r - alpha v; [||s|| <= tol ||b||: x += alpha y]
+//   z = K^{-1} s; t = A z; omega = <t, s> / <t, t>;
+//   x += alpha y + omega z; r = s - omega t; beta = (rho'/rho)(alpha/omega).
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+
+namespace vie {
+
+constexpr int KT = 256;               // threads per workgroup
+constexpr int KEPT = 8;               // elements per thread
+constexpr int KCH = KT * KEPT;        // elements per chunk
+constexpr int NPART = 4;              // doubles per partial
+
+__host__ __device__ int64_t chunks_of(int64_t n) { return (n + KCH - 1) / KCH; }
+int64_t krylov_chunks(int64_t n) { return chunks_of(n); }
+
+static void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
+}
+
+// Sum NV doubles over the workgroup; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double sm[KT / 64][NV];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sm[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double a = sm[0][k];
+      for (int w = 1; w < KT / 64; ++w) a += sm[w][k];
+      v[k] = a;
+    }
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void write_partial(double* partials, int64_t chunks, int sys, int64_t chunk,
+                                              double (&v)[NV]) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0) {
+    double* p = partials + ((int64_t)sys * chunks + chunk) * NPART;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) p[k] = v[k];
+  }
+}
+
+// Sum of the system's partials (fixed order), valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void final_sum(const double* partials, int64_t chunks, int sys, double (&v)[NV]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (int64_t c = threadIdx.x; c < chunks; c += KT) {
+    const double* p = partials + ((int64_t)sys * chunks + c) * NPART;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += p[k];
+  }
+  block_sum<NV>(v);
+}
+
+__device__ __forceinline__ c128 cdiv(c128 a, c128 b) {
+  // a / b, scaled to avoid overflow
+  const double s = fabs(b.x) + fabs(b.y);
+  const double br = b.x / s, bi = b.y / s, ar = a.x / s, ai = a.y / s;
+  const double d = br * br + bi * bi;
+  return mk<double>((ar * br + ai * bi) / d, (ai * br - ar * bi) / d);
+}
+
+// chunk / system decomposition of a (chunks x nsys) grid
+#define KRYLOV_INDEX                                         \
+  const int64_t chunks = chunks_of(n);                   \
+  const int sys = (int)(blockIdx.x / chunks);                \
+  const int64_t chunk = blockIdx.x - (int64_t)sys * chunks;  \
+  const int64_t base = (int64_t)sys * n;                     \
+  const int64_t i0 = chunk * KCH + threadIdx.x;
+
+// ---------------------------------------------------------------- init
+__global__ void __launch_bounds__(KT) kk_init(int64_t n, const int* gate, const c128* b, c128* x, c128* r,
+                                              c128* rhat, double* partials) {
+  KRYLOV_INDEX
+  if (gate && *gate != ST_ACTIVE) return;
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 v = b[base + i];
+      x[base + i] = mk<double>(0.0, 0.0);
+      r[base + i] = v;
+      rhat[base + i] = v;
+      acc[0] += abs2(v);
+    }
+  }
+  write_partial<1>(partials, chunks, sys, chunk, acc);
+}
+
+__global__ void __launch_bounds__(KT) kk_init_fin(int64_t n, const int* gate, int* status, KState* st,
+                                                  const double* partials, double tol, int maxit) {
+  const int sys = blockIdx.x;
+  const int64_t chunks = chunks_of(n);
+  if (gate && *gate != ST_ACTIVE) {
+    if (threadIdx.x == 0) status[sys] = ST_IDLE;
+    return;
+  }
+  double v[1];
+  final_sum<1>(partials, chunks, sys, v);
+  if (threadIdx.x == 0) {
+    KState& k = st[sys];
+    const double nb = sqrt(v[0]);
+    k.nb = nb;
+    k.rho = mk<double>(v[0], 0.0);
+    k.rho_old = mk<double>(1.0, 0.0);
+    k.alpha = mk<double>(1.0, 0.0);
+    k.omega = mk<double>(1.0, 0.0);
+    k.beta = mk<double>(0.0, 0.0);
+    k.rnorm = nb > 0.0 ? 1.0 : 0.0;
+    k.snorm = k.rnorm;
+    k.tol = tol;
+    k.iters = 0;
+    k.maxit = maxit;
+    status[sys] = nb > 0.0 ? ST_ACTIVE : ST_CONVERGED;
+  }
+}
+
+void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, double tol, int maxit, const int* gate,
+            hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_init, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, gate, b, x, r, rhat, k.partials);
+  hipLaunchKernelGGL(kk_init_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, gate, k.status, k.st, k.partials, tol, maxit);
+  check_launch("krylov init");
+}
+
+// ---------------------------------------------------------------- p update
+__global__ void __launch_bounds__(KT) kk_update_p(int64_t n, const int* status, const KState* st, const c128* r,
+                                                  const c128* v, c128* p) {
+  KRYLOV_INDEX
+  (void)chunk;
+  if (status[sys] != ST_ACTIVE) return;
+  const KState& k = st[sys];
+  const bool first = k.iters == 0;
+  const c128 beta = k.beta, omega = k.omega;
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 rv = r[base + i];
+      if (first) {
+        p[base + i] = rv;
+      } else {
+        p[base + i] = rv + beta * (p[base + i] - omega * v[base + i]);
+      }
+    }
+  }
+}
+
+void k_update_p(const KBatch& k, const c128* r, const c128* v, c128* p, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_update_p, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, k.st, r, v, p);
+  check_launch("krylov p");
+}
+
+// ---------------------------------------------------------------- alpha
+__global__ void __launch_bounds__(KT) kk_dot(int64_t n, const int* status, const c128* a, const c128* b,
+                                             double* partials) {
+  KRYLOV_INDEX
+  if (status[sys] != ST_ACTIVE) return;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 d = cdot1(a[base + i], b[base + i]);
+      acc[0] += d.x;
+      acc[1] += d.y;
+    }
+  }
+  write_partial<2>(partials, chunks, sys, chunk, acc);
+}
+
+__global__ void __launch_bounds__(KT) kk_alpha_fin(int64_t n, int* status, KState* st, const double* partials) {
+  const int sys = blockIdx.x;
+  if (status[sys] != ST_ACTIVE) return;
+  double v[2];
+  final_sum<2>(partials, chunks_of(n), sys, v);
+  if (threadIdx.x == 0) {
+    KState& k = st[sys];
+    k.iters += 1;
+    const c128 den = mk<double>(v[0], v[1]);
+    if (den.x == 0.0 && den.y == 0.0) {
+      status[sys] = ST_BREAKDOWN;
+    } else {
+      k.alpha = cdiv(k.rho, den);
+    }
+  }
+}
+
+void k_alpha(const KBatch& k, const c128* rhat, const c128* v, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_dot, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, rhat, v, k.partials);
+  hipLaunchKernelGGL(kk_alpha_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  check_launch("krylov alpha");
+}
+
+// ---------------------------------------------------------------- s update
+__global__ void __launch_bounds__(KT) kk_update_s(int64_t n, const int* status, const KState* st, const c128* r,
+                                                  const c128* v, c128* sv, double* partials) {
+  KRYLOV_INDEX
+  if (status[sys] != ST_ACTIVE) return;
+  const c128 alpha = st[sys].alpha;
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 sval = r[base + i] - alpha * v[base + i];
+      sv[base + i] = sval;
+      acc[0] += abs2(sval);
+    }
+  }
+  write_partial<1>(partials, chunks, sys, chunk, acc);
+}
+
+__global__ void __launch_bounds__(KT) kk_s_fin(int64_t n, int* status, KState* st, const double* partials) {
+  const int sys = blockIdx.x;
+  if (status[sys] != ST_ACTIVE) return;
+  double v[1];
+  final_sum<1>(partials, chunks_of(n), sys, v);
+  if (threadIdx.x == 0) {
+    KState& k = st[sys];
+    k.snorm = sqrt(v[0]) / k.nb;
+    if (k.snorm <= k.tol) status[sys] = ST_HALF;
+  }
+}
+
+void k_update_s(const KBatch& k, const c128* r, const c128* v, c128* sv, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_update_s, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, k.st, r, v, sv,
+                     k.partials);
+  hipLaunchKernelGGL(kk_s_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  check_launch("krylov s");
+}
+
+// ---------------------------------------------------------------- omega
+__global__ void __launch_bounds__(KT) kk_dot_ts(int64_t n, const int* status, const c128* t, const c128* sv,
+                                                double* partials) {
+  KRYLOV_INDEX
+  if (status[sys] != ST_ACTIVE) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 tv = t[base + i];
+      const c128 d = cdot1(tv, sv[base + i]);
+      acc[0] += d.x;
+      acc[1] += d.y;
+      acc[2] += abs2(tv);
+    }
+  }
+  write_partial<3>(partials, chunks, sys, chunk, acc);
+}
+
+__global__ void __launch_bounds__(KT) kk_omega_fin(int64_t n, int* status, KState* st, const double* partials) {
+  const int sys = blockIdx.x;
+  if (status[sys] != ST_ACTIVE) return;
+  double v[3];
+  final_sum<3>(partials, chunks_of(n), sys, v);
+  if (threadIdx.x == 0) {
+    KState& k = st[sys];
+    if (v[2] == 0.0) {
+      status[sys] = ST_BREAKDOWN;
+    } else {
+      k.omega = mk<double>(v[0] / v[2], v[1] / v[2]);
+    }
+  }
+}
+
+void k_omega(const KBatch& k, const c128* t, const c128* sv, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_dot_ts, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, t, sv, k.partials);
+  hipLaunchKernelGGL(kk_omega_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  check_launch("krylov omega");
+}
+
+// ---------------------------------------------------------------- x, r update
+__global__ void __launch_bounds__(KT) kk_update_xr(int64_t n, const int* status, const KState* st, c128* x,
+                                                   const c128* y, const c128* z, c128* r, const c128* sv,
+                                                   const c128* t, const c128* rhat, double* partials) {
+  KRYLOV_INDEX
+  const int stt = status[sys];
+  if (stt == ST_HALF) {
+    const c128 alpha = st[sys].alpha;
+#pragma unroll
+    for (int j = 0; j < KEPT; ++j) {
+      const int64_t i = i0 + (int64_t)j * KT;
+      if (i < n) x[base + i] = x[base + i] + alpha * y[base + i];
+    }
+    return;
+  }
+  if (stt != ST_ACTIVE) return;
+  const c128 alpha = st[sys].alpha, omega = st[sys].omega;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      x[base + i] = x[base + i] + alpha * y[base + i] + omega * z[base + i];
+      const c128 rv = sv[base + i] - omega * t[base + i];
+      r[base + i] = rv;
+      const c128 d = cdot1(rhat[base + i], rv);
+      acc[0] += d.x;
+      acc[1] += d.y;
+      acc[2] += abs2(rv);
+    }
+  }
+  write_partial<3>(partials, chunks, sys, chunk, acc);
+}
+
+__global__ void __launch_bounds__(KT) kk_xr_fin(int64_t n, int* status, KState* st, const double* partials) {
+  const int sys = blockIdx.x;
+  const int stt = status[sys];
+  if (stt == ST_HALF) {
+    if (threadIdx.x == 0) {
+      st[sys].rnorm = st[sys].snorm;
+      status[sys] = ST_CONVERGED;
+    }
+    return;
+  }
+  if (stt != ST_ACTIVE) return;
+  double v[3];
+  final_sum<3>(partials, chunks_of(n), sys, v);
+  if (threadIdx.x == 0) {
+    KState& k = st[sys];
+    k.rnorm = sqrt(v[2]) / k.nb;
+    k.rho_old = k.rho;
+    k.rho = mk<double>(v[0], v[1]);
+    const bool om0 = k.omega.x == 0.0 && k.omega.y == 0.0;
+    const bool rho0 = k.rho.x == 0.0 && k.rho.y == 0.0;
+    if (k.rnorm <= k.tol) {
+      status[sys] = ST_CONVERGED;
+    } else if (om0 || rho0 || !(k.rnorm == k.rnorm)) {
+      status[sys] = ST_BREAKDOWN;
+    } else if (k.iters >= k.maxit) {
+      status[sys] = ST_MAXIT;
+    } else {
+      k.beta = cdiv(k.rho, k.rho_old) * cdiv(k.alpha, k.omega);
+    }
+  }
+}
+
+void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv, const c128* t,
+                 const c128* rhat, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_update_xr, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, k.st, x, y, z, r,
+                     sv, t, rhat, k.partials);
+  hipLaunchKernelGGL(kk_xr_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  check_launch("krylov xr");
+}
+
+// ---------------------------------------------------------------- bookkeeping
+__global__ void __launch_bounds__(KT) kk_record_inner(const int* gate, const KState* st, const int* slots,
+                                                      int nslots, int64_t* acc, int32_t* hist, int64_t hist_cap) {
+  if (gate && *gate != ST_ACTIVE) return;
+  double v[1] = {0.0};
+  for (int j = threadIdx.x; j < nslots; j += KT) v[0] += (double)st[slots[j]].iters;
+  block_sum<1>(v);
+  __shared__ int64_t len;
+  if (threadIdx.x == 0) {
+    acc[0] += (int64_t)v[0];
+    acc[1] += 1;
+    len = acc[2];
+    acc[2] = len + nslots;
+  }
+  __syncthreads();
+  if (hist && len + nslots <= hist_cap)
+    for (int j = threadIdx.x; j < nslots; j += KT) hist[len + j] = st[slots[j]].iters;
+}
+
+void record_inner(const int* gate, const KState* st, const int* slots, int nslots, int64_t* acc, int32_t* hist,
+                  int64_t hist_cap, hipStream_t s) {
+  hipLaunchKernelGGL(kk_record_inner, dim3(1), dim3(KT), 0, s, gate, st, slots, nslots, acc, hist, hist_cap);
+  check_launch("record inner");
+}
+
+// ---------------------------------------------------------------- helpers
+__global__ void __launch_bounds__(KT) kk_count_active(const int* status, int n, int* out) {
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += KT) v[0] += status[i] == ST_ACTIVE ? 1.0 : 0.0;
+  block_sum<1>(v);
+  if (threadIdx.x == 0) *out = (int)v[0];
+}
+
+void count_active(const int* status, int n, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(kk_count_active, dim3(1), dim3(KT), 0, s, status, n, out);
+  check_launch("count active");
+}
+
+__global__ void kk_total_field(const c128* P, const c128* chi, c128* e, int64_t nv, int ncomp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * ncomp) return;
+  const c128 ci = chi[i % nv];
+  e[i] = (ci.x == 0.0 && ci.y == 0.0) ? mk<double>(0.0, 0.0) : P[i] * ci;
+}
+
+void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int ncomp, hipStream_t s) {
+  const int64_t n = nv * ncomp;
+  hipLaunchKernelGGL(kk_total_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, chi_inv, e, nv, ncomp);
+  check_launch("total field");
+}
+
+__global__ void kk_masked_copy(const c128* e, const c128* chi, c128* b, int64_t nv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * nv) return;
+  const c128 ci = chi[i % nv];
+  b[i] = (ci.x == 0.0 && ci.y == 0.0) ? mk<double>(0.0, 0.0) : e[i];
+}
+
+void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s) {
+  hipLaunchKernelGGL(kk_masked_copy, dim3((unsigned)((3 * nv + 255) / 256)), dim3(256), 0, s, e, chi_inv, b, nv);
+  check_launch("masked copy");
+}
+
+__global__ void kk_sub(const c128* b, const c128* a, c128* r, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = b[i] - a[i];
+}
+void sub_vec(const c128* b, const c128* a, c128* r, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(kk_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, a, r, n);
+  check_launch("sub");
+}
+
+__global__ void kk_add(c128* x, const c128* d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = x[i] + d[i];
+}
+void add_vec(c128* x, const c128* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(kk_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, d, n);
+  check_launch("add");
+}
+
+__global__ void __launch_bounds__(KT) kk_norm2(int64_t n, const c128* v, double* partials) {
+  KRYLOV_INDEX
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) acc[0] += abs2(v[base + i]);
+  }
+  write_partial<1>(partials, chunks, sys, chunk, acc);
+}
+
+__global__ void __launch_bounds__(KT) kk_norm2_fin(int64_t n, const double* partials, double* out) {
+  double v[1];
+  final_sum<1>(partials, chunks_of(n), 0, v);
+  if (threadIdx.x == 0) *out = v[0];
+}
+
+void norm2(const c128* v, int64_t n, double* partials, double* out, hipStream_t s) {
+  const int64_t chunks = chunks_of(n);
+  hipLaunchKernelGGL(kk_norm2, dim3((unsigned)chunks), dim3(KT), 0, s, n, v, partials);
+  hipLaunchKernelGGL(kk_norm2_fin, dim3(1), dim3(KT), 0, s, n, partials, out);
+  check_launch("norm2");
+}
+
+// ---------------------------------------------------------------- blocks
+__device__ __forceinline__ int64_t block_local(const BlockMap& m, int k, int x, int y, int z, int* g, int* sysi,
+                                               int64_t* bnv) {
+  *g = m.block_group[k];
+  *sysi = m.block_sys[k];
+  const int4 o = m.block_origin[k];
+  const int4 b = m.gbox[*g];
+  *bnv = (int64_t)b.x * b.y * b.z;
+  return ((int64_t)(z - o.z) * b.y + (y - o.y)) * b.x + (x - o.x);
+}
+
+__global__ void kk_gather(BlockMap m, const c128* w, c128* const* gdst) {
+  const int64_t nv = (int64_t)m.nx * m.ny * m.nz;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const int k = m.block_id[v];
+  if (k < 0) return;
+  const int x = (int)(v % m.nx), y = (int)((v / m.nx) % m.ny), z = (int)(v / ((int64_t)m.nx * m.ny));
+  int g, sysi;
+  int64_t bnv;
+  const int64_t loc = block_local(m, k, x, y, z, &g, &sysi, &bnv);
+  c128* dst = gdst[g] + (int64_t)sysi * 3 * bnv + loc;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dst[c * bnv] = w[c * nv + v];
+}
+
+void block_gather(const BlockMap& m, const c128* w, c128* const* gdst, hipStream_t s) {
+  const int64_t nv = (int64_t)m.nx * m.ny * m.nz;
+  hipLaunchKernelGGL(kk_gather, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, m, w, gdst);
+  check_launch("gather");
+}
+
+__global__ void kk_scatter(BlockMap m, c128* const* gsrc, c128* y) {
+  const int64_t nv = (int64_t)m.nx * m.ny * m.nz;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const int k = m.block_id[v];
+  if (k < 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c * nv + v] = mk<double>(0.0, 0.0);
+    return;
+  }
+  const int x = (int)(v % m.nx), yy = (int)((v / m.nx) % m.ny), z = (int)(v / ((int64_t)m.nx * m.ny));
+  int g, sysi;
+  int64_t bnv;
+  const int64_t loc = block_local(m, k, x, yy, z, &g, &sysi, &bnv);
+  const c128* src = gsrc[g] + (int64_t)sysi * 3 * bnv + loc;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[c * nv + v] = src[c * bnv];
+}
+
+void block_scatter(const BlockMap& m, c128* const* gsrc, c128* y, hipStream_t s) {
+  const int64_t nv = (int64_t)m.nx * m.ny * m.nz;
+  hipLaunchKernelGGL(kk_scatter, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, m, gsrc, y);
+  check_launch("scatter");
+}
+
+}  // namespace vie

@@ -1,0 +1,553 @@
+// FFT-accelerated product with the discretised VIE operator, and the setup of
+// the Green-tensor spectra.
+//
+// Operator (eqs. (2)-(4) and (6) of the paper, unknown P = J/(j omega eps0)):
+//   (A x)_m = x_m / chi_m - sum_n T(m - n) x_n   on the scatterer voxels,
+//   (A x)_m = 0                                   on vacuum voxels.
+// The sum is a 3-D convolution with the block-Toeplitz kernel T (Sec. I),
+// done as a circulant convolution on a (lx, ly, lz) grid with L >= 2n - 1 per
+// axis, in five passes over HBM:
+//   1. x forward, pruned: rows of nx voxels, zero-padded to lx;
+//   2. y forward, pruned: only the nz non-zero z-planes exist;
+//   3. z forward + 3x3 symmetric spectral multiply + z inverse, fused in one
+//      workgroup per (qy, tile of qx) with all three components in LDS;
+//      the spectrum is read from its octant q in [0, L/2]^3 with the parity
+//      signs of the odd components (T_xy is odd in x and y, ...);
+//   4. y inverse, cropped to ny rows;
+//   5. x inverse, cropped to nx, scaled by 1/(lx ly lz), fused with the
+//      local term and the vacuum mask, written as c128.
+#include <cmath>
+#include <stdexcept>
+#include <string>
+
+#include "fft_core.h"
+#include "kernels.h"
+
+namespace vie {
+
+int smallest_fft_length(int min_len) {
+  for (int L : kFftLengths)
+    if (L >= min_len) return L;
+  return -1;
+}
+
+// ------------------------------------------------------------------ geometry
+constexpr int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <typename R, int L>
+struct Geo {
+  static constexpr int T = PlanInfo<L>::max_butterflies;  // threads per pencil
+  static constexpr int ES = (int)sizeof(cx<R>);
+  // rows (contiguous pencils): ~256 threads, LDS [ROWP][L]
+  static constexpr int ROWP = cmax(1, cmin(256 / T, (64 * 1024) / (L * ES)));
+  // columns (strided pencils): >= 16 columns for coalescing, LDS [L][COLP]
+  static constexpr int COLP = cmax(1, pow2_floor(cmin(cmax(16, 256 / T), cmin(512 / T, (64 * 1024) / (L * ES)))));
+  // fused z pass: three components side by side, LDS [3][L][ZP]
+  static constexpr int ZP = cmax(1, pow2_floor(cmin(64, cmin(1024 / (3 * T), (144 * 1024) / (3 * L * ES)))));
+};
+
+__device__ __forceinline__ bool sys_active(const int* status, int s) {
+  return status == nullptr || status[s] == ST_ACTIVE;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> czero() {
+  return mk<R>(R(0), R(0));
+}
+
+// ------------------------------------------------------------------ kernels
+template <typename R>
+struct RowArgs {
+  int nx, ny, nz, lx, ly;
+  int64_t vstride, cstride, wstride;
+  const c128* x;
+  c128* y;
+  const c128* chi_inv;
+  cx<R>* work;
+  const int* status;
+  const cx<R>* tw;
+  int mask_input;
+  double scale;
+};
+
+// Pass 1: x forward with zero padding nx -> lx, c128 -> R.
+template <typename R, int L>
+__global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_fwd(RowArgs<R> a) {
+  using G = Geo<R, L>;
+  __shared__ cx<R> lds[G::ROWP * L];
+  const int rows = 3 * a.nz * a.ny;
+  const int tiles = (rows + G::ROWP - 1) / G::ROWP;
+  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  if (!sys_active(a.status, sys)) return;
+  const int p = threadIdx.x / G::T, t = threadIdx.x - p * G::T;
+  const int row = tile * G::ROWP + p;
+  const bool valid = row < rows;
+  const int rr = valid ? row : 0;
+  const int c = rr / (a.nz * a.ny), zy = rr - c * (a.nz * a.ny);
+  const int z = zy / a.ny, yy = zy - z * a.ny;
+  const c128* xin = a.x + sys * a.vstride + (int64_t)rr * a.nx;
+  const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
+  cx<R>* w = a.work + sys * a.wstride + ((int64_t)(c * a.nz + z) * a.ly + yy) * a.lx;
+  const int nx = a.nx;
+  const bool msk = a.mask_input != 0;
+  auto ld = [&](int n) -> cx<R> {
+    if (n < nx) {
+      c128 v = xin[n];
+      if (msk) {
+        c128 ci = chi[n];
+        if (ci.x == 0.0 && ci.y == 0.0) v = mk<double>(0.0, 0.0);
+      }
+      return cvt<R>(v);
+    }
+    return czero<R>();
+  };
+  auto st = [&](int k, cx<R> v) { w[k] = v; };
+  fft_pencil<R, L, G::T, -1>(ld, st, lds + p * L, 1, t, valid, a.tw);
+}
+
+// Pass 5: x inverse, crop lx -> nx, y = x/chi - scale * Q on the mask, 0 off it.
+template <typename R, int L>
+__global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_local(RowArgs<R> a) {
+  using G = Geo<R, L>;
+  __shared__ cx<R> lds[G::ROWP * L];
+  const int rows = 3 * a.nz * a.ny;
+  const int tiles = (rows + G::ROWP - 1) / G::ROWP;
+  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  if (!sys_active(a.status, sys)) return;
+  const int p = threadIdx.x / G::T, t = threadIdx.x - p * G::T;
+  const int row = tile * G::ROWP + p;
+  const bool valid = row < rows;
+  const int rr = valid ? row : 0;
+  const int c = rr / (a.nz * a.ny), zy = rr - c * (a.nz * a.ny);
+  const int z = zy / a.ny, yy = zy - z * a.ny;
+  const c128* xin = a.x + sys * a.vstride + (int64_t)rr * a.nx;
+  c128* yout = a.y + sys * a.vstride + (int64_t)rr * a.nx;
+  const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
+  const cx<R>* w = a.work + sys * a.wstride + ((int64_t)(c * a.nz + z) * a.ly + yy) * a.lx;
+  const int nx = a.nx;
+  const double scale = a.scale;
+  auto ld = [&](int n) -> cx<R> { return w[n]; };
+  auto st = [&](int k, cx<R> v) {
+    if (k < nx) {
+      c128 ci = chi[k];
+      c128 out = mk<double>(0.0, 0.0);
+      if (ci.x != 0.0 || ci.y != 0.0) {
+        c128 q = cvt<double>(v);
+        out = xin[k] * ci - scale * q;
+      }
+      yout[k] = out;
+    }
+  };
+  fft_pencil<R, L, G::T, +1>(ld, st, lds + p * L, 1, t, valid, a.tw);
+}
+
+// In-place FFT of full-length rows (spectra setup).
+template <typename R, int L>
+__global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_full(cx<R>* data, int64_t rows,
+                                                                           const cx<R>* tw) {
+  using G = Geo<R, L>;
+  __shared__ cx<R> lds[G::ROWP * L];
+  const int p = threadIdx.x / G::T, t = threadIdx.x - p * G::T;
+  const int64_t row = (int64_t)blockIdx.x * G::ROWP + p;
+  const bool valid = row < rows;
+  cx<R>* d = data + (valid ? row : 0) * L;
+  auto ld = [&](int n) -> cx<R> { return d[n]; };
+  auto st = [&](int k, cx<R> v) { d[k] = v; };
+  fft_pencil<R, L, G::T, -1>(ld, st, lds + p * L, 1, t, valid, tw);
+}
+
+// Strided pencils, in place: per system, data[outer][L][inner]; element n of
+// column (o, i) at o*L*inner + n*inner + i.  Reads n < n_in (zero beyond),
+// writes k < n_out.  Passes 2 and 4, and the y/z passes of the setup.
+template <typename R>
+struct ColArgs {
+  cx<R>* data;
+  int outer, inner, n_in, n_out;
+  int64_t stride;
+  const int* status;
+  const cx<R>* tw;
+  int nsys;
+};
+
+template <typename R, int L, int DIR>
+__global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::COLP)) k_col(ColArgs<R> a) {
+  using G = Geo<R, L>;
+  __shared__ cx<R> lds[G::COLP * L];
+  const int64_t cols = (int64_t)a.outer * a.inner;
+  const int64_t tiles = (cols + G::COLP - 1) / G::COLP;
+  const int sys = (int)(blockIdx.x / tiles);
+  const int64_t tile = blockIdx.x - (int64_t)sys * tiles;
+  if (!sys_active(a.status, sys)) return;
+  const int p = threadIdx.x % G::COLP, t = threadIdx.x / G::COLP;
+  const int64_t col = tile * G::COLP + p;
+  const bool valid = col < cols;
+  const int64_t cc = valid ? col : 0;
+  const int64_t o = cc / a.inner, i = cc - o * a.inner;
+  cx<R>* base = a.data + sys * a.stride + o * (int64_t)L * a.inner + i;
+  const int inner = a.inner, n_in = a.n_in, n_out = a.n_out;
+  auto ld = [&](int n) -> cx<R> { return n < n_in ? base[(int64_t)n * inner] : czero<R>(); };
+  auto st = [&](int k, cx<R> v) {
+    if (k < n_out) base[(int64_t)k * inner] = v;
+  };
+  fft_pencil<R, L, G::T, DIR>(ld, st, lds + p, G::COLP, t, valid, a.tw);
+}
+
+// Pass 3: z forward (nz -> LZ), spectral multiply, z inverse (LZ -> nz).
+template <typename R>
+struct ZArgs {
+  int nz, ly, lx;
+  int64_t wstride, sstride;
+  cx<R>* work;
+  const cx<R>* spec;
+  const int* status;
+  const cx<R>* tw;
+};
+
+template <typename R, int LZ>
+__global__ void __launch_bounds__((3 * Geo<R, LZ>::T * Geo<R, LZ>::ZP)) k_zconv(ZArgs<R> a) {
+  using G = Geo<R, LZ>;
+  constexpr int T = G::T, ZP = G::ZP;
+  __shared__ cx<R> lds[3 * LZ * ZP];
+  const int cols = a.ly * a.lx;
+  const int tiles = (cols + ZP - 1) / ZP;
+  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  if (!sys_active(a.status, sys)) return;
+  const int comp = threadIdx.x / (T * ZP);
+  const int rem = threadIdx.x - comp * (T * ZP);
+  const int p = rem % ZP, t = rem / ZP;
+  const int col = tile * ZP + p;
+  const bool valid = col < cols;
+  const int64_t plane = (int64_t)a.ly * a.lx;
+  cx<R>* base = a.work + sys * a.wstride + (int64_t)comp * a.nz * plane + (valid ? col : 0);
+  cx<R>* slot = lds + comp * LZ * ZP + p;
+  const int nz = a.nz;
+  // forward along z into the component's LDS slot
+  auto ldg = [&](int n) -> cx<R> { return n < nz ? base[n * plane] : czero<R>(); };
+  auto sts = [&](int k, cx<R> v) { slot[k * ZP] = v; };
+  fft_pencil<R, LZ, T, -1, false, true>(ldg, sts, slot, ZP, t, valid, a.tw);
+
+  // Q(q) = S(q) X(q), S symmetric 3x3 from the octant with parity signs
+  const int lx = a.lx, ly = a.ly;
+  const int hx = lx / 2, hy = ly / 2, hz = LZ / 2;
+  const int64_t ox = hx + 1, oy = hy + 1;
+  const int64_t oct = ox * oy * (hz + 1);
+  const cx<R>* spec = a.spec + sys * a.sstride;
+  for (int i = threadIdx.x; i < LZ * ZP; i += 3 * T * ZP) {
+    const int qz = i / ZP, pp = i - qz * ZP;
+    const int c2 = tile * ZP + pp;
+    if (c2 >= cols) continue;
+    const int qy = c2 / lx, qx = c2 - qy * lx;
+    const int fx = qx <= hx ? qx : lx - qx, fy = qy <= hy ? qy : ly - qy, fz = qz <= hz ? qz : LZ - qz;
+    const R sx = qx <= hx ? R(1) : R(-1), sy = qy <= hy ? R(1) : R(-1), sz = qz <= hz ? R(1) : R(-1);
+    const int64_t o = ((int64_t)fz * oy + fy) * ox + fx;
+    const cx<R> sxx = spec[o], syy = spec[3 * oct + o], szz = spec[5 * oct + o];
+    const cx<R> sxy = (sx * sy) * spec[oct + o];
+    const cx<R> sxz = (sx * sz) * spec[2 * oct + o];
+    const cx<R> syz = (sy * sz) * spec[4 * oct + o];
+    const int e = qz * ZP + pp;
+    const cx<R> X = lds[e], Y = lds[LZ * ZP + e], Z = lds[2 * LZ * ZP + e];
+    lds[e] = sxx * X + sxy * Y + sxz * Z;
+    lds[LZ * ZP + e] = sxy * X + syy * Y + syz * Z;
+    lds[2 * LZ * ZP + e] = sxz * X + syz * Y + szz * Z;
+  }
+  __syncthreads();
+  // inverse along z, cropped to nz
+  auto lds_ld = [&](int n) -> cx<R> { return slot[n * ZP]; };
+  auto stg = [&](int k, cx<R> v) {
+    if (k < nz) base[k * plane] = v;
+  };
+  fft_pencil<R, LZ, T, +1, true, false>(lds_ld, stg, slot, ZP, t, valid, a.tw);
+}
+
+// ------------------------------------------------------------------ launchers
+#define VIE_L_CASES(F) \
+  F(1) F(2) F(3) F(4) F(6) F(8) F(12) F(16) F(24) F(32) F(48) F(64) F(96) F(128) F(192) F(256) F(384) F(512)
+
+[[noreturn]] static void bad_length(const char* what, int L) {
+  throw std::runtime_error(std::string("unsupported FFT length for ") + what + ": " + std::to_string(L));
+}
+
+static void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
+}
+
+template <typename R>
+static void launch_row_fwd(int L, const RowArgs<R>& a, int nsys, hipStream_t s) {
+  switch (L) {
+#define C(l)                                                                   \
+  case l: {                                                                    \
+    using G = Geo<R, l>;                                                       \
+    const int rows = 3 * a.nz * a.ny, tiles = (rows + G::ROWP - 1) / G::ROWP;  \
+    hipLaunchKernelGGL((k_row_fwd<R, l>), dim3(tiles * nsys), dim3(G::T * G::ROWP), 0, s, a); \
+    break;                                                                     \
+  }
+    VIE_L_CASES(C)
+#undef C
+    default:
+      bad_length("x pass", L);
+  }
+  check_launch("x forward");
+}
+
+template <typename R>
+static void launch_row_inv(int L, const RowArgs<R>& a, int nsys, hipStream_t s) {
+  switch (L) {
+#define C(l)                                                                   \
+  case l: {                                                                    \
+    using G = Geo<R, l>;                                                       \
+    const int rows = 3 * a.nz * a.ny, tiles = (rows + G::ROWP - 1) / G::ROWP;  \
+    hipLaunchKernelGGL((k_row_inv_local<R, l>), dim3(tiles * nsys), dim3(G::T * G::ROWP), 0, s, a); \
+    break;                                                                     \
+  }
+    VIE_L_CASES(C)
+#undef C
+    default:
+      bad_length("x pass", L);
+  }
+  check_launch("x inverse");
+}
+
+template <typename R, int DIR>
+static void launch_col(int L, const ColArgs<R>& a, hipStream_t s) {
+  switch (L) {
+#define C(l)                                                                        \
+  case l: {                                                                         \
+    using G = Geo<R, l>;                                                            \
+    const int64_t cols = (int64_t)a.outer * a.inner;                                \
+    const int64_t tiles = (cols + G::COLP - 1) / G::COLP;                           \
+    hipLaunchKernelGGL((k_col<R, l, DIR>), dim3((unsigned)(tiles * a.nsys)), dim3(G::T * G::COLP), 0, s, a); \
+    break;                                                                          \
+  }
+    VIE_L_CASES(C)
+#undef C
+    default:
+      bad_length("column pass", L);
+  }
+  check_launch("column pass");
+}
+
+template <typename R>
+static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
+  switch (L) {
+#define C(l)                                                                     \
+  case l: {                                                                      \
+    using G = Geo<R, l>;                                                         \
+    const int cols = a.ly * a.lx, tiles = (cols + G::ZP - 1) / G::ZP;            \
+    hipLaunchKernelGGL((k_zconv<R, l>), dim3(tiles * nsys), dim3(3 * G::T * G::ZP), 0, s, a); \
+    break;                                                                       \
+  }
+    VIE_L_CASES(C)
+#undef C
+    default:
+      bad_length("z pass", L);
+  }
+  check_launch("z pass");
+}
+
+template <typename R>
+void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s) {
+  if (b.nsys <= 0) return;
+  RowArgs<R> ra{};
+  ra.nx = b.nx;
+  ra.ny = b.ny;
+  ra.nz = b.nz;
+  ra.lx = b.lx;
+  ra.ly = b.ly;
+  ra.vstride = b.vstride;
+  ra.cstride = b.cstride;
+  ra.wstride = b.wstride;
+  ra.x = x;
+  ra.y = y;
+  ra.chi_inv = b.chi_inv;
+  ra.work = b.work;
+  ra.status = b.status;
+  ra.tw = b.tw->table[b.lx];
+  ra.mask_input = mask_input ? 1 : 0;
+  ra.scale = 1.0 / ((double)b.lx * (double)b.ly * (double)b.lz);
+  launch_row_fwd<R>(b.lx, ra, b.nsys, s);
+
+  ColArgs<R> ca{};
+  ca.data = b.work;
+  ca.outer = 3 * b.nz;
+  ca.inner = b.lx;
+  ca.n_in = b.ny;
+  ca.n_out = b.ly;
+  ca.stride = b.wstride;
+  ca.status = b.status;
+  ca.tw = b.tw->table[b.ly];
+  ca.nsys = b.nsys;
+  launch_col<R, -1>(b.ly, ca, s);
+
+  ZArgs<R> za{};
+  za.nz = b.nz;
+  za.ly = b.ly;
+  za.lx = b.lx;
+  za.wstride = b.wstride;
+  za.sstride = b.sstride;
+  za.work = b.work;
+  za.spec = b.spec;
+  za.status = b.status;
+  za.tw = b.tw->table[b.lz];
+  launch_zconv<R>(b.lz, za, b.nsys, s);
+
+  ca.n_in = b.ly;
+  ca.n_out = b.ny;
+  launch_col<R, +1>(b.ly, ca, s);
+
+  launch_row_inv<R>(b.lx, ra, b.nsys, s);
+}
+
+template void mvm<float>(const MvmBatch<float>&, const c128*, c128*, bool, hipStream_t);
+template void mvm<double>(const MvmBatch<double>&, const c128*, c128*, bool, hipStream_t);
+
+// ------------------------------------------------------------------ spectra setup
+// T(m) of the discretised dyadic Green's function (eq. (1) with the scalar
+// Green's function after it), collocated voxels: for m != 0 the dyadic
+// (I + grad grad / k0^2) g sampled at the centre separation R times
+// k0^2 dV,
+//   g [ (1 - j/u - 1/u^2) I + (3/u^2 + 3j/u - 1) Rhat Rhat ],  u = k0 |R|;
+// for m = 0 the integral of k0^2 G over the equal-volume sphere,
+//   ((2 (1 + j k0 a) exp(-j k0 a) - 3) / 3) I,  a = (3 dV / 4 pi)^(1/3).
+// Slot s of an axis of n voxels embedded in length L holds offset s (s < n),
+// s - L (s > L - n), nothing otherwise.  Output [6][lz][ly][lx], component
+// order xx, xy, xz, yy, yz, zz.
+__device__ __forceinline__ int slot_offset(int s, int n, int L, bool* ok) {
+  if (s < n) {
+    *ok = true;
+    return s;
+  }
+  if (s > L - n) {
+    *ok = true;
+    return s - L;
+  }
+  *ok = false;
+  return 0;
+}
+
+__global__ void k_green_embed(c128* out, int nx, int ny, int nz, int lx, int ly, int lz, double dx, double dy,
+                              double dz, double k0) {
+  const int64_t npts = (int64_t)lx * ly * lz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts) return;
+  const int sx = (int)(i % lx);
+  const int sy = (int)((i / lx) % ly);
+  const int sz = (int)(i / ((int64_t)lx * ly));
+  bool okx, oky, okz;
+  const int mx = slot_offset(sx, nx, lx, &okx);
+  const int my = slot_offset(sy, ny, ly, &oky);
+  const int mz = slot_offset(sz, nz, lz, &okz);
+  double t[6] = {0, 0, 0, 0, 0, 0};
+  double ti[6] = {0, 0, 0, 0, 0, 0};
+  if (okx && oky && okz) {
+    const double dV = dx * dy * dz;
+    if (mx == 0 && my == 0 && mz == 0) {
+      const double a = cbrt(3.0 * dV / (4.0 * M_PI));
+      const double x = k0 * a;
+      double sn, cs;
+      sincos(x, &sn, &cs);
+      // (1 + j x) exp(-j x) = (cos x + x sin x) + j (x cos x - sin x)
+      const double re = (2.0 * (cs + x * sn) - 3.0) / 3.0;
+      const double im = 2.0 * (x * cs - sn) / 3.0;
+      t[0] = t[3] = t[5] = re;
+      ti[0] = ti[3] = ti[5] = im;
+    } else {
+      const double Rx = mx * dx, Ry = my * dy, Rz = mz * dz;
+      const double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+      const double u = k0 * R;
+      double sn, cs;
+      sincos(u, &sn, &cs);
+      const double inv4piR = 1.0 / (4.0 * M_PI * R);
+      // pref = k0^2 dV g = k0^2 dV exp(-j u) / (4 pi R)
+      const double pr = k0 * k0 * dV * cs * inv4piR, pi = -k0 * k0 * dV * sn * inv4piR;
+      const double iu = 1.0 / u, iu2 = iu * iu;
+      const double ar = 1.0 - iu2, ai = -iu;          // 1 - j/u - 1/u^2
+      const double br = 3.0 * iu2 - 1.0, bi = 3.0 * iu;  // 3/u^2 + 3j/u - 1
+      const double rh[3] = {Rx / R, Ry / R, Rz / R};
+      const int ci[6] = {0, 0, 0, 1, 1, 2}, cj[6] = {0, 1, 2, 1, 2, 2};
+      for (int c = 0; c < 6; ++c) {
+        const double rr = rh[ci[c]] * rh[cj[c]];
+        double fr = br * rr, fi = bi * rr;
+        if (ci[c] == cj[c]) {
+          fr += ar;
+          fi += ai;
+        }
+        t[c] = pr * fr - pi * fi;
+        ti[c] = pr * fi + pi * fr;
+      }
+    }
+  }
+  for (int c = 0; c < 6; ++c) out[c * npts + i] = mk<double>(t[c], ti[c]);
+}
+
+__global__ void k_extract_octant(const c128* full, c128* s64, c64* s32, int lx, int ly, int lz) {
+  const int ox = lx / 2 + 1, oy = ly / 2 + 1, oz = lz / 2 + 1;
+  const int64_t oct = (int64_t)ox * oy * oz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 6 * oct) return;
+  const int c = (int)(i / oct);
+  const int64_t r = i - c * oct;
+  const int fx = (int)(r % ox), fy = (int)((r / ox) % oy), fz = (int)(r / ((int64_t)ox * oy));
+  const c128 v = full[(int64_t)c * lx * ly * lz + ((int64_t)fz * ly + fy) * lx + fx];
+  if (s64) s64[i] = v;
+  if (s32) s32[i] = cvt<float>(v);
+}
+
+template <int L>
+static void launch_row_full_L(c128* data, int64_t rows, const c128* tw, hipStream_t s) {
+  using G = Geo<double, L>;
+  const int64_t blocks = (rows + G::ROWP - 1) / G::ROWP;
+  hipLaunchKernelGGL((k_row_full<double, L>), dim3((unsigned)blocks), dim3(G::T * G::ROWP), 0, s, data, rows, tw);
+}
+
+static void launch_row_full(int L, c128* data, int64_t rows, const c128* tw, hipStream_t s) {
+  switch (L) {
+#define C(l)                                  \
+  case l:                                     \
+    launch_row_full_L<l>(data, rows, tw, s); \
+    break;
+    VIE_L_CASES(C)
+#undef C
+    default:
+      bad_length("setup x pass", L);
+  }
+  check_launch("setup x pass");
+}
+
+void green_spectra(int nx, int ny, int nz, int lx, int ly, int lz, double dx, double dy, double dz, double k0,
+                   c128* scratch, c128* spec64, c64* spec32, const TwiddleSet<double>& tw, hipStream_t s) {
+  const int64_t npts = (int64_t)lx * ly * lz;
+  hipLaunchKernelGGL(k_green_embed, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, scratch, nx, ny, nz, lx,
+                     ly, lz, dx, dy, dz, k0);
+  check_launch("green embed");
+  launch_row_full(lx, scratch, 6 * (int64_t)ly * lz, tw.table[lx], s);
+  ColArgs<double> ca{};
+  ca.data = scratch;
+  ca.outer = 6 * lz;
+  ca.inner = lx;
+  ca.n_in = ly;
+  ca.n_out = ly;
+  ca.stride = 0;
+  ca.status = nullptr;
+  ca.tw = tw.table[ly];
+  ca.nsys = 1;
+  launch_col<double, -1>(ly, ca, s);
+  ca.outer = 6;
+  ca.inner = lx * ly;
+  ca.n_in = lz;
+  ca.n_out = lz;
+  ca.tw = tw.table[lz];
+  launch_col<double, -1>(lz, ca, s);
+  const int64_t oct = 6 * (int64_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1);
+  hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, s, scratch, spec64, spec32,
+                     lx, ly, lz);
+  check_launch("octant");
+}
+
+}  // namespace vie

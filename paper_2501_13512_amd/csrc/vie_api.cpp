@@ -1,0 +1,934 @@
+// C ABI of libvie: context, problem set-up (block plan, spectra cache),
+// products, preconditioner and the block-preconditioned BiCGSTAB driver.
+// See include/vie.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+#include "vie.h"
+
+using vie::KBatch;
+using vie::KState;
+using vie::MvmBatch;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct VieError : std::runtime_error {
+  vie_status code;
+  VieError(vie_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(vie_status c, const std::string& m) { throw VieError(c, m); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    fail(VIE_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+  fail(VIE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  void alloc(size_t n) {
+    reset();
+    if (n == 0) return;
+    hip_check(hipMalloc(&p, n), "hipMalloc");
+    bytes = n;
+  }
+  void zero() {
+    if (p) hip_check(hipMemset(p, 0, bytes), "hipMemset");
+  }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { reset(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+template <class T>
+void upload(DevBuf& d, const std::vector<T>& h) {
+  d.alloc(h.size() * sizeof(T));
+  if (!h.empty()) hip_check(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+}
+
+template <class F>
+vie_status guarded(F&& f) {
+  try {
+    vie_status s = f();
+    if (s == VIE_OK) g_last_error.clear();
+    return s;
+  } catch (const VieError& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return VIE_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return VIE_EINTERNAL;
+  } catch (...) {
+    g_last_error = "unknown internal error";
+    return VIE_EINTERNAL;
+  }
+}
+
+// exp(-2 pi i t / L) with exact values on the quadrant points.
+void cis_neg(long t, long L, double* c, double* s) {
+  t %= L;
+  const long q = (4 * t) / L;
+  const long r4 = 4 * t - q * L;  // angle = (q + r4 / L) pi / 2
+  double cs, sn;
+  if (2 * r4 <= L) {
+    const double th = (M_PI / 2) * (double)r4 / (double)L;
+    cs = std::cos(th);
+    sn = std::sin(th);
+  } else {
+    const double th = (M_PI / 2) * (double)(L - r4) / (double)L;
+    cs = std::sin(th);
+    sn = std::cos(th);
+  }
+  double C, S;
+  switch (q) {
+    case 0: C = cs; S = sn; break;
+    case 1: C = -sn; S = cs; break;
+    case 2: C = -cs; S = -sn; break;
+    default: C = sn; S = -cs; break;
+  }
+  *c = C;
+  *s = -S;
+}
+
+struct SpecKey {
+  int lx, ly, lz;
+  double dx, dy, dz, k0;
+  bool operator<(const SpecKey& o) const {
+    return std::tie(lx, ly, lz, dx, dy, dz, k0) < std::tie(o.lx, o.ly, o.lz, o.dx, o.dy, o.dz, o.k0);
+  }
+};
+
+struct Spectra {
+  DevBuf s64, s32;
+  size_t bytes() const { return s64.bytes + s32.bytes; }
+};
+
+constexpr int kRing = 16;
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct vie_context {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  hipStream_t stream = nullptr;
+  DevBuf tw64, tw32;
+  vie::TwiddleSet<double> tws64{};
+  vie::TwiddleSet<float> tws32{};
+  std::mutex mu;
+  std::map<SpecKey, std::weak_ptr<Spectra>> cache;
+};
+
+namespace {
+
+std::shared_ptr<Spectra> get_spectra(vie_context* ctx, int lx, int ly, int lz, double dx, double dy, double dz,
+                                     double k0) {
+  SpecKey key{lx, ly, lz, dx, dy, dz, k0};
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->cache.find(key);
+    if (it != ctx->cache.end())
+      if (auto sp = it->second.lock()) return sp;
+  }
+  auto sp = std::make_shared<Spectra>();
+  const int64_t oct = 6 * (int64_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1);
+  sp->s64.alloc(oct * sizeof(c128));
+  sp->s32.alloc(oct * sizeof(c64));
+  DevBuf scratch(6 * (size_t)lx * ly * lz * sizeof(c128));
+  // embed with the largest box the lengths support: a box of n <= (L+1)/2
+  // voxels touches only offsets |m| <= n - 1, all of which are present.
+  vie::green_spectra((lx + 1) / 2, (ly + 1) / 2, (lz + 1) / 2, lx, ly, lz, dx, dy, dz, k0, scratch.as<c128>(),
+                     sp->s64.as<c128>(), sp->s32.as<c64>(), ctx->tws64, ctx->stream);
+  hip_check(hipStreamSynchronize(ctx->stream), "spectra");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->cache[key] = sp;
+  return sp;
+}
+
+// Krylov vectors of a batch of systems.
+enum VecKind { V_B = 0, V_X, V_R, V_RHAT, V_P, V_V, V_S, V_T, V_Y, V_Z, V_TMP1, V_TMP2, V_COUNT };
+
+struct Group {
+  int bx, by, bz, lx, ly, lz, nsys;
+  int64_t bnv, n;
+  std::shared_ptr<Spectra> spec;
+  DevBuf chi, work, vecs, partials;
+  c128* vec[8];  // B, X, R, RHAT, P, V, S, T
+  int slot0;     // first entry in the problem's inner status/state arrays
+  std::vector<int> blocks;
+};
+
+}  // namespace
+
+struct vie_problem {
+  vie_context* ctx = nullptr;
+  vie_grid g{};
+  int64_t nv = 0;
+  int lx = 0, ly = 0, lz = 0;
+  double k0 = 0;
+  std::shared_ptr<Spectra> spec;
+  DevBuf chi, work, vecs, partials, ostate, ostatus, scal;
+  c128* vec[V_COUNT] = {};
+  // blocks
+  int n_blocks = 0, n_nonempty = 0;
+  std::vector<Group> groups;
+  DevBuf d_block_id, d_block_group, d_block_sys, d_block_origin, d_gbox, d_gptr, d_istatus, d_istate, d_slots;
+  DevBuf d_acc, d_hist, d_count;
+  int n_inner = 0;
+  vie::BlockMap bmap{};
+  // polling: ring 0 for the outer loop, ring 1 for the inner loops
+  int* h_ring = nullptr;
+  hipEvent_t ev[2][kRing] = {};
+  std::mutex mu;
+  size_t footprint = 0;
+
+  ~vie_problem() {
+    for (auto& r : ev)
+      for (auto& e : r)
+        if (e) (void)hipEventDestroy(e);
+    if (h_ring) (void)hipHostFree(h_ring);
+  }
+};
+
+namespace {
+
+// Progress checks that trail the enqueued work (pinned ring + events).
+struct Poller {
+  vie_problem& P;
+  hipStream_t s;
+  int ring;
+  long n = 0;
+  Poller(vie_problem& p, hipStream_t st, int which) : P(p), s(st), ring(which) {}
+  long push(const int* dval) {
+    const int slot = (int)(n % kRing);
+    hip_check(hipMemcpyAsync(&P.h_ring[ring * kRing + slot], dval, sizeof(int), hipMemcpyDeviceToHost, s),
+              "poll copy");
+    hip_check(hipEventRecord(P.ev[ring][slot], s), "poll event");
+    return n++;
+  }
+  int wait(long ticket) {
+    const int slot = (int)(ticket % kRing);
+    hip_check(hipEventSynchronize(P.ev[ring][slot]), "poll wait");
+    return P.h_ring[ring * kRing + slot];
+  }
+};
+
+template <typename R>
+const cx<R>* spec_ptr(const Spectra& s);
+template <>
+const cx<double>* spec_ptr<double>(const Spectra& s) {
+  return s.s64.as<c128>();
+}
+template <>
+const cx<float>* spec_ptr<float>(const Spectra& s) {
+  return s.s32.as<c64>();
+}
+template <typename R>
+const vie::TwiddleSet<R>* tw_set(vie_context* c);
+template <>
+const vie::TwiddleSet<double>* tw_set<double>(vie_context* c) {
+  return &c->tws64;
+}
+template <>
+const vie::TwiddleSet<float>* tw_set<float>(vie_context* c) {
+  return &c->tws32;
+}
+
+template <typename R>
+MvmBatch<R> outer_batch(vie_problem& P, bool gated) {
+  MvmBatch<R> b{};
+  b.nx = P.g.nx;
+  b.ny = P.g.ny;
+  b.nz = P.g.nz;
+  b.lx = P.lx;
+  b.ly = P.ly;
+  b.lz = P.lz;
+  b.nsys = 1;
+  b.vstride = 3 * P.nv;
+  b.cstride = P.nv;
+  b.wstride = 3 * (int64_t)P.g.nz * P.ly * P.lx;
+  b.sstride = 0;
+  b.chi_inv = P.chi.as<c128>();
+  b.spec = spec_ptr<R>(*P.spec);
+  b.work = P.work.as<cx<R>>();
+  b.status = gated ? P.ostatus.as<int>() : nullptr;
+  b.tw = tw_set<R>(P.ctx);
+  return b;
+}
+
+template <typename R>
+MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
+  MvmBatch<R> b{};
+  b.nx = G.bx;
+  b.ny = G.by;
+  b.nz = G.bz;
+  b.lx = G.lx;
+  b.ly = G.ly;
+  b.lz = G.lz;
+  b.nsys = G.nsys;
+  b.vstride = G.n;
+  b.cstride = G.bnv;
+  b.wstride = 3 * (int64_t)G.bz * G.ly * G.lx;
+  b.sstride = 0;
+  b.chi_inv = G.chi.as<c128>();
+  b.spec = spec_ptr<R>(*G.spec);
+  b.work = G.work.as<cx<R>>();
+  b.status = gated ? P.d_istatus.as<int>() + G.slot0 : nullptr;
+  b.tw = tw_set<R>(P.ctx);
+  return b;
+}
+
+KBatch outer_kbatch(vie_problem& P) {
+  KBatch k{};
+  k.nsys = 1;
+  k.n = 3 * P.nv;
+  k.status = P.ostatus.as<int>();
+  k.st = P.ostate.as<KState>();
+  k.partials = P.partials.as<double>();
+  return k;
+}
+
+KBatch group_kbatch(vie_problem& P, Group& G) {
+  KBatch k{};
+  k.nsys = G.nsys;
+  k.n = G.n;
+  k.status = P.d_istatus.as<int>() + G.slot0;
+  k.st = P.d_istate.as<KState>() + G.slot0;
+  k.partials = G.partials.as<double>();
+  return k;
+}
+
+c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (size_t)kind * P.groups.size(); }
+
+// y = K2^{-1} w: batched inner BiCGSTAB-FFT solves of every block (Sec. II-B).
+template <typename R>
+void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit, const int* gate, int lag,
+                   int32_t* hist, int64_t hist_cap, hipStream_t s) {
+  vie::block_gather(P.bmap, w, gptr(P, V_B), s);
+  for (auto& G : P.groups) {
+    KBatch k = group_kbatch(P, G);
+    vie::k_init(k, G.vec[V_B], G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], tol, maxit, gate, s);
+  }
+  Poller poll(P, s, 1);
+  for (int it = 1; it <= maxit; ++it) {
+    for (auto& G : P.groups) {
+      KBatch k = group_kbatch(P, G);
+      MvmBatch<R> m = group_batch<R>(P, G, true);
+      c128** v = G.vec;
+      vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
+      vie::mvm<R>(m, v[V_P], v[V_V], false, s);
+      vie::k_alpha(k, v[V_RHAT], v[V_V], s);
+      vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
+      vie::mvm<R>(m, v[V_S], v[V_T], false, s);
+      vie::k_omega(k, v[V_T], v[V_S], s);
+      vie::k_update_xr(k, v[V_X], v[V_P], v[V_S], v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
+    }
+    vie::count_active(P.d_istatus.as<int>(), P.n_inner, P.d_count.as<int>(), s);
+    const long t = poll.push(P.d_count.as<int>());
+    if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
+  }
+  vie::block_scatter(P.bmap, gptr(P, V_X), y, s);
+  vie::record_inner(gate, P.d_istate.as<KState>(), P.d_slots.as<int>(), P.n_nonempty, P.d_acc.as<int64_t>(), hist,
+                    hist_cap, s);
+}
+
+struct RunResult {
+  KState st;
+  int status;
+};
+
+// Right-preconditioned BiCGSTAB on the full grid: A x = rhs (Sec. II-B).
+template <typename R>
+RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int maxit, bool prec, double tol_in,
+                       int maxit_in, int lag, int32_t* hist, int64_t hist_cap, hipStream_t s) {
+  KBatch k = outer_kbatch(P);
+  MvmBatch<R> m = outer_batch<R>(P, true);
+  c128** v = P.vec;
+  const int* gate = P.ostatus.as<int>();
+  vie::k_init(k, rhs, x, v[V_R], v[V_RHAT], tol, maxit, nullptr, s);
+  Poller poll(P, s, 0);
+  for (int it = 1; it <= maxit; ++it) {
+    vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
+    c128* yv = v[V_P];
+    if (prec) {
+      yv = v[V_Y];
+      precond_apply<R>(P, v[V_P], yv, tol_in, maxit_in, gate, lag, hist, hist_cap, s);
+    }
+    vie::mvm<R>(m, yv, v[V_V], false, s);
+    vie::k_alpha(k, v[V_RHAT], v[V_V], s);
+    vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
+    c128* zv = v[V_S];
+    if (prec) {
+      zv = v[V_Z];
+      precond_apply<R>(P, v[V_S], zv, tol_in, maxit_in, gate, lag, hist, hist_cap, s);
+    }
+    vie::mvm<R>(m, zv, v[V_T], false, s);
+    vie::k_omega(k, v[V_T], v[V_S], s);
+    vie::k_update_xr(k, x, yv, zv, v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
+    const long t = poll.push(P.ostatus.as<int>());
+    if (t - lag >= 0 && poll.wait(t - lag) != vie::ST_ACTIVE) break;
+  }
+  hip_check(hipStreamSynchronize(s), "solve");
+  RunResult r{};
+  hip_check(hipMemcpy(&r.st, P.ostate.p, sizeof(KState), hipMemcpyDeviceToHost), "state");
+  hip_check(hipMemcpy(&r.status, P.ostatus.p, sizeof(int), hipMemcpyDeviceToHost), "state");
+  return r;
+}
+
+double true_relres(vie_problem& P, const c128* rhs, const c128* x, c128* tmp_ax, c128* tmp_r, double nb,
+                   hipStream_t s) {
+  MvmBatch<double> m = outer_batch<double>(P, false);
+  vie::mvm<double>(m, x, tmp_ax, false, s);
+  vie::sub_vec(rhs, tmp_ax, tmp_r, 3 * P.nv, s);
+  vie::norm2(tmp_r, 3 * P.nv, P.partials.as<double>(), P.scal.as<double>(), s);
+  double r2 = 0;
+  hip_check(hipMemcpyAsync(&r2, P.scal.p, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
+  hip_check(hipStreamSynchronize(s), "norm");
+  return nb > 0 ? std::sqrt(r2) / nb : 0.0;
+}
+
+void validate_opts(const vie_opts* o, const vie_problem* p) {
+  if (!o) fail(VIE_EINVAL, "opts is NULL");
+  if (!(o->tol_outer >= 0) || !is_finite(o->tol_outer)) fail(VIE_EINVAL, "tol_outer must be finite and >= 0");
+  if (o->maxit_outer < 0 || o->maxit_outer > 1000000) fail(VIE_EINVAL, "maxit_outer out of range");
+  if (o->precision != VIE_FP64 && o->precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
+  if (o->poll_lag < 0 || o->poll_lag > kRing - 2) fail(VIE_EINVAL, "poll_lag out of range");
+  if (o->max_refine < 0 || o->max_refine > 100) fail(VIE_EINVAL, "max_refine out of range");
+  if (o->precondition) {
+    if (p->groups.empty()) fail(VIE_EINVAL, "precondition requested but the problem has no blocks");
+    if (!(o->tol_inner >= 0) || !is_finite(o->tol_inner)) fail(VIE_EINVAL, "tol_inner must be finite and >= 0");
+    if (o->maxit_inner < 1 || o->maxit_inner > 1000000) fail(VIE_EINVAL, "maxit_inner out of range");
+  }
+}
+
+void set_device(vie_context* ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
+
+vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128* e_tot, c128* pol,
+                      vie_stats* stats, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  vie_problem& P = *p;
+  c128** v = P.vec;
+  const bool prec = o->precondition != 0;
+  int32_t* hist = nullptr;
+  int64_t hist_cap = 0;
+  if (stats && stats->inner_hist && stats->inner_hist_cap > 0 && prec) {
+    P.d_hist.alloc((size_t)stats->inner_hist_cap * sizeof(int32_t));
+    hist = P.d_hist.as<int32_t>();
+    hist_cap = stats->inner_hist_cap;
+  }
+  if (prec) hip_check(hipMemsetAsync(P.d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
+  vie::masked_copy(e_inc, P.chi.as<c128>(), v[V_B], P.nv, s);
+  RunResult rr;
+  int refine = 0, refine_iters = 0;
+  double relres_true = 0;
+  if (o->precision == VIE_FP64) {
+    rr = run_bicgstab<double>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
+                              o->poll_lag, hist, hist_cap, s);
+    relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], rr.st.nb, s);
+  } else {
+    rr = run_bicgstab<float>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
+                             o->poll_lag, hist, hist_cap, s);
+    const double nb = rr.st.nb;
+    relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
+    // iterative refinement: solve A d = b - A x with FP32 products, x += d
+    while (rr.status != vie::ST_BREAKDOWN && relres_true > o->tol_outer && refine < o->max_refine && nb > 0) {
+      const double tol_c = std::min(0.5, o->tol_outer / relres_true);
+      RunResult rc = run_bicgstab<float>(P, v[V_TMP2], v[V_TMP1], tol_c, o->maxit_outer, prec, o->tol_inner,
+                                         o->maxit_inner, o->poll_lag, hist, hist_cap, s);
+      vie::add_vec(v[V_X], v[V_TMP1], 3 * P.nv, s);
+      ++refine;
+      refine_iters += rc.st.iters;
+      relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
+    }
+  }
+  vie::total_field(v[V_X], P.chi.as<c128>(), e_tot, P.nv, 3, s);
+  if (pol) hip_check(hipMemcpyAsync(pol, v[V_X], 3 * P.nv * sizeof(c128), hipMemcpyDeviceToDevice, s), "pol");
+  int64_t acc[3] = {0, 0, 0};
+  if (prec) hip_check(hipMemcpyAsync(acc, P.d_acc.p, sizeof(acc), hipMemcpyDeviceToHost, s), "acc");
+  hip_check(hipStreamSynchronize(s), "solve end");
+  if (stats) {
+    stats->outer_iters = rr.st.iters;
+    stats->refine_steps = refine;
+    stats->refine_iters = refine_iters;
+    stats->inner_iters_total = acc[0];
+    stats->precond_applies = acc[1];
+    stats->relres_recursive = rr.st.rnorm;
+    stats->relres_true = relres_true;
+    stats->final_state = rr.status == vie::ST_BREAKDOWN ? 3 : (rr.status == vie::ST_CONVERGED ? 1 : 4);
+    stats->inner_hist_len = 0;
+    if (hist) {
+      const int64_t len = std::min<int64_t>(acc[2], hist_cap);
+      if (acc[2] <= hist_cap) {
+        hip_check(hipMemcpy(stats->inner_hist, hist, len * sizeof(int32_t), hipMemcpyDeviceToHost), "hist");
+        stats->inner_hist_len = len;
+      }
+    }
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (rr.status == vie::ST_BREAKDOWN) {
+    g_last_error = "BiCGSTAB breakdown (last iterate written)";
+    return VIE_EBREAKDOWN;
+  }
+  if (rr.status == vie::ST_CONVERGED || rr.status == vie::ST_HALF) {
+    if (o->precision == VIE_MIXED && relres_true > o->tol_outer) {
+      g_last_error = "mixed-precision solve stopped above tol_outer after refinement";
+      return VIE_NOT_CONVERGED;
+    }
+    return VIE_OK;
+  }
+  g_last_error = "iteration cap reached";
+  return VIE_NOT_CONVERGED;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int32_t vie_abi_version(void) { return VIE_ABI_VERSION; }
+
+const char* vie_last_error(void) { return g_last_error.c_str(); }
+
+vie_status vie_context_create(int32_t device, size_t hbm_budget_bytes, vie_context** out) {
+  return guarded([&]() -> vie_status {
+    if (!out) fail(VIE_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) fail(VIE_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= n) fail(VIE_EDEVICE, "device index out of range");
+    auto ctx = std::make_unique<vie_context>();
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    set_device(ctx.get());
+    hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "stream");
+    // twiddle tables for every supported length, both precisions
+    size_t total = 0;
+    for (int L : vie::kFftLengths) total += L;
+    std::vector<c128> h64(total);
+    std::vector<c64> h32(total);
+    size_t off = 0;
+    for (int L : vie::kFftLengths) {
+      for (int t = 0; t < L; ++t) {
+        double c, sn;
+        cis_neg(t, L, &c, &sn);
+        h64[off + t] = mk<double>(c, sn);
+        h32[off + t] = mk<float>((float)c, (float)sn);
+      }
+      off += L;
+    }
+    upload(ctx->tw64, h64);
+    upload(ctx->tw32, h32);
+    off = 0;
+    for (int L : vie::kFftLengths) {
+      ctx->tws64.table[L] = ctx->tw64.as<c128>() + off;
+      ctx->tws32.table[L] = ctx->tw32.as<c64>() + off;
+      off += L;
+    }
+    *out = ctx.release();
+    return VIE_OK;
+  });
+}
+
+vie_status vie_context_destroy(vie_context* ctx) {
+  return guarded([&]() -> vie_status {
+    if (!ctx) return VIE_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return VIE_OK;
+  });
+}
+
+vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
+                              int32_t n_blocks, vie_problem** out) {
+  return guarded([&]() -> vie_status {
+    if (!out) fail(VIE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx || !grid || !eps_r) fail(VIE_EINVAL, "ctx, grid and eps_r are required");
+    const vie_grid g = *grid;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > 256 || g.ny > 256 || g.nz > 256)
+      fail(VIE_EINVAL, "grid sizes must be in [1, 256]");
+    if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !(g.wavelength > 0) || !is_finite(g.dx) || !is_finite(g.dy) ||
+        !is_finite(g.dz) || !is_finite(g.wavelength))
+      fail(VIE_EINVAL, "spacing and wavelength must be finite and > 0");
+    if (block_id && n_blocks < 1) fail(VIE_EINVAL, "n_blocks must be >= 1 when block_id is given");
+    if (n_blocks < 0) fail(VIE_EINVAL, "n_blocks must be >= 0");
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    // 1/chi on the host
+    std::vector<c128> chi(nv);
+    for (int64_t i = 0; i < nv; ++i) {
+      const double er = eps_r[2 * i], ei = eps_r[2 * i + 1];
+      if (!is_finite(er) || !is_finite(ei)) fail(VIE_EINVAL, "eps_r has non-finite entries");
+      if (er == 1.0 && ei == 0.0) {
+        chi[i] = mk<double>(0.0, 0.0);
+      } else {
+        const std::complex<double> c = 1.0 / (std::complex<double>(er, ei) - 1.0);
+        chi[i] = mk<double>(c.real(), c.imag());
+      }
+    }
+    std::vector<int32_t> bid;
+    if (block_id) {
+      bid.assign(nv, -1);
+      for (int64_t i = 0; i < nv; ++i) {
+        const bool vac = chi[i].x == 0.0 && chi[i].y == 0.0;
+        if (vac) continue;
+        const int32_t k = block_id[i];
+        if (k < 0 || k >= n_blocks) fail(VIE_EINVAL, "block id out of range on a scatterer voxel");
+        bid[i] = k;
+      }
+    }
+    set_device(ctx);
+    auto P = std::make_unique<vie_problem>();
+    P->ctx = ctx;
+    P->g = g;
+    P->nv = nv;
+    P->lx = vie::smallest_fft_length(2 * g.nx - 1);
+    P->ly = vie::smallest_fft_length(2 * g.ny - 1);
+    P->lz = vie::smallest_fft_length(2 * g.nz - 1);
+    if (P->lx < 0 || P->ly < 0 || P->lz < 0) fail(VIE_EINVAL, "grid too large for the compiled FFT lengths");
+    P->k0 = 2.0 * M_PI / g.wavelength;
+    P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0);
+    upload(P->chi, chi);
+    P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
+    P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
+    P->vecs.zero();
+    for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
+    P->partials.alloc(vie::krylov_chunks(3 * nv) * 4 * sizeof(double));
+    P->ostate.alloc(sizeof(KState));
+    P->ostate.zero();
+    P->ostatus.alloc(sizeof(int));
+    P->ostatus.zero();
+    P->scal.alloc(64);
+    P->d_count.alloc(sizeof(int));
+    P->d_acc.alloc(3 * sizeof(int64_t));
+    P->d_acc.zero();
+    hip_check(hipHostMalloc((void**)&P->h_ring, 2 * kRing * sizeof(int)), "pinned ring");
+    for (auto& r : P->ev)
+      for (auto& e : r) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+
+    size_t foot = P->chi.bytes + P->work.bytes + P->vecs.bytes + P->partials.bytes + P->spec->bytes();
+
+    if (block_id) {
+      // tight bounding box of every block
+      P->n_blocks = n_blocks;
+      std::vector<int> lo(3 * n_blocks, 1 << 30), hi(3 * n_blocks, -1);
+      std::vector<int64_t> cnt(n_blocks, 0);
+      for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+          for (int x = 0; x < g.nx; ++x) {
+            const int k = bid[((int64_t)z * g.ny + y) * g.nx + x];
+            if (k < 0) continue;
+            cnt[k]++;
+            const int c[3] = {x, y, z};
+            for (int a = 0; a < 3; ++a) {
+              lo[3 * k + a] = std::min(lo[3 * k + a], c[a]);
+              hi[3 * k + a] = std::max(hi[3 * k + a], c[a]);
+            }
+          }
+      // group blocks by circulant lengths of their bounding boxes
+      std::map<std::tuple<int, int, int>, std::vector<int>> bylen;
+      for (int k = 0; k < n_blocks; ++k) {
+        if (cnt[k] == 0) continue;
+        const int ex = hi[3 * k] - lo[3 * k] + 1, ey = hi[3 * k + 1] - lo[3 * k + 1] + 1,
+                  ez = hi[3 * k + 2] - lo[3 * k + 2] + 1;
+        bylen[{vie::smallest_fft_length(2 * ex - 1), vie::smallest_fft_length(2 * ey - 1),
+               vie::smallest_fft_length(2 * ez - 1)}]
+            .push_back(k);
+      }
+      std::vector<int> block_group(n_blocks, -1), block_sys(n_blocks, -1);
+      std::vector<int4> origin(n_blocks, int4{0, 0, 0, 0}), gbox;
+      int slot = 0;
+      for (auto& kv : bylen) {
+        Group G{};
+        G.lx = std::get<0>(kv.first);
+        G.ly = std::get<1>(kv.first);
+        G.lz = std::get<2>(kv.first);
+        G.blocks = kv.second;
+        G.nsys = (int)G.blocks.size();
+        G.bx = G.by = G.bz = 1;
+        for (int k : G.blocks) {
+          G.bx = std::max(G.bx, hi[3 * k] - lo[3 * k] + 1);
+          G.by = std::max(G.by, hi[3 * k + 1] - lo[3 * k + 1] + 1);
+          G.bz = std::max(G.bz, hi[3 * k + 2] - lo[3 * k + 2] + 1);
+        }
+        G.bnv = (int64_t)G.bx * G.by * G.bz;
+        G.n = 3 * G.bnv;
+        const int gi = (int)P->groups.size();
+        std::vector<c128> gchi((size_t)G.nsys * G.bnv, mk<double>(0.0, 0.0));
+        for (int s = 0; s < G.nsys; ++s) {
+          const int k = G.blocks[s];
+          block_group[k] = gi;
+          block_sys[k] = s;
+          origin[k] = int4{lo[3 * k], lo[3 * k + 1], lo[3 * k + 2], 0};
+          for (int z = 0; z < G.bz; ++z)
+            for (int y = 0; y < G.by; ++y)
+              for (int x = 0; x < G.bx; ++x) {
+                const int X = lo[3 * k] + x, Y = lo[3 * k + 1] + y, Z = lo[3 * k + 2] + z;
+                if (X >= g.nx || Y >= g.ny || Z >= g.nz) continue;
+                const int64_t v = ((int64_t)Z * g.ny + Y) * g.nx + X;
+                if (bid[v] == k) gchi[(size_t)s * G.bnv + ((int64_t)z * G.by + y) * G.bx + x] = chi[v];
+              }
+        }
+        gbox.push_back(int4{G.bx, G.by, G.bz, 0});
+        upload(G.chi, gchi);
+        G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0);
+        G.work.alloc((size_t)G.nsys * 3 * G.bz * G.ly * G.lx * sizeof(c128));
+        G.vecs.alloc(8 * (size_t)G.nsys * G.n * sizeof(c128));
+        G.vecs.zero();
+        for (int q = 0; q < 8; ++q) G.vec[q] = G.vecs.as<c128>() + (size_t)q * G.nsys * G.n;
+        G.partials.alloc((size_t)G.nsys * vie::krylov_chunks(G.n) * 4 * sizeof(double));
+        G.slot0 = slot;
+        slot += G.nsys;
+        foot += G.chi.bytes + G.work.bytes + G.vecs.bytes + G.partials.bytes + G.spec->bytes();
+        P->groups.push_back(std::move(G));
+      }
+      P->n_inner = slot;
+      std::vector<int> slots;
+      for (int k = 0; k < n_blocks; ++k)
+        if (cnt[k] > 0) slots.push_back(P->groups[block_group[k]].slot0 + block_sys[k]);
+      P->n_nonempty = (int)slots.size();
+      upload(P->d_block_id, bid);
+      upload(P->d_block_group, block_group);
+      upload(P->d_block_sys, block_sys);
+      upload(P->d_block_origin, origin);
+      upload(P->d_gbox, gbox);
+      upload(P->d_slots, slots);
+      std::vector<c128*> ptrs(8 * P->groups.size());
+      for (size_t gi = 0; gi < P->groups.size(); ++gi)
+        for (int q = 0; q < 8; ++q) ptrs[q * P->groups.size() + gi] = P->groups[gi].vec[q];
+      upload(P->d_gptr, ptrs);
+      P->d_istatus.alloc(std::max(1, slot) * sizeof(int));
+      P->d_istatus.zero();
+      P->d_istate.alloc(std::max(1, slot) * sizeof(KState));
+      P->d_istate.zero();
+      vie::BlockMap& m = P->bmap;
+      m.nblocks = n_blocks;
+      m.ngroups = (int)P->groups.size();
+      m.block_id = P->d_block_id.as<int>();
+      m.block_group = P->d_block_group.as<int>();
+      m.block_sys = P->d_block_sys.as<int>();
+      m.block_origin = P->d_block_origin.as<int4>();
+      m.gbox = P->d_gbox.as<int4>();
+      m.nx = g.nx;
+      m.ny = g.ny;
+      m.nz = g.nz;
+    }
+    P->footprint = foot;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      if (ctx->budget && ctx->used + foot > ctx->budget) fail(VIE_EBUSY, "problem exceeds the context's HBM budget");
+      ctx->used += foot;
+    }
+    hip_check(hipDeviceSynchronize(), "problem set-up");
+    *out = P.release();
+    return VIE_OK;
+  });
+}
+
+vie_status vie_problem_destroy(vie_problem* p) {
+  return guarded([&]() -> vie_status {
+    if (!p) return VIE_OK;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    {
+      std::lock_guard<std::mutex> lk(p->ctx->mu);
+      p->ctx->used -= std::min(p->ctx->used, p->footprint);
+    }
+    delete p;
+    return VIE_OK;
+  });
+}
+
+vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info) {
+  return guarded([&]() -> vie_status {
+    if (!p || !info) fail(VIE_EINVAL, "problem and info are required");
+    info->lx = p->lx;
+    info->ly = p->ly;
+    info->lz = p->lz;
+    info->n_blocks = p->n_nonempty;
+    info->n_groups = (int32_t)p->groups.size();
+    info->footprint_bytes = (int64_t)p->footprint;
+    return VIE_OK;
+  });
+}
+
+vie_status vie_plane_wave(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc) {
+  return guarded([&]() -> vie_status {
+    if (!grid || !kdir || !pol || !e_inc) fail(VIE_EINVAL, "all arguments are required");
+    const vie_grid g = *grid;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) fail(VIE_EINVAL, "grid sizes must be >= 1");
+    if (!(g.wavelength > 0) || !is_finite(g.wavelength) || !is_finite(g.dx) || !is_finite(g.dy) || !is_finite(g.dz))
+      fail(VIE_EINVAL, "bad spacing or wavelength");
+    const double kn = std::sqrt(kdir[0] * kdir[0] + kdir[1] * kdir[1] + kdir[2] * kdir[2]);
+    if (!(std::fabs(kn - 1.0) <= 1e-12)) fail(VIE_EINVAL, "kdir must be a unit vector");
+    for (int i = 0; i < 6; ++i)
+      if (!is_finite(pol[i])) fail(VIE_EINVAL, "pol has non-finite entries");
+    const double k0 = 2.0 * M_PI / g.wavelength;
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    for (int z = 0; z < g.nz; ++z)
+      for (int y = 0; y < g.ny; ++y)
+        for (int x = 0; x < g.nx; ++x) {
+          const double rx = (x - 0.5 * (g.nx - 1)) * g.dx, ry = (y - 0.5 * (g.ny - 1)) * g.dy,
+                       rz = (z - 0.5 * (g.nz - 1)) * g.dz;
+          const double ph = -k0 * (kdir[0] * rx + kdir[1] * ry + kdir[2] * rz);
+          const std::complex<double> e = std::polar(1.0, ph);
+          const int64_t v = ((int64_t)z * g.ny + y) * g.nx + x;
+          for (int c = 0; c < 3; ++c) {
+            const std::complex<double> val = std::complex<double>(pol[2 * c], pol[2 * c + 1]) * e;
+            e_inc[2 * (c * nv + v)] = val.real();
+            e_inc[2 * (c * nv + v) + 1] = val.imag();
+          }
+        }
+    return VIE_OK;
+  });
+}
+
+vie_status vie_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !x_dev || !y_dev) fail(VIE_EINVAL, "problem, x and y are required");
+    if (x_dev == y_dev) fail(VIE_EINVAL, "x and y must not overlap");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == VIE_FP64)
+      vie::mvm<double>(outer_batch<double>(*p, false), (const c128*)x_dev, (c128*)y_dev, true, s);
+    else if (precision == VIE_MIXED)
+      vie::mvm<float>(outer_batch<float>(*p, false), (const c128*)x_dev, (c128*)y_dev, true, s);
+    else
+      fail(VIE_EINVAL, "unknown precision");
+    return VIE_OK;
+  });
+}
+
+vie_status vie_block_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !x_dev || !y_dev) fail(VIE_EINVAL, "problem, x and y are required");
+    if (x_dev == y_dev) fail(VIE_EINVAL, "x and y must not overlap");
+    if (p->groups.empty()) fail(VIE_EINVAL, "problem has no blocks");
+    if (precision != VIE_FP64 && precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    hipStream_t s = (hipStream_t)stream;
+    vie::block_gather(p->bmap, (const c128*)x_dev, gptr(*p, V_B), s);
+    for (auto& G : p->groups) {
+      if (precision == VIE_FP64)
+        vie::mvm<double>(group_batch<double>(*p, G, false), G.vec[V_B], G.vec[V_V], false, s);
+      else
+        vie::mvm<float>(group_batch<float>(*p, G, false), G.vec[V_B], G.vec[V_V], false, s);
+    }
+    vie::block_scatter(p->bmap, gptr(*p, V_V), (c128*)y_dev, s);
+    return VIE_OK;
+  });
+}
+
+vie_status vie_precond_apply(vie_problem* p, int32_t precision, double tol_inner, int32_t maxit_inner,
+                             const void* w_dev, void* y_dev, void* stream, int64_t* inner_iters) {
+  return guarded([&]() -> vie_status {
+    if (!p || !w_dev || !y_dev) fail(VIE_EINVAL, "problem, w and y are required");
+    if (w_dev == y_dev) fail(VIE_EINVAL, "w and y must not overlap");
+    if (p->groups.empty()) fail(VIE_EINVAL, "problem has no blocks");
+    if (!(tol_inner >= 0) || !is_finite(tol_inner)) fail(VIE_EINVAL, "tol_inner must be finite and >= 0");
+    if (maxit_inner < 1) fail(VIE_EINVAL, "maxit_inner must be >= 1");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    hipStream_t s = (hipStream_t)stream;
+    hip_check(hipMemsetAsync(p->d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
+    if (precision == VIE_FP64)
+      precond_apply<double>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, s);
+    else if (precision == VIE_MIXED)
+      precond_apply<float>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, s);
+    else
+      fail(VIE_EINVAL, "unknown precision");
+    if (inner_iters) {
+      int64_t acc[3];
+      hip_check(hipMemcpyAsync(acc, p->d_acc.p, sizeof(acc), hipMemcpyDeviceToHost, s), "acc");
+      hip_check(hipStreamSynchronize(s), "precond");
+      *inner_iters = acc[0];
+    }
+    return VIE_OK;
+  });
+}
+
+vie_status vie_solve_device(vie_problem* p, const void* e_inc_dev, const vie_opts* opts, void* e_tot_dev,
+                            void* pol_dev, vie_stats* stats, void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !e_inc_dev || !e_tot_dev) fail(VIE_EINVAL, "problem, e_inc and e_tot are required");
+    validate_opts(opts, p);
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    return solve_impl(p, (const c128*)e_inc_dev, opts, (c128*)e_tot_dev, (c128*)pol_dev, stats, (hipStream_t)stream);
+  });
+}
+
+vie_status vie_solve(vie_problem* p, const double* e_inc, const vie_opts* opts, double* e_tot_out, double* pol_out,
+                     vie_stats* stats) {
+  return guarded([&]() -> vie_status {
+    if (!p || !e_inc || !e_tot_out) fail(VIE_EINVAL, "problem, e_inc and e_tot_out are required");
+    validate_opts(opts, p);
+    const int64_t n = 3 * p->nv;
+    for (int64_t i = 0; i < 2 * n; ++i)
+      if (!is_finite(e_inc[i])) fail(VIE_EINVAL, "e_inc has non-finite entries");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    hipStream_t s = p->ctx->stream;
+    DevBuf din(n * sizeof(c128)), dout(n * sizeof(c128)), dpol;
+    if (pol_out) dpol.alloc(n * sizeof(c128));
+    hip_check(hipMemcpyAsync(din.p, e_inc, n * sizeof(c128), hipMemcpyHostToDevice, s), "upload e_inc");
+    vie_status st = solve_impl(p, din.as<c128>(), opts, dout.as<c128>(), pol_out ? dpol.as<c128>() : nullptr, stats, s);
+    hip_check(hipMemcpyAsync(e_tot_out, dout.p, n * sizeof(c128), hipMemcpyDeviceToHost, s), "download e_tot");
+    if (pol_out) hip_check(hipMemcpyAsync(pol_out, dpol.p, n * sizeof(c128), hipMemcpyDeviceToHost, s), "download pol");
+    hip_check(hipStreamSynchronize(s), "download");
+    return st;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,246 @@
+"""Python binding of libvie (ctypes; argument marshalling only).
+
+Every function below has the name of the C entry point it calls (see
+``include/vie.h``) and does no arithmetic of its own: all steps of the solve
+run in the HIP library.  Device buffers are torch tensors on the GPU
+(complex128, contiguous, shape ``[3, nz, ny, nx]``); torch is used for device
+memory and the current HIP stream only.
+
+Importing this module loads ``libvie.so`` built in place by
+``paper_2501_13512_amd.build``; it raises ``ImportError`` if the library is
+missing, so nothing can silently fall back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvie.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libvie.so is not built ({LIB_PATH}); run `python -m paper_2501_13512_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+VIE_OK, VIE_NOT_CONVERGED = 0, 1
+VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_EBREAKDOWN, VIE_EBUSY, VIE_ECANCELLED, VIE_EINTERNAL = -1, -2, -3, -4, -5, -6, -7
+VIE_FP64, VIE_MIXED = 0, 1
+STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_ENOMEM", -3: "VIE_EDEVICE",
+                -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL"}
+
+ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
+               "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_plane_wave",
+               "vie_matvec", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device")
+
+
+class VieError(RuntimeError):
+    def __init__(self, code: int, func: str, msg: str):
+        super().__init__(f"{func}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class vie_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("wavelength", ctypes.c_double)]
+
+
+class vie_opts(ctypes.Structure):
+    _fields_ = [("tol_outer", ctypes.c_double), ("tol_inner", ctypes.c_double),
+                ("maxit_outer", ctypes.c_int32), ("maxit_inner", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("precondition", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("poll_lag", ctypes.c_int32)]
+
+
+class vie_stats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("refine_iters", ctypes.c_int32), ("final_state", ctypes.c_int32),
+                ("inner_iters_total", ctypes.c_int64), ("precond_applies", ctypes.c_int64),
+                ("relres_recursive", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("inner_hist", ctypes.POINTER(ctypes.c_int32)),
+                ("inner_hist_cap", ctypes.c_int64), ("inner_hist_len", ctypes.c_int64)]
+
+
+class vie_problem_info(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("lz", ctypes.c_int32),
+                ("n_blocks", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+                ("footprint_bytes", ctypes.c_int64)]
+
+
+_vp = ctypes.c_void_p
+_lib.vie_abi_version.restype = ctypes.c_int32
+_lib.vie_abi_version.argtypes = []
+_lib.vie_last_error.restype = ctypes.c_char_p
+_lib.vie_last_error.argtypes = []
+for _name, _args in {
+    "vie_context_create": [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(_vp)],
+    "vie_context_destroy": [_vp],
+    "vie_problem_create": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
+    "vie_problem_destroy": [_vp],
+    "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
+    "vie_plane_wave": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
+    "vie_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
+    "vie_block_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
+    "vie_precond_apply": [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp,
+                          ctypes.POINTER(ctypes.c_int64)],
+    "vie_solve": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats)],
+    "vie_solve_device": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats), _vp],
+}.items():
+    getattr(_lib, _name).restype = ctypes.c_int
+    getattr(_lib, _name).argtypes = _args
+
+
+def _check(code: int, func: str, warn_ok: bool = False) -> int:
+    if code == VIE_OK or (warn_ok and code > 0):
+        return code
+    raise VieError(code, func, vie_last_error())
+
+
+# ------------------------------------------------------------------ raw calls
+def vie_abi_version() -> int:
+    return int(_lib.vie_abi_version())
+
+
+def vie_last_error() -> str:
+    return _lib.vie_last_error().decode()
+
+
+def vie_context_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    out = _vp()
+    _check(_lib.vie_context_create(device, hbm_budget_bytes, ctypes.byref(out)), "vie_context_create")
+    return out.value
+
+
+def vie_context_destroy(ctx: int) -> None:
+    _check(_lib.vie_context_destroy(ctx), "vie_context_destroy")
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def vie_problem_create(ctx: int, grid: vie_grid, eps_r: np.ndarray, block_id: Optional[np.ndarray],
+                       n_blocks: int) -> int:
+    eps = np.ascontiguousarray(eps_r, dtype=np.complex128)
+    bid = None if block_id is None else np.ascontiguousarray(block_id, dtype=np.int32)
+    out = _vp()
+    _check(_lib.vie_problem_create(ctx, ctypes.byref(grid), _np_ptr(eps), _np_ptr(bid), int(n_blocks),
+                                   ctypes.byref(out)), "vie_problem_create")
+    return out.value
+
+
+def vie_problem_destroy(p: int) -> None:
+    _check(_lib.vie_problem_destroy(p), "vie_problem_destroy")
+
+
+def vie_problem_get_info(p: int) -> vie_problem_info:
+    info = vie_problem_info()
+    _check(_lib.vie_problem_get_info(p, ctypes.byref(info)), "vie_problem_get_info")
+    return info
+
+
+def vie_plane_wave(grid: vie_grid, kdir: Sequence[float], pol: Sequence[complex]) -> np.ndarray:
+    k = np.ascontiguousarray(kdir, dtype=np.float64)
+    pl = np.ascontiguousarray(np.asarray(pol, dtype=np.complex128))
+    out = np.empty((3, grid.nz, grid.ny, grid.nx), dtype=np.complex128)
+    _check(_lib.vie_plane_wave(ctypes.byref(grid), _np_ptr(k), _np_ptr(pl), _np_ptr(out)), "vie_plane_wave")
+    return out
+
+
+def _dev(t) -> int:
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("device buffers must be contiguous GPU tensors")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def vie_matvec(p: int, precision: int, x, y, stream=None) -> None:
+    _check(_lib.vie_matvec(p, precision, _dev(x), _dev(y), _stream(stream)), "vie_matvec")
+
+
+def vie_block_matvec(p: int, precision: int, x, y, stream=None) -> None:
+    _check(_lib.vie_block_matvec(p, precision, _dev(x), _dev(y), _stream(stream)), "vie_block_matvec")
+
+
+def vie_precond_apply(p: int, precision: int, tol_inner: float, maxit_inner: int, w, y, stream=None) -> int:
+    it = ctypes.c_int64(0)
+    _check(_lib.vie_precond_apply(p, precision, tol_inner, maxit_inner, _dev(w), _dev(y), _stream(stream),
+                                  ctypes.byref(it)), "vie_precond_apply")
+    return int(it.value)
+
+
+def vie_solve(p: int, e_inc: np.ndarray, opts: vie_opts, stats: vie_stats, want_pol: bool = False):
+    e = np.ascontiguousarray(e_inc, dtype=np.complex128)
+    e_tot = np.empty_like(e)
+    pol = np.empty_like(e) if want_pol else None
+    code = _check(_lib.vie_solve(p, _np_ptr(e), ctypes.byref(opts), _np_ptr(e_tot), _np_ptr(pol),
+                                 ctypes.byref(stats)), "vie_solve", warn_ok=True)
+    return code, e_tot, pol
+
+
+def vie_solve_device(p: int, e_inc, opts: vie_opts, e_tot, pol, stats: vie_stats, stream=None) -> int:
+    return _check(_lib.vie_solve_device(p, _dev(e_inc), ctypes.byref(opts), _dev(e_tot), _dev(pol),
+                                        ctypes.byref(stats), _stream(stream)), "vie_solve_device", warn_ok=True)
+
+
+# ------------------------------------------------------------------ conveniences
+def make_grid(nx, ny, nz, dx, dy, dz, wavelength) -> vie_grid:
+    return vie_grid(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(wavelength))
+
+
+def make_opts(tol_outer=1e-6, tol_inner=1e-2, maxit_outer=1000, maxit_inner=500, max_refine=3,
+              precondition=True, precision=VIE_FP64, poll_lag=1) -> vie_opts:
+    return vie_opts(float(tol_outer), float(tol_inner), int(maxit_outer), int(maxit_inner), int(max_refine),
+                    1 if precondition else 0, int(precision), int(poll_lag))
+
+
+def stats_dict(st: vie_stats) -> dict:
+    return {f: getattr(st, f) for f, _ in vie_stats._fields_ if f != "inner_hist"}
+
+
+class Problem:
+    """Owns a context (optional) and a problem handle."""
+
+    def __init__(self, grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray] = None, n_blocks: int = 0,
+                 ctx: Optional[int] = None, device: int = 0):
+        self._own_ctx = ctx is None
+        self.ctx = vie_context_create(device) if ctx is None else ctx
+        self.grid = grid
+        self.handle = vie_problem_create(self.ctx, grid, eps, block_id, n_blocks)
+
+    @property
+    def shape(self) -> Tuple[int, int, int, int]:
+        return (3, self.grid.nz, self.grid.ny, self.grid.nx)
+
+    def info(self) -> vie_problem_info:
+        return vie_problem_get_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            vie_problem_destroy(self.handle)
+            self.handle = None
+        if getattr(self, "_own_ctx", False) and getattr(self, "ctx", None):
+            vie_context_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

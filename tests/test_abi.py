@@ -1,0 +1,78 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point of include/vie.h, validates arguments, and its host helper (the
+incident plane wave) matches the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import operator as op, physics
+from paper_2501_13512_amd import vie as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "vie.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vie_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    syms = _header_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(V._lib, s), s
+    assert sorted(V.ABI_SYMBOLS) == syms
+
+
+def test_abi_version():
+    assert V.vie_abi_version() == 1
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_context_without_device_is_edevice():
+    with pytest.raises(V.VieError) as e:
+        V.vie_context_create(0)
+    assert e.value.code == V.VIE_EDEVICE
+    assert "device" in V.vie_last_error()
+
+
+def test_null_arguments_are_einval():
+    out = V._vp()
+    assert V._lib.vie_context_create(0, 0, None) == V.VIE_EINVAL
+    g = V.make_grid(2, 2, 2, 1, 1, 1, 10)
+    assert V._lib.vie_problem_create(None, V.ctypes.byref(g), None, None, 0, V.ctypes.byref(out)) == V.VIE_EINVAL
+    assert V._lib.vie_matvec(None, 0, None, None, None) == V.VIE_EINVAL
+    assert V._lib.vie_solve(None, None, None, None, None, None) == V.VIE_EINVAL
+    assert V._lib.vie_problem_get_info(None, None) == V.VIE_EINVAL
+    assert V._lib.vie_problem_destroy(None) == V.VIE_OK
+    assert V._lib.vie_context_destroy(None) == V.VIE_OK
+
+
+@pytest.mark.parametrize("kdir,pol", [((0, 0, 1), (1, 0, 0)), ((0.6, 0, 0.8), (0.8, 0, -0.6)),
+                                      ((0, 1, 0), (0, 0, 1j))])
+def test_plane_wave_matches_oracle(kdir, pol):
+    case = W.random_tiny(3, (5, 4, 7), spacing=(0.03, 0.05, 0.04), wavelength=0.7)
+    g = op.Grid.from_case(case)
+    want = physics.plane_wave(g, kdir, pol)
+    got = V.vie_plane_wave(V.make_grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.wavelength),
+                           kdir, pol)
+    assert np.abs(got - want).max() <= 1e-13
+
+
+def test_plane_wave_rejects_non_unit_direction():
+    g = V.make_grid(2, 2, 2, 1, 1, 1, 10)
+    with pytest.raises(V.VieError) as e:
+        V.vie_plane_wave(g, (0, 0, 2), (1, 0, 0))
+    assert e.value.code == V.VIE_EINVAL
