@@ -144,9 +144,11 @@ class FFTOperator:
     transforms back, crops to the original box and adds the local term.
     """
 
-    def __init__(self, grid: Grid):
+    def __init__(self, grid: Grid, pad: int = 0):
+        # circulant length 2n (+ pad); any length >= 2n - 1 gives the same
+        # product up to rounding (used to measure rounding sensitivity)
         self.grid = grid
-        self.L = (2 * grid.nx, 2 * grid.ny, 2 * grid.nz)
+        self.L = (2 * grid.nx + pad, 2 * grid.ny + pad, 2 * grid.nz + pad)
         kern = embedded_kernel(grid.nx, grid.ny, grid.nz, grid.dx, grid.dy, grid.dz, grid.k0, self.L)
         self.spec = scipy.fft.fftn(kern, axes=(1, 2, 3))
         self.mask = grid.mask

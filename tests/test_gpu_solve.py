@@ -3,9 +3,12 @@
 * K2^{-1} w: same inner iteration counts, same result (FP64).
 * Dielectric cube (16^3, lambda/20, eps 4, 8 blocks; Sec. III-style case):
   preconditioned and plain FP64 solves match the oracle's outer step counts
-  (+-2) and fields (1e-10 when the inner count histories agree); at
-  tol 1e-12 both agree with each other and with the oracle to 1e-10; the
-  mixed-precision solve matches to 1e-5.
+  (+-2).  At the case tolerance (1e-6) BiCGSTAB iterates are sensitive to
+  rounding: two oracle runs that differ only in their FFT embedding length
+  differ by d (about 1e-10 preconditioned, 1e-6 plain on this case).  The
+  GPU field must agree with the oracle to max(1e-10, 10 d).  At tol 1e-12
+  both agree with each other and with the oracle to 1e-10; the
+  mixed-precision solve matches the FP64 oracle to 1e-5.
 * Random tiny problems vs dense LU; edge cases (all vacuum, iteration cap,
   empty blocks, a single layer); repeat runs are bitwise identical.
 """
@@ -60,10 +63,18 @@ def cube_oracle():
     case = W.cube16()
     g = op.Grid.from_case(case)
     e = physics.plane_wave(g)
-    pre = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks, case.tol_inner,
-                       case.maxit_inner)
-    plain = krylov.solve(g, e, case.tol_outer, case.maxit_outer)
-    return case, pre, plain
+    out = {}
+    for pad in (0, 4):
+        out[("pre", pad)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks,
+                                         case.tol_inner, case.maxit_inner, pad=pad)
+        out[("plain", pad)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, pad=pad)
+    return case, out
+
+
+def _rounding_bar(a, b):
+    """Agreement bar at a loose tolerance: 10x the oracle's own sensitivity to
+    rounding (two runs differing only in FFT embedding length), >= 1e-10."""
+    return max(1e-10, 10 * _rel(b.E_tot, a.E_tot))
 
 
 def test_precond_apply_matches_oracle(vie_ctx):
@@ -87,26 +98,27 @@ def test_precond_apply_matches_oracle(vie_ctx):
 
 
 def test_cube_preconditioned_fp64(vie_ctx, cube_oracle):
-    case, ref, _ = cube_oracle
+    case, o = cube_oracle
+    ref = o[("pre", 0)]
     n_app = 2 * ref.info.iterations
     code, e_tot, P, st, hist = _solve(vie_ctx, case, hist_cap=8 * (n_app + 8))
     assert code == V.VIE_OK
     assert abs(st.outer_iters - ref.info.iterations) <= 2
     oracle_hist = [c for app in ref.inner_counts for c in app]
+    assert hist == oracle_hist
     err = _rel(e_tot, ref.E_tot)
-    if hist == oracle_hist:
-        assert err <= 1e-10, err
-    else:
-        assert err <= 10 * case.tol_outer, err
+    assert err <= _rounding_bar(ref, o[("pre", 4)]), err
     assert st.relres_true <= 1.01 * case.tol_outer
 
 
 def test_cube_plain_fp64(vie_ctx, cube_oracle):
-    case, _, ref = cube_oracle
+    case, o = cube_oracle
+    ref = o[("plain", 0)]
     code, e_tot, P, st, _ = _solve(vie_ctx, case, precondition=False)
     assert code == V.VIE_OK
     assert abs(st.outer_iters - ref.info.iterations) <= 2
-    assert _rel(e_tot, ref.E_tot) <= 1e-10
+    err = _rel(e_tot, ref.E_tot)
+    assert err <= _rounding_bar(ref, o[("plain", 4)]), err
     assert st.precond_applies == 0
 
 
@@ -123,7 +135,8 @@ def test_cube_tight_tolerance_agrees(vie_ctx):
 
 
 def test_cube_mixed_precision(vie_ctx, cube_oracle):
-    case, ref, _ = cube_oracle
+    case, o = cube_oracle
+    ref = o[("pre", 0)]
     code, e_tot, P, st, _ = _solve(vie_ctx, case, prec=V.VIE_MIXED)
     assert code == V.VIE_OK
     assert abs(st.outer_iters - ref.info.iterations) <= 2
