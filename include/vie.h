@@ -165,6 +165,15 @@ vie_status vie_plane_wave(const vie_grid* grid, const double kdir[3], const doub
  * on input; y is 0 on vacuum voxels.  x_dev and y_dev must not overlap. */
 vie_status vie_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream);
 
+/* Instrumented product for measurement: runs y = A x `reps` times on
+ * `stream` (x must be zero on vacuum voxels; no input masking, as inside the
+ * solver) with HIP events around each of the five passes (x forward,
+ * y forward, z forward + spectral multiply + z inverse, y inverse,
+ * x inverse + local term) and writes the mean duration of each pass in
+ * milliseconds to pass_ms[0..4].  Synchronises the stream. */
+vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream,
+                              int32_t reps, double* pass_ms);
+
 /* y = K2 x with K2 = blockdiag(A_1, ..., A_N) (eq. (10)): every block's
  * matrix applied to the block's part of x.  Needs block ids. */
 vie_status vie_block_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream);

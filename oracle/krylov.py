@@ -131,7 +131,8 @@ class BlockPreconditioner:
     bounding box with every other voxel masked as vacuum.
     """
 
-    def __init__(self, grid: Grid, block_id: np.ndarray, n_blocks: int, tol: float, maxit: int, pad: int = 0):
+    def __init__(self, grid: Grid, block_id: np.ndarray, n_blocks: int, tol: float, maxit: int, pad: int = 0,
+                 product: str = "fp64"):
         self.tol = tol
         self.maxit = maxit
         self.blocks: List[_Block] = []
@@ -146,7 +147,7 @@ class BlockPreconditioner:
             sub_eps = np.where(member, grid.eps[sl], 1.0 + 0.0j)
             sub = Grid(sub_eps.shape[2], sub_eps.shape[1], sub_eps.shape[0],
                        grid.dx, grid.dy, grid.dz, grid.wavelength, sub_eps)
-            self.blocks.append(_Block(k, sl, member, FFTOperator(sub, pad)))
+            self.blocks.append(_Block(k, sl, member, FFTOperator(sub, pad, product)))
 
     def __call__(self, w: np.ndarray) -> np.ndarray:
         y = np.zeros_like(w)
@@ -181,17 +182,19 @@ def total_field(grid: Grid, P: np.ndarray) -> np.ndarray:
 
 def solve(grid: Grid, e_inc: np.ndarray, tol_outer: float, maxit_outer: int = 1000,
           block_id: Optional[np.ndarray] = None, n_blocks: int = 0,
-          tol_inner: float = 1e-2, maxit_inner: int = 500, pad: int = 0) -> Solution:
+          tol_inner: float = 1e-2, maxit_inner: int = 500, pad: int = 0, product: str = "fp64") -> Solution:
     """Solve A P = E_inc on S; block preconditioner if ``block_id`` is given.
 
     ``pad`` lengthens every circulant embedding (same operator, different
     rounding); comparing runs with pad 0 and pad > 0 measures how much
-    rounding alone moves the iterates at a given tolerance."""
-    A = FFTOperator(grid, pad)
+    rounding alone moves the iterates at a given tolerance.
+    ``product="c64"`` runs every FFT convolution in complex64 (the mixed
+    mode's products); vectors and inner products stay FP64."""
+    A = FFTOperator(grid, pad, product)
     b = masked_rhs(grid, e_inc)
     pre = None
     if block_id is not None:
-        pre = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner, pad)
+        pre = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner, pad, product)
     P, info = bicgstab(A, b, tol_outer, maxit_outer, pre)
     return Solution(P, total_field(grid, P), info, pre.inner_counts if pre is not None else [])
 

@@ -144,13 +144,21 @@ class FFTOperator:
     transforms back, crops to the original box and adds the local term.
     """
 
-    def __init__(self, grid: Grid, pad: int = 0):
+    def __init__(self, grid: Grid, pad: int = 0, product: str = "fp64"):
         # circulant length 2n (+ pad); any length >= 2n - 1 gives the same
-        # product up to rounding (used to measure rounding sensitivity)
+        # product up to rounding (used to measure rounding sensitivity).
+        # product="c64": the convolution (transforms and spectral multiply)
+        # runs in complex64 and is widened again; the local term and every
+        # vector operation stay FP64 (the mixed-precision mode).
+        if product not in ("fp64", "c64"):
+            raise ValueError(product)
         self.grid = grid
+        self.product = product
         self.L = (2 * grid.nx + pad, 2 * grid.ny + pad, 2 * grid.nz + pad)
         kern = embedded_kernel(grid.nx, grid.ny, grid.nz, grid.dx, grid.dy, grid.dz, grid.k0, self.L)
         self.spec = scipy.fft.fftn(kern, axes=(1, 2, 3))
+        if product == "c64":
+            self.spec = self.spec.astype(np.complex64)
         self.mask = grid.mask
         self.chi_inv = grid.chi_inv
 
@@ -158,7 +166,8 @@ class FFTOperator:
         """sum_n T(m - n) x_n for every voxel m of the box (no mask on output)."""
         g = self.grid
         Lx, Ly, Lz = self.L
-        xp = np.zeros((3, Lz, Ly, Lx), dtype=np.complex128)
+        dt = np.complex64 if self.product == "c64" else np.complex128
+        xp = np.zeros((3, Lz, Ly, Lx), dtype=dt)
         xp[:, :g.nz, :g.ny, :g.nx] = x * self.mask
         X = scipy.fft.fftn(xp, axes=(1, 2, 3))
         Y = np.zeros_like(X)
@@ -167,7 +176,7 @@ class FFTOperator:
             if a != b:
                 Y[b] += self.spec[c] * X[a]
         y = scipy.fft.ifftn(Y, axes=(1, 2, 3))
-        return y[:, :g.nz, :g.ny, :g.nx]
+        return y[:, :g.nz, :g.ny, :g.nx].astype(np.complex128)
 
     def __call__(self, x: np.ndarray) -> np.ndarray:
         xm = x * self.mask

@@ -49,8 +49,10 @@ struct MvmBatch {
 
 // y = A x for every active system of the batch (Sec. I Toeplitz + FFT;
 // eqs. (2)-(4)).  `mask_input` zeroes x where 1/chi = 0 before transforming.
+// `ev` (optional, 6 events): ev[0] is recorded before pass 1 and ev[i] after
+// pass i, on stream s.
 template <typename R>
-void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s);
+void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s, hipEvent_t* ev = nullptr);
 
 // Octant spectra of the 6 Green-tensor components for one box shape:
 // evaluates T(m) on the (lz, ly, lx) circulant grid in FP64, transforms it

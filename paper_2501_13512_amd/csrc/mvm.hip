@@ -351,9 +351,14 @@ static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
   check_launch("z pass");
 }
 
+static void mark(hipEvent_t* ev, int i, hipStream_t s) {
+  if (ev && hipEventRecord(ev[i], s) != hipSuccess) throw std::runtime_error("hipEventRecord failed");
+}
+
 template <typename R>
-void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s) {
+void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s, hipEvent_t* ev) {
   if (b.nsys <= 0) return;
+  mark(ev, 0, s);
   RowArgs<R> ra{};
   ra.nx = b.nx;
   ra.ny = b.ny;
@@ -372,6 +377,7 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
   ra.mask_input = mask_input ? 1 : 0;
   ra.scale = 1.0 / ((double)b.lx * (double)b.ly * (double)b.lz);
   launch_row_fwd<R>(b.lx, ra, b.nsys, s);
+  mark(ev, 1, s);
 
   ColArgs<R> ca{};
   ca.data = b.work;
@@ -384,6 +390,7 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
   ca.tw = b.tw->table[b.ly];
   ca.nsys = b.nsys;
   launch_col<R, -1>(b.ly, ca, s);
+  mark(ev, 2, s);
 
   ZArgs<R> za{};
   za.nz = b.nz;
@@ -396,16 +403,19 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
   za.status = b.status;
   za.tw = b.tw->table[b.lz];
   launch_zconv<R>(b.lz, za, b.nsys, s);
+  mark(ev, 3, s);
 
   ca.n_in = b.ly;
   ca.n_out = b.ny;
   launch_col<R, +1>(b.ly, ca, s);
+  mark(ev, 4, s);
 
   launch_row_inv<R>(b.lx, ra, b.nsys, s);
+  mark(ev, 5, s);
 }
 
-template void mvm<float>(const MvmBatch<float>&, const c128*, c128*, bool, hipStream_t);
-template void mvm<double>(const MvmBatch<double>&, const c128*, c128*, bool, hipStream_t);
+template void mvm<float>(const MvmBatch<float>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);
+template void mvm<double>(const MvmBatch<double>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);
 
 // ------------------------------------------------------------------ spectra setup
 // T(m) of the discretised dyadic Green's function (eq. (1) with the scalar

@@ -849,6 +849,42 @@ vie_status vie_matvec(vie_problem* p, int32_t precision, const void* x_dev, void
   });
 }
 
+vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream,
+                              int32_t reps, double* pass_ms) {
+  return guarded([&]() -> vie_status {
+    if (!p || !x_dev || !y_dev || !pass_ms) fail(VIE_EINVAL, "problem, x, y and pass_ms are required");
+    if (x_dev == y_dev) fail(VIE_EINVAL, "x and y must not overlap");
+    if (reps < 1 || reps > 100000) fail(VIE_EINVAL, "reps out of range");
+    if (precision != VIE_FP64 && precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[6];
+    for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+    double acc[5] = {0, 0, 0, 0, 0};
+    try {
+      for (int r = 0; r < reps; ++r) {
+        if (precision == VIE_FP64)
+          vie::mvm<double>(outer_batch<double>(*p, false), (const c128*)x_dev, (c128*)y_dev, false, s, ev);
+        else
+          vie::mvm<float>(outer_batch<float>(*p, false), (const c128*)x_dev, (c128*)y_dev, false, s, ev);
+        hip_check(hipEventSynchronize(ev[5]), "profile");
+        for (int i = 0; i < 5; ++i) {
+          float ms = 0;
+          hip_check(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "elapsed");
+          acc[i] += ms;
+        }
+      }
+    } catch (...) {
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int i = 0; i < 5; ++i) pass_ms[i] = acc[i] / reps;
+    return VIE_OK;
+  });
+}
+
 vie_status vie_block_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream) {
   return guarded([&]() -> vie_status {
     if (!p || !x_dev || !y_dev) fail(VIE_EINVAL, "problem, x and y are required");

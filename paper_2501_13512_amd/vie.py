@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
 
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
                "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_plane_wave",
-               "vie_matvec", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device")
+               "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device")
 
 
 class VieError(RuntimeError):
@@ -83,6 +83,7 @@ for _name, _args in {
     "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
     "vie_plane_wave": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
     "vie_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
+    "vie_matvec_profile": [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp],
     "vie_block_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
     "vie_precond_apply": [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp,
                           ctypes.POINTER(ctypes.c_int64)],
@@ -166,6 +167,13 @@ def _stream(stream) -> Optional[int]:
 
 def vie_matvec(p: int, precision: int, x, y, stream=None) -> None:
     _check(_lib.vie_matvec(p, precision, _dev(x), _dev(y), _stream(stream)), "vie_matvec")
+
+
+def vie_matvec_profile(p: int, precision: int, x, y, reps: int, stream=None) -> np.ndarray:
+    ms = np.zeros(5, dtype=np.float64)
+    _check(_lib.vie_matvec_profile(p, precision, _dev(x), _dev(y), _stream(stream), int(reps), _np_ptr(ms)),
+           "vie_matvec_profile")
+    return ms
 
 
 def vie_block_matvec(p: int, precision: int, x, y, stream=None) -> None:

@@ -8,7 +8,8 @@
   differ by d (about 1e-10 preconditioned, 1e-6 plain on this case).  The
   GPU field must agree with the oracle to max(1e-10, 10 d).  At tol 1e-12
   both agree with each other and with the oracle to 1e-10; the
-  mixed-precision solve matches the FP64 oracle to 1e-5.
+  mixed-precision solve matches the FP64 oracle's field to 1e-5 and the
+  step count (+-2) of the oracle run with complex64 products.
 * Random tiny problems vs dense LU; edge cases (all vacuum, iteration cap,
   empty blocks, a single layer); repeat runs are bitwise identical.
 """
@@ -68,6 +69,8 @@ def cube_oracle():
         out[("pre", pad)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks,
                                          case.tol_inner, case.maxit_inner, pad=pad)
         out[("plain", pad)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, pad=pad)
+    out[("pre_c64", 0)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks,
+                                       case.tol_inner, case.maxit_inner, product="c64")
     return case, out
 
 
@@ -135,12 +138,14 @@ def test_cube_tight_tolerance_agrees(vie_ctx):
 
 
 def test_cube_mixed_precision(vie_ctx, cube_oracle):
+    """Mixed mode: step count vs the oracle doing the same arithmetic
+    (complex64 products, FP64 vectors); field vs the FP64 oracle."""
     case, o = cube_oracle
-    ref = o[("pre", 0)]
+    ref64, ref32 = o[("pre", 0)], o[("pre_c64", 0)]
     code, e_tot, P, st, _ = _solve(vie_ctx, case, prec=V.VIE_MIXED)
     assert code == V.VIE_OK
-    assert abs(st.outer_iters - ref.info.iterations) <= 2
-    assert _rel(e_tot, ref.E_tot) <= 1e-5
+    assert abs(st.outer_iters - ref32.info.iterations) <= 2
+    assert _rel(e_tot, ref64.E_tot) <= 1e-5
     assert st.relres_true <= case.tol_outer
 
 

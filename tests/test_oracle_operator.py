@@ -111,3 +111,20 @@ def test_embedding_length_does_not_change_product():
                 Y[b] += S[c] * X[a]
         y = scipy.fft.ifftn(Y, axes=(1, 2, 3))[:, :g.nz, :g.ny, :g.nx]
         assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_c64_product_mode_is_single_precision_of_the_same_operator():
+    """The complex64 product differs from FP64 by single-precision rounding
+    only (relative ~1e-7), and keeps the FP64 local term exactly."""
+    case = W.random_tiny(61, (9, 8, 7), fill=0.8)
+    g = op.Grid.from_case(case)
+    x = _rand_vec(np.random.default_rng(6), case.shape) * g.mask
+    a = op.FFTOperator(g)(x)
+    b = op.FFTOperator(g, product="c64")(x)
+    err = np.linalg.norm(a - b) / np.linalg.norm(a)
+    assert 1e-9 < err < 1e-5
+    local = x * g.chi_inv
+    ca = op.FFTOperator(g).convolve(x)
+    cb = op.FFTOperator(g, product="c64").convolve(x)
+    assert np.linalg.norm((local - cb) * g.mask - b) <= 1e-15 * np.linalg.norm(b)
+    assert np.linalg.norm(ca - cb) / np.linalg.norm(ca) < 1e-5
