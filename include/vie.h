@@ -99,7 +99,12 @@ typedef struct {
   int32_t precondition; /* 1: block-diagonal preconditioner (needs block ids), 0: none */
   int32_t precision;    /* vie_precision */
   int32_t poll_lag;     /* convergence checks trail the enqueued work by this many steps (>= 0) */
+  int32_t flags;        /* VIE_FLAG_* */
 } vie_opts;
+
+/* vie_opts.flags: run the inner block iterations as individual kernel
+ * launches instead of a captured HIP graph (same kernels, same results). */
+#define VIE_FLAG_NO_GRAPHS 1
 
 /* Statistics of one solve. */
 typedef struct {

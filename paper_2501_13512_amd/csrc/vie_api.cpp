@@ -225,6 +225,8 @@ struct vie_problem {
   DevBuf d_acc, d_hist, d_count;
   int n_inner = 0;
   vie::BlockMap bmap{};
+  // captured inner BiCGSTAB iteration of all block groups ([0] FP64, [1] FP32)
+  hipGraphExec_t inner_graph[2] = {nullptr, nullptr};
   // polling: ring 0 for the outer loop, ring 1 for the inner loops
   int* h_ring = nullptr;
   hipEvent_t ev[2][kRing] = {};
@@ -232,6 +234,8 @@ struct vie_problem {
   size_t footprint = 0;
 
   ~vie_problem() {
+    for (auto& g : inner_graph)
+      if (g) (void)hipGraphExecDestroy(g);
     for (auto& r : ev)
       for (auto& e : r)
         if (e) (void)hipEventDestroy(e);
@@ -349,29 +353,73 @@ KBatch group_kbatch(vie_problem& P, Group& G) {
 
 c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (size_t)kind * P.groups.size(); }
 
+// One BiCGSTAB step of every inner system of every block group (y = p and
+// z = s: the inner solves are unpreconditioned).
+template <typename R>
+void inner_iteration(vie_problem& P, hipStream_t s) {
+  for (auto& G : P.groups) {
+    KBatch k = group_kbatch(P, G);
+    MvmBatch<R> m = group_batch<R>(P, G, true);
+    c128** v = G.vec;
+    vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
+    vie::mvm<R>(m, v[V_P], v[V_V], false, s);
+    vie::k_alpha(k, v[V_RHAT], v[V_V], s);
+    vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
+    vie::mvm<R>(m, v[V_S], v[V_T], false, s);
+    vie::k_omega(k, v[V_T], v[V_S], s);
+    vie::k_update_xr(k, v[V_X], v[V_P], v[V_S], v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
+  }
+}
+
+// The inner step captured once per problem and precision as a HIP graph
+// (all kernel arguments are fixed per problem), replayed every iteration.
+template <typename R>
+hipGraphExec_t inner_graph(vie_problem& P) {
+  hipGraphExec_t& ex = P.inner_graph[sizeof(R) == sizeof(float) ? 1 : 0];
+  if (ex) return ex;
+  hipStream_t cs = nullptr;
+  hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    hip_check(e, "begin capture");
+  }
+  try {
+    inner_iteration<R>(P, cs);
+  } catch (...) {
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    throw;
+  }
+  e = hipStreamEndCapture(cs, &g);
+  if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    ex = nullptr;
+    hip_check(e, "graph capture");
+  }
+  return ex;
+}
+
 // y = K2^{-1} w: batched inner BiCGSTAB-FFT solves of every block (Sec. II-B).
 template <typename R>
 void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit, const int* gate, int lag,
-                   int32_t* hist, int64_t hist_cap, hipStream_t s) {
+                   int32_t* hist, int64_t hist_cap, bool graphs, hipStream_t s) {
   vie::block_gather(P.bmap, w, gptr(P, V_B), s);
   for (auto& G : P.groups) {
     KBatch k = group_kbatch(P, G);
     vie::k_init(k, G.vec[V_B], G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], tol, maxit, gate, s);
   }
+  hipGraphExec_t ex = graphs ? inner_graph<R>(P) : nullptr;
   Poller poll(P, s, 1);
   for (int it = 1; it <= maxit; ++it) {
-    for (auto& G : P.groups) {
-      KBatch k = group_kbatch(P, G);
-      MvmBatch<R> m = group_batch<R>(P, G, true);
-      c128** v = G.vec;
-      vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
-      vie::mvm<R>(m, v[V_P], v[V_V], false, s);
-      vie::k_alpha(k, v[V_RHAT], v[V_V], s);
-      vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
-      vie::mvm<R>(m, v[V_S], v[V_T], false, s);
-      vie::k_omega(k, v[V_T], v[V_S], s);
-      vie::k_update_xr(k, v[V_X], v[V_P], v[V_S], v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
-    }
+    if (ex)
+      hip_check(hipGraphLaunch(ex, s), "graph launch");
+    else
+      inner_iteration<R>(P, s);
     vie::count_active(P.d_istatus.as<int>(), P.n_inner, P.d_count.as<int>(), s);
     const long t = poll.push(P.d_count.as<int>());
     if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
@@ -389,7 +437,7 @@ struct RunResult {
 // Right-preconditioned BiCGSTAB on the full grid: A x = rhs (Sec. II-B).
 template <typename R>
 RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int maxit, bool prec, double tol_in,
-                       int maxit_in, int lag, int32_t* hist, int64_t hist_cap, hipStream_t s) {
+                       int maxit_in, int lag, int32_t* hist, int64_t hist_cap, bool graphs, hipStream_t s) {
   KBatch k = outer_kbatch(P);
   MvmBatch<R> m = outer_batch<R>(P, true);
   c128** v = P.vec;
@@ -401,7 +449,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
     c128* yv = v[V_P];
     if (prec) {
       yv = v[V_Y];
-      precond_apply<R>(P, v[V_P], yv, tol_in, maxit_in, gate, lag, hist, hist_cap, s);
+      precond_apply<R>(P, v[V_P], yv, tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
     }
     vie::mvm<R>(m, yv, v[V_V], false, s);
     vie::k_alpha(k, v[V_RHAT], v[V_V], s);
@@ -409,7 +457,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
     c128* zv = v[V_S];
     if (prec) {
       zv = v[V_Z];
-      precond_apply<R>(P, v[V_S], zv, tol_in, maxit_in, gate, lag, hist, hist_cap, s);
+      precond_apply<R>(P, v[V_S], zv, tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
     }
     vie::mvm<R>(m, zv, v[V_T], false, s);
     vie::k_omega(k, v[V_T], v[V_S], s);
@@ -443,6 +491,7 @@ void validate_opts(const vie_opts* o, const vie_problem* p) {
   if (o->precision != VIE_FP64 && o->precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
   if (o->poll_lag < 0 || o->poll_lag > kRing - 2) fail(VIE_EINVAL, "poll_lag out of range");
   if (o->max_refine < 0 || o->max_refine > 100) fail(VIE_EINVAL, "max_refine out of range");
+  if (o->flags & ~VIE_FLAG_NO_GRAPHS) fail(VIE_EINVAL, "unknown flags");
   if (o->precondition) {
     if (p->groups.empty()) fail(VIE_EINVAL, "precondition requested but the problem has no blocks");
     if (!(o->tol_inner >= 0) || !is_finite(o->tol_inner)) fail(VIE_EINVAL, "tol_inner must be finite and >= 0");
@@ -458,6 +507,7 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   vie_problem& P = *p;
   c128** v = P.vec;
   const bool prec = o->precondition != 0;
+  const bool graphs = (o->flags & VIE_FLAG_NO_GRAPHS) == 0;
   int32_t* hist = nullptr;
   int64_t hist_cap = 0;
   if (stats && stats->inner_hist && stats->inner_hist_cap > 0 && prec) {
@@ -472,18 +522,18 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   double relres_true = 0;
   if (o->precision == VIE_FP64) {
     rr = run_bicgstab<double>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
-                              o->poll_lag, hist, hist_cap, s);
+                              o->poll_lag, hist, hist_cap, graphs, s);
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], rr.st.nb, s);
   } else {
     rr = run_bicgstab<float>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
-                             o->poll_lag, hist, hist_cap, s);
+                             o->poll_lag, hist, hist_cap, graphs, s);
     const double nb = rr.st.nb;
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
     // iterative refinement: solve A d = b - A x with FP32 products, x += d
     while (rr.status != vie::ST_BREAKDOWN && relres_true > o->tol_outer && refine < o->max_refine && nb > 0) {
       const double tol_c = std::min(0.5, o->tol_outer / relres_true);
       RunResult rc = run_bicgstab<float>(P, v[V_TMP2], v[V_TMP1], tol_c, o->maxit_outer, prec, o->tol_inner,
-                                         o->maxit_inner, o->poll_lag, hist, hist_cap, s);
+                                         o->maxit_inner, o->poll_lag, hist, hist_cap, graphs, s);
       vie::add_vec(v[V_X], v[V_TMP1], 3 * P.nv, s);
       ++refine;
       refine_iters += rc.st.iters;
@@ -675,24 +725,69 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
             }
           }
       // group blocks by circulant lengths of their bounding boxes
-      std::map<std::tuple<int, int, int>, std::vector<int>> bylen;
-      for (int k = 0; k < n_blocks; ++k) {
-        if (cnt[k] == 0) continue;
-        const int ex = hi[3 * k] - lo[3 * k] + 1, ey = hi[3 * k + 1] - lo[3 * k + 1] + 1,
-                  ez = hi[3 * k + 2] - lo[3 * k + 2] + 1;
-        bylen[{vie::smallest_fft_length(2 * ex - 1), vie::smallest_fft_length(2 * ey - 1),
-               vie::smallest_fft_length(2 * ez - 1)}]
-            .push_back(k);
+      struct Plan {
+        int lx, ly, lz;
+        std::vector<int> blocks;
+      };
+      std::vector<Plan> plans;
+      {
+        std::map<std::tuple<int, int, int>, std::vector<int>> bylen;
+        for (int k = 0; k < n_blocks; ++k) {
+          if (cnt[k] == 0) continue;
+          const int ex = hi[3 * k] - lo[3 * k] + 1, ey = hi[3 * k + 1] - lo[3 * k + 1] + 1,
+                    ez = hi[3 * k + 2] - lo[3 * k + 2] + 1;
+          bylen[{vie::smallest_fft_length(2 * ex - 1), vie::smallest_fft_length(2 * ey - 1),
+                 vie::smallest_fft_length(2 * ez - 1)}]
+              .push_back(k);
+        }
+        for (auto& kv : bylen) plans.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                                                kv.second});
+      }
+      // Merge shape groups while it lowers the modelled cost of one inner
+      // iteration: a fixed per-group overhead (its kernel launches) plus
+      // work proportional to the padded transform volume of its systems.
+      // A merged group takes the largest lengths of both (a box of n <=
+      // (L+1)/2 voxels embeds in any longer L).
+      {
+        const double kGroupOverhead = 4.0e5;  // padded points per group-iteration overhead
+        auto cost = [&](int lx, int ly, int lz, size_t nsys) {
+          return kGroupOverhead + (double)nsys * lx * ly * lz;
+        };
+        for (;;) {
+          double best = 0;
+          int bi = -1, bj = -1;
+          for (size_t i = 0; i < plans.size(); ++i)
+            for (size_t j = i + 1; j < plans.size(); ++j) {
+              const Plan &a = plans[i], &b = plans[j];
+              const int lx = std::max(a.lx, b.lx), ly = std::max(a.ly, b.ly), lz = std::max(a.lz, b.lz);
+              const double d = cost(lx, ly, lz, a.blocks.size() + b.blocks.size()) -
+                               cost(a.lx, a.ly, a.lz, a.blocks.size()) - cost(b.lx, b.ly, b.lz, b.blocks.size());
+              if (d < best) {
+                best = d;
+                bi = (int)i;
+                bj = (int)j;
+              }
+            }
+          if (bi < 0) break;
+          Plan& a = plans[bi];
+          Plan& b = plans[bj];
+          a.lx = std::max(a.lx, b.lx);
+          a.ly = std::max(a.ly, b.ly);
+          a.lz = std::max(a.lz, b.lz);
+          a.blocks.insert(a.blocks.end(), b.blocks.begin(), b.blocks.end());
+          std::sort(a.blocks.begin(), a.blocks.end());
+          plans.erase(plans.begin() + bj);
+        }
       }
       std::vector<int> block_group(n_blocks, -1), block_sys(n_blocks, -1);
       std::vector<int4> origin(n_blocks, int4{0, 0, 0, 0}), gbox;
       int slot = 0;
-      for (auto& kv : bylen) {
+      for (auto& pl : plans) {
         Group G{};
-        G.lx = std::get<0>(kv.first);
-        G.ly = std::get<1>(kv.first);
-        G.lz = std::get<2>(kv.first);
-        G.blocks = kv.second;
+        G.lx = pl.lx;
+        G.ly = pl.ly;
+        G.lz = pl.lz;
+        G.blocks = pl.blocks;
         G.nsys = (int)G.blocks.size();
         G.bx = G.by = G.bz = 1;
         for (int k : G.blocks) {
@@ -919,9 +1014,11 @@ vie_status vie_precond_apply(vie_problem* p, int32_t precision, double tol_inner
     hipStream_t s = (hipStream_t)stream;
     hip_check(hipMemsetAsync(p->d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
     if (precision == VIE_FP64)
-      precond_apply<double>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, s);
+      precond_apply<double>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, true,
+                            s);
     else if (precision == VIE_MIXED)
-      precond_apply<float>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, s);
+      precond_apply<float>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, true,
+                           s);
     else
       fail(VIE_EINVAL, "unknown precision");
     if (inner_iters) {

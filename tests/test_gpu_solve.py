@@ -9,7 +9,7 @@
   GPU field must agree with the oracle to max(1e-10, 10 d).  At tol 1e-12
   both agree with each other and with the oracle to 1e-10; the
   mixed-precision solve matches the FP64 oracle's field to 1e-5 and the
-  step count (+-2) of the oracle run with complex64 products.
+  step counts (+-2) of oracle runs with complex64 products.
 * Random tiny problems vs dense LU; edge cases (all vacuum, iteration cap,
   empty blocks, a single layer); repeat runs are bitwise identical.
 """
@@ -69,8 +69,9 @@ def cube_oracle():
         out[("pre", pad)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks,
                                          case.tol_inner, case.maxit_inner, pad=pad)
         out[("plain", pad)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, pad=pad)
-    out[("pre_c64", 0)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks,
-                                       case.tol_inner, case.maxit_inner, product="c64")
+    for pad in (0, 2, 4):
+        out[("pre_c64", pad)] = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks,
+                                             case.tol_inner, case.maxit_inner, pad=pad, product="c64")
     return case, out
 
 
@@ -139,12 +140,16 @@ def test_cube_tight_tolerance_agrees(vie_ctx):
 
 def test_cube_mixed_precision(vie_ctx, cube_oracle):
     """Mixed mode: step count vs the oracle doing the same arithmetic
-    (complex64 products, FP64 vectors); field vs the FP64 oracle."""
+    (complex64 products, FP64 vectors).  FP32 rounding flips inner counts, so
+    oracle runs that differ only in rounding (embedding pad 0, 2, 4) already
+    spread; the GPU count must lie within that spread +-2.  Field vs the
+    FP64 oracle to 1e-5."""
     case, o = cube_oracle
-    ref64, ref32 = o[("pre", 0)], o[("pre_c64", 0)]
+    ref64 = o[("pre", 0)]
+    counts = [o[("pre_c64", pad)].info.iterations for pad in (0, 2, 4)]
     code, e_tot, P, st, _ = _solve(vie_ctx, case, prec=V.VIE_MIXED)
     assert code == V.VIE_OK
-    assert abs(st.outer_iters - ref32.info.iterations) <= 2
+    assert min(counts) - 2 <= st.outer_iters <= max(counts) + 2, (st.outer_iters, counts)
     assert _rel(e_tot, ref64.E_tot) <= 1e-5
     assert st.relres_true <= case.tol_outer
 
@@ -218,3 +223,28 @@ def test_nan_incident_field_rejected(vie_ctx):
         assert ex.value.code == V.VIE_EINVAL
     finally:
         P.close()
+
+
+def test_graph_replays_match_eager_launches(vie_ctx):
+    """The captured inner iteration is replayed once per inner step, with
+    eager kernels, copies and host waits in between; every replay must give
+    what the same kernels launched one by one give (bitwise)."""
+    case = W.random_tiny(56, (10, 9, 8), fill=0.8, n_blocks=4)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        e = torch.from_numpy(V.vie_plane_wave(P.grid, case.kdir, case.pol)).cuda()
+        outs = []
+        for flags in (V.VIE_FLAG_NO_GRAPHS, 0, V.VIE_FLAG_NO_GRAPHS, 0):
+            out = torch.empty_like(e)
+            st = V.vie_stats()
+            for prec in (V.VIE_FP64, V.VIE_MIXED):
+                opts = V.make_opts(tol_outer=1e-9, tol_inner=1e-2, precision=prec, flags=flags)
+                assert V.vie_solve_device(P.handle, e, opts, out, None, st) == V.VIE_OK
+                torch.cuda.synchronize()
+                outs.append((flags, prec, out.cpu().numpy(), st.outer_iters, st.inner_iters_total))
+    finally:
+        P.close()
+    for prec in (V.VIE_FP64, V.VIE_MIXED):
+        runs = [o for o in outs if o[1] == prec]
+        for r in runs[1:]:
+            assert np.array_equal(r[2], runs[0][2]) and r[3:] == runs[0][3:]
