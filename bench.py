@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=20)
+    ap.add_argument("--maxit-outer", type=int, default=None,
+                    help="cap the outer steps (profiling runs only; the result is then not a full solve)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,7 +111,8 @@ def main():
     info = P.info()
     e_inc = torch.from_numpy(V.vie_plane_wave(grid, case.kdir, case.pol)).cuda()
     e_tot = torch.empty_like(e_inc)
-    opts = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=case.maxit_outer,
+    maxit = case.maxit_outer if args.maxit_outer is None else args.maxit_outer
+    opts = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=maxit,
                        maxit_inner=case.maxit_inner, precondition=True, precision=prec, max_refine=3)
     st = V.vie_stats()
     for _ in range(args.warmup):
@@ -124,7 +127,7 @@ def main():
         code = V.vie_solve_device(P.handle, e_inc, opts, e_tot, None, st)
         lat.append(time.perf_counter() - t1)
         stats.append(V.stats_dict(st))
-        if code != V.VIE_OK:
+        if code != V.VIE_OK and args.maxit_outer is None:
             print(f"solve returned {V.STATUS_NAMES.get(code, code)}", file=sys.stderr)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
