@@ -54,6 +54,29 @@ struct MvmBatch {
 template <typename R>
 void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s, hipEvent_t* ev = nullptr);
 
+struct KBatch;
+// Product with BiCGSTAB work fused into its first and last passes.
+//   in_mode 1: the input is p = r + beta (p - omega v) (p = r on the first
+//              step), written back to p;
+//   in_mode 2: the input is s = r - alpha v, written to s, and the
+//              half-step test on ||s|| is made;
+//   out_mode 1: alpha = rho / <rhat, y> from the output y;
+//   out_mode 2: omega = <y, s> / <y, y>.
+// Vectors are batched like x and y (system stride 3 nx ny nz).
+struct FuseArgs {
+  int in_mode, out_mode;
+  const c128* r;
+  c128* p;        // in_mode 1: p (updated); in_mode 2: s (written)
+  const c128* v;
+  const c128* rhat;
+  const c128* s;  // out_mode 2
+};
+template <typename R>
+void mvm_fused(const MvmBatch<R>& b, const KBatch& k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s);
+
+// Chunks per system of the fused first/last passes (for partial sizing).
+int64_t mvm_row_tiles(int lx, int nz, int ny);
+
 // Octant spectra of the 6 Green-tensor components for one box shape:
 // evaluates T(m) on the (lz, ly, lx) circulant grid in FP64, transforms it
 // with the device FFT and keeps q in [0, L/2] per axis.  `scratch` holds
@@ -84,10 +107,12 @@ struct KBatch {
   int64_t n;
   int* status;
   KState* st;
-  double* partials;   // >= nsys * chunks(n) * 4 doubles
+  double* partials;   // per system `pstride` doubles (>= 4 * chunks)
+  int64_t pstride;
+  int* counters;      // per system, zero between kernels
 };
 
-int64_t krylov_chunks(int64_t n);   // reduction chunks per system
+int64_t krylov_chunks(int64_t n);   // reduction chunks per system (vector kernels)
 
 // x = 0, r = rhat = b, ||b||; status ACTIVE if ||b|| > 0 and the gate (if
 // any) is ACTIVE, CONVERGED (x = 0) if ||b|| = 0, IDLE if gated off.
@@ -120,8 +145,9 @@ void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStr
 void sub_vec(const c128* b, const c128* a, c128* r, int64_t n, hipStream_t s);
 // x += d
 void add_vec(c128* x, const c128* d, int64_t n, hipStream_t s);
-// ||v||^2 of one vector into *out (device double), deterministic
-void norm2(const c128* v, int64_t n, double* partials, double* out, hipStream_t s);
+// ||v||^2 of one vector into *out (device double), deterministic; partials
+// holds 4 * krylov_chunks(n) doubles, counter one zeroed int
+void norm2(const c128* v, int64_t n, double* partials, int* counter, double* out, hipStream_t s);
 
 // ------------------------------------------------------------------ blocks
 // Block k of the partition lives in group block_group[k] as system

@@ -2,10 +2,10 @@
 // systems, and the gather/scatter between the outer vector and the blocks of
 // the block-diagonal preconditioner (Sec. II-B, eqs. (10)-(11)).
 //
-// Every reduction is two-stage and deterministic: each workgroup reduces a
-// fixed chunk of 2048 elements (wavefront shuffles, then LDS) into a partial,
-// and one workgroup per system sums the partials in a fixed order and applies
-// the scalar step of the iteration.  No floating-point atomics.
+// Every reduction is deterministic: each workgroup reduces a fixed chunk of
+// 2048 elements (wavefront shuffles, then LDS) into a partial, and the last
+// workgroup of the system to finish sums the partials in a fixed order and
+// applies the scalar step of the iteration.  No floating-point atomics.
 //
 // BiCGSTAB (van der Vorst), right-preconditioned, per system:
 //   rho = <rhat, r>; p = r + beta (p - omega v); y = K^{-1} p; v = A y;
@@ -15,16 +15,15 @@
 #include <stdexcept>
 #include <string>
 
-#include "kernels.h"
+#include "krylov_dev.h"
 
 namespace vie {
 
 constexpr int KT = 256;               // threads per workgroup
 constexpr int KEPT = 8;               // elements per thread
 constexpr int KCH = KT * KEPT;        // elements per chunk
-constexpr int NPART = 4;              // doubles per partial
 
-__host__ __device__ int64_t chunks_of(int64_t n) { return (n + KCH - 1) / KCH; }
+__host__ __device__ inline int64_t chunks_of(int64_t n) { return (n + KCH - 1) / KCH; }
 int64_t krylov_chunks(int64_t n) { return chunks_of(n); }
 
 static void check_launch(const char* what) {
@@ -32,74 +31,23 @@ static void check_launch(const char* what) {
   if (e != hipSuccess) throw std::runtime_error(std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
 }
 
-// Sum NV doubles over the workgroup; result valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV]) {
-  __shared__ double sm[KT / 64][NV];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sm[wid][k] = v[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double a = sm[0][k];
-      for (int w = 1; w < KT / 64; ++w) a += sm[w][k];
-      v[k] = a;
-    }
-  }
-}
-
-template <int NV>
-__device__ __forceinline__ void write_partial(double* partials, int64_t chunks, int sys, int64_t chunk,
-                                              double (&v)[NV]) {
-  block_sum<NV>(v);
-  if (threadIdx.x == 0) {
-    double* p = partials + ((int64_t)sys * chunks + chunk) * NPART;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) p[k] = v[k];
-  }
-}
-
-// Sum of the system's partials (fixed order), valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void final_sum(const double* partials, int64_t chunks, int sys, double (&v)[NV]) {
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (int64_t c = threadIdx.x; c < chunks; c += KT) {
-    const double* p = partials + ((int64_t)sys * chunks + c) * NPART;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += p[k];
-  }
-  block_sum<NV>(v);
-}
-
-__device__ __forceinline__ c128 cdiv(c128 a, c128 b) {
-  // a / b, scaled to avoid overflow
-  const double s = fabs(b.x) + fabs(b.y);
-  const double br = b.x / s, bi = b.y / s, ar = a.x / s, ai = a.y / s;
-  const double d = br * br + bi * bi;
-  return mk<double>((ar * br + ai * bi) / d, (ai * br - ar * bi) / d);
-}
-
 // chunk / system decomposition of a (chunks x nsys) grid
 #define KRYLOV_INDEX                                         \
-  const int64_t chunks = chunks_of(n);                   \
+  const int64_t chunks = chunks_of(n);                       \
   const int sys = (int)(blockIdx.x / chunks);                \
   const int64_t chunk = blockIdx.x - (int64_t)sys * chunks;  \
   const int64_t base = (int64_t)sys * n;                     \
   const int64_t i0 = chunk * KCH + threadIdx.x;
 
 // ---------------------------------------------------------------- init
-__global__ void __launch_bounds__(KT) kk_init(int64_t n, const int* gate, const c128* b, c128* x, c128* r,
-                                              c128* rhat, double* partials) {
+__global__ void __launch_bounds__(KT) kk_init(KBatch k, const int* gate, const c128* b, c128* x, c128* r,
+                                              c128* rhat, double tol, int maxit) {
+  const int64_t n = k.n;
   KRYLOV_INDEX
-  if (gate && *gate != ST_ACTIVE) return;
+  if (gate && *gate != ST_ACTIVE) {
+    if (chunk == 0 && threadIdx.x == 0) k.status[sys] = ST_IDLE;
+    return;
+  }
   double acc[1] = {0.0};
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
@@ -112,122 +60,87 @@ __global__ void __launch_bounds__(KT) kk_init(int64_t n, const int* gate, const 
       acc[0] += abs2(v);
     }
   }
-  write_partial<1>(partials, chunks, sys, chunk, acc);
-}
-
-__global__ void __launch_bounds__(KT) kk_init_fin(int64_t n, const int* gate, int* status, KState* st,
-                                                  const double* partials, double tol, int maxit) {
-  const int sys = blockIdx.x;
-  const int64_t chunks = chunks_of(n);
-  if (gate && *gate != ST_ACTIVE) {
-    if (threadIdx.x == 0) status[sys] = ST_IDLE;
-    return;
-  }
-  double v[1];
-  final_sum<1>(partials, chunks, sys, v);
-  if (threadIdx.x == 0) {
-    KState& k = st[sys];
-    const double nb = sqrt(v[0]);
-    k.nb = nb;
-    k.rho = mk<double>(v[0], 0.0);
-    k.rho_old = mk<double>(1.0, 0.0);
-    k.alpha = mk<double>(1.0, 0.0);
-    k.omega = mk<double>(1.0, 0.0);
-    k.beta = mk<double>(0.0, 0.0);
-    k.rnorm = nb > 0.0 ? 1.0 : 0.0;
-    k.snorm = k.rnorm;
-    k.tol = tol;
-    k.iters = 0;
-    k.maxit = maxit;
-    status[sys] = nb > 0.0 ? ST_ACTIVE : ST_CONVERGED;
+  if (last_block_sum<1>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters)) {
+    KState& st = k.st[sys];
+    const double nb = sqrt(acc[0]);
+    st.nb = nb;
+    st.rho = mk<double>(acc[0], 0.0);
+    st.rho_old = mk<double>(1.0, 0.0);
+    st.alpha = mk<double>(1.0, 0.0);
+    st.omega = mk<double>(1.0, 0.0);
+    st.beta = mk<double>(0.0, 0.0);
+    st.rnorm = nb > 0.0 ? 1.0 : 0.0;
+    st.snorm = st.rnorm;
+    st.tol = tol;
+    st.iters = 0;
+    st.maxit = maxit;
+    k.status[sys] = nb > 0.0 ? ST_ACTIVE : ST_CONVERGED;
   }
 }
 
 void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, double tol, int maxit, const int* gate,
             hipStream_t s) {
   const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_init, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, gate, b, x, r, rhat, k.partials);
-  hipLaunchKernelGGL(kk_init_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, gate, k.status, k.st, k.partials, tol, maxit);
+  hipLaunchKernelGGL(kk_init, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, gate, b, x, r, rhat, tol, maxit);
   check_launch("krylov init");
 }
 
 // ---------------------------------------------------------------- p update
-__global__ void __launch_bounds__(KT) kk_update_p(int64_t n, const int* status, const KState* st, const c128* r,
-                                                  const c128* v, c128* p) {
+__global__ void __launch_bounds__(KT) kk_update_p(KBatch k, const c128* r, const c128* v, c128* p) {
+  const int64_t n = k.n;
   KRYLOV_INDEX
   (void)chunk;
-  if (status[sys] != ST_ACTIVE) return;
-  const KState& k = st[sys];
-  const bool first = k.iters == 0;
-  const c128 beta = k.beta, omega = k.omega;
+  if (k.status[sys] != ST_ACTIVE) return;
+  const KState& st = k.st[sys];
+  const bool first = st.iters == 0;
+  const c128 beta = st.beta, omega = st.omega;
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
     const int64_t i = i0 + (int64_t)j * KT;
     if (i < n) {
       const c128 rv = r[base + i];
-      if (first) {
-        p[base + i] = rv;
-      } else {
-        p[base + i] = rv + beta * (p[base + i] - omega * v[base + i]);
-      }
+      p[base + i] = first ? rv : rv + beta * (p[base + i] - omega * v[base + i]);
     }
   }
 }
 
 void k_update_p(const KBatch& k, const c128* r, const c128* v, c128* p, hipStream_t s) {
   const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_update_p, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, k.st, r, v, p);
+  hipLaunchKernelGGL(kk_update_p, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, r, v, p);
   check_launch("krylov p");
 }
 
 // ---------------------------------------------------------------- alpha
-__global__ void __launch_bounds__(KT) kk_dot(int64_t n, const int* status, const c128* a, const c128* b,
-                                             double* partials) {
+__global__ void __launch_bounds__(KT) kk_alpha(KBatch k, const c128* rhat, const c128* v) {
+  const int64_t n = k.n;
   KRYLOV_INDEX
-  if (status[sys] != ST_ACTIVE) return;
+  if (k.status[sys] != ST_ACTIVE) return;
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
     const int64_t i = i0 + (int64_t)j * KT;
     if (i < n) {
-      const c128 d = cdot1(a[base + i], b[base + i]);
+      const c128 d = cdot1(rhat[base + i], v[base + i]);
       acc[0] += d.x;
       acc[1] += d.y;
     }
   }
-  write_partial<2>(partials, chunks, sys, chunk, acc);
-}
-
-__global__ void __launch_bounds__(KT) kk_alpha_fin(int64_t n, int* status, KState* st, const double* partials) {
-  const int sys = blockIdx.x;
-  if (status[sys] != ST_ACTIVE) return;
-  double v[2];
-  final_sum<2>(partials, chunks_of(n), sys, v);
-  if (threadIdx.x == 0) {
-    KState& k = st[sys];
-    k.iters += 1;
-    const c128 den = mk<double>(v[0], v[1]);
-    if (den.x == 0.0 && den.y == 0.0) {
-      status[sys] = ST_BREAKDOWN;
-    } else {
-      k.alpha = cdiv(k.rho, den);
-    }
-  }
+  if (last_block_sum<2>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
+    fin_alpha(k.st[sys], &k.status[sys], acc);
 }
 
 void k_alpha(const KBatch& k, const c128* rhat, const c128* v, hipStream_t s) {
   const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_dot, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, rhat, v, k.partials);
-  hipLaunchKernelGGL(kk_alpha_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  hipLaunchKernelGGL(kk_alpha, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, rhat, v);
   check_launch("krylov alpha");
 }
 
 // ---------------------------------------------------------------- s update
-__global__ void __launch_bounds__(KT) kk_update_s(int64_t n, const int* status, const KState* st, const c128* r,
-                                                  const c128* v, c128* sv, double* partials) {
+__global__ void __launch_bounds__(KT) kk_update_s(KBatch k, const c128* r, const c128* v, c128* sv) {
+  const int64_t n = k.n;
   KRYLOV_INDEX
-  if (status[sys] != ST_ACTIVE) return;
-  const c128 alpha = st[sys].alpha;
+  if (k.status[sys] != ST_ACTIVE) return;
+  const c128 alpha = k.st[sys].alpha;
   double acc[1] = {0.0};
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
@@ -238,34 +151,21 @@ __global__ void __launch_bounds__(KT) kk_update_s(int64_t n, const int* status, 
       acc[0] += abs2(sval);
     }
   }
-  write_partial<1>(partials, chunks, sys, chunk, acc);
-}
-
-__global__ void __launch_bounds__(KT) kk_s_fin(int64_t n, int* status, KState* st, const double* partials) {
-  const int sys = blockIdx.x;
-  if (status[sys] != ST_ACTIVE) return;
-  double v[1];
-  final_sum<1>(partials, chunks_of(n), sys, v);
-  if (threadIdx.x == 0) {
-    KState& k = st[sys];
-    k.snorm = sqrt(v[0]) / k.nb;
-    if (k.snorm <= k.tol) status[sys] = ST_HALF;
-  }
+  if (last_block_sum<1>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
+    fin_s(k.st[sys], &k.status[sys], acc[0]);
 }
 
 void k_update_s(const KBatch& k, const c128* r, const c128* v, c128* sv, hipStream_t s) {
   const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_update_s, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, k.st, r, v, sv,
-                     k.partials);
-  hipLaunchKernelGGL(kk_s_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  hipLaunchKernelGGL(kk_update_s, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, r, v, sv);
   check_launch("krylov s");
 }
 
 // ---------------------------------------------------------------- omega
-__global__ void __launch_bounds__(KT) kk_dot_ts(int64_t n, const int* status, const c128* t, const c128* sv,
-                                                double* partials) {
+__global__ void __launch_bounds__(KT) kk_omega(KBatch k, const c128* t, const c128* sv) {
+  const int64_t n = k.n;
   KRYLOV_INDEX
-  if (status[sys] != ST_ACTIVE) return;
+  if (k.status[sys] != ST_ACTIVE) return;
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
@@ -278,48 +178,38 @@ __global__ void __launch_bounds__(KT) kk_dot_ts(int64_t n, const int* status, co
       acc[2] += abs2(tv);
     }
   }
-  write_partial<3>(partials, chunks, sys, chunk, acc);
-}
-
-__global__ void __launch_bounds__(KT) kk_omega_fin(int64_t n, int* status, KState* st, const double* partials) {
-  const int sys = blockIdx.x;
-  if (status[sys] != ST_ACTIVE) return;
-  double v[3];
-  final_sum<3>(partials, chunks_of(n), sys, v);
-  if (threadIdx.x == 0) {
-    KState& k = st[sys];
-    if (v[2] == 0.0) {
-      status[sys] = ST_BREAKDOWN;
-    } else {
-      k.omega = mk<double>(v[0] / v[2], v[1] / v[2]);
-    }
-  }
+  if (last_block_sum<3>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
+    fin_omega(k.st[sys], &k.status[sys], acc);
 }
 
 void k_omega(const KBatch& k, const c128* t, const c128* sv, hipStream_t s) {
   const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_dot_ts, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, t, sv, k.partials);
-  hipLaunchKernelGGL(kk_omega_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  hipLaunchKernelGGL(kk_omega, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, t, sv);
   check_launch("krylov omega");
 }
 
 // ---------------------------------------------------------------- x, r update
-__global__ void __launch_bounds__(KT) kk_update_xr(int64_t n, const int* status, const KState* st, c128* x,
-                                                   const c128* y, const c128* z, c128* r, const c128* sv,
-                                                   const c128* t, const c128* rhat, double* partials) {
+__global__ void __launch_bounds__(KT) kk_update_xr(KBatch k, c128* x, const c128* y, const c128* z, c128* r,
+                                                   const c128* sv, const c128* t, const c128* rhat) {
+  const int64_t n = k.n;
   KRYLOV_INDEX
-  const int stt = status[sys];
+  const int stt = k.status[sys];
   if (stt == ST_HALF) {
-    const c128 alpha = st[sys].alpha;
+    const c128 alpha = k.st[sys].alpha;
 #pragma unroll
     for (int j = 0; j < KEPT; ++j) {
       const int64_t i = i0 + (int64_t)j * KT;
       if (i < n) x[base + i] = x[base + i] + alpha * y[base + i];
     }
+    double acc[1] = {0.0};
+    if (last_block_sum<1>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters)) {
+      k.st[sys].rnorm = k.st[sys].snorm;
+      k.status[sys] = ST_CONVERGED;
+    }
     return;
   }
   if (stt != ST_ACTIVE) return;
-  const c128 alpha = st[sys].alpha, omega = st[sys].omega;
+  const c128 alpha = k.st[sys].alpha, omega = k.st[sys].omega;
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
@@ -334,47 +224,14 @@ __global__ void __launch_bounds__(KT) kk_update_xr(int64_t n, const int* status,
       acc[2] += abs2(rv);
     }
   }
-  write_partial<3>(partials, chunks, sys, chunk, acc);
-}
-
-__global__ void __launch_bounds__(KT) kk_xr_fin(int64_t n, int* status, KState* st, const double* partials) {
-  const int sys = blockIdx.x;
-  const int stt = status[sys];
-  if (stt == ST_HALF) {
-    if (threadIdx.x == 0) {
-      st[sys].rnorm = st[sys].snorm;
-      status[sys] = ST_CONVERGED;
-    }
-    return;
-  }
-  if (stt != ST_ACTIVE) return;
-  double v[3];
-  final_sum<3>(partials, chunks_of(n), sys, v);
-  if (threadIdx.x == 0) {
-    KState& k = st[sys];
-    k.rnorm = sqrt(v[2]) / k.nb;
-    k.rho_old = k.rho;
-    k.rho = mk<double>(v[0], v[1]);
-    const bool om0 = k.omega.x == 0.0 && k.omega.y == 0.0;
-    const bool rho0 = k.rho.x == 0.0 && k.rho.y == 0.0;
-    if (k.rnorm <= k.tol) {
-      status[sys] = ST_CONVERGED;
-    } else if (om0 || rho0 || !(k.rnorm == k.rnorm)) {
-      status[sys] = ST_BREAKDOWN;
-    } else if (k.iters >= k.maxit) {
-      status[sys] = ST_MAXIT;
-    } else {
-      k.beta = cdiv(k.rho, k.rho_old) * cdiv(k.alpha, k.omega);
-    }
-  }
+  if (last_block_sum<3>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
+    fin_xr(k.st[sys], &k.status[sys], acc);
 }
 
 void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv, const c128* t,
                  const c128* rhat, hipStream_t s) {
   const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_update_xr, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k.n, k.status, k.st, x, y, z, r,
-                     sv, t, rhat, k.partials);
-  hipLaunchKernelGGL(kk_xr_fin, dim3(k.nsys), dim3(KT), 0, s, k.n, k.status, k.st, k.partials);
+  hipLaunchKernelGGL(kk_update_xr, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, y, z, r, sv, t, rhat);
   check_launch("krylov xr");
 }
 
@@ -459,7 +316,9 @@ void add_vec(c128* x, const c128* d, int64_t n, hipStream_t s) {
   check_launch("add");
 }
 
-__global__ void __launch_bounds__(KT) kk_norm2(int64_t n, const c128* v, double* partials) {
+// ||v||^2 of one vector; partials [chunks * NPART], counter one int
+__global__ void __launch_bounds__(KT) kk_norm2(int64_t n, const c128* v, double* partials, int* counter,
+                                               double* out) {
   KRYLOV_INDEX
   double acc[1] = {0.0};
 #pragma unroll
@@ -467,19 +326,12 @@ __global__ void __launch_bounds__(KT) kk_norm2(int64_t n, const c128* v, double*
     const int64_t i = i0 + (int64_t)j * KT;
     if (i < n) acc[0] += abs2(v[base + i]);
   }
-  write_partial<1>(partials, chunks, sys, chunk, acc);
+  if (last_block_sum<1>(acc, partials, 0, sys, chunk, chunks, counter)) *out = acc[0];
 }
 
-__global__ void __launch_bounds__(KT) kk_norm2_fin(int64_t n, const double* partials, double* out) {
-  double v[1];
-  final_sum<1>(partials, chunks_of(n), 0, v);
-  if (threadIdx.x == 0) *out = v[0];
-}
-
-void norm2(const c128* v, int64_t n, double* partials, double* out, hipStream_t s) {
+void norm2(const c128* v, int64_t n, double* partials, int* counter, double* out, hipStream_t s) {
   const int64_t chunks = chunks_of(n);
-  hipLaunchKernelGGL(kk_norm2, dim3((unsigned)chunks), dim3(KT), 0, s, n, v, partials);
-  hipLaunchKernelGGL(kk_norm2_fin, dim3(1), dim3(KT), 0, s, n, partials, out);
+  hipLaunchKernelGGL(kk_norm2, dim3((unsigned)chunks), dim3(KT), 0, s, n, v, partials, counter, out);
   check_launch("norm2");
 }
 

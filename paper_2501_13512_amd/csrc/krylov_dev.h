@@ -1,0 +1,131 @@
+// Device-side pieces of the BiCGSTAB step shared by the vector kernels and
+// by the FFT passes that fuse vector updates and inner products.
+//
+// Reductions: every workgroup of a system writes its partial sum, then takes
+// a ticket from the system's counter; the workgroup holding the last ticket
+// sums all partials in a fixed order (deterministic, no float atomics),
+// applies the scalar step of the iteration and resets the counter.
+#pragma once
+#include "kernels.h"
+
+namespace vie {
+
+constexpr int NPART = 4;   // doubles per partial
+
+// Sum NV doubles over the workgroup (any size <= 1024); valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double sm[16][NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  // lanes that exist in this wavefront (the last one may be partial)
+  const int live = min(64, (int)blockDim.x - wid * 64);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double o = __shfl_down(v[k], off, 64);
+      if (lane + off < live) v[k] += o;
+    }
+  __syncthreads();   // sm may still be read by a previous call
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sm[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double a = sm[0][k];
+      for (int w = 1; w < nw; ++w) a += sm[w][k];
+      v[k] = a;
+    }
+  }
+}
+
+// Workgroup `tile` of `ntiles` of system `sys` contributes v.  Returns true in
+// thread 0 of the last workgroup to arrive, with the system total in v.
+template <int NV>
+__device__ __forceinline__ bool last_block_sum(double (&v)[NV], double* partials, int64_t pstride, int sys,
+                                               int64_t tile, int64_t ntiles, int* counters) {
+  __shared__ int is_last;
+  block_sum<NV>(v);
+  if (threadIdx.x == 0) {
+    double* p = partials + sys * pstride + tile * NPART;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) p[k] = v[k];
+    __threadfence();
+    const int prev = atomicAdd(&counters[sys], 1);
+    is_last = (prev == (int)ntiles - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  double w[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) w[k] = 0.0;
+  for (int64_t c = threadIdx.x; c < ntiles; c += blockDim.x) {
+    const double* p = partials + sys * pstride + c * NPART;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) w[k] += p[k];
+  }
+  block_sum<NV>(w);
+  if (threadIdx.x == 0) {
+    counters[sys] = 0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = w[k];
+    return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ c128 cdiv(c128 a, c128 b) {
+  const double s = fabs(b.x) + fabs(b.y);
+  const double br = b.x / s, bi = b.y / s, ar = a.x / s, ai = a.y / s;
+  const double d = br * br + bi * bi;
+  return mk<double>((ar * br + ai * bi) / d, (ai * br - ar * bi) / d);
+}
+
+// ---- scalar steps (thread 0 of the finishing workgroup) ----
+
+// alpha = rho / <rhat, v>; counts the step
+__device__ __forceinline__ void fin_alpha(KState& k, int* status, const double* v) {
+  k.iters += 1;
+  const c128 den = mk<double>(v[0], v[1]);
+  if (den.x == 0.0 && den.y == 0.0)
+    *status = ST_BREAKDOWN;
+  else
+    k.alpha = cdiv(k.rho, den);
+}
+
+// half-step test on ||s||
+__device__ __forceinline__ void fin_s(KState& k, int* status, double s2) {
+  k.snorm = sqrt(s2) / k.nb;
+  if (k.snorm <= k.tol) *status = ST_HALF;
+}
+
+// omega = <t, s> / <t, t>
+__device__ __forceinline__ void fin_omega(KState& k, int* status, const double* v) {
+  if (v[2] == 0.0)
+    *status = ST_BREAKDOWN;
+  else
+    k.omega = mk<double>(v[0] / v[2], v[1] / v[2]);
+}
+
+// new rho = <rhat, r>, ||r||; convergence, breakdown, cap, next beta
+__device__ __forceinline__ void fin_xr(KState& k, int* status, const double* v) {
+  k.rnorm = sqrt(v[2]) / k.nb;
+  k.rho_old = k.rho;
+  k.rho = mk<double>(v[0], v[1]);
+  const bool om0 = k.omega.x == 0.0 && k.omega.y == 0.0;
+  const bool rho0 = k.rho.x == 0.0 && k.rho.y == 0.0;
+  if (k.rnorm <= k.tol)
+    *status = ST_CONVERGED;
+  else if (om0 || rho0 || !(k.rnorm == k.rnorm))
+    *status = ST_BREAKDOWN;
+  else if (k.iters >= k.maxit)
+    *status = ST_MAXIT;
+  else
+    k.beta = cdiv(k.rho, k.rho_old) * cdiv(k.alpha, k.omega);
+}
+
+}  // namespace vie

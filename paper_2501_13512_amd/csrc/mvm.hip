@@ -10,9 +10,10 @@
 //   1. x forward, pruned: rows of nx voxels, zero-padded to lx;
 //   2. y forward, pruned: only the nz non-zero z-planes exist;
 //   3. z forward + 3x3 symmetric spectral multiply + z inverse, fused in one
-//      workgroup per (qy, tile of qx) with all three components in LDS;
-//      the spectrum is read from its octant q in [0, L/2]^3 with the parity
-//      signs of the odd components (T_xy is odd in x and y, ...);
+//      workgroup per (y-fold, tile of x-folds): the four mirror columns
+//      (+-qx, +-qy) of the three components sit in LDS together, so each
+//      value of the octant spectrum (q in [0, L/2]^3, parity signs for the
+//      odd components: T_xy is odd in x and y, ...) is read once;
 //   4. y inverse, cropped to ny rows;
 //   5. x inverse, cropped to nx, scaled by 1/(lx ly lz), fused with the
 //      local term and the vacuum mask, written as c128.
@@ -21,7 +22,7 @@
 #include <string>
 
 #include "fft_core.h"
-#include "kernels.h"
+#include "krylov_dev.h"
 
 namespace vie {
 
@@ -48,8 +49,6 @@ struct Geo {
   static constexpr int ROWP = cmax(1, cmin(256 / T, (64 * 1024) / (L * ES)));
   // columns (strided pencils): >= 16 columns for coalescing, LDS [L][COLP]
   static constexpr int COLP = cmax(1, pow2_floor(cmin(cmax(16, 256 / T), cmin(512 / T, (64 * 1024) / (L * ES)))));
-  // fused z pass: three components side by side, LDS [3][L][ZP]
-  static constexpr int ZP = cmax(1, pow2_floor(cmin(64, cmin(1024 / (3 * T), (144 * 1024) / (3 * L * ES)))));
 };
 
 __device__ __forceinline__ bool sys_active(const int* status, int s) {
@@ -74,6 +73,14 @@ struct RowArgs {
   const cx<R>* tw;
   int mask_input;
   double scale;
+  // BiCGSTAB work fused into pass 1 (in_mode) and pass 5 (out_mode)
+  int in_mode, out_mode;
+  const c128* r;
+  c128* p;
+  const c128* v;
+  const c128* rhat;
+  const c128* s;
+  KBatch k;
 };
 
 // Pass 1: x forward with zero padding nx -> lx, c128 -> R.
@@ -91,17 +98,40 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_fwd(Ro
   const int rr = valid ? row : 0;
   const int c = rr / (a.nz * a.ny), zy = rr - c * (a.nz * a.ny);
   const int z = zy / a.ny, yy = zy - z * a.ny;
-  const c128* xin = a.x + sys * a.vstride + (int64_t)rr * a.nx;
+  const int64_t vrow = sys * a.vstride + (int64_t)rr * a.nx;
+  const c128* xin = a.x + vrow;
   const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
   cx<R>* w = a.work + sys * a.wstride + ((int64_t)(c * a.nz + z) * a.ly + yy) * a.lx;
   const int nx = a.nx;
   const bool msk = a.mask_input != 0;
+  const int mode = a.in_mode;
+  c128 c1 = mk<double>(0.0, 0.0), c2 = c1;
+  bool first = false;
+  if (mode == 1) {
+    first = a.k.st[sys].iters == 0;
+    c1 = a.k.st[sys].beta;
+    c2 = a.k.st[sys].omega;
+  } else if (mode == 2) {
+    c1 = a.k.st[sys].alpha;
+  }
+  double acc = 0.0;
   auto ld = [&](int n) -> cx<R> {
     if (n < nx) {
-      c128 v = xin[n];
-      if (msk) {
-        c128 ci = chi[n];
-        if (ci.x == 0.0 && ci.y == 0.0) v = mk<double>(0.0, 0.0);
+      c128 v;
+      if (mode == 1) {          // p = r + beta (p - omega v), or r on the first step
+        const c128 rv = a.r[vrow + n];
+        v = first ? rv : rv + c1 * (a.p[vrow + n] - c2 * a.v[vrow + n]);
+        a.p[vrow + n] = v;
+      } else if (mode == 2) {   // s = r - alpha v
+        v = a.r[vrow + n] - c1 * a.v[vrow + n];
+        a.p[vrow + n] = v;
+        acc += abs2(v);
+      } else {
+        v = xin[n];
+        if (msk) {
+          c128 ci = chi[n];
+          if (ci.x == 0.0 && ci.y == 0.0) v = mk<double>(0.0, 0.0);
+        }
       }
       return cvt<R>(v);
     }
@@ -109,6 +139,11 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_fwd(Ro
   };
   auto st = [&](int k, cx<R> v) { w[k] = v; };
   fft_pencil<R, L, G::T, -1>(ld, st, lds + p * L, 1, t, valid, a.tw);
+  if (mode == 2) {
+    double sum[1] = {acc};
+    if (last_block_sum<1>(sum, a.k.partials, a.k.pstride, sys, tile, tiles, a.k.counters))
+      fin_s(a.k.st[sys], &a.k.status[sys], sum[0]);
+  }
 }
 
 // Pass 5: x inverse, crop lx -> nx, y = x/chi - scale * Q on the mask, 0 off it.
@@ -126,12 +161,15 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
   const int rr = valid ? row : 0;
   const int c = rr / (a.nz * a.ny), zy = rr - c * (a.nz * a.ny);
   const int z = zy / a.ny, yy = zy - z * a.ny;
-  const c128* xin = a.x + sys * a.vstride + (int64_t)rr * a.nx;
-  c128* yout = a.y + sys * a.vstride + (int64_t)rr * a.nx;
+  const int64_t vrow = sys * a.vstride + (int64_t)rr * a.nx;
+  const c128* xin = a.x + vrow;
+  c128* yout = a.y + vrow;
   const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
   const cx<R>* w = a.work + sys * a.wstride + ((int64_t)(c * a.nz + z) * a.ly + yy) * a.lx;
   const int nx = a.nx;
   const double scale = a.scale;
+  const int mode = a.out_mode;
+  double acc[3] = {0.0, 0.0, 0.0};
   auto ld = [&](int n) -> cx<R> { return w[n]; };
   auto st = [&](int k, cx<R> v) {
     if (k < nx) {
@@ -142,9 +180,27 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
         out = xin[k] * ci - scale * q;
       }
       yout[k] = out;
+      if (mode == 1) {          // <rhat, y>
+        const c128 d = cdot1(a.rhat[vrow + k], out);
+        acc[0] += d.x;
+        acc[1] += d.y;
+      } else if (mode == 2) {   // <y, s>, <y, y>
+        const c128 d = cdot1(out, a.s[vrow + k]);
+        acc[0] += d.x;
+        acc[1] += d.y;
+        acc[2] += abs2(out);
+      }
     }
   };
   fft_pencil<R, L, G::T, +1>(ld, st, lds + p * L, 1, t, valid, a.tw);
+  if (mode == 1) {
+    double sum[2] = {acc[0], acc[1]};
+    if (last_block_sum<2>(sum, a.k.partials, a.k.pstride, sys, tile, tiles, a.k.counters))
+      fin_alpha(a.k.st[sys], &a.k.status[sys], sum);
+  } else if (mode == 2) {
+    if (last_block_sum<3>(acc, a.k.partials, a.k.pstride, sys, tile, tiles, a.k.counters))
+      fin_omega(a.k.st[sys], &a.k.status[sys], acc);
+  }
 }
 
 // In-place FFT of full-length rows (spectra setup).
@@ -199,6 +255,38 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::COLP)) k_col(ColArg
 }
 
 // Pass 3: z forward (nz -> LZ), spectral multiply, z inverse (LZ -> nz).
+//
+// The spectrum is stored for q in [0, L/2] per axis only; the other octants
+// are the same values with a sign (S_ij(L - q) = +-S_ij(q)).  An axis of
+// length L is covered by folds f in [0, nfold(L)); fold f stands for column
+// f (mirror 0) and column L - f (mirror 1), both using spectral index f.
+// For even L fold 0's mirror is the Nyquist column L/2 (spectral index L/2,
+// sign +); for odd L fold 0 has no mirror.  A workgroup takes one y-fold and
+// ZP consecutive x-folds and transforms all four mirror columns
+// (+-qx, +-qy) of the three components, so each spectrum value is loaded
+// once and applied to up to 8 points (+-qx, +-qy, qz and LZ - qz).
+__host__ __device__ constexpr int nfold(int L) { return (L % 2 == 0) ? L / 2 : (L + 1) / 2; }
+
+struct FoldCol {
+  int col;  // column index, -1 if absent
+  int sf;   // spectral (octant) index
+  int sg;   // parity sign for components odd in this axis
+};
+
+__device__ __forceinline__ FoldCol fold_col(int f, int m, int L) {
+  if (m == 0) return {f, f, 1};
+  if (f > 0) return {L - f, f, -1};
+  if ((L & 1) == 0 && L >= 2) return {L / 2, L / 2, 1};
+  return {-1, 0, 1};
+}
+
+template <typename R, int LZ>
+struct ZGeo {
+  static constexpr int T = PlanInfo<LZ>::max_butterflies;
+  static constexpr int ES = (int)sizeof(cx<R>);
+  static constexpr int ZP = cmax(1, pow2_floor(cmin(64, cmin(1024 / (3 * T), (144 * 1024) / (12 * LZ * ES)))));
+};
+
 template <typename R>
 struct ZArgs {
   int nz, ly, lx;
@@ -210,59 +298,94 @@ struct ZArgs {
 };
 
 template <typename R, int LZ>
-__global__ void __launch_bounds__((3 * Geo<R, LZ>::T * Geo<R, LZ>::ZP)) k_zconv(ZArgs<R> a) {
-  using G = Geo<R, LZ>;
+__global__ void __launch_bounds__((3 * ZGeo<R, LZ>::T * ZGeo<R, LZ>::ZP)) k_zconv(ZArgs<R> a) {
+  using G = ZGeo<R, LZ>;
   constexpr int T = G::T, ZP = G::ZP;
-  __shared__ cx<R> lds[3 * LZ * ZP];
-  const int cols = a.ly * a.lx;
-  const int tiles = (cols + ZP - 1) / ZP;
-  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  constexpr int SLOT = LZ * ZP;           // one (mirror, component) pencil set
+  __shared__ cx<R> lds[12 * SLOT];        // [mirror 4][component 3][qz][p]
+  const int lx = a.lx, ly = a.ly, nz = a.nz;
+  const int nfx = nfold(lx), nfy = nfold(ly);
+  const int xt = (nfx + ZP - 1) / ZP;
+  const int per_sys = nfy * xt;
+  const int sys = blockIdx.x / per_sys;
+  const int rr = blockIdx.x - sys * per_sys;
+  const int fy = rr / xt, ft = rr - fy * xt;
   if (!sys_active(a.status, sys)) return;
   const int comp = threadIdx.x / (T * ZP);
   const int rem = threadIdx.x - comp * (T * ZP);
   const int p = rem % ZP, t = rem / ZP;
-  const int col = tile * ZP + p;
-  const bool valid = col < cols;
-  const int64_t plane = (int64_t)a.ly * a.lx;
-  cx<R>* base = a.work + sys * a.wstride + (int64_t)comp * a.nz * plane + (valid ? col : 0);
-  cx<R>* slot = lds + comp * LZ * ZP + p;
-  const int nz = a.nz;
-  // forward along z into the component's LDS slot
-  auto ldg = [&](int n) -> cx<R> { return n < nz ? base[n * plane] : czero<R>(); };
-  auto sts = [&](int k, cx<R> v) { slot[k * ZP] = v; };
-  fft_pencil<R, LZ, T, -1, false, true>(ldg, sts, slot, ZP, t, valid, a.tw);
+  const int fx = ft * ZP + p;
+  const bool pvalid = fx < nfx;
+  const int64_t plane = (int64_t)ly * lx;
+  cx<R>* wsys = a.work + sys * a.wstride + (int64_t)comp * nz * plane;
 
-  // Q(q) = S(q) X(q), S symmetric 3x3 from the octant with parity signs
-  const int lx = a.lx, ly = a.ly;
-  const int hx = lx / 2, hy = ly / 2, hz = LZ / 2;
-  const int64_t ox = hx + 1, oy = hy + 1;
-  const int64_t oct = ox * oy * (hz + 1);
+  // forward along z of the four mirror columns, into LDS
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const FoldCol cxm = fold_col(fx, m & 1, lx), cym = fold_col(fy, m >> 1, ly);
+    const bool valid = pvalid && cxm.col >= 0 && cym.col >= 0;
+    cx<R>* base = wsys + (valid ? (int64_t)cym.col * lx + cxm.col : 0);
+    cx<R>* slot = lds + (m * 3 + comp) * SLOT + p;
+    auto ldg = [&](int n) -> cx<R> { return n < nz ? base[n * plane] : czero<R>(); };
+    auto sts = [&](int k, cx<R> v) { slot[k * ZP] = v; };
+    fft_pencil<R, LZ, T, -1, false, true>(ldg, sts, slot, ZP, t, valid, a.tw);
+  }
+
+  // Q = S X at every point of the four columns; one spectrum load per
+  // (fold x, fold y, fold z), reused for its mirrors
+  const int64_t ox = lx / 2 + 1, oy = ly / 2 + 1;
+  const int64_t oct = ox * oy * (LZ / 2 + 1);
   const cx<R>* spec = a.spec + sys * a.sstride;
-  for (int i = threadIdx.x; i < LZ * ZP; i += 3 * T * ZP) {
-    const int qz = i / ZP, pp = i - qz * ZP;
-    const int c2 = tile * ZP + pp;
-    if (c2 >= cols) continue;
-    const int qy = c2 / lx, qx = c2 - qy * lx;
-    const int fx = qx <= hx ? qx : lx - qx, fy = qy <= hy ? qy : ly - qy, fz = qz <= hz ? qz : LZ - qz;
-    const R sx = qx <= hx ? R(1) : R(-1), sy = qy <= hy ? R(1) : R(-1), sz = qz <= hz ? R(1) : R(-1);
-    const int64_t o = ((int64_t)fz * oy + fy) * ox + fx;
-    const cx<R> sxx = spec[o], syy = spec[3 * oct + o], szz = spec[5 * oct + o];
-    const cx<R> sxy = (sx * sy) * spec[oct + o];
-    const cx<R> sxz = (sx * sz) * spec[2 * oct + o];
-    const cx<R> syz = (sy * sz) * spec[4 * oct + o];
-    const int e = qz * ZP + pp;
-    const cx<R> X = lds[e], Y = lds[LZ * ZP + e], Z = lds[2 * LZ * ZP + e];
-    lds[e] = sxx * X + sxy * Y + sxz * Z;
-    lds[LZ * ZP + e] = sxy * X + syy * Y + syz * Z;
-    lds[2 * LZ * ZP + e] = sxz * X + syz * Y + szz * Z;
+  constexpr int NFZ = nfold(LZ);
+  for (int i = threadIdx.x; i < NFZ * ZP; i += 3 * T * ZP) {
+    const int fz = i / ZP, pp = i - fz * ZP;
+    const int fxx = ft * ZP + pp;
+    if (fxx >= nfx) continue;
+    int64_t o_prev = -1;
+    cx<R> sxx, sxy, sxz, syy, syz, szz;
+#pragma unroll
+    for (int mz = 0; mz < 2; ++mz) {
+      const FoldCol czm = fold_col(fz, mz, LZ);
+      if (czm.col < 0) continue;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const FoldCol cxm = fold_col(fxx, m & 1, lx), cym = fold_col(fy, m >> 1, ly);
+        if (cxm.col < 0 || cym.col < 0) continue;
+        const int64_t o = ((int64_t)czm.sf * oy + cym.sf) * ox + cxm.sf;
+        if (o != o_prev) {
+          sxx = spec[o];
+          sxy = spec[oct + o];
+          sxz = spec[2 * oct + o];
+          syy = spec[3 * oct + o];
+          syz = spec[4 * oct + o];
+          szz = spec[5 * oct + o];
+          o_prev = o;
+        }
+        const R gxy = R(cxm.sg * cym.sg), gxz = R(cxm.sg * czm.sg), gyz = R(cym.sg * czm.sg);
+        const cx<R> axy = gxy * sxy, axz = gxz * sxz, ayz = gyz * syz;
+        cx<R>* e = lds + m * 3 * SLOT + czm.col * ZP + pp;
+        const cx<R> X = e[0], Y = e[SLOT], Z = e[2 * SLOT];
+        e[0] = sxx * X + axy * Y + axz * Z;
+        e[SLOT] = axy * X + syy * Y + ayz * Z;
+        e[2 * SLOT] = axz * X + ayz * Y + szz * Z;
+      }
+    }
   }
   __syncthreads();
-  // inverse along z, cropped to nz
-  auto lds_ld = [&](int n) -> cx<R> { return slot[n * ZP]; };
-  auto stg = [&](int k, cx<R> v) {
-    if (k < nz) base[k * plane] = v;
-  };
-  fft_pencil<R, LZ, T, +1, true, false>(lds_ld, stg, slot, ZP, t, valid, a.tw);
+
+  // inverse along z, cropped to nz, back to HBM
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const FoldCol cxm = fold_col(fx, m & 1, lx), cym = fold_col(fy, m >> 1, ly);
+    const bool valid = pvalid && cxm.col >= 0 && cym.col >= 0;
+    cx<R>* base = wsys + (valid ? (int64_t)cym.col * lx + cxm.col : 0);
+    cx<R>* slot = lds + (m * 3 + comp) * SLOT + p;
+    auto lds_ld = [&](int n) -> cx<R> { return slot[n * ZP]; };
+    auto stg = [&](int k, cx<R> v) {
+      if (k < nz) base[k * plane] = v;
+    };
+    fft_pencil<R, LZ, T, +1, true, false>(lds_ld, stg, slot, ZP, t, valid, a.tw);
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -335,13 +458,14 @@ static void launch_col(int L, const ColArgs<R>& a, hipStream_t s) {
 
 template <typename R>
 static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
+  const int per_sys_y = nfold(a.ly), nfx = nfold(a.lx);
   switch (L) {
-#define C(l)                                                                     \
-  case l: {                                                                      \
-    using G = Geo<R, l>;                                                         \
-    const int cols = a.ly * a.lx, tiles = (cols + G::ZP - 1) / G::ZP;            \
-    hipLaunchKernelGGL((k_zconv<R, l>), dim3(tiles * nsys), dim3(3 * G::T * G::ZP), 0, s, a); \
-    break;                                                                       \
+#define C(l)                                                                              \
+  case l: {                                                                               \
+    using G = ZGeo<R, l>;                                                                 \
+    const int blocks = per_sys_y * ((nfx + G::ZP - 1) / G::ZP) * nsys;                    \
+    hipLaunchKernelGGL((k_zconv<R, l>), dim3(blocks), dim3(3 * G::T * G::ZP), 0, s, a);   \
+    break;                                                                                \
   }
     VIE_L_CASES(C)
 #undef C
@@ -416,6 +540,95 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
 
 template void mvm<float>(const MvmBatch<float>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);
 template void mvm<double>(const MvmBatch<double>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);
+
+template <typename R>
+void mvm_fused(const MvmBatch<R>& b, const KBatch& k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s) {
+  if (b.nsys <= 0) return;
+  // The product's input: x, or the vector pass 1 computes and writes to f.p
+  // (the local term of pass 5 reads it).
+  const c128* xin = f.in_mode != 0 ? f.p : x;
+  if (!xin || !y || (f.in_mode != 0 && (!f.r || !f.v)) || (f.out_mode == 1 && !f.rhat) ||
+      (f.out_mode == 2 && !f.s))
+    throw std::runtime_error("mvm_fused: missing vector");
+  RowArgs<R> ra{};
+  ra.nx = b.nx;
+  ra.ny = b.ny;
+  ra.nz = b.nz;
+  ra.lx = b.lx;
+  ra.ly = b.ly;
+  ra.vstride = b.vstride;
+  ra.cstride = b.cstride;
+  ra.wstride = b.wstride;
+  ra.x = xin;
+  ra.y = y;
+  ra.chi_inv = b.chi_inv;
+  ra.work = b.work;
+  ra.status = b.status;
+  ra.tw = b.tw->table[b.lx];
+  ra.mask_input = 0;
+  ra.scale = 1.0 / ((double)b.lx * (double)b.ly * (double)b.lz);
+  ra.r = f.r;
+  ra.p = f.p;
+  ra.v = f.v;
+  ra.rhat = f.rhat;
+  ra.s = f.s;
+  ra.k = k;
+  ra.in_mode = f.in_mode;
+  ra.out_mode = 0;
+  launch_row_fwd<R>(b.lx, ra, b.nsys, s);
+
+  ColArgs<R> ca{};
+  ca.data = b.work;
+  ca.outer = 3 * b.nz;
+  ca.inner = b.lx;
+  ca.n_in = b.ny;
+  ca.n_out = b.ly;
+  ca.stride = b.wstride;
+  ca.status = b.status;
+  ca.tw = b.tw->table[b.ly];
+  ca.nsys = b.nsys;
+  launch_col<R, -1>(b.ly, ca, s);
+
+  ZArgs<R> za{};
+  za.nz = b.nz;
+  za.ly = b.ly;
+  za.lx = b.lx;
+  za.wstride = b.wstride;
+  za.sstride = b.sstride;
+  za.work = b.work;
+  za.spec = b.spec;
+  za.status = b.status;
+  za.tw = b.tw->table[b.lz];
+  launch_zconv<R>(b.lz, za, b.nsys, s);
+
+  ca.n_in = b.ly;
+  ca.n_out = b.ny;
+  launch_col<R, +1>(b.ly, ca, s);
+
+  ra.in_mode = 0;
+  ra.out_mode = f.out_mode;
+  launch_row_inv<R>(b.lx, ra, b.nsys, s);
+}
+
+template void mvm_fused<float>(const MvmBatch<float>&, const KBatch&, const FuseArgs&, const c128*, c128*,
+                               hipStream_t);
+template void mvm_fused<double>(const MvmBatch<double>&, const KBatch&, const FuseArgs&, const c128*, c128*,
+                                hipStream_t);
+
+int64_t mvm_row_tiles(int lx, int nz, int ny) {
+  const int64_t rows = 3 * (int64_t)nz * ny;
+  switch (lx) {
+#define C(l)                                                                            \
+  case l: {                                                                             \
+    const int rp = cmin(Geo<float, l>::ROWP, Geo<double, l>::ROWP);                     \
+    return (rows + rp - 1) / rp;                                                        \
+  }
+    VIE_L_CASES(C)
+#undef C
+    default:
+      bad_length("x pass", lx);
+  }
+}
 
 // ------------------------------------------------------------------ spectra setup
 // T(m) of the discretised dyadic Green's function (eq. (1) with the scalar

@@ -201,7 +201,8 @@ struct Group {
   int bx, by, bz, lx, ly, lz, nsys;
   int64_t bnv, n;
   std::shared_ptr<Spectra> spec;
-  DevBuf chi, work, vecs, partials;
+  DevBuf chi, work, vecs, partials, counters;
+  int64_t pstride;  // doubles of partials per system
   c128* vec[8];  // B, X, R, RHAT, P, V, S, T
   int slot0;     // first entry in the problem's inner status/state arrays
   std::vector<int> blocks;
@@ -216,7 +217,8 @@ struct vie_problem {
   int lx = 0, ly = 0, lz = 0;
   double k0 = 0;
   std::shared_ptr<Spectra> spec;
-  DevBuf chi, work, vecs, partials, ostate, ostatus, scal;
+  DevBuf chi, work, vecs, partials, counters, ostate, ostatus, scal;
+  int64_t pstride = 0;
   c128* vec[V_COUNT] = {};
   // blocks
   int n_blocks = 0, n_nonempty = 0;
@@ -338,6 +340,8 @@ KBatch outer_kbatch(vie_problem& P) {
   k.status = P.ostatus.as<int>();
   k.st = P.ostate.as<KState>();
   k.partials = P.partials.as<double>();
+  k.pstride = P.pstride;
+  k.counters = P.counters.as<int>();
   return k;
 }
 
@@ -348,7 +352,21 @@ KBatch group_kbatch(vie_problem& P, Group& G) {
   k.status = P.d_istatus.as<int>() + G.slot0;
   k.st = P.d_istate.as<KState>() + G.slot0;
   k.partials = G.partials.as<double>();
+  k.pstride = G.pstride;
+  k.counters = G.counters.as<int>();
   return k;
+}
+
+// One BiCGSTAB step with K = I, fused: p update + product + alpha; s update +
+// half-step test + product + omega; x, r update + rho, ||r||.  11 kernels.
+template <typename R>
+void fused_step(const MvmBatch<R>& m, const KBatch& k, c128* x, c128* r, c128* rhat, c128* p, c128* v, c128* sv,
+                c128* t, hipStream_t s) {
+  vie::FuseArgs f1{1, 1, r, p, v, rhat, nullptr};
+  vie::mvm_fused<R>(m, k, f1, nullptr, v, s);
+  vie::FuseArgs f2{2, 2, r, sv, v, nullptr, sv};
+  vie::mvm_fused<R>(m, k, f2, nullptr, t, s);
+  vie::k_update_xr(k, x, p, sv, r, sv, t, rhat, s);
 }
 
 c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (size_t)kind * P.groups.size(); }
@@ -361,13 +379,7 @@ void inner_iteration(vie_problem& P, hipStream_t s) {
     KBatch k = group_kbatch(P, G);
     MvmBatch<R> m = group_batch<R>(P, G, true);
     c128** v = G.vec;
-    vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
-    vie::mvm<R>(m, v[V_P], v[V_V], false, s);
-    vie::k_alpha(k, v[V_RHAT], v[V_V], s);
-    vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
-    vie::mvm<R>(m, v[V_S], v[V_T], false, s);
-    vie::k_omega(k, v[V_T], v[V_S], s);
-    vie::k_update_xr(k, v[V_X], v[V_P], v[V_S], v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
+    fused_step<R>(m, k, v[V_X], v[V_R], v[V_RHAT], v[V_P], v[V_V], v[V_S], v[V_T], s);
   }
 }
 
@@ -445,23 +457,19 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
   vie::k_init(k, rhs, x, v[V_R], v[V_RHAT], tol, maxit, nullptr, s);
   Poller poll(P, s, 0);
   for (int it = 1; it <= maxit; ++it) {
-    vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
-    c128* yv = v[V_P];
-    if (prec) {
-      yv = v[V_Y];
-      precond_apply<R>(P, v[V_P], yv, tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
+    if (!prec) {
+      fused_step<R>(m, k, x, v[V_R], v[V_RHAT], v[V_P], v[V_V], v[V_S], v[V_T], s);
+    } else {
+      vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
+      precond_apply<R>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
+      vie::FuseArgs fa{0, 1, nullptr, nullptr, nullptr, v[V_RHAT], nullptr};
+      vie::mvm_fused<R>(m, k, fa, v[V_Y], v[V_V], s);
+      vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
+      precond_apply<R>(P, v[V_S], v[V_Z], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
+      vie::FuseArgs fo{0, 2, nullptr, nullptr, nullptr, nullptr, v[V_S]};
+      vie::mvm_fused<R>(m, k, fo, v[V_Z], v[V_T], s);
+      vie::k_update_xr(k, x, v[V_Y], v[V_Z], v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
     }
-    vie::mvm<R>(m, yv, v[V_V], false, s);
-    vie::k_alpha(k, v[V_RHAT], v[V_V], s);
-    vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
-    c128* zv = v[V_S];
-    if (prec) {
-      zv = v[V_Z];
-      precond_apply<R>(P, v[V_S], zv, tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
-    }
-    vie::mvm<R>(m, zv, v[V_T], false, s);
-    vie::k_omega(k, v[V_T], v[V_S], s);
-    vie::k_update_xr(k, x, yv, zv, v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
     const long t = poll.push(P.ostatus.as<int>());
     if (t - lag >= 0 && poll.wait(t - lag) != vie::ST_ACTIVE) break;
   }
@@ -477,7 +485,7 @@ double true_relres(vie_problem& P, const c128* rhs, const c128* x, c128* tmp_ax,
   MvmBatch<double> m = outer_batch<double>(P, false);
   vie::mvm<double>(m, x, tmp_ax, false, s);
   vie::sub_vec(rhs, tmp_ax, tmp_r, 3 * P.nv, s);
-  vie::norm2(tmp_r, 3 * P.nv, P.partials.as<double>(), P.scal.as<double>(), s);
+  vie::norm2(tmp_r, 3 * P.nv, P.partials.as<double>(), P.counters.as<int>() + 1, P.scal.as<double>(), s);
   double r2 = 0;
   hip_check(hipMemcpyAsync(&r2, P.scal.p, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
   hip_check(hipStreamSynchronize(s), "norm");
@@ -692,7 +700,10 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
     P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
     P->vecs.zero();
     for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
-    P->partials.alloc(vie::krylov_chunks(3 * nv) * 4 * sizeof(double));
+    P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
+    P->partials.alloc(P->pstride * sizeof(double));
+    P->counters.alloc(2 * sizeof(int));   // [0] outer system, [1] norm2
+    P->counters.zero();
     P->ostate.alloc(sizeof(KState));
     P->ostate.zero();
     P->ostatus.alloc(sizeof(int));
@@ -820,10 +831,13 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
         G.vecs.alloc(8 * (size_t)G.nsys * G.n * sizeof(c128));
         G.vecs.zero();
         for (int q = 0; q < 8; ++q) G.vec[q] = G.vecs.as<c128>() + (size_t)q * G.nsys * G.n;
-        G.partials.alloc((size_t)G.nsys * vie::krylov_chunks(G.n) * 4 * sizeof(double));
+        G.pstride = 4 * std::max(vie::krylov_chunks(G.n), vie::mvm_row_tiles(G.lx, G.bz, G.by));
+        G.partials.alloc((size_t)G.nsys * G.pstride * sizeof(double));
+        G.counters.alloc((size_t)G.nsys * sizeof(int));
+        G.counters.zero();
         G.slot0 = slot;
         slot += G.nsys;
-        foot += G.chi.bytes + G.work.bytes + G.vecs.bytes + G.partials.bytes + G.spec->bytes();
+        foot += G.chi.bytes + G.work.bytes + G.vecs.bytes + G.partials.bytes + G.counters.bytes + G.spec->bytes();
         P->groups.push_back(std::move(G));
       }
       P->n_inner = slot;

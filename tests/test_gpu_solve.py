@@ -238,9 +238,9 @@ def test_graph_replays_match_eager_launches(vie_ctx):
             out = torch.empty_like(e)
             st = V.vie_stats()
             for prec in (V.VIE_FP64, V.VIE_MIXED):
-                tol = 1e-9 if prec == V.VIE_FP64 else 1e-6
-                opts = V.make_opts(tol_outer=tol, tol_inner=1e-2, precision=prec, flags=flags)
-                assert V.vie_solve_device(P.handle, e, opts, out, None, st) == V.VIE_OK
+                opts = V.make_opts(tol_outer=1e-9, tol_inner=1e-2, precision=prec, flags=flags, maxit_outer=25,
+                                   max_refine=0)
+                assert V.vie_solve_device(P.handle, e, opts, out, None, st) in (V.VIE_OK, V.VIE_NOT_CONVERGED)
                 torch.cuda.synchronize()
                 outs.append((flags, prec, out.cpu().numpy(), st.outer_iters, st.inner_iters_total))
     finally:
