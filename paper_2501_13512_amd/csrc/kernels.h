@@ -45,6 +45,7 @@ struct MvmBatch {
   cx<R>* work;
   const int* status;       // per system; null = always active
   const TwiddleSet<R>* tw; // host-side pointer table (values are device pointers)
+  int zvariant;            // z-pass kernel variant (0 column sets, 1 mirror columns)
 };
 
 // y = A x for every active system of the batch (Sec. I Toeplitz + FFT;
@@ -55,24 +56,34 @@ template <typename R>
 void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s, hipEvent_t* ev = nullptr);
 
 struct KBatch;
-// Product with BiCGSTAB work fused into its first and last passes.
-//   in_mode 1: the input is p = r + beta (p - omega v) (p = r on the first
-//              step), written back to p;
-//   in_mode 2: the input is s = r - alpha v, written to s, and the
-//              half-step test on ||s|| is made;
-//   out_mode 1: alpha = rho / <rhat, y> from the output y;
-//   out_mode 2: omega = <y, s> / <y, y>.
-// Vectors are batched like x and y (system stride 3 nx ny nz).
+// The product in three launches groups, with BiCGSTAB work fused into its
+// first and last passes.  Pass 1 input (in_mode):
+//   0: x (masked if mask_input);
+//   1: p = r + beta (p - omega v) (p = r on the first step), written to p;
+//   2: s = r - alpha v, written to p (the s vector), partials of ||s||^2.
+// Pass 5 (out_mode), after writing y = A x:
+//   0: nothing; 1: partials of <rhat, y>; 2: partials of <y, s>, <y, y>.
+// In pass 5, x is the product's input (x for in_mode 0, f.p otherwise).
 struct FuseArgs {
   int in_mode, out_mode;
   const c128* r;
-  c128* p;        // in_mode 1: p (updated); in_mode 2: s (written)
+  c128* p;
   const c128* v;
   const c128* rhat;
-  const c128* s;  // out_mode 2
+  const c128* s;
 };
 template <typename R>
-void mvm_fused(const MvmBatch<R>& b, const KBatch& k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s);
+void mvm_pass1(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, bool mask_input,
+               hipStream_t s);
+template <typename R>
+void mvm_mid(const MvmBatch<R>& b, hipStream_t s);   // passes 2-4
+template <typename R>
+void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s);
+
+// Times both z-pass variants on the batch's work buffer (clobbers it) and
+// returns the faster.
+template <typename R>
+int tune_zpass(const MvmBatch<R>& b, hipStream_t s);
 
 // Chunks per system of the fused first/last passes (for partial sizing).
 int64_t mvm_row_tiles(int lx, int nz, int ny);
@@ -107,27 +118,33 @@ struct KBatch {
   int64_t n;
   int* status;
   KState* st;
-  double* partials;   // per system `pstride` doubles (>= 4 * chunks)
+  double* partials;   // per system `pstride` doubles (>= 4 * partial count)
   int64_t pstride;
-  int* counters;      // per system, zero between kernels
+  int* ntile;         // per system: partial count written by the last producer
 };
+
+// Scalar steps applied by k_finalize after a producer wrote partials.
+enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4 };
 
 int64_t krylov_chunks(int64_t n);   // reduction chunks per system (vector kernels)
 
-// x = 0, r = rhat = b, ||b||; status ACTIVE if ||b|| > 0 and the gate (if
-// any) is ACTIVE, CONVERGED (x = 0) if ||b|| = 0, IDLE if gated off.
-void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, double tol, int maxit, const int* gate,
-            hipStream_t s);
+// x = 0, r = rhat = b, partials of ||b||^2 (skipped when the gate is set and
+// not ACTIVE).
+void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, const int* gate, hipStream_t s);
+// One workgroup per system of `k` (one launch for every system of a solve):
+//   FIN_INIT:  ||b||, rho; status ACTIVE, CONVERGED (||b|| = 0) or IDLE (gated)
+//   FIN_ALPHA: alpha = rho / <rhat, v> (counts the step)
+//   FIN_S:     half-step test on ||s||
+//   FIN_OMEGA: omega = <t, s> / <t, t>
+//   FIN_XR:    rho', ||r||, convergence, breakdown, cap, beta; HALF -> CONVERGED
+void k_finalize(const KBatch& k, FinKind kind, hipStream_t s, const int* gate = nullptr, double tol = 0,
+                int maxit = 0);
 // p = r (first step) or p = r + beta (p - omega v)
 void k_update_p(const KBatch& k, const c128* r, const c128* v, c128* p, hipStream_t s);
-// alpha = rho / <rhat, v>
-void k_alpha(const KBatch& k, const c128* rhat, const c128* v, hipStream_t s);
-// s = r - alpha v; half-step convergence test on ||s||
+// s = r - alpha v and partials of ||s||^2 (then FIN_S)
 void k_update_s(const KBatch& k, const c128* r, const c128* v, c128* sv, hipStream_t s);
-// omega = <t, s> / <t, t>
-void k_omega(const KBatch& k, const c128* t, const c128* sv, hipStream_t s);
-// x += alpha y + omega z, r = s - omega t, new rho and ||r||; or, after a
-// half-step convergence, x += alpha y only.
+// x += alpha y + omega z, r = s - omega t, partials of <rhat, r>, ||r||^2
+// (then FIN_XR); after a half-step convergence, x += alpha y only.
 void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv, const c128* t,
                  const c128* rhat, hipStream_t s);
 // After one preconditioner application (skipped when the gate is not
@@ -146,8 +163,8 @@ void sub_vec(const c128* b, const c128* a, c128* r, int64_t n, hipStream_t s);
 // x += d
 void add_vec(c128* x, const c128* d, int64_t n, hipStream_t s);
 // ||v||^2 of one vector into *out (device double), deterministic; partials
-// holds 4 * krylov_chunks(n) doubles, counter one zeroed int
-void norm2(const c128* v, int64_t n, double* partials, int* counter, double* out, hipStream_t s);
+// holds 4 * krylov_chunks(n) doubles
+void norm2(const c128* v, int64_t n, double* partials, double* out, hipStream_t s);
 
 // ------------------------------------------------------------------ blocks
 // Block k of the partition lives in group block_group[k] as system

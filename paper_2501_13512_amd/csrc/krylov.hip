@@ -3,9 +3,12 @@
 // the block-diagonal preconditioner (Sec. II-B, eqs. (10)-(11)).
 //
 // Every reduction is deterministic: each workgroup reduces a fixed chunk of
-// 2048 elements (wavefront shuffles, then LDS) into a partial, and the last
-// workgroup of the system to finish sums the partials in a fixed order and
+// 2048 elements (wavefront shuffles, then LDS) into a partial, and a finalize
+// kernel with one workgroup per system sums the partials in a fixed order and
 // applies the scalar step of the iteration.  No floating-point atomics.
+// Elementwise kernels issue all loads of a thread's elements before their
+// stores, so the loads overlap (the vectors may alias as far as the compiler
+// knows).
 //
 // BiCGSTAB (van der Vorst), right-preconditioned, per system:
 //   rho = <rhat, r>; p = r + beta (p - omega v); y = K^{-1} p; v = A y;
@@ -41,13 +44,10 @@ static void check_launch(const char* what) {
 
 // ---------------------------------------------------------------- init
 __global__ void __launch_bounds__(KT) kk_init(KBatch k, const int* gate, const c128* b, c128* x, c128* r,
-                                              c128* rhat, double tol, int maxit) {
+                                              c128* rhat) {
   const int64_t n = k.n;
   KRYLOV_INDEX
-  if (gate && *gate != ST_ACTIVE) {
-    if (chunk == 0 && threadIdx.x == 0) k.status[sys] = ST_IDLE;
-    return;
-  }
+  if (gate && *gate != ST_ACTIVE) return;
   double acc[1] = {0.0};
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
@@ -60,29 +60,75 @@ __global__ void __launch_bounds__(KT) kk_init(KBatch k, const int* gate, const c
       acc[0] += abs2(v);
     }
   }
-  if (last_block_sum<1>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters)) {
-    KState& st = k.st[sys];
-    const double nb = sqrt(acc[0]);
-    st.nb = nb;
-    st.rho = mk<double>(acc[0], 0.0);
-    st.rho_old = mk<double>(1.0, 0.0);
-    st.alpha = mk<double>(1.0, 0.0);
-    st.omega = mk<double>(1.0, 0.0);
-    st.beta = mk<double>(0.0, 0.0);
-    st.rnorm = nb > 0.0 ? 1.0 : 0.0;
-    st.snorm = st.rnorm;
-    st.tol = tol;
-    st.iters = 0;
-    st.maxit = maxit;
-    k.status[sys] = nb > 0.0 ? ST_ACTIVE : ST_CONVERGED;
+  write_partial<1>(acc, k.partials, k.pstride, k.ntile, sys, chunk, chunks);
+}
+
+void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, const int* gate, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_init, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, gate, b, x, r, rhat);
+  check_launch("krylov init");
+}
+
+// ---------------------------------------------------------------- finalize
+__global__ void __launch_bounds__(KT) kk_finalize(KBatch k, int kind, const int* gate, double tol, int maxit) {
+  const int sys = blockIdx.x;
+  const int stt = k.status[sys];
+  KState& st = k.st[sys];
+  if (kind == FIN_INIT) {
+    if (gate && *gate != ST_ACTIVE) {
+      if (threadIdx.x == 0) k.status[sys] = ST_IDLE;
+      return;
+    }
+    double v[1];
+    final_sum<1>(k.partials, k.pstride, k.ntile, sys, v);
+    if (threadIdx.x == 0) {
+      const double nb = sqrt(v[0]);
+      st.nb = nb;
+      st.rho = mk<double>(v[0], 0.0);
+      st.rho_old = mk<double>(1.0, 0.0);
+      st.alpha = mk<double>(1.0, 0.0);
+      st.omega = mk<double>(1.0, 0.0);
+      st.beta = mk<double>(0.0, 0.0);
+      st.rnorm = nb > 0.0 ? 1.0 : 0.0;
+      st.snorm = st.rnorm;
+      st.tol = tol;
+      st.iters = 0;
+      st.maxit = maxit;
+      k.status[sys] = nb > 0.0 ? ST_ACTIVE : ST_CONVERGED;
+    }
+    return;
+  }
+  if (kind == FIN_XR && stt == ST_HALF) {
+    if (threadIdx.x == 0) {
+      st.rnorm = st.snorm;
+      k.status[sys] = ST_CONVERGED;
+    }
+    return;
+  }
+  if (stt != ST_ACTIVE) return;
+  if (kind == FIN_ALPHA) {
+    double v[2];
+    final_sum<2>(k.partials, k.pstride, k.ntile, sys, v);
+    if (threadIdx.x == 0) fin_alpha(st, &k.status[sys], v);
+  } else if (kind == FIN_S) {
+    double v[1];
+    final_sum<1>(k.partials, k.pstride, k.ntile, sys, v);
+    if (threadIdx.x == 0) fin_s(st, &k.status[sys], v[0]);
+  } else if (kind == FIN_OMEGA) {
+    double v[3];
+    final_sum<3>(k.partials, k.pstride, k.ntile, sys, v);
+    if (threadIdx.x == 0) fin_omega(st, &k.status[sys], v);
+  } else {
+    double v[3];
+    final_sum<3>(k.partials, k.pstride, k.ntile, sys, v);
+    if (threadIdx.x == 0) fin_xr(st, &k.status[sys], v);
   }
 }
 
-void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, double tol, int maxit, const int* gate,
-            hipStream_t s) {
-  const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_init, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, gate, b, x, r, rhat, tol, maxit);
-  check_launch("krylov init");
+void k_finalize(const KBatch& k, FinKind kind, hipStream_t s, const int* gate, double tol, int maxit) {
+  if (k.nsys <= 0) return;
+  hipLaunchKernelGGL(kk_finalize, dim3(k.nsys), dim3(KT), 0, s, k, (int)kind, gate, tol, maxit);
+  check_launch("krylov finalize");
 }
 
 // ---------------------------------------------------------------- p update
@@ -94,13 +140,22 @@ __global__ void __launch_bounds__(KT) kk_update_p(KBatch k, const c128* r, const
   const KState& st = k.st[sys];
   const bool first = st.iters == 0;
   const c128 beta = st.beta, omega = st.omega;
+  c128 rv[KEPT], pv[KEPT], vv[KEPT];
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
     const int64_t i = i0 + (int64_t)j * KT;
     if (i < n) {
-      const c128 rv = r[base + i];
-      p[base + i] = first ? rv : rv + beta * (p[base + i] - omega * v[base + i]);
+      rv[j] = r[base + i];
+      if (!first) {
+        pv[j] = p[base + i];
+        vv[j] = v[base + i];
+      }
     }
+  }
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) p[base + i] = first ? rv[j] : rv[j] + beta * (pv[j] - omega * vv[j]);
   }
 }
 
@@ -110,31 +165,6 @@ void k_update_p(const KBatch& k, const c128* r, const c128* v, c128* p, hipStrea
   check_launch("krylov p");
 }
 
-// ---------------------------------------------------------------- alpha
-__global__ void __launch_bounds__(KT) kk_alpha(KBatch k, const c128* rhat, const c128* v) {
-  const int64_t n = k.n;
-  KRYLOV_INDEX
-  if (k.status[sys] != ST_ACTIVE) return;
-  double acc[2] = {0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < KEPT; ++j) {
-    const int64_t i = i0 + (int64_t)j * KT;
-    if (i < n) {
-      const c128 d = cdot1(rhat[base + i], v[base + i]);
-      acc[0] += d.x;
-      acc[1] += d.y;
-    }
-  }
-  if (last_block_sum<2>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
-    fin_alpha(k.st[sys], &k.status[sys], acc);
-}
-
-void k_alpha(const KBatch& k, const c128* rhat, const c128* v, hipStream_t s) {
-  const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_alpha, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, rhat, v);
-  check_launch("krylov alpha");
-}
-
 // ---------------------------------------------------------------- s update
 __global__ void __launch_bounds__(KT) kk_update_s(KBatch k, const c128* r, const c128* v, c128* sv) {
   const int64_t n = k.n;
@@ -142,50 +172,31 @@ __global__ void __launch_bounds__(KT) kk_update_s(KBatch k, const c128* r, const
   if (k.status[sys] != ST_ACTIVE) return;
   const c128 alpha = k.st[sys].alpha;
   double acc[1] = {0.0};
+  c128 rv[KEPT], vv[KEPT];
 #pragma unroll
   for (int j = 0; j < KEPT; ++j) {
     const int64_t i = i0 + (int64_t)j * KT;
     if (i < n) {
-      const c128 sval = r[base + i] - alpha * v[base + i];
+      rv[j] = r[base + i];
+      vv[j] = v[base + i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 sval = rv[j] - alpha * vv[j];
       sv[base + i] = sval;
       acc[0] += abs2(sval);
     }
   }
-  if (last_block_sum<1>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
-    fin_s(k.st[sys], &k.status[sys], acc[0]);
+  write_partial<1>(acc, k.partials, k.pstride, k.ntile, sys, chunk, chunks);
 }
 
 void k_update_s(const KBatch& k, const c128* r, const c128* v, c128* sv, hipStream_t s) {
   const int64_t chunks = chunks_of(k.n);
   hipLaunchKernelGGL(kk_update_s, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, r, v, sv);
   check_launch("krylov s");
-}
-
-// ---------------------------------------------------------------- omega
-__global__ void __launch_bounds__(KT) kk_omega(KBatch k, const c128* t, const c128* sv) {
-  const int64_t n = k.n;
-  KRYLOV_INDEX
-  if (k.status[sys] != ST_ACTIVE) return;
-  double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < KEPT; ++j) {
-    const int64_t i = i0 + (int64_t)j * KT;
-    if (i < n) {
-      const c128 tv = t[base + i];
-      const c128 d = cdot1(tv, sv[base + i]);
-      acc[0] += d.x;
-      acc[1] += d.y;
-      acc[2] += abs2(tv);
-    }
-  }
-  if (last_block_sum<3>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
-    fin_omega(k.st[sys], &k.status[sys], acc);
-}
-
-void k_omega(const KBatch& k, const c128* t, const c128* sv, hipStream_t s) {
-  const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_omega, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, t, sv);
-  check_launch("krylov omega");
 }
 
 // ---------------------------------------------------------------- x, r update
@@ -196,36 +207,57 @@ __global__ void __launch_bounds__(KT) kk_update_xr(KBatch k, c128* x, const c128
   const int stt = k.status[sys];
   if (stt == ST_HALF) {
     const c128 alpha = k.st[sys].alpha;
+    c128 xv[KEPT], yv[KEPT];
 #pragma unroll
     for (int j = 0; j < KEPT; ++j) {
       const int64_t i = i0 + (int64_t)j * KT;
-      if (i < n) x[base + i] = x[base + i] + alpha * y[base + i];
+      if (i < n) {
+        xv[j] = x[base + i];
+        yv[j] = y[base + i];
+      }
     }
-    double acc[1] = {0.0};
-    if (last_block_sum<1>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters)) {
-      k.st[sys].rnorm = k.st[sys].snorm;
-      k.status[sys] = ST_CONVERGED;
+#pragma unroll
+    for (int j = 0; j < KEPT; ++j) {
+      const int64_t i = i0 + (int64_t)j * KT;
+      if (i < n) x[base + i] = xv[j] + alpha * yv[j];
     }
     return;
   }
   if (stt != ST_ACTIVE) return;
   const c128 alpha = k.st[sys].alpha, omega = k.st[sys].omega;
   double acc[3] = {0.0, 0.0, 0.0};
+  // two halves of KEPT/2 elements: all loads of a half before its stores
 #pragma unroll
-  for (int j = 0; j < KEPT; ++j) {
-    const int64_t i = i0 + (int64_t)j * KT;
-    if (i < n) {
-      x[base + i] = x[base + i] + alpha * y[base + i] + omega * z[base + i];
-      const c128 rv = sv[base + i] - omega * t[base + i];
-      r[base + i] = rv;
-      const c128 d = cdot1(rhat[base + i], rv);
-      acc[0] += d.x;
-      acc[1] += d.y;
-      acc[2] += abs2(rv);
+  for (int h = 0; h < 2; ++h) {
+    constexpr int HE = KEPT / 2;
+    c128 xv[HE], yv[HE], zv[HE], sw[HE], tv[HE], hv[HE];
+#pragma unroll
+    for (int j = 0; j < HE; ++j) {
+      const int64_t i = i0 + (int64_t)(h * HE + j) * KT;
+      if (i < n) {
+        xv[j] = x[base + i];
+        yv[j] = y[base + i];
+        zv[j] = z[base + i];
+        sw[j] = sv[base + i];
+        tv[j] = t[base + i];
+        hv[j] = rhat[base + i];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < HE; ++j) {
+      const int64_t i = i0 + (int64_t)(h * HE + j) * KT;
+      if (i < n) {
+        x[base + i] = xv[j] + alpha * yv[j] + omega * zv[j];
+        const c128 rv = sw[j] - omega * tv[j];
+        r[base + i] = rv;
+        const c128 d = cdot1(hv[j], rv);
+        acc[0] += d.x;
+        acc[1] += d.y;
+        acc[2] += abs2(rv);
+      }
     }
   }
-  if (last_block_sum<3>(acc, k.partials, k.pstride, sys, chunk, chunks, k.counters))
-    fin_xr(k.st[sys], &k.status[sys], acc);
+  write_partial<3>(acc, k.partials, k.pstride, k.ntile, sys, chunk, chunks);
 }
 
 void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv, const c128* t,
@@ -316,9 +348,8 @@ void add_vec(c128* x, const c128* d, int64_t n, hipStream_t s) {
   check_launch("add");
 }
 
-// ||v||^2 of one vector; partials [chunks * NPART], counter one int
-__global__ void __launch_bounds__(KT) kk_norm2(int64_t n, const c128* v, double* partials, int* counter,
-                                               double* out) {
+// ||v||^2 of one vector: partials, then one workgroup sums them in order
+__global__ void __launch_bounds__(KT) kk_norm2(int64_t n, const c128* v, double* partials) {
   KRYLOV_INDEX
   double acc[1] = {0.0};
 #pragma unroll
@@ -326,12 +357,22 @@ __global__ void __launch_bounds__(KT) kk_norm2(int64_t n, const c128* v, double*
     const int64_t i = i0 + (int64_t)j * KT;
     if (i < n) acc[0] += abs2(v[base + i]);
   }
-  if (last_block_sum<1>(acc, partials, 0, sys, chunk, chunks, counter)) *out = acc[0];
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) partials[chunk * NPART] = acc[0];
 }
 
-void norm2(const c128* v, int64_t n, double* partials, int* counter, double* out, hipStream_t s) {
+__global__ void __launch_bounds__(KT) kk_norm2_fin(int64_t n, const double* partials, double* out) {
   const int64_t chunks = chunks_of(n);
-  hipLaunchKernelGGL(kk_norm2, dim3((unsigned)chunks), dim3(KT), 0, s, n, v, partials, counter, out);
+  double v[1] = {0.0};
+  for (int64_t c = threadIdx.x; c < chunks; c += KT) v[0] += partials[c * NPART];
+  block_sum<1>(v);
+  if (threadIdx.x == 0) *out = v[0];
+}
+
+void norm2(const c128* v, int64_t n, double* partials, double* out, hipStream_t s) {
+  const int64_t chunks = chunks_of(n);
+  hipLaunchKernelGGL(kk_norm2, dim3((unsigned)chunks), dim3(KT), 0, s, n, v, partials);
+  hipLaunchKernelGGL(kk_norm2_fin, dim3(1), dim3(KT), 0, s, n, partials, out);
   check_launch("norm2");
 }
 

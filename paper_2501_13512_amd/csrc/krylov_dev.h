@@ -1,10 +1,10 @@
 // Device-side pieces of the BiCGSTAB step shared by the vector kernels and
 // by the FFT passes that fuse vector updates and inner products.
 //
-// Reductions: every workgroup of a system writes its partial sum, then takes
-// a ticket from the system's counter; the workgroup holding the last ticket
-// sums all partials in a fixed order (deterministic, no float atomics),
-// applies the scalar step of the iteration and resets the counter.
+// Reductions: every workgroup of a system writes its partial sum; a finalize
+// kernel (one workgroup per system, all systems of a solve in one launch)
+// sums the partials in a fixed order (deterministic, no atomics or
+// device-scope fences) and applies the scalar step of the iteration.
 #pragma once
 #include "kernels.h"
 
@@ -42,40 +42,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
   }
 }
 
-// Workgroup `tile` of `ntiles` of system `sys` contributes v.  Returns true in
-// thread 0 of the last workgroup to arrive, with the system total in v.
+// Workgroup `tile` of `ntiles` of system `sys` writes its partial sum (plain
+// stores; the finalize kernel that reads them runs after this kernel ends).
+// Tile 0 also records how many partials the system has.
 template <int NV>
-__device__ __forceinline__ bool last_block_sum(double (&v)[NV], double* partials, int64_t pstride, int sys,
-                                               int64_t tile, int64_t ntiles, int* counters) {
-  __shared__ int is_last;
+__device__ __forceinline__ void write_partial(double (&v)[NV], double* partials, int64_t pstride, int* ntile,
+                                              int sys, int64_t tile, int64_t ntiles) {
   block_sum<NV>(v);
   if (threadIdx.x == 0) {
     double* p = partials + sys * pstride + tile * NPART;
 #pragma unroll
     for (int k = 0; k < NV; ++k) p[k] = v[k];
-    __threadfence();
-    const int prev = atomicAdd(&counters[sys], 1);
-    is_last = (prev == (int)ntiles - 1) ? 1 : 0;
+    if (tile == 0) ntile[sys] = (int)ntiles;
   }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  double w[NV];
+}
+
+// Sum of system `sys`'s partials in a fixed order; valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void final_sum(const double* partials, int64_t pstride, const int* ntile, int sys,
+                                          double (&v)[NV]) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) w[k] = 0.0;
-  for (int64_t c = threadIdx.x; c < ntiles; c += blockDim.x) {
-    const double* p = partials + sys * pstride + c * NPART;
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  const int nt = ntile[sys];
+  for (int c = threadIdx.x; c < nt; c += blockDim.x) {
+    const double* p = partials + sys * pstride + (int64_t)c * NPART;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) w[k] += p[k];
+    for (int k = 0; k < NV; ++k) v[k] += p[k];
   }
-  block_sum<NV>(w);
-  if (threadIdx.x == 0) {
-    counters[sys] = 0;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = w[k];
-    return true;
-  }
-  return false;
+  block_sum<NV>(v);
 }
 
 __device__ __forceinline__ c128 cdiv(c128 a, c128 b) {

@@ -83,123 +83,169 @@ struct RowArgs {
   KBatch k;
 };
 
-// Pass 1: x forward with zero padding nx -> lx, c128 -> R.
+// Pass 1: x forward with zero padding nx -> lx, c128 -> R.  With a fused
+// BiCGSTAB update (in_mode 1: p, in_mode 2: s) the new vector is formed in a
+// pre-pass that issues all loads of a chunk of elements before storing it to
+// HBM and to the pencil's LDS slot; the transform then starts from LDS.
 template <typename R, int L>
 __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_fwd(RowArgs<R> a) {
   using G = Geo<R, L>;
+  constexpr int T = G::T;
   __shared__ cx<R> lds[G::ROWP * L];
   const int rows = 3 * a.nz * a.ny;
   const int tiles = (rows + G::ROWP - 1) / G::ROWP;
   const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
   if (!sys_active(a.status, sys)) return;
-  const int p = threadIdx.x / G::T, t = threadIdx.x - p * G::T;
+  const int p = threadIdx.x / T, t = threadIdx.x - p * T;
   const int row = tile * G::ROWP + p;
   const bool valid = row < rows;
   const int rr = valid ? row : 0;
   const int c = rr / (a.nz * a.ny), zy = rr - c * (a.nz * a.ny);
   const int z = zy / a.ny, yy = zy - z * a.ny;
   const int64_t vrow = sys * a.vstride + (int64_t)rr * a.nx;
-  const c128* xin = a.x + vrow;
-  const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
   cx<R>* w = a.work + sys * a.wstride + ((int64_t)(c * a.nz + z) * a.ly + yy) * a.lx;
+  cx<R>* slot = lds + p * L;
   const int nx = a.nx;
-  const bool msk = a.mask_input != 0;
   const int mode = a.in_mode;
-  c128 c1 = mk<double>(0.0, 0.0), c2 = c1;
-  bool first = false;
-  if (mode == 1) {
-    first = a.k.st[sys].iters == 0;
-    c1 = a.k.st[sys].beta;
-    c2 = a.k.st[sys].omega;
-  } else if (mode == 2) {
-    c1 = a.k.st[sys].alpha;
-  }
-  double acc = 0.0;
-  auto ld = [&](int n) -> cx<R> {
-    if (n < nx) {
-      c128 v;
-      if (mode == 1) {          // p = r + beta (p - omega v), or r on the first step
-        const c128 rv = a.r[vrow + n];
-        v = first ? rv : rv + c1 * (a.p[vrow + n] - c2 * a.v[vrow + n]);
-        a.p[vrow + n] = v;
-      } else if (mode == 2) {   // s = r - alpha v
-        v = a.r[vrow + n] - c1 * a.v[vrow + n];
-        a.p[vrow + n] = v;
-        acc += abs2(v);
-      } else {
-        v = xin[n];
+  auto st = [&](int k, cx<R> v) { w[k] = v; };
+  if (mode == 0) {
+    const c128* xin = a.x + vrow;
+    const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
+    const bool msk = a.mask_input != 0;
+    auto ld = [&](int n) -> cx<R> {
+      if (n < nx) {
+        c128 v = xin[n];
         if (msk) {
           c128 ci = chi[n];
           if (ci.x == 0.0 && ci.y == 0.0) v = mk<double>(0.0, 0.0);
         }
+        return cvt<R>(v);
       }
-      return cvt<R>(v);
+      return czero<R>();
+    };
+    fft_pencil<R, L, T, -1>(ld, st, slot, 1, t, valid, a.tw);
+    return;
+  }
+  const KState& ks = a.k.st[sys];
+  const bool first = mode == 1 && ks.iters == 0;
+  const c128 c1 = mode == 1 ? ks.beta : ks.alpha;
+  const c128 c2 = ks.omega;
+  double acc = 0.0;
+  constexpr int E = (L + T - 1) / T;   // elements per thread
+  constexpr int CH = 4;                // elements per load batch
+#pragma unroll
+  for (int j0 = 0; j0 < E; j0 += CH) {
+    c128 rv[CH], pv[CH], vv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int n = t + (j0 + u) * T;
+      if (valid && j0 + u < E && n < nx) {
+        rv[u] = a.r[vrow + n];
+        if (!first) vv[u] = a.v[vrow + n];
+        if (mode == 1 && !first) pv[u] = a.p[vrow + n];
+      }
     }
-    return czero<R>();
-  };
-  auto st = [&](int k, cx<R> v) { w[k] = v; };
-  fft_pencil<R, L, G::T, -1>(ld, st, lds + p * L, 1, t, valid, a.tw);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int n = t + (j0 + u) * T;
+      if (valid && j0 + u < E && n < L) {
+        if (n < nx) {
+          c128 val;
+          if (mode == 1)
+            val = first ? rv[u] : rv[u] + c1 * (pv[u] - c2 * vv[u]);   // p = r + beta (p - omega v)
+          else
+            val = rv[u] - c1 * vv[u];                                    // s = r - alpha v
+          a.p[vrow + n] = val;
+          slot[n] = cvt<R>(val);
+          acc += abs2(val);
+        } else {
+          slot[n] = czero<R>();
+        }
+      }
+    }
+  }
+  __syncthreads();
+  auto ld = [&](int n) -> cx<R> { return slot[n]; };
+  fft_pencil<R, L, T, -1, true, false>(ld, st, slot, 1, t, valid, a.tw);
   if (mode == 2) {
     double sum[1] = {acc};
-    if (last_block_sum<1>(sum, a.k.partials, a.k.pstride, sys, tile, tiles, a.k.counters))
-      fin_s(a.k.st[sys], &a.k.status[sys], sum[0]);
+    write_partial<1>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
   }
 }
 
-// Pass 5: x inverse, crop lx -> nx, y = x/chi - scale * Q on the mask, 0 off it.
+// Pass 5: x inverse, crop lx -> nx, y = x/chi - scale * Q on the mask, 0 off
+// it.  The cropped transform lands in LDS; a post-pass issues the loads of
+// 1/chi, x and (fused inner products) rhat or s for a chunk of elements
+// before storing y.
 template <typename R, int L>
 __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_local(RowArgs<R> a) {
   using G = Geo<R, L>;
+  constexpr int T = G::T;
   __shared__ cx<R> lds[G::ROWP * L];
   const int rows = 3 * a.nz * a.ny;
   const int tiles = (rows + G::ROWP - 1) / G::ROWP;
   const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
   if (!sys_active(a.status, sys)) return;
-  const int p = threadIdx.x / G::T, t = threadIdx.x - p * G::T;
+  const int p = threadIdx.x / T, t = threadIdx.x - p * T;
   const int row = tile * G::ROWP + p;
   const bool valid = row < rows;
   const int rr = valid ? row : 0;
   const int c = rr / (a.nz * a.ny), zy = rr - c * (a.nz * a.ny);
   const int z = zy / a.ny, yy = zy - z * a.ny;
   const int64_t vrow = sys * a.vstride + (int64_t)rr * a.nx;
-  const c128* xin = a.x + vrow;
-  c128* yout = a.y + vrow;
   const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
   const cx<R>* w = a.work + sys * a.wstride + ((int64_t)(c * a.nz + z) * a.ly + yy) * a.lx;
+  cx<R>* slot = lds + p * L;
   const int nx = a.nx;
+  auto ld = [&](int n) -> cx<R> { return w[n]; };
+  auto sts = [&](int k, cx<R> v) {
+    if (k < nx) slot[k] = v;
+  };
+  fft_pencil<R, L, T, +1, false, true>(ld, sts, slot, 1, t, valid, a.tw);
+
   const double scale = a.scale;
   const int mode = a.out_mode;
   double acc[3] = {0.0, 0.0, 0.0};
-  auto ld = [&](int n) -> cx<R> { return w[n]; };
-  auto st = [&](int k, cx<R> v) {
-    if (k < nx) {
-      c128 ci = chi[k];
-      c128 out = mk<double>(0.0, 0.0);
-      if (ci.x != 0.0 || ci.y != 0.0) {
-        c128 q = cvt<double>(v);
-        out = xin[k] * ci - scale * q;
-      }
-      yout[k] = out;
-      if (mode == 1) {          // <rhat, y>
-        const c128 d = cdot1(a.rhat[vrow + k], out);
-        acc[0] += d.x;
-        acc[1] += d.y;
-      } else if (mode == 2) {   // <y, s>, <y, y>
-        const c128 d = cdot1(out, a.s[vrow + k]);
-        acc[0] += d.x;
-        acc[1] += d.y;
-        acc[2] += abs2(out);
+  constexpr int E = (L + T - 1) / T;
+  constexpr int CH = 4;
+#pragma unroll
+  for (int j0 = 0; j0 < E; j0 += CH) {
+    c128 ci[CH], xv[CH], ov[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int k = t + (j0 + u) * T;
+      if (valid && j0 + u < E && k < nx) {
+        ci[u] = chi[k];
+        xv[u] = a.x[vrow + k];
+        if (mode == 1) ov[u] = a.rhat[vrow + k];
+        if (mode == 2) ov[u] = a.s[vrow + k];
       }
     }
-  };
-  fft_pencil<R, L, G::T, +1>(ld, st, lds + p * L, 1, t, valid, a.tw);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int k = t + (j0 + u) * T;
+      if (valid && j0 + u < E && k < nx) {
+        c128 out = mk<double>(0.0, 0.0);
+        if (ci[u].x != 0.0 || ci[u].y != 0.0) out = xv[u] * ci[u] - scale * cvt<double>(slot[k]);
+        a.y[vrow + k] = out;
+        if (mode == 1) {          // <rhat, y>
+          const c128 d = cdot1(ov[u], out);
+          acc[0] += d.x;
+          acc[1] += d.y;
+        } else if (mode == 2) {   // <y, s>, <y, y>
+          const c128 d = cdot1(out, ov[u]);
+          acc[0] += d.x;
+          acc[1] += d.y;
+          acc[2] += abs2(out);
+        }
+      }
+    }
+  }
   if (mode == 1) {
     double sum[2] = {acc[0], acc[1]};
-    if (last_block_sum<2>(sum, a.k.partials, a.k.pstride, sys, tile, tiles, a.k.counters))
-      fin_alpha(a.k.st[sys], &a.k.status[sys], sum);
+    write_partial<2>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
   } else if (mode == 2) {
-    if (last_block_sum<3>(acc, a.k.partials, a.k.pstride, sys, tile, tiles, a.k.counters))
-      fin_omega(a.k.st[sys], &a.k.status[sys], acc);
+    write_partial<3>(acc, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
   }
 }
 
@@ -280,6 +326,16 @@ __device__ __forceinline__ FoldCol fold_col(int f, int m, int L) {
   return {-1, 0, 1};
 }
 
+// Variant 0: one (qy, tile of qx) column set per workgroup, three
+// components side by side; each point loads its spectrum values.
+template <typename R, int LZ>
+struct ZColGeo {
+  static constexpr int T = PlanInfo<LZ>::max_butterflies;
+  static constexpr int ES = (int)sizeof(cx<R>);
+  static constexpr int ZP = cmax(1, pow2_floor(cmin(64, cmin(1024 / (3 * T), (144 * 1024) / (3 * LZ * ES)))));
+};
+
+// Variant 1 (mirror columns): geometry.
 template <typename R, int LZ>
 struct ZGeo {
   static constexpr int T = PlanInfo<LZ>::max_butterflies;
@@ -290,6 +346,7 @@ struct ZGeo {
 template <typename R>
 struct ZArgs {
   int nz, ly, lx;
+  int variant;   // 0: column sets, 1: mirror columns
   int64_t wstride, sstride;
   cx<R>* work;
   const cx<R>* spec;
@@ -298,7 +355,7 @@ struct ZArgs {
 };
 
 template <typename R, int LZ>
-__global__ void __launch_bounds__((3 * ZGeo<R, LZ>::T * ZGeo<R, LZ>::ZP)) k_zconv(ZArgs<R> a) {
+__global__ void __launch_bounds__((3 * ZGeo<R, LZ>::T * ZGeo<R, LZ>::ZP)) k_zconv_mirror(ZArgs<R> a) {
   using G = ZGeo<R, LZ>;
   constexpr int T = G::T, ZP = G::ZP;
   constexpr int SLOT = LZ * ZP;           // one (mirror, component) pencil set
@@ -388,6 +445,62 @@ __global__ void __launch_bounds__((3 * ZGeo<R, LZ>::T * ZGeo<R, LZ>::ZP)) k_zcon
   }
 }
 
+template <typename R, int LZ>
+__global__ void __launch_bounds__((3 * ZColGeo<R, LZ>::T * ZColGeo<R, LZ>::ZP)) k_zconv_col(ZArgs<R> a) {
+  using G = ZColGeo<R, LZ>;
+  constexpr int T = G::T, ZP = G::ZP;
+  __shared__ cx<R> lds[3 * LZ * ZP];
+  const int cols = a.ly * a.lx;
+  const int tiles = (cols + ZP - 1) / ZP;
+  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  if (!sys_active(a.status, sys)) return;
+  const int comp = threadIdx.x / (T * ZP);
+  const int rem = threadIdx.x - comp * (T * ZP);
+  const int p = rem % ZP, t = rem / ZP;
+  const int col = tile * ZP + p;
+  const bool valid = col < cols;
+  const int64_t plane = (int64_t)a.ly * a.lx;
+  cx<R>* base = a.work + sys * a.wstride + (int64_t)comp * a.nz * plane + (valid ? col : 0);
+  cx<R>* slot = lds + comp * LZ * ZP + p;
+  const int nz = a.nz;
+  // forward along z into the component's LDS slot
+  auto ldg = [&](int n) -> cx<R> { return n < nz ? base[n * plane] : czero<R>(); };
+  auto sts = [&](int k, cx<R> v) { slot[k * ZP] = v; };
+  fft_pencil<R, LZ, T, -1, false, true>(ldg, sts, slot, ZP, t, valid, a.tw);
+
+  // Q(q) = S(q) X(q), S symmetric 3x3 from the octant with parity signs
+  const int lx = a.lx, ly = a.ly;
+  const int hx = lx / 2, hy = ly / 2, hz = LZ / 2;
+  const int64_t ox = hx + 1, oy = hy + 1;
+  const int64_t oct = ox * oy * (hz + 1);
+  const cx<R>* spec = a.spec + sys * a.sstride;
+  for (int i = threadIdx.x; i < LZ * ZP; i += 3 * T * ZP) {
+    const int qz = i / ZP, pp = i - qz * ZP;
+    const int c2 = tile * ZP + pp;
+    if (c2 >= cols) continue;
+    const int qy = c2 / lx, qx = c2 - qy * lx;
+    const int fx = qx <= hx ? qx : lx - qx, fy = qy <= hy ? qy : ly - qy, fz = qz <= hz ? qz : LZ - qz;
+    const R sx = qx <= hx ? R(1) : R(-1), sy = qy <= hy ? R(1) : R(-1), sz = qz <= hz ? R(1) : R(-1);
+    const int64_t o = ((int64_t)fz * oy + fy) * ox + fx;
+    const cx<R> sxx = spec[o], syy = spec[3 * oct + o], szz = spec[5 * oct + o];
+    const cx<R> sxy = (sx * sy) * spec[oct + o];
+    const cx<R> sxz = (sx * sz) * spec[2 * oct + o];
+    const cx<R> syz = (sy * sz) * spec[4 * oct + o];
+    const int e = qz * ZP + pp;
+    const cx<R> X = lds[e], Y = lds[LZ * ZP + e], Z = lds[2 * LZ * ZP + e];
+    lds[e] = sxx * X + sxy * Y + sxz * Z;
+    lds[LZ * ZP + e] = sxy * X + syy * Y + syz * Z;
+    lds[2 * LZ * ZP + e] = sxz * X + syz * Y + szz * Z;
+  }
+  __syncthreads();
+  // inverse along z, cropped to nz
+  auto lds_ld = [&](int n) -> cx<R> { return slot[n * ZP]; };
+  auto stg = [&](int k, cx<R> v) {
+    if (k < nz) base[k * plane] = v;
+  };
+  fft_pencil<R, LZ, T, +1, true, false>(lds_ld, stg, slot, ZP, t, valid, a.tw);
+}
+
 // ------------------------------------------------------------------ launchers
 #define VIE_L_CASES(F) \
   F(1) F(2) F(3) F(4) F(6) F(8) F(12) F(16) F(24) F(32) F(48) F(64) F(96) F(128) F(192) F(256) F(384) F(512)
@@ -458,14 +571,20 @@ static void launch_col(int L, const ColArgs<R>& a, hipStream_t s) {
 
 template <typename R>
 static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
-  const int per_sys_y = nfold(a.ly), nfx = nfold(a.lx);
+  const int nfy = nfold(a.ly), nfx = nfold(a.lx), cols = a.ly * a.lx;
   switch (L) {
-#define C(l)                                                                              \
-  case l: {                                                                               \
-    using G = ZGeo<R, l>;                                                                 \
-    const int blocks = per_sys_y * ((nfx + G::ZP - 1) / G::ZP) * nsys;                    \
-    hipLaunchKernelGGL((k_zconv<R, l>), dim3(blocks), dim3(3 * G::T * G::ZP), 0, s, a);   \
-    break;                                                                                \
+#define C(l)                                                                                      \
+  case l: {                                                                                       \
+    if (a.variant == 1) {                                                                         \
+      using G = ZGeo<R, l>;                                                                       \
+      const int blocks = nfy * ((nfx + G::ZP - 1) / G::ZP) * nsys;                                \
+      hipLaunchKernelGGL((k_zconv_mirror<R, l>), dim3(blocks), dim3(3 * G::T * G::ZP), 0, s, a);  \
+    } else {                                                                                      \
+      using G = ZColGeo<R, l>;                                                                    \
+      const int blocks = ((cols + G::ZP - 1) / G::ZP) * nsys;                                     \
+      hipLaunchKernelGGL((k_zconv_col<R, l>), dim3(blocks), dim3(3 * G::T * G::ZP), 0, s, a);     \
+    }                                                                                             \
+    break;                                                                                        \
   }
     VIE_L_CASES(C)
 #undef C
@@ -480,9 +599,8 @@ static void mark(hipEvent_t* ev, int i, hipStream_t s) {
 }
 
 template <typename R>
-void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s, hipEvent_t* ev) {
-  if (b.nsys <= 0) return;
-  mark(ev, 0, s);
+static RowArgs<R> row_args(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, c128* y,
+                           bool mask_input) {
   RowArgs<R> ra{};
   ra.nx = b.nx;
   ra.ny = b.ny;
@@ -500,83 +618,30 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
   ra.tw = b.tw->table[b.lx];
   ra.mask_input = mask_input ? 1 : 0;
   ra.scale = 1.0 / ((double)b.lx * (double)b.ly * (double)b.lz);
-  launch_row_fwd<R>(b.lx, ra, b.nsys, s);
-  mark(ev, 1, s);
-
-  ColArgs<R> ca{};
-  ca.data = b.work;
-  ca.outer = 3 * b.nz;
-  ca.inner = b.lx;
-  ca.n_in = b.ny;
-  ca.n_out = b.ly;
-  ca.stride = b.wstride;
-  ca.status = b.status;
-  ca.tw = b.tw->table[b.ly];
-  ca.nsys = b.nsys;
-  launch_col<R, -1>(b.ly, ca, s);
-  mark(ev, 2, s);
-
-  ZArgs<R> za{};
-  za.nz = b.nz;
-  za.ly = b.ly;
-  za.lx = b.lx;
-  za.wstride = b.wstride;
-  za.sstride = b.sstride;
-  za.work = b.work;
-  za.spec = b.spec;
-  za.status = b.status;
-  za.tw = b.tw->table[b.lz];
-  launch_zconv<R>(b.lz, za, b.nsys, s);
-  mark(ev, 3, s);
-
-  ca.n_in = b.ly;
-  ca.n_out = b.ny;
-  launch_col<R, +1>(b.ly, ca, s);
-  mark(ev, 4, s);
-
-  launch_row_inv<R>(b.lx, ra, b.nsys, s);
-  mark(ev, 5, s);
-}
-
-template void mvm<float>(const MvmBatch<float>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);
-template void mvm<double>(const MvmBatch<double>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);
-
-template <typename R>
-void mvm_fused(const MvmBatch<R>& b, const KBatch& k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s) {
-  if (b.nsys <= 0) return;
-  // The product's input: x, or the vector pass 1 computes and writes to f.p
-  // (the local term of pass 5 reads it).
-  const c128* xin = f.in_mode != 0 ? f.p : x;
-  if (!xin || !y || (f.in_mode != 0 && (!f.r || !f.v)) || (f.out_mode == 1 && !f.rhat) ||
-      (f.out_mode == 2 && !f.s))
-    throw std::runtime_error("mvm_fused: missing vector");
-  RowArgs<R> ra{};
-  ra.nx = b.nx;
-  ra.ny = b.ny;
-  ra.nz = b.nz;
-  ra.lx = b.lx;
-  ra.ly = b.ly;
-  ra.vstride = b.vstride;
-  ra.cstride = b.cstride;
-  ra.wstride = b.wstride;
-  ra.x = xin;
-  ra.y = y;
-  ra.chi_inv = b.chi_inv;
-  ra.work = b.work;
-  ra.status = b.status;
-  ra.tw = b.tw->table[b.lx];
-  ra.mask_input = 0;
-  ra.scale = 1.0 / ((double)b.lx * (double)b.ly * (double)b.lz);
   ra.r = f.r;
   ra.p = f.p;
   ra.v = f.v;
   ra.rhat = f.rhat;
   ra.s = f.s;
-  ra.k = k;
-  ra.in_mode = f.in_mode;
-  ra.out_mode = 0;
-  launch_row_fwd<R>(b.lx, ra, b.nsys, s);
+  if (k) ra.k = *k;
+  return ra;
+}
 
+template <typename R>
+void mvm_pass1(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, bool mask_input,
+               hipStream_t s) {
+  if (b.nsys <= 0) return;
+  if (f.in_mode == 0 && !x) throw std::runtime_error("mvm_pass1: missing input");
+  if (f.in_mode != 0 && (!k || !f.r || !f.v || !f.p))
+    throw std::runtime_error("mvm_pass1: missing fused vectors");
+  RowArgs<R> ra = row_args<R>(b, k, f, x, nullptr, mask_input);
+  ra.in_mode = f.in_mode;
+  launch_row_fwd<R>(b.lx, ra, b.nsys, s);
+}
+
+template <typename R>
+void mvm_mid(const MvmBatch<R>& b, hipStream_t s) {
+  if (b.nsys <= 0) return;
   ColArgs<R> ca{};
   ca.data = b.work;
   ca.outer = 3 * b.nz;
@@ -593,6 +658,7 @@ void mvm_fused(const MvmBatch<R>& b, const KBatch& k, const FuseArgs& f, const c
   za.nz = b.nz;
   za.ly = b.ly;
   za.lx = b.lx;
+  za.variant = b.zvariant;
   za.wstride = b.wstride;
   za.sstride = b.sstride;
   za.work = b.work;
@@ -604,16 +670,114 @@ void mvm_fused(const MvmBatch<R>& b, const KBatch& k, const FuseArgs& f, const c
   ca.n_in = b.ly;
   ca.n_out = b.ny;
   launch_col<R, +1>(b.ly, ca, s);
+}
 
-  ra.in_mode = 0;
+template <typename R>
+void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s) {
+  if (b.nsys <= 0) return;
+  if (!x || !y) throw std::runtime_error("mvm_pass5: missing vectors");
+  if ((f.out_mode != 0 && !k) || (f.out_mode == 1 && !f.rhat) || (f.out_mode == 2 && !f.s))
+    throw std::runtime_error("mvm_pass5: missing fused vectors");
+  RowArgs<R> ra = row_args<R>(b, k, f, x, y, false);
   ra.out_mode = f.out_mode;
   launch_row_inv<R>(b.lx, ra, b.nsys, s);
 }
 
-template void mvm_fused<float>(const MvmBatch<float>&, const KBatch&, const FuseArgs&, const c128*, c128*,
-                               hipStream_t);
-template void mvm_fused<double>(const MvmBatch<double>&, const KBatch&, const FuseArgs&, const c128*, c128*,
-                                hipStream_t);
+template <typename R>
+void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStream_t s, hipEvent_t* ev) {
+  if (b.nsys <= 0) return;
+  const FuseArgs none{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+  mark(ev, 0, s);
+  mvm_pass1<R>(b, nullptr, none, x, mask_input, s);
+  mark(ev, 1, s);
+  if (!ev) {
+    mvm_mid<R>(b, s);
+  } else {
+    // per-pass events for measurement
+    ColArgs<R> ca{};
+    ca.data = b.work;
+    ca.outer = 3 * b.nz;
+    ca.inner = b.lx;
+    ca.n_in = b.ny;
+    ca.n_out = b.ly;
+    ca.stride = b.wstride;
+    ca.status = b.status;
+    ca.tw = b.tw->table[b.ly];
+    ca.nsys = b.nsys;
+    launch_col<R, -1>(b.ly, ca, s);
+    mark(ev, 2, s);
+    ZArgs<R> za{};
+    za.nz = b.nz;
+    za.ly = b.ly;
+    za.lx = b.lx;
+    za.variant = b.zvariant;
+    za.wstride = b.wstride;
+    za.sstride = b.sstride;
+    za.work = b.work;
+    za.spec = b.spec;
+    za.status = b.status;
+    za.tw = b.tw->table[b.lz];
+    launch_zconv<R>(b.lz, za, b.nsys, s);
+    mark(ev, 3, s);
+    ca.n_in = b.ly;
+    ca.n_out = b.ny;
+    launch_col<R, +1>(b.ly, ca, s);
+    mark(ev, 4, s);
+  }
+  mvm_pass5<R>(b, nullptr, none, x, y, s);
+  mark(ev, 5, s);
+}
+
+// Autotuning of the z pass: time each variant on the batch's own work buffer
+// (contents are overwritten; call before the buffer holds live data) and
+// return the faster one.
+template <typename R>
+int tune_zpass(const MvmBatch<R>& b, hipStream_t s) {
+  if (b.nsys <= 0) return 0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    throw std::runtime_error("hipEventCreate failed");
+  float best = 1e30f;
+  int best_v = 0;
+  for (int v = 0; v < 2; ++v) {
+    ZArgs<R> za{};
+    za.nz = b.nz;
+    za.ly = b.ly;
+    za.lx = b.lx;
+    za.variant = v;
+    za.wstride = b.wstride;
+    za.sstride = b.sstride;
+    za.work = b.work;
+    za.spec = b.spec;
+    za.status = nullptr;
+    za.tw = b.tw->table[b.lz];
+    launch_zconv<R>(b.lz, za, b.nsys, s);   // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3; ++r) launch_zconv<R>(b.lz, za, b.nsys, s);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best_v;
+}
+template int tune_zpass<float>(const MvmBatch<float>&, hipStream_t);
+template int tune_zpass<double>(const MvmBatch<double>&, hipStream_t);
+
+#define VIE_MVM_INST(R)                                                                                           \
+  template void mvm<R>(const MvmBatch<R>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);                  \
+  template void mvm_pass1<R>(const MvmBatch<R>&, const KBatch*, const FuseArgs&, const c128*, bool, hipStream_t); \
+  template void mvm_mid<R>(const MvmBatch<R>&, hipStream_t);                                                     \
+  template void mvm_pass5<R>(const MvmBatch<R>&, const KBatch*, const FuseArgs&, const c128*, c128*, hipStream_t);
+VIE_MVM_INST(float)
+VIE_MVM_INST(double)
+#undef VIE_MVM_INST
 
 int64_t mvm_row_tiles(int lx, int nz, int ny) {
   const int64_t rows = 3 * (int64_t)nz * ny;

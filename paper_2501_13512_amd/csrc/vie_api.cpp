@@ -201,8 +201,8 @@ struct Group {
   int bx, by, bz, lx, ly, lz, nsys;
   int64_t bnv, n;
   std::shared_ptr<Spectra> spec;
-  DevBuf chi, work, vecs, partials, counters;
-  int64_t pstride;  // doubles of partials per system
+  DevBuf chi, work, vecs;
+  int zvar[2] = {0, 0};  // tuned z-pass variant per precision ([0] FP64, [1] FP32)
   c128* vec[8];  // B, X, R, RHAT, P, V, S, T
   int slot0;     // first entry in the problem's inner status/state arrays
   std::vector<int> blocks;
@@ -217,8 +217,12 @@ struct vie_problem {
   int lx = 0, ly = 0, lz = 0;
   double k0 = 0;
   std::shared_ptr<Spectra> spec;
-  DevBuf chi, work, vecs, partials, counters, ostate, ostatus, scal;
+  DevBuf chi, work, vecs, partials, ntile, ostate, ostatus, scal;
   int64_t pstride = 0;
+  int zvar[2] = {0, 0};
+  // inner systems of all groups: partials (per-system stride ipstride)
+  DevBuf d_ipartials, d_intile;
+  int64_t ipstride = 0;
   c128* vec[V_COUNT] = {};
   // blocks
   int n_blocks = 0, n_nonempty = 0;
@@ -308,6 +312,7 @@ MvmBatch<R> outer_batch(vie_problem& P, bool gated) {
   b.work = P.work.as<cx<R>>();
   b.status = gated ? P.ostatus.as<int>() : nullptr;
   b.tw = tw_set<R>(P.ctx);
+  b.zvariant = P.zvar[sizeof(R) == sizeof(float) ? 1 : 0];
   return b;
 }
 
@@ -330,6 +335,7 @@ MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
   b.work = G.work.as<cx<R>>();
   b.status = gated ? P.d_istatus.as<int>() + G.slot0 : nullptr;
   b.tw = tw_set<R>(P.ctx);
+  b.zvariant = G.zvar[sizeof(R) == sizeof(float) ? 1 : 0];
   return b;
 }
 
@@ -341,32 +347,71 @@ KBatch outer_kbatch(vie_problem& P) {
   k.st = P.ostate.as<KState>();
   k.partials = P.partials.as<double>();
   k.pstride = P.pstride;
-  k.counters = P.counters.as<int>();
+  k.ntile = P.ntile.as<int>();
   return k;
 }
 
+// One group's systems (producers), within the problem's inner arrays.
 KBatch group_kbatch(vie_problem& P, Group& G) {
   KBatch k{};
   k.nsys = G.nsys;
   k.n = G.n;
   k.status = P.d_istatus.as<int>() + G.slot0;
   k.st = P.d_istate.as<KState>() + G.slot0;
-  k.partials = G.partials.as<double>();
-  k.pstride = G.pstride;
-  k.counters = G.counters.as<int>();
+  k.partials = P.d_ipartials.as<double>() + (int64_t)G.slot0 * P.ipstride;
+  k.pstride = P.ipstride;
+  k.ntile = P.d_intile.as<int>() + G.slot0;
   return k;
 }
 
-// One BiCGSTAB step with K = I, fused: p update + product + alpha; s update +
-// half-step test + product + omega; x, r update + rho, ||r||.  11 kernels.
+// Every inner system of every group (finalize kernels).
+KBatch inner_all(vie_problem& P) {
+  KBatch k{};
+  k.nsys = P.n_inner;
+  k.n = 0;
+  k.status = P.d_istatus.as<int>();
+  k.st = P.d_istate.as<KState>();
+  k.partials = P.d_ipartials.as<double>();
+  k.pstride = P.ipstride;
+  k.ntile = P.d_intile.as<int>();
+  return k;
+}
+
+// Vectors of one unpreconditioned BiCGSTAB batch (y = p, z = s).
+struct StepVecs {
+  c128 *x, *r, *rhat, *p, *v, *s, *t;
+};
+
+// One BiCGSTAB step with K = I for several batches at once, phase by phase:
+// [p update + product + <rhat,v>] -> alpha -> [s update + ||s||] -> half-step
+// test -> [rest of the product + <t,s>, <t,t>] -> omega -> [x, r update +
+// <rhat,r>, ||r||] -> rho, beta, convergence.  Each bracket is one group of
+// launches per batch; each arrow one finalize launch for all systems
+// (`all`), so a step is 11 launches per batch plus 4.
 template <typename R>
-void fused_step(const MvmBatch<R>& m, const KBatch& k, c128* x, c128* r, c128* rhat, c128* p, c128* v, c128* sv,
-                c128* t, hipStream_t s) {
-  vie::FuseArgs f1{1, 1, r, p, v, rhat, nullptr};
-  vie::mvm_fused<R>(m, k, f1, nullptr, v, s);
-  vie::FuseArgs f2{2, 2, r, sv, v, nullptr, sv};
-  vie::mvm_fused<R>(m, k, f2, nullptr, t, s);
-  vie::k_update_xr(k, x, p, sv, r, sv, t, rhat, s);
+void fused_steps(const std::vector<MvmBatch<R>>& m, const std::vector<KBatch>& k, const std::vector<StepVecs>& v,
+                 const KBatch& all, hipStream_t s) {
+  const size_t G = m.size();
+  for (size_t g = 0; g < G; ++g) {
+    const vie::FuseArgs f1{1, 1, v[g].r, v[g].p, v[g].v, v[g].rhat, nullptr};
+    vie::mvm_pass1<R>(m[g], &k[g], f1, nullptr, false, s);
+    vie::mvm_mid<R>(m[g], s);
+    vie::mvm_pass5<R>(m[g], &k[g], f1, v[g].p, v[g].v, s);
+  }
+  vie::k_finalize(all, vie::FIN_ALPHA, s);
+  for (size_t g = 0; g < G; ++g) {
+    const vie::FuseArgs f2{2, 2, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
+    vie::mvm_pass1<R>(m[g], &k[g], f2, nullptr, false, s);
+  }
+  vie::k_finalize(all, vie::FIN_S, s);
+  for (size_t g = 0; g < G; ++g) {
+    const vie::FuseArgs f2{2, 2, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
+    vie::mvm_mid<R>(m[g], s);
+    vie::mvm_pass5<R>(m[g], &k[g], f2, v[g].s, v[g].t, s);
+  }
+  vie::k_finalize(all, vie::FIN_OMEGA, s);
+  for (size_t g = 0; g < G; ++g) vie::k_update_xr(k[g], v[g].x, v[g].p, v[g].s, v[g].r, v[g].s, v[g].t, v[g].rhat, s);
+  vie::k_finalize(all, vie::FIN_XR, s);
 }
 
 c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (size_t)kind * P.groups.size(); }
@@ -375,12 +420,15 @@ c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (siz
 // z = s: the inner solves are unpreconditioned).
 template <typename R>
 void inner_iteration(vie_problem& P, hipStream_t s) {
+  std::vector<MvmBatch<R>> m;
+  std::vector<KBatch> k;
+  std::vector<StepVecs> v;
   for (auto& G : P.groups) {
-    KBatch k = group_kbatch(P, G);
-    MvmBatch<R> m = group_batch<R>(P, G, true);
-    c128** v = G.vec;
-    fused_step<R>(m, k, v[V_X], v[V_R], v[V_RHAT], v[V_P], v[V_V], v[V_S], v[V_T], s);
+    m.push_back(group_batch<R>(P, G, true));
+    k.push_back(group_kbatch(P, G));
+    v.push_back({G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], G.vec[V_P], G.vec[V_V], G.vec[V_S], G.vec[V_T]});
   }
+  fused_steps<R>(m, k, v, inner_all(P), s);
 }
 
 // The inner step captured once per problem and precision as a HIP graph
@@ -423,8 +471,9 @@ void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit
   vie::block_gather(P.bmap, w, gptr(P, V_B), s);
   for (auto& G : P.groups) {
     KBatch k = group_kbatch(P, G);
-    vie::k_init(k, G.vec[V_B], G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], tol, maxit, gate, s);
+    vie::k_init(k, G.vec[V_B], G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], gate, s);
   }
+  vie::k_finalize(inner_all(P), vie::FIN_INIT, s, gate, tol, maxit);
   hipGraphExec_t ex = graphs ? inner_graph<R>(P) : nullptr;
   Poller poll(P, s, 1);
   for (int it = 1; it <= maxit; ++it) {
@@ -454,21 +503,33 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
   MvmBatch<R> m = outer_batch<R>(P, true);
   c128** v = P.vec;
   const int* gate = P.ostatus.as<int>();
-  vie::k_init(k, rhs, x, v[V_R], v[V_RHAT], tol, maxit, nullptr, s);
+  vie::k_init(k, rhs, x, v[V_R], v[V_RHAT], nullptr, s);
+  vie::k_finalize(k, vie::FIN_INIT, s, nullptr, tol, maxit);
+  const std::vector<MvmBatch<R>> mv{m};
+  const std::vector<KBatch> kv{k};
+  const std::vector<StepVecs> vv{{x, v[V_R], v[V_RHAT], v[V_P], v[V_V], v[V_S], v[V_T]}};
   Poller poll(P, s, 0);
   for (int it = 1; it <= maxit; ++it) {
     if (!prec) {
-      fused_step<R>(m, k, x, v[V_R], v[V_RHAT], v[V_P], v[V_V], v[V_S], v[V_T], s);
+      fused_steps<R>(mv, kv, vv, k, s);
     } else {
       vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
       precond_apply<R>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
-      vie::FuseArgs fa{0, 1, nullptr, nullptr, nullptr, v[V_RHAT], nullptr};
-      vie::mvm_fused<R>(m, k, fa, v[V_Y], v[V_V], s);
+      const vie::FuseArgs fa{0, 1, nullptr, nullptr, nullptr, v[V_RHAT], nullptr};
+      vie::mvm_pass1<R>(m, &k, fa, v[V_Y], false, s);
+      vie::mvm_mid<R>(m, s);
+      vie::mvm_pass5<R>(m, &k, fa, v[V_Y], v[V_V], s);
+      vie::k_finalize(k, vie::FIN_ALPHA, s);
       vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
+      vie::k_finalize(k, vie::FIN_S, s);
       precond_apply<R>(P, v[V_S], v[V_Z], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
-      vie::FuseArgs fo{0, 2, nullptr, nullptr, nullptr, nullptr, v[V_S]};
-      vie::mvm_fused<R>(m, k, fo, v[V_Z], v[V_T], s);
+      const vie::FuseArgs fo{0, 2, nullptr, nullptr, nullptr, nullptr, v[V_S]};
+      vie::mvm_pass1<R>(m, &k, fo, v[V_Z], false, s);
+      vie::mvm_mid<R>(m, s);
+      vie::mvm_pass5<R>(m, &k, fo, v[V_Z], v[V_T], s);
+      vie::k_finalize(k, vie::FIN_OMEGA, s);
       vie::k_update_xr(k, x, v[V_Y], v[V_Z], v[V_R], v[V_S], v[V_T], v[V_RHAT], s);
+      vie::k_finalize(k, vie::FIN_XR, s);
     }
     const long t = poll.push(P.ostatus.as<int>());
     if (t - lag >= 0 && poll.wait(t - lag) != vie::ST_ACTIVE) break;
@@ -485,7 +546,7 @@ double true_relres(vie_problem& P, const c128* rhs, const c128* x, c128* tmp_ax,
   MvmBatch<double> m = outer_batch<double>(P, false);
   vie::mvm<double>(m, x, tmp_ax, false, s);
   vie::sub_vec(rhs, tmp_ax, tmp_r, 3 * P.nv, s);
-  vie::norm2(tmp_r, 3 * P.nv, P.partials.as<double>(), P.counters.as<int>() + 1, P.scal.as<double>(), s);
+  vie::norm2(tmp_r, 3 * P.nv, P.partials.as<double>(), P.scal.as<double>(), s);
   double r2 = 0;
   hip_check(hipMemcpyAsync(&r2, P.scal.p, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
   hip_check(hipStreamSynchronize(s), "norm");
@@ -697,13 +758,14 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
     P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0);
     upload(P->chi, chi);
     P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
+    P->work.zero();
     P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
     P->vecs.zero();
     for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
     P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
     P->partials.alloc(P->pstride * sizeof(double));
-    P->counters.alloc(2 * sizeof(int));   // [0] outer system, [1] norm2
-    P->counters.zero();
+    P->ntile.alloc(sizeof(int));
+    P->ntile.zero();
     P->ostate.alloc(sizeof(KState));
     P->ostate.zero();
     P->ostatus.alloc(sizeof(int));
@@ -828,16 +890,15 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
         upload(G.chi, gchi);
         G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0);
         G.work.alloc((size_t)G.nsys * 3 * G.bz * G.ly * G.lx * sizeof(c128));
+        G.work.zero();
         G.vecs.alloc(8 * (size_t)G.nsys * G.n * sizeof(c128));
         G.vecs.zero();
         for (int q = 0; q < 8; ++q) G.vec[q] = G.vecs.as<c128>() + (size_t)q * G.nsys * G.n;
-        G.pstride = 4 * std::max(vie::krylov_chunks(G.n), vie::mvm_row_tiles(G.lx, G.bz, G.by));
-        G.partials.alloc((size_t)G.nsys * G.pstride * sizeof(double));
-        G.counters.alloc((size_t)G.nsys * sizeof(int));
-        G.counters.zero();
+        P->ipstride = std::max<int64_t>(
+            P->ipstride, 4 * std::max(vie::krylov_chunks(G.n), vie::mvm_row_tiles(G.lx, G.bz, G.by)));
         G.slot0 = slot;
         slot += G.nsys;
-        foot += G.chi.bytes + G.work.bytes + G.vecs.bytes + G.partials.bytes + G.counters.bytes + G.spec->bytes();
+        foot += G.chi.bytes + G.work.bytes + G.vecs.bytes + G.spec->bytes();
         P->groups.push_back(std::move(G));
       }
       P->n_inner = slot;
@@ -859,6 +920,16 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
       P->d_istatus.zero();
       P->d_istate.alloc(std::max(1, slot) * sizeof(KState));
       P->d_istate.zero();
+      P->d_ipartials.alloc((size_t)std::max(1, slot) * P->ipstride * sizeof(double));
+      P->d_intile.alloc(std::max(1, slot) * sizeof(int));
+      P->d_intile.zero();
+      foot += P->d_ipartials.bytes;
+      // pick the faster z-pass kernel per batch shape and precision (clobbers
+      // the work buffers, which hold no data yet)
+      for (auto& G : P->groups) {
+        G.zvar[0] = vie::tune_zpass<double>(group_batch<double>(*P, G, false), ctx->stream);
+        G.zvar[1] = vie::tune_zpass<float>(group_batch<float>(*P, G, false), ctx->stream);
+      }
       vie::BlockMap& m = P->bmap;
       m.nblocks = n_blocks;
       m.ngroups = (int)P->groups.size();
@@ -871,6 +942,9 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
       m.ny = g.ny;
       m.nz = g.nz;
     }
+    P->zvar[0] = vie::tune_zpass<double>(outer_batch<double>(*P, false), ctx->stream);
+    P->zvar[1] = vie::tune_zpass<float>(outer_batch<float>(*P, false), ctx->stream);
+    hip_check(hipStreamSynchronize(ctx->stream), "z-pass tuning");
     P->footprint = foot;
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
