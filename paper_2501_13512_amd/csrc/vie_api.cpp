@@ -208,6 +208,14 @@ struct Group {
   std::vector<int> blocks;
 };
 
+// Streams on which the per-batch chains of a step run in parallel (graph
+// capture only): fork from `s` on `fork`, join back before the next launch on
+// `s`.  With no branch streams everything runs on `s` in order.
+struct Branches {
+  std::vector<hipStream_t> streams;   // one per batch, or empty
+  std::vector<hipEvent_t> events;     // 1 + batches per phase, 4 phases
+};
+
 }  // namespace
 
 struct vie_problem {
@@ -233,6 +241,7 @@ struct vie_problem {
   vie::BlockMap bmap{};
   // captured inner BiCGSTAB iteration of all block groups ([0] FP64, [1] FP32)
   hipGraphExec_t inner_graph[2] = {nullptr, nullptr};
+  Branches branches;   // per-group capture streams (parallel graph branches)
   // polling: ring 0 for the outer loop, ring 1 for the inner loops
   int* h_ring = nullptr;
   hipEvent_t ev[2][kRing] = {};
@@ -242,6 +251,8 @@ struct vie_problem {
   ~vie_problem() {
     for (auto& g : inner_graph)
       if (g) (void)hipGraphExecDestroy(g);
+    for (auto b : branches.streams) (void)hipStreamDestroy(b);
+    for (auto e : branches.events) (void)hipEventDestroy(e);
     for (auto& r : ev)
       for (auto& e : r)
         if (e) (void)hipEventDestroy(e);
@@ -388,29 +399,64 @@ struct StepVecs {
 // <rhat,r>, ||r||] -> rho, beta, convergence.  Each bracket is one group of
 // launches per batch; each arrow one finalize launch for all systems
 // (`all`), so a step is 11 launches per batch plus 4.
+static void fork(const Branches& br, int phase, hipStream_t s) {
+  if (br.streams.empty()) return;
+  const size_t G = br.streams.size();
+  hipEvent_t ev = br.events[phase * (G + 1)];
+  hip_check(hipEventRecord(ev, s), "fork");
+  for (auto b : br.streams) hip_check(hipStreamWaitEvent(b, ev, 0), "fork wait");
+}
+
+static void join(const Branches& br, int phase, hipStream_t s) {
+  if (br.streams.empty()) return;
+  const size_t G = br.streams.size();
+  for (size_t g = 0; g < G; ++g) {
+    hipEvent_t ev = br.events[phase * (G + 1) + 1 + g];
+    hip_check(hipEventRecord(ev, br.streams[g]), "join");
+    hip_check(hipStreamWaitEvent(s, ev, 0), "join wait");
+  }
+}
+
+// One BiCGSTAB step with K = I for several batches at once, phase by phase:
+// [p update + product + <rhat,v>] -> alpha -> [s update + ||s||] -> half-step
+// test -> [rest of the product + <t,s>, <t,t>] -> omega -> [x, r update +
+// <rhat,r>, ||r||] -> rho, beta, convergence.  Each bracket is one chain of
+// launches per batch (run on the batch's branch stream if given); each arrow
+// one finalize launch for all systems (`all`) on `s`, so a step is 11
+// launches per batch plus 4.
 template <typename R>
 void fused_steps(const std::vector<MvmBatch<R>>& m, const std::vector<KBatch>& k, const std::vector<StepVecs>& v,
-                 const KBatch& all, hipStream_t s) {
+                 const KBatch& all, const Branches& br, hipStream_t s) {
   const size_t G = m.size();
+  auto bs = [&](size_t g) { return br.streams.empty() ? s : br.streams[g]; };
+  fork(br, 0, s);
   for (size_t g = 0; g < G; ++g) {
     const vie::FuseArgs f1{1, 1, v[g].r, v[g].p, v[g].v, v[g].rhat, nullptr};
-    vie::mvm_pass1<R>(m[g], &k[g], f1, nullptr, false, s);
-    vie::mvm_mid<R>(m[g], s);
-    vie::mvm_pass5<R>(m[g], &k[g], f1, v[g].p, v[g].v, s);
+    vie::mvm_pass1<R>(m[g], &k[g], f1, nullptr, false, bs(g));
+    vie::mvm_mid<R>(m[g], bs(g));
+    vie::mvm_pass5<R>(m[g], &k[g], f1, v[g].p, v[g].v, bs(g));
   }
+  join(br, 0, s);
   vie::k_finalize(all, vie::FIN_ALPHA, s);
+  fork(br, 1, s);
   for (size_t g = 0; g < G; ++g) {
     const vie::FuseArgs f2{2, 2, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
-    vie::mvm_pass1<R>(m[g], &k[g], f2, nullptr, false, s);
+    vie::mvm_pass1<R>(m[g], &k[g], f2, nullptr, false, bs(g));
   }
+  join(br, 1, s);
   vie::k_finalize(all, vie::FIN_S, s);
+  fork(br, 2, s);
   for (size_t g = 0; g < G; ++g) {
     const vie::FuseArgs f2{2, 2, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
-    vie::mvm_mid<R>(m[g], s);
-    vie::mvm_pass5<R>(m[g], &k[g], f2, v[g].s, v[g].t, s);
+    vie::mvm_mid<R>(m[g], bs(g));
+    vie::mvm_pass5<R>(m[g], &k[g], f2, v[g].s, v[g].t, bs(g));
   }
+  join(br, 2, s);
   vie::k_finalize(all, vie::FIN_OMEGA, s);
-  for (size_t g = 0; g < G; ++g) vie::k_update_xr(k[g], v[g].x, v[g].p, v[g].s, v[g].r, v[g].s, v[g].t, v[g].rhat, s);
+  fork(br, 3, s);
+  for (size_t g = 0; g < G; ++g)
+    vie::k_update_xr(k[g], v[g].x, v[g].p, v[g].s, v[g].r, v[g].s, v[g].t, v[g].rhat, bs(g));
+  join(br, 3, s);
   vie::k_finalize(all, vie::FIN_XR, s);
 }
 
@@ -419,7 +465,7 @@ c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (siz
 // One BiCGSTAB step of every inner system of every block group (y = p and
 // z = s: the inner solves are unpreconditioned).
 template <typename R>
-void inner_iteration(vie_problem& P, hipStream_t s) {
+void inner_iteration(vie_problem& P, hipStream_t s, const Branches& br) {
   std::vector<MvmBatch<R>> m;
   std::vector<KBatch> k;
   std::vector<StepVecs> v;
@@ -428,7 +474,7 @@ void inner_iteration(vie_problem& P, hipStream_t s) {
     k.push_back(group_kbatch(P, G));
     v.push_back({G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], G.vec[V_P], G.vec[V_V], G.vec[V_S], G.vec[V_T]});
   }
-  fused_steps<R>(m, k, v, inner_all(P), s);
+  fused_steps<R>(m, k, v, inner_all(P), br, s);
 }
 
 // The inner step captured once per problem and precision as a HIP graph
@@ -446,7 +492,7 @@ hipGraphExec_t inner_graph(vie_problem& P) {
     hip_check(e, "begin capture");
   }
   try {
-    inner_iteration<R>(P, cs);
+    inner_iteration<R>(P, cs, P.branches);
   } catch (...) {
     (void)hipStreamEndCapture(cs, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -480,7 +526,7 @@ void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit
     if (ex)
       hip_check(hipGraphLaunch(ex, s), "graph launch");
     else
-      inner_iteration<R>(P, s);
+      inner_iteration<R>(P, s, Branches{});
     vie::count_active(P.d_istatus.as<int>(), P.n_inner, P.d_count.as<int>(), s);
     const long t = poll.push(P.d_count.as<int>());
     if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
@@ -511,7 +557,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
   Poller poll(P, s, 0);
   for (int it = 1; it <= maxit; ++it) {
     if (!prec) {
-      fused_steps<R>(mv, kv, vv, k, s);
+      fused_steps<R>(mv, kv, vv, k, Branches{}, s);
     } else {
       vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
       precond_apply<R>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
@@ -822,7 +868,9 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
       // A merged group takes the largest lengths of both (a box of n <=
       // (L+1)/2 voxels embeds in any longer L).
       {
-        const double kGroupOverhead = 4.0e5;  // padded points per group-iteration overhead
+        // ~11 launches of >= 5 us per group and step, against ~50 ps per padded
+        // point and step (two products and the vector updates) on MI355X
+        const double kGroupOverhead = 1.2e6;  // padded points per group-iteration overhead
         auto cost = [&](int lx, int ly, int lz, size_t nsys) {
           return kGroupOverhead + (double)nsys * lx * ly * lz;
         };
@@ -929,6 +977,13 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
       for (auto& G : P->groups) {
         G.zvar[0] = vie::tune_zpass<double>(group_batch<double>(*P, G, false), ctx->stream);
         G.zvar[1] = vie::tune_zpass<float>(group_batch<float>(*P, G, false), ctx->stream);
+      }
+      if (P->groups.size() > 1) {
+        const size_t G = P->groups.size();
+        P->branches.streams.resize(G, nullptr);
+        for (auto& b : P->branches.streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
+        P->branches.events.resize(4 * (G + 1), nullptr);
+        for (auto& e : P->branches.events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
       }
       vie::BlockMap& m = P->bmap;
       m.nblocks = n_blocks;
