@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 1
+#define VIE_ABI_VERSION 2
 
 typedef enum {
   VIE_OK = 0,
@@ -105,6 +105,10 @@ typedef struct {
 /* vie_opts.flags: run the inner block iterations as individual kernel
  * launches instead of a captured HIP graph (same kernels, same results). */
 #define VIE_FLAG_NO_GRAPHS 1
+/* vie_opts.flags: solve every block with the batched multi-workgroup
+ * kernels, also blocks small enough for the one-workgroup block solver
+ * (same iteration, different summation order in the inner products). */
+#define VIE_FLAG_NO_BLOCK_KERNEL 2
 
 /* Statistics of one solve. */
 typedef struct {
@@ -184,10 +188,12 @@ vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_d
 vie_status vie_block_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream);
 
 /* y = K2^{-1} w by inner BiCGSTAB-FFT solves of every block to tol_inner
- * (x0 = 0, at most maxit_inner steps, last iterate kept), all blocks batched
- * (Sec. II-B).  inner_iters (optional) receives the total inner steps. */
+ * (x0 = 0, at most maxit_inner steps, last iterate kept), every block
+ * independent (Sec. II-B).  flags: VIE_FLAG_NO_GRAPHS and
+ * VIE_FLAG_NO_BLOCK_KERNEL as in vie_opts.flags (other bits: VIE_EINVAL).
+ * inner_iters (optional) receives the total inner steps. */
 vie_status vie_precond_apply(vie_problem* p, int32_t precision, double tol_inner, int32_t maxit_inner,
-                             const void* w_dev, void* y_dev, void* stream, int64_t* inner_iters);
+                             int32_t flags, const void* w_dev, void* y_dev, void* stream, int64_t* inner_iters);
 
 /* Solve A P = E_inc (host arrays).  e_inc: 3*nvox complex; e_tot_out:
  * 3*nvox complex, E_tot = P / chi on the scatterer, 0 in vacuum (eq. (2));

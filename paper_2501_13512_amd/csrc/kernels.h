@@ -123,6 +123,35 @@ struct KBatch {
   int* ntile;         // per system: partial count written by the last producer
 };
 
+// Inner block solves with one workgroup per system (Sec. II-B): the whole
+// unpreconditioned BiCGSTAB of each system of a group (x0 = 0, rhs b) in one
+// launch.  Vectors are c128 [nsys][3][bz][by][bx]; the work buffer holds
+// [nsys][3][bz][ly][lx] elements of R; lx == ly.  On return each system's
+// status is CONVERGED, MAXIT or BREAKDOWN (IDLE if the gate is not ACTIVE)
+// and its KState holds nb, iters and rnorm.
+struct BlockSolveArgs {
+  int nsys;
+  int bx, by, bz;
+  int64_t n;                 // 3 bx by bz
+  const c128* chi;           // 1/chi per system [nsys][bz][by][bx], 0 outside the block
+  const c128* b;
+  c128 *x, *r, *rhat, *p, *v, *s, *t;
+  void* work;
+  const void* spec;          // octant spectra for (lx, ly, lz), shared by the systems
+  const void* twx;           // twiddle table for lx (== ly)
+  const void* twz;           // twiddle table for lz
+  int* status;
+  KState* st;
+  const int* gate;           // skip unless *gate == ACTIVE (null: always run)
+  double tol;
+  int maxit;
+};
+// True if the group's FFT box (lx, ly, lz) with bz voxel planes has a
+// block-solver kernel and is small enough for one workgroup to win.
+bool block_solver_supported(int lx, int ly, int lz, int bz);
+template <typename R>
+void block_solve(const BlockSolveArgs& a, int lx, int lz, hipStream_t s);
+
 // Scalar steps applied by k_finalize after a producer wrote partials.
 enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4 };
 

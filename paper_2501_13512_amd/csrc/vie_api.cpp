@@ -205,6 +205,7 @@ struct Group {
   int zvar[2] = {0, 0};  // tuned z-pass variant per precision ([0] FP64, [1] FP32)
   c128* vec[8];  // B, X, R, RHAT, P, V, S, T
   int slot0;     // first entry in the problem's inner status/state arrays
+  bool wg = false;  // small enough for the one-workgroup block solver
   std::vector<int> blocks;
 };
 
@@ -239,8 +240,14 @@ struct vie_problem {
   DevBuf d_acc, d_hist, d_count;
   int n_inner = 0;
   vie::BlockMap bmap{};
-  // captured inner BiCGSTAB iteration of all block groups ([0] FP64, [1] FP32)
-  hipGraphExec_t inner_graph[2] = {nullptr, nullptr};
+  // Groups are ordered batched first, then the block-solver groups; with the
+  // block solver on, the batched groups own inner slots [0, n_batched_wg).
+  int n_batched_wg = 0, n_wg_groups = 0;
+  std::vector<hipStream_t> wg_streams;   // one per block-solver group
+  std::vector<hipEvent_t> wg_events;     // [0] fork, [1 + i] join of group i
+  // captured inner BiCGSTAB iteration of the batched groups
+  // [precision: 0 FP64, 1 FP32][block solver on]
+  hipGraphExec_t inner_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   Branches branches;   // per-group capture streams (parallel graph branches)
   // polling: ring 0 for the outer loop, ring 1 for the inner loops
   int* h_ring = nullptr;
@@ -249,8 +256,11 @@ struct vie_problem {
   size_t footprint = 0;
 
   ~vie_problem() {
-    for (auto& g : inner_graph)
-      if (g) (void)hipGraphExecDestroy(g);
+    for (auto& gp : inner_graph)
+      for (auto g : gp)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto b : wg_streams) (void)hipStreamDestroy(b);
+    for (auto e : wg_events) (void)hipEventDestroy(e);
     for (auto b : branches.streams) (void)hipStreamDestroy(b);
     for (auto e : branches.events) (void)hipEventDestroy(e);
     for (auto& r : ev)
@@ -375,10 +385,10 @@ KBatch group_kbatch(vie_problem& P, Group& G) {
   return k;
 }
 
-// Every inner system of every group (finalize kernels).
-KBatch inner_all(vie_problem& P) {
+// Inner systems [0, nsys) of the problem (finalize kernels).
+KBatch inner_all(vie_problem& P, int nsys) {
   KBatch k{};
-  k.nsys = P.n_inner;
+  k.nsys = nsys;
   k.n = 0;
   k.status = P.d_istatus.as<int>();
   k.st = P.d_istate.as<KState>();
@@ -462,26 +472,48 @@ void fused_steps(const std::vector<MvmBatch<R>>& m, const std::vector<KBatch>& k
 
 c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (size_t)kind * P.groups.size(); }
 
-// One BiCGSTAB step of every inner system of every block group (y = p and
-// z = s: the inner solves are unpreconditioned).
+// Groups solved by the batched kernels (all, or all but the block-solver
+// groups) and their inner slot count.
+bool batched(const Group& G, bool wg) { return !(wg && G.wg); }
+int batched_slots(const vie_problem& P, bool wg) { return wg ? P.n_batched_wg : P.n_inner; }
+
+// The first k branch streams (and their events), or none for k <= 1.
+Branches branch_view(const vie_problem& P, size_t k) {
+  Branches b;
+  if (k <= 1 || P.branches.streams.size() < k) return b;
+  b.streams.assign(P.branches.streams.begin(), P.branches.streams.begin() + (long)k);
+  b.events.assign(P.branches.events.begin(), P.branches.events.begin() + (long)(4 * (k + 1)));
+  return b;
+}
+
+size_t n_batched_groups(const vie_problem& P, bool wg) {
+  size_t n = 0;
+  for (auto& G : P.groups) n += batched(G, wg) ? 1 : 0;
+  return n;
+}
+
+// One BiCGSTAB step of every inner system of the batched block groups (y = p
+// and z = s: the inner solves are unpreconditioned).
 template <typename R>
-void inner_iteration(vie_problem& P, hipStream_t s, const Branches& br) {
+void inner_iteration(vie_problem& P, hipStream_t s, const Branches& br, bool wg) {
   std::vector<MvmBatch<R>> m;
   std::vector<KBatch> k;
   std::vector<StepVecs> v;
   for (auto& G : P.groups) {
+    if (!batched(G, wg)) continue;
     m.push_back(group_batch<R>(P, G, true));
     k.push_back(group_kbatch(P, G));
     v.push_back({G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], G.vec[V_P], G.vec[V_V], G.vec[V_S], G.vec[V_T]});
   }
-  fused_steps<R>(m, k, v, inner_all(P), br, s);
+  fused_steps<R>(m, k, v, inner_all(P, batched_slots(P, wg)), br, s);
 }
 
-// The inner step captured once per problem and precision as a HIP graph
-// (all kernel arguments are fixed per problem), replayed every iteration.
+// The inner step captured once per problem, precision and block-solver mode
+// as a HIP graph (all kernel arguments are fixed per problem), replayed
+// every iteration.
 template <typename R>
-hipGraphExec_t inner_graph(vie_problem& P) {
-  hipGraphExec_t& ex = P.inner_graph[sizeof(R) == sizeof(float) ? 1 : 0];
+hipGraphExec_t inner_graph(vie_problem& P, bool wg) {
+  hipGraphExec_t& ex = P.inner_graph[sizeof(R) == sizeof(float) ? 1 : 0][wg ? 1 : 0];
   if (ex) return ex;
   hipStream_t cs = nullptr;
   hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
@@ -492,7 +524,7 @@ hipGraphExec_t inner_graph(vie_problem& P) {
     hip_check(e, "begin capture");
   }
   try {
-    inner_iteration<R>(P, cs, P.branches);
+    inner_iteration<R>(P, cs, branch_view(P, n_batched_groups(P, wg)), wg);
   } catch (...) {
     (void)hipStreamEndCapture(cs, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -510,27 +542,77 @@ hipGraphExec_t inner_graph(vie_problem& P) {
   return ex;
 }
 
-// y = K2^{-1} w: batched inner BiCGSTAB-FFT solves of every block (Sec. II-B).
+template <typename R>
+vie::BlockSolveArgs wg_args(vie_problem& P, Group& G, const int* gate, double tol, int maxit) {
+  vie::BlockSolveArgs a{};
+  a.nsys = G.nsys;
+  a.bx = G.bx;
+  a.by = G.by;
+  a.bz = G.bz;
+  a.n = G.n;
+  a.chi = G.chi.as<c128>();
+  a.b = G.vec[V_B];
+  a.x = G.vec[V_X];
+  a.r = G.vec[V_R];
+  a.rhat = G.vec[V_RHAT];
+  a.p = G.vec[V_P];
+  a.v = G.vec[V_V];
+  a.s = G.vec[V_S];
+  a.t = G.vec[V_T];
+  a.work = G.work.p;
+  a.spec = spec_ptr<R>(*G.spec);
+  a.twx = tw_set<R>(P.ctx)->table[G.lx];
+  a.twz = tw_set<R>(P.ctx)->table[G.lz];
+  a.status = P.d_istatus.as<int>() + G.slot0;
+  a.st = P.d_istate.as<KState>() + G.slot0;
+  a.gate = gate;
+  a.tol = tol;
+  a.maxit = maxit;
+  return a;
+}
+
+// y = K2^{-1} w: inner BiCGSTAB-FFT solves of every block (Sec. II-B).
+// Block-solver groups (wg) run one launch each on their own streams while
+// the batched groups iterate on s; s waits for both before the scatter.
 template <typename R>
 void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit, const int* gate, int lag,
-                   int32_t* hist, int64_t hist_cap, bool graphs, hipStream_t s) {
+                   int32_t* hist, int64_t hist_cap, bool graphs, bool wg, hipStream_t s) {
   vie::block_gather(P.bmap, w, gptr(P, V_B), s);
-  for (auto& G : P.groups) {
-    KBatch k = group_kbatch(P, G);
-    vie::k_init(k, G.vec[V_B], G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], gate, s);
+  const bool any_wg = wg && P.n_wg_groups > 0;
+  if (any_wg) {
+    hip_check(hipEventRecord(P.wg_events[0], s), "fork");
+    int i = 0;
+    for (auto& G : P.groups) {
+      if (!G.wg) continue;
+      hipStream_t ws = P.wg_streams[i];
+      hip_check(hipStreamWaitEvent(ws, P.wg_events[0], 0), "fork wait");
+      vie::block_solve<R>(wg_args<R>(P, G, gate, tol, maxit), G.lx, G.lz, ws);
+      hip_check(hipEventRecord(P.wg_events[1 + i], ws), "join");
+      ++i;
+    }
   }
-  vie::k_finalize(inner_all(P), vie::FIN_INIT, s, gate, tol, maxit);
-  hipGraphExec_t ex = graphs ? inner_graph<R>(P) : nullptr;
-  Poller poll(P, s, 1);
-  for (int it = 1; it <= maxit; ++it) {
-    if (ex)
-      hip_check(hipGraphLaunch(ex, s), "graph launch");
-    else
-      inner_iteration<R>(P, s, Branches{});
-    vie::count_active(P.d_istatus.as<int>(), P.n_inner, P.d_count.as<int>(), s);
-    const long t = poll.push(P.d_count.as<int>());
-    if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
+  const int nslots = batched_slots(P, wg);
+  if (nslots > 0) {
+    for (auto& G : P.groups) {
+      if (!batched(G, wg)) continue;
+      KBatch k = group_kbatch(P, G);
+      vie::k_init(k, G.vec[V_B], G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], gate, s);
+    }
+    vie::k_finalize(inner_all(P, nslots), vie::FIN_INIT, s, gate, tol, maxit);
+    hipGraphExec_t ex = graphs ? inner_graph<R>(P, wg) : nullptr;
+    Poller poll(P, s, 1);
+    for (int it = 1; it <= maxit; ++it) {
+      if (ex)
+        hip_check(hipGraphLaunch(ex, s), "graph launch");
+      else
+        inner_iteration<R>(P, s, Branches{}, wg);
+      vie::count_active(P.d_istatus.as<int>(), nslots, P.d_count.as<int>(), s);
+      const long t = poll.push(P.d_count.as<int>());
+      if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
+    }
   }
+  if (any_wg)
+    for (int i = 0; i < P.n_wg_groups; ++i) hip_check(hipStreamWaitEvent(s, P.wg_events[1 + i], 0), "join wait");
   vie::block_scatter(P.bmap, gptr(P, V_X), y, s);
   vie::record_inner(gate, P.d_istate.as<KState>(), P.d_slots.as<int>(), P.n_nonempty, P.d_acc.as<int64_t>(), hist,
                     hist_cap, s);
@@ -544,7 +626,8 @@ struct RunResult {
 // Right-preconditioned BiCGSTAB on the full grid: A x = rhs (Sec. II-B).
 template <typename R>
 RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int maxit, bool prec, double tol_in,
-                       int maxit_in, int lag, int32_t* hist, int64_t hist_cap, bool graphs, hipStream_t s) {
+                       int maxit_in, int lag, int32_t* hist, int64_t hist_cap, bool graphs, bool wg,
+                       hipStream_t s) {
   KBatch k = outer_kbatch(P);
   MvmBatch<R> m = outer_batch<R>(P, true);
   c128** v = P.vec;
@@ -560,7 +643,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
       fused_steps<R>(mv, kv, vv, k, Branches{}, s);
     } else {
       vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
-      precond_apply<R>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
+      precond_apply<R>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
       const vie::FuseArgs fa{0, 1, nullptr, nullptr, nullptr, v[V_RHAT], nullptr};
       vie::mvm_pass1<R>(m, &k, fa, v[V_Y], false, s);
       vie::mvm_mid<R>(m, s);
@@ -568,7 +651,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
       vie::k_finalize(k, vie::FIN_ALPHA, s);
       vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
       vie::k_finalize(k, vie::FIN_S, s);
-      precond_apply<R>(P, v[V_S], v[V_Z], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, s);
+      precond_apply<R>(P, v[V_S], v[V_Z], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
       const vie::FuseArgs fo{0, 2, nullptr, nullptr, nullptr, nullptr, v[V_S]};
       vie::mvm_pass1<R>(m, &k, fo, v[V_Z], false, s);
       vie::mvm_mid<R>(m, s);
@@ -606,7 +689,7 @@ void validate_opts(const vie_opts* o, const vie_problem* p) {
   if (o->precision != VIE_FP64 && o->precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
   if (o->poll_lag < 0 || o->poll_lag > kRing - 2) fail(VIE_EINVAL, "poll_lag out of range");
   if (o->max_refine < 0 || o->max_refine > 100) fail(VIE_EINVAL, "max_refine out of range");
-  if (o->flags & ~VIE_FLAG_NO_GRAPHS) fail(VIE_EINVAL, "unknown flags");
+  if (o->flags & ~(VIE_FLAG_NO_GRAPHS | VIE_FLAG_NO_BLOCK_KERNEL)) fail(VIE_EINVAL, "unknown flags");
   if (o->precondition) {
     if (p->groups.empty()) fail(VIE_EINVAL, "precondition requested but the problem has no blocks");
     if (!(o->tol_inner >= 0) || !is_finite(o->tol_inner)) fail(VIE_EINVAL, "tol_inner must be finite and >= 0");
@@ -623,6 +706,7 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   c128** v = P.vec;
   const bool prec = o->precondition != 0;
   const bool graphs = (o->flags & VIE_FLAG_NO_GRAPHS) == 0;
+  const bool wg = (o->flags & VIE_FLAG_NO_BLOCK_KERNEL) == 0;
   int32_t* hist = nullptr;
   int64_t hist_cap = 0;
   if (stats && stats->inner_hist && stats->inner_hist_cap > 0 && prec) {
@@ -637,18 +721,18 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   double relres_true = 0;
   if (o->precision == VIE_FP64) {
     rr = run_bicgstab<double>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
-                              o->poll_lag, hist, hist_cap, graphs, s);
+                              o->poll_lag, hist, hist_cap, graphs, wg, s);
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], rr.st.nb, s);
   } else {
     rr = run_bicgstab<float>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
-                             o->poll_lag, hist, hist_cap, graphs, s);
+                             o->poll_lag, hist, hist_cap, graphs, wg, s);
     const double nb = rr.st.nb;
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
     // iterative refinement: solve A d = b - A x with FP32 products, x += d
     while (rr.status != vie::ST_BREAKDOWN && relres_true > o->tol_outer && refine < o->max_refine && nb > 0) {
       const double tol_c = std::min(0.5, o->tol_outer / relres_true);
       RunResult rc = run_bicgstab<float>(P, v[V_TMP2], v[V_TMP1], tol_c, o->maxit_outer, prec, o->tol_inner,
-                                         o->maxit_inner, o->poll_lag, hist, hist_cap, graphs, s);
+                                         o->maxit_inner, o->poll_lag, hist, hist_cap, graphs, wg, s);
       vie::add_vec(v[V_X], v[V_TMP1], 3 * P.nv, s);
       ++refine;
       refine_iters += rc.st.iters;
@@ -847,6 +931,7 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
       struct Plan {
         int lx, ly, lz;
         std::vector<int> blocks;
+        bool wg = false;
       };
       std::vector<Plan> plans;
       {
@@ -860,7 +945,20 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
               .push_back(k);
         }
         for (auto& kv : bylen) plans.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                                                kv.second});
+                                                kv.second, false});
+      }
+      // Shapes the one-workgroup block solver handles stay separate groups
+      // (one launch per group and application, whatever the group size).
+      std::vector<Plan> wg_plans;
+      {
+        std::vector<Plan> rest;
+        for (auto& pl : plans) {
+          int bz = 1;
+          for (int k : pl.blocks) bz = std::max(bz, hi[3 * k + 2] - lo[3 * k + 2] + 1);
+          pl.wg = vie::block_solver_supported(pl.lx, pl.ly, pl.lz, bz);
+          (pl.wg ? wg_plans : rest).push_back(std::move(pl));
+        }
+        plans = std::move(rest);
       }
       // Merge shape groups while it lowers the modelled cost of one inner
       // iteration: a fixed per-group overhead (its kernel launches) plus
@@ -900,6 +998,7 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
           plans.erase(plans.begin() + bj);
         }
       }
+      for (auto& pl : wg_plans) plans.push_back(std::move(pl));
       std::vector<int> block_group(n_blocks, -1), block_sys(n_blocks, -1);
       std::vector<int4> origin(n_blocks, int4{0, 0, 0, 0}), gbox;
       int slot = 0;
@@ -909,6 +1008,7 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
         G.ly = pl.ly;
         G.lz = pl.lz;
         G.blocks = pl.blocks;
+        G.wg = pl.wg;
         G.nsys = (int)G.blocks.size();
         G.bx = G.by = G.bz = 1;
         for (int k : G.blocks) {
@@ -950,6 +1050,12 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
         P->groups.push_back(std::move(G));
       }
       P->n_inner = slot;
+      for (auto& G : P->groups) {
+        if (G.wg)
+          ++P->n_wg_groups;
+        else
+          P->n_batched_wg += G.nsys;
+      }
       std::vector<int> slots;
       for (int k = 0; k < n_blocks; ++k)
         if (cnt[k] > 0) slots.push_back(P->groups[block_group[k]].slot0 + block_sys[k]);
@@ -984,6 +1090,12 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
         for (auto& b : P->branches.streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
         P->branches.events.resize(4 * (G + 1), nullptr);
         for (auto& e : P->branches.events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+      }
+      if (P->n_wg_groups > 0) {
+        P->wg_streams.resize(P->n_wg_groups, nullptr);
+        for (auto& b : P->wg_streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
+        P->wg_events.resize(1 + P->n_wg_groups, nullptr);
+        for (auto& e : P->wg_events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
       }
       vie::BlockMap& m = P->bmap;
       m.nblocks = n_blocks;
@@ -1145,23 +1257,25 @@ vie_status vie_block_matvec(vie_problem* p, int32_t precision, const void* x_dev
 }
 
 vie_status vie_precond_apply(vie_problem* p, int32_t precision, double tol_inner, int32_t maxit_inner,
-                             const void* w_dev, void* y_dev, void* stream, int64_t* inner_iters) {
+                             int32_t flags, const void* w_dev, void* y_dev, void* stream, int64_t* inner_iters) {
   return guarded([&]() -> vie_status {
     if (!p || !w_dev || !y_dev) fail(VIE_EINVAL, "problem, w and y are required");
     if (w_dev == y_dev) fail(VIE_EINVAL, "w and y must not overlap");
     if (p->groups.empty()) fail(VIE_EINVAL, "problem has no blocks");
     if (!(tol_inner >= 0) || !is_finite(tol_inner)) fail(VIE_EINVAL, "tol_inner must be finite and >= 0");
     if (maxit_inner < 1) fail(VIE_EINVAL, "maxit_inner must be >= 1");
+    if (flags & ~(VIE_FLAG_NO_GRAPHS | VIE_FLAG_NO_BLOCK_KERNEL)) fail(VIE_EINVAL, "unknown flags");
+    const bool graphs = (flags & VIE_FLAG_NO_GRAPHS) == 0, wg = (flags & VIE_FLAG_NO_BLOCK_KERNEL) == 0;
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
     hipStream_t s = (hipStream_t)stream;
     hip_check(hipMemsetAsync(p->d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
     if (precision == VIE_FP64)
-      precond_apply<double>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, true,
-                            s);
+      precond_apply<double>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, graphs,
+                            wg, s);
     else if (precision == VIE_MIXED)
-      precond_apply<float>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, true,
-                           s);
+      precond_apply<float>(*p, (const c128*)w_dev, (c128*)y_dev, tol_inner, maxit_inner, nullptr, 1, nullptr, 0, graphs,
+                           wg, s);
     else
       fail(VIE_EINVAL, "unknown precision");
     if (inner_iters) {

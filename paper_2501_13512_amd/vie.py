@@ -29,6 +29,7 @@ VIE_OK, VIE_NOT_CONVERGED = 0, 1
 VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_EBREAKDOWN, VIE_EBUSY, VIE_ECANCELLED, VIE_EINTERNAL = -1, -2, -3, -4, -5, -6, -7
 VIE_FP64, VIE_MIXED = 0, 1
 VIE_FLAG_NO_GRAPHS = 1
+VIE_FLAG_NO_BLOCK_KERNEL = 2
 STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_ENOMEM", -3: "VIE_EDEVICE",
                 -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL"}
 
@@ -86,7 +87,7 @@ for _name, _args in {
     "vie_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
     "vie_matvec_profile": [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp],
     "vie_block_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
-    "vie_precond_apply": [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp,
+    "vie_precond_apply": [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                           ctypes.POINTER(ctypes.c_int64)],
     "vie_solve": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats)],
     "vie_solve_device": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats), _vp],
@@ -181,9 +182,10 @@ def vie_block_matvec(p: int, precision: int, x, y, stream=None) -> None:
     _check(_lib.vie_block_matvec(p, precision, _dev(x), _dev(y), _stream(stream)), "vie_block_matvec")
 
 
-def vie_precond_apply(p: int, precision: int, tol_inner: float, maxit_inner: int, w, y, stream=None) -> int:
+def vie_precond_apply(p: int, precision: int, tol_inner: float, maxit_inner: int, w, y, stream=None,
+                      flags: int = 0) -> int:
     it = ctypes.c_int64(0)
-    _check(_lib.vie_precond_apply(p, precision, tol_inner, maxit_inner, _dev(w), _dev(y), _stream(stream),
+    _check(_lib.vie_precond_apply(p, precision, tol_inner, maxit_inner, flags, _dev(w), _dev(y), _stream(stream),
                                   ctypes.byref(it)), "vie_precond_apply")
     return int(it.value)
 

@@ -12,6 +12,10 @@
   step counts (+-2) of oracle runs with complex64 products.
 * Random tiny problems vs dense LU; edge cases (all vacuum, iteration cap,
   empty blocks, a single layer); repeat runs are bitwise identical.
+* Blocks whose FFT box fits the one-workgroup block solver run there by
+  default; the preconditioner and solve tests run in both modes (block
+  solver on, and every block on the batched kernels), and a partition with
+  both kinds of block boxes is checked in both.
 """
 import numpy as np
 import pytest
@@ -29,7 +33,7 @@ def _grid(case):
 
 
 def _solve(ctx, case, prec=V.VIE_FP64, precondition=True, tol=None, tol_in=None, maxit=None, hist_cap=0,
-           max_refine=3):
+           max_refine=3, flags=0):
     P = V.Problem(_grid(case), case.eps, case.block_id if precondition else None,
                   case.n_blocks if precondition else 0, ctx=ctx)
     try:
@@ -46,7 +50,7 @@ def _solve(ctx, case, prec=V.VIE_FP64, precondition=True, tol=None, tol_in=None,
                            tol_inner=case.tol_inner if tol_in is None else tol_in,
                            maxit_outer=case.maxit_outer if maxit is None else maxit,
                            maxit_inner=case.maxit_inner, precondition=precondition, precision=prec,
-                           max_refine=max_refine)
+                           max_refine=max_refine, flags=flags)
         code = V.vie_solve_device(P.handle, e, opts, out, pol, st)
         torch.cuda.synchronize()
         h = list(hist[:st.inner_hist_len]) if hist is not None else None
@@ -81,31 +85,82 @@ def _rounding_bar(a, b):
     return max(1e-10, 10 * _rel(b.E_tot, a.E_tot))
 
 
-def test_precond_apply_matches_oracle(vie_ctx):
-    case = W.cube16()
+BLOCK_MODES = [0, V.VIE_FLAG_NO_BLOCK_KERNEL]   # one-workgroup block solver on / off
+
+
+def _precond(ctx, case, w, prec, tol, flags):
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=ctx)
+    try:
+        wd = torch.from_numpy(w).cuda()
+        yd = torch.empty_like(wd)
+        iters = V.vie_precond_apply(P.handle, prec, tol, 500, wd, yd, flags=flags)
+        torch.cuda.synchronize()
+        return iters, yd.cpu().numpy()
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("flags", BLOCK_MODES)
+@pytest.mark.parametrize("name", ["cube16", "mixed_partition"])
+def test_precond_apply_matches_oracle(vie_ctx, name, flags):
+    """cube16: eight 8^3 blocks (block-solver shape); mixed_partition: two
+    8^3 blocks (block solver) and four 4x8x8 strips (batched kernels)."""
+    case = W.cube16() if name == "cube16" else W.mixed_partition()
     g = op.Grid.from_case(case)
     rng = np.random.default_rng(4)
     w = (rng.standard_normal((3,) + case.shape) + 1j * rng.standard_normal((3,) + case.shape)) * g.mask
     pre = krylov.BlockPreconditioner(g, case.block_id, case.n_blocks, 1e-3, 500)
     want = pre(w)
-    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
-    try:
-        wd = torch.from_numpy(w).cuda()
-        yd = torch.empty_like(wd)
-        iters = V.vie_precond_apply(P.handle, V.VIE_FP64, 1e-3, 500, wd, yd)
-        torch.cuda.synchronize()
-        got = yd.cpu().numpy()
-    finally:
-        P.close()
+    iters, got = _precond(vie_ctx, case, w, V.VIE_FP64, 1e-3, flags)
     assert iters == sum(pre.inner_counts[-1])
     assert _rel(got, want) <= 1e-10
 
 
-def test_cube_preconditioned_fp64(vie_ctx, cube_oracle):
+@pytest.mark.parametrize("flags", BLOCK_MODES)
+def test_precond_apply_mixed_precision(vie_ctx, flags):
+    """complex64 products: the result agrees with the oracle's complex64-
+    product preconditioner to 10x the spread between two such oracle runs
+    (FFT embedding lengths differ), and the step total within one per block."""
+    case = W.mixed_partition(1)
+    g = op.Grid.from_case(case)
+    rng = np.random.default_rng(5)
+    w = (rng.standard_normal((3,) + case.shape) + 1j * rng.standard_normal((3,) + case.shape)) * g.mask
+    refs = []
+    for pad in (0, 2):
+        pre = krylov.BlockPreconditioner(g, case.block_id, case.n_blocks, 1e-3, 500, pad=pad, product="c64")
+        refs.append((pre(w), sum(pre.inner_counts[-1])))
+    bar = max(1e-6, 10 * _rel(refs[1][0], refs[0][0]))
+    iters, got = _precond(vie_ctx, case, w, V.VIE_MIXED, 1e-3, flags)
+    assert abs(iters - refs[0][1]) <= case.n_blocks
+    assert _rel(got, refs[0][0]) <= bar
+
+
+@pytest.mark.parametrize("flags", BLOCK_MODES)
+def test_two_shape_partition_tight_solve(vie_ctx, flags):
+    case = W.mixed_partition(2)
+    g = op.Grid.from_case(case)
+    ref = krylov.solve(g, physics.plane_wave(g), 1e-12, 2000)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        e = torch.from_numpy(V.vie_plane_wave(P.grid, case.kdir, case.pol)).cuda()
+        out = torch.empty_like(e)
+        st = V.vie_stats()
+        opts = V.make_opts(tol_outer=1e-12, tol_inner=1e-3, maxit_outer=500, maxit_inner=500, precondition=True,
+                           precision=V.VIE_FP64, flags=flags)
+        code = V.vie_solve_device(P.handle, e, opts, out, None, st)
+        torch.cuda.synchronize()
+    finally:
+        P.close()
+    assert code == V.VIE_OK
+    assert _rel(out.cpu().numpy(), ref.E_tot) <= 1e-10
+
+
+@pytest.mark.parametrize("flags", BLOCK_MODES)
+def test_cube_preconditioned_fp64(vie_ctx, cube_oracle, flags):
     case, o = cube_oracle
     ref = o[("pre", 0)]
     n_app = 2 * ref.info.iterations
-    code, e_tot, P, st, hist = _solve(vie_ctx, case, hist_cap=8 * (n_app + 8))
+    code, e_tot, P, st, hist = _solve(vie_ctx, case, hist_cap=8 * (n_app + 8), flags=flags)
     assert code == V.VIE_OK
     assert abs(st.outer_iters - ref.info.iterations) <= 2
     oracle_hist = [c for app in ref.inner_counts for c in app]
@@ -138,7 +193,8 @@ def test_cube_tight_tolerance_agrees(vie_ctx):
     assert _rel(a, b) <= 1e-10
 
 
-def test_cube_mixed_precision(vie_ctx, cube_oracle):
+@pytest.mark.parametrize("flags", BLOCK_MODES)
+def test_cube_mixed_precision(vie_ctx, cube_oracle, flags):
     """Mixed mode: step count vs the oracle doing the same arithmetic
     (complex64 products, FP64 vectors).  FP32 rounding flips inner counts, so
     oracle runs that differ only in rounding (embedding pad 0, 2, 4) already
@@ -147,7 +203,7 @@ def test_cube_mixed_precision(vie_ctx, cube_oracle):
     case, o = cube_oracle
     ref64 = o[("pre", 0)]
     counts = [o[("pre_c64", pad)].info.iterations for pad in (0, 2, 4)]
-    code, e_tot, P, st, _ = _solve(vie_ctx, case, prec=V.VIE_MIXED)
+    code, e_tot, P, st, _ = _solve(vie_ctx, case, prec=V.VIE_MIXED, flags=flags)
     assert code == V.VIE_OK
     assert min(counts) - 2 <= st.outer_iters <= max(counts) + 2, (st.outer_iters, counts)
     assert _rel(e_tot, ref64.E_tot) <= 1e-5
@@ -155,7 +211,7 @@ def test_cube_mixed_precision(vie_ctx, cube_oracle):
 
 
 @pytest.mark.parametrize("seed,shape,nb", [(41, (3, 4, 5), 2), (42, (5, 5, 5), 3), (43, (2, 6, 3), 2),
-                                           (44, (7, 6, 5), 4)])
+                                           (44, (7, 6, 5), 4), (45, (8, 8, 8), 3)])
 def test_random_tiny_vs_dense_lu(vie_ctx, seed, shape, nb):
     case = W.random_tiny(seed, shape, fill=0.8, n_blocks=nb)
     g = op.Grid.from_case(case)

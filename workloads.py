@@ -39,7 +39,7 @@ import numpy as np
 
 __all__ = [
     "Case", "cube16", "metasurface", "plasmonic", "sweep_case", "sweep",
-    "sphere", "random_tiny", "CASES", "by_name",
+    "sphere", "random_tiny", "mixed_partition", "CASES", "by_name",
 ]
 
 
@@ -265,6 +265,26 @@ def random_tiny(seed: int, shape: Tuple[int, int, int], fill: float = 0.7,
     return Case(f"tiny{seed}_{nx}x{ny}x{nz}", nx, ny, nz, dx, dy, dz, wavelength, eps, bid,
                 max(len(used), 0), tol_outer=1e-10, tol_inner=1e-2, precision="fp64",
                 note="random tiny problem")
+
+
+def mixed_partition(seed: int = 0) -> Case:
+    """16x16x8 grid at lambda/20 whose blocks come in two box shapes: two
+    8x8x8 blocks (x < 8 and x >= 8, both y < 8) and four 4x8x8 strips
+    (y >= 8, x in [4i, 4i + 4)).  ``rng = default_rng(seed)``; mask ``rng.random
+    (shape) < 0.85``; eps ``rng.uniform(2, 5) - 1j * rng.uniform(0, 0.3)`` per
+    voxel."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = 16, 16, 8
+    shape = (nz, ny, nx)
+    mask = rng.random(shape) < 0.85
+    eps = np.where(mask, rng.uniform(2.0, 5.0, shape) - 1j * rng.uniform(0.0, 0.3, shape), 1.0 + 0.0j)
+    _, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    bid = np.where(yy < 8, (xx >= 8).astype(np.int32), 2 + xx // 4).astype(np.int32)
+    bid = np.where(mask, bid, -1).astype(np.int32)
+    d = 1.0 / 20.0
+    return Case(f"mixed_partition{seed}", nx, ny, nz, d, d, d, 1.0, eps.astype(np.complex128), bid, 6,
+                tol_outer=1e-6, tol_inner=1e-3, precision="fp64",
+                note="two block box shapes (8x8x8 and 4x8x8)")
 
 
 CASES = {"cube16": cube16, "metasurface": metasurface, "plasmonic": plasmonic}
