@@ -2,16 +2,21 @@
 
 One step = one complete solve of the metasurface-like workload (8x8
 dielectric pillars on a slab, 128x128x32 voxels at lambda/40, 65 blocks,
-mixed precision, outer tol 1e-5, inner tol 1e-2) with the incident field
-already in HBM: block gather, batched inner BiCGSTAB-FFT solves, scatter,
-outer FFT products, BiCGSTAB vector updates and the FP64 refinement check,
-all in libvie.  The problem (1/chi, block plan, Green spectra) is set up
-once before the timed region; its set-up time is reported separately.
+mixed precision, inner tol 1e-2) with the incident field already in HBM:
+block gather, batched inner BiCGSTAB-FFT solves, scatter, outer FFT
+products, BiCGSTAB vector updates and the FP64 refinement check, all in
+libvie.  The outer tolerance is 3e-6 instead of the workload's 1e-5: a
+solve to relative residual 1e-5 is about 2e-5 away from the converged field,
+3e-6 brings the field error under 1e-5 (--tol-outer changes it).  The
+problem (1/chi, block plan, Green spectra) is set up once before the timed
+region; its set-up time is reported separately.
 
 Prints one JSON line.  Extra fields: per-solve latency p50/p99, outer and
 inner step counts, the FP64 true residual, the sampled field error against
-the oracle's reference file (if present), the FFT product's per-pass times
-and the roofline of its dominant pass, and the CPU oracle baseline.
+the oracle's reference files (case tolerance, and tight), the FP64 GPU
+paths of the same workload (block-preconditioned and unpreconditioned),
+the FFT product's per-pass times and the roofline of its dominant pass (also
+on a 256x256x64 grid), and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -48,35 +53,98 @@ def pass_bytes(nx, ny, nz, lx, ly, lz, s):
 
 
 PASS_NAMES = ["k_row_fwd", "k_col(fwd)", "k_zconv", "k_col(inv)", "k_row_inv_local"]
+ZPASS_KERNELS = {0: "k_zconv_col<V0>", 1: "k_zconv_mirror", 2: "k_zconv_col<V2>", 3: "k_zconv_col<V3>",
+                 4: "k_zconv_col<V4>"}
+
+
+def pass_names(zvar):
+    n = list(PASS_NAMES)
+    n[2] = ZPASS_KERNELS.get(zvar, "k_zconv")
+    return n
+
+
+def mvm_profile(V, handle, info, nx, ny, nz, prec, reps):
+    """Per-pass times of the full-grid product (HIP events on the launch
+    stream) and their algorithmic bandwidth."""
+    import torch
+    x = torch.randn(3 * nx * ny * nz, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    ms = V.vie_matvec_profile(handle, prec, x, y, reps)
+    s_el = 8 if prec == V.VIE_MIXED else 16
+    pb = pass_bytes(nx, ny, nz, info.lx, info.ly, info.lz, s_el)
+    q = 1 if prec == V.VIE_MIXED else 0
+    zvar = int(info.zpass_variant[q])
+    names = pass_names(zvar)
+    dom = int(np.argmax(ms))
+    achieved = pb[dom] / (ms[dom] * 1e-3) / 1e9
+    return {"ms": float(np.sum(ms)), "algorithmic_GBps": sum(pb) / (float(np.sum(ms)) * 1e-3) / 1e9,
+            "pass_ms": [float(v) for v in ms], "pass_bytes": pb, "pass_names": names,
+            "pass_GBps": [b / (m * 1e-3) / 1e9 for b, m in zip(pb, ms)],
+            "zpass_variant": zvar, "zpass_tune_ms": [round(float(v), 4) for v in info.zpass_tune_ms[q]],
+            "dominant": {"kernel": names[dom], "achieved": achieved, "bytes": pb[dom], "ms": float(ms[dom])}}
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel
+    calibration), or None if no summary covers this kernel build."""
+    path = os.path.join(ROOT, "profiles", "mvm_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    for e in d.get("entries", []):
+        if e.get("kernel") == kernel and e.get("workload") == workload and e.get("source_hash") == _kernel_hash():
+            return e.get("bytes_per_launch")
+    return None
+
+
+def _kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mvm.hip", "fft_core.h", "kernels.h", "cx.h"):
+        h.update(open(os.path.join(ROOT, "paper_2501_13512_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def golden_error(case, e_tot):
-    path = os.path.join(ROOT, "tests", "golden", f"oracle_{case.name}.json")
-    if not os.path.exists(path):
-        return None
-    g = json.load(open(path))
-    vox = np.asarray(g["voxels_xyz"])
-    want = np.asarray(g["etot_re"]) + 1j * np.asarray(g["etot_im"])
-    got = e_tot[:, vox[:, 2], vox[:, 1], vox[:, 0]]
-    return {"sampled_rel_err": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
-            "oracle_outer_iters": g["outer_iters"], "n_samples": int(vox.shape[0])}
+    """Relative field difference at the oracle's sampled voxels: against the
+    oracle solve at the case tolerances and against the tight (1e-10)
+    oracle solve, where those reference files exist."""
+    out = {}
+    for key, suffix in (("case_tol", ""), ("tight", "_tight")):
+        path = os.path.join(ROOT, "tests", "golden", f"oracle_{case.name}{suffix}.json")
+        if not os.path.exists(path):
+            continue
+        g = json.load(open(path))
+        vox = np.asarray(g["voxels_xyz"])
+        want = np.asarray(g["etot_re"]) + 1j * np.asarray(g["etot_im"])
+        got = e_tot[:, vox[:, 2], vox[:, 1], vox[:, 0]]
+        out[key] = {"sampled_rel_err": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+                    "oracle_tol": g["tol_outer"], "oracle_outer_iters": g["outer_iters"],
+                    "n_samples": int(vox.shape[0])}
+    return out or None
 
 
 def cpu_baseline(case, outer_iters_hint):
     """Time the CPU oracle on a bounded sample: one outer BiCGSTAB step of the
     same solve (two preconditioner applications plus two products), scaled
-    by the oracle's outer step count for the full solve."""
+    by the oracle's outer step count for the full solve.  BLAS and FFT run
+    on one thread."""
+    from threadpoolctl import threadpool_limits
     from oracle import krylov, operator as op, physics
     g = op.Grid.from_case(case)
     e = physics.plane_wave(g, case.kdir, case.pol)
-    t0 = time.perf_counter()
-    sol = krylov.solve(g, e, case.tol_outer, 1, case.block_id, case.n_blocks, case.tol_inner, case.maxit_inner)
-    step_s = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        c0 = time.process_time()
+        krylov.solve(g, e, case.tol_outer, 1, case.block_id, case.n_blocks, case.tol_inner, case.maxit_inner)
+        step_s = time.perf_counter() - t0
+        cpu_s = time.process_time() - c0
     est = step_s * max(outer_iters_hint, 1)
     return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one outer step of the FP64 oracle solve of the same workload ({step_s:.1f} s, "
-                      f"includes set-up), scaled by {outer_iters_hint} outer steps",
-            "seconds_per_outer_step": step_s}
+            "sample": f"one outer step of the FP64 oracle solve of the same workload ({step_s:.1f} s wall, "
+                      f"{cpu_s:.1f} s CPU, includes set-up), scaled by {outer_iters_hint} outer steps",
+            "seconds_per_outer_step": step_s, "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -90,6 +158,13 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--maxit-outer", type=int, default=None,
                     help="cap the outer steps (profiling runs only; the result is then not a full solve)")
+    ap.add_argument("--tol-outer", type=float, default=3e-6,
+                    help="outer tolerance; the workload's own 1e-5 leaves a field error of about 2e-5 against a "
+                         "tight solve, 3e-6 brings it under 1e-5")
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="solves of each FP64 comparison path (block-preconditioned, unpreconditioned); 0 = skip")
+    ap.add_argument("--mvm-shapes", default="256x256x64",
+                    help="extra grids (comma-separated NXxNYxNZ, '' for none) whose full-grid product is timed per pass")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -112,6 +187,7 @@ def main():
     e_inc = torch.from_numpy(V.vie_plane_wave(grid, case.kdir, case.pol)).cuda()
     e_tot = torch.empty_like(e_inc)
     maxit = case.maxit_outer if args.maxit_outer is None else args.maxit_outer
+    case.tol_outer = args.tol_outer
     opts = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=maxit,
                        maxit_inner=case.maxit_inner, precondition=True, precision=prec, max_refine=3)
     st = V.vie_stats()
@@ -132,16 +208,47 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
+    # the FP64 GPU paths of the same workload, for comparison
+    compare = {}
+    for label, pre in (("fp64_block_preconditioned", True), ("fp64_unpreconditioned", False)):
+        if args.compare_steps <= 0 or args.maxit_outer is not None:
+            break
+        o64 = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=case.maxit_outer,
+                          maxit_inner=case.maxit_inner, precondition=pre, precision=V.VIE_FP64)
+        e64 = torch.empty_like(e_inc)
+        V.vie_solve_device(P.handle, e_inc, o64, e64, None, st)   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        lt = []
+        for _ in range(args.compare_steps):
+            t1 = time.perf_counter()
+            c64 = V.vie_solve_device(P.handle, e_inc, o64, e64, None, st)
+            lt.append(time.perf_counter() - t1)
+        sd = V.stats_dict(st)
+        d = e64.cpu().numpy()
+        compare[label] = {"solves_per_s": len(lt) / sum(lt), "latency_ms": {
+            "p50": 1e3 * float(np.percentile(lt, 50)), "p99": 1e3 * float(np.percentile(lt, 99))},
+            "status": V.STATUS_NAMES.get(c64, c64), "outer_iters": sd["outer_iters"],
+            "inner_iters_total": sd["inner_iters_total"], "relres_true": sd["relres_true"]}
+        if pre:
+            mine = e_tot.cpu().numpy()
+            compare[label]["mixed_vs_this_rel_field_diff"] = float(np.linalg.norm(mine - d) / np.linalg.norm(d))
+
     # FFT product of the full grid, per pass, HIP events on the launch stream
-    x = e_tot.clone()
-    y = torch.empty_like(x)
-    pass_ms = V.vie_matvec_profile(P.handle, prec, x, y, args.profile_reps)
-    s_el = 8 if prec == V.VIE_MIXED else 16
-    pbytes = pass_bytes(case.nx, case.ny, case.nz, info.lx, info.ly, info.lz, s_el)
-    dom = int(np.argmax(pass_ms))
-    achieved = pbytes[dom] / (pass_ms[dom] * 1e-3) / 1e9
-    mvm_ms = float(np.sum(pass_ms))
-    mvm_gbs = sum(pbytes) / (mvm_ms * 1e-3) / 1e9
+    mv = mvm_profile(V, P.handle, info, case.nx, case.ny, case.nz, prec, args.profile_reps)
+    dom = mv["dominant"]
+    wl = f"{case.name} {case.nx}x{case.ny}x{case.nz} {args.precision}"
+    traffic = traffic_for(dom["kernel"], wl)
+    extra = {}
+    for spec in [v for v in args.mvm_shapes.split(",") if v]:
+        nx, ny, nz = (int(v) for v in spec.split("x"))
+        eg = V.make_grid(nx, ny, nz, case.dx, case.dy, case.dz, case.wavelength)
+        Q = V.Problem(eg, np.full((nz, ny, nx), 4.0 + 0j), None, 0, ctx=ctx)
+        qi = Q.info()
+        extra[spec] = {p: mvm_profile(V, Q.handle, qi, nx, ny, nz, pv, args.profile_reps)
+                       for p, pv in (("mixed", V.VIE_MIXED), ("fp64", V.VIE_FP64))}
+        for p in extra[spec].values():
+            p["frac_of_hbm_peak"] = p["algorithmic_GBps"] / HBM_PEAK_GBS
+        Q.close()
 
     res = {
         "metric": "solves/s at 1e-5 rel field err + MVM HBM GB/s vs peak; p50/p99 solve latency",
@@ -167,17 +274,21 @@ def main():
         "inner_iters_total": stats[-1]["inner_iters_total"],
         "refine_steps": stats[-1]["refine_steps"],
         "relres_true": stats[-1]["relres_true"],
-        "mvm": {"ms": mvm_ms, "algorithmic_GBps": mvm_gbs, "pass_ms": [float(v) for v in pass_ms],
-                "pass_bytes": pbytes, "pass_names": PASS_NAMES},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": PASS_NAMES[dom] + f" (full-grid product, {args.precision})"},
+        "mvm": mv,
+        "roofline": {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dom["kernel"] + f" (full-grid product, {args.precision})"},
+        "mvm_other_grids": extra,
+        "fp64_gpu_paths": compare,
+        "block_solver_groups": int(info.n_block_solver_groups),
     }
     ge = golden_error(case, e_tot.cpu().numpy())
     if ge is not None:
         res["field_check"] = ge
     if not args.no_cpu_baseline:
-        hint = ge["oracle_outer_iters"] if ge else stats[-1]["outer_iters"]
+        # the FP64 GPU path runs the oracle's algorithm: its outer count at
+        # this tolerance stands for the oracle's
+        hint = compare.get("fp64_block_preconditioned", {}).get("outer_iters", stats[-1]["outer_iters"])
         res["cpu_baseline"] = cpu_baseline(case, hint)
     P.close()
     V.vie_context_destroy(ctx)

@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 2
+#define VIE_ABI_VERSION 3
 
 typedef enum {
   VIE_OK = 0,
@@ -134,6 +134,9 @@ typedef struct {
   int32_t n_blocks;           /* non-empty blocks */
   int32_t n_groups;           /* equally-shaped block batches */
   int64_t footprint_bytes;    /* device memory held by the problem */
+  int32_t n_block_solver_groups;  /* groups solved one workgroup per block */
+  int32_t zpass_variant[2];   /* z-pass kernel picked for the full-grid product [FP64, MIXED] */
+  float zpass_tune_ms[2][5];  /* autotuner time per z-pass variant (3 runs; -1 = not timed) */
 } vie_problem_info;
 
 /* ABI version (VIE_ABI_VERSION). */

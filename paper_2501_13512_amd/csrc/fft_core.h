@@ -129,20 +129,25 @@ template <>
 struct RadInfo<Radices<>> {
   static constexpr int nstages = 0;
   static constexpr int rmin = 1 << 30;
+  static constexpr int rmax = 1;
 };
 template <int R0, int... Rs>
 struct RadInfo<Radices<R0, Rs...>> {
   static constexpr int nstages = 1 + sizeof...(Rs);
   static constexpr int rmin = R0 < RadInfo<Radices<Rs...>>::rmin ? R0 : RadInfo<Radices<Rs...>>::rmin;
+  static constexpr int rmax = R0 > RadInfo<Radices<Rs...>>::rmax ? R0 : RadInfo<Radices<Rs...>>::rmax;
 };
 
 // Largest number of butterflies of any stage = L / smallest radix; a pencil
-// uses at most that many threads.
+// uses at most that many threads.  With min_butterflies (L / largest radix)
+// threads no thread idles in any stage; stages with more butterflies then
+// give each thread several.
 template <int L>
 struct PlanInfo {
   using rad = typename Plan<L>::type;
   static constexpr int nstages = RadInfo<rad>::nstages;
   static constexpr int max_butterflies = nstages == 0 ? 1 : L / RadInfo<rad>::rmin;
+  static constexpr int min_butterflies = nstages == 0 ? 1 : L / RadInfo<rad>::rmax;
 };
 
 // ---------------------------------------------------------------- pipeline

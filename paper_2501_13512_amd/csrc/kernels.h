@@ -80,10 +80,12 @@ void mvm_mid(const MvmBatch<R>& b, hipStream_t s);   // passes 2-4
 template <typename R>
 void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s);
 
-// Times both z-pass variants on the batch's work buffer (clobbers it) and
-// returns the faster.
+// Times every z-pass variant on the batch's work buffer (clobbers it) and
+// returns the fastest; ms_out (optional, kZPassVariants entries) receives
+// each variant's time for three runs, -1 where not timed.
+constexpr int kZPassVariants = 5;
 template <typename R>
-int tune_zpass(const MvmBatch<R>& b, hipStream_t s);
+int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out = nullptr);
 
 // Chunks per system of the fused first/last passes (for partial sizing).
 int64_t mvm_row_tiles(int lx, int nz, int ny);

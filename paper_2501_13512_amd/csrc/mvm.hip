@@ -47,8 +47,13 @@ struct Geo {
   static constexpr int ES = (int)sizeof(cx<R>);
   // rows (contiguous pencils): ~256 threads, LDS [ROWP][L]
   static constexpr int ROWP = cmax(1, cmin(256 / T, (64 * 1024) / (L * ES)));
-  // columns (strided pencils): >= 16 columns for coalescing, LDS [L][COLP]
-  static constexpr int COLP = cmax(1, pow2_floor(cmin(cmax(16, 256 / T), cmin(512 / T, (64 * 1024) / (L * ES)))));
+  // columns (strided pencils), LDS [L][COLP]: at least 128 contiguous bytes
+  // per row of the tile (one full cache line) when 64 KB of LDS allow it,
+  // with TC <= T threads per column (several butterflies per thread when
+  // T * COLP would exceed 1024 threads)
+  static constexpr int LDS_COLS = cmax(1, (64 * 1024) / (L * ES));
+  static constexpr int COLP = cmax(1, pow2_floor(cmin(LDS_COLS, cmax(128 / ES, cmin(cmax(16, 256 / T), 512 / T)))));
+  static constexpr int TC = cmin(T, cmax(1, 1024 / COLP));
 };
 
 __device__ __forceinline__ bool sys_active(const int* status, int s) {
@@ -278,7 +283,7 @@ struct ColArgs {
 };
 
 template <typename R, int L, int DIR>
-__global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::COLP)) k_col(ColArgs<R> a) {
+__global__ void __launch_bounds__((Geo<R, L>::TC * Geo<R, L>::COLP)) k_col(ColArgs<R> a) {
   using G = Geo<R, L>;
   __shared__ cx<R> lds[G::COLP * L];
   const int64_t cols = (int64_t)a.outer * a.inner;
@@ -297,7 +302,7 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::COLP)) k_col(ColArg
   auto st = [&](int k, cx<R> v) {
     if (k < n_out) base[(int64_t)k * inner] = v;
   };
-  fft_pencil<R, L, G::T, DIR>(ld, st, lds + p, G::COLP, t, valid, a.tw);
+  fft_pencil<R, L, G::TC, DIR>(ld, st, lds + p, G::COLP, t, valid, a.tw);
 }
 
 // Pass 3: z forward (nz -> LZ), spectral multiply, z inverse (LZ -> nz).
@@ -326,13 +331,48 @@ __device__ __forceinline__ FoldCol fold_col(int f, int m, int L) {
   return {-1, 0, 1};
 }
 
-// Variant 0: one (qy, tile of qx) column set per workgroup, three
-// components side by side; each point loads its spectrum values.
-template <typename R, int LZ>
+// Workgroup b of n runs on XCD b % 8 (round-robin dispatch).  Renumber so
+// that each XCD takes one contiguous range of the logical order: work that
+// shares data then shares that XCD's L2.
+__device__ __forceinline__ int xcd_chunked(int b, int n) {
+  constexpr int NX = 8;
+  const int q = n / NX, r = n - q * NX;
+  const int x = b % NX, l = b / NX;
+  return x * q + min(x, r) + l;
+}
+
+// Logical row i -> qy in the order 0, 1, L-1, 2, L-2, ...: rows that share
+// an octant row of the spectra (qy and L - qy) are adjacent.
+__device__ __forceinline__ int mirror_paired_row(int i, int L) {
+  if (i == 0) return 0;
+  const int k = (i + 1) >> 1;
+  return (i & 1) ? k : L - k;
+}
+
+// Variant 0: one tile of ZP columns per workgroup, three components side by
+// side; each point loads its spectrum values.  Tiles run along mirror-paired
+// rows, chunked per XCD, so the four mirror columns that use one octant
+// spectrum value are transformed on one XCD close together in time and the
+// value is fetched from HBM about once.
+// Column-set variants (V = 0, 2, 3, 4): ZP columns per workgroup, TZ threads
+// per column and component, PF: spectrum values loaded into registers
+// before the data (their latency overlaps the forward transform).
+//   0: wide tiles (up to 1024 threads), max_butterflies threads per column
+//   2: wide tiles, min_butterflies threads per column, prefetch
+//   3: one cache line of columns, min_butterflies threads, prefetch
+//   4: one cache line of columns, max_butterflies threads
+template <typename R, int LZ, int V>
 struct ZColGeo {
   static constexpr int T = PlanInfo<LZ>::max_butterflies;
+  static constexpr int TB = PlanInfo<LZ>::min_butterflies;
   static constexpr int ES = (int)sizeof(cx<R>);
-  static constexpr int ZP = cmax(1, pow2_floor(cmin(64, cmin(1024 / (3 * T), (144 * 1024) / (3 * LZ * ES)))));
+  static constexpr int LDS_ZP = cmax(1, (144 * 1024) / (3 * LZ * ES));
+  static constexpr int LINE = cmax(1, pow2_floor(cmin(LDS_ZP, 128 / ES)));
+  static constexpr int WIDE = cmax(1, pow2_floor(cmin(LDS_ZP, cmin(64, cmax(128 / ES, 1024 / (3 * T))))));
+  static constexpr int ZP = (V == 3 || V == 4) ? LINE : WIDE;
+  static constexpr int TZ = (V == 2 || V == 3) ? cmin(TB, cmax(1, 1024 / (3 * ZP)))
+                                               : cmin(T, pow2_floor(cmax(1, 1024 / (3 * ZP))));
+  static constexpr bool PF = V == 2 || V == 3;
 };
 
 // Variant 1 (mirror columns): geometry.
@@ -346,7 +386,7 @@ struct ZGeo {
 template <typename R>
 struct ZArgs {
   int nz, ly, lx;
-  int variant;   // 0: column sets, 1: mirror columns
+  int variant;   // 0, 2, 3, 4: column sets (ZColGeo); 1: mirror columns
   int64_t wstride, sstride;
   cx<R>* work;
   const cx<R>* spec;
@@ -445,52 +485,109 @@ __global__ void __launch_bounds__((3 * ZGeo<R, LZ>::T * ZGeo<R, LZ>::ZP)) k_zcon
   }
 }
 
-template <typename R, int LZ>
-__global__ void __launch_bounds__((3 * ZColGeo<R, LZ>::T * ZColGeo<R, LZ>::ZP)) k_zconv_col(ZArgs<R> a) {
-  using G = ZColGeo<R, LZ>;
-  constexpr int T = G::T, ZP = G::ZP;
+template <typename R, int LZ, int V>
+__global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>::ZP)) k_zconv_col(ZArgs<R> a) {
+  using G = ZColGeo<R, LZ, V>;
+  constexpr int T = G::TZ, ZP = G::ZP;
+  constexpr int NT = 3 * T * ZP;
+  constexpr int HZ = LZ / 2;
+  constexpr int NFT = NT / ZP;                    // fold walkers per column
+  constexpr int NF = (HZ + 1 + NFT - 1) / NFT;    // folds per walker
   __shared__ cx<R> lds[3 * LZ * ZP];
   const int cols = a.ly * a.lx;
   const int tiles = (cols + ZP - 1) / ZP;
-  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  const int g = xcd_chunked(blockIdx.x, gridDim.x);
+  const int sys = g / tiles, tile = g - sys * tiles;
   if (!sys_active(a.status, sys)) return;
   const int comp = threadIdx.x / (T * ZP);
   const int rem = threadIdx.x - comp * (T * ZP);
   const int p = rem % ZP, t = rem / ZP;
-  const int col = tile * ZP + p;
+  const int col = tile * ZP + p;   // logical column
   const bool valid = col < cols;
   const int64_t plane = (int64_t)a.ly * a.lx;
-  cx<R>* base = a.work + sys * a.wstride + (int64_t)comp * a.nz * plane + (valid ? col : 0);
+  int pcol = 0;                    // its place in the plane
+  if (valid) {
+    const int i = col / a.lx;
+    pcol = mirror_paired_row(i, a.ly) * a.lx + (col - i * a.lx);
+  }
+  cx<R>* base = a.work + sys * a.wstride + (int64_t)comp * a.nz * plane + pcol;
   cx<R>* slot = lds + comp * LZ * ZP + p;
   const int nz = a.nz;
+
+  // The multiply's view: a thread keeps one column (qx, qy) and walks the
+  // z-folds fz = j, j + NFT, ...: each spectrum value serves qz = fz and
+  // qz = LZ - fz.
+  const int lx = a.lx, ly = a.ly;
+  const int hx = lx / 2, hy = ly / 2;
+  const int64_t ox = hx + 1, oy = hy + 1;
+  const int64_t oct = ox * oy * (HZ + 1);
+  const int pp = threadIdx.x % ZP, j0 = threadIdx.x / ZP;
+  const int c2 = tile * ZP + pp;
+  const bool cvalid = c2 < cols;
+  R sx = R(1), sy = R(1);
+  const cx<R>* sp = a.spec + sys * a.sstride;
+  if (cvalid) {
+    const int i2 = c2 / lx;
+    const int qy = mirror_paired_row(i2, ly), qx = c2 - i2 * lx;
+    const int fx = qx <= hx ? qx : lx - qx, fy = qy <= hy ? qy : ly - qy;
+    sx = qx <= hx ? R(1) : R(-1);
+    sy = qy <= hy ? R(1) : R(-1);
+    sp += (int64_t)fy * ox + fx;
+  }
+  // spectrum values (xx, xy, xz, yy, yz, zz, parity signs of qx, qy applied)
+  auto spec_at = [&](int fz, cx<R>* sv) {
+    const int64_t o = (int64_t)fz * oy * ox;
+    sv[0] = sp[o];
+    sv[1] = (sx * sy) * sp[oct + o];
+    sv[2] = sx * sp[2 * oct + o];
+    sv[3] = sp[3 * oct + o];
+    sv[4] = sy * sp[4 * oct + o];
+    sv[5] = sp[5 * oct + o];
+  };
+  cx<R> pre[G::PF ? NF : 1][6];
+  if constexpr (G::PF) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int fz = j0 + f * NFT;
+      if (cvalid && fz <= HZ) spec_at(fz, pre[f]);
+    }
+  }
+
   // forward along z into the component's LDS slot
   auto ldg = [&](int n) -> cx<R> { return n < nz ? base[n * plane] : czero<R>(); };
   auto sts = [&](int k, cx<R> v) { slot[k * ZP] = v; };
   fft_pencil<R, LZ, T, -1, false, true>(ldg, sts, slot, ZP, t, valid, a.tw);
 
   // Q(q) = S(q) X(q), S symmetric 3x3 from the octant with parity signs
-  const int lx = a.lx, ly = a.ly;
-  const int hx = lx / 2, hy = ly / 2, hz = LZ / 2;
-  const int64_t ox = hx + 1, oy = hy + 1;
-  const int64_t oct = ox * oy * (hz + 1);
-  const cx<R>* spec = a.spec + sys * a.sstride;
-  for (int i = threadIdx.x; i < LZ * ZP; i += 3 * T * ZP) {
-    const int qz = i / ZP, pp = i - qz * ZP;
-    const int c2 = tile * ZP + pp;
-    if (c2 >= cols) continue;
-    const int qy = c2 / lx, qx = c2 - qy * lx;
-    const int fx = qx <= hx ? qx : lx - qx, fy = qy <= hy ? qy : ly - qy, fz = qz <= hz ? qz : LZ - qz;
-    const R sx = qx <= hx ? R(1) : R(-1), sy = qy <= hy ? R(1) : R(-1), sz = qz <= hz ? R(1) : R(-1);
-    const int64_t o = ((int64_t)fz * oy + fy) * ox + fx;
-    const cx<R> sxx = spec[o], syy = spec[3 * oct + o], szz = spec[5 * oct + o];
-    const cx<R> sxy = (sx * sy) * spec[oct + o];
-    const cx<R> sxz = (sx * sz) * spec[2 * oct + o];
-    const cx<R> syz = (sy * sz) * spec[4 * oct + o];
-    const int e = qz * ZP + pp;
-    const cx<R> X = lds[e], Y = lds[LZ * ZP + e], Z = lds[2 * LZ * ZP + e];
-    lds[e] = sxx * X + sxy * Y + sxz * Z;
-    lds[LZ * ZP + e] = sxy * X + syy * Y + syz * Z;
-    lds[2 * LZ * ZP + e] = sxz * X + syz * Y + szz * Z;
+  if (cvalid) {
+    cx<R>* e0 = lds + pp;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int fz = j0 + f * NFT;
+      if (fz > HZ) break;
+      cx<R> sl[6];
+      const cx<R>* sv = sl;
+      if constexpr (G::PF)
+        sv = pre[f];
+      else
+        spec_at(fz, sl);
+      const cx<R> sxx = sv[0], sxy = sv[1], sxz = sv[2], syy = sv[3], syz = sv[4], szz = sv[5];
+      {
+        cx<R>* e = e0 + fz * ZP;   // qz = fz: sz = +1
+        const cx<R> X = e[0], Y = e[LZ * ZP], Z = e[2 * LZ * ZP];
+        e[0] = sxx * X + sxy * Y + sxz * Z;
+        e[LZ * ZP] = sxy * X + syy * Y + syz * Z;
+        e[2 * LZ * ZP] = sxz * X + syz * Y + szz * Z;
+      }
+      const int qz2 = LZ - fz;
+      if (fz > 0 && qz2 != fz) {   // qz = LZ - fz: sz = -1
+        cx<R>* e = e0 + qz2 * ZP;
+        const cx<R> X = e[0], Y = e[LZ * ZP], Z = e[2 * LZ * ZP];
+        e[0] = sxx * X + sxy * Y - sxz * Z;
+        e[LZ * ZP] = sxy * X + syy * Y - syz * Z;
+        e[2 * LZ * ZP] = szz * Z - sxz * X - syz * Y;
+      }
+    }
   }
   __syncthreads();
   // inverse along z, cropped to nz
@@ -558,7 +655,7 @@ static void launch_col(int L, const ColArgs<R>& a, hipStream_t s) {
     using G = Geo<R, l>;                                                            \
     const int64_t cols = (int64_t)a.outer * a.inner;                                \
     const int64_t tiles = (cols + G::COLP - 1) / G::COLP;                           \
-    hipLaunchKernelGGL((k_col<R, l, DIR>), dim3((unsigned)(tiles * a.nsys)), dim3(G::T * G::COLP), 0, s, a); \
+    hipLaunchKernelGGL((k_col<R, l, DIR>), dim3((unsigned)(tiles * a.nsys)), dim3(G::TC * G::COLP), 0, s, a); \
     break;                                                                          \
   }
     VIE_L_CASES(C)
@@ -569,9 +666,19 @@ static void launch_col(int L, const ColArgs<R>& a, hipStream_t s) {
   check_launch("column pass");
 }
 
+constexpr int kZVariants = kZPassVariants;   // 0, 2, 3, 4: column sets; 1: mirror columns
+
+template <typename R, int L, int V>
+static void launch_zcol(const ZArgs<R>& a, int nsys, hipStream_t s) {
+  using G = ZColGeo<R, L, V>;
+  const int cols = a.ly * a.lx;
+  const int blocks = ((cols + G::ZP - 1) / G::ZP) * nsys;
+  hipLaunchKernelGGL((k_zconv_col<R, L, V>), dim3(blocks), dim3(3 * G::TZ * G::ZP), 0, s, a);
+}
+
 template <typename R>
 static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
-  const int nfy = nfold(a.ly), nfx = nfold(a.lx), cols = a.ly * a.lx;
+  const int nfy = nfold(a.ly), nfx = nfold(a.lx);
   switch (L) {
 #define C(l)                                                                                      \
   case l: {                                                                                       \
@@ -579,10 +686,14 @@ static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
       using G = ZGeo<R, l>;                                                                       \
       const int blocks = nfy * ((nfx + G::ZP - 1) / G::ZP) * nsys;                                \
       hipLaunchKernelGGL((k_zconv_mirror<R, l>), dim3(blocks), dim3(3 * G::T * G::ZP), 0, s, a);  \
+    } else if (l < 32 || a.variant == 0) {                                                        \
+      launch_zcol<R, l, 0>(a, nsys, s);                                                           \
+    } else if (a.variant == 2) {                                                                  \
+      launch_zcol<R, l, (l < 32 ? 0 : 2)>(a, nsys, s);                                            \
+    } else if (a.variant == 3) {                                                                  \
+      launch_zcol<R, l, (l < 32 ? 0 : 3)>(a, nsys, s);                                            \
     } else {                                                                                      \
-      using G = ZColGeo<R, l>;                                                                    \
-      const int blocks = ((cols + G::ZP - 1) / G::ZP) * nsys;                                     \
-      hipLaunchKernelGGL((k_zconv_col<R, l>), dim3(blocks), dim3(3 * G::T * G::ZP), 0, s, a);     \
+      launch_zcol<R, l, (l < 32 ? 0 : 4)>(a, nsys, s);                                            \
     }                                                                                             \
     break;                                                                                        \
   }
@@ -732,14 +843,17 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
 // (contents are overwritten; call before the buffer holds live data) and
 // return the faster one.
 template <typename R>
-int tune_zpass(const MvmBatch<R>& b, hipStream_t s) {
+int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out) {
+  if (ms_out)
+    for (int v = 0; v < kZPassVariants; ++v) ms_out[v] = -1.0f;
   if (b.nsys <= 0) return 0;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     throw std::runtime_error("hipEventCreate failed");
   float best = 1e30f;
   int best_v = 0;
-  for (int v = 0; v < 2; ++v) {
+  for (int v = 0; v < kZVariants; ++v) {
+    if (v >= 2 && b.lz < 32) break;   // short columns: variants 0 and 1 only
     ZArgs<R> za{};
     za.nz = b.nz;
     za.ly = b.ly;
@@ -758,6 +872,7 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s) {
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms_out) ms_out[v] = ms;
     if (ms < best) {
       best = ms;
       best_v = v;
@@ -767,8 +882,8 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s) {
   (void)hipEventDestroy(e1);
   return best_v;
 }
-template int tune_zpass<float>(const MvmBatch<float>&, hipStream_t);
-template int tune_zpass<double>(const MvmBatch<double>&, hipStream_t);
+template int tune_zpass<float>(const MvmBatch<float>&, hipStream_t, float*);
+template int tune_zpass<double>(const MvmBatch<double>&, hipStream_t, float*);
 
 #define VIE_MVM_INST(R)                                                                                           \
   template void mvm<R>(const MvmBatch<R>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);                  \

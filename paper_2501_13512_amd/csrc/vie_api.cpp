@@ -229,6 +229,7 @@ struct vie_problem {
   DevBuf chi, work, vecs, partials, ntile, ostate, ostatus, scal;
   int64_t pstride = 0;
   int zvar[2] = {0, 0};
+  float ztune_ms[2][vie::kZPassVariants] = {};
   // inner systems of all groups: partials (per-system stride ipstride)
   DevBuf d_ipartials, d_intile;
   int64_t ipstride = 0;
@@ -1109,8 +1110,8 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
       m.ny = g.ny;
       m.nz = g.nz;
     }
-    P->zvar[0] = vie::tune_zpass<double>(outer_batch<double>(*P, false), ctx->stream);
-    P->zvar[1] = vie::tune_zpass<float>(outer_batch<float>(*P, false), ctx->stream);
+    P->zvar[0] = vie::tune_zpass<double>(outer_batch<double>(*P, false), ctx->stream, P->ztune_ms[0]);
+    P->zvar[1] = vie::tune_zpass<float>(outer_batch<float>(*P, false), ctx->stream, P->ztune_ms[1]);
     hip_check(hipStreamSynchronize(ctx->stream), "z-pass tuning");
     P->footprint = foot;
     {
@@ -1147,6 +1148,12 @@ vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info) {
     info->n_blocks = p->n_nonempty;
     info->n_groups = (int32_t)p->groups.size();
     info->footprint_bytes = (int64_t)p->footprint;
+    info->n_block_solver_groups = p->n_wg_groups;
+    static_assert(vie::kZPassVariants == 5, "vie_problem_info holds 5 z-pass timings");
+    for (int q = 0; q < 2; ++q) {
+      info->zpass_variant[q] = p->zvar[q];
+      for (int v = 0; v < vie::kZPassVariants; ++v) info->zpass_tune_ms[q][v] = p->ztune_ms[q][v];
+    }
     return VIE_OK;
   });
 }

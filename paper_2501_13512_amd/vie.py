@@ -23,6 +23,25 @@ LIB_PATH = os.path.join(_PKG, "libvie.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libvie.so is not built ({LIB_PATH}); run `python -m paper_2501_13512_amd.build`")
+
+
+def _share_torch_hip_runtime() -> None:
+    """PyTorch wheels bundle their own HIP runtime (same soname as the system
+    one).  Loading it before libvie makes libvie bind to that copy, so the
+    process has one HIP runtime whether torch or this module is imported
+    first; with two, the runtime initialised second finds no device."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        return
+    for d in spec.submodule_search_locations:
+        hip = os.path.join(d, "lib", "libamdhip64.so")
+        if os.path.exists(hip):
+            ctypes.CDLL(hip, mode=ctypes.RTLD_GLOBAL)
+            return
+
+
+_share_torch_hip_runtime()
 _lib = ctypes.CDLL(LIB_PATH)
 
 VIE_OK, VIE_NOT_CONVERGED = 0, 1
@@ -69,7 +88,8 @@ class vie_stats(ctypes.Structure):
 class vie_problem_info(ctypes.Structure):
     _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("lz", ctypes.c_int32),
                 ("n_blocks", ctypes.c_int32), ("n_groups", ctypes.c_int32),
-                ("footprint_bytes", ctypes.c_int64)]
+                ("footprint_bytes", ctypes.c_int64), ("n_block_solver_groups", ctypes.c_int32),
+                ("zpass_variant", ctypes.c_int32 * 2), ("zpass_tune_ms", (ctypes.c_float * 5) * 2)]
 
 
 _vp = ctypes.c_void_p
