@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 3
+#define VIE_ABI_VERSION 4
 
 typedef enum {
   VIE_OK = 0,
@@ -70,11 +70,13 @@ typedef enum {
   VIE_EBREAKDOWN = -4,     /* BiCGSTAB breakdown (rho, <rhat,v> or <t,t> = 0, or non-finite); last iterate written */
   VIE_EBUSY = -5,          /* resource budget exceeded */
   VIE_ECANCELLED = -6,
-  VIE_EINTERNAL = -7
+  VIE_EINTERNAL = -7,
+  VIE_ETIMEDOUT = -8          /* vie_wait: not finished within the timeout (ticket still valid) */
 } vie_status;
 
 typedef struct vie_context vie_context;
 typedef struct vie_problem vie_problem;
+typedef struct vie_request* vie_ticket;
 
 /* Uniform grid (Sec. II-A: hexahedral mesh, staircase geometry). */
 typedef struct {
@@ -149,6 +151,9 @@ const char* vie_last_error(void);
  * context may hold for problems (0 = no limit); problem creation beyond it
  * returns VIE_EBUSY.  Returns VIE_EDEVICE when no such HIP device exists. */
 vie_status vie_context_create(int32_t device, size_t hbm_budget_bytes, vie_context** out);
+/* Stops the context's server (queued requests are cancelled, running ones
+ * stop after their current outer step); VIE_EBUSY, with nothing destroyed,
+ * while tickets are outstanding (not yet passed to vie_wait). */
 vie_status vie_context_destroy(vie_context* ctx);
 
 /* Set up a problem (Sec. II-A and II-B): uploads 1/chi, computes (or reuses
@@ -208,6 +213,54 @@ vie_status vie_solve(vie_problem* p, const double* e_inc, const vie_opts* opts, 
 /* Same with device buffers on `stream` (inputs already in HBM). */
 vie_status vie_solve_device(vie_problem* p, const void* e_inc_dev, const vie_opts* opts, void* e_tot_dev,
                             void* pol_dev, vie_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------ serving
+ * A request queue per context: independent solves (any grid, wavelength,
+ * partition and options) are admitted in arrival order as solver slots and
+ * device memory free up, and run concurrently, each slot on its own HIP
+ * stream, each request in a problem of its own (created when admitted,
+ * destroyed when it finishes).  Green spectra and tuned kernel choices are
+ * cached in the context and shared by requests of the same shapes, so a
+ * request gives the same result alone or among others.  Results come back
+ * to host memory.
+ *
+ * Memory admission: a request is started only when the context's memory in
+ * use (problems created by the caller + requests running) plus the
+ * request's footprint (vie_footprint) fits the context's hbm_budget_bytes
+ * (0 = no limit); until then it waits, in order, in the queue. */
+
+/* Start the server of ctx with `slots` concurrent solves (1..64) and room for
+ * queue_cap waiting requests (>= 1).  Optional: the first vie_submit starts
+ * it with 4 slots and 1024 places.  VIE_EBUSY if it is already running. */
+vie_status vie_server_start(vie_context* ctx, int32_t slots, int32_t queue_cap);
+
+/* Device bytes a problem with these inputs would hold (vie_problem_create's
+ * arguments; spectra already cached in ctx are not counted), plus the
+ * transient set-up memory of spectra not yet cached. */
+vie_status vie_footprint(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
+                         int32_t n_blocks, size_t* bytes);
+
+/* Queue one solve: the arguments of vie_problem_create plus those of
+ * vie_solve (e_inc: 3*nvox complex; opts as vie_solve).  All host arrays are
+ * copied before the call returns.  *out receives a ticket, to be passed to
+ * vie_wait exactly once.  VIE_EINVAL on invalid input (or a footprint larger
+ * than the whole budget), VIE_EBUSY when the queue is full. */
+vie_status vie_submit(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
+                      int32_t n_blocks, const double* e_inc, const vie_opts* opts, vie_ticket* out);
+
+/* Wait up to timeout_s seconds (< 0: no limit) for the request.  When it has
+ * finished: writes e_tot_out (3*nvox complex, may be NULL), stats (may be
+ * NULL) and times (may be NULL: seconds queued, in set-up, in the solve),
+ * releases the ticket and returns the request's status (that of vie_solve;
+ * VIE_ECANCELLED if cancelled).  VIE_ETIMEDOUT if still queued or running:
+ * nothing written, the ticket stays valid. */
+vie_status vie_wait(vie_ticket t, double timeout_s, double* e_tot_out, vie_stats* stats, double* times);
+
+/* Cancel a request: a queued one is dropped, a running one stops after its
+ * current outer step.  The ticket must still be passed to vie_wait (which
+ * then returns VIE_ECANCELLED, or the status of a request that had already
+ * finished). */
+vie_status vie_cancel(vie_ticket t);
 
 #ifdef __cplusplus
 }

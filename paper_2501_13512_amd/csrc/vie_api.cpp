@@ -4,15 +4,21 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -26,6 +32,7 @@ using vie::MvmBatch;
 namespace {
 
 thread_local std::string g_last_error;
+std::string vie_last_error_str() { return g_last_error; }
 
 struct VieError : std::runtime_error {
   vie_status code;
@@ -156,6 +163,8 @@ bool is_finite(double v) { return std::isfinite(v); }
 
 }  // namespace
 
+struct Server;
+
 struct vie_context {
   int device = 0;
   size_t budget = 0;
@@ -166,12 +175,17 @@ struct vie_context {
   vie::TwiddleSet<float> tws32{};
   std::mutex mu;
   std::map<SpecKey, std::weak_ptr<Spectra>> cache;
+  size_t reserved = 0;   // bytes reserved by requests admitted to the server
+  std::map<std::array<int, 8>, std::pair<int, std::array<float, vie::kZPassVariants>>> ztune;
+  std::unique_ptr<Server> server;
+  std::mutex server_mu;
+  ~vie_context();
 };
 
 namespace {
 
 std::shared_ptr<Spectra> get_spectra(vie_context* ctx, int lx, int ly, int lz, double dx, double dy, double dz,
-                                     double k0) {
+                                     double k0, hipStream_t s) {
   SpecKey key{lx, ly, lz, dx, dy, dz, k0};
   {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -187,10 +201,12 @@ std::shared_ptr<Spectra> get_spectra(vie_context* ctx, int lx, int ly, int lz, d
   // embed with the largest box the lengths support: a box of n <= (L+1)/2
   // voxels touches only offsets |m| <= n - 1, all of which are present.
   vie::green_spectra((lx + 1) / 2, (ly + 1) / 2, (lz + 1) / 2, lx, ly, lz, dx, dy, dz, k0, scratch.as<c128>(),
-                     sp->s64.as<c128>(), sp->s32.as<c64>(), ctx->tws64, ctx->stream);
-  hip_check(hipStreamSynchronize(ctx->stream), "spectra");
+                     sp->s64.as<c128>(), sp->s32.as<c64>(), ctx->tws64, s);
+  hip_check(hipStreamSynchronize(s), "spectra");
   std::lock_guard<std::mutex> g(ctx->mu);
-  ctx->cache[key] = sp;
+  auto& slot = ctx->cache[key];
+  if (auto other = slot.lock()) return other;   // built concurrently by another thread
+  slot = sp;
   return sp;
 }
 
@@ -255,6 +271,7 @@ struct vie_problem {
   hipEvent_t ev[2][kRing] = {};
   std::mutex mu;
   size_t footprint = 0;
+  const std::atomic<bool>* cancel = nullptr;   // set by the server: stop after the current outer step
 
   ~vie_problem() {
     for (auto& gp : inner_graph)
@@ -663,6 +680,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
     }
     const long t = poll.push(P.ostatus.as<int>());
     if (t - lag >= 0 && poll.wait(t - lag) != vie::ST_ACTIVE) break;
+    if (P.cancel && P.cancel->load(std::memory_order_relaxed)) break;
   }
   hip_check(hipStreamSynchronize(s), "solve");
   RunResult r{};
@@ -683,7 +701,7 @@ double true_relres(vie_problem& P, const c128* rhs, const c128* x, c128* tmp_ax,
   return nb > 0 ? std::sqrt(r2) / nb : 0.0;
 }
 
-void validate_opts(const vie_opts* o, const vie_problem* p) {
+void validate_opts(const vie_opts* o, bool has_blocks) {
   if (!o) fail(VIE_EINVAL, "opts is NULL");
   if (!(o->tol_outer >= 0) || !is_finite(o->tol_outer)) fail(VIE_EINVAL, "tol_outer must be finite and >= 0");
   if (o->maxit_outer < 0 || o->maxit_outer > 1000000) fail(VIE_EINVAL, "maxit_outer out of range");
@@ -692,7 +710,7 @@ void validate_opts(const vie_opts* o, const vie_problem* p) {
   if (o->max_refine < 0 || o->max_refine > 100) fail(VIE_EINVAL, "max_refine out of range");
   if (o->flags & ~(VIE_FLAG_NO_GRAPHS | VIE_FLAG_NO_BLOCK_KERNEL)) fail(VIE_EINVAL, "unknown flags");
   if (o->precondition) {
-    if (p->groups.empty()) fail(VIE_EINVAL, "precondition requested but the problem has no blocks");
+    if (!has_blocks) fail(VIE_EINVAL, "precondition requested but the problem has no blocks");
     if (!(o->tol_inner >= 0) || !is_finite(o->tol_inner)) fail(VIE_EINVAL, "tol_inner must be finite and >= 0");
     if (o->maxit_inner < 1 || o->maxit_inner > 1000000) fail(VIE_EINVAL, "maxit_inner out of range");
   }
@@ -730,7 +748,8 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     const double nb = rr.st.nb;
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
     // iterative refinement: solve A d = b - A x with FP32 products, x += d
-    while (rr.status != vie::ST_BREAKDOWN && relres_true > o->tol_outer && refine < o->max_refine && nb > 0) {
+    while (rr.status != vie::ST_BREAKDOWN && relres_true > o->tol_outer && refine < o->max_refine && nb > 0 &&
+           !(P.cancel && P.cancel->load())) {
       const double tol_c = std::min(0.5, o->tol_outer / relres_true);
       RunResult rc = run_bicgstab<float>(P, v[V_TMP2], v[V_TMP1], tol_c, o->maxit_outer, prec, o->tol_inner,
                                          o->maxit_inner, o->poll_lag, hist, hist_cap, graphs, wg, s);
@@ -764,6 +783,10 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     }
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  if (P.cancel && P.cancel->load()) {
+    g_last_error = "request cancelled";
+    return VIE_ECANCELLED;
+  }
   if (rr.status == vie::ST_BREAKDOWN) {
     g_last_error = "BiCGSTAB breakdown (last iterate written)";
     return VIE_EBREAKDOWN;
@@ -779,7 +802,514 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   return VIE_NOT_CONVERGED;
 }
 
+
+// ------------------------------------------------------------------ problem set-up
+// Host-side plan of a problem: 1/chi, block ids, the blocks' bounding boxes
+// and their shape groups.  Its device footprint is known before anything
+// is allocated (admission by memory), and build_problem() turns it into a
+// vie_problem with set-up work on a caller-chosen stream.
+struct GroupPlan {
+  int lx, ly, lz;
+  std::vector<int> blocks;
+  bool wg = false;
+  int bx = 1, by = 1, bz = 1;
+};
+
+struct ProblemPlan {
+  vie_grid g{};
+  int64_t nv = 0;
+  int lx = 0, ly = 0, lz = 0;
+  double k0 = 0;
+  std::vector<c128> chi;      // 1/chi, 0 on vacuum
+  bool has_blocks = false;
+  int n_blocks = 0;
+  std::vector<int32_t> bid;   // -1 on vacuum
+  std::vector<int> lo, hi;    // block bounding boxes [3 * n_blocks]
+  std::vector<int64_t> cnt;   // voxels per block
+  std::vector<GroupPlan> groups;   // batched groups first, then block-solver groups
+};
+
+ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* block_id, int32_t n_blocks) {
+  if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > 256 || g.ny > 256 || g.nz > 256)
+    fail(VIE_EINVAL, "grid sizes must be in [1, 256]");
+  if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !(g.wavelength > 0) || !is_finite(g.dx) || !is_finite(g.dy) ||
+      !is_finite(g.dz) || !is_finite(g.wavelength))
+    fail(VIE_EINVAL, "spacing and wavelength must be finite and > 0");
+  if (block_id && n_blocks < 1) fail(VIE_EINVAL, "n_blocks must be >= 1 when block_id is given");
+  if (n_blocks < 0) fail(VIE_EINVAL, "n_blocks must be >= 0");
+  ProblemPlan pl;
+  pl.g = g;
+  const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+  pl.nv = nv;
+  // 1/chi on the host
+  pl.chi.resize(nv);
+  for (int64_t i = 0; i < nv; ++i) {
+    const double er = eps_r[2 * i], ei = eps_r[2 * i + 1];
+    if (!is_finite(er) || !is_finite(ei)) fail(VIE_EINVAL, "eps_r has non-finite entries");
+    if (er == 1.0 && ei == 0.0) {
+      pl.chi[i] = mk<double>(0.0, 0.0);
+    } else {
+      const std::complex<double> c = 1.0 / (std::complex<double>(er, ei) - 1.0);
+      pl.chi[i] = mk<double>(c.real(), c.imag());
+    }
+  }
+  pl.lx = vie::smallest_fft_length(2 * g.nx - 1);
+  pl.ly = vie::smallest_fft_length(2 * g.ny - 1);
+  pl.lz = vie::smallest_fft_length(2 * g.nz - 1);
+  if (pl.lx < 0 || pl.ly < 0 || pl.lz < 0) fail(VIE_EINVAL, "grid too large for the compiled FFT lengths");
+  pl.k0 = 2.0 * M_PI / g.wavelength;
+  if (!block_id) return pl;
+  pl.has_blocks = true;
+  pl.n_blocks = n_blocks;
+  pl.bid.assign(nv, -1);
+  for (int64_t i = 0; i < nv; ++i) {
+    const bool vac = pl.chi[i].x == 0.0 && pl.chi[i].y == 0.0;
+    if (vac) continue;
+    const int32_t k = block_id[i];
+    if (k < 0 || k >= n_blocks) fail(VIE_EINVAL, "block id out of range on a scatterer voxel");
+    pl.bid[i] = k;
+  }
+  // tight bounding box of every block
+  auto& lo = pl.lo;
+  auto& hi = pl.hi;
+  auto& cnt = pl.cnt;
+  lo.assign(3 * n_blocks, 1 << 30);
+  hi.assign(3 * n_blocks, -1);
+  cnt.assign(n_blocks, 0);
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) {
+        const int k = pl.bid[((int64_t)z * g.ny + y) * g.nx + x];
+        if (k < 0) continue;
+        cnt[k]++;
+        const int c[3] = {x, y, z};
+        for (int a = 0; a < 3; ++a) {
+          lo[3 * k + a] = std::min(lo[3 * k + a], c[a]);
+          hi[3 * k + a] = std::max(hi[3 * k + a], c[a]);
+        }
+      }
+  // group blocks by circulant lengths of their bounding boxes
+  std::vector<GroupPlan> plans;
+  {
+    std::map<std::tuple<int, int, int>, std::vector<int>> bylen;
+    for (int k = 0; k < n_blocks; ++k) {
+      if (cnt[k] == 0) continue;
+      const int ex = hi[3 * k] - lo[3 * k] + 1, ey = hi[3 * k + 1] - lo[3 * k + 1] + 1,
+                ez = hi[3 * k + 2] - lo[3 * k + 2] + 1;
+      bylen[{vie::smallest_fft_length(2 * ex - 1), vie::smallest_fft_length(2 * ey - 1),
+             vie::smallest_fft_length(2 * ez - 1)}]
+          .push_back(k);
+    }
+    for (auto& kv : bylen) {
+      GroupPlan gp;
+      gp.lx = std::get<0>(kv.first);
+      gp.ly = std::get<1>(kv.first);
+      gp.lz = std::get<2>(kv.first);
+      gp.blocks = kv.second;
+      plans.push_back(std::move(gp));
+    }
+  }
+  // Shapes the one-workgroup block solver handles stay separate groups
+  // (one launch per group and application, whatever the group size).
+  std::vector<GroupPlan> wg_plans;
+  {
+    std::vector<GroupPlan> rest;
+    for (auto& gp : plans) {
+      int bz = 1;
+      for (int k : gp.blocks) bz = std::max(bz, hi[3 * k + 2] - lo[3 * k + 2] + 1);
+      gp.wg = vie::block_solver_supported(gp.lx, gp.ly, gp.lz, bz);
+      (gp.wg ? wg_plans : rest).push_back(std::move(gp));
+    }
+    plans = std::move(rest);
+  }
+  // Merge shape groups while it lowers the modelled cost of one inner
+  // iteration: a fixed per-group overhead (its kernel launches) plus
+  // work proportional to the padded transform volume of its systems.
+  // A merged group takes the largest lengths of both (a box of n <=
+  // (L+1)/2 voxels embeds in any longer L).
+  {
+    // ~11 launches of >= 5 us per group and step, against ~50 ps per padded
+    // point and step (two products and the vector updates) on MI355X
+    const double kGroupOverhead = 1.2e6;  // padded points per group-iteration overhead
+    auto cost = [&](int lx, int ly, int lz, size_t nsys) { return kGroupOverhead + (double)nsys * lx * ly * lz; };
+    for (;;) {
+      double best = 0;
+      int bi = -1, bj = -1;
+      for (size_t i = 0; i < plans.size(); ++i)
+        for (size_t j = i + 1; j < plans.size(); ++j) {
+          const GroupPlan &a = plans[i], &b = plans[j];
+          const int lx = std::max(a.lx, b.lx), ly = std::max(a.ly, b.ly), lz = std::max(a.lz, b.lz);
+          const double d = cost(lx, ly, lz, a.blocks.size() + b.blocks.size()) -
+                           cost(a.lx, a.ly, a.lz, a.blocks.size()) - cost(b.lx, b.ly, b.lz, b.blocks.size());
+          if (d < best) {
+            best = d;
+            bi = (int)i;
+            bj = (int)j;
+          }
+        }
+      if (bi < 0) break;
+      GroupPlan& a = plans[bi];
+      GroupPlan& b = plans[bj];
+      a.lx = std::max(a.lx, b.lx);
+      a.ly = std::max(a.ly, b.ly);
+      a.lz = std::max(a.lz, b.lz);
+      a.blocks.insert(a.blocks.end(), b.blocks.begin(), b.blocks.end());
+      std::sort(a.blocks.begin(), a.blocks.end());
+      plans.erase(plans.begin() + bj);
+    }
+  }
+  for (auto& gp : wg_plans) plans.push_back(std::move(gp));
+  for (auto& gp : plans)
+    for (int k : gp.blocks) {
+      gp.bx = std::max(gp.bx, hi[3 * k] - lo[3 * k] + 1);
+      gp.by = std::max(gp.by, hi[3 * k + 1] - lo[3 * k + 1] + 1);
+      gp.bz = std::max(gp.bz, hi[3 * k + 2] - lo[3 * k + 2] + 1);
+    }
+  pl.groups = std::move(plans);
+  return pl;
+}
+
+size_t spectra_bytes(int lx, int ly, int lz) {
+  return 6 * (size_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1) * (sizeof(c128) + sizeof(c64));
+}
+
+bool spectra_cached(vie_context* ctx, int lx, int ly, int lz, const vie_grid& g, double k0) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->cache.find(SpecKey{lx, ly, lz, g.dx, g.dy, g.dz, k0});
+  return it != ctx->cache.end() && !it->second.expired();
+}
+
+// Device bytes a problem built from `pl` holds (spectra already in the
+// context's cache are shared and not counted).
+size_t plan_footprint(vie_context* ctx, const ProblemPlan& pl) {
+  const auto& g = pl.g;
+  const size_t nv = (size_t)pl.nv;
+  size_t foot = nv * sizeof(c128)                                       // 1/chi
+                + 3 * (size_t)g.nz * pl.ly * pl.lx * sizeof(c128)       // work
+                + V_COUNT * 3 * nv * sizeof(c128)                       // Krylov vectors
+                + 4 * (size_t)std::max(vie::krylov_chunks(3 * (int64_t)nv), vie::mvm_row_tiles(pl.lx, g.nz, g.ny)) *
+                      sizeof(double);
+  std::set<std::tuple<int, int, int>> seen;
+  auto spec = [&](int lx, int ly, int lz) {
+    if (seen.insert({lx, ly, lz}).second && !spectra_cached(ctx, lx, ly, lz, g, pl.k0))
+      foot += spectra_bytes(lx, ly, lz);
+  };
+  spec(pl.lx, pl.ly, pl.lz);
+  int64_t ipstride = 0, slots = 0;
+  for (const auto& gp : pl.groups) {
+    const size_t nsys = gp.blocks.size(), bnv = (size_t)gp.bx * gp.by * gp.bz;
+    foot += nsys * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
+            8 * nsys * 3 * bnv * sizeof(c128);
+    spec(gp.lx, gp.ly, gp.lz);
+    ipstride = std::max<int64_t>(ipstride, 4 * std::max(vie::krylov_chunks(3 * (int64_t)bnv),
+                                                        vie::mvm_row_tiles(gp.lx, gp.bz, gp.by)));
+    slots += (int64_t)nsys;
+  }
+  foot += (size_t)std::max<int64_t>(1, slots) * ipstride * sizeof(double);
+  return foot;
+}
+
+// z-pass variant for a batch shape: tuned once per context, shape and
+// precision, so every problem of that shape uses the same kernels.
+template <typename R>
+int cached_zvariant(vie_context* ctx, const MvmBatch<R>& b, hipStream_t s, float* ms) {
+  const std::array<int, 8> key{(int)sizeof(R), b.nx, b.ny, b.nz, b.lx, b.ly, b.lz, b.nsys};
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->ztune.find(key);
+    if (it != ctx->ztune.end()) {
+      if (ms)
+        for (int v = 0; v < vie::kZPassVariants; ++v) ms[v] = it->second.second[v];
+      return it->second.first;
+    }
+  }
+  std::array<float, vie::kZPassVariants> t{};
+  const int v = vie::tune_zpass<R>(b, s, t.data());
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->ztune.emplace(key, std::make_pair(v, t)).first;   // first tuning wins
+  if (ms)
+    for (int q = 0; q < vie::kZPassVariants; ++q) ms[q] = it->second.second[q];
+  return it->second.first;
+}
+
+std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& pl, hipStream_t s) {
+  const vie_grid& g = pl.g;
+  const int64_t nv = pl.nv;
+  auto P = std::make_unique<vie_problem>();
+  P->ctx = ctx;
+  P->g = g;
+  P->nv = nv;
+  P->lx = pl.lx;
+  P->ly = pl.ly;
+  P->lz = pl.lz;
+  P->k0 = pl.k0;
+  P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0, s);
+  upload(P->chi, pl.chi);
+  P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
+  P->work.zero();
+  P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
+  P->vecs.zero();
+  for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
+  P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
+  P->partials.alloc(P->pstride * sizeof(double));
+  P->ntile.alloc(sizeof(int));
+  P->ntile.zero();
+  P->ostate.alloc(sizeof(KState));
+  P->ostate.zero();
+  P->ostatus.alloc(sizeof(int));
+  P->ostatus.zero();
+  P->scal.alloc(64);
+  P->d_count.alloc(sizeof(int));
+  P->d_acc.alloc(3 * sizeof(int64_t));
+  P->d_acc.zero();
+  hip_check(hipHostMalloc((void**)&P->h_ring, 2 * kRing * sizeof(int)), "pinned ring");
+  for (auto& r : P->ev)
+    for (auto& e : r) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+
+  if (pl.has_blocks) {
+    const int n_blocks = pl.n_blocks;
+    const auto& lo = pl.lo;
+    const auto& bid = pl.bid;
+    P->n_blocks = n_blocks;
+    std::vector<int> block_group(n_blocks, -1), block_sys(n_blocks, -1);
+    std::vector<int4> origin(n_blocks, int4{0, 0, 0, 0}), gbox;
+    int slot = 0;
+    for (const auto& gp : pl.groups) {
+      Group G{};
+      G.lx = gp.lx;
+      G.ly = gp.ly;
+      G.lz = gp.lz;
+      G.blocks = gp.blocks;
+      G.wg = gp.wg;
+      G.nsys = (int)G.blocks.size();
+      G.bx = gp.bx;
+      G.by = gp.by;
+      G.bz = gp.bz;
+      G.bnv = (int64_t)G.bx * G.by * G.bz;
+      G.n = 3 * G.bnv;
+      const int gi = (int)P->groups.size();
+      std::vector<c128> gchi((size_t)G.nsys * G.bnv, mk<double>(0.0, 0.0));
+      for (int q = 0; q < G.nsys; ++q) {
+        const int k = G.blocks[q];
+        block_group[k] = gi;
+        block_sys[k] = q;
+        origin[k] = int4{lo[3 * k], lo[3 * k + 1], lo[3 * k + 2], 0};
+        for (int z = 0; z < G.bz; ++z)
+          for (int y = 0; y < G.by; ++y)
+            for (int x = 0; x < G.bx; ++x) {
+              const int X = lo[3 * k] + x, Y = lo[3 * k + 1] + y, Z = lo[3 * k + 2] + z;
+              if (X >= g.nx || Y >= g.ny || Z >= g.nz) continue;
+              const int64_t v = ((int64_t)Z * g.ny + Y) * g.nx + X;
+              if (bid[v] == k) gchi[(size_t)q * G.bnv + ((int64_t)z * G.by + y) * G.bx + x] = pl.chi[v];
+            }
+      }
+      gbox.push_back(int4{G.bx, G.by, G.bz, 0});
+      upload(G.chi, gchi);
+      G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0, s);
+      G.work.alloc((size_t)G.nsys * 3 * G.bz * G.ly * G.lx * sizeof(c128));
+      G.work.zero();
+      G.vecs.alloc(8 * (size_t)G.nsys * G.n * sizeof(c128));
+      G.vecs.zero();
+      for (int q = 0; q < 8; ++q) G.vec[q] = G.vecs.as<c128>() + (size_t)q * G.nsys * G.n;
+      P->ipstride =
+          std::max<int64_t>(P->ipstride, 4 * std::max(vie::krylov_chunks(G.n), vie::mvm_row_tiles(G.lx, G.bz, G.by)));
+      G.slot0 = slot;
+      slot += G.nsys;
+      P->groups.push_back(std::move(G));
+    }
+    P->n_inner = slot;
+    for (auto& G : P->groups) {
+      if (G.wg)
+        ++P->n_wg_groups;
+      else
+        P->n_batched_wg += G.nsys;
+    }
+    std::vector<int> slots;
+    for (int k = 0; k < n_blocks; ++k)
+      if (pl.cnt[k] > 0) slots.push_back(P->groups[block_group[k]].slot0 + block_sys[k]);
+    P->n_nonempty = (int)slots.size();
+    upload(P->d_block_id, bid);
+    upload(P->d_block_group, block_group);
+    upload(P->d_block_sys, block_sys);
+    upload(P->d_block_origin, origin);
+    upload(P->d_gbox, gbox);
+    upload(P->d_slots, slots);
+    std::vector<c128*> ptrs(8 * P->groups.size());
+    for (size_t gi = 0; gi < P->groups.size(); ++gi)
+      for (int q = 0; q < 8; ++q) ptrs[q * P->groups.size() + gi] = P->groups[gi].vec[q];
+    upload(P->d_gptr, ptrs);
+    P->d_istatus.alloc(std::max(1, slot) * sizeof(int));
+    P->d_istatus.zero();
+    P->d_istate.alloc(std::max(1, slot) * sizeof(KState));
+    P->d_istate.zero();
+    P->d_ipartials.alloc((size_t)std::max(1, slot) * P->ipstride * sizeof(double));
+    P->d_intile.alloc(std::max(1, slot) * sizeof(int));
+    P->d_intile.zero();
+    // pick the faster z-pass kernel per batch shape and precision (tuning
+    // clobbers the work buffers, which hold no data yet)
+    for (auto& G : P->groups) {
+      G.zvar[0] = cached_zvariant<double>(ctx, group_batch<double>(*P, G, false), s, nullptr);
+      G.zvar[1] = cached_zvariant<float>(ctx, group_batch<float>(*P, G, false), s, nullptr);
+    }
+    if (P->groups.size() > 1) {
+      const size_t G = P->groups.size();
+      P->branches.streams.resize(G, nullptr);
+      for (auto& b : P->branches.streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
+      P->branches.events.resize(4 * (G + 1), nullptr);
+      for (auto& e : P->branches.events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    }
+    if (P->n_wg_groups > 0) {
+      P->wg_streams.resize(P->n_wg_groups, nullptr);
+      for (auto& b : P->wg_streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
+      P->wg_events.resize(1 + P->n_wg_groups, nullptr);
+      for (auto& e : P->wg_events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    }
+    vie::BlockMap& m = P->bmap;
+    m.nblocks = n_blocks;
+    m.ngroups = (int)P->groups.size();
+    m.block_id = P->d_block_id.as<int>();
+    m.block_group = P->d_block_group.as<int>();
+    m.block_sys = P->d_block_sys.as<int>();
+    m.block_origin = P->d_block_origin.as<int4>();
+    m.gbox = P->d_gbox.as<int4>();
+    m.nx = g.nx;
+    m.ny = g.ny;
+    m.nz = g.nz;
+  }
+  P->zvar[0] = cached_zvariant<double>(ctx, outer_batch<double>(*P, false), s, P->ztune_ms[0]);
+  P->zvar[1] = cached_zvariant<float>(ctx, outer_batch<float>(*P, false), s, P->ztune_ms[1]);
+  hip_check(hipStreamSynchronize(s), "problem set-up");
+  return P;
+}
+
 }  // namespace
+
+// ------------------------------------------------------------------ serving
+struct vie_request {
+  enum State { QUEUED, RUNNING, DONE };
+  ProblemPlan plan;
+  std::vector<double> e_inc;
+  vie_opts opts{};
+  size_t footprint = 0;
+  // result
+  State state = QUEUED;
+  vie_status status = VIE_OK;
+  std::string error;
+  std::vector<double> e_tot;
+  vie_stats stats{};
+  std::atomic<bool> cancel{false};
+  std::chrono::steady_clock::time_point t_submit, t_start, t_solve, t_end;
+  struct Server* server = nullptr;
+};
+
+// Worker threads (one HIP stream each) taking requests from a FIFO queue.
+struct Server {
+  vie_context* ctx = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<vie_request*> queue;
+  std::set<vie_request*> running;
+  std::vector<std::thread> workers;
+  int queue_cap = 0;
+  int64_t outstanding = 0;   // tickets not yet passed to vie_wait
+  bool stop = false;
+
+  // Front request fits the memory budget next to everything running.
+  bool admissible() {
+    if (queue.empty()) return false;
+    if (ctx->budget == 0) return true;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return ctx->used + ctx->reserved + queue.front()->footprint <= ctx->budget;
+  }
+
+  void run(vie_request* r, hipStream_t s) {
+    vie_status st = guarded([&]() -> vie_status {
+      set_device(ctx);
+      auto P = build_problem(ctx, r->plan, s);
+      P->footprint = r->footprint;
+      P->cancel = &r->cancel;
+      r->t_solve = std::chrono::steady_clock::now();
+      const int64_t n = 3 * P->nv;
+      DevBuf din(n * sizeof(c128)), dout(n * sizeof(c128));
+      hip_check(hipMemcpyAsync(din.p, r->e_inc.data(), n * sizeof(c128), hipMemcpyHostToDevice, s), "upload e_inc");
+      const vie_status code = solve_impl(P.get(), din.as<c128>(), &r->opts, dout.as<c128>(), nullptr, &r->stats, s);
+      if (code != VIE_ECANCELLED) {
+        r->e_tot.resize(2 * n);
+        hip_check(hipMemcpyAsync(r->e_tot.data(), dout.p, n * sizeof(c128), hipMemcpyDeviceToHost, s), "download");
+      }
+      hip_check(hipStreamSynchronize(s), "request");
+      return code;
+    });
+    r->status = st;
+    if (st != VIE_OK) r->error = vie_last_error_str();
+  }
+
+  void worker() {
+    hipStream_t s = nullptr;
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    for (;;) {
+      vie_request* r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || admissible(); });
+        if (stop) break;
+        r = queue.front();
+        queue.pop_front();
+        running.insert(r);
+        r->state = vie_request::RUNNING;
+        r->t_start = std::chrono::steady_clock::now();
+        std::lock_guard<std::mutex> lc(ctx->mu);
+        ctx->reserved += r->footprint;
+      }
+      cv_work.notify_all();   // the next request may fit as well
+      if (s)
+        run(r, s);
+      else {
+        r->status = VIE_EDEVICE;
+        r->error = "worker stream could not be created";
+      }
+      r->t_end = std::chrono::steady_clock::now();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        {
+          std::lock_guard<std::mutex> lc(ctx->mu);
+          ctx->reserved -= std::min(ctx->reserved, r->footprint);
+        }
+        running.erase(r);
+        r->state = vie_request::DONE;
+      }
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
+    if (s) (void)hipStreamDestroy(s);
+  }
+
+  void start(int slots, int cap) {
+    queue_cap = cap;
+    for (int i = 0; i < slots; ++i) workers.emplace_back([this] { worker(); });
+  }
+
+  ~Server() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+      for (auto* r : queue) {
+        r->status = VIE_ECANCELLED;
+        r->error = "server stopped";
+        r->state = vie_request::DONE;
+      }
+      queue.clear();
+      for (auto* r : running) r->cancel.store(true);
+    }
+    cv_work.notify_all();
+    for (auto& t : workers) t.join();
+    cv_done.notify_all();
+  }
+};
+
+vie_context::~vie_context() { server.reset(); }
+
 
 // =================================================================== C ABI
 extern "C" {
@@ -831,6 +1361,13 @@ vie_status vie_context_create(int32_t device, size_t hbm_budget_bytes, vie_conte
 vie_status vie_context_destroy(vie_context* ctx) {
   return guarded([&]() -> vie_status {
     if (!ctx) return VIE_OK;
+    if (ctx->server) {
+      {
+        std::lock_guard<std::mutex> lk(ctx->server->mu);
+        if (ctx->server->outstanding > 0) fail(VIE_EBUSY, "tickets are outstanding (pass each to vie_wait first)");
+      }
+      ctx->server.reset();
+    }
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -844,283 +1381,24 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
     if (!out) fail(VIE_EINVAL, "out is NULL");
     *out = nullptr;
     if (!ctx || !grid || !eps_r) fail(VIE_EINVAL, "ctx, grid and eps_r are required");
-    const vie_grid g = *grid;
-    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > 256 || g.ny > 256 || g.nz > 256)
-      fail(VIE_EINVAL, "grid sizes must be in [1, 256]");
-    if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !(g.wavelength > 0) || !is_finite(g.dx) || !is_finite(g.dy) ||
-        !is_finite(g.dz) || !is_finite(g.wavelength))
-      fail(VIE_EINVAL, "spacing and wavelength must be finite and > 0");
-    if (block_id && n_blocks < 1) fail(VIE_EINVAL, "n_blocks must be >= 1 when block_id is given");
-    if (n_blocks < 0) fail(VIE_EINVAL, "n_blocks must be >= 0");
-    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
-    // 1/chi on the host
-    std::vector<c128> chi(nv);
-    for (int64_t i = 0; i < nv; ++i) {
-      const double er = eps_r[2 * i], ei = eps_r[2 * i + 1];
-      if (!is_finite(er) || !is_finite(ei)) fail(VIE_EINVAL, "eps_r has non-finite entries");
-      if (er == 1.0 && ei == 0.0) {
-        chi[i] = mk<double>(0.0, 0.0);
-      } else {
-        const std::complex<double> c = 1.0 / (std::complex<double>(er, ei) - 1.0);
-        chi[i] = mk<double>(c.real(), c.imag());
-      }
-    }
-    std::vector<int32_t> bid;
-    if (block_id) {
-      bid.assign(nv, -1);
-      for (int64_t i = 0; i < nv; ++i) {
-        const bool vac = chi[i].x == 0.0 && chi[i].y == 0.0;
-        if (vac) continue;
-        const int32_t k = block_id[i];
-        if (k < 0 || k >= n_blocks) fail(VIE_EINVAL, "block id out of range on a scatterer voxel");
-        bid[i] = k;
-      }
-    }
+    ProblemPlan plan = make_plan(*grid, eps_r, block_id, n_blocks);
     set_device(ctx);
-    auto P = std::make_unique<vie_problem>();
-    P->ctx = ctx;
-    P->g = g;
-    P->nv = nv;
-    P->lx = vie::smallest_fft_length(2 * g.nx - 1);
-    P->ly = vie::smallest_fft_length(2 * g.ny - 1);
-    P->lz = vie::smallest_fft_length(2 * g.nz - 1);
-    if (P->lx < 0 || P->ly < 0 || P->lz < 0) fail(VIE_EINVAL, "grid too large for the compiled FFT lengths");
-    P->k0 = 2.0 * M_PI / g.wavelength;
-    P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0);
-    upload(P->chi, chi);
-    P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
-    P->work.zero();
-    P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
-    P->vecs.zero();
-    for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
-    P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
-    P->partials.alloc(P->pstride * sizeof(double));
-    P->ntile.alloc(sizeof(int));
-    P->ntile.zero();
-    P->ostate.alloc(sizeof(KState));
-    P->ostate.zero();
-    P->ostatus.alloc(sizeof(int));
-    P->ostatus.zero();
-    P->scal.alloc(64);
-    P->d_count.alloc(sizeof(int));
-    P->d_acc.alloc(3 * sizeof(int64_t));
-    P->d_acc.zero();
-    hip_check(hipHostMalloc((void**)&P->h_ring, 2 * kRing * sizeof(int)), "pinned ring");
-    for (auto& r : P->ev)
-      for (auto& e : r) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-
-    size_t foot = P->chi.bytes + P->work.bytes + P->vecs.bytes + P->partials.bytes + P->spec->bytes();
-
-    if (block_id) {
-      // tight bounding box of every block
-      P->n_blocks = n_blocks;
-      std::vector<int> lo(3 * n_blocks, 1 << 30), hi(3 * n_blocks, -1);
-      std::vector<int64_t> cnt(n_blocks, 0);
-      for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y)
-          for (int x = 0; x < g.nx; ++x) {
-            const int k = bid[((int64_t)z * g.ny + y) * g.nx + x];
-            if (k < 0) continue;
-            cnt[k]++;
-            const int c[3] = {x, y, z};
-            for (int a = 0; a < 3; ++a) {
-              lo[3 * k + a] = std::min(lo[3 * k + a], c[a]);
-              hi[3 * k + a] = std::max(hi[3 * k + a], c[a]);
-            }
-          }
-      // group blocks by circulant lengths of their bounding boxes
-      struct Plan {
-        int lx, ly, lz;
-        std::vector<int> blocks;
-        bool wg = false;
-      };
-      std::vector<Plan> plans;
-      {
-        std::map<std::tuple<int, int, int>, std::vector<int>> bylen;
-        for (int k = 0; k < n_blocks; ++k) {
-          if (cnt[k] == 0) continue;
-          const int ex = hi[3 * k] - lo[3 * k] + 1, ey = hi[3 * k + 1] - lo[3 * k + 1] + 1,
-                    ez = hi[3 * k + 2] - lo[3 * k + 2] + 1;
-          bylen[{vie::smallest_fft_length(2 * ex - 1), vie::smallest_fft_length(2 * ey - 1),
-                 vie::smallest_fft_length(2 * ez - 1)}]
-              .push_back(k);
-        }
-        for (auto& kv : bylen) plans.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                                                kv.second, false});
-      }
-      // Shapes the one-workgroup block solver handles stay separate groups
-      // (one launch per group and application, whatever the group size).
-      std::vector<Plan> wg_plans;
-      {
-        std::vector<Plan> rest;
-        for (auto& pl : plans) {
-          int bz = 1;
-          for (int k : pl.blocks) bz = std::max(bz, hi[3 * k + 2] - lo[3 * k + 2] + 1);
-          pl.wg = vie::block_solver_supported(pl.lx, pl.ly, pl.lz, bz);
-          (pl.wg ? wg_plans : rest).push_back(std::move(pl));
-        }
-        plans = std::move(rest);
-      }
-      // Merge shape groups while it lowers the modelled cost of one inner
-      // iteration: a fixed per-group overhead (its kernel launches) plus
-      // work proportional to the padded transform volume of its systems.
-      // A merged group takes the largest lengths of both (a box of n <=
-      // (L+1)/2 voxels embeds in any longer L).
-      {
-        // ~11 launches of >= 5 us per group and step, against ~50 ps per padded
-        // point and step (two products and the vector updates) on MI355X
-        const double kGroupOverhead = 1.2e6;  // padded points per group-iteration overhead
-        auto cost = [&](int lx, int ly, int lz, size_t nsys) {
-          return kGroupOverhead + (double)nsys * lx * ly * lz;
-        };
-        for (;;) {
-          double best = 0;
-          int bi = -1, bj = -1;
-          for (size_t i = 0; i < plans.size(); ++i)
-            for (size_t j = i + 1; j < plans.size(); ++j) {
-              const Plan &a = plans[i], &b = plans[j];
-              const int lx = std::max(a.lx, b.lx), ly = std::max(a.ly, b.ly), lz = std::max(a.lz, b.lz);
-              const double d = cost(lx, ly, lz, a.blocks.size() + b.blocks.size()) -
-                               cost(a.lx, a.ly, a.lz, a.blocks.size()) - cost(b.lx, b.ly, b.lz, b.blocks.size());
-              if (d < best) {
-                best = d;
-                bi = (int)i;
-                bj = (int)j;
-              }
-            }
-          if (bi < 0) break;
-          Plan& a = plans[bi];
-          Plan& b = plans[bj];
-          a.lx = std::max(a.lx, b.lx);
-          a.ly = std::max(a.ly, b.ly);
-          a.lz = std::max(a.lz, b.lz);
-          a.blocks.insert(a.blocks.end(), b.blocks.begin(), b.blocks.end());
-          std::sort(a.blocks.begin(), a.blocks.end());
-          plans.erase(plans.begin() + bj);
-        }
-      }
-      for (auto& pl : wg_plans) plans.push_back(std::move(pl));
-      std::vector<int> block_group(n_blocks, -1), block_sys(n_blocks, -1);
-      std::vector<int4> origin(n_blocks, int4{0, 0, 0, 0}), gbox;
-      int slot = 0;
-      for (auto& pl : plans) {
-        Group G{};
-        G.lx = pl.lx;
-        G.ly = pl.ly;
-        G.lz = pl.lz;
-        G.blocks = pl.blocks;
-        G.wg = pl.wg;
-        G.nsys = (int)G.blocks.size();
-        G.bx = G.by = G.bz = 1;
-        for (int k : G.blocks) {
-          G.bx = std::max(G.bx, hi[3 * k] - lo[3 * k] + 1);
-          G.by = std::max(G.by, hi[3 * k + 1] - lo[3 * k + 1] + 1);
-          G.bz = std::max(G.bz, hi[3 * k + 2] - lo[3 * k + 2] + 1);
-        }
-        G.bnv = (int64_t)G.bx * G.by * G.bz;
-        G.n = 3 * G.bnv;
-        const int gi = (int)P->groups.size();
-        std::vector<c128> gchi((size_t)G.nsys * G.bnv, mk<double>(0.0, 0.0));
-        for (int s = 0; s < G.nsys; ++s) {
-          const int k = G.blocks[s];
-          block_group[k] = gi;
-          block_sys[k] = s;
-          origin[k] = int4{lo[3 * k], lo[3 * k + 1], lo[3 * k + 2], 0};
-          for (int z = 0; z < G.bz; ++z)
-            for (int y = 0; y < G.by; ++y)
-              for (int x = 0; x < G.bx; ++x) {
-                const int X = lo[3 * k] + x, Y = lo[3 * k + 1] + y, Z = lo[3 * k + 2] + z;
-                if (X >= g.nx || Y >= g.ny || Z >= g.nz) continue;
-                const int64_t v = ((int64_t)Z * g.ny + Y) * g.nx + X;
-                if (bid[v] == k) gchi[(size_t)s * G.bnv + ((int64_t)z * G.by + y) * G.bx + x] = chi[v];
-              }
-        }
-        gbox.push_back(int4{G.bx, G.by, G.bz, 0});
-        upload(G.chi, gchi);
-        G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0);
-        G.work.alloc((size_t)G.nsys * 3 * G.bz * G.ly * G.lx * sizeof(c128));
-        G.work.zero();
-        G.vecs.alloc(8 * (size_t)G.nsys * G.n * sizeof(c128));
-        G.vecs.zero();
-        for (int q = 0; q < 8; ++q) G.vec[q] = G.vecs.as<c128>() + (size_t)q * G.nsys * G.n;
-        P->ipstride = std::max<int64_t>(
-            P->ipstride, 4 * std::max(vie::krylov_chunks(G.n), vie::mvm_row_tiles(G.lx, G.bz, G.by)));
-        G.slot0 = slot;
-        slot += G.nsys;
-        foot += G.chi.bytes + G.work.bytes + G.vecs.bytes + G.spec->bytes();
-        P->groups.push_back(std::move(G));
-      }
-      P->n_inner = slot;
-      for (auto& G : P->groups) {
-        if (G.wg)
-          ++P->n_wg_groups;
-        else
-          P->n_batched_wg += G.nsys;
-      }
-      std::vector<int> slots;
-      for (int k = 0; k < n_blocks; ++k)
-        if (cnt[k] > 0) slots.push_back(P->groups[block_group[k]].slot0 + block_sys[k]);
-      P->n_nonempty = (int)slots.size();
-      upload(P->d_block_id, bid);
-      upload(P->d_block_group, block_group);
-      upload(P->d_block_sys, block_sys);
-      upload(P->d_block_origin, origin);
-      upload(P->d_gbox, gbox);
-      upload(P->d_slots, slots);
-      std::vector<c128*> ptrs(8 * P->groups.size());
-      for (size_t gi = 0; gi < P->groups.size(); ++gi)
-        for (int q = 0; q < 8; ++q) ptrs[q * P->groups.size() + gi] = P->groups[gi].vec[q];
-      upload(P->d_gptr, ptrs);
-      P->d_istatus.alloc(std::max(1, slot) * sizeof(int));
-      P->d_istatus.zero();
-      P->d_istate.alloc(std::max(1, slot) * sizeof(KState));
-      P->d_istate.zero();
-      P->d_ipartials.alloc((size_t)std::max(1, slot) * P->ipstride * sizeof(double));
-      P->d_intile.alloc(std::max(1, slot) * sizeof(int));
-      P->d_intile.zero();
-      foot += P->d_ipartials.bytes;
-      // pick the faster z-pass kernel per batch shape and precision (clobbers
-      // the work buffers, which hold no data yet)
-      for (auto& G : P->groups) {
-        G.zvar[0] = vie::tune_zpass<double>(group_batch<double>(*P, G, false), ctx->stream);
-        G.zvar[1] = vie::tune_zpass<float>(group_batch<float>(*P, G, false), ctx->stream);
-      }
-      if (P->groups.size() > 1) {
-        const size_t G = P->groups.size();
-        P->branches.streams.resize(G, nullptr);
-        for (auto& b : P->branches.streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
-        P->branches.events.resize(4 * (G + 1), nullptr);
-        for (auto& e : P->branches.events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-      }
-      if (P->n_wg_groups > 0) {
-        P->wg_streams.resize(P->n_wg_groups, nullptr);
-        for (auto& b : P->wg_streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
-        P->wg_events.resize(1 + P->n_wg_groups, nullptr);
-        for (auto& e : P->wg_events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-      }
-      vie::BlockMap& m = P->bmap;
-      m.nblocks = n_blocks;
-      m.ngroups = (int)P->groups.size();
-      m.block_id = P->d_block_id.as<int>();
-      m.block_group = P->d_block_group.as<int>();
-      m.block_sys = P->d_block_sys.as<int>();
-      m.block_origin = P->d_block_origin.as<int4>();
-      m.gbox = P->d_gbox.as<int4>();
-      m.nx = g.nx;
-      m.ny = g.ny;
-      m.nz = g.nz;
-    }
-    P->zvar[0] = vie::tune_zpass<double>(outer_batch<double>(*P, false), ctx->stream, P->ztune_ms[0]);
-    P->zvar[1] = vie::tune_zpass<float>(outer_batch<float>(*P, false), ctx->stream, P->ztune_ms[1]);
-    hip_check(hipStreamSynchronize(ctx->stream), "z-pass tuning");
-    P->footprint = foot;
+    const size_t foot = plan_footprint(ctx, plan);
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
-      if (ctx->budget && ctx->used + foot > ctx->budget) fail(VIE_EBUSY, "problem exceeds the context's HBM budget");
+      if (ctx->budget && ctx->used + ctx->reserved + foot > ctx->budget)
+        fail(VIE_EBUSY, "problem exceeds the context's HBM budget");
       ctx->used += foot;
     }
-    hip_check(hipDeviceSynchronize(), "problem set-up");
-    *out = P.release();
+    try {
+      auto P = build_problem(ctx, plan, ctx->stream);
+      P->footprint = foot;
+      *out = P.release();
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->used -= std::min(ctx->used, foot);
+      throw;
+    }
     return VIE_OK;
   });
 }
@@ -1130,11 +1408,17 @@ vie_status vie_problem_destroy(vie_problem* p) {
     if (!p) return VIE_OK;
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
+    vie_context* ctx = p->ctx;
     {
-      std::lock_guard<std::mutex> lk(p->ctx->mu);
-      p->ctx->used -= std::min(p->ctx->used, p->footprint);
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->used -= std::min(ctx->used, p->footprint);
     }
     delete p;
+    {
+      // queued requests may fit now
+      std::lock_guard<std::mutex> lk(ctx->server_mu);
+      if (ctx->server) ctx->server->cv_work.notify_all();
+    }
     return VIE_OK;
   });
 }
@@ -1299,7 +1583,7 @@ vie_status vie_solve_device(vie_problem* p, const void* e_inc_dev, const vie_opt
                             void* pol_dev, vie_stats* stats, void* stream) {
   return guarded([&]() -> vie_status {
     if (!p || !e_inc_dev || !e_tot_dev) fail(VIE_EINVAL, "problem, e_inc and e_tot are required");
-    validate_opts(opts, p);
+    validate_opts(opts, !p->groups.empty());
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
     return solve_impl(p, (const c128*)e_inc_dev, opts, (c128*)e_tot_dev, (c128*)pol_dev, stats, (hipStream_t)stream);
@@ -1310,7 +1594,7 @@ vie_status vie_solve(vie_problem* p, const double* e_inc, const vie_opts* opts, 
                      vie_stats* stats) {
   return guarded([&]() -> vie_status {
     if (!p || !e_inc || !e_tot_out) fail(VIE_EINVAL, "problem, e_inc and e_tot_out are required");
-    validate_opts(opts, p);
+    validate_opts(opts, !p->groups.empty());
     const int64_t n = 3 * p->nv;
     for (int64_t i = 0; i < 2 * n; ++i)
       if (!is_finite(e_inc[i])) fail(VIE_EINVAL, "e_inc has non-finite entries");
@@ -1325,6 +1609,146 @@ vie_status vie_solve(vie_problem* p, const double* e_inc, const vie_opts* opts, 
     if (pol_out) hip_check(hipMemcpyAsync(pol_out, dpol.p, n * sizeof(c128), hipMemcpyDeviceToHost, s), "download pol");
     hip_check(hipStreamSynchronize(s), "download");
     return st;
+  });
+}
+
+static void start_server(vie_context* ctx, int slots, int cap) {
+  auto srv = std::make_unique<Server>();
+  srv->ctx = ctx;
+  srv->start(slots, cap);
+  ctx->server = std::move(srv);
+}
+
+vie_status vie_server_start(vie_context* ctx, int32_t slots, int32_t queue_cap) {
+  return guarded([&]() -> vie_status {
+    if (!ctx) fail(VIE_EINVAL, "ctx is NULL");
+    if (slots < 1 || slots > 64) fail(VIE_EINVAL, "slots must be in [1, 64]");
+    if (queue_cap < 1) fail(VIE_EINVAL, "queue_cap must be >= 1");
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    if (ctx->server) fail(VIE_EBUSY, "server already running");
+    start_server(ctx, slots, queue_cap);
+    return VIE_OK;
+  });
+}
+
+static size_t transient_bytes(vie_context* ctx, const ProblemPlan& pl) {
+  // spectra set-up scratch (6 full kernels in FP64) for lengths not cached
+  size_t t = 0;
+  auto one = [&](int lx, int ly, int lz) {
+    if (!spectra_cached(ctx, lx, ly, lz, pl.g, pl.k0))
+      t = std::max(t, 6 * (size_t)lx * ly * lz * sizeof(c128));
+  };
+  one(pl.lx, pl.ly, pl.lz);
+  for (const auto& gp : pl.groups) one(gp.lx, gp.ly, gp.lz);
+  return t;
+}
+
+vie_status vie_footprint(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
+                         int32_t n_blocks, size_t* bytes) {
+  return guarded([&]() -> vie_status {
+    if (!ctx || !grid || !eps_r || !bytes) fail(VIE_EINVAL, "ctx, grid, eps_r and bytes are required");
+    const ProblemPlan pl = make_plan(*grid, eps_r, block_id, n_blocks);
+    *bytes = plan_footprint(ctx, pl) + transient_bytes(ctx, pl);
+    return VIE_OK;
+  });
+}
+
+vie_status vie_submit(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
+                      int32_t n_blocks, const double* e_inc, const vie_opts* opts, vie_ticket* out) {
+  return guarded([&]() -> vie_status {
+    if (!out) fail(VIE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx || !grid || !eps_r || !e_inc || !opts) fail(VIE_EINVAL, "ctx, grid, eps_r, e_inc and opts are required");
+    auto r = std::make_unique<vie_request>();
+    r->plan = make_plan(*grid, eps_r, block_id, n_blocks);
+    r->opts = *opts;
+    validate_opts(opts, !r->plan.groups.empty());
+    const int64_t n = 2 * 3 * r->plan.nv;
+    r->e_inc.assign(e_inc, e_inc + n);
+    for (double v : r->e_inc)
+      if (!is_finite(v)) fail(VIE_EINVAL, "e_inc has non-finite entries");
+    set_device(ctx);
+    r->footprint = plan_footprint(ctx, r->plan) + transient_bytes(ctx, r->plan);
+    if (ctx->budget && r->footprint > ctx->budget) fail(VIE_EINVAL, "request needs more memory than the context budget");
+    {
+      std::lock_guard<std::mutex> lk(ctx->server_mu);
+      if (!ctx->server) start_server(ctx, 4, 1024);
+    }
+    Server& S = *ctx->server;
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      if ((int)S.queue.size() >= S.queue_cap) fail(VIE_EBUSY, "request queue is full");
+      r->t_submit = std::chrono::steady_clock::now();
+      r->server = &S;
+      S.queue.push_back(r.get());
+      ++S.outstanding;
+    }
+    *out = r.release();
+    S.cv_work.notify_all();
+    return VIE_OK;
+  });
+}
+
+vie_status vie_wait(vie_ticket t, double timeout_s, double* e_tot_out, vie_stats* stats, double* times) {
+  return guarded([&]() -> vie_status {
+    if (!t) fail(VIE_EINVAL, "ticket is NULL");
+    vie_request* r = t;
+    Server* S = nullptr;
+    // the request's server is the one whose queue or workers hold it; every
+    // request was submitted to a context whose server outlives its tickets
+    S = r->server;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      auto done = [&] { return r->state == vie_request::DONE; };
+      if (timeout_s < 0)
+        S->cv_done.wait(lk, done);
+      else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done))
+        fail(VIE_ETIMEDOUT, "request not finished");
+      --S->outstanding;
+    }
+    std::unique_ptr<vie_request> own(r);
+    if (e_tot_out && !r->e_tot.empty()) std::memcpy(e_tot_out, r->e_tot.data(), r->e_tot.size() * sizeof(double));
+    if (stats) {
+      int32_t* hist = stats->inner_hist;
+      const int64_t cap = stats->inner_hist_cap;
+      *stats = r->stats;
+      stats->inner_hist = hist;
+      stats->inner_hist_cap = cap;
+      stats->inner_hist_len = 0;
+    }
+    if (times) {
+      using d = std::chrono::duration<double>;
+      const bool ran = r->t_start.time_since_epoch().count() != 0;
+      const bool solved = r->t_solve.time_since_epoch().count() != 0;
+      times[0] = ran ? d(r->t_start - r->t_submit).count() : d(r->t_end - r->t_submit).count();
+      times[1] = solved ? d(r->t_solve - r->t_start).count() : 0.0;
+      times[2] = solved ? d(r->t_end - r->t_solve).count() : 0.0;
+    }
+    if (r->status != VIE_OK) g_last_error = r->error;
+    return r->status;
+  });
+}
+
+vie_status vie_cancel(vie_ticket t) {
+  return guarded([&]() -> vie_status {
+    if (!t) fail(VIE_EINVAL, "ticket is NULL");
+    vie_request* r = t;
+    Server* S = r->server;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      r->cancel.store(true);
+      if (r->state == vie_request::QUEUED) {
+        auto it = std::find(S->queue.begin(), S->queue.end(), r);
+        if (it != S->queue.end()) S->queue.erase(it);
+        r->status = VIE_ECANCELLED;
+        r->error = "request cancelled";
+        r->t_end = std::chrono::steady_clock::now();
+        r->state = vie_request::DONE;
+      }
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+    return VIE_OK;
   });
 }
 

@@ -46,15 +46,17 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 VIE_OK, VIE_NOT_CONVERGED = 0, 1
 VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_EBREAKDOWN, VIE_EBUSY, VIE_ECANCELLED, VIE_EINTERNAL = -1, -2, -3, -4, -5, -6, -7
+VIE_ETIMEDOUT = -8
 VIE_FP64, VIE_MIXED = 0, 1
 VIE_FLAG_NO_GRAPHS = 1
 VIE_FLAG_NO_BLOCK_KERNEL = 2
 STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_ENOMEM", -3: "VIE_EDEVICE",
-                -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL"}
+                -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL", -8: "VIE_ETIMEDOUT"}
 
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
                "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_plane_wave",
-               "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device")
+               "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
+               "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel")
 
 
 class VieError(RuntimeError):
@@ -111,6 +113,11 @@ for _name, _args in {
                           ctypes.POINTER(ctypes.c_int64)],
     "vie_solve": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats)],
     "vie_solve_device": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats), _vp],
+    "vie_server_start": [_vp, ctypes.c_int32, ctypes.c_int32],
+    "vie_footprint": [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "vie_submit": [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(vie_opts), ctypes.POINTER(_vp)],
+    "vie_wait": [_vp, ctypes.c_double, _vp, ctypes.POINTER(vie_stats), _vp],
+    "vie_cancel": [_vp],
 }.items():
     getattr(_lib, _name).restype = ctypes.c_int
     getattr(_lib, _name).argtypes = _args
@@ -222,6 +229,51 @@ def vie_solve(p: int, e_inc: np.ndarray, opts: vie_opts, stats: vie_stats, want_
 def vie_solve_device(p: int, e_inc, opts: vie_opts, e_tot, pol, stats: vie_stats, stream=None) -> int:
     return _check(_lib.vie_solve_device(p, _dev(e_inc), ctypes.byref(opts), _dev(e_tot), _dev(pol),
                                         ctypes.byref(stats), _stream(stream)), "vie_solve_device", warn_ok=True)
+
+
+def _host_problem_arrays(eps, block_id):
+    e = np.ascontiguousarray(eps, dtype=np.complex128)
+    b = None if block_id is None else np.ascontiguousarray(block_id, dtype=np.int32)
+    return e, b
+
+
+def vie_server_start(ctx: int, slots: int, queue_cap: int) -> None:
+    _check(_lib.vie_server_start(ctx, int(slots), int(queue_cap)), "vie_server_start")
+
+
+def vie_footprint(ctx: int, grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray], n_blocks: int) -> int:
+    e, b = _host_problem_arrays(eps, block_id)
+    out = ctypes.c_size_t(0)
+    _check(_lib.vie_footprint(ctx, ctypes.byref(grid), _np_ptr(e), _np_ptr(b), int(n_blocks), ctypes.byref(out)),
+           "vie_footprint")
+    return int(out.value)
+
+
+def vie_submit(ctx: int, grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray], n_blocks: int,
+               e_inc: np.ndarray, opts: vie_opts) -> int:
+    """Queue a solve; returns the ticket (pass it to vie_wait once)."""
+    e, b = _host_problem_arrays(eps, block_id)
+    inc = np.ascontiguousarray(e_inc, dtype=np.complex128)
+    t = _vp()
+    _check(_lib.vie_submit(ctx, ctypes.byref(grid), _np_ptr(e), _np_ptr(b), int(n_blocks), _np_ptr(inc),
+                           ctypes.byref(opts), ctypes.byref(t)), "vie_submit")
+    return t.value
+
+
+def vie_wait(ticket: int, shape, timeout_s: float = -1.0):
+    """Wait for a request.  Returns (status, e_tot [3, nz, ny, nx] or None,
+    stats, times [queued, set-up, solve] in seconds); raises VieError on
+    VIE_ETIMEDOUT (the ticket stays valid) and on errors."""
+    e_tot = np.empty((3,) + tuple(shape), dtype=np.complex128)
+    st = vie_stats()
+    times = np.zeros(3, dtype=np.float64)
+    code = _check(_lib.vie_wait(ticket, float(timeout_s), _np_ptr(e_tot), ctypes.byref(st), _np_ptr(times)),
+                  "vie_wait", warn_ok=True)
+    return code, e_tot, st, times
+
+
+def vie_cancel(ticket: int) -> None:
+    _check(_lib.vie_cancel(ticket), "vie_cancel")
 
 
 # ------------------------------------------------------------------ conveniences

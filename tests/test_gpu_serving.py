@@ -1,0 +1,169 @@
+"""Request server (vie_submit / vie_wait / vie_cancel).
+
+* Requests of different grids, wavelengths, partitions and precisions run
+  concurrently; each result is bitwise the result of the same solve run
+  alone (vie_solve) in the same context: the kernels are deterministic and
+  the context shares spectra and tuned kernel choices between them.
+* Memory admission: with a budget that holds one request, requests run one
+  after another (each waits in the queue about as long as the one before
+  it ran) and still give the same results.
+* Queue limit (VIE_EBUSY), cancellation of a queued and of a running
+  request (VIE_ECANCELLED), tickets outstanding at context destruction.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_2501_13512_amd import vie as V  # noqa: E402
+
+
+def _grid(case):
+    return V.make_grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.wavelength)
+
+
+def _opts(case, prec=V.VIE_FP64, precondition=True, tol=None, maxit=None):
+    return V.make_opts(tol_outer=case.tol_outer if tol is None else tol, tol_inner=case.tol_inner,
+                       maxit_outer=case.maxit_outer if maxit is None else maxit, maxit_inner=case.maxit_inner,
+                       precondition=precondition, precision=prec)
+
+
+def _requests():
+    out = []
+    c = W.cube16()
+    out.append((c, _opts(c)))
+    out.append((c, _opts(c, prec=V.VIE_MIXED)))
+    m = W.mixed_partition(3)
+    out.append((m, _opts(m)))
+    t = W.random_tiny(51, (6, 7, 5), fill=0.8, n_blocks=2)
+    out.append((t, _opts(t, precondition=False)))
+    s = W.sphere(5, 20.0, 2.25)
+    s.tol_outer = 1e-8
+    out.append((s, _opts(s)))
+    return out
+
+
+def _submit(ctx, case, opts):
+    e = V.vie_plane_wave(_grid(case), case.kdir, case.pol)
+    blocks = case.block_id if opts.precondition else None
+    return V.vie_submit(ctx, _grid(case), case.eps, blocks, case.n_blocks if opts.precondition else 0, e, opts)
+
+
+def _slow():
+    """A request that runs for a while without converging or breaking down:
+    the plasmonic cell without preconditioner (about 2000 steps to 1e-6)."""
+    case = W.by_name("plasmonic")
+    return case, _opts(case, precondition=False, tol=1e-9, maxit=1500)
+
+
+def _alone(ctx, case, opts):
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=ctx)
+    try:
+        st = V.vie_stats()
+        code, e_tot, _ = V.vie_solve(P.handle, V.vie_plane_wave(P.grid, case.kdir, case.pol), opts, st)
+        return code, e_tot, st
+    finally:
+        P.close()
+
+
+@pytest.fixture
+def ctx():
+    c = V.vie_context_create(0)
+    yield c
+    V.vie_context_destroy(c)
+
+
+def test_mixed_requests_match_solves_alone(ctx):
+    V.vie_server_start(ctx, 4, 64)
+    reqs = _requests()
+    tickets = [_submit(ctx, c, o) for c, o in reqs]
+    got = [V.vie_wait(t, c.shape) for t, (c, _) in zip(tickets, reqs)]
+    for (case, opts), (code, e_tot, st, times) in zip(reqs, got):
+        code0, e0, st0 = _alone(ctx, case, opts)
+        assert code == code0 == V.VIE_OK, (case.name, code, code0)
+        assert st.outer_iters == st0.outer_iters
+        assert np.array_equal(e_tot, e0), case.name
+        assert times[2] > 0
+
+
+def test_memory_admission_serialises_requests():
+    case = W.cube16()
+    opts = _opts(case)
+    c0 = V.vie_context_create(0)
+    try:
+        need = V.vie_footprint(c0, _grid(case), case.eps, case.block_id, case.n_blocks)
+        _, ref, _ = _alone(c0, case, opts)   # also fills the spectra cache of c0
+        need_cached = V.vie_footprint(c0, _grid(case), case.eps, case.block_id, case.n_blocks)
+        assert 0 < need_cached <= need
+    finally:
+        V.vie_context_destroy(c0)
+    c = V.vie_context_create(0, hbm_budget_bytes=need + need // 2)   # room for one request at a time
+    try:
+        V.vie_server_start(c, 4, 16)
+        tickets = [_submit(c, case, opts) for _ in range(3)]
+        res = [V.vie_wait(t, case.shape) for t in tickets]
+        for code, e_tot, st, times in res:
+            assert code == V.VIE_OK
+            assert np.array_equal(e_tot, ref)
+        # one at a time: each later request queued at least as long as most of
+        # an earlier one's set-up + solve
+        run0 = res[0][3][1] + res[0][3][2]
+        assert res[1][3][0] >= 0.5 * run0
+        assert res[2][3][0] >= res[1][3][0]
+    finally:
+        V.vie_context_destroy(c)
+
+
+def test_request_larger_than_budget_is_rejected():
+    case = W.cube16()
+    c = V.vie_context_create(0, hbm_budget_bytes=1 << 20)
+    try:
+        with pytest.raises(V.VieError) as e:
+            _submit(c, case, _opts(case))
+        assert e.value.code == V.VIE_EINVAL
+    finally:
+        V.vie_context_destroy(c)
+
+
+def test_queue_full_cancel_and_outstanding_tickets(ctx):
+    V.vie_server_start(ctx, 1, 1)
+    scase, slow = _slow()
+    case = W.cube16()
+    a = _submit(ctx, scase, slow)
+    # wait until a has left the queue (it is running), then fill the queue
+    for _ in range(200):
+        b = None
+        try:
+            b = _submit(ctx, case, _opts(case))
+            break
+        except V.VieError as e:
+            assert e.value.code == V.VIE_EBUSY
+            import time
+            time.sleep(0.01)
+    assert b is not None
+    with pytest.raises(V.VieError) as e:
+        _submit(ctx, case, _opts(case))
+    assert e.value.code == V.VIE_EBUSY
+    # tickets outstanding: the context refuses to go away
+    assert V._lib.vie_context_destroy(ctx) == V.VIE_EBUSY
+    V.vie_cancel(b)      # queued: dropped
+    V.vie_cancel(a)      # running: stops after its current outer step
+    for t, c in ((b, case), (a, scase)):
+        with pytest.raises(V.VieError) as e:
+            V.vie_wait(t, c.shape)
+        assert e.value.code == V.VIE_ECANCELLED
+
+
+def test_wait_timeout_keeps_ticket(ctx):
+    V.vie_server_start(ctx, 1, 4)
+    case, slow = _slow()
+    t = _submit(ctx, case, slow)
+    with pytest.raises(V.VieError) as e:
+        V.vie_wait(t, case.shape, timeout_s=0.0)
+    assert e.value.code == V.VIE_ETIMEDOUT
+    code, e_tot, st, _ = V.vie_wait(t, case.shape)
+    assert code == V.VIE_NOT_CONVERGED
+    assert st.outer_iters == 1500
+    assert np.all(np.isfinite(e_tot))
