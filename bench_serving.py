@@ -1,0 +1,162 @@
+"""Batched-sweep and serving measurements with libvie's request server.
+
+  python bench_serving.py sweep  [--n 64] [--slots 4]
+  python bench_serving.py stream [--rate 5] [--n 200] [--max-voxels N] [--slots 4]
+
+sweep: the solves of the batched sweep (workloads.sweep_case, mixed
+precision, block preconditioner, outer tol 1e-6, inner 1e-2) all submitted
+at once.  stream: a Poisson request stream (workloads.arrivals /
+serving_request) replayed in real time; requests larger than --max-voxels
+are left out of the measured stream (stated in the output).
+
+Each request goes through vie_submit / vie_wait with host arrays (set-up,
+upload and download included).  Reported: solves/s (requests / time from
+the first arrival to the last result), latency p50/p99 (arrival to result on
+the host), and the same figures for the plain FP64 GPU path run one request
+at a time in arrival order (FIFO, each request's FP64 solve timed alone),
+plus the largest relative field difference between a served result and
+its FP64 solve.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def _grid(V, c):
+    return V.make_grid(c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.wavelength)
+
+
+def _opts(V, W, c, precision):
+    pre = W.request_precondition(c)
+    return V.make_opts(tol_outer=c.tol_outer, tol_inner=c.tol_inner, maxit_outer=c.maxit_outer,
+                       maxit_inner=c.maxit_inner, precondition=pre, precision=precision)
+
+
+def served(V, W, ctx, cases, arrive):
+    """Replay the arrivals; returns per-request (status, latency s, e_tot,
+    times) in submission order."""
+    n = len(cases)
+    out = [None] * n
+    t0 = time.perf_counter()
+
+    def waiter(k, ticket, c):
+        code, e_tot, st, times = V.vie_wait(ticket, c.shape)
+        out[k] = (code, time.perf_counter() - t0 - arrive[k], e_tot, times, st.outer_iters)
+        print(f"served {k}: {V.STATUS_NAMES.get(code, code)} {c.nx}x{c.ny}x{c.nz} outer {st.outer_iters} "
+              f"latency {out[k][1]:.2f} s", file=sys.stderr, flush=True)
+
+    threads = []
+    for k, c in enumerate(cases):
+        delay = arrive[k] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        pre = W.request_precondition(c)
+        e = V.vie_plane_wave(_grid(V, c), c.kdir, c.pol)
+        t = V.vie_submit(ctx, _grid(V, c), c.eps, c.block_id if pre else None, c.n_blocks if pre else 0, e,
+                         _opts(V, W, c, V.VIE_MIXED))
+        th = threading.Thread(target=waiter, args=(k, t, c))
+        th.start()
+        threads.append(th)
+    for th in threads:
+        th.join()
+    return out, time.perf_counter() - t0
+
+
+def fp64_alone(V, W, ctx, c):
+    pre = W.request_precondition(c)
+    t = time.perf_counter()
+    P = V.Problem(_grid(V, c), c.eps, c.block_id if pre else None, c.n_blocks if pre else 0, ctx=ctx)
+    st = V.vie_stats()
+    code, e_tot, _ = V.vie_solve(P.handle, V.vie_plane_wave(P.grid, c.kdir, c.pol), _opts(V, W, c, V.VIE_FP64), st)
+    P.close()
+    return code, time.perf_counter() - t, e_tot
+
+
+def fifo(arrive, service):
+    end, lat = 0.0, []
+    for a, s in zip(arrive, service):
+        start = max(a, end)
+        end = start + s
+        lat.append(end - a)
+    return lat, end
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["sweep", "stream"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--rate", type=float, default=5.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-voxels", type=int, default=None)
+    args = ap.parse_args()
+
+    import workloads as W
+    from paper_2501_13512_amd import vie as V
+
+    if args.mode == "sweep":
+        n = args.n or 64
+        cases = [W.sweep_case(b) for b in range(n)]
+        arrive = np.zeros(n)
+        skipped = []
+    else:
+        n = args.n or 200
+        arrive_all = W.arrivals(args.rate, n)
+        cases, arrive, skipped = [], [], []
+        for i in range(n):
+            c = W.serving_request(args.rate, i)
+            if args.max_voxels and c.nx * c.ny * c.nz > args.max_voxels:
+                skipped.append(i)
+                continue
+            cases.append(c)
+            arrive.append(arrive_all[i])
+        arrive = np.asarray(arrive)
+        arrive -= arrive[0]
+
+    ctx = V.vie_context_create(0)
+    V.vie_server_start(ctx, args.slots, max(1024, len(cases)))
+    res, wall = served(V, W, ctx, cases, arrive)
+    lat = np.array([r[1] for r in res])
+    codes = [r[0] for r in res]
+    span = float(max(arrive[k] + lat[k] for k in range(len(cases))) - arrive[0])
+
+    service, diffs = [], []
+    for k, c in enumerate(cases):
+        code, secs, e64 = fp64_alone(V, W, ctx, c)
+        service.append(secs)
+        print(f"fp64 alone {k}: {V.STATUS_NAMES.get(code, code)} {secs:.2f} s", file=sys.stderr, flush=True)
+        e_mix = res[k][2]
+        diffs.append(float(np.linalg.norm(e_mix - e64) / max(np.linalg.norm(e64), 1e-300)))
+    blat, bend = fifo(arrive, service)
+    V.vie_context_destroy(ctx)
+
+    out = {
+        "mode": args.mode, "n": len(cases), "slots": args.slots,
+        "rate_req_per_s": None if args.mode == "sweep" else args.rate,
+        "skipped_requests": skipped, "max_voxels": args.max_voxels,
+        "grids": sorted({f"{c.nx}x{c.ny}x{c.nz}" for c in cases}),
+        "served_mixed": {"solves_per_s": len(cases) / span, "latency_ms": {
+            "p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
+            "status_counts": {V.STATUS_NAMES.get(s, s): codes.count(s) for s in set(codes)},
+            "mean_queue_s": float(np.mean([r[3][0] for r in res])),
+            "mean_setup_s": float(np.mean([r[3][1] for r in res])),
+            "mean_solve_s": float(np.mean([r[3][2] for r in res]))},
+        "plain_fp64_sequential": {"solves_per_s": len(cases) / bend, "latency_ms": {
+            "p50": 1e3 * float(np.percentile(blat, 50)), "p99": 1e3 * float(np.percentile(blat, 99))},
+            "mean_service_s": float(np.mean(service))},
+        "max_rel_field_diff_mixed_vs_fp64": max(diffs),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -39,7 +39,8 @@ import numpy as np
 
 __all__ = [
     "Case", "cube16", "metasurface", "plasmonic", "sweep_case", "sweep",
-    "sphere", "random_tiny", "mixed_partition", "CASES", "by_name",
+    "sphere", "random_tiny", "mixed_partition", "SERVING_GRIDS", "SERVING_RATES", "arrivals", "serving_request",
+    "request_precondition", "CASES", "by_name",
 ]
 
 
@@ -285,6 +286,86 @@ def mixed_partition(seed: int = 0) -> Case:
     return Case(f"mixed_partition{seed}", nx, ny, nz, d, d, d, 1.0, eps.astype(np.complex128), bid, 6,
                 tol_outer=1e-6, tol_inner=1e-3, precision="fp64",
                 note="two block box shapes (8x8x8 and 4x8x8)")
+
+
+SERVING_GRIDS = [(32, 32, 32), (48, 48, 48), (64, 64, 32), (96, 96, 32), (128, 128, 32), (128, 128, 64),
+                 (256, 256, 64)]
+SERVING_RATES = (1, 2, 5, 10, 20, 50)
+
+
+def arrivals(rate: float, n: int = 200) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream: cumulative sums of
+    ``default_rng(5000 + rate).exponential(1 / rate, n)``."""
+    rng = np.random.default_rng(5000 + int(rate))
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def serving_request(rate: float, i: int) -> Case:
+    """Request ``i`` of the stream at ``rate``.
+
+    ``rng = default_rng([5000 + rate, i])``; draws in order: grid index
+    ``rng.integers(7)`` into SERVING_GRIDS; wavelength ``rng.uniform(400,
+    800)`` nm with spacing 20 nm; kind ``rng.integers(2)``.
+    Kind 0, dielectric pillars: one per 16x16-voxel xy cell (row by row), eps
+    ``rng.uniform(2, 6)``, radius ``rng.uniform(0.25, 0.45) * 16`` voxels,
+    height ``rng.uniform(0.5, 1) * nz`` from z = 0; one block per pillar;
+    mixed precision with the block preconditioner, outer tol 1e-6, inner
+    1e-2.
+    Kind 1, plasmonic cell (the 96x96x64 cell scaled to the grid): slab
+    z < 3 nz / 8 with eps 12 - 0.5j, absorbing layer above with eps
+    3.0 - 0.3j, metal spheres eps -15 - 1.0j on a 24-voxel xy lattice
+    centred at z = 3 nz / 8 + 5 nz / 16, radius ``rng.integers(6, 11) * nz /
+    64`` voxels (at least 2) each; spacing lambda / 40 as in that cell (20 nm
+    under-resolves the metal); blocks per sphere, layer and slab; mixed
+    precision without preconditioner (the block preconditioner stalls on
+    metal-sphere blocks), outer tol 1e-6, at most 6000 outer steps.
+    """
+    rng = np.random.default_rng([5000 + int(rate), int(i)])
+    nx, ny, nz = SERVING_GRIDS[int(rng.integers(len(SERVING_GRIDS)))]
+    lam = float(rng.uniform(400.0, 800.0))
+    kind = int(rng.integers(2))
+    d = 20.0
+    eps = np.ones((nz, ny, nx), dtype=np.complex128)
+    bid = np.full((nz, ny, nx), -1, dtype=np.int32)
+    zc, yc, xc = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    nb = 0
+    if kind == 0:
+        for iy in range(ny // 16):
+            for ix in range(nx // 16):
+                e = float(rng.uniform(2.0, 6.0))
+                r = float(rng.uniform(0.25, 0.45)) * 16.0
+                h = float(rng.uniform(0.5, 1.0)) * nz
+                cx, cy = 16 * ix + 8.0, 16 * iy + 8.0
+                inside = ((xc - cx) ** 2 + (yc - cy) ** 2 <= r * r) & (zc <= h)
+                eps[inside] = e
+                bid[inside] = nb
+                nb += 1
+        return Case(f"req{rate}_{i}", nx, ny, nz, d, d, d, lam, eps, bid, nb, tol_outer=1e-6, tol_inner=1e-2,
+                    precision="mixed", note=f"serving request: pillars {nx}x{ny}x{nz}, lambda {lam:.1f} nm")
+    d = lam / 40.0
+    zs = (3 * nz) // 8
+    eps[:zs] = 12.0 - 0.5j
+    bid[:zs] = 0
+    eps[zs:] = 3.0 - 0.3j
+    bid[zs:] = 1
+    nb = 2
+    cz = zs + 5.0 * nz / 16.0
+    for iy in range(max(1, ny // 24)):
+        for ix in range(max(1, nx // 24)):
+            r = max(2.0, float(rng.integers(6, 11)) * nz / 64.0)
+            cx, cy = 24 * ix + 12.0, 24 * iy + 12.0
+            inside = (xc - cx) ** 2 + (yc - cy) ** 2 + (zc - cz) ** 2 <= r * r
+            eps[inside] = -15.0 - 1.0j
+            bid[inside] = nb
+            nb += 1
+    return Case(f"req{rate}_{i}", nx, ny, nz, d, d, d, lam, eps, bid, nb, tol_outer=1e-6, tol_inner=3e-2,
+                maxit_outer=6000, precision="mixed",
+                note=f"serving request: plasmonic cell {nx}x{ny}x{nz}, lambda {lam:.1f} nm")
+
+
+def request_precondition(case: Case) -> bool:
+    """Solver choice of a serving request (see serving_request)."""
+    return "pillars" in case.note or case.name.startswith("sweep")
 
 
 CASES = {"cube16": cube16, "metasurface": metasurface, "plasmonic": plasmonic}
