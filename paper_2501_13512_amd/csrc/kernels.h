@@ -45,8 +45,12 @@ struct MvmBatch {
   cx<R>* work;
   const int* status;       // per system; null = always active
   const TwiddleSet<R>* tw; // host-side pointer table (values are device pointers)
-  int zvariant;            // z-pass kernel variant (0 column sets, 1 mirror columns)
+  int zvariant;            // z-pass kernel variant (see tune_zpass)
+  int plane;               // 1: x and y transforms fused per z-plane (plane_supported(lx, ly))
 };
+
+// Square transforms small enough for the fused plane kernels.
+bool plane_supported(int lx, int ly);
 
 // y = A x for every active system of the batch (Sec. I Toeplitz + FFT;
 // eqs. (2)-(4)).  `mask_input` zeroes x where 1/chi = 0 before transforming.

@@ -254,6 +254,232 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
   }
 }
 
+// ------------------------------------------------------------------ plane passes
+// Small square transforms (lx = ly <= 64): the x and y transforms of a
+// z-plane run in one kernel with the plane in LDS, so passes 1 + 2 become
+// k_plane_fwd and passes 4 + 5 become k_plane_inv_local (one launch and one
+// trip through HBM fewer each way; same BiCGSTAB fusion as the row kernels).
+// A workgroup takes NPL consecutive planes (c, z) of one system; LDS holds
+// them as [NPL][L][L + 1] (rows padded against bank conflicts on columns).
+template <typename R, int L>
+struct PlaneGeo {
+  static constexpr int ES = (int)sizeof(cx<R>);
+  static constexpr int LP = L + 1;
+  static constexpr int NPL = cmax(1, cmin(16, (48 * 1024) / (L * LP * ES)));
+  static constexpr int BT = 256;
+  static constexpr int T = PlanInfo<L>::max_butterflies;
+  static constexpr int PP = BT / T;
+  static_assert(BT % T == 0, "pencil threads must divide the workgroup");
+};
+
+template <typename R, int L>
+__global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_fwd(RowArgs<R> a) {
+  using G = PlaneGeo<R, L>;
+  constexpr int T = G::T, PP = G::PP, LP = G::LP, NPL = G::NPL, BT = G::BT;
+  __shared__ cx<R> lds[NPL * L * LP];
+  const int planes = 3 * a.nz;
+  const int tiles = (planes + NPL - 1) / NPL;
+  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  if (!sys_active(a.status, sys)) return;
+  const int pl0 = tile * NPL, npl = min(NPL, planes - pl0);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int pe = ny * nx;
+  const int ne = npl * pe;
+  const int64_t v0 = sys * a.vstride + (int64_t)pl0 * pe;
+  const int mode = a.in_mode;
+  double acc = 0.0;
+  // zero the padding columns [nx, L) of rows y < ny
+  const int padw = L - nx;
+  for (int e = threadIdx.x; e < npl * ny * padw; e += BT) {
+    const int row = e / padw, xx = nx + (e - row * padw);
+    lds[row / ny * L * LP + (row % ny) * LP + xx] = czero<R>();
+  }
+  auto lds_at = [&](int e) -> cx<R>* {
+    const int q = e / pe, rem = e - q * pe, y = rem / nx;
+    return lds + (q * L + y) * LP + (rem - y * nx);
+  };
+  if (mode == 0) {
+    const c128* chi = a.chi_inv + sys * a.cstride;
+    const bool msk = a.mask_input != 0;
+    for (int e = threadIdx.x; e < ne; e += BT) {
+      c128 v = a.x[v0 + e];
+      if (msk) {
+        const int q = e / pe;
+        const int z = (pl0 + q) % nz;
+        const c128 ci = chi[(int64_t)z * pe + (e - q * pe)];
+        if (ci.x == 0.0 && ci.y == 0.0) v = mk<double>(0.0, 0.0);
+      }
+      *lds_at(e) = cvt<R>(v);
+    }
+  } else {
+    const KState& ks = a.k.st[sys];
+    const bool first = mode == 1 && ks.iters == 0;
+    const c128 c1 = mode == 1 ? ks.beta : ks.alpha;
+    const c128 c2 = ks.omega;
+    constexpr int CH = 4;
+    for (int e0 = 0; e0 < ne; e0 += CH * BT) {
+      c128 rv[CH], pv[CH], vv[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = e0 + u * BT + (int)threadIdx.x;
+        if (e < ne) {
+          rv[u] = a.r[v0 + e];
+          if (!first) vv[u] = a.v[v0 + e];
+          if (mode == 1 && !first) pv[u] = a.p[v0 + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = e0 + u * BT + (int)threadIdx.x;
+        if (e < ne) {
+          c128 val;
+          if (mode == 1)
+            val = first ? rv[u] : rv[u] + c1 * (pv[u] - c2 * vv[u]);   // p = r + beta (p - omega v)
+          else
+            val = rv[u] - c1 * vv[u];                                    // s = r - alpha v
+          a.p[v0 + e] = val;
+          *lds_at(e) = cvt<R>(val);
+          acc += abs2(val);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // x transforms of the rows y < ny, in place
+  {
+    const int p = threadIdx.x / T, t = threadIdx.x - p * T;
+    const int nrows = npl * ny;
+    for (int r0 = 0; r0 < nrows; r0 += PP) {
+      const int row = r0 + p;
+      const bool valid = p < PP && row < nrows;
+      const int rr = valid ? row : 0;
+      cx<R>* slot = lds + (rr / ny * L + rr % ny) * LP;
+      auto ld = [&](int n) -> cx<R> { return slot[n]; };
+      auto st = [&](int k, cx<R> v) { slot[k] = v; };
+      fft_pencil<R, L, T, -1, true, true>(ld, st, slot, 1, t, valid, a.tw);
+    }
+  }
+  // y transforms of the L columns (rows >= ny are zero), out to HBM
+  {
+    const int p = threadIdx.x % PP, t = threadIdx.x / PP;
+    const int ncols = npl * L;
+    cx<R>* w = a.work + sys * a.wstride + (int64_t)pl0 * L * L;
+    for (int c0 = 0; c0 < ncols; c0 += PP) {
+      const int col = c0 + p;
+      const bool valid = t < T && col < ncols;
+      const int cc = valid ? col : 0;
+      const int q = cc / L, xq = cc - q * L;
+      cx<R>* slot = lds + q * L * LP + xq;
+      cx<R>* wc = w + (int64_t)q * L * L + xq;
+      auto ld = [&](int n) -> cx<R> { return n < ny ? slot[n * LP] : czero<R>(); };
+      auto st = [&](int k, cx<R> v) { wc[k * L] = v; };
+      fft_pencil<R, L, T, -1, true, false>(ld, st, slot, LP, t, valid, a.tw);
+    }
+  }
+  if (mode == 2) {
+    double sum[1] = {acc};
+    write_partial<1>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
+  }
+}
+
+template <typename R, int L>
+__global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArgs<R> a) {
+  using G = PlaneGeo<R, L>;
+  constexpr int T = G::T, PP = G::PP, LP = G::LP, NPL = G::NPL, BT = G::BT;
+  __shared__ cx<R> lds[NPL * L * LP];
+  const int planes = 3 * a.nz;
+  const int tiles = (planes + NPL - 1) / NPL;
+  const int sys = blockIdx.x / tiles, tile = blockIdx.x - sys * tiles;
+  if (!sys_active(a.status, sys)) return;
+  const int pl0 = tile * NPL, npl = min(NPL, planes - pl0);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int pe = ny * nx;
+  const int ne = npl * pe;
+  const int64_t v0 = sys * a.vstride + (int64_t)pl0 * pe;
+  // y inverse of the L columns from HBM, rows k < ny kept in LDS
+  {
+    const int p = threadIdx.x % PP, t = threadIdx.x / PP;
+    const int ncols = npl * L;
+    const cx<R>* w = a.work + sys * a.wstride + (int64_t)pl0 * L * L;
+    for (int c0 = 0; c0 < ncols; c0 += PP) {
+      const int col = c0 + p;
+      const bool valid = t < T && col < ncols;
+      const int cc = valid ? col : 0;
+      const int q = cc / L, xq = cc - q * L;
+      cx<R>* slot = lds + q * L * LP + xq;
+      const cx<R>* wc = w + (int64_t)q * L * L + xq;
+      auto ld = [&](int n) -> cx<R> { return wc[n * L]; };
+      auto st = [&](int k, cx<R> v) {
+        if (k < ny) slot[k * LP] = v;
+      };
+      fft_pencil<R, L, T, +1, false, true>(ld, st, slot, LP, t, valid, a.tw);
+    }
+  }
+  // x inverse of the rows y < ny, in place, cropped to nx
+  {
+    const int p = threadIdx.x / T, t = threadIdx.x - p * T;
+    const int nrows = npl * ny;
+    for (int r0 = 0; r0 < nrows; r0 += PP) {
+      const int row = r0 + p;
+      const bool valid = p < PP && row < nrows;
+      const int rr = valid ? row : 0;
+      cx<R>* slot = lds + (rr / ny * L + rr % ny) * LP;
+      auto ld = [&](int n) -> cx<R> { return slot[n]; };
+      auto st = [&](int k, cx<R> v) {
+        if (k < nx) slot[k] = v;
+      };
+      fft_pencil<R, L, T, +1, true, true>(ld, st, slot, 1, t, valid, a.tw);
+    }
+  }
+  // y = x/chi - scale Q on the mask, fused inner products
+  const double scale = a.scale;
+  const int mode = a.out_mode;
+  const c128* chi = a.chi_inv + sys * a.cstride;
+  double acc[3] = {0.0, 0.0, 0.0};
+  constexpr int CH = 4;
+  for (int e0 = 0; e0 < ne; e0 += CH * BT) {
+    c128 ci[CH], xv[CH], ov[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = e0 + u * BT + (int)threadIdx.x;
+      if (e < ne) {
+        const int q = e / pe;
+        ci[u] = chi[(int64_t)((pl0 + q) % nz) * pe + (e - q * pe)];
+        xv[u] = a.x[v0 + e];
+        if (mode == 1) ov[u] = a.rhat[v0 + e];
+        if (mode == 2) ov[u] = a.s[v0 + e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = e0 + u * BT + (int)threadIdx.x;
+      if (e < ne) {
+        const int q = e / pe, rem = e - q * pe, y = rem / nx;
+        const cx<R> qv = lds[(q * L + y) * LP + (rem - y * nx)];
+        c128 out = mk<double>(0.0, 0.0);
+        if (ci[u].x != 0.0 || ci[u].y != 0.0) out = xv[u] * ci[u] - scale * cvt<double>(qv);
+        a.y[v0 + e] = out;
+        if (mode == 1) {          // <rhat, y>
+          const c128 d = cdot1(ov[u], out);
+          acc[0] += d.x;
+          acc[1] += d.y;
+        } else if (mode == 2) {   // <y, s>, <y, y>
+          const c128 d = cdot1(out, ov[u]);
+          acc[0] += d.x;
+          acc[1] += d.y;
+          acc[2] += abs2(out);
+        }
+      }
+    }
+  }
+  if (mode == 1) {
+    double sum[2] = {acc[0], acc[1]};
+    write_partial<2>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
+  } else if (mode == 2) {
+    write_partial<3>(acc, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
+  }
+}
+
 // In-place FFT of full-length rows (spectra setup).
 template <typename R, int L>
 __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_full(cx<R>* data, int64_t rows,
@@ -705,6 +931,38 @@ static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
   check_launch("z pass");
 }
 
+#define VIE_PLANE_CASES(F) F(8) F(12) F(16) F(24) F(32) F(48) F(64)
+
+bool plane_supported(int lx, int ly) {
+  if (lx != ly) return false;
+#define C(l) \
+  if (lx == l) return true;
+  VIE_PLANE_CASES(C)
+#undef C
+  return false;
+}
+
+template <typename R>
+static void launch_plane(bool fwd, int L, const RowArgs<R>& a, int nsys, hipStream_t s) {
+  switch (L) {
+#define C(l)                                                                                      \
+  case l: {                                                                                       \
+    using G = PlaneGeo<R, l>;                                                                     \
+    const int tiles = (3 * a.nz + G::NPL - 1) / G::NPL;                                           \
+    if (fwd)                                                                                      \
+      hipLaunchKernelGGL((k_plane_fwd<R, l>), dim3(tiles * nsys), dim3(G::BT), 0, s, a);          \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_plane_inv_local<R, l>), dim3(tiles * nsys), dim3(G::BT), 0, s, a);    \
+    break;                                                                                        \
+  }
+    VIE_PLANE_CASES(C)
+#undef C
+    default:
+      bad_length("plane pass", L);
+  }
+  check_launch("plane pass");
+}
+
 static void mark(hipEvent_t* ev, int i, hipStream_t s) {
   if (ev && hipEventRecord(ev[i], s) != hipSuccess) throw std::runtime_error("hipEventRecord failed");
 }
@@ -747,7 +1005,10 @@ void mvm_pass1(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c
     throw std::runtime_error("mvm_pass1: missing fused vectors");
   RowArgs<R> ra = row_args<R>(b, k, f, x, nullptr, mask_input);
   ra.in_mode = f.in_mode;
-  launch_row_fwd<R>(b.lx, ra, b.nsys, s);
+  if (b.plane)
+    launch_plane<R>(true, b.lx, ra, b.nsys, s);
+  else
+    launch_row_fwd<R>(b.lx, ra, b.nsys, s);
 }
 
 template <typename R>
@@ -763,7 +1024,7 @@ void mvm_mid(const MvmBatch<R>& b, hipStream_t s) {
   ca.status = b.status;
   ca.tw = b.tw->table[b.ly];
   ca.nsys = b.nsys;
-  launch_col<R, -1>(b.ly, ca, s);
+  if (!b.plane) launch_col<R, -1>(b.ly, ca, s);
 
   ZArgs<R> za{};
   za.nz = b.nz;
@@ -780,7 +1041,7 @@ void mvm_mid(const MvmBatch<R>& b, hipStream_t s) {
 
   ca.n_in = b.ly;
   ca.n_out = b.ny;
-  launch_col<R, +1>(b.ly, ca, s);
+  if (!b.plane) launch_col<R, +1>(b.ly, ca, s);
 }
 
 template <typename R>
@@ -791,7 +1052,10 @@ void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c
     throw std::runtime_error("mvm_pass5: missing fused vectors");
   RowArgs<R> ra = row_args<R>(b, k, f, x, y, false);
   ra.out_mode = f.out_mode;
-  launch_row_inv<R>(b.lx, ra, b.nsys, s);
+  if (b.plane)
+    launch_plane<R>(false, b.lx, ra, b.nsys, s);
+  else
+    launch_row_inv<R>(b.lx, ra, b.nsys, s);
 }
 
 template <typename R>
@@ -815,7 +1079,7 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
     ca.status = b.status;
     ca.tw = b.tw->table[b.ly];
     ca.nsys = b.nsys;
-    launch_col<R, -1>(b.ly, ca, s);
+    if (!b.plane) launch_col<R, -1>(b.ly, ca, s);
     mark(ev, 2, s);
     ZArgs<R> za{};
     za.nz = b.nz;
@@ -832,7 +1096,7 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
     mark(ev, 3, s);
     ca.n_in = b.ly;
     ca.n_out = b.ny;
-    launch_col<R, +1>(b.ly, ca, s);
+    if (!b.plane) launch_col<R, +1>(b.ly, ca, s);
     mark(ev, 4, s);
   }
   mvm_pass5<R>(b, nullptr, none, x, y, s);
@@ -896,6 +1160,17 @@ VIE_MVM_INST(double)
 
 int64_t mvm_row_tiles(int lx, int nz, int ny) {
   const int64_t rows = 3 * (int64_t)nz * ny;
+  if (plane_supported(lx, lx)) {   // plane kernels: at most one workgroup per plane
+    switch (lx) {
+#define C(l)                                                                                 \
+  case l: {                                                                                  \
+    const int rp = cmin(Geo<float, l>::ROWP, Geo<double, l>::ROWP);                          \
+    return std::max<int64_t>((rows + rp - 1) / rp, 3 * (int64_t)nz);                        \
+  }
+      VIE_PLANE_CASES(C)
+#undef C
+    }
+  }
   switch (lx) {
 #define C(l)                                                                            \
   case l: {                                                                             \

@@ -352,6 +352,7 @@ MvmBatch<R> outer_batch(vie_problem& P, bool gated) {
   b.status = gated ? P.ostatus.as<int>() : nullptr;
   b.tw = tw_set<R>(P.ctx);
   b.zvariant = P.zvar[sizeof(R) == sizeof(float) ? 1 : 0];
+  b.plane = vie::plane_supported(b.lx, b.ly) ? 1 : 0;
   return b;
 }
 
@@ -375,6 +376,7 @@ MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
   b.status = gated ? P.d_istatus.as<int>() + G.slot0 : nullptr;
   b.tw = tw_set<R>(P.ctx);
   b.zvariant = G.zvar[sizeof(R) == sizeof(float) ? 1 : 0];
+  b.plane = vie::plane_supported(b.lx, b.ly) ? 1 : 0;
   return b;
 }
 
