@@ -84,26 +84,21 @@ def mvm_profile(V, handle, info, nx, ny, nz, prec, reps):
             "dominant": {"kernel": names[dom], "achieved": achieved, "bytes": pb[dom], "ms": float(ms[dom])}}
 
 
-def traffic_for(kernel, workload):
+def traffic_for(kernel, workload, precision, lz):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel
     calibration), or None if no summary covers this kernel build."""
+    from paper_2501_13512_amd.profile_traffic import kernel_hash
     path = os.path.join(ROOT, "profiles", "mvm_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
+    h = kernel_hash()
     for e in d.get("entries", []):
-        if e.get("kernel") == kernel and e.get("workload") == workload and e.get("source_hash") == _kernel_hash():
+        if (e.get("kernel") == kernel and e.get("workload") == workload and e.get("source_hash") == h
+                and e.get("precision") == precision and e.get("lz") == lz):
             return e.get("bytes_per_launch")
     return None
-
-
-def _kernel_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("mvm.hip", "fft_core.h", "kernels.h", "cx.h"):
-        h.update(open(os.path.join(ROOT, "paper_2501_13512_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
 
 
 def golden_error(case, e_tot):
@@ -163,6 +158,8 @@ def main():
                          "tight solve, 2e-6 brings it under 1e-5")
     ap.add_argument("--compare-steps", type=int, default=3,
                     help="solves of each FP64 comparison path (block-preconditioned, unpreconditioned); 0 = skip")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also copy 512 MiB device to device three times (reference kernel for HBM counters)")
     ap.add_argument("--mvm-shapes", default="256x256x64",
                     help="extra grids (comma-separated NXxNYxNZ, '' for none) whose full-grid product is timed per pass")
     args = ap.parse_args()
@@ -237,7 +234,7 @@ def main():
     mv = mvm_profile(V, P.handle, info, case.nx, case.ny, case.nz, prec, args.profile_reps)
     dom = mv["dominant"]
     wl = f"{case.name} {case.nx}x{case.ny}x{case.nz} {args.precision}"
-    traffic = traffic_for(dom["kernel"], wl)
+    traffic = traffic_for(dom["kernel"], wl, "float" if prec == V.VIE_MIXED else "double", info.lz)
     extra = {}
     for spec in [v for v in args.mvm_shapes.split(",") if v]:
         nx, ny, nz = (int(v) for v in spec.split("x"))
@@ -249,6 +246,15 @@ def main():
         for p in extra[spec].values():
             p["frac_of_hbm_peak"] = p["algorithmic_GBps"] / HBM_PEAK_GBS
         Q.close()
+
+    if args.calibration_copy:
+        ca = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        cb = torch.empty_like(ca)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            cb.copy_(ca)
+        torch.cuda.synchronize()
+        del ca, cb
 
     res = {
         "metric": "solves/s at 1e-5 rel field err + MVM HBM GB/s vs peak; p50/p99 solve latency",

@@ -154,7 +154,7 @@ struct PlanInfo {
 // Twiddle table tw[t] = exp(-2 pi i t / L), t < L, in HBM (shared, cached).
 template <int DIR, typename R>
 __device__ __forceinline__ cx<R> twiddle(const cx<R>* __restrict__ tw, int idx) {
-  cx<R> w = tw[idx];
+  cx<R> w = tw[(unsigned)idx];   // unsigned 32-bit offset from a uniform base
   return DIR < 0 ? w : conj(w);
 }
 

@@ -557,6 +557,18 @@ __device__ __forceinline__ FoldCol fold_col(int f, int m, int L) {
   return {-1, 0, 1};
 }
 
+// Element i of an array whose byte size is below 4 GiB: the byte offset is
+// formed in 32 bits, so the access can use a uniform base register plus a
+// 32-bit per-lane offset.
+template <typename T>
+__device__ __forceinline__ T* elem(T* base, unsigned i) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T* elem(const T* base, unsigned i) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+
 // Workgroup b of n runs on XCD b % 8 (round-robin dispatch).  Renumber so
 // that each XCD takes one contiguous range of the logical order: work that
 // shares data then shares that XCD's L2.
@@ -722,7 +734,7 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   __shared__ cx<R> lds[3 * LZ * ZP];
   const int cols = a.ly * a.lx;
   const int tiles = (cols + ZP - 1) / ZP;
-  const int g = xcd_chunked(blockIdx.x, gridDim.x);
+  const int g = __builtin_amdgcn_readfirstlane(xcd_chunked(blockIdx.x, gridDim.x));   // uniform
   const int sys = g / tiles, tile = g - sys * tiles;
   if (!sys_active(a.status, sys)) return;
   const int comp = threadIdx.x / (T * ZP);
@@ -730,13 +742,16 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   const int p = rem % ZP, t = rem / ZP;
   const int col = tile * ZP + p;   // logical column
   const bool valid = col < cols;
-  const int64_t plane = (int64_t)a.ly * a.lx;
-  int pcol = 0;                    // its place in the plane
+  // element offsets in 32 bits from the system's base (one system's work
+  // buffer holds < 2^31 elements), so loads use a uniform base + offset
+  const unsigned plane = (unsigned)a.ly * (unsigned)a.lx;
+  unsigned pcol = 0;               // its place in the plane
   if (valid) {
     const int i = col / a.lx;
-    pcol = mirror_paired_row(i, a.ly) * a.lx + (col - i * a.lx);
+    pcol = (unsigned)(mirror_paired_row(i, a.ly) * a.lx + (col - i * a.lx));
   }
-  cx<R>* base = a.work + sys * a.wstride + (int64_t)comp * a.nz * plane + pcol;
+  cx<R>* const wsys = a.work + sys * a.wstride;
+  const unsigned coff = (unsigned)comp * (unsigned)a.nz * plane + pcol;
   cx<R>* slot = lds + comp * LZ * ZP + p;
   const int nz = a.nz;
 
@@ -751,24 +766,26 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   const int c2 = tile * ZP + pp;
   const bool cvalid = c2 < cols;
   R sx = R(1), sy = R(1);
-  const cx<R>* sp = a.spec + sys * a.sstride;
+  const cx<R>* const sp = a.spec + sys * a.sstride;
+  unsigned soff = 0;
   if (cvalid) {
     const int i2 = c2 / lx;
     const int qy = mirror_paired_row(i2, ly), qx = c2 - i2 * lx;
     const int fx = qx <= hx ? qx : lx - qx, fy = qy <= hy ? qy : ly - qy;
     sx = qx <= hx ? R(1) : R(-1);
     sy = qy <= hy ? R(1) : R(-1);
-    sp += (int64_t)fy * ox + fx;
+    soff = (unsigned)(fy * ox + fx);
   }
+  const unsigned oct32 = (unsigned)oct, fzs = (unsigned)(oy * ox);
   // spectrum values (xx, xy, xz, yy, yz, zz, parity signs of qx, qy applied)
   auto spec_at = [&](int fz, cx<R>* sv) {
-    const int64_t o = (int64_t)fz * oy * ox;
-    sv[0] = sp[o];
-    sv[1] = (sx * sy) * sp[oct + o];
-    sv[2] = sx * sp[2 * oct + o];
-    sv[3] = sp[3 * oct + o];
-    sv[4] = sy * sp[4 * oct + o];
-    sv[5] = sp[5 * oct + o];
+    const unsigned o = soff + (unsigned)fz * fzs;
+    sv[0] = *elem(sp, o);
+    sv[1] = (sx * sy) * *elem(sp, oct32 + o);
+    sv[2] = sx * *elem(sp, 2 * oct32 + o);
+    sv[3] = *elem(sp, 3 * oct32 + o);
+    sv[4] = sy * *elem(sp, 4 * oct32 + o);
+    sv[5] = *elem(sp, 5 * oct32 + o);
   };
   cx<R> pre[G::PF ? NF : 1][6];
   if constexpr (G::PF) {
@@ -780,7 +797,12 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   }
 
   // forward along z into the component's LDS slot
-  auto ldg = [&](int n) -> cx<R> { return n < nz ? base[n * plane] : czero<R>(); };
+  // first-stage element n = t + (a constant of the unrolled stage): offsets
+  // split into a per-thread part and a uniform part
+  const unsigned toff = coff + (unsigned)t * plane;
+  auto ldg = [&](int n) -> cx<R> {
+    return n < nz ? *elem(wsys, toff + (unsigned)(n - t) * plane) : czero<R>();
+  };
   auto sts = [&](int k, cx<R> v) { slot[k * ZP] = v; };
   fft_pencil<R, LZ, T, -1, false, true>(ldg, sts, slot, ZP, t, valid, a.tw);
 
@@ -819,7 +841,7 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   // inverse along z, cropped to nz
   auto lds_ld = [&](int n) -> cx<R> { return slot[n * ZP]; };
   auto stg = [&](int k, cx<R> v) {
-    if (k < nz) base[k * plane] = v;
+    if (k < nz) *elem(wsys, toff + (unsigned)(k - t) * plane) = v;
   };
   fft_pencil<R, LZ, T, +1, true, false>(lds_ld, stg, slot, ZP, t, valid, a.tw);
 }
