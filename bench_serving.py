@@ -50,9 +50,13 @@ def served(V, W, ctx, cases, arrive):
     t0 = time.perf_counter()
 
     def waiter(k, ticket, c):
-        code, e_tot, st, times = V.vie_wait(ticket, c.shape)
-        out[k] = (code, time.perf_counter() - t0 - arrive[k], e_tot, times, st.outer_iters)
-        print(f"served {k}: {V.STATUS_NAMES.get(code, code)} {c.nx}x{c.ny}x{c.nz} outer {st.outer_iters} "
+        try:
+            code, e_tot, st, times = V.vie_wait(ticket, c.shape)
+            iters = st.outer_iters
+        except V.VieError as err:          # the request failed: keep its status
+            code, e_tot, times, iters = err.code, np.full((3,) + c.shape, np.nan + 0j), np.zeros(3), -1
+        out[k] = (code, time.perf_counter() - t0 - arrive[k], e_tot, times, iters)
+        print(f"served {k}: {V.STATUS_NAMES.get(code, code)} {c.nx}x{c.ny}x{c.nz} outer {iters} "
               f"latency {out[k][1]:.2f} s", file=sys.stderr, flush=True)
 
     threads = []

@@ -60,8 +60,10 @@ struct DevBuf {
     hip_check(hipMalloc(&p, n), "hipMalloc");
     bytes = n;
   }
-  void zero() {
-    if (p) hip_check(hipMemset(p, 0, bytes), "hipMemset");
+  // Stream-ordered: work on `s` sees the zeros (the null stream is not
+  // ordered with the library's non-blocking streams).
+  void zero(hipStream_t s) {
+    if (p) hip_check(hipMemsetAsync(p, 0, bytes, s), "hipMemsetAsync");
   }
   void reset() {
     if (p) (void)hipFree(p);
@@ -92,9 +94,12 @@ struct DevBuf {
 };
 
 template <class T>
-void upload(DevBuf& d, const std::vector<T>& h) {
+void upload(DevBuf& d, const std::vector<T>& h, hipStream_t s) {
   d.alloc(h.size() * sizeof(T));
-  if (!h.empty()) hip_check(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  if (h.empty()) return;
+  // ordered on s and complete before h can go away
+  hip_check(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  hip_check(hipStreamSynchronize(s), "upload");
 }
 
 template <class F>
@@ -1046,24 +1051,24 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
   P->lz = pl.lz;
   P->k0 = pl.k0;
   P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0, s);
-  upload(P->chi, pl.chi);
+  upload(P->chi, pl.chi, s);
   P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
-  P->work.zero();
+  P->work.zero(s);
   P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
-  P->vecs.zero();
+  P->vecs.zero(s);
   for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
   P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
   P->partials.alloc(P->pstride * sizeof(double));
   P->ntile.alloc(sizeof(int));
-  P->ntile.zero();
+  P->ntile.zero(s);
   P->ostate.alloc(sizeof(KState));
-  P->ostate.zero();
+  P->ostate.zero(s);
   P->ostatus.alloc(sizeof(int));
-  P->ostatus.zero();
+  P->ostatus.zero(s);
   P->scal.alloc(64);
   P->d_count.alloc(sizeof(int));
   P->d_acc.alloc(3 * sizeof(int64_t));
-  P->d_acc.zero();
+  P->d_acc.zero(s);
   hip_check(hipHostMalloc((void**)&P->h_ring, 2 * kRing * sizeof(int)), "pinned ring");
   for (auto& r : P->ev)
     for (auto& e : r) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
@@ -1106,12 +1111,12 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
             }
       }
       gbox.push_back(int4{G.bx, G.by, G.bz, 0});
-      upload(G.chi, gchi);
+      upload(G.chi, gchi, s);
       G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0, s);
       G.work.alloc((size_t)G.nsys * 3 * G.bz * G.ly * G.lx * sizeof(c128));
-      G.work.zero();
+      G.work.zero(s);
       G.vecs.alloc(8 * (size_t)G.nsys * G.n * sizeof(c128));
-      G.vecs.zero();
+      G.vecs.zero(s);
       for (int q = 0; q < 8; ++q) G.vec[q] = G.vecs.as<c128>() + (size_t)q * G.nsys * G.n;
       P->ipstride =
           std::max<int64_t>(P->ipstride, 4 * std::max(vie::krylov_chunks(G.n), vie::mvm_row_tiles(G.lx, G.bz, G.by)));
@@ -1130,23 +1135,23 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     for (int k = 0; k < n_blocks; ++k)
       if (pl.cnt[k] > 0) slots.push_back(P->groups[block_group[k]].slot0 + block_sys[k]);
     P->n_nonempty = (int)slots.size();
-    upload(P->d_block_id, bid);
-    upload(P->d_block_group, block_group);
-    upload(P->d_block_sys, block_sys);
-    upload(P->d_block_origin, origin);
-    upload(P->d_gbox, gbox);
-    upload(P->d_slots, slots);
+    upload(P->d_block_id, bid, s);
+    upload(P->d_block_group, block_group, s);
+    upload(P->d_block_sys, block_sys, s);
+    upload(P->d_block_origin, origin, s);
+    upload(P->d_gbox, gbox, s);
+    upload(P->d_slots, slots, s);
     std::vector<c128*> ptrs(8 * P->groups.size());
     for (size_t gi = 0; gi < P->groups.size(); ++gi)
       for (int q = 0; q < 8; ++q) ptrs[q * P->groups.size() + gi] = P->groups[gi].vec[q];
-    upload(P->d_gptr, ptrs);
+    upload(P->d_gptr, ptrs, s);
     P->d_istatus.alloc(std::max(1, slot) * sizeof(int));
-    P->d_istatus.zero();
+    P->d_istatus.zero(s);
     P->d_istate.alloc(std::max(1, slot) * sizeof(KState));
-    P->d_istate.zero();
+    P->d_istate.zero(s);
     P->d_ipartials.alloc((size_t)std::max(1, slot) * P->ipstride * sizeof(double));
     P->d_intile.alloc(std::max(1, slot) * sizeof(int));
-    P->d_intile.zero();
+    P->d_intile.zero(s);
     // pick the faster z-pass kernel per batch shape and precision (tuning
     // clobbers the work buffers, which hold no data yet)
     for (auto& G : P->groups) {
@@ -1347,8 +1352,8 @@ vie_status vie_context_create(int32_t device, size_t hbm_budget_bytes, vie_conte
       }
       off += L;
     }
-    upload(ctx->tw64, h64);
-    upload(ctx->tw32, h32);
+    upload(ctx->tw64, h64, ctx->stream);
+    upload(ctx->tw32, h32, ctx->stream);
     off = 0;
     for (int L : vie::kFftLengths) {
       ctx->tws64.table[L] = ctx->tw64.as<c128>() + off;
