@@ -9,6 +9,7 @@ Test infrastructure (see ``oracle/__init__``).
   extinction  Im(P^H E_inc), absorption  sum Im(1/chi) |P|^2,
   scattering  -P^H Im(T) P.  For the discrete solution of A P = E_inc with
   complex-symmetric T they balance exactly (P_ext = P_abs + P_sca).
+* The total field at every box voxel (incident plus scattered, eq. (3)).
 * Far field of the voxel currents and the E-plane bistatic RCS used for the
   Mie comparison of Sec. III (Figs. 1-2).
 * Mie series for a homogeneous sphere (the reference solution of Sec. III,
@@ -51,6 +52,14 @@ def power_terms(grid: Grid, P: np.ndarray, e_inc: np.ndarray, op: FFTOperator = 
     # T complex symmetric => P^H Im(T) P = Im(P^H T P)
     sca = -float(np.imag(np.vdot(Pm.ravel(), TP.ravel())))
     return ext, absn, sca
+
+
+def total_field_box(grid: Grid, P: np.ndarray, e_inc: np.ndarray) -> np.ndarray:
+    """E_tot at every voxel of the box, scatterer or not: E_inc plus the
+    scattered field sum_n T(m - n) P_n (eq. (3) with the discretised
+    operator of eq. (1)).  On the scatterer this equals P / chi for the
+    solution of A P = E_inc (eq. (2))."""
+    return e_inc + FFTOperator(grid).convolve(P * grid.mask)
 
 
 def far_field_vector(grid: Grid, P: np.ndarray, rhat: np.ndarray) -> np.ndarray:

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import krylov, operator as op, physics
+from oracle import green, krylov, operator as op, physics
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -135,3 +135,28 @@ def test_cube_mirror_symmetries():
     assert np.allclose(Py[1], -P[1], atol=1e-9 * sc)
     assert np.allclose(Px[0], P[0], atol=1e-9 * sc)
     assert np.allclose(Px[1], -P[1], atol=1e-9 * sc) and np.allclose(Px[2], -P[2], atol=1e-9 * sc)
+
+
+def test_total_field_box_brute_force_and_on_scatterer():
+    """E_tot everywhere = E_inc + sum_n T(m - n) P_n: checked against the
+    O(N^2) sum written out, and on the scatterer against P / chi of the
+    dense solution (the discrete equation itself)."""
+    case = W.random_tiny(71, (3, 4, 5), fill=0.6)
+    g = op.Grid.from_case(case)
+    e = physics.plane_wave(g, (0.6, 0.0, 0.8), (0.8, 0.0, -0.6))
+    P = krylov.solve_dense(g, e)
+    E = physics.total_field_box(g, P, e)
+    # brute force everywhere (vacuum voxels included)
+    idx = np.argwhere(np.ones(case.shape, bool))
+    src = np.argwhere(g.mask)
+    want = e.copy()
+    for (k, j, i) in idx:
+        dm = np.stack([i - src[:, 2], j - src[:, 1], k - src[:, 0]])
+        T = green.offset_tensor(dm[0], dm[1], dm[2], g.dx, g.dy, g.dz, g.k0)   # [n, 3, 3]
+        Pn = P[:, src[:, 0], src[:, 1], src[:, 2]].T                            # [n, 3]
+        want[:, k, j, i] += np.einsum("nab,nb->a", T, Pn)
+    assert np.linalg.norm(E - want) <= 1e-12 * np.linalg.norm(want)
+    m = g.mask
+    assert np.linalg.norm((E - P * g.chi_inv)[:, m]) <= 1e-10 * np.linalg.norm(E[:, m])
+    # outside the scatterer the field differs from the incident one
+    assert np.linalg.norm((E - e)[:, ~m]) > 1e-3 * np.linalg.norm(e[:, ~m])
