@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 4
+#define VIE_ABI_VERSION 5
 
 typedef enum {
   VIE_OK = 0,
@@ -213,6 +213,32 @@ vie_status vie_solve(vie_problem* p, const double* e_inc, const vie_opts* opts, 
 /* Same with device buffers on `stream` (inputs already in HBM). */
 vie_status vie_solve_device(vie_problem* p, const void* e_inc_dev, const vie_opts* opts, void* e_tot_dev,
                             void* pol_dev, vie_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------ fields
+ * Post-processing of a solution P (the pol output of a solve, device,
+ * 3*nvox complex). */
+
+/* Total field at every voxel of the box, scatterer and vacuum alike:
+ * e_box = E_inc + sum_n T(m - n) P_n (eq. (3) with the operator of eq. (1);
+ * on the scatterer this is P / chi, eq. (2)).  One FFT product in
+ * `precision`.  All three device buffers are 3*nvox complex and must not
+ * overlap e_box. */
+vie_status vie_total_field_box(vie_problem* p, int32_t precision, const void* pol_dev, const void* e_inc_dev,
+                               void* e_box_dev, void* stream);
+
+/* Far field of the voxel currents, F(rhat) = (I - rhat rhat) sum_n P_n dV
+ * exp(+j k0 rhat . r_n) (r_n: voxel centre relative to the grid centre), for
+ * n_dir unit directions rhat (host, 3 doubles each; |rhat| = 1 within 1e-12
+ * else VIE_EINVAL).  f_out: host, 3*n_dir complex.  FP64; synchronises the
+ * stream. */
+vie_status vie_far_field(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat, double* f_out,
+                         void* stream);
+
+/* Bistatic radar cross-section for a unit-amplitude incident wave,
+ * sigma(rhat) = k0^4 |F(rhat)|^2 / (4 pi) (the E-plane curves of Sec. III,
+ * Figs. 1-2, for rhat in the x-z plane).  sigma_out: host, n_dir doubles. */
+vie_status vie_rcs(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat, double* sigma_out,
+                   void* stream);
 
 /* ------------------------------------------------------------------ serving
  * A request queue per context: independent solves (any grid, wavelength,

@@ -66,7 +66,9 @@ struct KBatch;
 //   1: p = r + beta (p - omega v) (p = r on the first step), written to p;
 //   2: s = r - alpha v, written to p (the s vector), partials of ||s||^2.
 // Pass 5 (out_mode), after writing y = A x:
-//   0: nothing; 1: partials of <rhat, y>; 2: partials of <y, s>, <y, y>.
+//   0: nothing; 1: partials of <rhat, y>; 2: partials of <y, s>, <y, y>;
+//   3: y = rhat + sum T x at every voxel (rhat = E_inc: the total field of
+//      eq. (3) in and around the scatterer; no mask, no partials).
 // In pass 5, x is the product's input (x for in_mode 0, f.p otherwise).
 struct FuseArgs {
   int in_mode, out_mode;
@@ -157,6 +159,13 @@ struct BlockSolveArgs {
 bool block_solver_supported(int lx, int ly, int lz, int bz);
 template <typename R>
 void block_solve(const BlockSolveArgs& a, int lx, int lz, hipStream_t s);
+
+// Far field F(rhat) = (I - rhat rhat) sum_n P_n dV exp(+j k0 rhat . r_n)
+// for ndir directions (rhat: device, 3 doubles each; F: device, 3 c128 each).
+// part: device scratch of 6 far_field_chunks(nx ny nz) doubles per direction.
+int64_t far_field_chunks(int64_t nv);
+void far_field(const c128* P, int nx, int ny, int nz, double dx, double dy, double dz, double k0, const double* rhat,
+               int ndir, double* part, c128* F, hipStream_t s);
 
 // Scalar steps applied by k_finalize after a producer wrote partials.
 enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4 };

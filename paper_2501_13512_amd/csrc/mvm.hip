@@ -222,7 +222,7 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
       if (valid && j0 + u < E && k < nx) {
         ci[u] = chi[k];
         xv[u] = a.x[vrow + k];
-        if (mode == 1) ov[u] = a.rhat[vrow + k];
+        if (mode == 1 || mode == 3) ov[u] = a.rhat[vrow + k];
         if (mode == 2) ov[u] = a.s[vrow + k];
       }
     }
@@ -231,7 +231,10 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
       const int k = t + (j0 + u) * T;
       if (valid && j0 + u < E && k < nx) {
         c128 out = mk<double>(0.0, 0.0);
-        if (ci[u].x != 0.0 || ci[u].y != 0.0) out = xv[u] * ci[u] - scale * cvt<double>(slot[k]);
+        if (mode == 3)   // field at every voxel: E_inc + sum T P
+          out = ov[u] + scale * cvt<double>(slot[k]);
+        else if (ci[u].x != 0.0 || ci[u].y != 0.0)
+          out = xv[u] * ci[u] - scale * cvt<double>(slot[k]);
         a.y[vrow + k] = out;
         if (mode == 1) {          // <rhat, y>
           const c128 d = cdot1(ov[u], out);
@@ -446,7 +449,7 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArg
         const int q = e / pe;
         ci[u] = chi[(int64_t)((pl0 + q) % nz) * pe + (e - q * pe)];
         xv[u] = a.x[v0 + e];
-        if (mode == 1) ov[u] = a.rhat[v0 + e];
+        if (mode == 1 || mode == 3) ov[u] = a.rhat[v0 + e];
         if (mode == 2) ov[u] = a.s[v0 + e];
       }
     }
@@ -457,7 +460,10 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArg
         const int q = e / pe, rem = e - q * pe, y = rem / nx;
         const cx<R> qv = lds[(q * L + y) * LP + (rem - y * nx)];
         c128 out = mk<double>(0.0, 0.0);
-        if (ci[u].x != 0.0 || ci[u].y != 0.0) out = xv[u] * ci[u] - scale * cvt<double>(qv);
+        if (mode == 3)   // field at every voxel: E_inc + sum T P
+          out = ov[u] + scale * cvt<double>(qv);
+        else if (ci[u].x != 0.0 || ci[u].y != 0.0)
+          out = xv[u] * ci[u] - scale * cvt<double>(qv);
         a.y[v0 + e] = out;
         if (mode == 1) {          // <rhat, y>
           const c128 d = cdot1(ov[u], out);
@@ -1070,7 +1076,9 @@ template <typename R>
 void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s) {
   if (b.nsys <= 0) return;
   if (!x || !y) throw std::runtime_error("mvm_pass5: missing vectors");
-  if ((f.out_mode != 0 && !k) || (f.out_mode == 1 && !f.rhat) || (f.out_mode == 2 && !f.s))
+  if ((f.out_mode == 1 || f.out_mode == 2) && !k)
+    throw std::runtime_error("mvm_pass5: missing Krylov batch");
+  if (((f.out_mode == 1 || f.out_mode == 3) && !f.rhat) || (f.out_mode == 2 && !f.s))
     throw std::runtime_error("mvm_pass5: missing fused vectors");
   RowArgs<R> ra = row_args<R>(b, k, f, x, y, false);
   ra.out_mode = f.out_mode;

@@ -1497,6 +1497,90 @@ vie_status vie_matvec(vie_problem* p, int32_t precision, const void* x_dev, void
   });
 }
 
+extern "C++" {
+template <typename R>
+static void total_field_box(vie_problem* p, const c128* pol, const c128* e_inc, c128* e_box, hipStream_t s) {
+  const MvmBatch<R> m = outer_batch<R>(*p, false);
+  const vie::FuseArgs none{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const vie::FuseArgs field{0, 3, nullptr, nullptr, nullptr, e_inc, nullptr};
+  vie::mvm_pass1<R>(m, nullptr, none, pol, true, s);
+  vie::mvm_mid<R>(m, s);
+  vie::mvm_pass5<R>(m, nullptr, field, pol, e_box, s);
+}
+}  // extern "C++"
+
+vie_status vie_total_field_box(vie_problem* p, int32_t precision, const void* pol_dev, const void* e_inc_dev,
+                               void* e_box_dev, void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !pol_dev || !e_inc_dev || !e_box_dev) fail(VIE_EINVAL, "problem, pol, e_inc and e_box are required");
+    if (e_box_dev == pol_dev || e_box_dev == e_inc_dev) fail(VIE_EINVAL, "e_box must not overlap the inputs");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == VIE_FP64)
+      total_field_box<double>(p, (const c128*)pol_dev, (const c128*)e_inc_dev, (c128*)e_box_dev, s);
+    else if (precision == VIE_MIXED)
+      total_field_box<float>(p, (const c128*)pol_dev, (const c128*)e_inc_dev, (c128*)e_box_dev, s);
+    else
+      fail(VIE_EINVAL, "unknown precision");
+    return VIE_OK;
+  });
+}
+
+extern "C++" {
+static void far_field_host(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat,
+                           std::vector<c128>& F, hipStream_t s) {
+  if (!p || !pol_dev || !rhat) fail(VIE_EINVAL, "problem, pol and rhat are required");
+  if (n_dir < 1 || n_dir > 1000000) fail(VIE_EINVAL, "n_dir out of range");
+  for (int32_t d = 0; d < n_dir; ++d) {
+    const double* r = rhat + 3 * d;
+    if (!is_finite(r[0]) || !is_finite(r[1]) || !is_finite(r[2])) fail(VIE_EINVAL, "rhat has non-finite entries");
+    const double nrm = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(std::fabs(nrm - 1.0) <= 1e-12)) fail(VIE_EINVAL, "rhat entries must be unit vectors");
+  }
+  set_device(p->ctx);
+  const vie_grid& g = p->g;
+  const int64_t nchunk = vie::far_field_chunks(p->nv);
+  DevBuf dr(3 * (size_t)n_dir * sizeof(double)), part(6 * (size_t)n_dir * nchunk * sizeof(double)),
+      dF(3 * (size_t)n_dir * sizeof(c128));
+  hip_check(hipMemcpyAsync(dr.p, rhat, dr.bytes, hipMemcpyHostToDevice, s), "upload rhat");
+  vie::far_field((const c128*)pol_dev, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, p->k0, dr.as<double>(), n_dir,
+                 part.as<double>(), dF.as<c128>(), s);
+  F.resize(3 * (size_t)n_dir);
+  hip_check(hipMemcpyAsync(F.data(), dF.p, dF.bytes, hipMemcpyDeviceToHost, s), "download F");
+  hip_check(hipStreamSynchronize(s), "far field");
+}
+}  // extern "C++"
+
+vie_status vie_far_field(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat, double* f_out,
+                         void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !f_out) fail(VIE_EINVAL, "problem and f_out are required");
+    std::lock_guard<std::mutex> lk(p->mu);
+    std::vector<c128> F;
+    far_field_host(p, pol_dev, n_dir, rhat, F, (hipStream_t)stream);
+    std::memcpy(f_out, F.data(), F.size() * sizeof(c128));
+    return VIE_OK;
+  });
+}
+
+vie_status vie_rcs(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat, double* sigma_out,
+                   void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !sigma_out) fail(VIE_EINVAL, "problem and sigma_out are required");
+    std::lock_guard<std::mutex> lk(p->mu);
+    std::vector<c128> F;
+    far_field_host(p, pol_dev, n_dir, rhat, F, (hipStream_t)stream);
+    const double k4 = std::pow(p->k0, 4) / (4.0 * M_PI);
+    for (int32_t d = 0; d < n_dir; ++d) {
+      double a = 0;
+      for (int q = 0; q < 3; ++q) a += F[3 * d + q].x * F[3 * d + q].x + F[3 * d + q].y * F[3 * d + q].y;
+      sigma_out[d] = k4 * a;
+    }
+    return VIE_OK;
+  });
+}
+
 vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream,
                               int32_t reps, double* pass_ms) {
   return guarded([&]() -> vie_status {

@@ -56,7 +56,8 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
                "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_plane_wave",
                "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
-               "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel")
+               "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
+               "vie_total_field_box", "vie_far_field", "vie_rcs")
 
 
 class VieError(RuntimeError):
@@ -118,6 +119,9 @@ for _name, _args in {
     "vie_submit": [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(vie_opts), ctypes.POINTER(_vp)],
     "vie_wait": [_vp, ctypes.c_double, _vp, ctypes.POINTER(vie_stats), _vp],
     "vie_cancel": [_vp],
+    "vie_total_field_box": [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp],
+    "vie_far_field": [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp],
+    "vie_rcs": [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp],
 }.items():
     getattr(_lib, _name).restype = ctypes.c_int
     getattr(_lib, _name).argtypes = _args
@@ -274,6 +278,26 @@ def vie_wait(ticket: int, shape, timeout_s: float = -1.0):
 
 def vie_cancel(ticket: int) -> None:
     _check(_lib.vie_cancel(ticket), "vie_cancel")
+
+
+def vie_total_field_box(p: int, precision: int, pol, e_inc, e_box, stream=None) -> None:
+    _check(_lib.vie_total_field_box(p, precision, _dev(pol), _dev(e_inc), _dev(e_box), _stream(stream)),
+           "vie_total_field_box")
+
+
+def vie_far_field(p: int, pol, rhat: np.ndarray, stream=None) -> np.ndarray:
+    r = np.ascontiguousarray(rhat, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((r.shape[0], 3), dtype=np.complex128)
+    _check(_lib.vie_far_field(p, _dev(pol), int(r.shape[0]), _np_ptr(r), _np_ptr(out), _stream(stream)),
+           "vie_far_field")
+    return out
+
+
+def vie_rcs(p: int, pol, rhat: np.ndarray, stream=None) -> np.ndarray:
+    r = np.ascontiguousarray(rhat, dtype=np.float64).reshape(-1, 3)
+    out = np.empty(r.shape[0], dtype=np.float64)
+    _check(_lib.vie_rcs(p, _dev(pol), int(r.shape[0]), _np_ptr(r), _np_ptr(out), _stream(stream)), "vie_rcs")
+    return out
 
 
 # ------------------------------------------------------------------ conveniences
