@@ -115,6 +115,95 @@ def bicgstab(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: fl
     return x, info
 
 
+def _givens(a: complex, b: complex):
+    """Complex plane rotation (c real, s complex) with [c, s; -conj(s), c]
+    (a, b) = (r, 0)."""
+    if b == 0:
+        return 1.0, 0.0 + 0.0j
+    if a == 0:
+        return 0.0, complex(np.conj(b) / abs(b))
+    d = np.hypot(abs(a), abs(b))
+    return abs(a) / d, complex((a / abs(a)) * np.conj(b) / d)
+
+
+def fgmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float, maxit: int,
+           restart: int = 30, precond: Optional[Callable[[np.ndarray], np.ndarray]] = None):
+    """Flexible GMRES(restart), right preconditioned (Saad, SIAM J. Sci.
+    Comput. 14 (1993)): the preconditioned vectors z_j = M_j(v_j) are kept, so
+    the preconditioner may change from step to step (an inner iterative
+    solve).  Arnoldi by modified Gram-Schmidt, complex Givens rotations on
+    the Hessenberg matrix; the residual norm |g_{j+1}| of the small least-
+    squares problem is the stopping test (relative to ||b||).  A step is one
+    preconditioner application and one product.  At a restart or at the end
+    x += Z y and the residual is recomputed from b - A x."""
+    M = precond if precond is not None else (lambda w: w)
+    x = np.zeros_like(b)
+    nb = _norm(b)
+    info = KrylovInfo()
+    if nb == 0.0:
+        info.status, info.relres = "converged", 0.0
+        return x, info
+    r = b.copy()
+    it = 0
+    while True:
+        beta = _norm(r)
+        info.relres = beta / nb
+        if beta / nb <= tol:
+            info.status = "converged"
+            return x, info
+        if it >= maxit:
+            return x, info
+        m = restart
+        V = [r / beta]
+        Z = []
+        H = np.zeros((m + 1, m), dtype=complex)
+        g = np.zeros(m + 1, dtype=complex)
+        g[0] = beta
+        cs, sn = [], []
+        k = 0
+        done = False
+        for j in range(m):
+            it += 1
+            k = j + 1
+            z = M(V[j])
+            Z.append(z)
+            w = apply_A(z)
+            for i in range(j + 1):
+                H[i, j] = _dot(V[i], w)
+                w = w - H[i, j] * V[i]
+            h = _norm(w)
+            H[j + 1, j] = h
+            for i in range(j):
+                a0, a1 = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a0 + sn[i] * a1
+                H[i + 1, j] = -np.conj(sn[i]) * a0 + cs[i] * a1
+            c, s_ = _givens(H[j, j], H[j + 1, j])
+            cs.append(c)
+            sn.append(s_)
+            H[j, j] = c * H[j, j] + s_ * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -np.conj(s_) * g[j]
+            g[j] = c * g[j]
+            res = abs(g[j + 1]) / nb
+            info.history.append(res)
+            info.iterations = it
+            if res <= tol or it >= maxit or h == 0.0:
+                done = True
+                break
+            V.append(w / h)
+        y = scipy.linalg.solve_triangular(H[:k, :k], g[:k])
+        for i in range(k):
+            x = x + y[i] * Z[i]
+        r = b - apply_A(x)
+        if done and abs(g[k]) / nb <= tol:
+            info.relres = _norm(r) / nb
+            info.status = "converged"
+            return x, info
+        if it >= maxit:
+            info.relres = _norm(r) / nb
+            return x, info
+
+
 @dataclasses.dataclass
 class _Block:
     index: int
@@ -182,20 +271,26 @@ def total_field(grid: Grid, P: np.ndarray) -> np.ndarray:
 
 def solve(grid: Grid, e_inc: np.ndarray, tol_outer: float, maxit_outer: int = 1000,
           block_id: Optional[np.ndarray] = None, n_blocks: int = 0,
-          tol_inner: float = 1e-2, maxit_inner: int = 500, pad: int = 0, product: str = "fp64") -> Solution:
+          tol_inner: float = 1e-2, maxit_inner: int = 500, pad: int = 0, product: str = "fp64",
+          method: str = "bicgstab", restart: int = 30) -> Solution:
     """Solve A P = E_inc on S; block preconditioner if ``block_id`` is given.
 
     ``pad`` lengthens every circulant embedding (same operator, different
     rounding); comparing runs with pad 0 and pad > 0 measures how much
     rounding alone moves the iterates at a given tolerance.
     ``product="c64"`` runs every FFT convolution in complex64 (the mixed
-    mode's products); vectors and inner products stay FP64."""
+    mode's products); vectors and inner products stay FP64.
+    ``method="fgmres"`` replaces the outer BiCGSTAB by flexible GMRES(restart)
+    (a solver variant; the paper's method is BiCGSTAB)."""
     A = FFTOperator(grid, pad, product)
     b = masked_rhs(grid, e_inc)
     pre = None
     if block_id is not None:
         pre = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner, pad, product)
-    P, info = bicgstab(A, b, tol_outer, maxit_outer, pre)
+    if method == "fgmres":
+        P, info = fgmres(A, b, tol_outer, maxit_outer, restart, pre)
+    else:
+        P, info = bicgstab(A, b, tol_outer, maxit_outer, pre)
     return Solution(P, total_field(grid, P), info, pre.inner_counts if pre is not None else [])
 
 
