@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 5
+#define VIE_ABI_VERSION 6
 
 typedef enum {
   VIE_OK = 0,
@@ -102,7 +102,27 @@ typedef struct {
   int32_t precision;    /* vie_precision */
   int32_t poll_lag;     /* convergence checks trail the enqueued work by this many steps (>= 0) */
   int32_t flags;        /* VIE_FLAG_* */
+  int32_t solver;       /* vie_solver */
+  int32_t restart;      /* VIE_SOLVER_FGMRES: Arnoldi steps per cycle, in [1, 1000] */
 } vie_opts;
+
+/* Outer Krylov solver.  Both are right preconditioned with the block
+ * preconditioner of eq. (10) and start from x0 = 0.
+ *  VIE_SOLVER_BICGSTAB: the BiCGSTAB of Sec. II-B; one step = two products
+ *    and two preconditioner applications; maxit_outer counts steps.
+ *  VIE_SOLVER_FGMRES: flexible GMRES(restart) (Saad's form for a
+ *    preconditioner that varies from step to step, as the inexact inner
+ *    solves make it); one Arnoldi step = one product and one preconditioner
+ *    application; maxit_outer counts Arnoldi steps; stops when the minimal
+ *    residual of the Arnoldi least-squares problem reaches tol_outer.
+ *    Needs (2 restart + 1) vectors of 3 nx ny nz complex doubles (restart + 1
+ *    without preconditioner), allocated by the first such solve of a problem
+ *    and kept with it (counted in footprint_bytes; VIE_EBUSY beyond the
+ *    context's budget).  Not accepted by vie_submit. */
+typedef enum {
+  VIE_SOLVER_BICGSTAB = 0,
+  VIE_SOLVER_FGMRES = 1
+} vie_solver;
 
 /* vie_opts.flags: run the inner block iterations as individual kernel
  * launches instead of a captured HIP graph (same kernels, same results). */

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libvie.so")
 OBJ = os.path.join(ROOT, "_build")
 
-SOURCES = ["mvm.hip", "krylov.hip", "block_solver.hip", "fields.hip", "vie_api.cpp"]
+SOURCES = ["mvm.hip", "krylov.hip", "block_solver.hip", "fields.hip", "gmres.hip", "vie_api.cpp"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),

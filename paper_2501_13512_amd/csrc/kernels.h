@@ -16,6 +16,7 @@ enum SysStatus : int {
   ST_BREAKDOWN = 3,   // rho, <rhat, v> or omega vanished; x = last iterate
   ST_MAXIT = 4,       // iteration cap reached; x = last iterate
   ST_IDLE = 5,        // not started / skipped (zero right-hand side)
+  ST_RESTART = 6,     // flexible GMRES: cycle full, x update and restart pending
 };
 
 // FFT lengths with compiled kernels (2^a 3^b, up to 512).
@@ -166,6 +167,33 @@ void block_solve(const BlockSolveArgs& a, int lx, int lz, hipStream_t s);
 int64_t far_field_chunks(int64_t nv);
 void far_field(const c128* P, int nx, int ny, int nz, double dx, double dy, double dz, double k0, const double* rhat,
                int ndir, double* part, c128* F, hipStream_t s);
+
+// Flexible GMRES(m) of one system (the outer solve).  V: m+1 basis vectors,
+// Z: m preconditioned vectors (or null without preconditioner), each n c128;
+// H: (m+1) x m column-major; status: the solve's status (ST_ACTIVE while
+// iterating; gates the product and the preconditioner as well).
+struct GmresState {
+  double nb, tol, relres, hnext;
+  int iters, maxit, k, pad;   // k: columns of the current cycle
+};
+struct GmresDev {
+  c128* V;
+  c128* Z;
+  int64_t n;
+  int m;
+  c128 *H, *sn, *g, *y, *h, *c;
+  double* cs;
+  double* part;     // (m+1) * nchunk * 2 doubles
+  int64_t nchunk;   // gmres_chunks(n)
+  double* scal;     // scal[0]: squared norm input of gmres_arnoldi / gmres_start
+  GmresState* st;
+  int* status;
+};
+int64_t gmres_chunks(int64_t n);
+void gmres_orthogonalise(const GmresDev& d, c128* w, int j, hipStream_t s);   // CGS2 of w against V_0..V_j
+void gmres_arnoldi(const GmresDev& d, c128* w, int j, hipStream_t s);         // column j, rotations, w /= ||w||
+void gmres_start(const GmresDev& d, c128* v0, bool first, double tol, int maxit, hipStream_t s);   // g, status; v0 /= ||v0||
+void gmres_update(const GmresDev& d, c128* x, const c128* B, hipStream_t s);  // x += B y
 
 // Scalar steps applied by k_finalize after a producer wrote partials.
 enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4 };

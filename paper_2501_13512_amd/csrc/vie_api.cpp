@@ -277,6 +277,11 @@ struct vie_problem {
   std::mutex mu;
   size_t footprint = 0;
   const std::atomic<bool>* cancel = nullptr;   // set by the server: stop after the current outer step
+  // flexible GMRES storage, allocated by the first such solve (restart gm_m,
+  // with the preconditioned vectors Z when gm_z)
+  DevBuf gm_basis, gm_small, gm_part, gm_state;
+  int gm_m = 0;
+  bool gm_z = false;
 
   ~vie_problem() {
     for (auto& gp : inner_graph)
@@ -696,6 +701,141 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
   return r;
 }
 
+// Storage of flexible GMRES(m): m + 1 Arnoldi vectors, m preconditioned
+// vectors (with a preconditioner), the small dense arrays and the partials.
+// Allocated on first use and counted in the problem's footprint.
+size_t gmres_small_bytes(int m) {
+  return ((size_t)(m + 1) * m + 2 * (size_t)m + 3 * (size_t)(m + 1)) * sizeof(c128) + (size_t)m * sizeof(double);
+}
+
+void ensure_gmres(vie_problem& P, int m, bool prec) {
+  if (P.gm_m == m && (P.gm_z || !prec)) return;
+  const int64_t n = 3 * P.nv;
+  const size_t basis = ((size_t)(m + 1) + (prec ? (size_t)m : 0)) * (size_t)n * sizeof(c128);
+  const size_t part = (size_t)(m + 1) * (size_t)vie::gmres_chunks(n) * 2 * sizeof(double);
+  const size_t total = basis + gmres_small_bytes(m) + part + sizeof(vie::GmresState);
+  const size_t old = P.gm_basis.bytes + P.gm_small.bytes + P.gm_part.bytes + P.gm_state.bytes;
+  vie_context* ctx = P.ctx;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const size_t others = ctx->used + ctx->reserved - std::min(ctx->used + ctx->reserved, old);
+    if (ctx->budget && others + total > ctx->budget) fail(VIE_EBUSY, "GMRES storage exceeds the context's HBM budget");
+    ctx->used = ctx->used - std::min(ctx->used, old) + total;
+  }
+  P.footprint = P.footprint - std::min(P.footprint, old) + total;
+  P.gm_m = 0;
+  P.gm_basis.reset();
+  P.gm_small.reset();
+  P.gm_part.reset();
+  P.gm_state.reset();
+  try {
+    P.gm_basis.alloc(basis);
+    P.gm_small.alloc(gmres_small_bytes(m));
+    P.gm_part.alloc(part);
+    P.gm_state.alloc(sizeof(vie::GmresState));
+  } catch (...) {
+    P.gm_basis.reset();
+    P.gm_small.reset();
+    P.gm_part.reset();
+    P.gm_state.reset();
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->used -= std::min(ctx->used, total);
+    P.footprint -= std::min(P.footprint, total);
+    throw;
+  }
+  P.gm_m = m;
+  P.gm_z = prec;
+}
+
+vie::GmresDev gmres_dev(vie_problem& P) {
+  vie::GmresDev d{};
+  const int m = P.gm_m;
+  const int64_t n = 3 * P.nv;
+  d.V = P.gm_basis.as<c128>();
+  d.Z = P.gm_z ? d.V + (int64_t)(m + 1) * n : nullptr;
+  d.n = n;
+  d.m = m;
+  c128* q = P.gm_small.as<c128>();
+  d.H = q;
+  q += (int64_t)(m + 1) * m;
+  d.sn = q;
+  q += m;
+  d.g = q;
+  q += m + 1;
+  d.y = q;
+  q += m;
+  d.h = q;
+  q += m + 1;
+  d.c = q;
+  q += m + 1;
+  d.cs = reinterpret_cast<double*>(q);
+  d.part = P.gm_part.as<double>();
+  d.nchunk = vie::gmres_chunks(n);
+  d.scal = P.scal.as<double>();
+  d.st = P.gm_state.as<vie::GmresState>();
+  d.status = P.ostatus.as<int>();
+  return d;
+}
+
+// Flexible GMRES(m) on the full grid, x0 = 0: a solver variant next to the
+// BiCGSTAB of Sec. II-B.  Each Arnoldi step applies the block preconditioner
+// of eq. (10) once and the product once; the preconditioned vectors are kept
+// because the inexact inner solves make the preconditioner change from step
+// to step.  Cycles of m steps end with x += Z y and a restart from the
+// residual b - A x (in the product precision R).
+template <typename R>
+RunResult run_fgmres(vie_problem& P, const c128* rhs, c128* x, double tol, int maxit, int restart, bool prec,
+                     double tol_in, int maxit_in, int lag, int32_t* hist, int64_t hist_cap, bool graphs, bool wg,
+                     hipStream_t s) {
+  ensure_gmres(P, restart, prec);
+  const vie::GmresDev d = gmres_dev(P);
+  const int64_t n = d.n;
+  const MvmBatch<R> mg = outer_batch<R>(P, true);
+  const MvmBatch<R> mu = outer_batch<R>(P, false);
+  const int* gate = P.ostatus.as<int>();
+  auto V = [&](int j) { return d.V + (int64_t)j * n; };
+  auto Z = [&](int j) { return d.Z + (int64_t)j * n; };
+  hip_check(hipMemsetAsync(x, 0, n * sizeof(c128), s), "x0");
+  hip_check(hipMemcpyAsync(V(0), rhs, n * sizeof(c128), hipMemcpyDeviceToDevice, s), "r0");
+  vie::norm2(V(0), n, P.partials.as<double>(), P.scal.as<double>(), s);
+  vie::gmres_start(d, V(0), true, tol, maxit, s);
+  int status = vie::ST_ACTIVE;
+  for (;;) {
+    Poller poll(P, s, 0);
+    for (int j = 0; j < d.m; ++j) {
+      const c128* src = V(j);
+      if (prec) {
+        precond_apply<R>(P, V(j), Z(j), tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
+        src = Z(j);
+      }
+      vie::mvm<R>(mg, src, V(j + 1), false, s);
+      vie::gmres_orthogonalise(d, V(j + 1), j, s);
+      vie::norm2(V(j + 1), n, P.partials.as<double>(), P.scal.as<double>(), s);
+      vie::gmres_arnoldi(d, V(j + 1), j, s);
+      const long t = poll.push(P.ostatus.as<int>());
+      if (t - lag >= 0 && poll.wait(t - lag) != vie::ST_ACTIVE) break;
+      if (P.cancel && P.cancel->load(std::memory_order_relaxed)) break;
+    }
+    vie::gmres_update(d, x, prec ? d.Z : d.V, s);
+    hip_check(hipMemcpyAsync(&status, P.ostatus.p, sizeof(int), hipMemcpyDeviceToHost, s), "status");
+    hip_check(hipStreamSynchronize(s), "fgmres cycle");
+    if (status != vie::ST_RESTART || (P.cancel && P.cancel->load())) break;
+    // restart from the residual of the updated iterate
+    vie::mvm<R>(mu, x, V(0), false, s);
+    vie::sub_vec(rhs, V(0), V(0), n, s);
+    vie::norm2(V(0), n, P.partials.as<double>(), P.scal.as<double>(), s);
+    vie::gmres_start(d, V(0), false, tol, maxit, s);
+  }
+  vie::GmresState gs{};
+  hip_check(hipMemcpy(&gs, d.st, sizeof(gs), hipMemcpyDeviceToHost), "state");
+  RunResult r{};
+  r.st.nb = gs.nb;
+  r.st.iters = gs.iters;
+  r.st.rnorm = gs.relres;
+  r.status = status == vie::ST_RESTART ? vie::ST_MAXIT : status;
+  return r;
+}
+
 double true_relres(vie_problem& P, const c128* rhs, const c128* x, c128* tmp_ax, c128* tmp_r, double nb,
                    hipStream_t s) {
   MvmBatch<double> m = outer_batch<double>(P, false);
@@ -716,6 +856,9 @@ void validate_opts(const vie_opts* o, bool has_blocks) {
   if (o->poll_lag < 0 || o->poll_lag > kRing - 2) fail(VIE_EINVAL, "poll_lag out of range");
   if (o->max_refine < 0 || o->max_refine > 100) fail(VIE_EINVAL, "max_refine out of range");
   if (o->flags & ~(VIE_FLAG_NO_GRAPHS | VIE_FLAG_NO_BLOCK_KERNEL)) fail(VIE_EINVAL, "unknown flags");
+  if (o->solver != VIE_SOLVER_BICGSTAB && o->solver != VIE_SOLVER_FGMRES) fail(VIE_EINVAL, "unknown solver");
+  if (o->solver == VIE_SOLVER_FGMRES && (o->restart < 1 || o->restart > 1000))
+    fail(VIE_EINVAL, "restart must be in [1, 1000]");
   if (o->precondition) {
     if (!has_blocks) fail(VIE_EINVAL, "precondition requested but the problem has no blocks");
     if (!(o->tol_inner >= 0) || !is_finite(o->tol_inner)) fail(VIE_EINVAL, "tol_inner must be finite and >= 0");
@@ -745,21 +888,27 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   RunResult rr;
   int refine = 0, refine_iters = 0;
   double relres_true = 0;
+  const bool fgmres = o->solver == VIE_SOLVER_FGMRES;
+  auto run = [&](auto tag, const c128* rhs, c128* x, double tol) {
+    using R = decltype(tag);
+    if (fgmres)
+      return run_fgmres<R>(P, rhs, x, tol, o->maxit_outer, o->restart, prec, o->tol_inner, o->maxit_inner,
+                           o->poll_lag, hist, hist_cap, graphs, wg, s);
+    return run_bicgstab<R>(P, rhs, x, tol, o->maxit_outer, prec, o->tol_inner, o->maxit_inner, o->poll_lag, hist,
+                           hist_cap, graphs, wg, s);
+  };
   if (o->precision == VIE_FP64) {
-    rr = run_bicgstab<double>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
-                              o->poll_lag, hist, hist_cap, graphs, wg, s);
+    rr = run(double{}, v[V_B], v[V_X], o->tol_outer);
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], rr.st.nb, s);
   } else {
-    rr = run_bicgstab<float>(P, v[V_B], v[V_X], o->tol_outer, o->maxit_outer, prec, o->tol_inner, o->maxit_inner,
-                             o->poll_lag, hist, hist_cap, graphs, wg, s);
+    rr = run(float{}, v[V_B], v[V_X], o->tol_outer);
     const double nb = rr.st.nb;
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
     // iterative refinement: solve A d = b - A x with FP32 products, x += d
     while (rr.status != vie::ST_BREAKDOWN && relres_true > o->tol_outer && refine < o->max_refine && nb > 0 &&
            !(P.cancel && P.cancel->load())) {
       const double tol_c = std::min(0.5, o->tol_outer / relres_true);
-      RunResult rc = run_bicgstab<float>(P, v[V_TMP2], v[V_TMP1], tol_c, o->maxit_outer, prec, o->tol_inner,
-                                         o->maxit_inner, o->poll_lag, hist, hist_cap, graphs, wg, s);
+      RunResult rc = run(float{}, v[V_TMP2], v[V_TMP1], tol_c);
       vie::add_vec(v[V_X], v[V_TMP1], 3 * P.nv, s);
       ++refine;
       refine_iters += rc.st.iters;
@@ -795,7 +944,7 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     return VIE_ECANCELLED;
   }
   if (rr.status == vie::ST_BREAKDOWN) {
-    g_last_error = "BiCGSTAB breakdown (last iterate written)";
+    g_last_error = fgmres ? "GMRES breakdown (last iterate written)" : "BiCGSTAB breakdown (last iterate written)";
     return VIE_EBREAKDOWN;
   }
   if (rr.status == vie::ST_CONVERGED || rr.status == vie::ST_HALF) {
@@ -1754,6 +1903,7 @@ vie_status vie_submit(vie_context* ctx, const vie_grid* grid, const double* eps_
     r->plan = make_plan(*grid, eps_r, block_id, n_blocks);
     r->opts = *opts;
     validate_opts(opts, !r->plan.groups.empty());
+    if (opts->solver != VIE_SOLVER_BICGSTAB) fail(VIE_EINVAL, "the request server runs BiCGSTAB solves only");
     const int64_t n = 2 * 3 * r->plan.nv;
     r->e_inc.assign(e_inc, e_inc + n);
     for (double v : r->e_inc)

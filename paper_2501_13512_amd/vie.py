@@ -50,6 +50,7 @@ VIE_ETIMEDOUT = -8
 VIE_FP64, VIE_MIXED = 0, 1
 VIE_FLAG_NO_GRAPHS = 1
 VIE_FLAG_NO_BLOCK_KERNEL = 2
+VIE_SOLVER_BICGSTAB, VIE_SOLVER_FGMRES = 0, 1
 STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_ENOMEM", -3: "VIE_EDEVICE",
                 -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL", -8: "VIE_ETIMEDOUT"}
 
@@ -76,7 +77,8 @@ class vie_opts(ctypes.Structure):
     _fields_ = [("tol_outer", ctypes.c_double), ("tol_inner", ctypes.c_double),
                 ("maxit_outer", ctypes.c_int32), ("maxit_inner", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("precondition", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("poll_lag", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("poll_lag", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
 
 class vie_stats(ctypes.Structure):
@@ -306,9 +308,9 @@ def make_grid(nx, ny, nz, dx, dy, dz, wavelength) -> vie_grid:
 
 
 def make_opts(tol_outer=1e-6, tol_inner=1e-2, maxit_outer=1000, maxit_inner=500, max_refine=3,
-              precondition=True, precision=VIE_FP64, poll_lag=1, flags=0) -> vie_opts:
+              precondition=True, precision=VIE_FP64, poll_lag=1, flags=0, solver=0, restart=30) -> vie_opts:
     return vie_opts(float(tol_outer), float(tol_inner), int(maxit_outer), int(maxit_inner), int(max_refine),
-                    1 if precondition else 0, int(precision), int(poll_lag), int(flags))
+                    1 if precondition else 0, int(precision), int(poll_lag), int(flags), int(solver), int(restart))
 
 
 def stats_dict(st: vie_stats) -> dict:
