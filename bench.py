@@ -14,7 +14,8 @@ region; its set-up time is reported separately.
 Prints one JSON line.  Extra fields: per-solve latency p50/p99, outer and
 inner step counts, the FP64 true residual, the sampled field error against
 the oracle's reference files (case tolerance, and tight), the FP64 GPU
-paths of the same workload (block-preconditioned and unpreconditioned),
+paths of the same workload (block-preconditioned and unpreconditioned), the
+flexible GMRES(m) outer-solver variant with the same preconditioner,
 the FFT product's per-pass times and the roofline of its dominant pass (also
 on a 256x256x64 grid), and the CPU oracle baseline.
 """
@@ -158,6 +159,13 @@ def main():
                          "tight solve, 2e-6 brings it under 1e-5")
     ap.add_argument("--compare-steps", type=int, default=3,
                     help="solves of each FP64 comparison path (block-preconditioned, unpreconditioned); 0 = skip")
+    ap.add_argument("--variant-steps", type=int, default=3,
+                    help="solves of the flexible GMRES(m) outer-solver variant (same preconditioner and precision); "
+                         "0 = skip")
+    ap.add_argument("--fgmres-restart", type=int, default=100)
+    ap.add_argument("--fgmres-tol", type=float, default=1e-6,
+                    help="GMRES stops at its tolerance where BiCGSTAB's last step overshoots; 1e-6 keeps the field "
+                         "error under 1e-5 on this workload")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also copy 512 MiB device to device three times (reference kernel for HBM counters)")
     ap.add_argument("--mvm-shapes", default="256x256x64",
@@ -230,6 +238,33 @@ def main():
             mine = e_tot.cpu().numpy()
             compare[label]["mixed_vs_this_rel_field_diff"] = float(np.linalg.norm(mine - d) / np.linalg.norm(d))
 
+    # outer-solver variant: flexible GMRES(m), same preconditioner and precision
+    variants = {}
+    if args.variant_steps > 0 and args.maxit_outer is None:
+        of = V.make_opts(tol_outer=args.fgmres_tol, tol_inner=case.tol_inner, maxit_outer=case.maxit_outer,
+                         maxit_inner=case.maxit_inner, precondition=True, precision=prec, max_refine=3,
+                         solver=V.VIE_SOLVER_FGMRES, restart=args.fgmres_restart)
+        ef = torch.empty_like(e_inc)
+        V.vie_solve_device(P.handle, e_inc, of, ef, None, st)   # warm-up (storage, graph capture)
+        torch.cuda.synchronize()
+        lt = []
+        for _ in range(args.variant_steps):
+            t1 = time.perf_counter()
+            cf = V.vie_solve_device(P.handle, e_inc, of, ef, None, st)
+            lt.append(time.perf_counter() - t1)
+        sd = V.stats_dict(st)
+        f = ef.cpu().numpy()
+        mine = e_tot.cpu().numpy()
+        variants["fgmres"] = {
+            "restart": args.fgmres_restart, "tol_outer": args.fgmres_tol, "solves_per_s": len(lt) / sum(lt),
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lt, 50)), "p99": 1e3 * float(np.percentile(lt, 99))},
+            "status": V.STATUS_NAMES.get(cf, cf), "arnoldi_steps": sd["outer_iters"],
+            "precond_applies": sd["precond_applies"], "inner_iters_total": sd["inner_iters_total"],
+            "refine_steps": sd["refine_steps"], "relres_true": sd["relres_true"],
+            "field_check": golden_error(case, f),
+            "rel_field_diff_vs_bicgstab": float(np.linalg.norm(f - mine) / np.linalg.norm(mine)),
+            "footprint_bytes": int(P.info().footprint_bytes)}
+
     # FFT product of the full grid, per pass, HIP events on the launch stream
     mv = mvm_profile(V, P.handle, info, case.nx, case.ny, case.nz, prec, args.profile_reps)
     dom = mv["dominant"]
@@ -286,6 +321,7 @@ def main():
                      "kernel": dom["kernel"] + f" (full-grid product, {args.precision})"},
         "mvm_other_grids": extra,
         "fp64_gpu_paths": compare,
+        "solver_variants": variants,
         "block_solver_groups": int(info.n_block_solver_groups),
     }
     ge = golden_error(case, e_tot.cpu().numpy())
