@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 6
+#define VIE_ABI_VERSION 7
 
 typedef enum {
   VIE_OK = 0,
@@ -190,6 +190,16 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
                               int32_t n_blocks, vie_problem** out);
 vie_status vie_problem_destroy(vie_problem* p);
 vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info);
+
+/* Pins the z-pass kernel variant (0-4; 1 = mirror columns; lengths below
+ * 32 use 0 for 2-4) of every FFT product of
+ * the problem in one precision, full-grid and block products alike; -1
+ * restores the autotuned choice.  For kernel studies and a reproducible
+ * kernel choice: the variants compute the same transform (results agree to
+ * rounding; tested).  Synchronises the device; call it while no work of the
+ * problem is in flight.  Errors: VIE_EINVAL for a bad precision or
+ * variant. */
+vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t variant);
 
 /* Incident plane wave E_inc = pol * exp(-j k0 khat . r) at every voxel centre
  * (Sec. III: x-polarised wave along z).  kdir: unit vector (|kdir| = 1 within

@@ -1579,6 +1579,36 @@ vie_status vie_problem_destroy(vie_problem* p) {
   });
 }
 
+vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t variant) {
+  return guarded([&]() -> vie_status {
+    if (!p) fail(VIE_EINVAL, "problem is NULL");
+    if (precision != VIE_FP64 && precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
+    if (variant < -1 || variant >= vie::kZPassVariants) fail(VIE_EINVAL, "z-pass variant out of range");
+    set_device(p->ctx);
+    hip_check(hipDeviceSynchronize(), "synchronise");
+    std::lock_guard<std::mutex> lk(p->mu);
+    const int q = precision == VIE_MIXED ? 1 : 0;
+    hipStream_t s = p->ctx->stream;
+    if (variant >= 0) {
+      p->zvar[q] = variant;
+      for (auto& G : p->groups) G.zvar[q] = variant;
+    } else if (q == 0) {
+      p->zvar[0] = cached_zvariant<double>(p->ctx, outer_batch<double>(*p, false), s, nullptr);
+      for (auto& G : p->groups) G.zvar[0] = cached_zvariant<double>(p->ctx, group_batch<double>(*p, G, false), s, nullptr);
+    } else {
+      p->zvar[1] = cached_zvariant<float>(p->ctx, outer_batch<float>(*p, false), s, nullptr);
+      for (auto& G : p->groups) G.zvar[1] = cached_zvariant<float>(p->ctx, group_batch<float>(*p, G, false), s, nullptr);
+    }
+    // captured inner iterations hold the old kernels
+    for (auto& g : p->inner_graph[q])
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    return VIE_OK;
+  });
+}
+
 vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info) {
   return guarded([&]() -> vie_status {
     if (!p || !info) fail(VIE_EINVAL, "problem and info are required");

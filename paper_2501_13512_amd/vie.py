@@ -55,7 +55,8 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
                 -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL", -8: "VIE_ETIMEDOUT"}
 
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
-               "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_plane_wave",
+               "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass",
+               "vie_plane_wave",
                "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
                "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
                "vie_total_field_box", "vie_far_field", "vie_rcs")
@@ -108,6 +109,7 @@ for _name, _args in {
     "vie_problem_create": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
     "vie_problem_destroy": [_vp],
     "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
+    "vie_problem_set_zpass": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_plane_wave": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
     "vie_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
     "vie_matvec_profile": [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp],
@@ -176,6 +178,10 @@ def vie_problem_get_info(p: int) -> vie_problem_info:
     info = vie_problem_info()
     _check(_lib.vie_problem_get_info(p, ctypes.byref(info)), "vie_problem_get_info")
     return info
+
+
+def vie_problem_set_zpass(p: int, precision: int, variant: int) -> None:
+    _check(_lib.vie_problem_set_zpass(p, int(precision), int(variant)), "vie_problem_set_zpass")
 
 
 def vie_plane_wave(grid: vie_grid, kdir: Sequence[float], pol: Sequence[complex]) -> np.ndarray:

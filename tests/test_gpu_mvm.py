@@ -118,3 +118,67 @@ def test_matvec_is_deterministic(vie_ctx):
     a = _matvec(vie_ctx, case, x, V.VIE_MIXED)
     b = _matvec(vie_ctx, case, x, V.VIE_MIXED)
     assert np.array_equal(a, b)
+
+
+ZSHAPES = [(16, 8, 12), (24, 9, 7), (32, 10, 10), (48, 6, 5), (64, 5, 6)]   # (nz, ny, nx): z lengths 32 ... 128
+
+
+@pytest.mark.parametrize("prec", [V.VIE_FP64, V.VIE_MIXED])
+@pytest.mark.parametrize("shape", ZSHAPES)
+def test_zpass_variants_agree(vie_ctx, shape, prec):
+    """Every z-pass variant (pinned with vie_problem_set_zpass) gives the
+    oracle's product, full-grid and block-diagonal, and the variants agree
+    with each other to rounding."""
+    seed = 7000 + shape[0]
+    case = W.random_tiny(seed, shape, fill=0.8, n_blocks=3)
+    g = op.Grid.from_case(case)
+    x = _rand(seed, case.shape)
+    want = op.FFTOperator(g)(x * g.mask)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        xd = torch.from_numpy(x).cuda()
+        outs = {}
+        for v in range(5):
+            V.vie_problem_set_zpass(P.handle, prec, v)
+            yd = torch.full_like(xd, complex("nan"))
+            V.vie_matvec(P.handle, prec, xd, yd)
+            bd = torch.full_like(xd, complex("nan"))
+            V.vie_block_matvec(P.handle, prec, xd, bd)
+            torch.cuda.synchronize()
+            outs[v] = (yd.cpu().numpy(), bd.cpu().numpy())
+            _assert_close(outs[v][0], want, g.mask, TOL[prec])
+        V.vie_problem_set_zpass(P.handle, prec, -1)
+        agree = 1e-14 if prec == V.VIE_FP64 else 1e-6
+        for v in range(1, 5):
+            for k in range(2):
+                a, b = outs[v][k], outs[0][k]
+                assert np.abs(a - b).max() <= agree * np.abs(b).max(), (v, k)
+        with pytest.raises(V.VieError):
+            V.vie_problem_set_zpass(P.handle, prec, 5)
+    finally:
+        P.close()
+
+
+def test_pinned_zpass_preconditioned_solve(vie_ctx):
+    """Pinned z-pass variants inside gated batched inner solves (blocks that
+    converge at different steps are skipped) and the outer product: same
+    field as the tuned kernels (at tol 1e-12, where rounding differences
+    between kernels no longer move the converged field beyond 1e-10)."""
+    case = W.cube16()
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        e = torch.from_numpy(V.vie_plane_wave(P.grid, case.kdir, case.pol)).cuda()
+        res = {}
+        for v in (-1, 1, 3):
+            V.vie_problem_set_zpass(P.handle, V.VIE_FP64, v)
+            out = torch.empty_like(e)
+            st = V.vie_stats()
+            opts = V.make_opts(tol_outer=1e-12, tol_inner=1e-3, maxit_outer=2000, flags=V.VIE_FLAG_NO_BLOCK_KERNEL)
+            assert V.vie_solve_device(P.handle, e, opts, out, None, st) == V.VIE_OK
+            torch.cuda.synchronize()
+            res[v] = out.cpu().numpy()
+        for v in (1, 3):
+            assert np.linalg.norm(res[v] - res[-1]) <= 1e-10 * np.linalg.norm(res[-1])
+    finally:
+        V.vie_problem_set_zpass(P.handle, V.VIE_FP64, -1)
+        P.close()
