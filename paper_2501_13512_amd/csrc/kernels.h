@@ -69,7 +69,9 @@ struct KBatch;
 // Pass 5 (out_mode), after writing y = A x:
 //   0: nothing; 1: partials of <rhat, y>; 2: partials of <y, s>, <y, y>;
 //   3: y = rhat + sum T x at every voxel (rhat = E_inc: the total field of
-//      eq. (3) in and around the scatterer; no mask, no partials).
+//      eq. (3) in and around the scatterer; no mask, no partials);
+//   4: as 2, plus partials of ||s||^2 (then FIN_SOMEGA: the half-step test
+//      and omega in one finalize).
 // In pass 5, x is the product's input (x for in_mode 0, f.p otherwise).
 struct FuseArgs {
   int in_mode, out_mode;
@@ -196,7 +198,7 @@ void gmres_start(const GmresDev& d, c128* v0, bool first, double tol, int maxit,
 void gmres_update(const GmresDev& d, c128* x, const c128* B, hipStream_t s);  // x += B y
 
 // Scalar steps applied by k_finalize after a producer wrote partials.
-enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4 };
+enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4, FIN_SOMEGA = 5 };
 
 int64_t krylov_chunks(int64_t n);   // reduction chunks per system (vector kernels)
 
@@ -208,6 +210,7 @@ void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, const 
 //   FIN_ALPHA: alpha = rho / <rhat, v> (counts the step)
 //   FIN_S:     half-step test on ||s||
 //   FIN_OMEGA: omega = <t, s> / <t, t>
+//   FIN_SOMEGA: half-step test on ||s|| (from pass-5 out_mode 4), then omega
 //   FIN_XR:    rho', ||r||, convergence, breakdown, cap, beta; HALF -> CONVERGED
 void k_finalize(const KBatch& k, FinKind kind, hipStream_t s, const int* gate = nullptr, double tol = 0,
                 int maxit = 0);

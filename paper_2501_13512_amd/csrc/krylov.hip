@@ -118,6 +118,13 @@ __global__ void __launch_bounds__(KT) kk_finalize(KBatch k, int kind, const int*
     double v[3];
     final_sum<3>(k.partials, k.pstride, k.ntile, sys, v);
     if (threadIdx.x == 0) fin_omega(st, &k.status[sys], v);
+  } else if (kind == FIN_SOMEGA) {
+    double v[4];
+    final_sum<4>(k.partials, k.pstride, k.ntile, sys, v);
+    if (threadIdx.x == 0) {
+      fin_s(st, &k.status[sys], v[3]);
+      if (k.status[sys] == ST_ACTIVE) fin_omega(st, &k.status[sys], v);
+    }
   } else {
     double v[3];
     final_sum<3>(k.partials, k.pstride, k.ntile, sys, v);

@@ -210,7 +210,7 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
 
   const double scale = a.scale;
   const int mode = a.out_mode;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   constexpr int E = (L + T - 1) / T;
   constexpr int CH = 4;
 #pragma unroll
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
         ci[u] = chi[k];
         xv[u] = a.x[vrow + k];
         if (mode == 1 || mode == 3) ov[u] = a.rhat[vrow + k];
-        if (mode == 2) ov[u] = a.s[vrow + k];
+        if (mode == 2 || mode == 4) ov[u] = a.s[vrow + k];
       }
     }
 #pragma unroll
@@ -240,11 +240,12 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
           const c128 d = cdot1(ov[u], out);
           acc[0] += d.x;
           acc[1] += d.y;
-        } else if (mode == 2) {   // <y, s>, <y, y>
+        } else if (mode == 2 || mode == 4) {   // <y, s>, <y, y> (and ||s||^2)
           const c128 d = cdot1(out, ov[u]);
           acc[0] += d.x;
           acc[1] += d.y;
           acc[2] += abs2(out);
+          if (mode == 4) acc[3] += abs2(ov[u]);
         }
       }
     }
@@ -253,7 +254,10 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
     double sum[2] = {acc[0], acc[1]};
     write_partial<2>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
   } else if (mode == 2) {
-    write_partial<3>(acc, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
+    double sum[3] = {acc[0], acc[1], acc[2]};
+    write_partial<3>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
+  } else if (mode == 4) {
+    write_partial<4>(acc, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
   }
 }
 
@@ -438,7 +442,7 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArg
   const double scale = a.scale;
   const int mode = a.out_mode;
   const c128* chi = a.chi_inv + sys * a.cstride;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   constexpr int CH = 4;
   for (int e0 = 0; e0 < ne; e0 += CH * BT) {
     c128 ci[CH], xv[CH], ov[CH];
@@ -450,7 +454,7 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArg
         ci[u] = chi[(int64_t)((pl0 + q) % nz) * pe + (e - q * pe)];
         xv[u] = a.x[v0 + e];
         if (mode == 1 || mode == 3) ov[u] = a.rhat[v0 + e];
-        if (mode == 2) ov[u] = a.s[v0 + e];
+        if (mode == 2 || mode == 4) ov[u] = a.s[v0 + e];
       }
     }
 #pragma unroll
@@ -469,11 +473,12 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArg
           const c128 d = cdot1(ov[u], out);
           acc[0] += d.x;
           acc[1] += d.y;
-        } else if (mode == 2) {   // <y, s>, <y, y>
+        } else if (mode == 2 || mode == 4) {   // <y, s>, <y, y> (and ||s||^2)
           const c128 d = cdot1(out, ov[u]);
           acc[0] += d.x;
           acc[1] += d.y;
           acc[2] += abs2(out);
+          if (mode == 4) acc[3] += abs2(ov[u]);
         }
       }
     }
@@ -482,7 +487,10 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArg
     double sum[2] = {acc[0], acc[1]};
     write_partial<2>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
   } else if (mode == 2) {
-    write_partial<3>(acc, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
+    double sum[3] = {acc[0], acc[1], acc[2]};
+    write_partial<3>(sum, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
+  } else if (mode == 4) {
+    write_partial<4>(acc, a.k.partials, a.k.pstride, a.k.ntile, sys, tile, tiles);
   }
 }
 
@@ -1076,9 +1084,9 @@ template <typename R>
 void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c128* x, c128* y, hipStream_t s) {
   if (b.nsys <= 0) return;
   if (!x || !y) throw std::runtime_error("mvm_pass5: missing vectors");
-  if ((f.out_mode == 1 || f.out_mode == 2) && !k)
+  if ((f.out_mode == 1 || f.out_mode == 2 || f.out_mode == 4) && !k)
     throw std::runtime_error("mvm_pass5: missing Krylov batch");
-  if (((f.out_mode == 1 || f.out_mode == 3) && !f.rhat) || (f.out_mode == 2 && !f.s))
+  if (((f.out_mode == 1 || f.out_mode == 3) && !f.rhat) || ((f.out_mode == 2 || f.out_mode == 4) && !f.s))
     throw std::runtime_error("mvm_pass5: missing fused vectors");
   RowArgs<R> ra = row_args<R>(b, k, f, x, y, false);
   ra.out_mode = f.out_mode;

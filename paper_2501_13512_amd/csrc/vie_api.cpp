@@ -458,12 +458,14 @@ static void join(const Branches& br, int phase, hipStream_t s) {
 }
 
 // One BiCGSTAB step with K = I for several batches at once, phase by phase:
-// [p update + product + <rhat,v>] -> alpha -> [s update + ||s||] -> half-step
-// test -> [rest of the product + <t,s>, <t,t>] -> omega -> [x, r update +
-// <rhat,r>, ||r||] -> rho, beta, convergence.  Each bracket is one chain of
-// launches per batch (run on the batch's branch stream if given); each arrow
-// one finalize launch for all systems (`all`) on `s`, so a step is 11
-// launches per batch plus 4.
+// [p update + product + <rhat,v>] -> alpha -> [s update + product + <t,s>,
+// <t,t>, ||s||] -> half-step test and omega -> [x, r update + <rhat,r>,
+// ||r||] -> rho, beta, convergence.  Each bracket is one chain of launches
+// per batch (run on the batch's branch stream if given); each arrow one
+// finalize launch for all systems (`all`) on `s`.  The product t = A s runs
+// before the half-step test: a system that converges at the half step
+// computes one product it does not use, and every step saves a finalize
+// launch and a join of the branches.
 template <typename R>
 void fused_steps(const std::vector<MvmBatch<R>>& m, const std::vector<KBatch>& k, const std::vector<StepVecs>& v,
                  const KBatch& all, const Branches& br, hipStream_t s) {
@@ -480,23 +482,17 @@ void fused_steps(const std::vector<MvmBatch<R>>& m, const std::vector<KBatch>& k
   vie::k_finalize(all, vie::FIN_ALPHA, s);
   fork(br, 1, s);
   for (size_t g = 0; g < G; ++g) {
-    const vie::FuseArgs f2{2, 2, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
+    const vie::FuseArgs f2{2, 4, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
     vie::mvm_pass1<R>(m[g], &k[g], f2, nullptr, false, bs(g));
-  }
-  join(br, 1, s);
-  vie::k_finalize(all, vie::FIN_S, s);
-  fork(br, 2, s);
-  for (size_t g = 0; g < G; ++g) {
-    const vie::FuseArgs f2{2, 2, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
     vie::mvm_mid<R>(m[g], bs(g));
     vie::mvm_pass5<R>(m[g], &k[g], f2, v[g].s, v[g].t, bs(g));
   }
-  join(br, 2, s);
-  vie::k_finalize(all, vie::FIN_OMEGA, s);
-  fork(br, 3, s);
+  join(br, 1, s);
+  vie::k_finalize(all, vie::FIN_SOMEGA, s);
+  fork(br, 2, s);
   for (size_t g = 0; g < G; ++g)
     vie::k_update_xr(k[g], v[g].x, v[g].p, v[g].s, v[g].r, v[g].s, v[g].t, v[g].rhat, bs(g));
-  join(br, 3, s);
+  join(br, 2, s);
   vie::k_finalize(all, vie::FIN_XR, s);
 }
 
