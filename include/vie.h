@@ -87,8 +87,12 @@ typedef struct {
 
 typedef enum {
   VIE_FP64 = 0,   /* every product, vector and reduction in FP64 */
-  VIE_MIXED = 1   /* FFT products in complex FP32; vectors, inner products and
+  VIE_MIXED = 1,  /* FFT products in complex FP32; vectors, inner products and
                      the iterative-refinement residual in FP64 */
+  VIE_MIXED_INNER = 2  /* solves only: the inner block solves' products in
+                          complex FP32, the full-grid products and everything
+                          else in FP64 (no refinement needed); other entry
+                          points taking a precision reject it */
 } vie_precision;
 
 /* Solver settings (Sec. II-B and III: outer/inner residual tolerances). */

@@ -650,7 +650,8 @@ struct RunResult {
 };
 
 // Right-preconditioned BiCGSTAB on the full grid: A x = rhs (Sec. II-B).
-template <typename R>
+// R: precision of the full-grid products; RI: of the inner block solves.
+template <typename R, typename RI = R>
 RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int maxit, bool prec, double tol_in,
                        int maxit_in, int lag, int32_t* hist, int64_t hist_cap, bool graphs, bool wg,
                        hipStream_t s) {
@@ -669,7 +670,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
       fused_steps<R>(mv, kv, vv, k, Branches{}, s);
     } else {
       vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
-      precond_apply<R>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
+      precond_apply<RI>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
       const vie::FuseArgs fa{0, 1, nullptr, nullptr, nullptr, v[V_RHAT], nullptr};
       vie::mvm_pass1<R>(m, &k, fa, v[V_Y], false, s);
       vie::mvm_mid<R>(m, s);
@@ -677,7 +678,7 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
       vie::k_finalize(k, vie::FIN_ALPHA, s);
       vie::k_update_s(k, v[V_R], v[V_V], v[V_S], s);
       vie::k_finalize(k, vie::FIN_S, s);
-      precond_apply<R>(P, v[V_S], v[V_Z], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
+      precond_apply<RI>(P, v[V_S], v[V_Z], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
       const vie::FuseArgs fo{0, 2, nullptr, nullptr, nullptr, nullptr, v[V_S]};
       vie::mvm_pass1<R>(m, &k, fo, v[V_Z], false, s);
       vie::mvm_mid<R>(m, s);
@@ -778,8 +779,8 @@ vie::GmresDev gmres_dev(vie_problem& P) {
 // of eq. (10) once and the product once; the preconditioned vectors are kept
 // because the inexact inner solves make the preconditioner change from step
 // to step.  Cycles of m steps end with x += Z y and a restart from the
-// residual b - A x (in the product precision R).
-template <typename R>
+// residual b - A x (in the product precision R; RI: inner block solves).
+template <typename R, typename RI = R>
 RunResult run_fgmres(vie_problem& P, const c128* rhs, c128* x, double tol, int maxit, int restart, bool prec,
                      double tol_in, int maxit_in, int lag, int32_t* hist, int64_t hist_cap, bool graphs, bool wg,
                      hipStream_t s) {
@@ -801,7 +802,7 @@ RunResult run_fgmres(vie_problem& P, const c128* rhs, c128* x, double tol, int m
     for (int j = 0; j < d.m; ++j) {
       const c128* src = V(j);
       if (prec) {
-        precond_apply<R>(P, V(j), Z(j), tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
+        precond_apply<RI>(P, V(j), Z(j), tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
         src = Z(j);
       }
       vie::mvm<R>(mg, src, V(j + 1), false, s);
@@ -848,7 +849,8 @@ void validate_opts(const vie_opts* o, bool has_blocks) {
   if (!o) fail(VIE_EINVAL, "opts is NULL");
   if (!(o->tol_outer >= 0) || !is_finite(o->tol_outer)) fail(VIE_EINVAL, "tol_outer must be finite and >= 0");
   if (o->maxit_outer < 0 || o->maxit_outer > 1000000) fail(VIE_EINVAL, "maxit_outer out of range");
-  if (o->precision != VIE_FP64 && o->precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
+  if (o->precision != VIE_FP64 && o->precision != VIE_MIXED && o->precision != VIE_MIXED_INNER)
+    fail(VIE_EINVAL, "unknown precision");
   if (o->poll_lag < 0 || o->poll_lag > kRing - 2) fail(VIE_EINVAL, "poll_lag out of range");
   if (o->max_refine < 0 || o->max_refine > 100) fail(VIE_EINVAL, "max_refine out of range");
   if (o->flags & ~(VIE_FLAG_NO_GRAPHS | VIE_FLAG_NO_BLOCK_KERNEL)) fail(VIE_EINVAL, "unknown flags");
@@ -885,26 +887,31 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   int refine = 0, refine_iters = 0;
   double relres_true = 0;
   const bool fgmres = o->solver == VIE_SOLVER_FGMRES;
-  auto run = [&](auto tag, const c128* rhs, c128* x, double tol) {
+  auto run = [&](auto tag, auto itag, const c128* rhs, c128* x, double tol) {
     using R = decltype(tag);
+    using RI = decltype(itag);
     if (fgmres)
-      return run_fgmres<R>(P, rhs, x, tol, o->maxit_outer, o->restart, prec, o->tol_inner, o->maxit_inner,
-                           o->poll_lag, hist, hist_cap, graphs, wg, s);
-    return run_bicgstab<R>(P, rhs, x, tol, o->maxit_outer, prec, o->tol_inner, o->maxit_inner, o->poll_lag, hist,
-                           hist_cap, graphs, wg, s);
+      return run_fgmres<R, RI>(P, rhs, x, tol, o->maxit_outer, o->restart, prec, o->tol_inner, o->maxit_inner,
+                               o->poll_lag, hist, hist_cap, graphs, wg, s);
+    return run_bicgstab<R, RI>(P, rhs, x, tol, o->maxit_outer, prec, o->tol_inner, o->maxit_inner, o->poll_lag,
+                               hist, hist_cap, graphs, wg, s);
   };
-  if (o->precision == VIE_FP64) {
-    rr = run(double{}, v[V_B], v[V_X], o->tol_outer);
+  if (o->precision == VIE_FP64 || o->precision == VIE_MIXED_INNER) {
+    // FP64 full-grid products: the recursive residual stays accurate, no refinement
+    if (o->precision == VIE_FP64)
+      rr = run(double{}, double{}, v[V_B], v[V_X], o->tol_outer);
+    else
+      rr = run(double{}, float{}, v[V_B], v[V_X], o->tol_outer);
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], rr.st.nb, s);
   } else {
-    rr = run(float{}, v[V_B], v[V_X], o->tol_outer);
+    rr = run(float{}, float{}, v[V_B], v[V_X], o->tol_outer);
     const double nb = rr.st.nb;
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
     // iterative refinement: solve A d = b - A x with FP32 products, x += d
     while (rr.status != vie::ST_BREAKDOWN && relres_true > o->tol_outer && refine < o->max_refine && nb > 0 &&
            !(P.cancel && P.cancel->load())) {
       const double tol_c = std::min(0.5, o->tol_outer / relres_true);
-      RunResult rc = run(float{}, v[V_TMP2], v[V_TMP1], tol_c);
+      RunResult rc = run(float{}, float{}, v[V_TMP2], v[V_TMP1], tol_c);
       vie::add_vec(v[V_X], v[V_TMP1], 3 * P.nv, s);
       ++refine;
       refine_iters += rc.st.iters;

@@ -47,7 +47,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 VIE_OK, VIE_NOT_CONVERGED = 0, 1
 VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_EBREAKDOWN, VIE_EBUSY, VIE_ECANCELLED, VIE_EINTERNAL = -1, -2, -3, -4, -5, -6, -7
 VIE_ETIMEDOUT = -8
-VIE_FP64, VIE_MIXED = 0, 1
+VIE_FP64, VIE_MIXED, VIE_MIXED_INNER = 0, 1, 2
 VIE_FLAG_NO_GRAPHS = 1
 VIE_FLAG_NO_BLOCK_KERNEL = 2
 VIE_SOLVER_BICGSTAB, VIE_SOLVER_FGMRES = 0, 1

@@ -305,3 +305,34 @@ def test_graph_replays_match_eager_launches(vie_ctx):
         runs = [o for o in outs if o[1] == prec]
         for r in runs[1:]:
             assert np.array_equal(r[2], runs[0][2]) and r[3:] == runs[0][3:]
+
+
+@pytest.mark.parametrize("flags", BLOCK_MODES)
+def test_cube_mixed_inner_precision(vie_ctx, cube_oracle, flags):
+    """VIE_MIXED_INNER: FP32 products in the inner block solves only, FP64
+    full-grid products.  The outer step count is set by the inexact FP32
+    preconditioner, not by the outer products: it lies in the spread of the
+    oracle runs with complex64 products everywhere (44-48 on this case, 30
+    in FP64) +-2, as in the fully mixed mode; the field matches the FP64
+    oracle to 1e-5, with no refinement step."""
+    case, o = cube_oracle
+    ref = o[("pre", 0)]
+    counts = [o[("pre_c64", pad)].info.iterations for pad in (0, 2, 4)]
+    code, e_tot, P, st, _ = _solve(vie_ctx, case, prec=V.VIE_MIXED_INNER, flags=flags)
+    assert code == V.VIE_OK
+    assert min(counts) - 2 <= st.outer_iters <= max(counts) + 2, (st.outer_iters, counts)
+    assert st.refine_steps == 0
+    assert _rel(e_tot, ref.E_tot) <= 1e-5
+    assert st.relres_true <= 1.01 * case.tol_outer
+
+
+def test_mixed_inner_rejected_outside_solves(vie_ctx):
+    case = W.random_tiny(55, (4, 4, 4), fill=0.8)
+    P = V.Problem(_grid(case), case.eps, None, 0, ctx=vie_ctx)
+    try:
+        x = torch.zeros(3 * 64, dtype=torch.complex128, device="cuda")
+        with pytest.raises(V.VieError) as ei:
+            V.vie_matvec(P.handle, V.VIE_MIXED_INNER, x, torch.empty_like(x))
+        assert ei.value.code == V.VIE_EINVAL
+    finally:
+        P.close()
