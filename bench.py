@@ -35,6 +35,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def pass_bytes(nx, ny, nz, lx, ly, lz, s):
     """Algorithmic bytes of the five passes of one product (s = bytes per
     complex element of the transform: 8 in complex64, 16 in complex128;
@@ -215,6 +220,7 @@ def main():
             print(f"solve returned {V.STATUS_NAMES.get(code, code)}", file=sys.stderr)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    log(f"timed solves done: {args.steps} in {elapsed:.2f} s")
 
     # the FP64 GPU paths of the same workload, for comparison
     compare = {}
@@ -234,6 +240,7 @@ def main():
             lt.append(time.perf_counter() - t1)
         sd = V.stats_dict(st)
         d = e64.cpu().numpy()
+        log(f"{label} done: {len(lt)} solves in {sum(lt):.2f} s")
         compare[label] = {"solves_per_s": len(lt) / sum(lt), "latency_ms": {
             "p50": 1e3 * float(np.percentile(lt, 50)), "p99": 1e3 * float(np.percentile(lt, 99))},
             "status": V.STATUS_NAMES.get(c64, c64), "tol_outer": o64.tol_outer, "outer_iters": sd["outer_iters"],
@@ -258,6 +265,7 @@ def main():
             ci = V.vie_solve_device(P.handle, e_inc, oi, ei, None, st)
             lt.append(time.perf_counter() - t1)
         sd = V.stats_dict(st)
+        log(f"mixed-inner variant done: {len(lt)} solves in {sum(lt):.2f} s")
         variants["bicgstab_mixed_inner"] = {
             "tol_outer": case.tol_outer, "solves_per_s": len(lt) / sum(lt),
             "latency_ms": {"p50": 1e3 * float(np.percentile(lt, 50)), "p99": 1e3 * float(np.percentile(lt, 99))},
@@ -278,6 +286,7 @@ def main():
         sd = V.stats_dict(st)
         f = ef.cpu().numpy()
         mine = e_tot.cpu().numpy()
+        log(f"fgmres variant done: {len(lt)} solves in {sum(lt):.2f} s")
         variants["fgmres"] = {
             "restart": args.fgmres_restart, "tol_outer": args.fgmres_tol, "solves_per_s": len(lt) / sum(lt),
             "latency_ms": {"p50": 1e3 * float(np.percentile(lt, 50)), "p99": 1e3 * float(np.percentile(lt, 99))},
@@ -350,6 +359,7 @@ def main():
     ge = golden_error(case, e_tot.cpu().numpy())
     if ge is not None:
         res["field_check"] = ge
+    log("product profiles done")
     if not args.no_cpu_baseline:
         # the FP64 GPU path runs the oracle's algorithm: its outer count at
         # this tolerance stands for the oracle's
