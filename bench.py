@@ -90,10 +90,11 @@ def mvm_profile(V, handle, info, nx, ny, nz, prec, reps):
             "dominant": {"kernel": names[dom], "achieved": achieved, "bytes": pb[dom], "ms": float(ms[dom])}}
 
 
-def traffic_for(kernel, workload, precision, lz):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel
-    calibration), or None if no summary covers this kernel build."""
+def counters_for(kernel, workload, precision, lz):
+    """Counter entry of `kernel` on `workload` from the committed summary
+    (HBM bytes per launch from FETCH_SIZE and WRITE_SIZE scaled by a
+    copy-kernel calibration; wavefront VALU instructions per launch), or
+    None if no summary covers this kernel build."""
     from paper_2501_13512_amd.profile_traffic import kernel_hash
     path = os.path.join(ROOT, "profiles", "mvm_hbm_traffic.json")
     if not os.path.exists(path):
@@ -103,7 +104,7 @@ def traffic_for(kernel, workload, precision, lz):
     for e in d.get("entries", []):
         if (e.get("kernel") == kernel and e.get("workload") == workload and e.get("source_hash") == h
                 and e.get("precision") == precision and e.get("lz") == lz):
-            return e.get("bytes_per_launch")
+            return e
     return None
 
 
@@ -301,7 +302,16 @@ def main():
     mv = mvm_profile(V, P.handle, info, case.nx, case.ny, case.nz, prec, args.profile_reps)
     dom = mv["dominant"]
     wl = f"{case.name} {case.nx}x{case.ny}x{case.nz} {args.precision}"
-    traffic = traffic_for(dom["kernel"], wl, "float" if prec == V.VIE_MIXED else "double", info.lz)
+    cnt = counters_for(dom["kernel"], wl, "float" if prec == V.VIE_MIXED else "double", info.lz)
+    traffic = cnt.get("bytes_per_launch") if cnt else None
+    valu = None
+    if cnt and cnt.get("valu_insts_per_launch"):
+        # wave64 VALU issue without packed FP32: one instruction per 4 cycles
+        # per SIMD, 4 SIMDs per CU, 256 CUs at 2.4 GHz
+        issue_peak = 256 * 4 * 2.4e9 / 4
+        vi = cnt["valu_insts_per_launch"]
+        valu = {"insts_per_launch": vi, "issue_peak_per_s": issue_peak,
+                "frac": vi / (issue_peak * dom["ms"] * 1e-3), "min_us": 1e6 * vi / issue_peak}
     extra = {}
     for spec in [v for v in args.mvm_shapes.split(",") if v]:
         nx, ny, nz = (int(v) for v in spec.split("x"))
@@ -349,7 +359,7 @@ def main():
         "relres_true": stats[-1]["relres_true"],
         "mvm": mv,
         "roofline": {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": dom["achieved"] / HBM_PEAK_GBS, "traffic": traffic, "valu_issue": valu,
                      "kernel": dom["kernel"] + f" (full-grid product, {args.precision})"},
         "mvm_other_grids": extra,
         "fp64_gpu_paths": compare,

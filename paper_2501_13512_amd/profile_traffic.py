@@ -1,6 +1,6 @@
 """HBM traffic per launch of libvie kernels from rocprofv3 counter runs.
 
-    python -m paper_2501_13512_amd.profile_traffic FETCH_DIR WRITE_DIR WORKLOAD OUT.json
+    python -m paper_2501_13512_amd.profile_traffic FETCH_DIR WRITE_DIR WORKLOAD OUT.json [VALU_DIR]
 
 FETCH_DIR / WRITE_DIR: output directories of two ``rocprofv3 --pmc FETCH_SIZE``
 and ``rocprofv3 --pmc WRITE_SIZE`` runs (``--output-format csv``) of a
@@ -10,6 +10,8 @@ read the copy's true byte count (the largest ``__amd_rocclr_copyBuffer``
 dispatches); the result is the mean HBM bytes per dispatch of every z-pass
 kernel variant, written with a hash of the kernel sources so that a reader
 can tell whether the numbers still describe the current kernels.
+VALU_DIR (optional): a ``rocprofv3 --pmc SQ_INSTS_VALU`` run of the same
+program; adds the mean wavefront VALU instructions per dispatch.
 """
 from __future__ import annotations
 
@@ -56,9 +58,10 @@ def _label(name):
     return None
 
 
-def main(fetch_dir, write_dir, workload, out):
+def main(fetch_dir, write_dir, workload, out, valu_dir=None):
     fk = _per_kernel(_rows(fetch_dir))
     wk = _per_kernel(_rows(write_dir))
+    vk = _per_kernel(_rows(valu_dir)) if valu_dir else {}
     copy = "__amd_rocclr_copyBuffer"
     fc = max(fk[copy], key=lambda t: t[0])
     big_f = [v for g, v in fk[copy] if g == fc[0]]
@@ -77,6 +80,8 @@ def main(fetch_dir, write_dir, workload, out):
                         "fetch_kib": kib_f, "write_kib": kib_w,
                         "bytes_per_launch": 1024 * (kib_f * f_factor + kib_w * w_factor),
                         "source_hash": kernel_hash()})
+        if name in vk:
+            entries[-1]["valu_insts_per_launch"] = sum(v for _, v in vk[name]) / len(vk[name])
     doc = {"note": "HBM bytes per dispatch = FETCH_SIZE * f + WRITE_SIZE * w (KiB * 1024); f, w make the counters "
                    "read the true bytes of a 512 MiB device copy in the same runs",
            "fetch_factor": f_factor, "write_factor": w_factor, "entries": entries}
@@ -85,4 +90,4 @@ def main(fetch_dir, write_dir, workload, out):
 
 
 if __name__ == "__main__":
-    main(*sys.argv[1:5])
+    main(*sys.argv[1:6])
