@@ -168,6 +168,9 @@ def main():
     ap.add_argument("--plain-tol", type=float, default=5e-7,
                     help="outer tolerance of the unpreconditioned FP64 comparison path: at the same residual the "
                          "plain iterate is farther from the converged field (2.3e-5 at 2e-6 on this workload)")
+    ap.add_argument("--batch-rhs", type=int, default=8,
+                    help="right-hand sides of the batched unpreconditioned FP64 solve (incidence directions tilted "
+                         "about x; 0 = skip)")
     ap.add_argument("--variant-steps", type=int, default=3,
                     help="solves of the flexible GMRES(m) outer-solver variant (same preconditioner and precision); "
                          "0 = skip")
@@ -297,6 +300,36 @@ def main():
             "field_check": golden_error(case, f),
             "rel_field_diff_vs_bicgstab": float(np.linalg.norm(f - mine) / np.linalg.norm(mine)),
             "footprint_bytes": int(P.info().footprint_bytes)}
+
+    # several incident directions on the same operator: the unpreconditioned
+    # FP64 path as one batch (vie_solve_batch) against the same solves one by one
+    if args.batch_rhs > 0 and args.compare_steps > 0 and args.maxit_outer is None:
+        nb_rhs = args.batch_rhs
+        waves = []
+        for r in range(nb_rhs):
+            th = 0.5 * np.pi * r / max(nb_rhs, 1)   # tilt in the y-z plane, polarised along x
+            waves.append(((0.0, float(np.sin(th)), float(np.cos(th))), (1.0, 0.0, 0.0)))
+        eb = torch.from_numpy(np.stack([V.vie_plane_wave(grid, k, pv) for k, pv in waves])).cuda()
+        ob = torch.empty_like(eb)
+        stb = (V.vie_stats * nb_rhs)()
+        o64 = V.make_opts(tol_outer=args.plain_tol, maxit_outer=4 * case.maxit_outer, precondition=False,
+                          precision=V.VIE_FP64)
+        V.vie_solve_batch(P.handle, nb_rhs, eb, o64, ob, None, stb)   # warm-up (storage)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cb = V.vie_solve_batch(P.handle, nb_rhs, eb, o64, ob, None, stb)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        for r in range(nb_rhs):
+            V.vie_solve_device(P.handle, eb[r].contiguous(), o64, ob[r], None, st)
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t1
+        variants["fp64_unpreconditioned_batch"] = {
+            "nrhs": nb_rhs, "tol_outer": args.plain_tol, "status": V.STATUS_NAMES.get(cb, cb),
+            "solves_per_s": nb_rhs / t_batch, "one_by_one_solves_per_s": nb_rhs / t_one,
+            "outer_iters": [int(stb[r].outer_iters) for r in range(nb_rhs)]}
+        log(f"batched right-hand sides done: {nb_rhs} in {t_batch:.2f} s (one by one {t_one:.2f} s)")
 
     # FFT product of the full grid, per pass, HIP events on the launch stream
     mv = mvm_profile(V, P.handle, info, case.nx, case.ny, case.nz, prec, args.profile_reps)

@@ -282,6 +282,11 @@ struct vie_problem {
   DevBuf gm_basis, gm_small, gm_part, gm_state;
   int gm_m = 0;
   bool gm_z = false;
+  // batched right-hand sides (plain BiCGSTAB), allocated by the first batch
+  // solve: kBatchVecs vectors, one FFT work buffer and the Krylov scalars per
+  // right-hand side
+  DevBuf mr_vecs, mr_work, mr_state, mr_status, mr_partials, mr_ntile, mr_count;
+  int mr_cap = 0;
 
   ~vie_problem() {
     for (auto& gp : inner_graph)
@@ -433,12 +438,8 @@ struct StepVecs {
   c128 *x, *r, *rhat, *p, *v, *s, *t;
 };
 
-// One BiCGSTAB step with K = I for several batches at once, phase by phase:
-// [p update + product + <rhat,v>] -> alpha -> [s update + ||s||] -> half-step
-// test -> [rest of the product + <t,s>, <t,t>] -> omega -> [x, r update +
-// <rhat,r>, ||r||] -> rho, beta, convergence.  Each bracket is one group of
-// launches per batch; each arrow one finalize launch for all systems
-// (`all`), so a step is 11 launches per batch plus 4.
+// Branch streams of a captured step: fork from `s` before a phase, join back
+// after it.
 static void fork(const Branches& br, int phase, hipStream_t s) {
   if (br.streams.empty()) return;
   const size_t G = br.streams.size();
@@ -866,8 +867,11 @@ void validate_opts(const vie_opts* o, bool has_blocks) {
 
 void set_device(vie_context* ctx) { hip_check(hipSetDevice(ctx->device), "hipSetDevice"); }
 
+// One solve.  With `solved`, the main iteration has already run (a batch of
+// right-hand sides): V_B and V_X hold this system's rhs and iterate, and
+// only the true residual, refinement, fields and statistics follow.
 vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128* e_tot, c128* pol,
-                      vie_stats* stats, hipStream_t s) {
+                      vie_stats* stats, hipStream_t s, const RunResult* solved = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   vie_problem& P = *p;
   c128** v = P.vec;
@@ -882,7 +886,7 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     hist_cap = stats->inner_hist_cap;
   }
   if (prec) hip_check(hipMemsetAsync(P.d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
-  vie::masked_copy(e_inc, P.chi.as<c128>(), v[V_B], P.nv, s);
+  if (!solved) vie::masked_copy(e_inc, P.chi.as<c128>(), v[V_B], P.nv, s);
   RunResult rr;
   int refine = 0, refine_iters = 0;
   double relres_true = 0;
@@ -898,13 +902,15 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   };
   if (o->precision == VIE_FP64 || o->precision == VIE_MIXED_INNER) {
     // FP64 full-grid products: the recursive residual stays accurate, no refinement
-    if (o->precision == VIE_FP64)
+    if (solved)
+      rr = *solved;
+    else if (o->precision == VIE_FP64)
       rr = run(double{}, double{}, v[V_B], v[V_X], o->tol_outer);
     else
       rr = run(double{}, float{}, v[V_B], v[V_X], o->tol_outer);
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], rr.st.nb, s);
   } else {
-    rr = run(float{}, float{}, v[V_B], v[V_X], o->tol_outer);
+    rr = solved ? *solved : run(float{}, float{}, v[V_B], v[V_X], o->tol_outer);
     const double nb = rr.st.nb;
     relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
     // iterative refinement: solve A d = b - A x with FP32 products, x += d
@@ -961,6 +967,97 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   return VIE_NOT_CONVERGED;
 }
 
+// Vectors of a batch of right-hand sides: B, X, R, RHAT, P, V, S, T.
+constexpr int kBatchVecs = 8;
+
+void ensure_batch(vie_problem& P, int nrhs) {
+  if (P.mr_cap >= nrhs) return;
+  const int64_t n = 3 * P.nv;
+  const size_t vecs = (size_t)kBatchVecs * nrhs * n * sizeof(c128);
+  const size_t work = (size_t)nrhs * 3 * P.g.nz * P.ly * P.lx * sizeof(c128);
+  const size_t small = (size_t)nrhs * (sizeof(KState) + 2 * sizeof(int) + (size_t)P.pstride * sizeof(double)) +
+                       sizeof(int);
+  const size_t total = vecs + work + small;
+  const size_t old = P.mr_vecs.bytes + P.mr_work.bytes + P.mr_state.bytes + P.mr_status.bytes +
+                     P.mr_partials.bytes + P.mr_ntile.bytes + P.mr_count.bytes;
+  vie_context* ctx = P.ctx;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const size_t others = ctx->used + ctx->reserved - std::min(ctx->used + ctx->reserved, old);
+    if (ctx->budget && others + total > ctx->budget) fail(VIE_EBUSY, "batch storage exceeds the context's HBM budget");
+    ctx->used = ctx->used - std::min(ctx->used, old) + total;
+  }
+  P.footprint = P.footprint - std::min(P.footprint, old) + total;
+  P.mr_cap = 0;
+  DevBuf* bufs[] = {&P.mr_vecs, &P.mr_work, &P.mr_state, &P.mr_status, &P.mr_partials, &P.mr_ntile, &P.mr_count};
+  for (DevBuf* b : bufs) b->reset();
+  try {
+    P.mr_vecs.alloc(vecs);
+    P.mr_work.alloc(work);
+    P.mr_state.alloc((size_t)nrhs * sizeof(KState));
+    P.mr_status.alloc((size_t)nrhs * sizeof(int));
+    P.mr_partials.alloc((size_t)nrhs * P.pstride * sizeof(double));
+    P.mr_ntile.alloc((size_t)nrhs * sizeof(int));
+    P.mr_count.alloc(sizeof(int));
+  } catch (...) {
+    for (DevBuf* b : bufs) b->reset();
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->used -= std::min(ctx->used, total);
+    P.footprint -= std::min(P.footprint, total);
+    throw;
+  }
+  P.mr_cap = nrhs;
+}
+
+c128* batch_vec(vie_problem& P, int kind, int nrhs) {
+  return P.mr_vecs.as<c128>() + (int64_t)kind * nrhs * 3 * P.nv;
+}
+
+// nrhs systems with the full-grid operator: shared 1/chi and spectra, one
+// work buffer, vector and status per system.
+template <typename R>
+MvmBatch<R> batch_mvm(vie_problem& P, int nrhs) {
+  MvmBatch<R> b = outer_batch<R>(P, true);
+  b.nsys = nrhs;
+  b.cstride = 0;
+  b.work = P.mr_work.as<cx<R>>();
+  b.status = P.mr_status.as<int>();
+  return b;
+}
+
+KBatch batch_kbatch(vie_problem& P, int nrhs) {
+  KBatch k{};
+  k.nsys = nrhs;
+  k.n = 3 * P.nv;
+  k.status = P.mr_status.as<int>();
+  k.st = P.mr_state.as<KState>();
+  k.partials = P.mr_partials.as<double>();
+  k.pstride = P.pstride;
+  k.ntile = P.mr_ntile.as<int>();
+  return k;
+}
+
+// Plain BiCGSTAB of nrhs systems in one batch (x0 = 0): every launch covers
+// all systems, each stops on its own status (same per-system arithmetic as a
+// single solve).  Rhs in batch vector B, iterates in X.
+template <typename R>
+void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag, hipStream_t s) {
+  const KBatch k = batch_kbatch(P, nrhs);
+  auto vec = [&](int kind) { return batch_vec(P, kind, nrhs); };
+  vie::k_init(k, vec(0), vec(1), vec(2), vec(3), nullptr, s);
+  vie::k_finalize(k, vie::FIN_INIT, s, nullptr, tol, maxit);
+  const std::vector<MvmBatch<R>> mv{batch_mvm<R>(P, nrhs)};
+  const std::vector<KBatch> kv{k};
+  const std::vector<StepVecs> vv{{vec(1), vec(2), vec(3), vec(4), vec(5), vec(6), vec(7)}};
+  Poller poll(P, s, 0);
+  for (int it = 1; it <= maxit; ++it) {
+    fused_steps<R>(mv, kv, vv, k, Branches{}, s);
+    vie::count_active(P.mr_status.as<int>(), nrhs, P.mr_count.as<int>(), s);
+    const long t = poll.push(P.mr_count.as<int>());
+    if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
+  }
+  hip_check(hipStreamSynchronize(s), "batch solve");
+}
 
 // ------------------------------------------------------------------ problem set-up
 // Host-side plan of a problem: 1/chi, block ids, the blocks' bounding boxes
@@ -1860,6 +1957,62 @@ vie_status vie_solve_device(vie_problem* p, const void* e_inc_dev, const vie_opt
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
     return solve_impl(p, (const c128*)e_inc_dev, opts, (c128*)e_tot_dev, (c128*)pol_dev, stats, (hipStream_t)stream);
+  });
+}
+
+vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, const vie_opts* opts,
+                           void* e_tot_dev, void* pol_dev, vie_stats* stats, void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !e_inc_dev || !e_tot_dev) fail(VIE_EINVAL, "problem, e_inc and e_tot are required");
+    if (nrhs < 1 || nrhs > 4096) fail(VIE_EINVAL, "nrhs must be in [1, 4096]");
+    validate_opts(opts, !p->groups.empty());
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    vie_problem& P = *p;
+    const int64_t n = 3 * P.nv;
+    const c128* ein = (const c128*)e_inc_dev;
+    c128* eout = (c128*)e_tot_dev;
+    c128* pol = (c128*)pol_dev;
+    // the first error, else a warning, else OK
+    vie_status worst = VIE_OK;
+    auto keep = [&](vie_status st) {
+      if (worst >= 0 && (st < 0 || st > worst)) worst = st;
+    };
+    const bool batched = nrhs > 1 && !opts->precondition && opts->solver == VIE_SOLVER_BICGSTAB;
+    if (!batched) {
+      for (int r = 0; r < nrhs; ++r)
+        keep(solve_impl(p, ein + r * n, opts, eout + r * n, pol ? pol + r * n : nullptr, stats ? &stats[r] : nullptr,
+                        s));
+      return worst;
+    }
+    ensure_batch(P, nrhs);
+    for (int r = 0; r < nrhs; ++r)
+      vie::masked_copy(ein + r * n, P.chi.as<c128>(), batch_vec(P, 0, nrhs) + r * n, P.nv, s);
+    if (opts->precision == VIE_MIXED)
+      run_bicgstab_batch<float>(P, nrhs, opts->tol_outer, opts->maxit_outer, opts->poll_lag, s);
+    else
+      run_bicgstab_batch<double>(P, nrhs, opts->tol_outer, opts->maxit_outer, opts->poll_lag, s);
+    std::vector<KState> st(nrhs);
+    std::vector<int> status(nrhs);
+    hip_check(hipMemcpy(st.data(), P.mr_state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost), "batch state");
+    hip_check(hipMemcpy(status.data(), P.mr_status.p, nrhs * sizeof(int), hipMemcpyDeviceToHost), "batch status");
+    const double batch_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    // per system: true residual, refinement (mixed), fields, statistics
+    for (int r = 0; r < nrhs; ++r) {
+      hip_check(hipMemcpyAsync(P.vec[V_B], batch_vec(P, 0, nrhs) + r * n, n * sizeof(c128), hipMemcpyDeviceToDevice,
+                               s),
+                "batch rhs");
+      hip_check(hipMemcpyAsync(P.vec[V_X], batch_vec(P, 1, nrhs) + r * n, n * sizeof(c128), hipMemcpyDeviceToDevice,
+                               s),
+                "batch iterate");
+      const RunResult rr{st[r], status[r]};
+      keep(solve_impl(p, nullptr, opts, eout + r * n, pol ? pol + r * n : nullptr, stats ? &stats[r] : nullptr, s,
+                      &rr));
+      if (stats) stats[r].seconds += batch_s;
+    }
+    return worst;
   });
 }
 

@@ -58,6 +58,7 @@ ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_c
                "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass",
                "vie_plane_wave",
                "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
+               "vie_solve_batch",
                "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
                "vie_total_field_box", "vie_far_field", "vie_rcs")
 
@@ -118,6 +119,8 @@ for _name, _args in {
                           ctypes.POINTER(ctypes.c_int64)],
     "vie_solve": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats)],
     "vie_solve_device": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats), _vp],
+    "vie_solve_batch": [_vp, ctypes.c_int32, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats),
+                        _vp],
     "vie_server_start": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_footprint": [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "vie_submit": [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(vie_opts), ctypes.POINTER(_vp)],
@@ -241,6 +244,13 @@ def vie_solve(p: int, e_inc: np.ndarray, opts: vie_opts, stats: vie_stats, want_
 def vie_solve_device(p: int, e_inc, opts: vie_opts, e_tot, pol, stats: vie_stats, stream=None) -> int:
     return _check(_lib.vie_solve_device(p, _dev(e_inc), ctypes.byref(opts), _dev(e_tot), _dev(pol),
                                         ctypes.byref(stats), _stream(stream)), "vie_solve_device", warn_ok=True)
+
+
+def vie_solve_batch(p: int, nrhs: int, e_inc, opts: vie_opts, e_tot, pol=None, stats=None, stream=None) -> int:
+    """stats: None or a ctypes array of nrhs vie_stats."""
+    st = ctypes.cast(stats, ctypes.POINTER(vie_stats)) if stats is not None else None
+    return _check(_lib.vie_solve_batch(p, int(nrhs), _dev(e_inc), ctypes.byref(opts), _dev(e_tot), _dev(pol), st,
+                                       _stream(stream)), "vie_solve_batch", warn_ok=True)
 
 
 def _host_problem_arrays(eps, block_id):
