@@ -1,11 +1,14 @@
 """Text summary of a rocprofv3 kernel trace (``--kernel-trace --stats
 --output-format csv``).
 
-    python -m paper_2501_13512_amd.profile_summary OUT_DIR [--top N] [--drop-trace]
+    python -m paper_2501_13512_amd.profile_summary OUT_DIR [--top N] [--tail NAME K] [--drop-trace]
 
 Prints the kernels by total time (calls, total, mean), the trace's span,
 busy and idle time, and the distribution of idle gaps between consecutive
 kernels with the kernel pairs that account for most of the long gaps.
+``--tail NAME K`` adds the mean, minimum and maximum duration of the last K
+launches of the kernel whose name contains NAME (e.g. a benchmark's timed
+repetitions at the end of a run).
 ``--drop-trace`` deletes the per-dispatch trace CSV afterwards (it can be
 hundreds of MB for a whole solve).
 """
@@ -23,7 +26,7 @@ def _find(d, suffix):
     return f[0] if f else None
 
 
-def summarize(d: str, top: int = 40) -> str:
+def summarize(d: str, top: int = 40, tail=None) -> str:
     out = []
     stats = _find(d, "kernel_stats.csv")
     if stats:
@@ -57,6 +60,12 @@ def summarize(d: str, top: int = 40) -> str:
                     big[(a, b)] += g
             for (a, b), s in big.most_common(8):
                 out.append(f"  {s / 1e3:8.2f} ms after {a} -> {b}")
+        if tail:
+            name, k = tail[0], int(tail[1])
+            d_us = [(e - s0) / 1e3 for s0, e, n in t if name in n][-k:]
+            if d_us:
+                out.append(f"last {len(d_us)} launches of '{name}': mean {sum(d_us) / len(d_us):.2f} us, "
+                           f"min {min(d_us):.2f}, max {max(d_us):.2f}")
     return "\n".join(out)
 
 
@@ -64,9 +73,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("dir")
     ap.add_argument("--top", type=int, default=40)
+    ap.add_argument("--tail", nargs=2, metavar=("NAME", "K"))
     ap.add_argument("--drop-trace", action="store_true")
     a = ap.parse_args()
-    print(summarize(a.dir, a.top), flush=True)
+    print(summarize(a.dir, a.top, a.tail), flush=True)
     if a.drop_trace:
         tr = _find(a.dir, "kernel_trace.csv")
         if tr:
