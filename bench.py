@@ -178,6 +178,10 @@ def main():
     ap.add_argument("--fgmres-tol", type=float, default=1e-6,
                     help="GMRES stops at its tolerance where BiCGSTAB's last step overshoots; 1e-6 keeps the field "
                          "error under 1e-5 on this workload")
+    ap.add_argument("--other-cases", default="plasmonic",
+                    help="further workloads (comma-separated) reported beside the headline: solves without the block "
+                         "preconditioner (it stalls on metal-sphere blocks), mixed and FP64, and their product's roofline; "
+                         "'' for none")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also copy 512 MiB device to device three times (reference kernel for HBM counters)")
     ap.add_argument("--mvm-shapes", default="256x256x64",
@@ -357,6 +361,39 @@ def main():
             p["frac_of_hbm_peak"] = p["algorithmic_GBps"] / HBM_PEAK_GBS
         Q.close()
 
+    others = {}
+    for name in [v for v in args.other_cases.split(",") if v] if args.maxit_outer is None else []:
+        oc = W.by_name(name)
+        og = V.make_grid(oc.nx, oc.ny, oc.nz, oc.dx, oc.dy, oc.dz, oc.wavelength)
+        Q = V.Problem(og, oc.eps, None, 0, ctx=ctx)
+        qi = Q.info()
+        qe = torch.from_numpy(V.vie_plane_wave(og, oc.kdir, oc.pol)).cuda()
+        qo = torch.empty_like(qe)
+        entry = {"grid": [oc.nx, oc.ny, oc.nz], "fft": [qi.lx, qi.ly, qi.lz], "tol_outer": oc.tol_outer,
+                 "maxit_outer": 6000}
+        for label, pv in (("mixed", V.VIE_MIXED), ("fp64", V.VIE_FP64)):
+            oo = V.make_opts(tol_outer=oc.tol_outer, maxit_outer=6000, precondition=False, precision=pv)
+            V.vie_solve_device(Q.handle, qe, oo, qo, None, st)   # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            cq = V.vie_solve_device(Q.handle, qe, oo, qo, None, st)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            entry[label] = {"solves_per_s": 1.0 / dt, "status": V.STATUS_NAMES.get(cq, cq),
+                            "outer_iters": st.outer_iters, "refine_steps": st.refine_steps,
+                            "relres_true": st.relres_true}
+            if label == "mixed":
+                mixed_field = qo.cpu().numpy()
+            else:
+                f64 = qo.cpu().numpy()
+                entry["mixed_vs_fp64_rel_field_diff"] = float(np.linalg.norm(mixed_field - f64) / np.linalg.norm(f64))
+        pm = mvm_profile(V, Q.handle, qi, oc.nx, oc.ny, oc.nz, V.VIE_MIXED, args.profile_reps)
+        entry["mvm_mixed"] = {"ms": pm["ms"], "algorithmic_GBps": pm["algorithmic_GBps"],
+                              "frac_of_hbm_peak": pm["algorithmic_GBps"] / HBM_PEAK_GBS, "dominant": pm["dominant"]}
+        others[name] = entry
+        Q.close()
+        log(f"{name} done")
+
     if args.calibration_copy:
         ca = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         cb = torch.empty_like(ca)
@@ -397,6 +434,7 @@ def main():
         "mvm_other_grids": extra,
         "fp64_gpu_paths": compare,
         "solver_variants": variants,
+        "other_workloads": others,
         "block_solver_groups": int(info.n_block_solver_groups),
     }
     ge = golden_error(case, e_tot.cpu().numpy())

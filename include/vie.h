@@ -141,7 +141,8 @@ typedef struct {
   int32_t outer_iters;        /* BiCGSTAB steps of the main solve */
   int32_t refine_steps;       /* VIE_MIXED correction solves */
   int32_t refine_iters;       /* BiCGSTAB steps spent in correction solves */
-  int32_t final_state;        /* 1 converged, 3 breakdown, 4 iteration cap */
+  int32_t final_state;        /* main loop: 1 converged, 3 breakdown, 4 iteration cap (VIE_MIXED returns
+                                 VIE_OK after a cap when refinement reached tol_outer) */
   int64_t inner_iters_total;  /* sum over preconditioner applications and blocks */
   int64_t precond_applies;
   double relres_recursive;    /* ||r|| / ||b|| of the recursion at exit */

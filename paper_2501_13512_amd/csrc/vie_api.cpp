@@ -956,7 +956,9 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     g_last_error = fgmres ? "GMRES breakdown (last iterate written)" : "BiCGSTAB breakdown (last iterate written)";
     return VIE_EBREAKDOWN;
   }
-  if (rr.status == vie::ST_CONVERGED || rr.status == vie::ST_HALF) {
+  // mixed: the refinement may reach the tolerance after the main loop's cap
+  const bool refined_ok = o->precision == VIE_MIXED && refine > 0 && relres_true <= o->tol_outer;
+  if (rr.status == vie::ST_CONVERGED || rr.status == vie::ST_HALF || refined_ok) {
     if (o->precision == VIE_MIXED && relres_true > o->tol_outer) {
       g_last_error = "mixed-precision solve stopped above tol_outer after refinement";
       return VIE_NOT_CONVERGED;
