@@ -178,14 +178,23 @@ __global__ void kg_start(GmresDev d, int first, double tol, int maxit) {
   *d.status = st;
 }
 
-// y = H[:k, :k]^{-1} g[:k] (back substitution, k = columns of this cycle)
+// y = H[:k, :k]^{-1} g[:k] (back substitution, k = columns of this cycle).
+// A zero pivot (the flexible Arnoldi relation turned singular: a
+// preconditioned direction added nothing new) drops that direction and marks
+// the solve as broken down.
 __global__ void kg_solve_y(GmresDev d) {
   if (threadIdx.x != 0) return;
   const int k = d.st->k;
   for (int i = k - 1; i >= 0; --i) {
     c128 acc = d.g[i];
     for (int q = i + 1; q < k; ++q) acc = acc - hcol(d, i, q) * d.y[q];
-    d.y[i] = cdiv(acc, hcol(d, i, i));
+    const c128 piv = hcol(d, i, i);
+    if (piv.x == 0.0 && piv.y == 0.0) {
+      d.y[i] = mk<double>(0.0, 0.0);
+      *d.status = ST_BREAKDOWN;
+    } else {
+      d.y[i] = cdiv(acc, piv);
+    }
   }
 }
 
