@@ -279,19 +279,22 @@ vie_status vie_rcs(vie_problem* p, const void* pol_dev, int32_t n_dir, const dou
  * directions or polarisations on the same operator and partition).
  * e_inc_dev, e_tot_dev and pol_dev (optional): nrhs consecutive vectors of
  * 3*nx*ny*nz complex each (device, ordered on the stream); stats: NULL or
- * nrhs entries.  Without the preconditioner (plain BiCGSTAB) the nrhs
- * systems run as one batch: every product, vector update and finalize
- * launch covers all of them and each system stops on its own status, with
- * the same per-system arithmetic as a single solve (results equal those of
- * separate vie_solve_device calls; tested).  With the preconditioner, or
- * with VIE_SOLVER_FGMRES, the right-hand sides are solved one after another
- * (sharing the spectra, block plan and captured inner iteration).  The
- * batch's storage (8 vectors and one FFT work buffer per right-hand side) is
- * allocated by the first batched call and kept with the problem (counted in
- * footprint_bytes; VIE_EBUSY beyond the context's budget).  Returns the
- * first error, else VIE_NOT_CONVERGED if any system did not converge, else
- * VIE_OK; every system's result and statistics are written.  nrhs in
- * [1, 4096]. */
+ * nrhs entries.  BiCGSTAB runs the nrhs systems as one batch: every
+ * full-grid product, vector update and finalize launch covers all of them
+ * and each system stops on its own status, with the same per-system
+ * arithmetic as a single solve (plain solves: results equal those of
+ * separate vie_solve_device calls; tested).  With the preconditioner, each
+ * application solves the blocks of all right-hand sides together: the
+ * blocks of nrhs copies of the problem stacked along z, in the problem's own
+ * shape groups (a replica built by the first such call for that nrhs, kept
+ * with the problem); a system that has stopped contributes zero right-hand
+ * sides, which its blocks skip.  Its inner_iters_total and precond_applies
+ * are the batch's totals.  VIE_SOLVER_FGMRES solves the right-hand sides
+ * one after another.  Batch storage (12 vectors and one FFT work buffer per
+ * right-hand side, plus the replica) is counted in footprint_bytes
+ * (VIE_EBUSY beyond the context's budget).  Returns the first error, else
+ * VIE_NOT_CONVERGED if any system did not converge, else VIE_OK; every
+ * system's result and statistics are written.  nrhs in [1, 4096]. */
 vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, const vie_opts* opts,
                            void* e_tot_dev, void* pol_dev, vie_stats* stats, void* stream);
 

@@ -235,6 +235,11 @@ void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int nc
 void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s);
 // r = b - a (c128, n elements) ; partial-free helper for refinement
 void sub_vec(const c128* b, const c128* a, c128* r, int64_t n, hipStream_t s);
+// Batch layout [nrhs][3][nv] <-> stacked layout [3][nrhs][nv] (the same
+// vectors on a grid of nrhs copies stacked along z).  batch_to_stacked
+// writes zeros for systems whose status is not ACTIVE (status may be null).
+void batch_to_stacked(const c128* src, c128* dst, int nrhs, int64_t nv, const int* status, hipStream_t s);
+void stacked_to_batch(const c128* src, c128* dst, int nrhs, int64_t nv, hipStream_t s);
 // x += d
 void add_vec(c128* x, const c128* d, int64_t n, hipStream_t s);
 // ||v||^2 of one vector into *out (device double), deterministic; partials

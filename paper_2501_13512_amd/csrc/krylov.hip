@@ -346,6 +346,41 @@ void sub_vec(const c128* b, const c128* a, c128* r, int64_t n, hipStream_t s) {
   check_launch("sub");
 }
 
+// dst[(c nrhs + r) nv + i] = src[(3 r + c) nv + i], zero for stopped systems
+__global__ void kk_batch_to_stacked(const c128* src, c128* dst, int nrhs, int64_t nv, const int* status) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = 3 * (int64_t)nrhs * nv;
+  if (j >= total) return;
+  const int64_t c = j / ((int64_t)nrhs * nv);
+  const int64_t rem = j - c * nrhs * nv;
+  const int64_t r = rem / nv, i = rem - r * nv;
+  const bool live = status == nullptr || status[r] == ST_ACTIVE;
+  dst[j] = live ? src[(3 * r + c) * nv + i] : mk<double>(0.0, 0.0);
+}
+
+__global__ void kk_stacked_to_batch(const c128* src, c128* dst, int nrhs, int64_t nv) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // batch index
+  const int64_t total = 3 * (int64_t)nrhs * nv;
+  if (j >= total) return;
+  const int64_t r = j / (3 * nv);
+  const int64_t rem = j - r * 3 * nv;
+  const int64_t c = rem / nv, i = rem - c * nv;
+  dst[j] = src[(c * nrhs + r) * nv + i];
+}
+
+void batch_to_stacked(const c128* src, c128* dst, int nrhs, int64_t nv, const int* status, hipStream_t s) {
+  const int64_t total = 3 * (int64_t)nrhs * nv;
+  hipLaunchKernelGGL(kk_batch_to_stacked, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, nrhs, nv,
+                     status);
+  check_launch("batch to stacked");
+}
+
+void stacked_to_batch(const c128* src, c128* dst, int nrhs, int64_t nv, hipStream_t s) {
+  const int64_t total = 3 * (int64_t)nrhs * nv;
+  hipLaunchKernelGGL(kk_stacked_to_batch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, nrhs, nv);
+  check_launch("stacked to batch");
+}
+
 __global__ void kk_add(c128* x, const c128* d, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = x[i] + d[i];

@@ -240,6 +240,31 @@ struct Branches {
 
 }  // namespace
 
+// Host-side plan of a problem: 1/chi, block ids, the blocks' bounding boxes
+// and their shape groups.  Its device footprint is known before anything
+// is allocated (admission by memory), and build_problem() turns it into a
+// vie_problem with set-up work on a caller-chosen stream.
+struct GroupPlan {
+  int lx, ly, lz;
+  std::vector<int> blocks;
+  bool wg = false;
+  int bx = 1, by = 1, bz = 1;
+};
+
+struct ProblemPlan {
+  vie_grid g{};
+  int64_t nv = 0;
+  int lx = 0, ly = 0, lz = 0;
+  double k0 = 0;
+  std::vector<c128> chi;      // 1/chi, 0 on vacuum
+  bool has_blocks = false;
+  int n_blocks = 0;
+  std::vector<int32_t> bid;   // -1 on vacuum
+  std::vector<int> lo, hi;    // block bounding boxes [3 * n_blocks]
+  std::vector<int64_t> cnt;   // voxels per block
+  std::vector<GroupPlan> groups;   // batched groups first, then block-solver groups
+};
+
 struct vie_problem {
   vie_context* ctx = nullptr;
   vie_grid g{};
@@ -287,6 +312,12 @@ struct vie_problem {
   // right-hand side
   DevBuf mr_vecs, mr_work, mr_state, mr_status, mr_partials, mr_ntile, mr_count;
   int mr_cap = 0;
+  // host plan (kept for batches) and, for preconditioned batches, the blocks
+  // of nrhs copies of the problem stacked along z (inner solves only)
+  std::shared_ptr<const ProblemPlan> plan;
+  std::unique_ptr<vie_problem> replica;
+  int replica_nrhs = 0;
+  size_t replica_bytes = 0;
 
   ~vie_problem() {
     for (auto& gp : inner_graph)
@@ -969,8 +1000,10 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
   return VIE_NOT_CONVERGED;
 }
 
-// Vectors of a batch of right-hand sides: B, X, R, RHAT, P, V, S, T.
-constexpr int kBatchVecs = 8;
+// Vectors of a batch of right-hand sides: B, X, R, RHAT, P, V, S, T, Y, Z,
+// and two in the stacked layout (preconditioner input and output).
+constexpr int kBatchVecs = 12;
+enum BatchVec { BV_B = 0, BV_X, BV_R, BV_RHAT, BV_P, BV_V, BV_S, BV_T, BV_Y, BV_Z, BV_WI, BV_WO };
 
 void ensure_batch(vie_problem& P, int nrhs) {
   if (P.mr_cap >= nrhs) return;
@@ -1039,21 +1072,53 @@ KBatch batch_kbatch(vie_problem& P, int nrhs) {
   return k;
 }
 
-// Plain BiCGSTAB of nrhs systems in one batch (x0 = 0): every launch covers
-// all systems, each stops on its own status (same per-system arithmetic as a
-// single solve).  Rhs in batch vector B, iterates in X.
-template <typename R>
-void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag, hipStream_t s) {
+// BiCGSTAB of nrhs systems in one batch (x0 = 0): every launch covers all
+// systems, each stops on its own status (same per-system arithmetic as a
+// single solve).  Rhs in batch vector B, iterates in X.  With the
+// preconditioner, each application solves the blocks of all right-hand
+// sides together on the replica problem (R: outer products, RI: inner).
+template <typename R, typename RI = R>
+void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag, bool prec, double tol_in,
+                        int maxit_in, bool graphs, bool wg, hipStream_t s) {
   const KBatch k = batch_kbatch(P, nrhs);
   auto vec = [&](int kind) { return batch_vec(P, kind, nrhs); };
-  vie::k_init(k, vec(0), vec(1), vec(2), vec(3), nullptr, s);
+  vie::k_init(k, vec(BV_B), vec(BV_X), vec(BV_R), vec(BV_RHAT), nullptr, s);
   vie::k_finalize(k, vie::FIN_INIT, s, nullptr, tol, maxit);
-  const std::vector<MvmBatch<R>> mv{batch_mvm<R>(P, nrhs)};
+  const MvmBatch<R> m = batch_mvm<R>(P, nrhs);
+  const std::vector<MvmBatch<R>> mv{m};
   const std::vector<KBatch> kv{k};
-  const std::vector<StepVecs> vv{{vec(1), vec(2), vec(3), vec(4), vec(5), vec(6), vec(7)}};
+  const std::vector<StepVecs> vv{{vec(BV_X), vec(BV_R), vec(BV_RHAT), vec(BV_P), vec(BV_V), vec(BV_S), vec(BV_T)}};
+  // y = K2^{-1} w for every right-hand side: to the stacked layout (systems
+  // that no longer iterate give zero right-hand sides, which the inner
+  // solves skip), one application on the replica, back
+  auto apply = [&](const c128* w, c128* y) {
+    vie::batch_to_stacked(w, vec(BV_WI), nrhs, P.nv, P.mr_status.as<int>(), s);
+    precond_apply<RI>(*P.replica, vec(BV_WI), vec(BV_WO), tol_in, maxit_in, nullptr, lag, nullptr, 0, graphs, wg, s);
+    vie::stacked_to_batch(vec(BV_WO), y, nrhs, P.nv, s);
+  };
   Poller poll(P, s, 0);
   for (int it = 1; it <= maxit; ++it) {
-    fused_steps<R>(mv, kv, vv, k, Branches{}, s);
+    if (!prec) {
+      fused_steps<R>(mv, kv, vv, k, Branches{}, s);
+    } else {
+      vie::k_update_p(k, vec(BV_R), vec(BV_V), vec(BV_P), s);
+      apply(vec(BV_P), vec(BV_Y));
+      const vie::FuseArgs fa{0, 1, nullptr, nullptr, nullptr, vec(BV_RHAT), nullptr};
+      vie::mvm_pass1<R>(m, &k, fa, vec(BV_Y), false, s);
+      vie::mvm_mid<R>(m, s);
+      vie::mvm_pass5<R>(m, &k, fa, vec(BV_Y), vec(BV_V), s);
+      vie::k_finalize(k, vie::FIN_ALPHA, s);
+      vie::k_update_s(k, vec(BV_R), vec(BV_V), vec(BV_S), s);
+      vie::k_finalize(k, vie::FIN_S, s);
+      apply(vec(BV_S), vec(BV_Z));
+      const vie::FuseArgs fo{0, 2, nullptr, nullptr, nullptr, nullptr, vec(BV_S)};
+      vie::mvm_pass1<R>(m, &k, fo, vec(BV_Z), false, s);
+      vie::mvm_mid<R>(m, s);
+      vie::mvm_pass5<R>(m, &k, fo, vec(BV_Z), vec(BV_T), s);
+      vie::k_finalize(k, vie::FIN_OMEGA, s);
+      vie::k_update_xr(k, vec(BV_X), vec(BV_Y), vec(BV_Z), vec(BV_R), vec(BV_S), vec(BV_T), vec(BV_RHAT), s);
+      vie::k_finalize(k, vie::FIN_XR, s);
+    }
     vie::count_active(P.mr_status.as<int>(), nrhs, P.mr_count.as<int>(), s);
     const long t = poll.push(P.mr_count.as<int>());
     if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
@@ -1061,32 +1126,86 @@ void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag
   hip_check(hipStreamSynchronize(s), "batch solve");
 }
 
+// The plan of nrhs copies of a problem stacked along z, with block ids
+// offset per copy and the original shape groups (so every block is solved
+// with the same transform lengths and box as in the problem itself).
+ProblemPlan stacked_plan(const ProblemPlan& pl, int nrhs) {
+  ProblemPlan sp;
+  sp.g = pl.g;
+  sp.g.nz = pl.g.nz * nrhs;
+  sp.nv = pl.nv * nrhs;
+  sp.k0 = pl.k0;
+  sp.has_blocks = pl.has_blocks;
+  const int nb = pl.n_blocks;
+  sp.n_blocks = nb * nrhs;
+  sp.chi.reserve((size_t)sp.nv);
+  sp.bid.reserve((size_t)sp.nv);
+  for (int r = 0; r < nrhs; ++r) {
+    sp.chi.insert(sp.chi.end(), pl.chi.begin(), pl.chi.end());
+    for (int32_t b : pl.bid) sp.bid.push_back(b < 0 ? -1 : b + r * nb);
+    for (int k = 0; k < nb; ++k) {
+      for (int a = 0; a < 3; ++a) {
+        sp.lo.push_back(pl.lo[3 * k + a] + (a == 2 ? r * pl.g.nz : 0));
+        sp.hi.push_back(pl.hi[3 * k + a] + (a == 2 ? r * pl.g.nz : 0));
+      }
+    }
+    sp.cnt.insert(sp.cnt.end(), pl.cnt.begin(), pl.cnt.end());
+  }
+  for (const auto& gp : pl.groups) {
+    GroupPlan g2 = gp;
+    g2.blocks.clear();
+    for (int r = 0; r < nrhs; ++r)
+      for (int k : gp.blocks) g2.blocks.push_back(k + r * nb);
+    sp.groups.push_back(std::move(g2));
+  }
+  return sp;
+}
+
+std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& pl, hipStream_t s,
+                                           bool inner_only = false);
+
+// The replica problem for preconditioned batches of nrhs right-hand sides
+// (rebuilt when nrhs changes; counted in the problem's footprint).
+void ensure_replica(vie_problem& P, int nrhs, hipStream_t s) {
+  if (P.replica && P.replica_nrhs == nrhs) return;
+  if (!P.plan) fail(VIE_EINVAL, "this problem keeps no plan for batched preconditioned solves");
+  vie_context* ctx = P.ctx;
+  const size_t old = P.replica_bytes;
+  P.replica.reset();
+  P.replica_nrhs = 0;
+  P.replica_bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->used -= std::min(ctx->used, old);
+  }
+  P.footprint -= std::min(P.footprint, old);
+  const ProblemPlan sp = stacked_plan(*P.plan, nrhs);
+  size_t foot = 0;
+  for (const auto& gp : sp.groups) {
+    const size_t nsys = gp.blocks.size(), bnv = (size_t)gp.bx * gp.by * gp.bz;
+    foot += nsys * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
+            8 * nsys * 3 * bnv * sizeof(c128) + nsys * (sizeof(KState) + 2 * sizeof(int));
+  }
+  foot += (size_t)sp.nv * (sizeof(int32_t) + 4 * sizeof(int));   // block map
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->budget && ctx->used + ctx->reserved + foot > ctx->budget)
+      fail(VIE_EBUSY, "batch replica exceeds the context's HBM budget");
+    ctx->used += foot;
+  }
+  try {
+    P.replica = build_problem(ctx, sp, s, true);
+  } catch (...) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->used -= std::min(ctx->used, foot);
+    throw;
+  }
+  P.replica_nrhs = nrhs;
+  P.replica_bytes = foot;
+  P.footprint += foot;
+}
+
 // ------------------------------------------------------------------ problem set-up
-// Host-side plan of a problem: 1/chi, block ids, the blocks' bounding boxes
-// and their shape groups.  Its device footprint is known before anything
-// is allocated (admission by memory), and build_problem() turns it into a
-// vie_problem with set-up work on a caller-chosen stream.
-struct GroupPlan {
-  int lx, ly, lz;
-  std::vector<int> blocks;
-  bool wg = false;
-  int bx = 1, by = 1, bz = 1;
-};
-
-struct ProblemPlan {
-  vie_grid g{};
-  int64_t nv = 0;
-  int lx = 0, ly = 0, lz = 0;
-  double k0 = 0;
-  std::vector<c128> chi;      // 1/chi, 0 on vacuum
-  bool has_blocks = false;
-  int n_blocks = 0;
-  std::vector<int32_t> bid;   // -1 on vacuum
-  std::vector<int> lo, hi;    // block bounding boxes [3 * n_blocks]
-  std::vector<int64_t> cnt;   // voxels per block
-  std::vector<GroupPlan> groups;   // batched groups first, then block-solver groups
-};
-
 ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* block_id, int32_t n_blocks) {
   if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > 256 || g.ny > 256 || g.nz > 256)
     fail(VIE_EINVAL, "grid sizes must be in [1, 256]");
@@ -1290,7 +1409,11 @@ int cached_zvariant(vie_context* ctx, const MvmBatch<R>& b, hipStream_t s, float
   return it->second.first;
 }
 
-std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& pl, hipStream_t s) {
+// inner_only: the blocks and their inner solves only (no full-grid operator:
+// no outer spectra, work buffer or Krylov vectors); used for the stacked
+// replica of preconditioned batches.
+std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& pl, hipStream_t s,
+                                           bool inner_only) {
   const vie_grid& g = pl.g;
   const int64_t nv = pl.nv;
   auto P = std::make_unique<vie_problem>();
@@ -1301,15 +1424,17 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
   P->ly = pl.ly;
   P->lz = pl.lz;
   P->k0 = pl.k0;
-  P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0, s);
-  upload(P->chi, pl.chi, s);
-  P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
-  P->work.zero(s);
-  P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
-  P->vecs.zero(s);
-  for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
-  P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
-  P->partials.alloc(P->pstride * sizeof(double));
+  if (!inner_only) {
+    P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0, s);
+    upload(P->chi, pl.chi, s);
+    P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
+    P->work.zero(s);
+    P->vecs.alloc(V_COUNT * 3 * (size_t)nv * sizeof(c128));
+    P->vecs.zero(s);
+    for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
+    P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
+    P->partials.alloc(P->pstride * sizeof(double));
+  }
   P->ntile.alloc(sizeof(int));
   P->ntile.zero(s);
   P->ostate.alloc(sizeof(KState));
@@ -1434,8 +1559,10 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     m.ny = g.ny;
     m.nz = g.nz;
   }
-  P->zvar[0] = cached_zvariant<double>(ctx, outer_batch<double>(*P, false), s, P->ztune_ms[0]);
-  P->zvar[1] = cached_zvariant<float>(ctx, outer_batch<float>(*P, false), s, P->ztune_ms[1]);
+  if (!inner_only) {
+    P->zvar[0] = cached_zvariant<double>(ctx, outer_batch<double>(*P, false), s, P->ztune_ms[0]);
+    P->zvar[1] = cached_zvariant<float>(ctx, outer_batch<float>(*P, false), s, P->ztune_ms[1]);
+  }
   hip_check(hipStreamSynchronize(s), "problem set-up");
   return P;
 }
@@ -1651,6 +1778,7 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
     try {
       auto P = build_problem(ctx, plan, ctx->stream);
       P->footprint = foot;
+      P->plan = std::make_shared<const ProblemPlan>(std::move(plan));
       *out = P.release();
     } catch (...) {
       std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1982,7 +2110,10 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
     auto keep = [&](vie_status st) {
       if (worst >= 0 && (st < 0 || st > worst)) worst = st;
     };
-    const bool batched = nrhs > 1 && !opts->precondition && opts->solver == VIE_SOLVER_BICGSTAB;
+    const bool batched = nrhs > 1 && opts->solver == VIE_SOLVER_BICGSTAB;
+    const bool prec = opts->precondition != 0;
+    const bool graphs = (opts->flags & VIE_FLAG_NO_GRAPHS) == 0;
+    const bool wgk = (opts->flags & VIE_FLAG_NO_BLOCK_KERNEL) == 0;
     if (!batched) {
       for (int r = 0; r < nrhs; ++r)
         keep(solve_impl(p, ein + r * n, opts, eout + r * n, pol ? pol + r * n : nullptr, stats ? &stats[r] : nullptr,
@@ -1990,12 +2121,24 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
       return worst;
     }
     ensure_batch(P, nrhs);
+    if (prec) {
+      ensure_replica(P, nrhs, s);
+      hip_check(hipMemsetAsync(P.replica->d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
+    }
     for (int r = 0; r < nrhs; ++r)
-      vie::masked_copy(ein + r * n, P.chi.as<c128>(), batch_vec(P, 0, nrhs) + r * n, P.nv, s);
+      vie::masked_copy(ein + r * n, P.chi.as<c128>(), batch_vec(P, BV_B, nrhs) + r * n, P.nv, s);
+    const double ti = opts->tol_inner;
+    const int mi = opts->maxit_inner, lag = opts->poll_lag;
     if (opts->precision == VIE_MIXED)
-      run_bicgstab_batch<float>(P, nrhs, opts->tol_outer, opts->maxit_outer, opts->poll_lag, s);
+      run_bicgstab_batch<float, float>(P, nrhs, opts->tol_outer, opts->maxit_outer, lag, prec, ti, mi, graphs, wgk, s);
+    else if (opts->precision == VIE_MIXED_INNER)
+      run_bicgstab_batch<double, float>(P, nrhs, opts->tol_outer, opts->maxit_outer, lag, prec, ti, mi, graphs, wgk,
+                                        s);
     else
-      run_bicgstab_batch<double>(P, nrhs, opts->tol_outer, opts->maxit_outer, opts->poll_lag, s);
+      run_bicgstab_batch<double, double>(P, nrhs, opts->tol_outer, opts->maxit_outer, lag, prec, ti, mi, graphs,
+                                         wgk, s);
+    int64_t acc[3] = {0, 0, 0};
+    if (prec) hip_check(hipMemcpy(acc, P.replica->d_acc.p, sizeof(acc), hipMemcpyDeviceToHost), "acc");
     std::vector<KState> st(nrhs);
     std::vector<int> status(nrhs);
     hip_check(hipMemcpy(st.data(), P.mr_state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost), "batch state");
@@ -2003,16 +2146,20 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
     const double batch_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     // per system: true residual, refinement (mixed), fields, statistics
     for (int r = 0; r < nrhs; ++r) {
-      hip_check(hipMemcpyAsync(P.vec[V_B], batch_vec(P, 0, nrhs) + r * n, n * sizeof(c128), hipMemcpyDeviceToDevice,
-                               s),
+      hip_check(hipMemcpyAsync(P.vec[V_B], batch_vec(P, BV_B, nrhs) + r * n, n * sizeof(c128),
+                               hipMemcpyDeviceToDevice, s),
                 "batch rhs");
-      hip_check(hipMemcpyAsync(P.vec[V_X], batch_vec(P, 1, nrhs) + r * n, n * sizeof(c128), hipMemcpyDeviceToDevice,
-                               s),
+      hip_check(hipMemcpyAsync(P.vec[V_X], batch_vec(P, BV_X, nrhs) + r * n, n * sizeof(c128),
+                               hipMemcpyDeviceToDevice, s),
                 "batch iterate");
       const RunResult rr{st[r], status[r]};
       keep(solve_impl(p, nullptr, opts, eout + r * n, pol ? pol + r * n : nullptr, stats ? &stats[r] : nullptr, s,
                       &rr));
-      if (stats) stats[r].seconds += batch_s;
+      if (stats) {
+        stats[r].seconds += batch_s;
+        stats[r].inner_iters_total += acc[0];   // the batch's totals (all right-hand sides)
+        stats[r].precond_applies += acc[1];
+      }
     }
     return worst;
   });

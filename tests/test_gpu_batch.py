@@ -6,8 +6,9 @@
   (where the per-system refinement follows the batch).
 * Oblique and differently polarised incidence (general incidence) against
   the oracle's dense LU solution at tol 1e-12.
-* With the preconditioner the right-hand sides are solved in turn: again
-  equal to separate solves.
+* With the preconditioner the blocks of all right-hand sides are solved
+  together: step counts and fields as separate solves (to rounding), and the
+  mixed mode against dense LU.
 * Errors: nrhs out of range; the batch storage is counted in the footprint.
 """
 import numpy as np
@@ -89,17 +90,49 @@ def test_batch_general_incidence_vs_dense_lu(vie_ctx):
         P.close()
 
 
-def test_batch_preconditioned_solves_in_turn(vie_ctx):
+@pytest.mark.parametrize("flags", [0, V.VIE_FLAG_NO_BLOCK_KERNEL])
+def test_batch_preconditioned_matches_separate_solves(vie_ctx, flags):
+    """Preconditioned batch: the blocks of all right-hand sides are solved
+    together (stacked replica).  At the case tolerance the step counts match
+    separate solves (+-2) and the fields agree to the tolerance's rounding
+    sensitivity; at 1e-12 the fields agree to 1e-10."""
     case = W.cube16()
     P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
     try:
-        e = _incident(P.grid, WAVES[:2])
-        opts = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner)
+        e = _incident(P.grid, WAVES)
+        opts = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, flags=flags)
         want, iters = _separate(P, e, opts)
         code, got, _, stats = _batch(P, e, opts)
         assert code == V.VIE_OK
-        assert [s.outer_iters for s in stats] == iters
-        assert np.array_equal(got, want)
+        for s, it in zip(stats, iters):
+            assert abs(s.outer_iters - it) <= 2, ([s.outer_iters for s in stats], iters)
+            assert s.relres_true <= 1.01 * case.tol_outer
+        assert stats[0].precond_applies >= 2 * max(s.outer_iters for s in stats)
+        for r in range(len(WAVES)):
+            assert np.linalg.norm(got[r] - want[r]) <= 1e-5 * np.linalg.norm(want[r])
+        tight = V.make_opts(tol_outer=1e-12, tol_inner=1e-3, maxit_outer=2000, flags=flags)
+        want, _ = _separate(P, e, tight)
+        code, got, _, _ = _batch(P, e, tight)
+        assert code == V.VIE_OK
+        for r in range(len(WAVES)):
+            assert np.linalg.norm(got[r] - want[r]) <= 1e-10 * np.linalg.norm(want[r])
+    finally:
+        P.close()
+
+
+def test_batch_preconditioned_mixed_vs_oracle(vie_ctx):
+    case = W.mixed_partition()
+    g = op.Grid.from_case(case)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        e = _incident(P.grid, WAVES[:2])
+        opts = V.make_opts(tol_outer=1e-10, tol_inner=1e-3, precision=V.VIE_MIXED, maxit_outer=2000)
+        code, _, pol, stats = _batch(P, e, opts)
+        assert code == V.VIE_OK
+        for r, (kdir, pvec) in enumerate(WAVES[:2]):
+            ref = krylov.solve_dense(g, physics.plane_wave(g, kdir, pvec))
+            assert np.linalg.norm(pol[r] - ref) <= 1e-8 * np.linalg.norm(ref), r
+            assert stats[r].relres_true <= 1e-10
     finally:
         P.close()
 
