@@ -153,3 +153,29 @@ def test_batch_errors_and_footprint(vie_ctx):
         assert P.info().footprint_bytes - before >= 8 * 2 * n * 16
     finally:
         P.close()
+
+
+def test_batch_sizes_change_and_fgmres_in_turn(vie_ctx):
+    """The batch storage grows and the replica is rebuilt when nrhs changes
+    (2 -> 3 -> 2); FGMRES batches run the right-hand sides in turn and equal
+    separate solves exactly."""
+    case = W.mixed_partition()
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        opts = V.make_opts(tol_outer=1e-10, tol_inner=1e-3, maxit_outer=2000)
+        for n in (2, 3, 2):
+            e = _incident(P.grid, WAVES[:n])
+            want, _ = _separate(P, e, opts)
+            code, got, _, _ = _batch(P, e, opts)
+            assert code == V.VIE_OK
+            for r in range(n):
+                assert np.linalg.norm(got[r] - want[r]) <= 1e-8 * np.linalg.norm(want[r]), (n, r)
+        fg = V.make_opts(tol_outer=1e-8, tol_inner=1e-3, solver=V.VIE_SOLVER_FGMRES, restart=20)
+        e = _incident(P.grid, WAVES[:2])
+        want, iters = _separate(P, e, fg)
+        code, got, _, stats = _batch(P, e, fg)
+        assert code == V.VIE_OK
+        assert [s.outer_iters for s in stats] == iters
+        assert np.array_equal(got, want)
+    finally:
+        P.close()
