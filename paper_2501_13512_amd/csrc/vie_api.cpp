@@ -1819,22 +1819,29 @@ vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t vari
     std::lock_guard<std::mutex> lk(p->mu);
     const int q = precision == VIE_MIXED ? 1 : 0;
     hipStream_t s = p->ctx->stream;
-    if (variant >= 0) {
-      p->zvar[q] = variant;
-      for (auto& G : p->groups) G.zvar[q] = variant;
-    } else if (q == 0) {
-      p->zvar[0] = cached_zvariant<double>(p->ctx, outer_batch<double>(*p, false), s, nullptr);
-      for (auto& G : p->groups) G.zvar[0] = cached_zvariant<double>(p->ctx, group_batch<double>(*p, G, false), s, nullptr);
-    } else {
-      p->zvar[1] = cached_zvariant<float>(p->ctx, outer_batch<float>(*p, false), s, nullptr);
-      for (auto& G : p->groups) G.zvar[1] = cached_zvariant<float>(p->ctx, group_batch<float>(*p, G, false), s, nullptr);
-    }
-    // captured inner iterations hold the old kernels
-    for (auto& g : p->inner_graph[q])
-      if (g) {
-        (void)hipGraphExecDestroy(g);
-        g = nullptr;
+    // the problem, and the replica of its blocks used by preconditioned batches
+    for (vie_problem* x : {p, p->replica.get()}) {
+      if (!x) continue;
+      const bool outer = x->spec != nullptr;
+      if (variant >= 0) {
+        x->zvar[q] = variant;
+        for (auto& G : x->groups) G.zvar[q] = variant;
+      } else if (q == 0) {
+        if (outer) x->zvar[0] = cached_zvariant<double>(x->ctx, outer_batch<double>(*x, false), s, nullptr);
+        for (auto& G : x->groups)
+          G.zvar[0] = cached_zvariant<double>(x->ctx, group_batch<double>(*x, G, false), s, nullptr);
+      } else {
+        if (outer) x->zvar[1] = cached_zvariant<float>(x->ctx, outer_batch<float>(*x, false), s, nullptr);
+        for (auto& G : x->groups)
+          G.zvar[1] = cached_zvariant<float>(x->ctx, group_batch<float>(*x, G, false), s, nullptr);
       }
+      // captured inner iterations hold the old kernels
+      for (auto& g : x->inner_graph[q])
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+    }
     return VIE_OK;
   });
 }
