@@ -28,6 +28,7 @@ from typing import Callable, List, Optional
 
 import numpy as np
 import scipy.linalg
+import scipy.ndimage
 
 from .operator import FFTOperator, Grid, dense_matrix, from_support, to_support
 
@@ -207,9 +208,20 @@ def fgmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: floa
 @dataclasses.dataclass
 class _Block:
     index: int
-    sl: tuple                  # slices (z, y, x) of the bounding box
-    member: np.ndarray         # bool [bz, by, bx]
+    sl: tuple                  # slices (z, y, x) of the bounding box of the solve set
+    member: np.ndarray         # bool [bz, by, bx]: the voxels solved for
     op: FFTOperator
+    own: np.ndarray            # bool [bz, by, bx]: the block's own voxels (kept)
+
+
+def expanded_block(grid: Grid, block_id: np.ndarray, k: int, overlap: int) -> np.ndarray:
+    """Scatterer voxels within ``overlap`` voxels of block k in every axis
+    (the block dilated by a (2 overlap + 1)^3 cube, restricted to S)."""
+    own = block_id == k
+    if overlap <= 0:
+        return own
+    grown = scipy.ndimage.binary_dilation(own, structure=np.ones((3, 3, 3), dtype=bool), iterations=overlap)
+    return grown & grid.mask
 
 
 class BlockPreconditioner:
@@ -218,25 +230,33 @@ class BlockPreconditioner:
     Block k is the set of voxels with ``block_id == k``.  Its matrix A_k is
     A restricted to those voxels, applied with the FFT product on the block's
     bounding box with every other voxel masked as vacuum.
+
+    ``overlap`` > 0 expands every block (the paper names expanded blocks as
+    future work): block k is solved on E_k, its voxels dilated by ``overlap``
+    voxels in every axis within the scatterer, and only its own voxels are
+    kept (restricted additive Schwarz: y|B_k = (A_{E_k}^{-1} w|E_k)|B_k).
+    With overlap 0 this is the block-diagonal preconditioner above.
     """
 
     def __init__(self, grid: Grid, block_id: np.ndarray, n_blocks: int, tol: float, maxit: int, pad: int = 0,
-                 product: str = "fp64"):
+                 product: str = "fp64", overlap: int = 0):
         self.tol = tol
         self.maxit = maxit
         self.blocks: List[_Block] = []
         self.inner_counts: List[List[int]] = []
         for k in range(n_blocks):
-            kk, jj, ii = np.nonzero(block_id == k)
-            if ii.size == 0:
+            if not np.any(block_id == k):
                 continue
+            solve_set = expanded_block(grid, block_id, k, overlap)
+            kk, jj, ii = np.nonzero(solve_set)
             sl = (slice(kk.min(), kk.max() + 1), slice(jj.min(), jj.max() + 1),
                   slice(ii.min(), ii.max() + 1))
-            member = block_id[sl] == k
+            member = solve_set[sl]
+            own = block_id[sl] == k
             sub_eps = np.where(member, grid.eps[sl], 1.0 + 0.0j)
             sub = Grid(sub_eps.shape[2], sub_eps.shape[1], sub_eps.shape[0],
                        grid.dx, grid.dy, grid.dz, grid.wavelength, sub_eps)
-            self.blocks.append(_Block(k, sl, member, FFTOperator(sub, pad, product)))
+            self.blocks.append(_Block(k, sl, member, FFTOperator(sub, pad, product), own))
 
     def __call__(self, w: np.ndarray) -> np.ndarray:
         y = np.zeros_like(w)
@@ -247,7 +267,7 @@ class BlockPreconditioner:
                 counts.append(0)
                 continue
             yk, info = bicgstab(blk.op, bk, self.tol, self.maxit)
-            y[(slice(None),) + blk.sl] += yk * blk.member
+            y[(slice(None),) + blk.sl] += yk * blk.own
             counts.append(info.iterations)
         self.inner_counts.append(counts)
         return y
@@ -272,7 +292,7 @@ def total_field(grid: Grid, P: np.ndarray) -> np.ndarray:
 def solve(grid: Grid, e_inc: np.ndarray, tol_outer: float, maxit_outer: int = 1000,
           block_id: Optional[np.ndarray] = None, n_blocks: int = 0,
           tol_inner: float = 1e-2, maxit_inner: int = 500, pad: int = 0, product: str = "fp64",
-          method: str = "bicgstab", restart: int = 30) -> Solution:
+          method: str = "bicgstab", restart: int = 30, overlap: int = 0) -> Solution:
     """Solve A P = E_inc on S; block preconditioner if ``block_id`` is given.
 
     ``pad`` lengthens every circulant embedding (same operator, different
@@ -286,7 +306,7 @@ def solve(grid: Grid, e_inc: np.ndarray, tol_outer: float, maxit_outer: int = 10
     b = masked_rhs(grid, e_inc)
     pre = None
     if block_id is not None:
-        pre = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner, pad, product)
+        pre = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner, pad, product, overlap)
     if method == "fgmres":
         P, info = fgmres(A, b, tol_outer, maxit_outer, restart, pre)
     else:

@@ -220,3 +220,61 @@ def test_fgmres_block_preconditioned_cube16_uses_fewer_applications():
     assert len(f.inner_counts) == f.info.iterations
     assert len(f.inner_counts) < len(a.inner_counts)
     assert np.linalg.norm(f.E_tot - a.E_tot) <= 1e-4 * np.linalg.norm(a.E_tot)
+
+
+# ---- expanded (overlapping) blocks: restricted additive Schwarz
+def _dense_ras(g, block_id, n_blocks, overlap, w):
+    """y|B_k = (A_{E_k}^{-1} w|E_k)|B_k by dense LU of A restricted to E_k,
+    with E_k found by brute force (Chebyshev distance to block k <= overlap,
+    inside the scatterer)."""
+    Z, idx = op.dense_matrix(g)
+    i, j, k = idx
+    n = i.size
+    ws = op.to_support(g, w, idx)
+    bid = block_id[k, j, i]
+    y = np.zeros(3 * n, complex)
+    for b in range(n_blocks):
+        own = np.nonzero(bid == b)[0]
+        if own.size == 0:
+            continue
+        d = np.max(np.abs(np.stack([i[:, None] - i[own][None, :], j[:, None] - j[own][None, :],
+                                    k[:, None] - k[own][None, :]])), axis=0).min(axis=1)
+        sset = np.nonzero(d <= overlap)[0]
+        rows = np.concatenate([sset + c * n for c in range(3)])
+        sol = np.linalg.solve(Z[np.ix_(rows, rows)], ws[rows])
+        pos = {int(v): q for q, v in enumerate(sset)}
+        for c in range(3):
+            for v in own:
+                y[c * n + v] = sol[c * sset.size + pos[int(v)]]
+    return op.from_support(g, y, idx)
+
+
+@pytest.mark.parametrize("overlap", [1, 2])
+def test_expanded_blocks_match_dense_restricted_solves(overlap):
+    case, g, e = _problem(56, (4, 5, 6), n_blocks=3)
+    rng = np.random.default_rng(1)
+    w = (rng.standard_normal((3,) + case.shape) + 1j * rng.standard_normal((3,) + case.shape)) * g.mask
+    pre = krylov.BlockPreconditioner(g, case.block_id, case.n_blocks, 1e-14, 2000, overlap=overlap)
+    y = pre(w)
+    want = _dense_ras(g, case.block_id, case.n_blocks, overlap, w)
+    assert np.linalg.norm(y - want) <= 1e-10 * np.linalg.norm(want)
+    assert np.all(y[:, ~g.mask] == 0)
+
+
+def test_overlap_zero_is_the_block_diagonal_preconditioner():
+    case, g, e = _problem(57, (4, 4, 5), n_blocks=3)
+    rng = np.random.default_rng(2)
+    w = (rng.standard_normal((3,) + case.shape) + 1j * rng.standard_normal((3,) + case.shape)) * g.mask
+    a = krylov.BlockPreconditioner(g, case.block_id, case.n_blocks, 1e-12, 500)(w)
+    want = _dense_ras(g, case.block_id, case.n_blocks, 0, w)
+    assert np.linalg.norm(a - want) <= 1e-9 * np.linalg.norm(want)
+
+
+def test_overlap_covering_the_scatterer_is_exact():
+    """Every expanded block covers the whole scatterer: K2 = A, one outer
+    step (the half-step test) gives the dense solution."""
+    case, g, e = _problem(58, (3, 4, 4), n_blocks=2)
+    s = krylov.solve(g, e, 1e-10, 10, case.block_id, case.n_blocks, 1e-14, 2000, overlap=4)
+    assert s.info.iterations == 1
+    ref = krylov.solve_dense(g, e)
+    assert np.linalg.norm(s.P - ref) <= 1e-10 * np.linalg.norm(ref)
