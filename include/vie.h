@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 8
+#define VIE_ABI_VERSION 9
 
 typedef enum {
   VIE_OK = 0,
@@ -193,6 +193,16 @@ vie_status vie_context_destroy(vie_context* ctx);
  * VIE_EINVAL on bad sizes, non-finite values or ids out of range. */
 vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
                               int32_t n_blocks, vie_problem** out);
+
+/* As vie_problem_create, with expanded blocks (the paper's future work,
+ * Sec. IV): block k is solved on its voxels dilated by `overlap` voxels in
+ * every axis (a (2 overlap + 1)^3 cube) within the scatterer, and only its
+ * own voxels are kept from that solve (restricted additive Schwarz).  The
+ * block partition still decides ownership.  overlap in [0, 256]; 0 is
+ * vie_problem_create; ignored without block ids.  Larger solve sets mean
+ * larger FFT boxes per block. */
+vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, const double* eps_r,
+                                      const int32_t* block_id, int32_t n_blocks, int32_t overlap, vie_problem** out);
 vie_status vie_problem_destroy(vie_problem* p);
 vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info);
 

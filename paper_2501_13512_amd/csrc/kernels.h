@@ -265,5 +265,9 @@ struct BlockMap {
 void block_gather(const BlockMap& m, const c128* w, c128* const* gdst, hipStream_t s);
 // y[c][v] = gsrc_k[c][local(v)] for scatterer voxels, 0 for vacuum
 void block_scatter(const BlockMap& m, c128* const* gsrc, c128* y, hipStream_t s);
+// Expanded (overlapping) blocks: system q of a group gathers w at every voxel
+// of its solve set, marked by chi_q != 0 on its box (origin[q], box bx by bz).
+void gather_sets(const c128* w, int nx, int ny, int nz, int bx, int by, int bz, int nsys, const int4* origin,
+                 const c128* chi, c128* gdst, hipStream_t s);
 
 }  // namespace vie

@@ -469,6 +469,34 @@ __global__ void kk_scatter(BlockMap m, c128* const* gsrc, c128* y) {
   for (int c = 0; c < 3; ++c) y[c * nv + v] = src[c * bnv];
 }
 
+__global__ void kk_gather_sets(const c128* w, int nx, int ny, int nz, int bx, int by, int bz, int nsys,
+                               const int4* origin, const c128* chi, c128* gdst) {
+  const int64_t bnv = (int64_t)bx * by * bz;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= (int64_t)nsys * bnv) return;
+  const c128 ci = chi[j];
+  if (ci.x == 0.0 && ci.y == 0.0) return;   // not in the set (stays zero)
+  const int64_t q = j / bnv, pos = j - q * bnv;
+  const int x = (int)(pos % bx), y = (int)((pos / bx) % by), z = (int)(pos / ((int64_t)bx * by));
+  const int4 o = origin[q];
+  const int X = o.x + x, Y = o.y + y, Z = o.z + z;
+  if (X >= nx || Y >= ny || Z >= nz) return;
+  const int64_t nv = (int64_t)nx * ny * nz;
+  const int64_t v = ((int64_t)Z * ny + Y) * nx + X;
+  c128* dst = gdst + q * 3 * bnv + pos;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dst[c * bnv] = w[c * nv + v];
+}
+
+void gather_sets(const c128* w, int nx, int ny, int nz, int bx, int by, int bz, int nsys, const int4* origin,
+                 const c128* chi, c128* gdst, hipStream_t s) {
+  const int64_t total = (int64_t)nsys * bx * by * bz;
+  if (total == 0) return;
+  hipLaunchKernelGGL(kk_gather_sets, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, nx, ny, nz, bx, by,
+                     bz, nsys, origin, chi, gdst);
+  check_launch("gather sets");
+}
+
 void block_scatter(const BlockMap& m, c128* const* gsrc, c128* y, hipStream_t s) {
   const int64_t nv = (int64_t)m.nx * m.ny * m.nz;
   hipLaunchKernelGGL(kk_scatter, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, m, gsrc, y);

@@ -223,6 +223,7 @@ struct Group {
   int64_t bnv, n;
   std::shared_ptr<Spectra> spec;
   DevBuf chi, work, vecs;
+  DevBuf sys_origin;     // expanded blocks: box origin of each system (int4)
   int zvar[2] = {0, 0};  // tuned z-pass variant per precision ([0] FP64, [1] FP32)
   c128* vec[8];  // B, X, R, RHAT, P, V, S, T
   int slot0;     // first entry in the problem's inner status/state arrays
@@ -260,8 +261,13 @@ struct ProblemPlan {
   bool has_blocks = false;
   int n_blocks = 0;
   std::vector<int32_t> bid;   // -1 on vacuum
-  std::vector<int> lo, hi;    // block bounding boxes [3 * n_blocks]
+  std::vector<int> lo, hi;    // bounding boxes of the solve sets [3 * n_blocks]
   std::vector<int64_t> cnt;   // voxels per block
+  // expanded blocks (overlap > 0): block k is solved on its voxels dilated by
+  // `overlap` in every axis within the scatterer; emask[k] marks that set on
+  // the box lo..hi (x fastest)
+  int overlap = 0;
+  std::vector<std::vector<uint8_t>> emask;
   std::vector<GroupPlan> groups;   // batched groups first, then block-solver groups
 };
 
@@ -315,6 +321,7 @@ struct vie_problem {
   // host plan (kept for batches) and, for preconditioned batches, the blocks
   // of nrhs copies of the problem stacked along z (inner solves only)
   std::shared_ptr<const ProblemPlan> plan;
+  int overlap = 0;   // expanded blocks: gather the dilated sets, scatter the own voxels
   std::unique_ptr<vie_problem> replica;
   int replica_nrhs = 0;
   size_t replica_bytes = 0;
@@ -635,7 +642,13 @@ vie::BlockSolveArgs wg_args(vie_problem& P, Group& G, const int* gate, double to
 template <typename R>
 void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit, const int* gate, int lag,
                    int32_t* hist, int64_t hist_cap, bool graphs, bool wg, hipStream_t s) {
-  vie::block_gather(P.bmap, w, gptr(P, V_B), s);
+  if (P.overlap == 0) {
+    vie::block_gather(P.bmap, w, gptr(P, V_B), s);
+  } else {   // expanded blocks overlap: each system gathers its own set
+    for (auto& G : P.groups)
+      vie::gather_sets(w, P.g.nx, P.g.ny, P.g.nz, G.bx, G.by, G.bz, G.nsys, G.sys_origin.as<int4>(),
+                       G.chi.as<c128>(), G.vec[V_B], s);
+  }
   const bool any_wg = wg && P.n_wg_groups > 0;
   if (any_wg) {
     hip_check(hipEventRecord(P.wg_events[0], s), "fork");
@@ -1136,6 +1149,7 @@ ProblemPlan stacked_plan(const ProblemPlan& pl, int nrhs) {
   sp.nv = pl.nv * nrhs;
   sp.k0 = pl.k0;
   sp.has_blocks = pl.has_blocks;
+  sp.overlap = pl.overlap;
   const int nb = pl.n_blocks;
   sp.n_blocks = nb * nrhs;
   sp.chi.reserve((size_t)sp.nv);
@@ -1150,6 +1164,7 @@ ProblemPlan stacked_plan(const ProblemPlan& pl, int nrhs) {
       }
     }
     sp.cnt.insert(sp.cnt.end(), pl.cnt.begin(), pl.cnt.end());
+    if (pl.overlap > 0) sp.emask.insert(sp.emask.end(), pl.emask.begin(), pl.emask.end());
   }
   for (const auto& gp : pl.groups) {
     GroupPlan g2 = gp;
@@ -1206,7 +1221,76 @@ void ensure_replica(vie_problem& P, int nrhs, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ problem set-up
-ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* block_id, int32_t n_blocks) {
+// Expanded blocks: the set of block k grows by `m` voxels in every axis (a
+// (2m+1)^3 cube dilation, separable into three 1-D running maxima) and is
+// cut to the scatterer; lo/hi become the set's tight bounding box.
+void expand_blocks(ProblemPlan& pl, int m) {
+  const vie_grid& g = pl.g;
+  const int n_blocks = pl.n_blocks;
+  pl.overlap = m;
+  pl.emask.assign(n_blocks, {});
+  for (int k = 0; k < n_blocks; ++k) {
+    if (pl.cnt[k] == 0) continue;
+    int b0[3], ext[3];
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+      b0[a] = std::max(0, pl.lo[3 * k + a] - m);
+      ext[a] = std::min(dims[a] - 1, pl.hi[3 * k + a] + m) - b0[a] + 1;
+    }
+    const int64_t bn = (int64_t)ext[0] * ext[1] * ext[2];
+    auto at = [&](int x, int y, int z) { return ((int64_t)z * ext[1] + y) * ext[0] + x; };
+    std::vector<uint8_t> cur(bn, 0), nxt(bn, 0);
+    for (int z = 0; z < ext[2]; ++z)
+      for (int y = 0; y < ext[1]; ++y)
+        for (int x = 0; x < ext[0]; ++x) {
+          const int64_t v = ((int64_t)(b0[2] + z) * g.ny + (b0[1] + y)) * g.nx + (b0[0] + x);
+          cur[at(x, y, z)] = pl.bid[v] == k;
+        }
+    for (int a = 0; a < 3; ++a) {   // running max of radius m along axis a
+      for (int z = 0; z < ext[2]; ++z)
+        for (int y = 0; y < ext[1]; ++y)
+          for (int x = 0; x < ext[0]; ++x) {
+            const int c[3] = {x, y, z};
+            uint8_t v = 0;
+            for (int d = -m; d <= m && !v; ++d) {
+              int q[3] = {x, y, z};
+              q[a] = c[a] + d;
+              if (q[a] < 0 || q[a] >= ext[a]) continue;
+              v = cur[at(q[0], q[1], q[2])];
+            }
+            nxt[at(x, y, z)] = v;
+          }
+      std::swap(cur, nxt);
+    }
+    int lo[3] = {ext[0], ext[1], ext[2]}, hi[3] = {-1, -1, -1};
+    for (int z = 0; z < ext[2]; ++z)
+      for (int y = 0; y < ext[1]; ++y)
+        for (int x = 0; x < ext[0]; ++x) {
+          const int64_t v = ((int64_t)(b0[2] + z) * g.ny + (b0[1] + y)) * g.nx + (b0[0] + x);
+          uint8_t& e = cur[at(x, y, z)];
+          e = e && (pl.chi[v].x != 0.0 || pl.chi[v].y != 0.0);
+          if (!e) continue;
+          const int c[3] = {x, y, z};
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], c[a]);
+            hi[a] = std::max(hi[a], c[a]);
+          }
+        }
+    std::vector<uint8_t>& em = pl.emask[k];
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    em.assign((size_t)ex * ey * ez, 0);
+    for (int z = 0; z < ez; ++z)
+      for (int y = 0; y < ey; ++y)
+        for (int x = 0; x < ex; ++x) em[((size_t)z * ey + y) * ex + x] = cur[at(lo[0] + x, lo[1] + y, lo[2] + z)];
+    for (int a = 0; a < 3; ++a) {
+      pl.lo[3 * k + a] = b0[a] + lo[a];
+      pl.hi[3 * k + a] = b0[a] + hi[a];
+    }
+  }
+}
+
+ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* block_id, int32_t n_blocks,
+                      int overlap = 0) {
   if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > 256 || g.ny > 256 || g.nz > 256)
     fail(VIE_EINVAL, "grid sizes must be in [1, 256]");
   if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !(g.wavelength > 0) || !is_finite(g.dx) || !is_finite(g.dy) ||
@@ -1265,6 +1349,7 @@ ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* blo
           hi[3 * k + a] = std::max(hi[3 * k + a], c[a]);
         }
       }
+  if (overlap > 0) expand_blocks(pl, overlap);
   // group blocks by circulant lengths of their bounding boxes
   std::vector<GroupPlan> plans;
   {
@@ -1424,6 +1509,7 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
   P->ly = pl.ly;
   P->lz = pl.lz;
   P->k0 = pl.k0;
+  P->overlap = pl.overlap;
   if (!inner_only) {
     P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0, s);
     upload(P->chi, pl.chi, s);
@@ -1472,22 +1558,31 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
       G.n = 3 * G.bnv;
       const int gi = (int)P->groups.size();
       std::vector<c128> gchi((size_t)G.nsys * G.bnv, mk<double>(0.0, 0.0));
+      std::vector<int4> sorg(G.nsys);
       for (int q = 0; q < G.nsys; ++q) {
         const int k = G.blocks[q];
         block_group[k] = gi;
         block_sys[k] = q;
         origin[k] = int4{lo[3 * k], lo[3 * k + 1], lo[3 * k + 2], 0};
+        sorg[q] = origin[k];
+        const int ex = pl.hi[3 * k] - lo[3 * k] + 1, ey = pl.hi[3 * k + 1] - lo[3 * k + 1] + 1;
         for (int z = 0; z < G.bz; ++z)
           for (int y = 0; y < G.by; ++y)
             for (int x = 0; x < G.bx; ++x) {
               const int X = lo[3 * k] + x, Y = lo[3 * k + 1] + y, Z = lo[3 * k + 2] + z;
               if (X >= g.nx || Y >= g.ny || Z >= g.nz) continue;
               const int64_t v = ((int64_t)Z * g.ny + Y) * g.nx + X;
-              if (bid[v] == k) gchi[(size_t)q * G.bnv + ((int64_t)z * G.by + y) * G.bx + x] = pl.chi[v];
+              // the block's solve set: its own voxels, or the expanded set
+              bool in = bid[v] == k;
+              if (pl.overlap > 0)
+                in = X <= pl.hi[3 * k] && Y <= pl.hi[3 * k + 1] && Z <= pl.hi[3 * k + 2] &&
+                     pl.emask[k][((size_t)z * ey + y) * ex + x] != 0;
+              if (in) gchi[(size_t)q * G.bnv + ((int64_t)z * G.by + y) * G.bx + x] = pl.chi[v];
             }
       }
       gbox.push_back(int4{G.bx, G.by, G.bz, 0});
       upload(G.chi, gchi, s);
+      if (pl.overlap > 0) upload(G.sys_origin, sorg, s);
       G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0, s);
       G.work.alloc((size_t)G.nsys * 3 * G.bz * G.ly * G.lx * sizeof(c128));
       G.work.zero(s);
@@ -1760,13 +1855,14 @@ vie_status vie_context_destroy(vie_context* ctx) {
   });
 }
 
-vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
-                              int32_t n_blocks, vie_problem** out) {
+static vie_status problem_create(vie_context* ctx, const vie_grid* grid, const double* eps_r,
+                                 const int32_t* block_id, int32_t n_blocks, int32_t overlap, vie_problem** out) {
   return guarded([&]() -> vie_status {
     if (!out) fail(VIE_EINVAL, "out is NULL");
     *out = nullptr;
     if (!ctx || !grid || !eps_r) fail(VIE_EINVAL, "ctx, grid and eps_r are required");
-    ProblemPlan plan = make_plan(*grid, eps_r, block_id, n_blocks);
+    if (overlap < 0 || overlap > 256) fail(VIE_EINVAL, "overlap must be in [0, 256]");
+    ProblemPlan plan = make_plan(*grid, eps_r, block_id, n_blocks, block_id ? overlap : 0);
     set_device(ctx);
     const size_t foot = plan_footprint(ctx, plan);
     {
@@ -1787,6 +1883,16 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
     }
     return VIE_OK;
   });
+}
+
+vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
+                              int32_t n_blocks, vie_problem** out) {
+  return problem_create(ctx, grid, eps_r, block_id, n_blocks, 0, out);
+}
+
+vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, const double* eps_r,
+                                      const int32_t* block_id, int32_t n_blocks, int32_t overlap, vie_problem** out) {
+  return problem_create(ctx, grid, eps_r, block_id, n_blocks, overlap, out);
 }
 
 vie_status vie_problem_destroy(vie_problem* p) {

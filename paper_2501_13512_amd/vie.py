@@ -55,7 +55,7 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
                 -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL", -8: "VIE_ETIMEDOUT"}
 
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
-               "vie_problem_create", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass",
+               "vie_problem_create", "vie_problem_create_overlap", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass",
                "vie_plane_wave",
                "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
                "vie_solve_batch",
@@ -108,6 +108,8 @@ for _name, _args in {
     "vie_context_create": [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(_vp)],
     "vie_context_destroy": [_vp],
     "vie_problem_create": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
+    "vie_problem_create_overlap": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(_vp)],
     "vie_problem_destroy": [_vp],
     "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
     "vie_problem_set_zpass": [_vp, ctypes.c_int32, ctypes.c_int32],
@@ -170,6 +172,16 @@ def vie_problem_create(ctx: int, grid: vie_grid, eps_r: np.ndarray, block_id: Op
     out = _vp()
     _check(_lib.vie_problem_create(ctx, ctypes.byref(grid), _np_ptr(eps), _np_ptr(bid), int(n_blocks),
                                    ctypes.byref(out)), "vie_problem_create")
+    return out.value
+
+
+def vie_problem_create_overlap(ctx: int, grid: vie_grid, eps_r: np.ndarray, block_id: np.ndarray, n_blocks: int,
+                               overlap: int) -> int:
+    eps = np.ascontiguousarray(eps_r, dtype=np.complex128)
+    bid = np.ascontiguousarray(block_id, dtype=np.int32)
+    out = _vp()
+    _check(_lib.vie_problem_create_overlap(ctx, ctypes.byref(grid), _np_ptr(eps), _np_ptr(bid), int(n_blocks),
+                                           int(overlap), ctypes.byref(out)), "vie_problem_create_overlap")
     return out.value
 
 
@@ -337,11 +349,14 @@ class Problem:
     """Owns a context (optional) and a problem handle."""
 
     def __init__(self, grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray] = None, n_blocks: int = 0,
-                 ctx: Optional[int] = None, device: int = 0):
+                 ctx: Optional[int] = None, device: int = 0, overlap: int = 0):
         self._own_ctx = ctx is None
         self.ctx = vie_context_create(device) if ctx is None else ctx
         self.grid = grid
-        self.handle = vie_problem_create(self.ctx, grid, eps, block_id, n_blocks)
+        if overlap and block_id is not None:
+            self.handle = vie_problem_create_overlap(self.ctx, grid, eps, block_id, n_blocks, overlap)
+        else:
+            self.handle = vie_problem_create(self.ctx, grid, eps, block_id, n_blocks)
 
     @property
     def shape(self) -> Tuple[int, int, int, int]:
