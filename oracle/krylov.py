@@ -11,7 +11,7 @@ matrix A_k keeps all x/y/z couplings (eq. (11)) and is itself solved by
 BiCGSTAB with FFT products to a loose ("softened") tolerance.  The block
 solutions are written back into one vector for the outer iteration.
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
 
 * inner products are conjugated in the first argument; the shadow vector is
   the initial residual; x0 = 0 for the outer and for every inner solve;
@@ -20,6 +20,10 @@ Readings where the paper is silent (listed in the design doc):
 * an inner solve that reaches its iteration cap (or breaks down) returns its
   last iterate; a block whose right-hand side is zero returns zero;
 * one "step" is one pass of the loop below.
+
+Solver variants beside the paper's BiCGSTAB: flexible GMRES (``fgmres``)
+and conjugate gradient squared (``cgs``), the latter named by the paper as
+another applicable Krylov method (Sec. II-B).
 """
 from __future__ import annotations
 
@@ -214,6 +218,57 @@ class _Block:
     own: np.ndarray            # bool [bz, by, bx]: the block's own voxels (kept)
 
 
+def cgs(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float, maxit: int,
+        precond: Optional[Callable[[np.ndarray], np.ndarray]] = None):
+    """Conjugate gradient squared (Sonneveld, SIAM J. Sci. Stat. Comput. 10
+    (1989)), right preconditioned, x0 = 0: one of the Krylov solvers the
+    paper lists as applicable (Sec. II-B).  The residual is recomputed as
+    b - A x after every step (the form of the standard template that
+    replaces the recursive update; same two products per step).  A step is
+    two preconditioner applications and two products; the stopping test is
+    ||b - A x|| / ||b|| after the step."""
+    M = precond if precond is not None else (lambda w: w)
+    x = np.zeros_like(b)
+    nb = _norm(b)
+    info = KrylovInfo()
+    if nb == 0.0:
+        info.status, info.relres = "converged", 0.0
+        return x, info
+    r = b.copy()
+    rhat = r.copy()
+    rho = _dot(rhat, r)
+    u = p = q = None
+    for it in range(1, maxit + 1):
+        if it == 1:
+            u = r.copy()
+            p = r.copy()
+        else:
+            rho_new = _dot(rhat, r)
+            if rho_new == 0.0:
+                info.status = "breakdown"
+                return x, info
+            beta = rho_new / rho
+            rho = rho_new
+            u = r + beta * q
+            p = u + beta * (q + beta * p)
+        v = apply_A(M(p))
+        rv = _dot(rhat, v)
+        if rv == 0.0:
+            info.status = "breakdown"
+            return x, info
+        alpha = rho / rv
+        q = u - alpha * v
+        x = x + alpha * M(u + q)
+        r = b - apply_A(x)
+        info.iterations = it
+        info.relres = _norm(r) / nb
+        info.history.append(info.relres)
+        if info.relres <= tol:
+            info.status = "converged"
+            return x, info
+    return x, info
+
+
 def expanded_block(grid: Grid, block_id: np.ndarray, k: int, overlap: int) -> np.ndarray:
     """Scatterer voxels within ``overlap`` voxels of block k in every axis
     (the block dilated by a (2 overlap + 1)^3 cube, restricted to S)."""
@@ -300,8 +355,9 @@ def solve(grid: Grid, e_inc: np.ndarray, tol_outer: float, maxit_outer: int = 10
     rounding alone moves the iterates at a given tolerance.
     ``product="c64"`` runs every FFT convolution in complex64 (the mixed
     mode's products); vectors and inner products stay FP64.
-    ``method="fgmres"`` replaces the outer BiCGSTAB by flexible GMRES(restart)
-    (a solver variant; the paper's method is BiCGSTAB)."""
+    ``method="fgmres"`` replaces the outer BiCGSTAB by flexible GMRES(restart),
+    ``method="cgs"`` by conjugate gradient squared (solver variants; the
+    paper's method is BiCGSTAB)."""
     A = FFTOperator(grid, pad, product)
     b = masked_rhs(grid, e_inc)
     pre = None
@@ -309,6 +365,8 @@ def solve(grid: Grid, e_inc: np.ndarray, tol_outer: float, maxit_outer: int = 10
         pre = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner, pad, product, overlap)
     if method == "fgmres":
         P, info = fgmres(A, b, tol_outer, maxit_outer, restart, pre)
+    elif method == "cgs":
+        P, info = cgs(A, b, tol_outer, maxit_outer, pre)
     else:
         P, info = bicgstab(A, b, tol_outer, maxit_outer, pre)
     return Solution(P, total_field(grid, P), info, pre.inner_counts if pre is not None else [])

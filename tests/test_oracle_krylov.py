@@ -3,7 +3,9 @@
 * BiCGSTAB iterates equal those of an independent library implementation of
   the same van der Vorst recurrence (scipy), with and without a right
   preconditioner, iteration by iteration.
-* Converged solutions equal the dense LU solution.
+* CGS iterates equal scipy's (same recurrence, residual recomputed as
+  b - A x), with and without a right preconditioner.
+* Converged solutions (BiCGSTAB, CGS) equal the dense LU solution.
 * Special cases of the block preconditioner: one block solved exactly gives
   convergence in one outer step; single-voxel blocks reduce to the explicit
   3x3 block-Jacobi inverse; every partition reaches the same solution.
@@ -278,3 +280,61 @@ def test_overlap_covering_the_scatterer_is_exact():
     assert s.info.iterations == 1
     ref = krylov.solve_dense(g, e)
     assert np.linalg.norm(s.P - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("precondition", [False, True])
+def test_cgs_iterates_match_scipy_cgs(precondition):
+    """CGS (solver variant): every iterate equals that of an independent
+    library implementation of Sonneveld's recurrence with the residual
+    recomputed as b - A x (scipy), with and without a right preconditioner."""
+    n4 = 4
+    kk, jj, ii = np.meshgrid(*[np.arange(n4)] * 3, indexing="ij")
+    g = op.Grid(n4, n4, n4, 0.06, 0.06, 0.06, 1.0, np.full((n4,) * 3, 4.0 + 0j))
+    block_id = (ii >= 2).astype(np.int32)
+    e = physics.plane_wave(g)
+    Z, idx = op.dense_matrix(g)
+    A = lambda x: op.from_support(g, Z @ op.to_support(g, x, idx), idx)
+    b = op.to_support(g, e * g.mask, idx)
+    n = b.size
+    M_grid = M_s = None
+    if precondition:
+        i, j, k = idx
+        blk = np.tile(block_id[k, j, i], 3)
+        Minv = np.linalg.inv(np.where(blk[:, None] == blk[None, :], Z, 0))
+        M_grid = lambda w: op.from_support(g, Minv @ op.to_support(g, w, idx), idx)
+        M_s = spla.LinearOperator((n, n), matvec=lambda v: Minv @ v, dtype=complex)
+    A_s = spla.LinearOperator((n, n), matvec=lambda v: Z @ v, dtype=complex)
+    hist = []
+    spla.cgs(A_s, b, rtol=1e-30, atol=0.0, maxiter=6, M=M_s, callback=lambda xk: hist.append(xk.copy()))
+    assert len(hist) == 6
+    for k in range(1, 7):
+        x, info = krylov.cgs(A, e * g.mask, 0.0, k, M_grid)
+        assert info.iterations == k
+        xs = op.to_support(g, x, idx)
+        assert np.linalg.norm(xs - hist[k - 1]) <= 1e-12 * np.linalg.norm(hist[k - 1])
+        r = op.to_support(g, e * g.mask - A(x), idx)
+        assert info.relres == pytest.approx(np.linalg.norm(r) / np.linalg.norm(b), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed,shape", [(44, (3, 4, 5)), (45, (4, 4, 4))])
+def test_cgs_converges_to_dense_lu(seed, shape):
+    case, g, e = _problem(seed, shape)
+    Pd = krylov.solve_dense(g, e)
+    s = krylov.solve(g, e, 1e-12, 3000, method="cgs")
+    assert s.info.status == "converged"
+    assert np.linalg.norm(s.P - Pd) <= 1e-9 * np.linalg.norm(Pd)
+    sp = krylov.solve(g, e, 1e-12, 3000, case.block_id, case.n_blocks, 1e-6, 500, method="cgs")
+    assert sp.info.status == "converged"
+    assert np.linalg.norm(sp.P - Pd) <= 1e-9 * np.linalg.norm(Pd)
+    # two preconditioner applications per step, as in BiCGSTAB
+    assert len(sp.inner_counts) == 2 * sp.info.iterations
+
+
+def test_cgs_exact_preconditioner_one_step_and_zero_rhs():
+    A, b = _dense_problem(5)
+    Ainv = np.linalg.inv(A)
+    x, info = krylov.cgs(lambda v: A @ v, b, 1e-12, 10, precond=lambda w: Ainv @ w)
+    assert info.iterations == 1 and info.status == "converged"
+    assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+    x, info = krylov.cgs(lambda v: v, np.zeros(4, complex), 1e-8, 10)
+    assert info.iterations == 0 and info.status == "converged" and not np.any(x)
