@@ -175,6 +175,7 @@ def main():
                     help="solves of the flexible GMRES(m) outer-solver variant (same preconditioner and precision); "
                          "0 = skip")
     ap.add_argument("--fgmres-restart", type=int, default=100)
+    ap.add_argument("--cgs-maxit", type=int, default=1500, help="step cap of the CGS variant")
     ap.add_argument("--fgmres-tol", type=float, default=1e-6,
                     help="GMRES stops at its tolerance where BiCGSTAB's last step overshoots; 1e-6 keeps the field "
                          "error under 1e-5 on this workload")
@@ -304,6 +305,33 @@ def main():
             "field_check": golden_error(case, f),
             "rel_field_diff_vs_bicgstab": float(np.linalg.norm(f - mine) / np.linalg.norm(mine)),
             "footprint_bytes": int(P.info().footprint_bytes)}
+        # conjugate gradient squared with FP64 products (its squared residual
+        # polynomial amplifies complex64 rounding): one timed solve
+        oc = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=args.cgs_maxit,
+                         maxit_inner=case.maxit_inner, precondition=True, precision=V.VIE_FP64,
+                         solver=V.VIE_SOLVER_CGS)
+        ec = torch.empty_like(e_inc)
+        ow = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=2,
+                         maxit_inner=case.maxit_inner, precondition=True, precision=V.VIE_FP64,
+                         solver=V.VIE_SOLVER_CGS)
+        V.vie_solve_device(P.handle, e_inc, ow, ec, None, st)   # warm-up (FP64 graph capture)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        try:
+            cc = V.vie_solve_device(P.handle, e_inc, oc, ec, None, st)
+        except V.VieError as ex:   # a breakdown is a result of the variant, not of the run
+            cc = ex.code
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t1
+        sd = V.stats_dict(st)
+        f = ec.cpu().numpy()
+        log(f"cgs variant done: {sd['outer_iters']} steps in {tc:.2f} s")
+        variants["cgs_fp64"] = {
+            "tol_outer": case.tol_outer, "maxit_outer": args.cgs_maxit, "solves_per_s": 1.0 / tc,
+            "status": V.STATUS_NAMES.get(cc, cc), "outer_iters": sd["outer_iters"],
+            "precond_applies": sd["precond_applies"], "inner_iters_total": sd["inner_iters_total"],
+            "relres_true": sd["relres_true"], "field_check": golden_error(case, f),
+            "rel_field_diff_vs_bicgstab": float(np.linalg.norm(f - mine) / np.linalg.norm(mine))}
 
     # several incident directions on the same operator: the unpreconditioned
     # FP64 path as one batch (vie_solve_batch) against the same solves one by one

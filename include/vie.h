@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 9
+#define VIE_ABI_VERSION 10
 
 typedef enum {
   VIE_OK = 0,
@@ -67,7 +67,8 @@ typedef enum {
   VIE_EINVAL = -1,         /* invalid argument (sizes, non-finite values, block ids, ...) */
   VIE_ENOMEM = -2,         /* device or host allocation failed */
   VIE_EDEVICE = -3,        /* no usable HIP device, or a HIP runtime error */
-  VIE_EBREAKDOWN = -4,     /* BiCGSTAB breakdown (rho, <rhat,v> or <t,t> = 0, or non-finite); last iterate written */
+  VIE_EBREAKDOWN = -4,     /* Krylov breakdown (BiCGSTAB: rho, <rhat,v> or <t,t> = 0; CGS: rho or <rhat,v> = 0;
+                              GMRES: singular least-squares; or non-finite); last iterate written */
   VIE_EBUSY = -5,          /* resource budget exceeded */
   VIE_ECANCELLED = -6,
   VIE_EINTERNAL = -7,
@@ -110,7 +111,7 @@ typedef struct {
   int32_t restart;      /* VIE_SOLVER_FGMRES: Arnoldi steps per cycle, in [1, 1000] */
 } vie_opts;
 
-/* Outer Krylov solver.  Both are right preconditioned with the block
+/* Outer Krylov solver.  All are right preconditioned with the block
  * preconditioner of eq. (10) and start from x0 = 0.
  *  VIE_SOLVER_BICGSTAB: the BiCGSTAB of Sec. II-B; one step = two products
  *    and two preconditioner applications; maxit_outer counts steps.
@@ -122,10 +123,17 @@ typedef struct {
  *    Needs (2 restart + 1) vectors of 3 nx ny nz complex doubles (restart + 1
  *    without preconditioner), allocated by the first such solve of a problem
  *    and kept with it (counted in footprint_bytes; VIE_EBUSY beyond the
- *    context's budget).  Not accepted by vie_submit. */
+ *    context's budget).  Not accepted by vie_submit.
+ *  VIE_SOLVER_CGS: conjugate gradient squared (Sonneveld), the other
+ *    Krylov method Sec. II-B names as applicable; one step = two products
+ *    and two preconditioner applications, like BiCGSTAB.  The residual is
+ *    recomputed as b - A x after every step (one of the two products) and
+ *    tested against tol_outer; maxit_outer counts steps.  Uses the problem's
+ *    own vectors (no extra storage).  Not accepted by vie_submit. */
 typedef enum {
   VIE_SOLVER_BICGSTAB = 0,
-  VIE_SOLVER_FGMRES = 1
+  VIE_SOLVER_FGMRES = 1,
+  VIE_SOLVER_CGS = 2
 } vie_solver;
 
 /* vie_opts.flags: run the inner block iterations as individual kernel
@@ -299,8 +307,8 @@ vie_status vie_rcs(vie_problem* p, const void* pol_dev, int32_t n_dir, const dou
  * shape groups (a replica built by the first such call for that nrhs, kept
  * with the problem); a system that has stopped contributes zero right-hand
  * sides, which its blocks skip.  Its inner_iters_total and precond_applies
- * are the batch's totals.  VIE_SOLVER_FGMRES solves the right-hand sides
- * one after another.  Batch storage (12 vectors and one FFT work buffer per
+ * are the batch's totals.  VIE_SOLVER_FGMRES and VIE_SOLVER_CGS solve the
+ * right-hand sides one after another.  Batch storage (12 vectors and one FFT work buffer per
  * right-hand side, plus the replica) is counted in footprint_bytes
  * (VIE_EBUSY beyond the context's budget).  Returns the first error, else
  * VIE_NOT_CONVERGED if any system did not converge, else VIE_OK; every

@@ -198,7 +198,7 @@ void gmres_start(const GmresDev& d, c128* v0, bool first, double tol, int maxit,
 void gmres_update(const GmresDev& d, c128* x, const c128* B, hipStream_t s);  // x += B y
 
 // Scalar steps applied by k_finalize after a producer wrote partials.
-enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4, FIN_SOMEGA = 5 };
+enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_S = 2, FIN_OMEGA = 3, FIN_XR = 4, FIN_SOMEGA = 5, FIN_CGS = 6 };
 
 int64_t krylov_chunks(int64_t n);   // reduction chunks per system (vector kernels)
 
@@ -212,6 +212,8 @@ void k_init(const KBatch& k, const c128* b, c128* x, c128* r, c128* rhat, const 
 //   FIN_OMEGA: omega = <t, s> / <t, t>
 //   FIN_SOMEGA: half-step test on ||s|| (from pass-5 out_mode 4), then omega
 //   FIN_XR:    rho', ||r||, convergence, breakdown, cap, beta; HALF -> CONVERGED
+//   FIN_CGS:   CGS step end: rho' = <rhat, r>, ||r||, convergence, breakdown,
+//              cap, beta = rho' / rho
 void k_finalize(const KBatch& k, FinKind kind, hipStream_t s, const int* gate = nullptr, double tol = 0,
                 int maxit = 0);
 // p = r (first step) or p = r + beta (p - omega v)
@@ -222,6 +224,16 @@ void k_update_s(const KBatch& k, const c128* r, const c128* v, c128* sv, hipStre
 // (then FIN_XR); after a half-step convergence, x += alpha y only.
 void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv, const c128* t,
                  const c128* rhat, hipStream_t s);
+// Conjugate gradient squared (solver variant), per system, skipped unless
+// ACTIVE:
+// u = r, p = r (first step) or u = r + beta q, p = u + beta (q + beta p)
+void cgs_update_up(const KBatch& k, const c128* r, c128* u, const c128* q, c128* p, hipStream_t s);
+// q = u - alpha v, w = u + q (after FIN_ALPHA)
+void cgs_update_q(const KBatch& k, const c128* u, const c128* v, c128* q, c128* w, hipStream_t s);
+// x += alpha uh
+void cgs_update_x(const KBatch& k, c128* x, const c128* uh, hipStream_t s);
+// r = b - t (t = A x), partials of <rhat, r>, ||r||^2 (then FIN_CGS)
+void cgs_update_r(const KBatch& k, const c128* b, const c128* t, c128* r, const c128* rhat, hipStream_t s);
 // After one preconditioner application (skipped when the gate is not
 // ACTIVE): acc[0] += sum of the inner iteration counts of `slots`,
 // acc[1] += 1, and the counts are appended to hist at acc[2] (if they fit).

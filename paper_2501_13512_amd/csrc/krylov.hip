@@ -15,6 +15,11 @@
 //   alpha = rho / <rhat, v>; s = r - alpha v; [||s|| <= tol ||b||: x += alpha y]
 //   z = K^{-1} s; t = A z; omega = <t, s> / <t, t>;
 //   x += alpha y + omega z; r = s - omega t; beta = (rho'/rho)(alpha/omega).
+//
+// Conjugate gradient squared (Sonneveld), right-preconditioned, per system:
+//   u = r + beta q; p = u + beta (q + beta p); v = A K^{-1} p;
+//   alpha = rho / <rhat, v>; q = u - alpha v; x += alpha K^{-1} (u + q);
+//   r = b - A x; rho' = <rhat, r>; beta = rho' / rho.
 #include <stdexcept>
 #include <string>
 
@@ -125,6 +130,10 @@ __global__ void __launch_bounds__(KT) kk_finalize(KBatch k, int kind, const int*
       fin_s(st, &k.status[sys], v[3]);
       if (k.status[sys] == ST_ACTIVE) fin_omega(st, &k.status[sys], v);
     }
+  } else if (kind == FIN_CGS) {
+    double v[3];
+    final_sum<3>(k.partials, k.pstride, k.ntile, sys, v);
+    if (threadIdx.x == 0) fin_cgs(st, &k.status[sys], v);
   } else {
     double v[3];
     final_sum<3>(k.partials, k.pstride, k.ntile, sys, v);
@@ -272,6 +281,144 @@ void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r
   const int64_t chunks = chunks_of(k.n);
   hipLaunchKernelGGL(kk_update_xr, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, y, z, r, sv, t, rhat);
   check_launch("krylov xr");
+}
+
+// ---------------------------------------------------------------- CGS
+__global__ void __launch_bounds__(KT) kk_cgs_up(KBatch k, const c128* r, c128* u, const c128* q, c128* p) {
+  const int64_t n = k.n;
+  KRYLOV_INDEX
+  (void)chunk;
+  if (k.status[sys] != ST_ACTIVE) return;
+  const bool first = k.st[sys].iters == 0;
+  const c128 beta = k.st[sys].beta;
+  c128 rv[KEPT], qv[KEPT], pv[KEPT];
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      rv[j] = r[base + i];
+      if (!first) {
+        qv[j] = q[base + i];
+        pv[j] = p[base + i];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      if (first) {
+        u[base + i] = rv[j];
+        p[base + i] = rv[j];
+      } else {
+        const c128 uv = rv[j] + beta * qv[j];
+        u[base + i] = uv;
+        p[base + i] = uv + beta * (qv[j] + beta * pv[j]);
+      }
+    }
+  }
+}
+
+void cgs_update_up(const KBatch& k, const c128* r, c128* u, const c128* q, c128* p, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_cgs_up, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, r, u, q, p);
+  check_launch("cgs u, p");
+}
+
+__global__ void __launch_bounds__(KT) kk_cgs_q(KBatch k, const c128* u, const c128* v, c128* q, c128* w) {
+  const int64_t n = k.n;
+  KRYLOV_INDEX
+  (void)chunk;
+  if (k.status[sys] != ST_ACTIVE) return;
+  const c128 alpha = k.st[sys].alpha;
+  c128 uv[KEPT], vv[KEPT];
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      uv[j] = u[base + i];
+      vv[j] = v[base + i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 qv = uv[j] - alpha * vv[j];
+      q[base + i] = qv;
+      w[base + i] = uv[j] + qv;
+    }
+  }
+}
+
+void cgs_update_q(const KBatch& k, const c128* u, const c128* v, c128* q, c128* w, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_cgs_q, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, u, v, q, w);
+  check_launch("cgs q");
+}
+
+__global__ void __launch_bounds__(KT) kk_cgs_x(KBatch k, c128* x, const c128* uh) {
+  const int64_t n = k.n;
+  KRYLOV_INDEX
+  (void)chunk;
+  if (k.status[sys] != ST_ACTIVE) return;
+  const c128 alpha = k.st[sys].alpha;
+  c128 xv[KEPT], hv[KEPT];
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      xv[j] = x[base + i];
+      hv[j] = uh[base + i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) x[base + i] = xv[j] + alpha * hv[j];
+  }
+}
+
+void cgs_update_x(const KBatch& k, c128* x, const c128* uh, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_cgs_x, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, uh);
+  check_launch("cgs x");
+}
+
+__global__ void __launch_bounds__(KT) kk_cgs_r(KBatch k, const c128* b, const c128* t, c128* r, const c128* rhat) {
+  const int64_t n = k.n;
+  KRYLOV_INDEX
+  if (k.status[sys] != ST_ACTIVE) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  c128 bv[KEPT], tv[KEPT], hv[KEPT];
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      bv[j] = b[base + i];
+      tv[j] = t[base + i];
+      hv[j] = rhat[base + i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KEPT; ++j) {
+    const int64_t i = i0 + (int64_t)j * KT;
+    if (i < n) {
+      const c128 rv = bv[j] - tv[j];
+      r[base + i] = rv;
+      const c128 d = cdot1(hv[j], rv);
+      acc[0] += d.x;
+      acc[1] += d.y;
+      acc[2] += abs2(rv);
+    }
+  }
+  write_partial<3>(acc, k.partials, k.pstride, k.ntile, sys, chunk, chunks);
+}
+
+void cgs_update_r(const KBatch& k, const c128* b, const c128* t, c128* r, const c128* rhat, hipStream_t s) {
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_cgs_r, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, b, t, r, rhat);
+  check_launch("cgs r");
 }
 
 // ---------------------------------------------------------------- bookkeeping

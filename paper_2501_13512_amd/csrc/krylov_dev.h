@@ -122,4 +122,21 @@ __device__ __forceinline__ void fin_xr(KState& k, int* status, const double* v) 
     k.beta = cdiv(k.rho, k.rho_old) * cdiv(k.alpha, k.omega);
 }
 
+// end of a CGS step (r recomputed as b - A x): new rho = <rhat, r>, ||r||;
+// convergence, breakdown, cap, beta = rho' / rho
+__device__ __forceinline__ void fin_cgs(KState& k, int* status, const double* v) {
+  k.rnorm = sqrt(v[2]) / k.nb;
+  k.rho_old = k.rho;
+  k.rho = mk<double>(v[0], v[1]);
+  const bool rho0 = k.rho.x == 0.0 && k.rho.y == 0.0;
+  if (k.rnorm <= k.tol)
+    *status = ST_CONVERGED;
+  else if (rho0 || !(k.rnorm == k.rnorm))
+    *status = ST_BREAKDOWN;
+  else if (k.iters >= k.maxit)
+    *status = ST_MAXIT;
+  else
+    k.beta = cdiv(k.rho, k.rho_old);
+}
+
 }  // namespace vie

@@ -878,6 +878,51 @@ RunResult run_fgmres(vie_problem& P, const c128* rhs, c128* x, double tol, int m
   return r;
 }
 
+// Conjugate gradient squared (Sonneveld) on the full grid, x0 = 0: a solver
+// variant that Sec. II-B names beside BiCGSTAB, right-preconditioned with the
+// block preconditioner of eq. (10).  Each step applies the preconditioner
+// twice (to p and to u + q) and the product twice (to K^{-1} p and to the new
+// x: the residual is recomputed as b - A x and tested).  Vectors: u in V_S,
+// q in V_T, v and A x in V_V, u + q in V_Z, K^{-1} p then K^{-1}(u + q) in
+// V_Y; rhs and x may be V_TMP2 / V_TMP1 (refinement).
+template <typename R, typename RI = R>
+RunResult run_cgs(vie_problem& P, const c128* rhs, c128* x, double tol, int maxit, bool prec, double tol_in,
+                  int maxit_in, int lag, int32_t* hist, int64_t hist_cap, bool graphs, bool wg, hipStream_t s) {
+  KBatch k = outer_kbatch(P);
+  MvmBatch<R> m = outer_batch<R>(P, true);
+  c128** v = P.vec;
+  const int* gate = P.ostatus.as<int>();
+  c128 *r = v[V_R], *rhat = v[V_RHAT], *u = v[V_S], *q = v[V_T], *p = v[V_P], *av = v[V_V], *w = v[V_Z];
+  c128* ph = prec ? v[V_Y] : p;    // K^{-1} p
+  c128* uh = prec ? v[V_Y] : w;    // K^{-1} (u + q)
+  vie::k_init(k, rhs, x, r, rhat, nullptr, s);
+  vie::k_finalize(k, vie::FIN_INIT, s, nullptr, tol, maxit);
+  const vie::FuseArgs fa{0, 1, nullptr, nullptr, nullptr, rhat, nullptr};
+  Poller poll(P, s, 0);
+  for (int it = 1; it <= maxit; ++it) {
+    vie::cgs_update_up(k, r, u, q, p, s);
+    if (prec) precond_apply<RI>(P, p, ph, tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
+    vie::mvm_pass1<R>(m, &k, fa, ph, false, s);
+    vie::mvm_mid<R>(m, s);
+    vie::mvm_pass5<R>(m, &k, fa, ph, av, s);
+    vie::k_finalize(k, vie::FIN_ALPHA, s);
+    vie::cgs_update_q(k, u, av, q, w, s);
+    if (prec) precond_apply<RI>(P, w, uh, tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
+    vie::cgs_update_x(k, x, uh, s);
+    vie::mvm<R>(m, x, av, false, s);
+    vie::cgs_update_r(k, rhs, av, r, rhat, s);
+    vie::k_finalize(k, vie::FIN_CGS, s);
+    const long t = poll.push(P.ostatus.as<int>());
+    if (t - lag >= 0 && poll.wait(t - lag) != vie::ST_ACTIVE) break;
+    if (P.cancel && P.cancel->load(std::memory_order_relaxed)) break;
+  }
+  hip_check(hipStreamSynchronize(s), "solve");
+  RunResult res{};
+  hip_check(hipMemcpy(&res.st, P.ostate.p, sizeof(KState), hipMemcpyDeviceToHost), "state");
+  hip_check(hipMemcpy(&res.status, P.ostatus.p, sizeof(int), hipMemcpyDeviceToHost), "state");
+  return res;
+}
+
 double true_relres(vie_problem& P, const c128* rhs, const c128* x, c128* tmp_ax, c128* tmp_r, double nb,
                    hipStream_t s) {
   MvmBatch<double> m = outer_batch<double>(P, false);
@@ -899,7 +944,8 @@ void validate_opts(const vie_opts* o, bool has_blocks) {
   if (o->poll_lag < 0 || o->poll_lag > kRing - 2) fail(VIE_EINVAL, "poll_lag out of range");
   if (o->max_refine < 0 || o->max_refine > 100) fail(VIE_EINVAL, "max_refine out of range");
   if (o->flags & ~(VIE_FLAG_NO_GRAPHS | VIE_FLAG_NO_BLOCK_KERNEL)) fail(VIE_EINVAL, "unknown flags");
-  if (o->solver != VIE_SOLVER_BICGSTAB && o->solver != VIE_SOLVER_FGMRES) fail(VIE_EINVAL, "unknown solver");
+  if (o->solver != VIE_SOLVER_BICGSTAB && o->solver != VIE_SOLVER_FGMRES && o->solver != VIE_SOLVER_CGS)
+    fail(VIE_EINVAL, "unknown solver");
   if (o->solver == VIE_SOLVER_FGMRES && (o->restart < 1 || o->restart > 1000))
     fail(VIE_EINVAL, "restart must be in [1, 1000]");
   if (o->precondition) {
@@ -941,6 +987,9 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     if (fgmres)
       return run_fgmres<R, RI>(P, rhs, x, tol, o->maxit_outer, o->restart, prec, o->tol_inner, o->maxit_inner,
                                o->poll_lag, hist, hist_cap, graphs, wg, s);
+    if (o->solver == VIE_SOLVER_CGS)
+      return run_cgs<R, RI>(P, rhs, x, tol, o->maxit_outer, prec, o->tol_inner, o->maxit_inner, o->poll_lag, hist,
+                            hist_cap, graphs, wg, s);
     return run_bicgstab<R, RI>(P, rhs, x, tol, o->maxit_outer, prec, o->tol_inner, o->maxit_inner, o->poll_lag,
                                hist, hist_cap, graphs, wg, s);
   };
@@ -997,7 +1046,9 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     return VIE_ECANCELLED;
   }
   if (rr.status == vie::ST_BREAKDOWN) {
-    g_last_error = fgmres ? "GMRES breakdown (last iterate written)" : "BiCGSTAB breakdown (last iterate written)";
+    g_last_error = fgmres                           ? "GMRES breakdown (last iterate written)"
+                   : o->solver == VIE_SOLVER_CGS ? "CGS breakdown (last iterate written)"
+                                                 : "BiCGSTAB breakdown (last iterate written)";
     return VIE_EBREAKDOWN;
   }
   // mixed: the refinement may reach the tolerance after the main loop's cap

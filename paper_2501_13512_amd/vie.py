@@ -50,7 +50,7 @@ VIE_ETIMEDOUT = -8
 VIE_FP64, VIE_MIXED, VIE_MIXED_INNER = 0, 1, 2
 VIE_FLAG_NO_GRAPHS = 1
 VIE_FLAG_NO_BLOCK_KERNEL = 2
-VIE_SOLVER_BICGSTAB, VIE_SOLVER_FGMRES = 0, 1
+VIE_SOLVER_BICGSTAB, VIE_SOLVER_FGMRES, VIE_SOLVER_CGS = 0, 1, 2
 STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_ENOMEM", -3: "VIE_EDEVICE",
                 -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL", -8: "VIE_ETIMEDOUT"}
 
