@@ -304,6 +304,7 @@ struct vie_problem {
   Branches branches;   // per-group capture streams (parallel graph branches)
   // polling: ring 0 for the outer loop, ring 1 for the inner loops
   int* h_ring = nullptr;
+  int* d_ring = nullptr;   // the device's address of h_ring (null: progress values are copied)
   hipEvent_t ev[2][kRing] = {};
   std::mutex mu;
   size_t footprint = 0;
@@ -354,6 +355,20 @@ struct Poller {
     const int slot = (int)(n % kRing);
     hip_check(hipMemcpyAsync(&P.h_ring[ring * kRing + slot], dval, sizeof(int), hipMemcpyDeviceToHost, s),
               "poll copy");
+    hip_check(hipEventRecord(P.ev[ring][slot], s), "poll event");
+    return n++;
+  }
+  // The number of ACTIVE entries of status[0..nsys) as the next value.  The
+  // counting kernel stores it straight into the pinned ring (no copy launch
+  // per inner step); without a device address for the ring it counts into
+  // dtmp and the value is copied.
+  long push_count(const int* status, int nsys, int* dtmp) {
+    if (!P.d_ring) {
+      vie::count_active(status, nsys, dtmp, s);
+      return push(dtmp);
+    }
+    const int slot = (int)(n % kRing);
+    vie::count_active(status, nsys, P.d_ring + ring * kRing + slot, s);
     hip_check(hipEventRecord(P.ev[ring][slot], s), "poll event");
     return n++;
   }
@@ -677,8 +692,7 @@ void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit
         hip_check(hipGraphLaunch(ex, s), "graph launch");
       else
         inner_iteration<R>(P, s, Branches{}, wg);
-      vie::count_active(P.d_istatus.as<int>(), nslots, P.d_count.as<int>(), s);
-      const long t = poll.push(P.d_count.as<int>());
+      const long t = poll.push_count(P.d_istatus.as<int>(), nslots, P.d_count.as<int>());
       if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
     }
   }
@@ -1183,8 +1197,7 @@ void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag
       vie::k_update_xr(k, vec(BV_X), vec(BV_Y), vec(BV_Z), vec(BV_R), vec(BV_S), vec(BV_T), vec(BV_RHAT), s);
       vie::k_finalize(k, vie::FIN_XR, s);
     }
-    vie::count_active(P.mr_status.as<int>(), nrhs, P.mr_count.as<int>(), s);
-    const long t = poll.push(P.mr_count.as<int>());
+    const long t = poll.push_count(P.mr_status.as<int>(), nrhs, P.mr_count.as<int>());
     if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
   }
   hip_check(hipStreamSynchronize(s), "batch solve");
@@ -1583,6 +1596,13 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
   P->d_acc.alloc(3 * sizeof(int64_t));
   P->d_acc.zero(s);
   hip_check(hipHostMalloc((void**)&P->h_ring, 2 * kRing * sizeof(int)), "pinned ring");
+  {
+    void* dv = nullptr;
+    if (hipHostGetDevicePointer(&dv, P->h_ring, 0) == hipSuccess && dv)
+      P->d_ring = static_cast<int*>(dv);
+    else
+      (void)hipGetLastError();
+  }
   for (auto& r : P->ev)
     for (auto& e : r) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
 
