@@ -379,6 +379,14 @@ struct Poller {
   }
 };
 
+// Device-to-host copy ordered on the solve's own (non-blocking) stream.  A
+// synchronous hipMemcpy would go through the legacy stream, which HIP
+// refuses while another server slot is capturing its inner-step graph.
+void copy_out(void* dst, const void* src, size_t bytes, hipStream_t s, const char* what) {
+  hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s), what);
+  hip_check(hipStreamSynchronize(s), what);
+}
+
 template <typename R>
 const cx<R>* spec_ptr(const Spectra& s);
 template <>
@@ -752,8 +760,8 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
   }
   hip_check(hipStreamSynchronize(s), "solve");
   RunResult r{};
-  hip_check(hipMemcpy(&r.st, P.ostate.p, sizeof(KState), hipMemcpyDeviceToHost), "state");
-  hip_check(hipMemcpy(&r.status, P.ostatus.p, sizeof(int), hipMemcpyDeviceToHost), "state");
+  copy_out(&r.st, P.ostate.p, sizeof(KState), s, "state");
+  copy_out(&r.status, P.ostatus.p, sizeof(int), s, "state");
   return r;
 }
 
@@ -883,7 +891,7 @@ RunResult run_fgmres(vie_problem& P, const c128* rhs, c128* x, double tol, int m
     vie::gmres_start(d, V(0), false, tol, maxit, s);
   }
   vie::GmresState gs{};
-  hip_check(hipMemcpy(&gs, d.st, sizeof(gs), hipMemcpyDeviceToHost), "state");
+  copy_out(&gs, d.st, sizeof(gs), s, "state");
   RunResult r{};
   r.st.nb = gs.nb;
   r.st.iters = gs.iters;
@@ -932,8 +940,8 @@ RunResult run_cgs(vie_problem& P, const c128* rhs, c128* x, double tol, int maxi
   }
   hip_check(hipStreamSynchronize(s), "solve");
   RunResult res{};
-  hip_check(hipMemcpy(&res.st, P.ostate.p, sizeof(KState), hipMemcpyDeviceToHost), "state");
-  hip_check(hipMemcpy(&res.status, P.ostatus.p, sizeof(int), hipMemcpyDeviceToHost), "state");
+  copy_out(&res.st, P.ostate.p, sizeof(KState), s, "state");
+  copy_out(&res.status, P.ostatus.p, sizeof(int), s, "state");
   return res;
 }
 
@@ -1049,7 +1057,7 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     if (hist) {
       const int64_t len = std::min<int64_t>(acc[2], hist_cap);
       if (acc[2] <= hist_cap) {
-        hip_check(hipMemcpy(stats->inner_hist, hist, len * sizeof(int32_t), hipMemcpyDeviceToHost), "hist");
+        copy_out(stats->inner_hist, hist, len * sizeof(int32_t), s, "hist");
         stats->inner_hist_len = len;
       }
     }
@@ -2322,11 +2330,11 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
       run_bicgstab_batch<double, double>(P, nrhs, opts->tol_outer, opts->maxit_outer, lag, prec, ti, mi, graphs,
                                          wgk, s);
     int64_t acc[3] = {0, 0, 0};
-    if (prec) hip_check(hipMemcpy(acc, P.replica->d_acc.p, sizeof(acc), hipMemcpyDeviceToHost), "acc");
+    if (prec) copy_out(acc, P.replica->d_acc.p, sizeof(acc), s, "acc");
     std::vector<KState> st(nrhs);
     std::vector<int> status(nrhs);
-    hip_check(hipMemcpy(st.data(), P.mr_state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost), "batch state");
-    hip_check(hipMemcpy(status.data(), P.mr_status.p, nrhs * sizeof(int), hipMemcpyDeviceToHost), "batch status");
+    copy_out(st.data(), P.mr_state.p, nrhs * sizeof(KState), s, "batch state");
+    copy_out(status.data(), P.mr_status.p, nrhs * sizeof(int), s, "batch status");
     const double batch_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     // per system: true residual, refinement (mixed), fields, statistics
     for (int r = 0; r < nrhs; ++r) {
