@@ -66,7 +66,8 @@ struct DevBuf {
     if (p) hip_check(hipMemsetAsync(p, 0, bytes, s), "hipMemsetAsync");
   }
   void reset() {
-    if (p) (void)hipFree(p);
+    // a failed free must not leave its error for the next launch check
+    if (p && hipFree(p) != hipSuccess) (void)hipGetLastError();
     p = nullptr;
     bytes = 0;
   }
