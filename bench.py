@@ -192,8 +192,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
-              f"build", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
