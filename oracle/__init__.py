@@ -14,7 +14,9 @@ Electromagnetic Response from Nanostructures" (arXiv 2501.13512):
 * ``operator`` the VIE operator of eqs. (2)-(4)/(6): dense assembly, a
                brute-force O(N^2) product and the FFT product;
 * ``krylov``   BiCGSTAB with the right block-diagonal preconditioner of
-               Sec. II-B (eqs. (10)-(11)) and a dense LU reference solve;
+               Sec. II-B (eqs. (10)-(11)), a dense LU reference solve, and
+               the mixed-precision mode (complex64 products, FP64 vectors,
+               FP64 residual and correction solves);
 * ``physics``  plane-wave excitation, power balance, far field and RCS, and
                the Mie series used in Sec. III.
 

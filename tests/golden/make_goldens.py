@@ -1,26 +1,51 @@
-"""Write the oracle reference files for the full-size benchmark cases.
+"""Write the oracle reference files of the full-size metasurface case.
 
-Calls only ``oracle/`` and ``workloads``.  Two kinds of file per case:
+Calls only ``oracle/`` and ``workloads``.  Each run writes
+``oracle_metasurface_<run>.json`` (settings, outer step count, residual
+history, inner step counts of every preconditioner application, refinement
+counts, timing) and ``oracle_metasurface_<run>_etot.npy``: E_tot at every
+scatterer voxel, complex128 [3, n] in the order of ``numpy.nonzero(mask)``
+over the [z, y, x] grid.
 
-* ``oracle_<case>.json``: the FP64 oracle solve at the case's tolerances
-  (block preconditioner): outer step count, the inner step counts of every
-  preconditioner application, the residual history, the norm of E_tot over
-  the scatterer, and E_tot at 1024 scatterer voxels drawn with
-  default_rng(99).
-* ``oracle_<case>_tight.json`` (``--tight``): the FP64 oracle solve without
-  preconditioner to relative residual 1e-10 (the discrete solution is
-  unique, so any converged variant reaches it), E_tot at the same voxels.
+Runs (the case is 128x128x32 at lambda/40, 64 pillar blocks + slab):
 
-    python tests/golden/make_goldens.py metasurface
-    python tests/golden/make_goldens.py --tight metasurface
+* ``tight``       FP64, no preconditioner, outer tolerance 1e-12 (the
+                  discrete solution is unique, so every converged variant
+                  reaches it);
+* ``case``        FP64 block-preconditioned at the case tolerances (outer
+                  1e-5, inner 1e-2), circulant lengths 2n;
+* ``case_pad4``   the same with every circulant length 2n + 4 (the same
+                  operator with different rounding: how far rounding alone
+                  moves the iterates at these tolerances);
+* ``mixed``       complex64 products with FP64 refinement, block
+                  preconditioned at the benchmark's settings (outer 2e-6,
+                  inner 1e-2, at most 3 corrections);
+* ``mixed_pad4``  the same with lengths 2n + 4;
+* ``bench_fp64``  FP64 block-preconditioned at the benchmark's settings;
+* ``spread``      reads the stored fields and writes
+                  ``oracle_metasurface_spread.json``: relative field
+                  differences between the runs and the step counts side by
+                  side.
+
+BLAS is held to one thread so inner products are summed in a fixed order
+(the results do not depend on the machine's core count); ``--workers`` only
+splits independent FFTs.
+
+    python tests/golden/make_goldens.py --workers 4 tight
+    python tests/golden/make_goldens.py case
+    python tests/golden/make_goldens.py spread
 """
-import json
 import os
-import sys
-import time
 
-import numpy as np
-import scipy.fft
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
+import json  # noqa: E402
+import sys  # noqa: E402
+import time  # noqa: E402
+
+import numpy as np  # noqa: E402
+import scipy.fft  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -28,56 +53,106 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import workloads as W  # noqa: E402
 from oracle import krylov, operator as op, physics  # noqa: E402
 
-TIGHT_TOL = 1e-10
+CASE = "metasurface"
+TIGHT_TOL = 1e-12
+BENCH_TOL = 2e-6
+
+RUNS = {
+    "tight": dict(kind="fp64", prec=False, tol=TIGHT_TOL, maxit=20000, pad=0),
+    "case": dict(kind="fp64", prec=True, tol=None, pad=0),
+    "case_pad4": dict(kind="fp64", prec=True, tol=None, pad=4),
+    "mixed": dict(kind="mixed", prec=True, tol=BENCH_TOL, pad=0),
+    "mixed_pad4": dict(kind="mixed", prec=True, tol=BENCH_TOL, pad=4),
+    "bench_fp64": dict(kind="fp64", prec=True, tol=BENCH_TOL, pad=0),
+}
 
 
-def _samples(g, E):
+def path(run, ext):
+    suffix = "_etot.npy" if ext == "npy" else ".json"
+    return os.path.join(HERE, f"oracle_{CASE}_{run}{suffix}")
+
+
+def scatterer_values(g, E):
     k, j, i = np.nonzero(g.mask)
-    rng = np.random.default_rng(99)
-    pick = np.sort(rng.choice(i.size, size=min(1024, i.size), replace=False))
-    vox = np.stack([i[pick], j[pick], k[pick]], axis=1)
-    return vox, E[:, k[pick], j[pick], i[pick]]          # [3, n]
+    return np.ascontiguousarray(E[:, k, j, i])
 
 
-def golden(name: str, tight: bool) -> dict:
-    case = W.by_name(name)
+def run(name: str) -> dict:
+    spec = RUNS[name]
+    case = W.by_name(CASE)
     g = op.Grid.from_case(case)
     e = physics.plane_wave(g, case.kdir, case.pol)
+    tol = spec["tol"] if spec["tol"] is not None else case.tol_outer
+    maxit = spec.get("maxit", case.maxit_outer)
+    blocks = (case.block_id, case.n_blocks) if spec["prec"] else (None, 0)
     t0 = time.time()
-    if tight:
-        sol = krylov.solve(g, e, TIGHT_TOL, 20000)
+    if spec["kind"] == "mixed":
+        sol = krylov.solve_mixed(g, e, tol, maxit, blocks[0], blocks[1], case.tol_inner, case.maxit_inner,
+                                 max_refine=3, pad=spec["pad"])
     else:
-        sol = krylov.solve(g, e, case.tol_outer, case.maxit_outer, case.block_id, case.n_blocks,
-                           case.tol_inner, case.maxit_inner)
+        sol = krylov.solve(g, e, tol, maxit, blocks[0], blocks[1], case.tol_inner, case.maxit_inner,
+                           pad=spec["pad"])
     secs = time.time() - t0
-    vox, E = _samples(g, sol.E_tot)
     d = {
-        "case": name,
-        "source": ("oracle FP64 solve without preconditioner to relative residual 1e-10" if tight else
-                   "oracle FP64 solve (oracle/krylov.py solve) at the case tolerances") +
-                  "; tests/golden/make_goldens.py",
-        "tol_outer": TIGHT_TOL if tight else case.tol_outer,
-        "outer_iters": sol.info.iterations, "status": sol.info.status,
+        "case": CASE, "run": name,
+        "source": "oracle/ (krylov.solve_mixed)" if spec["kind"] == "mixed" else "oracle/ (krylov.solve)",
+        "script": "tests/golden/make_goldens.py",
+        "precision": "complex64 products, FP64 vectors and refinement" if spec["kind"] == "mixed" else "FP64",
+        "precondition": spec["prec"], "pad": spec["pad"],
+        "tol_outer": tol, "maxit_outer": maxit,
+        "outer_iters": sol.info.iterations, "status": sol.info.status, "half_step": sol.info.half_step,
         "history": sol.info.history,
         "etot_norm": float(np.linalg.norm(sol.E_tot)),
-        "voxels_xyz": vox.tolist(),
-        "etot_re": E.real.tolist(), "etot_im": E.imag.tolist(),
+        "n_scatterer": int(np.count_nonzero(g.mask)),
         "oracle_seconds": secs,
     }
-    if not tight:
+    if spec["prec"]:
         d["tol_inner"] = case.tol_inner
+        d["maxit_inner"] = case.maxit_inner
         d["inner_counts"] = sol.inner_counts
+    if spec["kind"] == "mixed":
+        d.update(max_refine=3, refine_steps=sol.refine_steps, refine_iters=sol.refine_iters,
+                 relres_true=sol.relres_true, true_history=sol.true_history)
+    np.save(path(name, "npy"), scatterer_values(g, sol.E_tot), allow_pickle=False)
     return d
+
+
+def spread() -> dict:
+    fields, meta = {}, {}
+    for name in RUNS:
+        if os.path.exists(path(name, "npy")) and os.path.exists(path(name, "json")):
+            fields[name] = np.load(path(name, "npy"), allow_pickle=False)
+            meta[name] = json.load(open(path(name, "json")))
+    out = {"case": CASE, "script": "tests/golden/make_goldens.py spread",
+           "outer_iters": {k: v["outer_iters"] for k, v in meta.items()},
+           "refine_steps": {k: v.get("refine_steps", 0) for k, v in meta.items()},
+           "rel_field_diff": {}}
+    names = sorted(fields)
+    for a in names:
+        for b in names:
+            if a < b:
+                out["rel_field_diff"][f"{a}|{b}"] = float(np.linalg.norm(fields[a] - fields[b]) /
+                                                          np.linalg.norm(fields[b]))
+    return out
 
 
 if __name__ == "__main__":
     args = sys.argv[1:]
-    tight = "--tight" in args
-    names = [a for a in args if not a.startswith("--")]
-    with scipy.fft.set_workers(os.cpu_count() or 1):   # independent transforms, same results
-        for name in names:
-            d = golden(name, tight)
-            path = os.path.join(HERE, f"oracle_{name}{'_tight' if tight else ''}.json")
-            with open(path, "w") as f:
-                json.dump(d, f, separators=(",", ":"))
-            print(name, d["outer_iters"], d["status"], f"{d['oracle_seconds']:.0f}s", flush=True)
+    workers = 1
+    if "--workers" in args:
+        i = args.index("--workers")
+        workers = int(args[i + 1])
+        del args[i:i + 2]
+    for name in args:
+        if name == "spread":
+            d = spread()
+            with open(os.path.join(HERE, f"oracle_{CASE}_spread.json"), "w") as f:
+                json.dump(d, f, indent=1)
+            print(json.dumps(d, indent=1), flush=True)
+            continue
+        with scipy.fft.set_workers(workers):
+            d = run(name)
+        with open(path(name, "json"), "w") as f:
+            json.dump(d, f, separators=(",", ":"))
+        print(name, d["outer_iters"], d["status"], d.get("refine_steps", ""), f"{d['oracle_seconds']:.0f}s",
+              flush=True)

@@ -9,6 +9,11 @@
 * Special cases of the block preconditioner: one block solved exactly gives
   convergence in one outer step; single-voxel blocks reduce to the explicit
   3x3 block-Jacobi inverse; every partition reaches the same solution.
+* Mixed precision with refinement: complex64 products alone stall at the
+  single-precision level of the true residual; the FP64 residual and the
+  corrections carry the iterate to the dense LU solution at the requested
+  tolerance; the reported true residual is that of the dense matrix; no
+  correction means the plain complex64 run.
 """
 import numpy as np
 import pytest
@@ -69,6 +74,56 @@ def test_converged_bicgstab_matches_dense_lu(seed, shape):
     sp = krylov.solve(g, e, 1e-13, 2000, case.block_id, case.n_blocks, 1e-6, 500)
     assert sp.info.status == "converged"
     assert np.linalg.norm(sp.P - Pd) <= 1e-10 * np.linalg.norm(Pd)
+
+
+@pytest.mark.parametrize("seed,shape,precondition", [(41, (3, 4, 5), True), (44, (5, 4, 6), False),
+                                                     (45, (4, 4, 4), True)])
+def test_mixed_refinement_reaches_dense_lu(seed, shape, precondition):
+    """The complex64 main loop ends (converged on its recursive residual, or
+    at its cap: inexact complex64 inner solves vary from step to step) with a
+    true (FP64) residual at the single-precision level (> 1e-8 here); with
+    refinement the true residual meets 1e-11 and the iterate is the dense LU
+    solution to 1e-9.  Refining with the complex64 product instead of the
+    FP64 one could not get below the single-precision level, and a
+    correction of the wrong sign would diverge."""
+    case, g, e = _problem(seed, shape)
+    Pd = krylov.solve_dense(g, e)
+    blocks = (case.block_id, case.n_blocks) if precondition else (None, 0)
+    # inner solves tight: with inexact ones (1e-2, 1e-3) BiCGSTAB stalls on
+    # these random partitions in FP64 as well (the preconditioner varies)
+    s = krylov.solve_mixed(g, e, 1e-11, 400, blocks[0], blocks[1], 1e-6, 500, max_refine=3)
+    assert s.info.status in ("converged", "not_converged")
+    assert s.true_history[0] > 1e-8
+    assert 1 <= s.refine_steps <= 3 and s.relres_true <= 1e-11
+    assert np.linalg.norm(s.P - Pd) <= 1e-9 * np.linalg.norm(Pd)
+    # the reported true residual is that of the assembled matrix
+    Z, idx = op.dense_matrix(g)
+    b = op.to_support(g, e * g.mask, idx)
+    dense = np.linalg.norm(b - Z @ op.to_support(g, s.P, idx)) / np.linalg.norm(b)
+    assert abs(dense - s.relres_true) <= 1e-3 * s.relres_true + 1e-15
+    # every correction at least halves the true residual (its tolerance is
+    # min(0.5, tol / relres), plus single-precision product error)
+    for a, b_ in zip(s.true_history, s.true_history[1:]):
+        assert b_ <= 0.6 * a
+
+
+def test_mixed_without_refinement_is_the_complex64_loop():
+    case, g, e = _problem(46, (4, 3, 5))
+    s = krylov.solve_mixed(g, e, 1e-9, 300, case.block_id, case.n_blocks, 1e-3, 200, max_refine=0)
+    p = krylov.solve(g, e, 1e-9, 300, case.block_id, case.n_blocks, 1e-3, 200, product="c64")
+    assert s.refine_steps == 0 and s.info.iterations == p.info.iterations
+    assert np.array_equal(s.P, p.P)
+    assert s.inner_counts == p.inner_counts
+
+
+def test_mixed_refinement_stops_at_tolerance_and_cap():
+    """No correction when the main loop's true residual already meets the
+    tolerance; at most max_refine corrections otherwise."""
+    case, g, e = _problem(47, (4, 4, 3))
+    loose = krylov.solve_mixed(g, e, 1e-4, 500, max_refine=3)
+    assert loose.refine_steps == 0 and loose.true_history[0] <= 1e-4
+    capped = krylov.solve_mixed(g, e, 1e-15, 500, max_refine=1)
+    assert capped.refine_steps == 1 and len(capped.true_history) == 2
 
 
 def test_single_exact_block_converges_in_one_step():
