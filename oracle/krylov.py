@@ -47,12 +47,16 @@ class KrylovInfo:
 
 
 def _dot(a, b) -> complex:
-    """<a, b> = sum conj(a) b."""
-    return complex(np.vdot(a.ravel(), b.ravel()))
+    """<a, b> = sum conj(a) b, summed by numpy's pairwise summation in a fixed
+    order (a BLAS dot product may split the sum over threads, which makes the
+    rounding, and so the iterates, depend on the machine's core count)."""
+    return complex(np.sum(np.conj(a.ravel()) * b.ravel()))
 
 
 def _norm(a) -> float:
-    return float(np.linalg.norm(a.ravel()))
+    """2-norm with the same fixed-order summation as ``_dot``."""
+    v = a.ravel()
+    return float(np.sqrt(np.sum(v.real * v.real + v.imag * v.imag)))
 
 
 def bicgstab(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, tol: float,

@@ -210,6 +210,40 @@ def test_cube_mixed_precision(vie_ctx, cube_oracle, flags):
     assert st.relres_true <= case.tol_outer
 
 
+@pytest.mark.parametrize("name,tol", [("cube16", 1e-9), ("tiny44", 1e-11), ("tiny53", 1e-10)])
+def test_mixed_refinement_matches_oracle(vie_ctx, name, tol):
+    """Mixed mode's refinement (complex64 main loop, FP64 residual, correction
+    solves) against the oracle's ``solve_mixed`` on the same input, without
+    the block preconditioner: the main loop's true residual is at the
+    single-precision level, both reach the tolerance on the FP64 true
+    residual, and the refined fields agree with each other and with the FP64
+    solution far below the mixed bar (1e-8: both are converged to tol).  A
+    correction ends just under its target, so whether a second one is needed
+    is decided by rounding: oracle runs that differ only in rounding (pad 0,
+    2, 4) take 1 or 2 on these inputs.  The GPU's correction count lies in
+    that spread.  Without preconditioner the complex64 main loop runs over a
+    hundred steps and its count spreads widely with rounding alone (113 to
+    125 on the cube for five embedding lengths): the GPU's count must lie in
+    that spread widened by half its width on each side (at least 2)."""
+    case = W.cube16() if name == "cube16" else W.random_tiny(int(name[4:]), (7, 6, 5), fill=0.8, n_blocks=2)
+    g = op.Grid.from_case(case)
+    e = physics.plane_wave(g)
+    refs = [krylov.solve_mixed(g, e, tol, 2000, max_refine=3, pad=pad) for pad in (0, 2, 4, 6, 8)]
+    ref64 = krylov.solve(g, e, 1e-13, 4000)
+    code, e_tot, P, st, _ = _solve(vie_ctx, case, prec=V.VIE_MIXED, precondition=False, tol=tol, maxit=2000)
+    assert code == V.VIE_OK
+    o = refs[0]
+    assert o.refine_steps >= 1 and o.true_history[0] > 10 * tol
+    rsteps = [r.refine_steps for r in refs]
+    assert min(rsteps) <= st.refine_steps <= max(rsteps), (st.refine_steps, rsteps)
+    counts = [r.info.iterations for r in refs]
+    w = max(2, (max(counts) - min(counts) + 1) // 2)
+    assert min(counts) - w <= st.outer_iters <= max(counts) + w, (st.outer_iters, counts)
+    assert st.relres_true <= tol and o.relres_true <= tol
+    assert _rel(e_tot, o.E_tot) <= 1e-8
+    assert _rel(e_tot, ref64.E_tot) <= 1e-8
+
+
 @pytest.mark.parametrize("seed,shape,nb", [(41, (3, 4, 5), 2), (42, (5, 5, 5), 3), (43, (2, 6, 3), 2),
                                            (44, (7, 6, 5), 4), (45, (8, 8, 8), 3)])
 def test_random_tiny_vs_dense_lu(vie_ctx, seed, shape, nb):
@@ -284,7 +318,12 @@ def test_nan_incident_field_rejected(vie_ctx):
 def test_graph_replays_match_eager_launches(vie_ctx):
     """The captured inner iteration is replayed once per inner step, with
     eager kernels, copies and host waits in between; every replay must give
-    what the same kernels launched one by one give (bitwise)."""
+    what the same kernels launched one by one give (bitwise).  The solve is
+    capped at 25 outer steps and may end not converged: on this random
+    partition (blocks interleaved voxel by voxel) the block-preconditioned
+    BiCGSTAB with inner tolerance 1e-2 does not converge in the oracle
+    either (relative residual 4.6 after 40 steps), and the comparison only
+    needs identical launches, not a converged result."""
     case = W.random_tiny(56, (10, 9, 8), fill=0.8, n_blocks=4)
     P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
     try:
