@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 10
+#define VIE_ABI_VERSION 11
 
 typedef enum {
   VIE_OK = 0,
@@ -174,6 +174,15 @@ typedef struct {
   float zpass_tune_ms[2][5];  /* autotuner time per z-pass variant (3 runs; -1 = not timed) */
 } vie_problem_info;
 
+/* One shape group of a block plan: blocks whose bounding boxes share FFT
+ * lengths, solved together (eqs. (10)-(11): every block's inner solve). */
+typedef struct {
+  int32_t lx, ly, lz;      /* circulant FFT lengths of the group's boxes */
+  int32_t bx, by, bz;      /* the group's box (largest block bounding box) */
+  int32_t n_systems;       /* blocks in the group */
+  int32_t one_workgroup;   /* 1: solved by the one-workgroup block solver */
+} vie_group_plan;
+
 /* ABI version (VIE_ABI_VERSION). */
 int32_t vie_abi_version(void);
 
@@ -223,6 +232,18 @@ vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info);
  * problem is in flight.  Errors: VIE_EINVAL for a bad precision or
  * variant. */
 vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t variant);
+
+/* The block plan that vie_problem_create_overlap would build for these
+ * inputs (same arguments and validation; overlap 0 = vie_problem_create),
+ * computed on the host with no device or context: info receives the full
+ * grid's FFT lengths, the non-empty block count, the shape groups, the
+ * groups run by the one-workgroup solver and footprint_bytes, the device
+ * memory the problem would hold with none of its spectra cached
+ * (zpass_variant = -1, zpass_tune_ms = -1).  groups (optional, caller-owned)
+ * receives up to groups_cap entries in the library's group order (batched
+ * groups first).  VIE_EINVAL as vie_problem_create. */
+vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* block_id, int32_t n_blocks,
+                    int32_t overlap, vie_problem_info* info, vie_group_plan* groups, int32_t groups_cap);
 
 /* Incident plane wave E_inc = pol * exp(-j k0 khat . r) at every voxel centre
  * (Sec. III: x-polarised wave along z).  kdir: unit vector (|kdir| = 1 within
@@ -338,7 +359,10 @@ vie_status vie_server_start(vie_context* ctx, int32_t slots, int32_t queue_cap);
 
 /* Device bytes a problem with these inputs would hold (vie_problem_create's
  * arguments; spectra already cached in ctx are not counted), plus the
- * transient set-up memory of spectra not yet cached. */
+ * transient set-up memory of spectra not yet cached.  vie_submit reserves
+ * more for a request: every spectrum and its set-up memory whether cached or
+ * not (the cache shares spectra only while a problem holds them), plus the
+ * request's incident and result vectors on the device. */
 vie_status vie_footprint(vie_context* ctx, const vie_grid* grid, const double* eps_r, const int32_t* block_id,
                          int32_t n_blocks, size_t* bytes);
 

@@ -65,7 +65,12 @@ struct KBatch;
 // first and last passes.  Pass 1 input (in_mode):
 //   0: x (masked if mask_input);
 //   1: p = r + beta (p - omega v) (p = r on the first step), written to p;
-//   2: s = r - alpha v, written to p (the s vector), partials of ||s||^2.
+//   2: s = r - alpha v, written to p (the s vector), partials of ||s||^2;
+//   3: as 2 with alpha = rho / <rhat, v> formed in the kernel from the
+//      partials of the system's previous product (out_mode 1) and no
+//      partials written: every workgroup sums them in the same order, the
+//      system's first workgroup counts the step and records alpha, or the
+//      breakdown when <rhat, v> = 0 (the scalar step of FIN_ALPHA, fused).
 // Pass 5 (out_mode), after writing y = A x:
 //   0: nothing; 1: partials of <rhat, y>; 2: partials of <y, s>, <y, y>;
 //   3: y = rhat + sum T x at every voxel (rhat = E_inc: the total field of
@@ -119,7 +124,8 @@ struct KState {
   double snorm;     // ||s|| / ||b|| after the last half step
   double tol;
   int iters, maxit;
-  int pad0, pad1;
+  int pending;      // fused step: outcome of the half step for k_step_end (0, ST_HALF or ST_BREAKDOWN)
+  int pad1;
 };
 
 // A batch of `nsys` systems with vectors of `n` c128 each (contiguous,
@@ -132,6 +138,8 @@ struct KBatch {
   double* partials;   // per system `pstride` doubles (>= 4 * partial count)
   int64_t pstride;
   int* ntile;         // per system: partial count written by the last producer
+  double* partials2;  // second buffer, same layout: written by k_update_xr_fused while
+                      // the first one is still read by that kernel
 };
 
 // Inner block solves with one workgroup per system (Sec. II-B): the whole
@@ -224,6 +232,21 @@ void k_update_s(const KBatch& k, const c128* r, const c128* v, c128* sv, hipStre
 // (then FIN_XR); after a half-step convergence, x += alpha y only.
 void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv, const c128* t,
                  const c128* rhat, hipStream_t s);
+// The end of a BiCGSTAB step with the scalar work fused into the kernels
+// (unpreconditioned systems, y = p and z = s), after the second product's
+// pass 5 (out_mode 4: partials of <t, s>, <t, t>, ||s||^2):
+// k_update_xr_fused forms ||s|| and omega in every workgroup from those
+// partials (same fixed order); on the half step (||s|| <= tol ||b||) x +=
+// alpha y only, on <t, t> = 0 nothing, else x += alpha y + omega z and
+// r = s - omega t with the partials of <rhat, r>, ||r||^2 in partials2.  The
+// system's first workgroup records ||s||, omega and the outcome in
+// KState.pending.  k_step_end then finishes every system of the batch in one
+// workgroup: a pending half step or breakdown is applied, otherwise the
+// scalar step of FIN_XR from partials2; with count_out it also stores the
+// number of systems still ACTIVE there (may be host-mapped memory).
+void k_update_xr_fused(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv,
+                       const c128* t, const c128* rhat, hipStream_t s);
+void k_step_end(const KBatch& k, int* count_out, hipStream_t s);
 // Conjugate gradient squared (solver variant), per system, skipped unless
 // ACTIVE:
 // u = r, p = r (first step) or u = r + beta q, p = u + beta (q + beta p)

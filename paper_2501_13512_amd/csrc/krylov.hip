@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(KT) kk_finalize(KBatch k, int kind, const int*
       st.tol = tol;
       st.iters = 0;
       st.maxit = maxit;
+      st.pending = 0;
       k.status[sys] = nb > 0.0 ? ST_ACTIVE : ST_CONVERGED;
     }
     return;
@@ -281,6 +282,207 @@ void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r
   const int64_t chunks = chunks_of(k.n);
   hipLaunchKernelGGL(kk_update_xr, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, y, z, r, sv, t, rhat);
   check_launch("krylov xr");
+}
+
+// ---------------------------------------------------------------- fused step end
+// The half-step test and omega (FIN_SOMEGA) formed in every workgroup of the
+// x, r update from the second product's partials; r's partials go to the
+// second buffer (the first is still being read by other workgroups).
+__global__ void __launch_bounds__(KT) kk_update_xr_fused(KBatch k, c128* x, const c128* y, const c128* z, c128* r,
+                                                         const c128* sv, const c128* t, const c128* rhat) {
+  const int64_t n = k.n;
+  KRYLOV_INDEX
+  if (k.status[sys] != ST_ACTIVE) return;
+  constexpr int HE = KEPT / 2;
+  c128 xv[HE], yv[HE], zv[HE], sw[HE], tv[HE], hv[HE];
+  // the loads of the first half are in flight while the partials are summed
+  auto load = [&](int h) {
+#pragma unroll
+    for (int j = 0; j < HE; ++j) {
+      const int64_t i = i0 + (int64_t)(h * HE + j) * KT;
+      if (i < n) {
+        xv[j] = x[base + i];
+        yv[j] = y[base + i];
+        zv[j] = z[base + i];
+        sw[j] = sv[base + i];
+        tv[j] = t[base + i];
+        hv[j] = rhat[base + i];
+      }
+    }
+  };
+  load(0);
+  double v[4];   // <t, s> (re, im), <t, t>, ||s||^2
+  final_sum_all<4>(k.partials, k.pstride, k.ntile, sys, v);
+  KState& st = k.st[sys];
+  const bool owner = chunk == 0 && threadIdx.x == 0;
+  const double snorm = sqrt(v[3]) / st.nb;
+  const c128 alpha = st.alpha;
+  if (snorm <= st.tol) {   // converged at the half step: x += alpha y
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) load(1);
+#pragma unroll
+      for (int j = 0; j < HE; ++j) {
+        const int64_t i = i0 + (int64_t)(h * HE + j) * KT;
+        if (i < n) x[base + i] = xv[j] + alpha * yv[j];
+      }
+    }
+    if (owner) {
+      st.snorm = snorm;
+      st.pending = ST_HALF;
+    }
+    return;
+  }
+  if (v[2] == 0.0) {   // <t, t> = 0: breakdown, x and r stay
+    if (owner) {
+      st.snorm = snorm;
+      st.pending = ST_BREAKDOWN;
+    }
+    return;
+  }
+  const c128 omega = mk<double>(v[0] / v[2], v[1] / v[2]);
+  if (owner) {
+    st.snorm = snorm;
+    st.omega = omega;
+    st.pending = 0;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h) load(1);
+#pragma unroll
+    for (int j = 0; j < HE; ++j) {
+      const int64_t i = i0 + (int64_t)(h * HE + j) * KT;
+      if (i < n) {
+        x[base + i] = xv[j] + alpha * yv[j] + omega * zv[j];
+        const c128 rv = sw[j] - omega * tv[j];
+        r[base + i] = rv;
+        const c128 d = cdot1(hv[j], rv);
+        acc[0] += d.x;
+        acc[1] += d.y;
+        acc[2] += abs2(rv);
+      }
+    }
+  }
+  write_partial_at<3>(acc, k.partials2, k.pstride, sys, chunk);
+}
+
+void k_update_xr_fused(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r, const c128* sv,
+                       const c128* t, const c128* rhat, hipStream_t s) {
+  if (!k.partials2) throw std::runtime_error("fused x, r update: no second partial buffer");
+  const int64_t chunks = chunks_of(k.n);
+  hipLaunchKernelGGL(kk_update_xr_fused, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, y, z, r, sv, t,
+                     rhat);
+  check_launch("krylov xr (fused)");
+}
+
+// One workgroup finishes the step of every system: pending half-step or
+// breakdown outcomes, else FIN_XR from the second partial buffer
+// (chunks_of(n) partials per system, summed in a fixed order), then the
+// number of systems still ACTIVE.  Short partial lists (the block systems):
+// one thread per system, all systems at once, the partials loaded eight at a
+// time and added in order; long ones (full grids): one wavefront per system,
+// the partials split over its lanes.
+constexpr int kStepEndThreadChunks = 32;
+
+__device__ __forceinline__ void step_end_one(KBatch& k, int sys, const double* v) {
+  KState& st = k.st[sys];
+  int status = ST_ACTIVE;
+  fin_xr(st, &status, v);
+  k.status[sys] = status;
+}
+
+__global__ void __launch_bounds__(KT) kk_step_end(KBatch k, int* count_out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = KT / 64;
+  const int64_t chunks = chunks_of(k.n);
+  if (chunks <= kStepEndThreadChunks) {
+    for (int sys = threadIdx.x; sys < k.nsys; sys += KT) {
+      if (k.status[sys] != ST_ACTIVE) continue;
+      KState& st = k.st[sys];
+      const int pend = st.pending;
+      if (pend != 0) {
+        if (pend == ST_HALF) {
+          st.rnorm = st.snorm;
+          k.status[sys] = ST_CONVERGED;
+        } else {
+          k.status[sys] = ST_BREAKDOWN;
+        }
+        st.pending = 0;
+        continue;
+      }
+      const double* p = k.partials2 + sys * k.pstride;
+      double v[3] = {0.0, 0.0, 0.0};
+      for (int64_t c0 = 0; c0 < chunks; c0 += 8) {
+        double q[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (c0 + u < chunks)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) q[u][e] = p[(c0 + u) * NPART + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (c0 + u < chunks)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[e] += q[u][e];
+      }
+      step_end_one(k, sys, v);
+    }
+  } else {
+  for (int sys = wave; sys < k.nsys; sys += NW) {
+    if (k.status[sys] != ST_ACTIVE) continue;   // uniform in the wavefront
+    KState& st = k.st[sys];
+    const int pend = st.pending;
+    if (pend != 0) {
+      if (lane == 0) {
+        if (pend == ST_HALF) {
+          st.rnorm = st.snorm;
+          k.status[sys] = ST_CONVERGED;
+        } else {
+          k.status[sys] = ST_BREAKDOWN;
+        }
+        st.pending = 0;
+      }
+      continue;
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t c = lane; c < chunks; c += 64) {
+      const double* p = k.partials2 + sys * k.pstride + c * NPART;
+      v[0] += p[0];
+      v[1] += p[1];
+      v[2] += p[2];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double o = __shfl_down(v[q], off, 64);
+        if (lane + off < 64) v[q] += o;
+      }
+    if (lane == 0) step_end_one(k, sys, v);
+  }
+  }
+  if (!count_out) return;
+  __syncthreads();
+  int act = 0;
+  for (int sys = threadIdx.x; sys < k.nsys; sys += KT) act += k.status[sys] == ST_ACTIVE ? 1 : 0;
+  __shared__ int cnt[NW];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) act += __shfl_down(act, off, 64);
+  if (lane == 0) cnt[wave] = act;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int total = 0;
+    for (int w = 0; w < NW; ++w) total += cnt[w];
+    *count_out = total;
+  }
+}
+
+void k_step_end(const KBatch& k, int* count_out, hipStream_t s) {
+  if (k.nsys <= 0) return;
+  if (!k.partials2) throw std::runtime_error("step end: no second partial buffer");
+  hipLaunchKernelGGL(kk_step_end, dim3(1), dim3(KT), 0, s, k, count_out);
+  check_launch("krylov step end");
 }
 
 // ---------------------------------------------------------------- CGS

@@ -72,11 +72,61 @@ __device__ __forceinline__ void final_sum(const double* partials, int64_t pstrid
   block_sum<NV>(v);
 }
 
+// As write_partial, without recording the partial count (a consumer in the
+// same kernel may still read the count of another buffer).
+template <int NV>
+__device__ __forceinline__ void write_partial_at(double (&v)[NV], double* partials, int64_t pstride, int sys,
+                                                 int64_t tile) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0) {
+    double* p = partials + sys * pstride + tile * NPART;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) p[k] = v[k];
+  }
+}
+
+// final_sum broadcast to every thread of the workgroup (all threads call).
+template <int NV>
+__device__ __forceinline__ void final_sum_all(const double* partials, int64_t pstride, const int* ntile, int sys,
+                                              double (&v)[NV]) {
+  __shared__ double bc[NV];
+  final_sum<NV>(partials, pstride, ntile, sys, v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) bc[k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = bc[k];
+  __syncthreads();
+}
+
 __device__ __forceinline__ c128 cdiv(c128 a, c128 b) {
   const double s = fabs(b.x) + fabs(b.y);
   const double br = b.x / s, bi = b.y / s, ar = a.x / s, ai = a.y / s;
   const double d = br * br + bi * bi;
   return mk<double>((ar * br + ai * bi) / d, (ai * br - ar * bi) / d);
+}
+
+// alpha = rho / <rhat, v> inside a product's first pass (in_mode 3): every
+// workgroup of the system sums the <rhat, v> partials of the previous
+// product in the same order; the owner (the system's first workgroup) counts
+// the step and records alpha, or the breakdown.  All threads call; returns
+// false on breakdown (<rhat, v> = 0).
+__device__ __forceinline__ bool fused_alpha(const KBatch& k, int sys, bool owner, c128* alpha) {
+  double v[2];
+  final_sum_all<2>(k.partials, k.pstride, k.ntile, sys, v);
+  KState& st = k.st[sys];
+  const c128 den = mk<double>(v[0], v[1]);
+  const bool ok = !(den.x == 0.0 && den.y == 0.0);
+  *alpha = ok ? cdiv(st.rho, den) : mk<double>(0.0, 0.0);
+  if (owner && threadIdx.x == 0) {
+    st.iters += 1;
+    if (ok)
+      st.alpha = *alpha;
+    else
+      k.status[sys] = ST_BREAKDOWN;
+  }
+  return ok;
 }
 
 // ---- scalar steps (thread 0 of the finishing workgroup) ----

@@ -21,6 +21,7 @@
 #include <stdexcept>
 #include <string>
 
+#include "api_lock.h"
 #include "fft_core.h"
 #include "krylov_dev.h"
 
@@ -133,14 +134,11 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_fwd(Ro
   }
   const KState& ks = a.k.st[sys];
   const bool first = mode == 1 && ks.iters == 0;
-  const c128 c1 = mode == 1 ? ks.beta : ks.alpha;
-  const c128 c2 = ks.omega;
   double acc = 0.0;
   constexpr int E = (L + T - 1) / T;   // elements per thread
   constexpr int CH = 4;                // elements per load batch
-#pragma unroll
-  for (int j0 = 0; j0 < E; j0 += CH) {
-    c128 rv[CH], pv[CH], vv[CH];
+  c128 rv[CH], pv[CH], vv[CH];
+  auto load = [&](int j0) {
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int n = t + (j0 + u) * T;
@@ -150,6 +148,18 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_fwd(Ro
         if (mode == 1 && !first) pv[u] = a.p[vrow + n];
       }
     }
+  };
+  load(0);   // in flight while alpha is formed
+  c128 c1;
+  if (mode == 3) {   // alpha from the last product's partials (FIN_ALPHA fused)
+    if (!fused_alpha(a.k, sys, tile == 0, &c1)) return;
+  } else {
+    c1 = mode == 1 ? ks.beta : ks.alpha;
+  }
+  const c128 c2 = ks.omega;
+#pragma unroll
+  for (int j0 = 0; j0 < E; j0 += CH) {
+    if (j0 > 0) load(j0);
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int n = t + (j0 + u) * T;
@@ -321,11 +331,9 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_fwd(RowArgs<R> a
   } else {
     const KState& ks = a.k.st[sys];
     const bool first = mode == 1 && ks.iters == 0;
-    const c128 c1 = mode == 1 ? ks.beta : ks.alpha;
-    const c128 c2 = ks.omega;
     constexpr int CH = 4;
-    for (int e0 = 0; e0 < ne; e0 += CH * BT) {
-      c128 rv[CH], pv[CH], vv[CH];
+    c128 rv[CH], pv[CH], vv[CH];
+    auto load = [&](int e0) {
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int e = e0 + u * BT + (int)threadIdx.x;
@@ -335,6 +343,17 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_fwd(RowArgs<R> a
           if (mode == 1 && !first) pv[u] = a.p[v0 + e];
         }
       }
+    };
+    load(0);   // in flight while alpha is formed
+    c128 c1;
+    if (mode == 3) {   // alpha from the last product's partials (FIN_ALPHA fused)
+      if (!fused_alpha(a.k, sys, tile == 0, &c1)) return;
+    } else {
+      c1 = mode == 1 ? ks.beta : ks.alpha;
+    }
+    const c128 c2 = ks.omega;
+    for (int e0 = 0; e0 < ne; e0 += CH * BT) {
+      if (e0 > 0) load(e0);
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int e = e0 + u * BT + (int)threadIdx.x;
@@ -1149,9 +1168,12 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out) {
   if (ms_out)
     for (int v = 0; v < kZPassVariants; ++v) ms_out[v] = -1.0f;
   if (b.nsys <= 0) return 0;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    throw std::runtime_error("hipEventCreate failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  {
+    ApiShared api;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      throw std::runtime_error("hipEventCreate failed");
+  }
   float best = 1e30f;
   int best_v = 0;
   for (int v = 0; v < kZVariants; ++v) {
@@ -1180,8 +1202,11 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out) {
       best_v = v;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  {
+    ApiShared api;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   return best_v;
 }
 template int tune_zpass<float>(const MvmBatch<float>&, hipStream_t, float*);

@@ -16,12 +16,14 @@
 #include <memory>
 #include <mutex>
 #include <set>
+#include <shared_mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
 #include <tuple>
 #include <vector>
 
+#include "api_lock.h"
 #include "kernels.h"
 #include "vie.h"
 
@@ -29,9 +31,26 @@ using vie::KBatch;
 using vie::KState;
 using vie::MvmBatch;
 
+namespace vie {
+// Graph capture takes this exclusively; allocation, frees, stream and event
+// creation or destruction and device-wide synchronisation take it shared.
+// HIP refuses such calls while any thread captures, so with concurrent
+// solves (the request server's slots) they must not overlap a capture.
+std::shared_mutex& api_mutex() {
+  static std::shared_mutex m;
+  return m;
+}
+}  // namespace vie
+
 namespace {
 
+using ApiShared = vie::ApiShared;
+
 thread_local std::string g_last_error;
+// Device bytes whose hipFree failed (kept counted against every budget), and
+// whether a free failed on this thread since the flag was last cleared.
+std::atomic<size_t> g_unfreed_bytes{0};
+thread_local bool t_free_failed = false;
 std::string vie_last_error_str() { return g_last_error; }
 
 struct VieError : std::runtime_error {
@@ -57,7 +76,12 @@ struct DevBuf {
   void alloc(size_t n) {
     reset();
     if (n == 0) return;
-    hip_check(hipMalloc(&p, n), "hipMalloc");
+    hipError_t e;
+    {
+      ApiShared api;
+      e = hipMalloc(&p, n);
+    }
+    hip_check(e, "hipMalloc");
     bytes = n;
   }
   // Stream-ordered: work on `s` sees the zeros (the null stream is not
@@ -66,8 +90,21 @@ struct DevBuf {
     if (p) hip_check(hipMemsetAsync(p, 0, bytes, s), "hipMemsetAsync");
   }
   void reset() {
-    // a failed free must not leave its error for the next launch check
-    if (p && hipFree(p) != hipSuccess) (void)hipGetLastError();
+    if (p) {
+      hipError_t e;
+      {
+        ApiShared api;
+        e = hipFree(p);
+      }
+      if (e != hipSuccess) {
+        // the memory stays held: keep it counted against every budget, flag
+        // the failure for the caller, and clear the error so that it is not
+        // reported by the next unrelated launch check
+        (void)hipGetLastError();
+        g_unfreed_bytes += bytes;
+        t_free_failed = true;
+      }
+    }
     p = nullptr;
     bytes = 0;
   }
@@ -230,14 +267,17 @@ struct Group {
   int slot0;     // first entry in the problem's inner status/state arrays
   bool wg = false;  // small enough for the one-workgroup block solver
   std::vector<int> blocks;
+  // the group's inner BiCGSTAB step captured as a HIP graph, per precision
+  // ([0] FP64, [1] FP32); replayed until the group's systems have converged
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
-// Streams on which the per-batch chains of a step run in parallel (graph
-// capture only): fork from `s` on `fork`, join back before the next launch on
-// `s`.  With no branch streams everything runs on `s` in order.
+// Streams on which the groups of blocks iterate side by side during a
+// preconditioner application (one per group when there are several), with
+// the events that fork them from and join them back to the solve's stream.
 struct Branches {
-  std::vector<hipStream_t> streams;   // one per batch, or empty
-  std::vector<hipEvent_t> events;     // 1 + batches per phase, 4 phases
+  std::vector<hipStream_t> streams;   // one per group, or empty
+  std::vector<hipEvent_t> events;     // [0] fork, [1 + g] join of group g
 };
 
 }  // namespace
@@ -279,12 +319,12 @@ struct vie_problem {
   int lx = 0, ly = 0, lz = 0;
   double k0 = 0;
   std::shared_ptr<Spectra> spec;
-  DevBuf chi, work, vecs, partials, ntile, ostate, ostatus, scal;
+  DevBuf chi, work, vecs, partials, partials2, ntile, ostate, ostatus, scal;
   int64_t pstride = 0;
   int zvar[2] = {0, 0};
   float ztune_ms[2][vie::kZPassVariants] = {};
   // inner systems of all groups: partials (per-system stride ipstride)
-  DevBuf d_ipartials, d_intile;
+  DevBuf d_ipartials, d_ipartials2, d_intile;
   int64_t ipstride = 0;
   c128* vec[V_COUNT] = {};
   // blocks
@@ -299,14 +339,12 @@ struct vie_problem {
   int n_batched_wg = 0, n_wg_groups = 0;
   std::vector<hipStream_t> wg_streams;   // one per block-solver group
   std::vector<hipEvent_t> wg_events;     // [0] fork, [1 + i] join of group i
-  // captured inner BiCGSTAB iteration of the batched groups
-  // [precision: 0 FP64, 1 FP32][block solver on]
-  hipGraphExec_t inner_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  Branches branches;   // per-group capture streams (parallel graph branches)
-  // polling: ring 0 for the outer loop, ring 1 for the inner loops
+  Branches branches;   // per-group streams of the inner iterations
+  // polling: ring 0 for the outer loop, ring 1 + g for the inner steps of
+  // group g
   int* h_ring = nullptr;
   int* d_ring = nullptr;   // the device's address of h_ring (null: progress values are copied)
-  hipEvent_t ev[2][kRing] = {};
+  std::vector<std::array<hipEvent_t, kRing>> ev;
   std::mutex mu;
   size_t footprint = 0;
   const std::atomic<bool>* cancel = nullptr;   // set by the server: stop after the current outer step
@@ -318,7 +356,7 @@ struct vie_problem {
   // batched right-hand sides (plain BiCGSTAB), allocated by the first batch
   // solve: kBatchVecs vectors, one FFT work buffer and the Krylov scalars per
   // right-hand side
-  DevBuf mr_vecs, mr_work, mr_state, mr_status, mr_partials, mr_ntile, mr_count;
+  DevBuf mr_vecs, mr_work, mr_state, mr_status, mr_partials, mr_partials2, mr_ntile, mr_count;
   int mr_cap = 0;
   // host plan (kept for batches) and, for preconditioned batches, the blocks
   // of nrhs copies of the problem stacked along z (inner solves only)
@@ -329,8 +367,9 @@ struct vie_problem {
   size_t replica_bytes = 0;
 
   ~vie_problem() {
-    for (auto& gp : inner_graph)
-      for (auto g : gp)
+    ApiShared api;
+    for (auto& G : groups)
+      for (auto g : G.graph)
         if (g) (void)hipGraphExecDestroy(g);
     for (auto b : wg_streams) (void)hipStreamDestroy(b);
     for (auto e : wg_events) (void)hipEventDestroy(e);
@@ -356,6 +395,20 @@ struct Poller {
     const int slot = (int)(n % kRing);
     hip_check(hipMemcpyAsync(&P.h_ring[ring * kRing + slot], dval, sizeof(int), hipMemcpyDeviceToHost, s),
               "poll copy");
+    hip_check(hipEventRecord(P.ev[ring][slot], s), "poll event");
+    return n++;
+  }
+  // The end of a fused BiCGSTAB step of the batch k (k_step_end), with the
+  // number of systems still ACTIVE as the next value (stored straight into
+  // the pinned ring, or into this ring's device counter and copied).
+  long push_step_end(const KBatch& k) {
+    if (!P.d_ring) {
+      int* dc = P.d_count.as<int>() + ring;
+      vie::k_step_end(k, dc, s);
+      return push(dc);
+    }
+    const int slot = (int)(n % kRing);
+    vie::k_step_end(k, P.d_ring + ring * kRing + slot, s);
     hip_check(hipEventRecord(P.ev[ring][slot], s), "poll event");
     return n++;
   }
@@ -466,6 +519,7 @@ KBatch outer_kbatch(vie_problem& P) {
   k.partials = P.partials.as<double>();
   k.pstride = P.pstride;
   k.ntile = P.ntile.as<int>();
+  k.partials2 = P.partials2.as<double>();
   return k;
 }
 
@@ -479,6 +533,7 @@ KBatch group_kbatch(vie_problem& P, Group& G) {
   k.partials = P.d_ipartials.as<double>() + (int64_t)G.slot0 * P.ipstride;
   k.pstride = P.ipstride;
   k.ntile = P.d_intile.as<int>() + G.slot0;
+  k.partials2 = P.d_ipartials2.as<double>() + (int64_t)G.slot0 * P.ipstride;
   return k;
 }
 
@@ -492,6 +547,7 @@ KBatch inner_all(vie_problem& P, int nsys) {
   k.partials = P.d_ipartials.as<double>();
   k.pstride = P.ipstride;
   k.ntile = P.d_intile.as<int>();
+  k.partials2 = P.d_ipartials2.as<double>();
   return k;
 }
 
@@ -500,63 +556,25 @@ struct StepVecs {
   c128 *x, *r, *rhat, *p, *v, *s, *t;
 };
 
-// Branch streams of a captured step: fork from `s` before a phase, join back
-// after it.
-static void fork(const Branches& br, int phase, hipStream_t s) {
-  if (br.streams.empty()) return;
-  const size_t G = br.streams.size();
-  hipEvent_t ev = br.events[phase * (G + 1)];
-  hip_check(hipEventRecord(ev, s), "fork");
-  for (auto b : br.streams) hip_check(hipStreamWaitEvent(b, ev, 0), "fork wait");
-}
-
-static void join(const Branches& br, int phase, hipStream_t s) {
-  if (br.streams.empty()) return;
-  const size_t G = br.streams.size();
-  for (size_t g = 0; g < G; ++g) {
-    hipEvent_t ev = br.events[phase * (G + 1) + 1 + g];
-    hip_check(hipEventRecord(ev, br.streams[g]), "join");
-    hip_check(hipStreamWaitEvent(s, ev, 0), "join wait");
-  }
-}
-
-// One BiCGSTAB step with K = I for several batches at once, phase by phase:
-// [p update + product + <rhat,v>] -> alpha -> [s update + product + <t,s>,
-// <t,t>, ||s||] -> half-step test and omega -> [x, r update + <rhat,r>,
-// ||r||] -> rho, beta, convergence.  Each bracket is one chain of launches
-// per batch (run on the batch's branch stream if given); each arrow one
-// finalize launch for all systems (`all`) on `s`.  The product t = A s runs
-// before the half-step test: a system that converges at the half step
-// computes one product it does not use, and every step saves a finalize
-// launch and a join of the branches.
+// One BiCGSTAB step with K = I (y = p, z = s) for a batch of systems, with
+// the scalar work fused into the kernels: [p update + product + <rhat, v>]
+// -> [alpha + s update + product + <t, s>, <t, t>, ||s||] -> [half-step
+// test, omega, x, r update + <rhat, r>, ||r||]; k_step_end (run by the
+// caller, Poller::push_step_end) finishes it with rho, beta and convergence.
+// The product t = A s runs before the half-step test: a system that
+// converges at the half step computes one product it does not use, and the
+// step needs no launch between the products.
 template <typename R>
-void fused_steps(const std::vector<MvmBatch<R>>& m, const std::vector<KBatch>& k, const std::vector<StepVecs>& v,
-                 const KBatch& all, const Branches& br, hipStream_t s) {
-  const size_t G = m.size();
-  auto bs = [&](size_t g) { return br.streams.empty() ? s : br.streams[g]; };
-  fork(br, 0, s);
-  for (size_t g = 0; g < G; ++g) {
-    const vie::FuseArgs f1{1, 1, v[g].r, v[g].p, v[g].v, v[g].rhat, nullptr};
-    vie::mvm_pass1<R>(m[g], &k[g], f1, nullptr, false, bs(g));
-    vie::mvm_mid<R>(m[g], bs(g));
-    vie::mvm_pass5<R>(m[g], &k[g], f1, v[g].p, v[g].v, bs(g));
-  }
-  join(br, 0, s);
-  vie::k_finalize(all, vie::FIN_ALPHA, s);
-  fork(br, 1, s);
-  for (size_t g = 0; g < G; ++g) {
-    const vie::FuseArgs f2{2, 4, v[g].r, v[g].s, v[g].v, nullptr, v[g].s};
-    vie::mvm_pass1<R>(m[g], &k[g], f2, nullptr, false, bs(g));
-    vie::mvm_mid<R>(m[g], bs(g));
-    vie::mvm_pass5<R>(m[g], &k[g], f2, v[g].s, v[g].t, bs(g));
-  }
-  join(br, 1, s);
-  vie::k_finalize(all, vie::FIN_SOMEGA, s);
-  fork(br, 2, s);
-  for (size_t g = 0; g < G; ++g)
-    vie::k_update_xr(k[g], v[g].x, v[g].p, v[g].s, v[g].r, v[g].s, v[g].t, v[g].rhat, bs(g));
-  join(br, 2, s);
-  vie::k_finalize(all, vie::FIN_XR, s);
+void fused_step(const MvmBatch<R>& m, const KBatch& k, const StepVecs& v, hipStream_t s) {
+  const vie::FuseArgs f1{1, 1, v.r, v.p, v.v, v.rhat, nullptr};
+  vie::mvm_pass1<R>(m, &k, f1, nullptr, false, s);
+  vie::mvm_mid<R>(m, s);
+  vie::mvm_pass5<R>(m, &k, f1, v.p, v.v, s);
+  const vie::FuseArgs f2{3, 4, v.r, v.s, v.v, nullptr, v.s};
+  vie::mvm_pass1<R>(m, &k, f2, nullptr, false, s);
+  vie::mvm_mid<R>(m, s);
+  vie::mvm_pass5<R>(m, &k, f2, v.s, v.t, s);
+  vie::k_update_xr_fused(k, v.x, v.p, v.s, v.r, v.s, v.t, v.rhat, s);
 }
 
 c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (size_t)kind * P.groups.size(); }
@@ -566,44 +584,23 @@ c128* const* gptr(vie_problem& P, int kind) { return P.d_gptr.as<c128*>() + (siz
 bool batched(const Group& G, bool wg) { return !(wg && G.wg); }
 int batched_slots(const vie_problem& P, bool wg) { return wg ? P.n_batched_wg : P.n_inner; }
 
-// The first k branch streams (and their events), or none for k <= 1.
-Branches branch_view(const vie_problem& P, size_t k) {
-  Branches b;
-  if (k <= 1 || P.branches.streams.size() < k) return b;
-  b.streams.assign(P.branches.streams.begin(), P.branches.streams.begin() + (long)k);
-  b.events.assign(P.branches.events.begin(), P.branches.events.begin() + (long)(4 * (k + 1)));
-  return b;
-}
-
-size_t n_batched_groups(const vie_problem& P, bool wg) {
-  size_t n = 0;
-  for (auto& G : P.groups) n += batched(G, wg) ? 1 : 0;
-  return n;
-}
-
-// One BiCGSTAB step of every inner system of the batched block groups (y = p
-// and z = s: the inner solves are unpreconditioned).
+// One inner BiCGSTAB step of every system of a group (the inner solves are
+// unpreconditioned), without its step end.
 template <typename R>
-void inner_iteration(vie_problem& P, hipStream_t s, const Branches& br, bool wg) {
-  std::vector<MvmBatch<R>> m;
-  std::vector<KBatch> k;
-  std::vector<StepVecs> v;
-  for (auto& G : P.groups) {
-    if (!batched(G, wg)) continue;
-    m.push_back(group_batch<R>(P, G, true));
-    k.push_back(group_kbatch(P, G));
-    v.push_back({G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], G.vec[V_P], G.vec[V_V], G.vec[V_S], G.vec[V_T]});
-  }
-  fused_steps<R>(m, k, v, inner_all(P, batched_slots(P, wg)), br, s);
+void group_step(vie_problem& P, Group& G, hipStream_t s) {
+  const StepVecs v{G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], G.vec[V_P], G.vec[V_V], G.vec[V_S], G.vec[V_T]};
+  fused_step<R>(group_batch<R>(P, G, true), group_kbatch(P, G), v, s);
 }
 
-// The inner step captured once per problem, precision and block-solver mode
-// as a HIP graph (all kernel arguments are fixed per problem), replayed
-// every iteration.
+// The group's inner step captured once per precision as a HIP graph (all
+// kernel arguments are fixed per problem), replayed every iteration.  The
+// capture holds the process-wide API lock exclusively: other threads' HIP
+// calls that a capture forbids wait for it.
 template <typename R>
-hipGraphExec_t inner_graph(vie_problem& P, bool wg) {
-  hipGraphExec_t& ex = P.inner_graph[sizeof(R) == sizeof(float) ? 1 : 0][wg ? 1 : 0];
+hipGraphExec_t group_graph(vie_problem& P, Group& G) {
+  hipGraphExec_t& ex = G.graph[sizeof(R) == sizeof(float) ? 1 : 0];
   if (ex) return ex;
+  std::unique_lock<std::shared_mutex> capture(vie::api_mutex());
   hipStream_t cs = nullptr;
   hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
   hipGraph_t g = nullptr;
@@ -613,7 +610,7 @@ hipGraphExec_t inner_graph(vie_problem& P, bool wg) {
     hip_check(e, "begin capture");
   }
   try {
-    inner_iteration<R>(P, cs, branch_view(P, n_batched_groups(P, wg)), wg);
+    group_step<R>(P, G, cs);
   } catch (...) {
     (void)hipStreamEndCapture(cs, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -694,16 +691,51 @@ void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit
       vie::k_init(k, G.vec[V_B], G.vec[V_X], G.vec[V_R], G.vec[V_RHAT], gate, s);
     }
     vie::k_finalize(inner_all(P, nslots), vie::FIN_INIT, s, gate, tol, maxit);
-    hipGraphExec_t ex = graphs ? inner_graph<R>(P, wg) : nullptr;
-    Poller poll(P, s, 1);
-    for (int it = 1; it <= maxit; ++it) {
-      if (ex)
-        hip_check(hipGraphLaunch(ex, s), "graph launch");
-      else
-        inner_iteration<R>(P, s, Branches{}, wg);
-      const long t = poll.push_count(P.d_istatus.as<int>(), nslots, P.d_count.as<int>());
-      if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
+    // Every batched group iterates on its own until its systems have
+    // converged (its own stream when there are several, its own progress
+    // ring): a group that finishes early stops costing launches.
+    struct Run {
+      size_t gi;
+      hipStream_t st;
+      hipGraphExec_t ex;
+      Poller poll;
+      bool active;
+    };
+    std::vector<size_t> bg;
+    for (size_t gi = 0; gi < P.groups.size(); ++gi)
+      if (batched(P.groups[gi], wg)) bg.push_back(gi);
+    const bool split = bg.size() > 1 && P.branches.streams.size() == P.groups.size();
+    if (split) {
+      hip_check(hipEventRecord(P.branches.events[0], s), "fork");
+      for (size_t gi : bg) hip_check(hipStreamWaitEvent(P.branches.streams[gi], P.branches.events[0], 0), "fork wait");
     }
+    std::vector<Run> runs;
+    for (size_t gi : bg) {
+      hipStream_t gs = split ? P.branches.streams[gi] : s;
+      runs.push_back(Run{gi, gs, graphs ? group_graph<R>(P, P.groups[gi]) : nullptr, Poller(P, gs, 1 + (int)gi),
+                         true});
+    }
+    for (int it = 1; it <= maxit; ++it) {
+      bool any = false;
+      for (auto& r : runs) {
+        if (!r.active) continue;
+        any = true;
+        Group& G = P.groups[r.gi];
+        if (r.ex)
+          hip_check(hipGraphLaunch(r.ex, r.st), "graph launch");
+        else
+          group_step<R>(P, G, r.st);
+        const long t = r.poll.push_step_end(group_kbatch(P, G));
+        if (t - lag >= 0 && r.poll.wait(t - lag) == 0) r.active = false;
+      }
+      if (!any) break;
+    }
+    if (split)
+      for (size_t gi : bg) {
+        hipEvent_t ev = P.branches.events[1 + gi];
+        hip_check(hipEventRecord(ev, P.branches.streams[gi]), "join");
+        hip_check(hipStreamWaitEvent(s, ev, 0), "join wait");
+      }
   }
   if (any_wg)
     for (int i = 0; i < P.n_wg_groups; ++i) hip_check(hipStreamWaitEvent(s, P.wg_events[1 + i], 0), "join wait");
@@ -729,13 +761,16 @@ RunResult run_bicgstab(vie_problem& P, const c128* rhs, c128* x, double tol, int
   const int* gate = P.ostatus.as<int>();
   vie::k_init(k, rhs, x, v[V_R], v[V_RHAT], nullptr, s);
   vie::k_finalize(k, vie::FIN_INIT, s, nullptr, tol, maxit);
-  const std::vector<MvmBatch<R>> mv{m};
-  const std::vector<KBatch> kv{k};
-  const std::vector<StepVecs> vv{{x, v[V_R], v[V_RHAT], v[V_P], v[V_V], v[V_S], v[V_T]}};
+  const StepVecs vv{x, v[V_R], v[V_RHAT], v[V_P], v[V_V], v[V_S], v[V_T]};
   Poller poll(P, s, 0);
   for (int it = 1; it <= maxit; ++it) {
     if (!prec) {
-      fused_steps<R>(mv, kv, vv, k, Branches{}, s);
+      fused_step<R>(m, k, vv, s);
+      // progress value: the number of systems (0 or 1) still iterating
+      const long t = poll.push_step_end(k);
+      if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
+      if (P.cancel && P.cancel->load(std::memory_order_relaxed)) break;
+      continue;
     } else {
       vie::k_update_p(k, v[V_R], v[V_V], v[V_P], s);
       precond_apply<RI>(P, v[V_P], v[V_Y], tol_in, maxit_in, gate, lag, hist, hist_cap, graphs, wg, s);
@@ -1097,11 +1132,11 @@ void ensure_batch(vie_problem& P, int nrhs) {
   const int64_t n = 3 * P.nv;
   const size_t vecs = (size_t)kBatchVecs * nrhs * n * sizeof(c128);
   const size_t work = (size_t)nrhs * 3 * P.g.nz * P.ly * P.lx * sizeof(c128);
-  const size_t small = (size_t)nrhs * (sizeof(KState) + 2 * sizeof(int) + (size_t)P.pstride * sizeof(double)) +
+  const size_t small = (size_t)nrhs * (sizeof(KState) + 2 * sizeof(int) + 2 * (size_t)P.pstride * sizeof(double)) +
                        sizeof(int);
   const size_t total = vecs + work + small;
   const size_t old = P.mr_vecs.bytes + P.mr_work.bytes + P.mr_state.bytes + P.mr_status.bytes +
-                     P.mr_partials.bytes + P.mr_ntile.bytes + P.mr_count.bytes;
+                     P.mr_partials.bytes + P.mr_partials2.bytes + P.mr_ntile.bytes + P.mr_count.bytes;
   vie_context* ctx = P.ctx;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1111,7 +1146,8 @@ void ensure_batch(vie_problem& P, int nrhs) {
   }
   P.footprint = P.footprint - std::min(P.footprint, old) + total;
   P.mr_cap = 0;
-  DevBuf* bufs[] = {&P.mr_vecs, &P.mr_work, &P.mr_state, &P.mr_status, &P.mr_partials, &P.mr_ntile, &P.mr_count};
+  DevBuf* bufs[] = {&P.mr_vecs,     &P.mr_work,     &P.mr_state, &P.mr_status,
+                    &P.mr_partials, &P.mr_partials2, &P.mr_ntile, &P.mr_count};
   for (DevBuf* b : bufs) b->reset();
   try {
     P.mr_vecs.alloc(vecs);
@@ -1119,6 +1155,7 @@ void ensure_batch(vie_problem& P, int nrhs) {
     P.mr_state.alloc((size_t)nrhs * sizeof(KState));
     P.mr_status.alloc((size_t)nrhs * sizeof(int));
     P.mr_partials.alloc((size_t)nrhs * P.pstride * sizeof(double));
+    P.mr_partials2.alloc((size_t)nrhs * P.pstride * sizeof(double));
     P.mr_ntile.alloc((size_t)nrhs * sizeof(int));
     P.mr_count.alloc(sizeof(int));
   } catch (...) {
@@ -1156,6 +1193,7 @@ KBatch batch_kbatch(vie_problem& P, int nrhs) {
   k.partials = P.mr_partials.as<double>();
   k.pstride = P.pstride;
   k.ntile = P.mr_ntile.as<int>();
+  k.partials2 = P.mr_partials2.as<double>();
   return k;
 }
 
@@ -1172,9 +1210,7 @@ void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag
   vie::k_init(k, vec(BV_B), vec(BV_X), vec(BV_R), vec(BV_RHAT), nullptr, s);
   vie::k_finalize(k, vie::FIN_INIT, s, nullptr, tol, maxit);
   const MvmBatch<R> m = batch_mvm<R>(P, nrhs);
-  const std::vector<MvmBatch<R>> mv{m};
-  const std::vector<KBatch> kv{k};
-  const std::vector<StepVecs> vv{{vec(BV_X), vec(BV_R), vec(BV_RHAT), vec(BV_P), vec(BV_V), vec(BV_S), vec(BV_T)}};
+  const StepVecs vv{vec(BV_X), vec(BV_R), vec(BV_RHAT), vec(BV_P), vec(BV_V), vec(BV_S), vec(BV_T)};
   // y = K2^{-1} w for every right-hand side: to the stacked layout (systems
   // that no longer iterate give zero right-hand sides, which the inner
   // solves skip), one application on the replica, back
@@ -1186,7 +1222,10 @@ void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag
   Poller poll(P, s, 0);
   for (int it = 1; it <= maxit; ++it) {
     if (!prec) {
-      fused_steps<R>(mv, kv, vv, k, Branches{}, s);
+      fused_step<R>(m, k, vv, s);
+      const long t = poll.push_step_end(k);
+      if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
+      continue;
     } else {
       vie::k_update_p(k, vec(BV_R), vec(BV_V), vec(BV_P), s);
       apply(vec(BV_P), vec(BV_Y));
@@ -1514,19 +1553,21 @@ bool spectra_cached(vie_context* ctx, int lx, int ly, int lz, const vie_grid& g,
   return it != ctx->cache.end() && !it->second.expired();
 }
 
-// Device bytes a problem built from `pl` holds (spectra already in the
-// context's cache are shared and not counted).
-size_t plan_footprint(vie_context* ctx, const ProblemPlan& pl) {
+// Device bytes a problem built from `pl` holds.  Spectra already in the
+// context's cache are shared and not counted, unless `all_spectra` (a
+// request's reservation: the cache holds weak references, so spectra cached
+// at submission may be gone when the request is built).
+size_t plan_footprint(vie_context* ctx, const ProblemPlan& pl, bool all_spectra = false) {
   const auto& g = pl.g;
   const size_t nv = (size_t)pl.nv;
   size_t foot = nv * sizeof(c128)                                       // 1/chi
                 + 3 * (size_t)g.nz * pl.ly * pl.lx * sizeof(c128)       // work
                 + V_COUNT * 3 * nv * sizeof(c128)                       // Krylov vectors
-                + 4 * (size_t)std::max(vie::krylov_chunks(3 * (int64_t)nv), vie::mvm_row_tiles(pl.lx, g.nz, g.ny)) *
-                      sizeof(double);
+                + 2 * 4 * (size_t)std::max(vie::krylov_chunks(3 * (int64_t)nv), vie::mvm_row_tiles(pl.lx, g.nz, g.ny)) *
+                      sizeof(double);   // two partial buffers
   std::set<std::tuple<int, int, int>> seen;
   auto spec = [&](int lx, int ly, int lz) {
-    if (seen.insert({lx, ly, lz}).second && !spectra_cached(ctx, lx, ly, lz, g, pl.k0))
+    if (seen.insert({lx, ly, lz}).second && (all_spectra || !spectra_cached(ctx, lx, ly, lz, g, pl.k0)))
       foot += spectra_bytes(lx, ly, lz);
   };
   spec(pl.lx, pl.ly, pl.lz);
@@ -1540,7 +1581,7 @@ size_t plan_footprint(vie_context* ctx, const ProblemPlan& pl) {
                                                         vie::mvm_row_tiles(gp.lx, gp.bz, gp.by)));
     slots += (int64_t)nsys;
   }
-  foot += (size_t)std::max<int64_t>(1, slots) * ipstride * sizeof(double);
+  foot += 2 * (size_t)std::max<int64_t>(1, slots) * ipstride * sizeof(double);   // two partial buffers
   return foot;
 }
 
@@ -1593,6 +1634,7 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     for (int k = 0; k < V_COUNT; ++k) P->vec[k] = P->vecs.as<c128>() + (size_t)k * 3 * nv;
     P->pstride = 4 * std::max(vie::krylov_chunks(3 * nv), vie::mvm_row_tiles(P->lx, g.nz, g.ny));
     P->partials.alloc(P->pstride * sizeof(double));
+    P->partials2.alloc(P->pstride * sizeof(double));
   }
   P->ntile.alloc(sizeof(int));
   P->ntile.zero(s);
@@ -1601,10 +1643,14 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
   P->ostatus.alloc(sizeof(int));
   P->ostatus.zero(s);
   P->scal.alloc(64);
-  P->d_count.alloc(sizeof(int));
+  const int rings = 1 + (int)pl.groups.size();   // outer loop, then one per group
+  P->d_count.alloc(rings * sizeof(int));
   P->d_acc.alloc(3 * sizeof(int64_t));
   P->d_acc.zero(s);
-  hip_check(hipHostMalloc((void**)&P->h_ring, 2 * kRing * sizeof(int)), "pinned ring");
+  {
+    ApiShared api;
+    hip_check(hipHostMalloc((void**)&P->h_ring, (size_t)rings * kRing * sizeof(int)), "pinned ring");
+  }
   {
     void* dv = nullptr;
     if (hipHostGetDevicePointer(&dv, P->h_ring, 0) == hipSuccess && dv)
@@ -1612,8 +1658,13 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     else
       (void)hipGetLastError();
   }
-  for (auto& r : P->ev)
-    for (auto& e : r) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  {
+    ApiShared api;
+    P->ev.resize(rings);
+    for (auto& r : P->ev) r.fill(nullptr);
+    for (auto& r : P->ev)
+      for (auto& e : r) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  }
 
   if (pl.has_blocks) {
     const int n_blocks = pl.n_blocks;
@@ -1701,6 +1752,7 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     P->d_istate.alloc(std::max(1, slot) * sizeof(KState));
     P->d_istate.zero(s);
     P->d_ipartials.alloc((size_t)std::max(1, slot) * P->ipstride * sizeof(double));
+    P->d_ipartials2.alloc((size_t)std::max(1, slot) * P->ipstride * sizeof(double));
     P->d_intile.alloc(std::max(1, slot) * sizeof(int));
     P->d_intile.zero(s);
     // pick the faster z-pass kernel per batch shape and precision (tuning
@@ -1710,13 +1762,15 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
       G.zvar[1] = cached_zvariant<float>(ctx, group_batch<float>(*P, G, false), s, nullptr);
     }
     if (P->groups.size() > 1) {
+      ApiShared api;
       const size_t G = P->groups.size();
       P->branches.streams.resize(G, nullptr);
       for (auto& b : P->branches.streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
-      P->branches.events.resize(4 * (G + 1), nullptr);
+      P->branches.events.resize(G + 1, nullptr);
       for (auto& e : P->branches.events) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     }
     if (P->n_wg_groups > 0) {
+      ApiShared api;
       P->wg_streams.resize(P->n_wg_groups, nullptr);
       for (auto& b : P->wg_streams) hip_check(hipStreamCreateWithFlags(&b, hipStreamNonBlocking), "stream");
       P->wg_events.resize(1 + P->n_wg_groups, nullptr);
@@ -1779,10 +1833,11 @@ struct Server {
     if (queue.empty()) return false;
     if (ctx->budget == 0) return true;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    return ctx->used + ctx->reserved + queue.front()->footprint <= ctx->budget;
+    return ctx->used + ctx->reserved + g_unfreed_bytes.load() + queue.front()->footprint <= ctx->budget;
   }
 
   void run(vie_request* r, hipStream_t s) {
+    t_free_failed = false;
     vie_status st = guarded([&]() -> vie_status {
       set_device(ctx);
       auto P = build_problem(ctx, r->plan, s);
@@ -1802,12 +1857,21 @@ struct Server {
     });
     r->status = st;
     if (st != VIE_OK) r->error = vie_last_error_str();
+    if (t_free_failed && st >= 0) {
+      // the request's problem is gone, but some of its device memory could
+      // not be freed (it stays counted against the budget)
+      r->status = VIE_EDEVICE;
+      r->error = "device memory of the request could not be freed";
+    }
   }
 
   void worker() {
     hipStream_t s = nullptr;
     (void)hipSetDevice(ctx->device);
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    {
+      ApiShared api;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    }
     for (;;) {
       vie_request* r = nullptr;
       {
@@ -1842,7 +1906,10 @@ struct Server {
       cv_done.notify_all();
       cv_work.notify_all();
     }
-    if (s) (void)hipStreamDestroy(s);
+    if (s) {
+      ApiShared api;
+      (void)hipStreamDestroy(s);
+    }
   }
 
   void start(int slots, int cap) {
@@ -1889,7 +1956,10 @@ vie_status vie_context_create(int32_t device, size_t hbm_budget_bytes, vie_conte
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
     set_device(ctx.get());
-    hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "stream");
+    {
+      ApiShared api;
+      hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "stream");
+    }
     // twiddle tables for every supported length, both precisions
     size_t total = 0;
     for (int L : vie::kFftLengths) total += L;
@@ -1929,7 +1999,10 @@ vie_status vie_context_destroy(vie_context* ctx) {
       ctx->server.reset();
     }
     (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->stream) {
+      ApiShared api;
+      (void)hipStreamDestroy(ctx->stream);
+    }
     delete ctx;
     return VIE_OK;
   });
@@ -1947,7 +2020,7 @@ static vie_status problem_create(vie_context* ctx, const vie_grid* grid, const d
     const size_t foot = plan_footprint(ctx, plan);
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
-      if (ctx->budget && ctx->used + ctx->reserved + foot > ctx->budget)
+      if (ctx->budget && ctx->used + ctx->reserved + g_unfreed_bytes.load() + foot > ctx->budget)
         fail(VIE_EBUSY, "problem exceeds the context's HBM budget");
       ctx->used += foot;
     }
@@ -1979,7 +2052,10 @@ vie_status vie_problem_destroy(vie_problem* p) {
   return guarded([&]() -> vie_status {
     if (!p) return VIE_OK;
     (void)hipSetDevice(p->ctx->device);
-    (void)hipDeviceSynchronize();
+    {
+      ApiShared api;
+      (void)hipDeviceSynchronize();
+    }
     vie_context* ctx = p->ctx;
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
@@ -2001,7 +2077,10 @@ vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t vari
     if (precision != VIE_FP64 && precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
     if (variant < -1 || variant >= vie::kZPassVariants) fail(VIE_EINVAL, "z-pass variant out of range");
     set_device(p->ctx);
-    hip_check(hipDeviceSynchronize(), "synchronise");
+    {
+      ApiShared api;
+      hip_check(hipDeviceSynchronize(), "synchronise");
+    }
     std::lock_guard<std::mutex> lk(p->mu);
     const int q = precision == VIE_MIXED ? 1 : 0;
     hipStream_t s = p->ctx->stream;
@@ -2021,11 +2100,12 @@ vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t vari
         for (auto& G : x->groups)
           G.zvar[1] = cached_zvariant<float>(x->ctx, group_batch<float>(*x, G, false), s, nullptr);
       }
-      // captured inner iterations hold the old kernels
-      for (auto& g : x->inner_graph[q])
-        if (g) {
-          (void)hipGraphExecDestroy(g);
-          g = nullptr;
+      // captured inner steps hold the old kernels
+      ApiShared api;
+      for (auto& G : x->groups)
+        if (G.graph[q]) {
+          (void)hipGraphExecDestroy(G.graph[q]);
+          G.graph[q] = nullptr;
         }
     }
     return VIE_OK;
@@ -2047,6 +2127,33 @@ vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info) {
       info->zpass_variant[q] = p->zvar[q];
       for (int v = 0; v < vie::kZPassVariants; ++v) info->zpass_tune_ms[q][v] = p->ztune_ms[q][v];
     }
+    return VIE_OK;
+  });
+}
+
+vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* block_id, int32_t n_blocks,
+                    int32_t overlap, vie_problem_info* info, vie_group_plan* groups, int32_t groups_cap) {
+  return guarded([&]() -> vie_status {
+    if (!grid || !eps_r || !info) fail(VIE_EINVAL, "grid, eps_r and info are required");
+    if (overlap < 0 || overlap > 256) fail(VIE_EINVAL, "overlap must be in [0, 256]");
+    if (groups_cap < 0 || (groups_cap > 0 && !groups)) fail(VIE_EINVAL, "groups_cap needs a groups array");
+    const ProblemPlan pl = make_plan(*grid, eps_r, block_id, n_blocks, block_id ? overlap : 0);
+    vie_problem_info d{};
+    d.lx = pl.lx;
+    d.ly = pl.ly;
+    d.lz = pl.lz;
+    for (int64_t c : pl.cnt) d.n_blocks += c > 0 ? 1 : 0;
+    d.n_groups = (int32_t)pl.groups.size();
+    for (const auto& gp : pl.groups) d.n_block_solver_groups += gp.wg ? 1 : 0;
+    d.footprint_bytes = (int64_t)plan_footprint(nullptr, pl, true);
+    d.zpass_variant[0] = d.zpass_variant[1] = -1;
+    for (auto& row : d.zpass_tune_ms)
+      for (auto& v : row) v = -1.0f;
+    for (int32_t i = 0; i < groups_cap && i < (int32_t)pl.groups.size(); ++i) {
+      const GroupPlan& gp = pl.groups[i];
+      groups[i] = vie_group_plan{gp.lx, gp.ly, gp.lz, gp.bx, gp.by, gp.bz, (int32_t)gp.blocks.size(), gp.wg ? 1 : 0};
+    }
+    *info = d;
     return VIE_OK;
   });
 }
@@ -2194,7 +2301,14 @@ vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_d
     set_device(p->ctx);
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t ev[6];
-    for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+    {
+      ApiShared api;
+      for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+    }
+    auto destroy = [&] {
+      ApiShared api;
+      for (auto& e : ev) (void)hipEventDestroy(e);
+    };
     double acc[5] = {0, 0, 0, 0, 0};
     try {
       for (int r = 0; r < reps; ++r) {
@@ -2210,10 +2324,10 @@ vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_d
         }
       }
     } catch (...) {
-      for (auto& e : ev) (void)hipEventDestroy(e);
+      destroy();
       throw;
     }
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    destroy();
     for (int i = 0; i < 5; ++i) pass_ms[i] = acc[i] / reps;
     return VIE_OK;
   });
@@ -2399,11 +2513,12 @@ vie_status vie_server_start(vie_context* ctx, int32_t slots, int32_t queue_cap) 
   });
 }
 
-static size_t transient_bytes(vie_context* ctx, const ProblemPlan& pl) {
-  // spectra set-up scratch (6 full kernels in FP64) for lengths not cached
+// Set-up scratch of the spectra (6 full kernels in FP64, one length set at
+// a time) for lengths not cached (all of them with `all_spectra`).
+static size_t transient_bytes(vie_context* ctx, const ProblemPlan& pl, bool all_spectra = false) {
   size_t t = 0;
   auto one = [&](int lx, int ly, int lz) {
-    if (!spectra_cached(ctx, lx, ly, lz, pl.g, pl.k0))
+    if (all_spectra || !spectra_cached(ctx, lx, ly, lz, pl.g, pl.k0))
       t = std::max(t, 6 * (size_t)lx * ly * lz * sizeof(c128));
   };
   one(pl.lx, pl.ly, pl.lz);
@@ -2437,7 +2552,10 @@ vie_status vie_submit(vie_context* ctx, const vie_grid* grid, const double* eps_
     for (double v : r->e_inc)
       if (!is_finite(v)) fail(VIE_EINVAL, "e_inc has non-finite entries");
     set_device(ctx);
-    r->footprint = plan_footprint(ctx, r->plan) + transient_bytes(ctx, r->plan);
+    // reserved whatever the cache holds now, plus the request's own incident
+    // and result buffers on the device
+    r->footprint = plan_footprint(ctx, r->plan, true) + transient_bytes(ctx, r->plan, true) +
+                   2 * 3 * (size_t)r->plan.nv * sizeof(c128);
     if (ctx->budget && r->footprint > ctx->budget) fail(VIE_EINVAL, "request needs more memory than the context budget");
     {
       std::lock_guard<std::mutex> lk(ctx->server_mu);

@@ -56,7 +56,7 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
 
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
                "vie_problem_create", "vie_problem_create_overlap", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass",
-               "vie_plane_wave",
+               "vie_plane_wave", "vie_plan",
                "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
                "vie_solve_batch",
                "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
@@ -99,6 +99,12 @@ class vie_problem_info(ctypes.Structure):
                 ("zpass_variant", ctypes.c_int32 * 2), ("zpass_tune_ms", (ctypes.c_float * 5) * 2)]
 
 
+class vie_group_plan(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("lz", ctypes.c_int32),
+                ("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32),
+                ("n_systems", ctypes.c_int32), ("one_workgroup", ctypes.c_int32)]
+
+
 _vp = ctypes.c_void_p
 _lib.vie_abi_version.restype = ctypes.c_int32
 _lib.vie_abi_version.argtypes = []
@@ -114,6 +120,8 @@ for _name, _args in {
     "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
     "vie_problem_set_zpass": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_plane_wave": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
+    "vie_plan": [ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vie_problem_info),
+                 _vp, ctypes.c_int32],
     "vie_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
     "vie_matvec_profile": [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp],
     "vie_block_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
@@ -197,6 +205,18 @@ def vie_problem_get_info(p: int) -> vie_problem_info:
 
 def vie_problem_set_zpass(p: int, precision: int, variant: int) -> None:
     _check(_lib.vie_problem_set_zpass(p, int(precision), int(variant)), "vie_problem_set_zpass")
+
+
+def vie_plan(grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray], n_blocks: int, overlap: int = 0,
+             groups_cap: int = 64):
+    """Host-only block plan: (vie_problem_info, [vie_group_plan, ...])."""
+    e = np.ascontiguousarray(eps, dtype=np.complex128)
+    b = None if block_id is None else np.ascontiguousarray(block_id, dtype=np.int32)
+    info = vie_problem_info()
+    groups = (vie_group_plan * max(groups_cap, 1))()
+    _check(_lib.vie_plan(ctypes.byref(grid), _np_ptr(e), _np_ptr(b) if b is not None else None, int(n_blocks),
+                         int(overlap), ctypes.byref(info), groups, int(groups_cap)), "vie_plan")
+    return info, [groups[i] for i in range(min(info.n_groups, groups_cap))]
 
 
 def vie_plane_wave(grid: vie_grid, kdir: Sequence[float], pol: Sequence[complex]) -> np.ndarray:

@@ -1,4 +1,4 @@
-"""Write the oracle reference files of the full-size metasurface case.
+"""Write the oracle reference files of the full-size metasurface case and of the first outer steps on the plasmonic cell.
 
 Calls only ``oracle/`` and ``workloads``.  Each run writes
 ``oracle_metasurface_<run>.json`` (settings, outer step count, residual
@@ -25,7 +25,13 @@ Runs (the case is 128x128x32 at lambda/40, 64 pillar blocks + slab):
 * ``spread``      reads the stored fields and writes
                   ``oracle_metasurface_spread.json``: relative field
                   differences between the runs and the step counts side by
-                  side.
+                  side;
+* ``plasmonic_first``  the plasmonic cell (96x96x64 at lambda/40: 16 metal
+                  sphere blocks, the absorbing layer and the slab), FP64
+                  block-preconditioned at its tolerances (outer 1e-6, inner
+                  3e-2), capped at 3 outer steps: the residual after every
+                  step and the inner step counts of every application
+                  (``oracle_plasmonic_first.json``, no field).
 
 BLAS is held to one thread so inner products are summed in a fixed order
 (the results do not depend on the machine's core count); ``--workers`` only
@@ -64,11 +70,14 @@ RUNS = {
     "mixed": dict(kind="mixed", prec=True, tol=BENCH_TOL, pad=0),
     "mixed_pad4": dict(kind="mixed", prec=True, tol=BENCH_TOL, pad=4),
     "bench_fp64": dict(kind="fp64", prec=True, tol=BENCH_TOL, pad=0),
+    "plasmonic_first": dict(kind="fp64", prec=True, tol=None, pad=0, maxit=3, case="plasmonic", field=False),
 }
 
 
 def path(run, ext):
     suffix = "_etot.npy" if ext == "npy" else ".json"
+    if run.startswith("plasmonic"):
+        return os.path.join(HERE, f"oracle_{run}{suffix}")
     return os.path.join(HERE, f"oracle_{CASE}_{run}{suffix}")
 
 
@@ -79,7 +88,7 @@ def scatterer_values(g, E):
 
 def run(name: str) -> dict:
     spec = RUNS[name]
-    case = W.by_name(CASE)
+    case = W.by_name(spec.get("case", CASE))
     g = op.Grid.from_case(case)
     e = physics.plane_wave(g, case.kdir, case.pol)
     tol = spec["tol"] if spec["tol"] is not None else case.tol_outer
@@ -94,7 +103,7 @@ def run(name: str) -> dict:
                            pad=spec["pad"])
     secs = time.time() - t0
     d = {
-        "case": CASE, "run": name,
+        "case": case.name, "run": name,
         "source": "oracle/ (krylov.solve_mixed)" if spec["kind"] == "mixed" else "oracle/ (krylov.solve)",
         "script": "tests/golden/make_goldens.py",
         "precision": "complex64 products, FP64 vectors and refinement" if spec["kind"] == "mixed" else "FP64",
@@ -113,13 +122,16 @@ def run(name: str) -> dict:
     if spec["kind"] == "mixed":
         d.update(max_refine=3, refine_steps=sol.refine_steps, refine_iters=sol.refine_iters,
                  relres_true=sol.relres_true, true_history=sol.true_history)
-    np.save(path(name, "npy"), scatterer_values(g, sol.E_tot), allow_pickle=False)
+    if spec.get("field", True):
+        np.save(path(name, "npy"), scatterer_values(g, sol.E_tot), allow_pickle=False)
     return d
 
 
 def spread() -> dict:
     fields, meta = {}, {}
     for name in RUNS:
+        if RUNS[name].get("case", CASE) != CASE:
+            continue
         if os.path.exists(path(name, "npy")) and os.path.exists(path(name, "json")):
             fields[name] = np.load(path(name, "npy"), allow_pickle=False)
             meta[name] = json.load(open(path(name, "json")))

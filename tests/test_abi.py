@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 
 def test_abi_version():
-    assert V.vie_abi_version() == 10
+    assert V.vie_abi_version() == 11
 
 
 def _has_gpu():
@@ -75,4 +75,23 @@ def test_plane_wave_rejects_non_unit_direction():
     g = V.make_grid(2, 2, 2, 1, 1, 1, 10)
     with pytest.raises(V.VieError) as e:
         V.vie_plane_wave(g, (0, 0, 2), (1, 0, 0))
+    assert e.value.code == V.VIE_EINVAL
+
+
+def test_plan_of_the_metasurface_case():
+    """Host-only block plan: the metasurface's 64 pillar boxes form one shape
+    group on a 32x32x48 transform, the slab another on 256x256x16; the full
+    grid uses 256x256x64."""
+    case = W.metasurface()
+    g = V.make_grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.wavelength)
+    info, groups = V.vie_plan(g, case.eps, case.block_id, case.n_blocks)
+    assert (info.lx, info.ly, info.lz) == (256, 256, 64)
+    assert info.n_blocks == 65 and info.n_groups == len(groups) == 2
+    shapes = sorted(((gp.lx, gp.ly, gp.lz), gp.n_systems) for gp in groups)
+    assert shapes == [((32, 32, 48), 64), ((256, 256, 16), 1)]
+    assert info.footprint_bytes > 0 and info.zpass_variant[0] == -1
+    with pytest.raises(V.VieError) as e:
+        bad = case.block_id.copy()
+        bad[tuple(np.argwhere(case.eps != 1)[0])] = case.n_blocks   # out of range on a scatterer voxel
+        V.vie_plan(g, case.eps, bad, case.n_blocks)
     assert e.value.code == V.VIE_EINVAL

@@ -221,10 +221,12 @@ def test_mixed_refinement_matches_oracle(vie_ctx, name, tol):
     correction ends just under its target, so whether a second one is needed
     is decided by rounding: oracle runs that differ only in rounding (pad 0,
     2, 4) take 1 or 2 on these inputs.  The GPU's correction count lies in
-    that spread.  Without preconditioner the complex64 main loop runs over a
-    hundred steps and its count spreads widely with rounding alone (113 to
-    125 on the cube for five embedding lengths): the GPU's count must lie in
-    that spread widened by half its width on each side (at least 2)."""
+    that spread.  The main loop runs to a recursive residual (1e-9 on the
+    cube) far below the complex64 product's rounding level (~1e-7): from
+    there on its step count is set by rounding, not by the method.  On the
+    cube, oracle runs that differ only in embedding length or summation order
+    took 113 to 133 steps, the GPU 110.  The GPU's count must lie within 15%
+    of the median of the oracle runs."""
     case = W.cube16() if name == "cube16" else W.random_tiny(int(name[4:]), (7, 6, 5), fill=0.8, n_blocks=2)
     g = op.Grid.from_case(case)
     e = physics.plane_wave(g)
@@ -237,8 +239,8 @@ def test_mixed_refinement_matches_oracle(vie_ctx, name, tol):
     rsteps = [r.refine_steps for r in refs]
     assert min(rsteps) <= st.refine_steps <= max(rsteps), (st.refine_steps, rsteps)
     counts = [r.info.iterations for r in refs]
-    w = max(2, (max(counts) - min(counts) + 1) // 2)
-    assert min(counts) - w <= st.outer_iters <= max(counts) + w, (st.outer_iters, counts)
+    med = float(np.median(counts))
+    assert abs(st.outer_iters - med) <= 0.15 * med, (st.outer_iters, counts)
     assert st.relres_true <= tol and o.relres_true <= tol
     assert _rel(e_tot, o.E_tot) <= 1e-8
     assert _rel(e_tot, ref64.E_tot) <= 1e-8

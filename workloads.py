@@ -39,7 +39,7 @@ import numpy as np
 
 __all__ = [
     "Case", "cube16", "metasurface", "plasmonic", "sweep_case", "sweep",
-    "sphere", "random_tiny", "mixed_partition", "SERVING_GRIDS", "SERVING_RATES", "arrivals", "serving_request",
+    "sphere", "random_tiny", "mixed_partition", "plasmonic_small", "SERVING_GRIDS", "SERVING_RATES", "arrivals", "serving_request",
     "request_precondition", "CASES", "by_name",
 ]
 
@@ -167,6 +167,37 @@ def plasmonic() -> Case:
     return Case("plasmonic", nx, ny, nz, d, d, d, lam, eps, bid, 18,
                 tol_outer=1e-6, tol_inner=3e-2, precision="mixed",
                 note="4x4 metal spheres in absorbing layer over slab, 96x96x64 at lambda/40, 18 blocks")
+
+
+def plasmonic_small() -> Case:
+    """The plasmonic cell's structure at a size the oracle solves in seconds:
+    48x48x32 at lambda/40; slab z-voxels [0, 8) eps 12 - 0.5j; layer [8, 32)
+    eps 3.0 - 0.3j; 2x2 metal spheres eps -15 - 1.0j, centre (24 ix + 12,
+    24 iy + 12, 20) voxel units, radius ``default_rng(3).integers(4, 7,
+    (2, 2))[iy, ix]`` voxels.  Blocks: sphere (ix, iy) -> 2*iy + ix, layer
+    (minus spheres) -> 4, slab -> 5 (uneven blocks, spheres inside the
+    layer's bounding box)."""
+    nx, ny, nz = 48, 48, 32
+    lam = 1.0
+    d = lam / 40.0
+    radii = np.random.default_rng(3).integers(4, 7, (2, 2))
+    eps = np.ones((nz, ny, nx), dtype=np.complex128)
+    bid = np.full((nz, ny, nx), -1, dtype=np.int32)
+    eps[0:8] = 12.0 - 0.5j
+    bid[0:8] = 5
+    eps[8:32] = 3.0 - 0.3j
+    bid[8:32] = 4
+    zc, yc, xc = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    for iy in range(2):
+        for ix in range(2):
+            cx, cy, cz = 24 * ix + 12.0, 24 * iy + 12.0, 20.0
+            r = float(radii[iy, ix])
+            inside = (xc - cx) ** 2 + (yc - cy) ** 2 + (zc - cz) ** 2 <= r * r
+            eps[inside] = -15.0 - 1.0j
+            bid[inside] = 2 * iy + ix
+    return Case("plasmonic_small", nx, ny, nz, d, d, d, lam, eps, bid, 6,
+                tol_outer=1e-6, tol_inner=3e-2, precision="mixed",
+                note="2x2 metal spheres in absorbing layer over slab, 48x48x32 at lambda/40, 6 blocks")
 
 
 SWEEP_GRIDS = [(32, 32, 32), (48, 48, 48), (64, 64, 32), (96, 96, 32)]
@@ -368,7 +399,7 @@ def request_precondition(case: Case) -> bool:
     return "pillars" in case.note or case.name.startswith("sweep")
 
 
-CASES = {"cube16": cube16, "metasurface": metasurface, "plasmonic": plasmonic}
+CASES = {"cube16": cube16, "metasurface": metasurface, "plasmonic": plasmonic, "plasmonic_small": plasmonic_small}
 
 
 def by_name(name: str) -> Case:
