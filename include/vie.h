@@ -308,6 +308,23 @@ vie_status vie_total_field_box(vie_problem* p, int32_t precision, const void* po
 vie_status vie_far_field(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat, double* f_out,
                          void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): vie_far_field
+ * with device arrays in and out and no allocation of any kind.
+ *   pol_dev:  3*nvox complex, the solution P (device);
+ *   rhat_dev: n_dir unit directions, 3 doubles each (device; not checked);
+ *   f_dev:    3*n_dir complex written (device), as vie_far_field's f_out.
+ * The per-chunk partial sums live in a fixed array of 8 MiB that the library
+ * keeps on every GPU it runs on until the process ends (its device address
+ * is looked up by vie_context_create).  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU race, so run them in order (one
+ * stream, or synchronised).  n_dir * ceil(nx ny nz / 2048) * 6 must not
+ * exceed 1048576 (VIE_EINVAL otherwise).  Ordered on `stream`; returns
+ * without synchronising.  Same kernels and summation order as
+ * vie_far_field, so the results are identical. */
+vie_status vie_far_field_noalloc(vie_problem* p, const void* pol_dev, int32_t n_dir, const void* rhat_dev,
+                                 void* f_dev, void* stream);
+
 /* Bistatic radar cross-section for a unit-amplitude incident wave,
  * sigma(rhat) = k0^4 |F(rhat)|^2 / (4 pi) (the E-plane curves of Sec. III,
  * Figs. 1-2, for rhat in the x-z plane).  sigma_out: host, n_dir doubles. */

@@ -14,6 +14,14 @@ namespace vie {
 constexpr int FF_T = 256;          // threads per workgroup
 constexpr int FF_CHUNK = 2048;     // voxels per workgroup
 
+// Partial sums of the far field that allocates nothing (6 doubles per
+// direction and voxel chunk): a fixed array of 8 MiB on every GPU the
+// library runs on, held until the process ends.  Host code never uses the
+// name itself (it is a host-side stand-in there): far_field_scratch_address
+// returns the device's own address of its copy.
+constexpr int64_t kFarScratchDoubles = int64_t(1) << 20;
+static __device__ __align__(256) double scratch[kFarScratchDoubles];
+
 __global__ void __launch_bounds__(FF_T) k_far_partial(const c128* P, int nx, int ny, int nz, double dx, double dy,
                                                       double dz, double k0, const double* rhat, int nchunk,
                                                       double* part) {
@@ -70,6 +78,16 @@ __global__ void __launch_bounds__(FF_T) k_far_final(const double* part, int nchu
 }
 
 int64_t far_field_chunks(int64_t nv) { return (nv + FF_CHUNK - 1) / FF_CHUNK; }
+
+int64_t far_field_scratch_doubles() { return kFarScratchDoubles; }
+
+void* far_field_scratch_address() {
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw std::runtime_error(std::string("far-field scratch address: ") + hipGetErrorString(e));
+  return ptr;
+}
 
 void far_field(const c128* P, int nx, int ny, int nz, double dx, double dy, double dz, double k0, const double* rhat,
                int ndir, double* part, c128* F, hipStream_t s) {

@@ -175,6 +175,11 @@ void block_solve(const BlockSolveArgs& a, int lx, int lz, hipStream_t s);
 // for ndir directions (rhat: device, 3 doubles each; F: device, 3 c128 each).
 // part: device scratch of 6 far_field_chunks(nx ny nz) doubles per direction.
 int64_t far_field_chunks(int64_t nv);
+// The far field's fixed scratch array (for the entry point that allocates
+// nothing): its capacity in doubles, and its address on the current device
+// (looked up once per device at set-up; throws on failure).
+int64_t far_field_scratch_doubles();
+void* far_field_scratch_address();
 void far_field(const c128* P, int nx, int ny, int nz, double dx, double dy, double dz, double k0, const double* rhat,
                int ndir, double* part, c128* F, hipStream_t s);
 

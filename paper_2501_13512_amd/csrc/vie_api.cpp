@@ -222,6 +222,7 @@ struct vie_context {
   std::map<std::array<int, 8>, std::pair<int, std::array<float, vie::kZPassVariants>>> ztune;
   std::unique_ptr<Server> server;
   std::mutex server_mu;
+  double* far_scratch = nullptr;   // this device's copy of the far field's fixed scratch array
   ~vie_context();
 };
 
@@ -1983,6 +1984,12 @@ vie_status vie_context_create(int32_t device, size_t hbm_budget_bytes, vie_conte
       ctx->tws32.table[L] = ctx->tw32.as<c64>() + off;
       off += L;
     }
+    // the device address of the fixed scratch array, with this device current
+    try {
+      ctx->far_scratch = static_cast<double*>(vie::far_field_scratch_address());
+    } catch (const std::exception& e) {
+      fail(VIE_EDEVICE, e.what());
+    }
     *out = ctx.release();
     return VIE_OK;
   });
@@ -2269,6 +2276,25 @@ vie_status vie_far_field(vie_problem* p, const void* pol_dev, int32_t n_dir, con
     std::vector<c128> F;
     far_field_host(p, pol_dev, n_dir, rhat, F, (hipStream_t)stream);
     std::memcpy(f_out, F.data(), F.size() * sizeof(c128));
+    return VIE_OK;
+  });
+}
+
+vie_status vie_far_field_noalloc(vie_problem* p, const void* pol_dev, int32_t n_dir, const void* rhat_dev,
+                                 void* f_dev, void* stream) {
+  return guarded([&]() -> vie_status {
+    if (!p || !pol_dev || !rhat_dev || !f_dev) fail(VIE_EINVAL, "problem, pol, rhat and f are required");
+    if (n_dir < 1) fail(VIE_EINVAL, "n_dir must be >= 1");
+    const int64_t nchunk = vie::far_field_chunks(p->nv);
+    if ((int64_t)n_dir * nchunk * 6 > vie::far_field_scratch_doubles())
+      fail(VIE_EINVAL, "n_dir * ceil(nx ny nz / 2048) * 6 exceeds the fixed scratch of 1048576 doubles (use "
+                       "vie_far_field, or fewer directions per call)");
+    if (!p->ctx->far_scratch) fail(VIE_EDEVICE, "far-field scratch not set up");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    const vie_grid& g = p->g;
+    vie::far_field((const c128*)pol_dev, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, p->k0, (const double*)rhat_dev, n_dir,
+                   p->ctx->far_scratch, (c128*)f_dev, (hipStream_t)stream);
     return VIE_OK;
   });
 }

@@ -60,7 +60,7 @@ ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_c
                "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
                "vie_solve_batch",
                "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
-               "vie_total_field_box", "vie_far_field", "vie_rcs")
+               "vie_total_field_box", "vie_far_field", "vie_far_field_noalloc", "vie_rcs")
 
 
 class VieError(RuntimeError):
@@ -138,6 +138,7 @@ for _name, _args in {
     "vie_cancel": [_vp],
     "vie_total_field_box": [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp],
     "vie_far_field": [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp],
+    "vie_far_field_noalloc": [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp],
     "vie_rcs": [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp],
 }.items():
     getattr(_lib, _name).restype = ctypes.c_int
@@ -341,6 +342,13 @@ def vie_far_field(p: int, pol, rhat: np.ndarray, stream=None) -> np.ndarray:
     _check(_lib.vie_far_field(p, _dev(pol), int(r.shape[0]), _np_ptr(r), _np_ptr(out), _stream(stream)),
            "vie_far_field")
     return out
+
+
+def vie_far_field_noalloc(p: int, pol, n_dir: int, rhat_dev, f_dev, stream=None) -> None:
+    """Far field into a caller's device buffer (rhat_dev: n_dir x 3 float64,
+    f_dev: n_dir x 3 complex128, both device tensors); allocates nothing."""
+    _check(_lib.vie_far_field_noalloc(p, _dev(pol), int(n_dir), _dev(rhat_dev), _dev(f_dev), _stream(stream)),
+           "vie_far_field_noalloc")
 
 
 def vie_rcs(p: int, pol, rhat: np.ndarray, stream=None) -> np.ndarray:
