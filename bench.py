@@ -11,13 +11,23 @@ solve to relative residual 1e-5 is about 2e-5 away from the converged field,
 problem (1/chi, block plan, Green spectra) is set up once before the timed
 region; its set-up time is reported separately.
 
-Prints one JSON line.  Extra fields: per-solve latency p50/p99, outer and
-inner step counts, the FP64 true residual, the sampled field error against
-the oracle's reference files (case tolerance, and tight), the FP64 GPU
-paths of the same workload (block-preconditioned and unpreconditioned), the
-flexible GMRES(m) outer-solver variant with the same preconditioner,
-the FFT product's per-pass times and the roofline of its dominant pass (also
-on a 256x256x64 grid), and the CPU oracle baseline.
+Prints one JSON line.  ``roofline`` describes the dominant kernel of the
+timed solves: the z pass (z transforms and spectral multiply) of the block
+group whose z passes take the most time.  Its algorithmic bytes per launch
+count the systems active in that launch (a converged block's workgroups do
+nothing), reconstructed from the inner step counts the timed solve records
+for every application; its duration at each active count is measured live
+with HIP events on the launch stream (vie_group_profile, the same kernel and
+grid as in the solves) and weighted by the launches of the timed solve.
+``roofline_full_grid`` gives the full-grid product on a 256x256x64 grid
+(the survey's per-product byte model) beside it.  Extra fields: per-solve
+latency p50/p99, outer and inner step counts, the FP64 true residual, the
+field error at every scatterer voxel against the oracle's stored solves
+(case tolerance, and 1e-12), the FP64 GPU paths of the same workload
+(block-preconditioned and unpreconditioned), solver variants, the FFT
+product's per-pass times, and the CPU oracle baseline (set-up and three
+outer steps of the oracle's mixed-precision solve of this workload on every
+host core, scaled by the oracle's own step count).
 """
 from __future__ import annotations
 
@@ -95,7 +105,7 @@ def counters_for(kernel, workload, precision, lz):
     (HBM bytes per launch from FETCH_SIZE and WRITE_SIZE scaled by a
     copy-kernel calibration; wavefront VALU instructions per launch), or
     None if no summary covers this kernel build."""
-    from paper_2501_13512_amd.profile_traffic import kernel_hash
+    from profile_tools import kernel_hash
     path = os.path.join(ROOT, "profiles", "mvm_hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -127,26 +137,102 @@ def golden_error(case, e_tot):
     return out or None
 
 
-def cpu_baseline(case, outer_iters_hint):
-    """Time the CPU oracle on a bounded sample: one outer BiCGSTAB step of the
-    same solve (two preconditioner applications plus two products), scaled
-    by the oracle's outer step count for the full solve.  BLAS and FFT run
-    on one thread."""
-    from threadpoolctl import threadpool_limits
+def oracle_steps(case):
+    """The oracle's own outer step count (main loop + corrections) for the
+    benchmark's mixed solve, from its stored run (tests/golden/)."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{case.name}_mixed.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    return int(g["outer_iters"]) + int(g.get("refine_iters", 0)), int(g.get("refine_steps", 0))
+
+
+def cpu_baseline(case, tol_outer, gpu_steps, sample_steps=3):
+    """The CPU oracle on a bounded sample of the same workload, on every host
+    core (scipy.fft workers; the oracle's inner products are plain numpy
+    sums): its set-up (operators with the complex64 products of the mixed
+    mode, the FP64 operator of the true residual, the block preconditioner)
+    timed on its own, then `sample_steps` outer BiCGSTAB steps of its
+    mixed-precision solve and one FP64 product, scaled to a whole solve with
+    the oracle's own step count for this workload (its stored run), else with
+    the GPU's."""
+    import scipy.fft
     from oracle import krylov, operator as op, physics
+    cores = os.cpu_count() or 1
     g = op.Grid.from_case(case)
-    e = physics.plane_wave(g, case.kdir, case.pol)
-    with threadpool_limits(limits=1):
+    b = krylov.masked_rhs(g, physics.plane_wave(g, case.kdir, case.pol))
+    with scipy.fft.set_workers(cores):
         t0 = time.perf_counter()
-        c0 = time.process_time()
-        krylov.solve(g, e, case.tol_outer, 1, case.block_id, case.n_blocks, case.tol_inner, case.maxit_inner)
-        step_s = time.perf_counter() - t0
-        cpu_s = time.process_time() - c0
-    est = step_s * max(outer_iters_hint, 1)
-    return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one outer step of the FP64 oracle solve of the same workload ({step_s:.1f} s wall, "
-                      f"{cpu_s:.1f} s CPU, includes set-up), scaled by {outer_iters_hint} outer steps",
-            "seconds_per_outer_step": step_s, "host_cpus": os.cpu_count()}
+        A32 = op.FFTOperator(g, 0, "c64")
+        A64 = op.FFTOperator(g, 0, "fp64")
+        pre = krylov.BlockPreconditioner(g, case.block_id, case.n_blocks, case.tol_inner, case.maxit_inner, 0, "c64")
+        setup_s = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        krylov.bicgstab(A32, b, tol_outer, sample_steps, pre)
+        step_s = (time.perf_counter() - t1) / sample_steps
+        t2 = time.perf_counter()
+        A64(b)
+        prod64_s = time.perf_counter() - t2
+    own = oracle_steps(case)
+    steps, refine = (own if own else (gpu_steps, 1))
+    est = setup_s + steps * step_s + (1 + refine) * prod64_s
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle mixed-precision solve of the same workload: set-up {setup_s:.1f} s, {sample_steps} outer "
+                      f"steps {sample_steps * step_s:.1f} s, one FP64 product {prod64_s:.1f} s, on {cores} host threads "
+                      f"(FFT workers); whole solve estimated with {steps} outer steps "
+                      f"({'the oracle' + chr(39) + 's own stored run' if own else 'the GPU count, no stored oracle run'})"
+                      f" and {1 + refine} FP64 residuals",
+            "setup_s": setup_s, "seconds_per_outer_step": step_s, "fp64_product_s": prod64_s,
+            "outer_steps": steps, "steps_from": "oracle" if own else "gpu"}
+
+
+def launch_mix(hist, block_group, group, lag):
+    """Active systems of `group` in every product launch of a solve (two per
+    inner step), from the inner step counts of every preconditioner
+    application (hist: counts of the non-empty blocks in ascending id,
+    application-major).  A block with count c is active in the first c
+    steps of an application; the host stops replaying a group `lag` steps
+    after its last block converged (at least one step)."""
+    nonempty = [g for g in block_group if g >= 0]
+    nb = len(nonempty)
+    mine = [j for j, g in enumerate(nonempty) if g == group]
+    out = []
+    for a in range(0, len(hist) - nb + 1, nb):
+        c = [hist[a + j] for j in mine]
+        reps = max(max(c), 1) + lag
+        for t in range(1, reps + 1):
+            n = sum(1 for v in c if v >= t)
+            out += [n, n]
+    return out
+
+
+def zpass_roofline(V, handle, grid_groups, block_group, hist, prec, lag, reps):
+    """The z pass of every batched block group over the timed solve's
+    launches: algorithmic bytes (active systems x (2 B s) + the octant
+    spectra once when any system is active; B = 3 bz ly lx) against the
+    launch durations measured at each active count."""
+    s_el = 8 if prec == V.VIE_MIXED else 16
+    out = []
+    for gi, gp in enumerate(grid_groups):
+        if gp.one_workgroup:
+            continue
+        mix = launch_mix(hist, block_group, gi, lag)
+        if not mix:
+            continue
+        B = 3 * gp.bz * gp.ly * gp.lx
+        oct_ = 6 * (gp.lx // 2 + 1) * (gp.ly // 2 + 1) * (gp.lz // 2 + 1)
+        dur = {}
+        for n in sorted(set(mix)):
+            dur[n] = float(V.vie_group_profile(handle, prec, gi, n, reps)[2])
+        t_ms = sum(dur[n] for n in mix)
+        by = sum(n * 2 * B * s_el + (oct_ * s_el if n > 0 else 0) for n in mix)
+        out.append({"group": gi, "fft": [gp.lx, gp.ly, gp.lz], "box": [gp.bx, gp.by, gp.bz], "systems": gp.n_systems,
+                    "launches": len(mix), "mean_active_systems": float(np.mean(mix)),
+                    "mean_launch_us": 1e3 * t_ms / len(mix), "bytes_per_launch": by / len(mix),
+                    "achieved_GBps": by / (t_ms * 1e-3) / 1e9, "total_ms": t_ms,
+                    "us_at_active": {str(n): round(1e3 * d, 2) for n, d in dur.items()
+                                     if n in (0, 1, 2, 4, 8, 16, 32, max(dur))}})
+    return out
 
 
 def main():
@@ -176,6 +262,15 @@ def main():
                          "0 = skip")
     ap.add_argument("--fgmres-restart", type=int, default=100)
     ap.add_argument("--cgs-maxit", type=int, default=1500, help="step cap of the CGS variant")
+    ap.add_argument("--cgs", action="store_true",
+                    help="also time the CGS variant in FP64 (it diverges on this workload at inner tol 1e-2 and runs "
+                         "to its cap)")
+    ap.add_argument("--roofline-reps", type=int, default=10,
+                    help="repetitions per active-system count when timing the dominant kernel")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="outer steps of the CPU oracle sample")
+    ap.add_argument("--serving-n", type=int, default=12,
+                    help="requests of the short Poisson stream served beside the headline (0 = skip)")
+    ap.add_argument("--serving-rate", type=float, default=10.0, help="its arrival rate (req/s)")
     ap.add_argument("--inner-tol-sweep", default="1e-2,3e-3,1e-3,3e-4,1e-4",
                     help="inner tolerances for one timed headline solve each ('' to skip)")
     ap.add_argument("--fgmres-tol", type=float, default=1e-6,
@@ -215,6 +310,10 @@ def main():
     opts = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=maxit,
                        maxit_inner=case.maxit_inner, precondition=True, precision=prec, max_refine=3)
     st = V.vie_stats()
+    hist_cap = info.n_blocks * 2 * (maxit + 4 * maxit) + 1024   # main loop and corrections
+    hist = (V.ctypes.c_int32 * hist_cap)()
+    st.inner_hist = hist
+    st.inner_hist_cap = hist_cap
     for _ in range(args.warmup):
         V.vie_solve_device(P.handle, e_inc, opts, e_tot, None, st)
     torch.cuda.synchronize()
@@ -232,6 +331,16 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     log(f"timed solves done: {args.steps} in {elapsed:.2f} s")
+    timed_hist = list(hist[:st.inner_hist_len])
+    st.inner_hist = None
+    st.inner_hist_cap = 0
+
+    # the dominant kernel of the timed solves: the z pass of the block group
+    # that spends the most time in it, launch by launch
+    _, grid_groups, block_group = V.vie_plan(grid, case.eps, case.block_id, case.n_blocks)
+    zr = zpass_roofline(V, P.handle, grid_groups, block_group, timed_hist, prec, opts.poll_lag, args.roofline_reps)
+    dom_z = max(zr, key=lambda e: e["total_ms"]) if zr else None
+    log("dominant-kernel timing done")
 
     # the FP64 GPU paths of the same workload, for comparison
     compare = {}
@@ -307,8 +416,11 @@ def main():
             "field_check": golden_error(case, f),
             "rel_field_diff_vs_bicgstab": float(np.linalg.norm(f - mine) / np.linalg.norm(mine)),
             "footprint_bytes": int(P.info().footprint_bytes)}
-        # conjugate gradient squared with FP64 products (its squared residual
-        # polynomial amplifies complex64 rounding): one timed solve
+
+    # conjugate gradient squared with FP64 products (its squared residual
+    # polynomial amplifies complex64 rounding): one timed solve
+    if args.cgs and args.variant_steps > 0 and args.maxit_outer is None:
+        mine = e_tot.cpu().numpy()
         oc = V.make_opts(tol_outer=case.tol_outer, tol_inner=case.tol_inner, maxit_outer=args.cgs_maxit,
                          maxit_inner=case.maxit_inner, precondition=True, precision=V.VIE_FP64,
                          solver=V.VIE_SOLVER_CGS)
@@ -472,6 +584,16 @@ def main():
         Q.close()
         log(f"{name} done")
 
+    # a short Poisson stream of the serving workload (every grid size of its
+    # mix, none left out) through the request server, against the plain FP64
+    # GPU path one request at a time
+    serving = None
+    if args.serving_n > 0 and args.maxit_outer is None:
+        import bench_serving as BS
+        sc, sa, sk = BS.stream_cases(W, args.serving_rate, args.serving_n)
+        serving = BS.measure(V, W, sc, sa, 4, "stream", args.serving_rate, sk, None)
+        log(f"serving stream done: {len(sc)} requests")
+
     if args.calibration_copy:
         ca = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         cb = torch.empty_like(ca)
@@ -506,25 +628,41 @@ def main():
         "refine_steps": stats[-1]["refine_steps"],
         "relres_true": stats[-1]["relres_true"],
         "mvm": mv,
-        "roofline": {"bound": "hbm", "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["achieved"] / HBM_PEAK_GBS, "traffic": traffic, "valu_issue": valu,
-                     "kernel": dom["kernel"] + f" (full-grid product, {args.precision})"},
+        "roofline": ({"bound": "hbm", "achieved": dom_z["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": dom_z["achieved_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                      "kernel": f"z pass of the block group on the {dom_z['fft'][0]}x{dom_z['fft'][1]}x{dom_z['fft'][2]} "
+                                f"transform ({dom_z['systems']} systems, box {dom_z['box']}), {args.precision}; "
+                                f"k_zconv_col<{'float' if prec == V.VIE_MIXED else 'double'}, {dom_z['fft'][2]}, *>",
+                      "launches": dom_z["launches"], "mean_active_systems": dom_z["mean_active_systems"],
+                      "mean_launch_us": dom_z["mean_launch_us"], "bytes_per_launch": dom_z["bytes_per_launch"]}
+                     if dom_z else None),
+        "roofline_groups": zr,
+        "roofline_full_grid": None,
+        "mvm_dominant_pass": {"kernel": dom["kernel"] + f" (full-grid product, {args.precision})",
+                              "achieved": dom["achieved"], "frac": dom["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
+                              "valu_issue": valu},
         "mvm_other_grids": extra,
         "fp64_gpu_paths": compare,
         "solver_variants": variants,
         "inner_tol_sweep": sweep,
         "other_workloads": others,
+        "serving_stream": serving,
         "block_solver_groups": int(info.n_block_solver_groups),
     }
+    big = extra.get("256x256x64", {}).get("mixed" if prec == V.VIE_MIXED else "fp64")
+    if big:
+        res["roofline_full_grid"] = {"bound": "hbm", "achieved": big["algorithmic_GBps"], "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": big["algorithmic_GBps"] / HBM_PEAK_GBS,
+                                     "kernel": "full-grid product (five passes) on 256x256x64, FFT 512x512x128",
+                                     "bytes_per_launch": sum(big["pass_bytes"]), "ms": big["ms"]}
     ge = golden_error(case, e_tot.cpu().numpy())
     if ge is not None:
         res["field_check"] = ge
     log("product profiles done")
     if not args.no_cpu_baseline:
-        # the FP64 GPU path runs the oracle's algorithm: its outer count at
-        # this tolerance stands for the oracle's
-        hint = compare.get("fp64_block_preconditioned", {}).get("outer_iters", stats[-1]["outer_iters"])
-        res["cpu_baseline"] = cpu_baseline(case, hint)
+        res["cpu_baseline"] = cpu_baseline(case, case.tol_outer,
+                                           stats[-1]["outer_iters"] + stats[-1]["refine_iters"], args.cpu_steps)
+        log("cpu baseline done")
     P.close()
     V.vie_context_destroy(ctx)
     print(json.dumps(res), flush=True)

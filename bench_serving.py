@@ -1,13 +1,14 @@
 """Batched-sweep and serving measurements with libvie's request server.
 
   python bench_serving.py sweep  [--n 64] [--slots 4]
-  python bench_serving.py stream [--rate 5] [--n 200] [--max-voxels N] [--slots 4]
+  python bench_serving.py stream [--rates 1,2,5,10,20,50] [--n 200] [--max-voxels N] [--slots 4]
 
 sweep: the solves of the batched sweep (workloads.sweep_case, mixed
 precision, block preconditioner, outer tol 1e-6, inner 1e-2) all submitted
 at once.  stream: a Poisson request stream (workloads.arrivals /
-serving_request) replayed in real time; requests larger than --max-voxels
-are left out of the measured stream (stated in the output).
+serving_request) replayed in real time, one JSON line per rate; by default
+every request is served (grids up to 256x256x64); requests larger than
+--max-voxels are left out of the measured stream (stated in the output).
 
 Each request goes through vie_submit / vie_wait with host arrays (set-up,
 upload and download included).  Reported: solves/s (requests / time from
@@ -95,44 +96,31 @@ def fifo(arrive, service):
     return lat, end
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["sweep", "stream"])
-    ap.add_argument("--n", type=int, default=None)
-    ap.add_argument("--rate", type=float, default=5.0)
-    ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--max-voxels", type=int, default=None)
-    args = ap.parse_args()
+def stream_cases(W, rate, n, max_voxels=None):
+    """The first n requests of the stream at `rate` (optionally without those
+    above max_voxels voxels) and their arrival times from the first one."""
+    arrive_all = W.arrivals(rate, n)
+    cases, arrive, skipped = [], [], []
+    for i in range(n):
+        c = W.serving_request(rate, i)
+        if max_voxels and c.nx * c.ny * c.nz > max_voxels:
+            skipped.append(i)
+            continue
+        cases.append(c)
+        arrive.append(arrive_all[i])
+    arrive = np.asarray(arrive)
+    return cases, arrive - arrive[0], skipped
 
-    import workloads as W
-    from paper_2501_13512_amd import vie as V
 
-    if args.mode == "sweep":
-        n = args.n or 64
-        cases = [W.sweep_case(b) for b in range(n)]
-        arrive = np.zeros(n)
-        skipped = []
-    else:
-        n = args.n or 200
-        arrive_all = W.arrivals(args.rate, n)
-        cases, arrive, skipped = [], [], []
-        for i in range(n):
-            c = W.serving_request(args.rate, i)
-            if args.max_voxels and c.nx * c.ny * c.nz > args.max_voxels:
-                skipped.append(i)
-                continue
-            cases.append(c)
-            arrive.append(arrive_all[i])
-        arrive = np.asarray(arrive)
-        arrive -= arrive[0]
-
+def measure(V, W, cases, arrive, slots, mode, rate, skipped, max_voxels):
+    """Serve `cases` (mixed precision) through a fresh context's server, then
+    run the plain FP64 GPU path of each request alone; one result dict."""
     ctx = V.vie_context_create(0)
-    V.vie_server_start(ctx, args.slots, max(1024, len(cases)))
+    V.vie_server_start(ctx, slots, max(1024, len(cases)))
     res, wall = served(V, W, ctx, cases, arrive)
     lat = np.array([r[1] for r in res])
     codes = [r[0] for r in res]
     span = float(max(arrive[k] + lat[k] for k in range(len(cases))) - arrive[0])
-
     service, diffs = [], []
     for k, c in enumerate(cases):
         code, secs, e64 = fp64_alone(V, W, ctx, c)
@@ -142,12 +130,11 @@ def main():
         diffs.append(float(np.linalg.norm(e_mix - e64) / max(np.linalg.norm(e64), 1e-300)))
     blat, bend = fifo(arrive, service)
     V.vie_context_destroy(ctx)
-
-    out = {
-        "mode": args.mode, "n": len(cases), "slots": args.slots,
-        "rate_req_per_s": None if args.mode == "sweep" else args.rate,
-        "skipped_requests": skipped, "max_voxels": args.max_voxels,
+    return {
+        "mode": mode, "n": len(cases), "slots": slots, "rate_req_per_s": rate,
+        "skipped_requests": skipped, "max_voxels": max_voxels,
         "grids": sorted({f"{c.nx}x{c.ny}x{c.nz}" for c in cases}),
+        "tol_outer": sorted({c.tol_outer for c in cases}),
         "served_mixed": {"solves_per_s": len(cases) / span, "latency_ms": {
             "p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
             "status_counts": {V.STATUS_NAMES.get(s, s): codes.count(s) for s in set(codes)},
@@ -158,8 +145,31 @@ def main():
             "p50": 1e3 * float(np.percentile(blat, 50)), "p99": 1e3 * float(np.percentile(blat, 99))},
             "mean_service_s": float(np.mean(service))},
         "max_rel_field_diff_mixed_vs_fp64": max(diffs),
+        "median_rel_field_diff_mixed_vs_fp64": float(np.median(diffs)),
     }
-    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["sweep", "stream"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--rates", default="1,2,5,10,20,50")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-voxels", type=int, default=None)
+    args = ap.parse_args()
+
+    import workloads as W
+    from paper_2501_13512_amd import vie as V
+
+    if args.mode == "sweep":
+        n = args.n or 64
+        cases = [W.sweep_case(b) for b in range(n)]
+        print(json.dumps(measure(V, W, cases, np.zeros(n), args.slots, "sweep", None, [], None)), flush=True)
+        return
+    for rate in [float(r) for r in args.rates.split(",") if r]:
+        cases, arrive, skipped = stream_cases(W, rate, args.n or 200, args.max_voxels)
+        print(json.dumps(measure(V, W, cases, arrive, args.slots, "stream", rate, skipped, args.max_voxels)),
+              flush=True)
 
 
 if __name__ == "__main__":

@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 11
+#define VIE_ABI_VERSION 12
 
 typedef enum {
   VIE_OK = 0,
@@ -241,9 +241,12 @@ vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t vari
  * memory the problem would hold with none of its spectra cached
  * (zpass_variant = -1, zpass_tune_ms = -1).  groups (optional, caller-owned)
  * receives up to groups_cap entries in the library's group order (batched
- * groups first).  VIE_EINVAL as vie_problem_create. */
+ * groups first); block_group (optional, n_blocks entries) the group of
+ * every block, -1 for a block without voxels.  VIE_EINVAL as
+ * vie_problem_create. */
 vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* block_id, int32_t n_blocks,
-                    int32_t overlap, vie_problem_info* info, vie_group_plan* groups, int32_t groups_cap);
+                    int32_t overlap, vie_problem_info* info, vie_group_plan* groups, int32_t groups_cap,
+                    int32_t* block_group);
 
 /* Incident plane wave E_inc = pol * exp(-j k0 khat . r) at every voxel centre
  * (Sec. III: x-polarised wave along z).  kdir: unit vector (|kdir| = 1 within
@@ -264,6 +267,20 @@ vie_status vie_matvec(vie_problem* p, int32_t precision, const void* x_dev, void
  * milliseconds to pass_ms[0..4].  Synchronises the stream. */
 vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream,
                               int32_t reps, double* pass_ms);
+
+/* Instrumented product of one shape group of blocks, for measurement: marks
+ * the first n_active systems of group `group` (in vie_plan's group order)
+ * iterating and the others converged, runs the group's batched product
+ * `reps` times on `stream` with HIP events around each of its passes (those
+ * of vie_matvec_profile; passes 2 and 4 are empty for groups on the fused
+ * plane kernels) and writes the mean duration of each pass in milliseconds
+ * to pass_ms[0..4].  Kernels, grid and tuned variant are those of the inner
+ * solves; the pass-1 and pass-5 kernels run without the fused vector
+ * updates.  Uses and overwrites the problem's inner solver state: call it
+ * between solves.  Synchronises the stream.  Errors: VIE_EINVAL for a bad
+ * group, count, precision or reps. */
+vie_status vie_group_profile(vie_problem* p, int32_t precision, int32_t group, int32_t n_active, int32_t reps,
+                             void* stream, double* pass_ms);
 
 /* y = K2 x with K2 = blockdiag(A_1, ..., A_N) (eq. (10)): every block's
  * matrix applied to the block's part of x.  Needs block ids. */

@@ -767,8 +767,14 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   __shared__ cx<R> lds[3 * LZ * ZP];
   const int cols = a.ly * a.lx;
   const int tiles = (cols + ZP - 1) / ZP;
+  // Tile-major logical order (the grid is tiles x systems): each XCD takes
+  // a contiguous range of tiles of every system, so the systems still
+  // active are spread over all XCDs whichever they are, and the group's
+  // shared spectrum columns of a tile are reused from that XCD's L2 by the
+  // consecutive workgroups of the other systems.
+  const int nsys = (int)gridDim.x / tiles;
   const int g = __builtin_amdgcn_readfirstlane(xcd_chunked(blockIdx.x, gridDim.x));   // uniform
-  const int sys = g / tiles, tile = g - sys * tiles;
+  const int tile = g / nsys, sys = g - tile * nsys;
   if (!sys_active(a.status, sys)) return;
   const int comp = threadIdx.x / (T * ZP);
   const int rem = threadIdx.x - comp * (T * ZP);

@@ -2139,7 +2139,8 @@ vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info) {
 }
 
 vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* block_id, int32_t n_blocks,
-                    int32_t overlap, vie_problem_info* info, vie_group_plan* groups, int32_t groups_cap) {
+                    int32_t overlap, vie_problem_info* info, vie_group_plan* groups, int32_t groups_cap,
+                    int32_t* block_group) {
   return guarded([&]() -> vie_status {
     if (!grid || !eps_r || !info) fail(VIE_EINVAL, "grid, eps_r and info are required");
     if (overlap < 0 || overlap > 256) fail(VIE_EINVAL, "overlap must be in [0, 256]");
@@ -2159,6 +2160,11 @@ vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* bl
     for (int32_t i = 0; i < groups_cap && i < (int32_t)pl.groups.size(); ++i) {
       const GroupPlan& gp = pl.groups[i];
       groups[i] = vie_group_plan{gp.lx, gp.ly, gp.lz, gp.bx, gp.by, gp.bz, (int32_t)gp.blocks.size(), gp.wg ? 1 : 0};
+    }
+    if (block_group && block_id) {
+      for (int32_t k = 0; k < n_blocks; ++k) block_group[k] = -1;
+      for (size_t gi = 0; gi < pl.groups.size(); ++gi)
+        for (int k : pl.groups[gi].blocks) block_group[k] = (int32_t)gi;
     }
     *info = d;
     return VIE_OK;
@@ -2342,6 +2348,57 @@ vie_status vie_matvec_profile(vie_problem* p, int32_t precision, const void* x_d
           vie::mvm<double>(outer_batch<double>(*p, false), (const c128*)x_dev, (c128*)y_dev, false, s, ev);
         else
           vie::mvm<float>(outer_batch<float>(*p, false), (const c128*)x_dev, (c128*)y_dev, false, s, ev);
+        hip_check(hipEventSynchronize(ev[5]), "profile");
+        for (int i = 0; i < 5; ++i) {
+          float ms = 0;
+          hip_check(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "elapsed");
+          acc[i] += ms;
+        }
+      }
+    } catch (...) {
+      destroy();
+      throw;
+    }
+    destroy();
+    for (int i = 0; i < 5; ++i) pass_ms[i] = acc[i] / reps;
+    return VIE_OK;
+  });
+}
+
+vie_status vie_group_profile(vie_problem* p, int32_t precision, int32_t group, int32_t n_active, int32_t reps,
+                             void* stream, double* pass_ms) {
+  return guarded([&]() -> vie_status {
+    if (!p || !pass_ms) fail(VIE_EINVAL, "problem and pass_ms are required");
+    if (group < 0 || group >= (int32_t)p->groups.size()) fail(VIE_EINVAL, "group out of range");
+    if (precision != VIE_FP64 && precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
+    if (reps < 1 || reps > 100000) fail(VIE_EINVAL, "reps out of range");
+    Group& G = p->groups[group];
+    if (n_active < 0 || n_active > G.nsys) fail(VIE_EINVAL, "n_active out of range");
+    std::lock_guard<std::mutex> lk(p->mu);
+    set_device(p->ctx);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int> st(G.nsys, vie::ST_CONVERGED);
+    for (int q = 0; q < n_active; ++q) st[q] = vie::ST_ACTIVE;
+    hip_check(hipMemcpyAsync(p->d_istatus.as<int>() + G.slot0, st.data(), st.size() * sizeof(int),
+                             hipMemcpyHostToDevice, s),
+              "profile status");
+    hip_check(hipStreamSynchronize(s), "profile status");
+    hipEvent_t ev[6];
+    {
+      ApiShared api;
+      for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+    }
+    auto destroy = [&] {
+      ApiShared api;
+      for (auto& e : ev) (void)hipEventDestroy(e);
+    };
+    double acc[5] = {0, 0, 0, 0, 0};
+    try {
+      for (int r = 0; r < reps; ++r) {
+        if (precision == VIE_FP64)
+          vie::mvm<double>(group_batch<double>(*p, G, true), G.vec[V_P], G.vec[V_V], false, s, ev);
+        else
+          vie::mvm<float>(group_batch<float>(*p, G, true), G.vec[V_P], G.vec[V_V], false, s, ev);
         hip_check(hipEventSynchronize(ev[5]), "profile");
         for (int i = 0; i < 5; ++i) {
           float ms = 0;

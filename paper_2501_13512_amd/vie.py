@@ -57,7 +57,7 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
                "vie_problem_create", "vie_problem_create_overlap", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass",
                "vie_plane_wave", "vie_plan",
-               "vie_matvec", "vie_matvec_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
+               "vie_matvec", "vie_matvec_profile", "vie_group_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
                "vie_solve_batch",
                "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
                "vie_total_field_box", "vie_far_field", "vie_far_field_noalloc", "vie_rcs")
@@ -121,9 +121,10 @@ for _name, _args in {
     "vie_problem_set_zpass": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_plane_wave": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
     "vie_plan": [ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vie_problem_info),
-                 _vp, ctypes.c_int32],
+                 _vp, ctypes.c_int32, _vp],
     "vie_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
     "vie_matvec_profile": [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp],
+    "vie_group_profile": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp],
     "vie_block_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
     "vie_precond_apply": [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                           ctypes.POINTER(ctypes.c_int64)],
@@ -210,14 +211,16 @@ def vie_problem_set_zpass(p: int, precision: int, variant: int) -> None:
 
 def vie_plan(grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray], n_blocks: int, overlap: int = 0,
              groups_cap: int = 64):
-    """Host-only block plan: (vie_problem_info, [vie_group_plan, ...])."""
+    """Host-only block plan: (vie_problem_info, [vie_group_plan, ...], group of every block or None)."""
     e = np.ascontiguousarray(eps, dtype=np.complex128)
     b = None if block_id is None else np.ascontiguousarray(block_id, dtype=np.int32)
     info = vie_problem_info()
     groups = (vie_group_plan * max(groups_cap, 1))()
+    bg = np.full(max(int(n_blocks), 1), -1, dtype=np.int32) if b is not None else None
     _check(_lib.vie_plan(ctypes.byref(grid), _np_ptr(e), _np_ptr(b) if b is not None else None, int(n_blocks),
-                         int(overlap), ctypes.byref(info), groups, int(groups_cap)), "vie_plan")
-    return info, [groups[i] for i in range(min(info.n_groups, groups_cap))]
+                         int(overlap), ctypes.byref(info), groups, int(groups_cap),
+                         _np_ptr(bg) if bg is not None else None), "vie_plan")
+    return info, [groups[i] for i in range(min(info.n_groups, groups_cap))], (bg[:n_blocks] if bg is not None else None)
 
 
 def vie_plane_wave(grid: vie_grid, kdir: Sequence[float], pol: Sequence[complex]) -> np.ndarray:
@@ -250,6 +253,13 @@ def vie_matvec_profile(p: int, precision: int, x, y, reps: int, stream=None) -> 
     ms = np.zeros(5, dtype=np.float64)
     _check(_lib.vie_matvec_profile(p, precision, _dev(x), _dev(y), _stream(stream), int(reps), _np_ptr(ms)),
            "vie_matvec_profile")
+    return ms
+
+
+def vie_group_profile(p: int, precision: int, group: int, n_active: int, reps: int, stream=None) -> np.ndarray:
+    ms = np.zeros(5, dtype=np.float64)
+    _check(_lib.vie_group_profile(p, precision, int(group), int(n_active), int(reps), _stream(stream), _np_ptr(ms)),
+           "vie_group_profile")
     return ms
 
 

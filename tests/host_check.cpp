@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <random>
 #include <string>
@@ -85,8 +86,19 @@ static Input random_input(unsigned seed, int nx, int ny, int nz, int n_blocks, d
 
 static vie_status plan(const Input& in, int overlap, vie_problem_info* info, std::vector<vie_group_plan>* gp) {
   gp->assign(64, vie_group_plan{});
-  return vie_plan(&in.g, in.eps.data(), in.bid.empty() ? nullptr : in.bid.data(), in.n_blocks, overlap, info,
-                  gp->data(), (int32_t)gp->size());
+  std::vector<int32_t> bg(std::max(1, in.n_blocks), -7);
+  const vie_status st = vie_plan(&in.g, in.eps.data(), in.bid.empty() ? nullptr : in.bid.data(), in.n_blocks,
+                                 overlap, info, gp->data(), (int32_t)gp->size(), in.bid.empty() ? nullptr : bg.data());
+  if (st == VIE_OK && !in.bid.empty()) {
+    // every non-empty block in exactly one group, in range
+    std::vector<int> per(64, 0);
+    for (int k = 0; k < in.n_blocks; ++k) {
+      CHECK(bg[k] >= -1 && bg[k] < info->n_groups);
+      if (bg[k] >= 0 && bg[k] < 64) per[bg[k]]++;
+    }
+    for (int i = 0; i < info->n_groups && i < 64; ++i) CHECK(per[i] == (*gp)[i].n_systems);
+  }
+  return st;
 }
 
 int main() {
@@ -154,15 +166,15 @@ int main() {
     CHECK(plan(bad, 0, &info, &gp) == VIE_EINVAL);
     bad = in;
     bad.g.nx = 300;
-    CHECK(vie_plan(&bad.g, in.eps.data(), nullptr, 0, 0, &info, nullptr, 0) == VIE_EINVAL);
+    CHECK(vie_plan(&bad.g, in.eps.data(), nullptr, 0, 0, &info, nullptr, 0, nullptr) == VIE_EINVAL);
     bad = in;
     bad.g.dz = -1.0;
     CHECK(plan(bad, 0, &info, &gp) == VIE_EINVAL);
     CHECK(plan(in, -1, &info, &gp) == VIE_EINVAL);
-    CHECK(vie_plan(&in.g, in.eps.data(), in.bid.data(), in.n_blocks, 0, &info, nullptr, 4) == VIE_EINVAL);
-    CHECK(vie_plan(nullptr, in.eps.data(), nullptr, 0, 0, &info, nullptr, 0) == VIE_EINVAL);
+    CHECK(vie_plan(&in.g, in.eps.data(), in.bid.data(), in.n_blocks, 0, &info, nullptr, 4, nullptr) == VIE_EINVAL);
+    CHECK(vie_plan(nullptr, in.eps.data(), nullptr, 0, 0, &info, nullptr, 0, nullptr) == VIE_EINVAL);
     CHECK(std::string(vie_last_error()).size() > 0);
-    CHECK(vie_plan(&in.g, in.eps.data(), in.bid.data(), 0, 0, &info, nullptr, 0) == VIE_EINVAL);
+    CHECK(vie_plan(&in.g, in.eps.data(), in.bid.data(), 0, 0, &info, nullptr, 0, nullptr) == VIE_EINVAL);
     CHECK(vie_solve(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == VIE_EINVAL);
     CHECK(vie_matvec(nullptr, 0, nullptr, nullptr, nullptr) == VIE_EINVAL);
     CHECK(vie_problem_destroy(nullptr) == VIE_OK);

@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 
 def test_abi_version():
-    assert V.vie_abi_version() == 11
+    assert V.vie_abi_version() == 12
 
 
 def _has_gpu():
@@ -84,11 +84,13 @@ def test_plan_of_the_metasurface_case():
     grid uses 256x256x64."""
     case = W.metasurface()
     g = V.make_grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.wavelength)
-    info, groups = V.vie_plan(g, case.eps, case.block_id, case.n_blocks)
+    info, groups, bgrp = V.vie_plan(g, case.eps, case.block_id, case.n_blocks)
     assert (info.lx, info.ly, info.lz) == (256, 256, 64)
     assert info.n_blocks == 65 and info.n_groups == len(groups) == 2
     shapes = sorted(((gp.lx, gp.ly, gp.lz), gp.n_systems) for gp in groups)
     assert shapes == [((32, 32, 48), 64), ((256, 256, 16), 1)]
+    pillar = [i for i, gp in enumerate(groups) if gp.n_systems == 64][0]
+    assert list(bgrp[:64]) == [pillar] * 64 and bgrp[64] == 1 - pillar
     assert info.footprint_bytes > 0 and info.zpass_variant[0] == -1
     with pytest.raises(V.VieError) as e:
         bad = case.block_id.copy()

@@ -340,7 +340,7 @@ def serving_request(rate: float, i: int) -> Case:
     Kind 0, dielectric pillars: one per 16x16-voxel xy cell (row by row), eps
     ``rng.uniform(2, 6)``, radius ``rng.uniform(0.25, 0.45) * 16`` voxels,
     height ``rng.uniform(0.5, 1) * nz`` from z = 0; one block per pillar;
-    mixed precision with the block preconditioner, outer tol 1e-6, inner
+    mixed precision with the block preconditioner, outer tol 3e-7, inner
     1e-2.
     Kind 1, plasmonic cell (the 96x96x64 cell scaled to the grid): slab
     z < 3 nz / 8 with eps 12 - 0.5j, absorbing layer above with eps
@@ -349,7 +349,13 @@ def serving_request(rate: float, i: int) -> Case:
     64`` voxels (at least 2) each; spacing lambda / 40 as in that cell (20 nm
     under-resolves the metal); blocks per sphere, layer and slab; mixed
     precision without preconditioner (the block preconditioner stalls on
-    metal-sphere blocks), outer tol 1e-6, at most 6000 outer steps.
+    metal-sphere blocks), outer tol 3e-7, at most 8000 outer steps.
+
+    The outer tolerance 3e-7 (instead of the 1e-6 of the batched sweep)
+    makes two solves of a request at that tolerance (mixed precision, and
+    the plain FP64 path it is compared with) agree to about 1e-5: a solve
+    stopped at relative residual r is some multiple of r away from the
+    converged field.
     """
     rng = np.random.default_rng([5000 + int(rate), int(i)])
     nx, ny, nz = SERVING_GRIDS[int(rng.integers(len(SERVING_GRIDS)))]
@@ -371,7 +377,7 @@ def serving_request(rate: float, i: int) -> Case:
                 eps[inside] = e
                 bid[inside] = nb
                 nb += 1
-        return Case(f"req{rate}_{i}", nx, ny, nz, d, d, d, lam, eps, bid, nb, tol_outer=1e-6, tol_inner=1e-2,
+        return Case(f"req{rate}_{i}", nx, ny, nz, d, d, d, lam, eps, bid, nb, tol_outer=3e-7, tol_inner=1e-2,
                     precision="mixed", note=f"serving request: pillars {nx}x{ny}x{nz}, lambda {lam:.1f} nm")
     d = lam / 40.0
     zs = (3 * nz) // 8
@@ -389,8 +395,8 @@ def serving_request(rate: float, i: int) -> Case:
             eps[inside] = -15.0 - 1.0j
             bid[inside] = nb
             nb += 1
-    return Case(f"req{rate}_{i}", nx, ny, nz, d, d, d, lam, eps, bid, nb, tol_outer=1e-6, tol_inner=3e-2,
-                maxit_outer=6000, precision="mixed",
+    return Case(f"req{rate}_{i}", nx, ny, nz, d, d, d, lam, eps, bid, nb, tol_outer=3e-7, tol_inner=3e-2,
+                maxit_outer=8000, precision="mixed",
                 note=f"serving request: plasmonic cell {nx}x{ny}x{nz}, lambda {lam:.1f} nm")
 
 
