@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 12
+#define VIE_ABI_VERSION 13
 
 typedef enum {
   VIE_OK = 0,
@@ -172,6 +172,9 @@ typedef struct {
   int32_t n_block_solver_groups;  /* groups solved one workgroup per block */
   int32_t zpass_variant[2];   /* z-pass kernel picked for the full-grid product [FP64, MIXED] */
   float zpass_tune_ms[2][5];  /* autotuner time per z-pass variant (3 runs; -1 = not timed) */
+  int32_t plane_variant[2];   /* plane-kernel variant picked for the full-grid product [FP64, MIXED]
+                                 (0 when its transforms are not square and small enough) */
+  float plane_tune_ms[2][3];  /* autotuner time per plane variant (3 forward + inverse pairs; -1 = not timed) */
 } vie_problem_info;
 
 /* One shape group of a block plan: blocks whose bounding boxes share FFT
@@ -233,13 +236,23 @@ vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info);
  * variant. */
 vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t variant);
 
+/* Pins the plane-kernel variant of every FFT product of the problem in one
+ * precision (products whose x and y lengths are equal and at most 64 run
+ * the x and y transforms of a z-plane in one kernel; the variants differ in
+ * the planes one workgroup takes: 0 as many as 48 KB of LDS hold, at most
+ * 16; 1 at most two; 2 one); -1 restores the autotuned choice.  Same
+ * transform, results agree to rounding (tested).  Synchronises the device;
+ * call it while no work of the problem is in flight.  Errors: VIE_EINVAL
+ * for a bad precision or variant. */
+vie_status vie_problem_set_plane(vie_problem* p, int32_t precision, int32_t variant);
+
 /* The block plan that vie_problem_create_overlap would build for these
  * inputs (same arguments and validation; overlap 0 = vie_problem_create),
  * computed on the host with no device or context: info receives the full
  * grid's FFT lengths, the non-empty block count, the shape groups, the
  * groups run by the one-workgroup solver and footprint_bytes, the device
  * memory the problem would hold with none of its spectra cached
- * (zpass_variant = -1, zpass_tune_ms = -1).  groups (optional, caller-owned)
+ * (zpass_variant, zpass_tune_ms, plane_variant, plane_tune_ms all -1).  groups (optional, caller-owned)
  * receives up to groups_cap entries in the library's group order (batched
  * groups first); block_group (optional, n_blocks entries) the group of
  * every block, -1 for a block without voxels.  VIE_EINVAL as

@@ -48,6 +48,7 @@ struct MvmBatch {
   const TwiddleSet<R>* tw; // host-side pointer table (values are device pointers)
   int zvariant;            // z-pass kernel variant (see tune_zpass)
   int plane;               // 1: x and y transforms fused per z-plane (plane_supported(lx, ly))
+  int pvariant;            // plane kernels: planes per workgroup variant (see tune_plane)
 };
 
 // Square transforms small enough for the fused plane kernels.
@@ -100,6 +101,14 @@ void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c
 constexpr int kZPassVariants = 5;
 template <typename R>
 int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out = nullptr);
+
+// Plane-kernel variants (planes per workgroup: 0 as LDS allows, 1 two,
+// 2 one).  tune_plane times the forward and inverse plane passes of each on
+// the batch's work buffer with x as input and y as output (clobbers all
+// three) and returns the fastest; 0 for batches without plane kernels.
+constexpr int kPlaneVariants = 3;
+template <typename R>
+int tune_plane(const MvmBatch<R>& b, const c128* x, c128* y, hipStream_t s, float* ms_out = nullptr);
 
 // Chunks per system of the fused first/last passes (for partial sizing).
 int64_t mvm_row_tiles(int lx, int nz, int ny);

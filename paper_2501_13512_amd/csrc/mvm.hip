@@ -278,20 +278,26 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
 // trip through HBM fewer each way; same BiCGSTAB fusion as the row kernels).
 // A workgroup takes NPL consecutive planes (c, z) of one system; LDS holds
 // them as [NPL][L][L + 1] (rows padded against bank conflicts on columns).
-template <typename R, int L>
+// Variant PV sets NPL: 0 as many planes as 48 KB of LDS hold (at most 16),
+// 1 at most two, 2 one plane.  Fewer planes per workgroup mean more, shorter
+// workgroups: the product's latency falls when few systems are active (two
+// 32 x 32 planes of a 16 x 16 box take 3 transform rounds of 32 pencils
+// where five planes take 8), at the cost of more workgroups to dispatch.
+template <typename R, int L, int PV>
 struct PlaneGeo {
   static constexpr int ES = (int)sizeof(cx<R>);
   static constexpr int LP = L + 1;
-  static constexpr int NPL = cmax(1, cmin(16, (48 * 1024) / (L * LP * ES)));
+  static constexpr int NPL_LDS = cmax(1, cmin(16, (48 * 1024) / (L * LP * ES)));
+  static constexpr int NPL = PV == 0 ? NPL_LDS : (PV == 1 ? cmin(2, NPL_LDS) : 1);
   static constexpr int BT = 256;
   static constexpr int T = PlanInfo<L>::max_butterflies;
   static constexpr int PP = BT / T;
   static_assert(BT % T == 0, "pencil threads must divide the workgroup");
 };
 
-template <typename R, int L>
-__global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_fwd(RowArgs<R> a) {
-  using G = PlaneGeo<R, L>;
+template <typename R, int L, int PV>
+__global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_fwd(RowArgs<R> a) {
+  using G = PlaneGeo<R, L, PV>;
   constexpr int T = G::T, PP = G::PP, LP = G::LP, NPL = G::NPL, BT = G::BT;
   __shared__ cx<R> lds[NPL * L * LP];
   const int planes = 3 * a.nz;
@@ -408,9 +414,9 @@ __global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_fwd(RowArgs<R> a
   }
 }
 
-template <typename R, int L>
-__global__ void __launch_bounds__((PlaneGeo<R, L>::BT)) k_plane_inv_local(RowArgs<R> a) {
-  using G = PlaneGeo<R, L>;
+template <typename R, int L, int PV>
+__global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_inv_local(RowArgs<R> a) {
+  using G = PlaneGeo<R, L, PV>;
   constexpr int T = G::T, PP = G::PP, LP = G::LP, NPL = G::NPL, BT = G::BT;
   __shared__ cx<R> lds[NPL * L * LP];
   const int planes = 3 * a.nz;
@@ -1003,18 +1009,29 @@ bool plane_supported(int lx, int ly) {
   return false;
 }
 
+template <typename R, int L, int PV>
+static void launch_plane_pv(bool fwd, const RowArgs<R>& a, int nsys, hipStream_t s) {
+  using G = PlaneGeo<R, L, PV>;
+  const int tiles = (3 * a.nz + G::NPL - 1) / G::NPL;
+  if (fwd)
+    hipLaunchKernelGGL((k_plane_fwd<R, L, PV>), dim3(tiles * nsys), dim3(G::BT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_plane_inv_local<R, L, PV>), dim3(tiles * nsys), dim3(G::BT), 0, s, a);
+}
+
 template <typename R>
-static void launch_plane(bool fwd, int L, const RowArgs<R>& a, int nsys, hipStream_t s) {
+static void launch_plane(bool fwd, int L, int pv, const RowArgs<R>& a, int nsys, hipStream_t s) {
+  if (pv < 0 || pv >= kPlaneVariants) throw std::runtime_error("plane variant out of range");
   switch (L) {
-#define C(l)                                                                                      \
-  case l: {                                                                                       \
-    using G = PlaneGeo<R, l>;                                                                     \
-    const int tiles = (3 * a.nz + G::NPL - 1) / G::NPL;                                           \
-    if (fwd)                                                                                      \
-      hipLaunchKernelGGL((k_plane_fwd<R, l>), dim3(tiles * nsys), dim3(G::BT), 0, s, a);          \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_plane_inv_local<R, l>), dim3(tiles * nsys), dim3(G::BT), 0, s, a);    \
-    break;                                                                                        \
+#define C(l)                                                 \
+  case l: {                                                  \
+    if (pv == 0)                                             \
+      launch_plane_pv<R, l, 0>(fwd, a, nsys, s);             \
+    else if (pv == 1)                                        \
+      launch_plane_pv<R, l, 1>(fwd, a, nsys, s);             \
+    else                                                     \
+      launch_plane_pv<R, l, 2>(fwd, a, nsys, s);             \
+    break;                                                   \
   }
     VIE_PLANE_CASES(C)
 #undef C
@@ -1067,7 +1084,7 @@ void mvm_pass1(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c
   RowArgs<R> ra = row_args<R>(b, k, f, x, nullptr, mask_input);
   ra.in_mode = f.in_mode;
   if (b.plane)
-    launch_plane<R>(true, b.lx, ra, b.nsys, s);
+    launch_plane<R>(true, b.lx, b.pvariant, ra, b.nsys, s);
   else
     launch_row_fwd<R>(b.lx, ra, b.nsys, s);
 }
@@ -1116,7 +1133,7 @@ void mvm_pass5(const MvmBatch<R>& b, const KBatch* k, const FuseArgs& f, const c
   RowArgs<R> ra = row_args<R>(b, k, f, x, y, false);
   ra.out_mode = f.out_mode;
   if (b.plane)
-    launch_plane<R>(false, b.lx, ra, b.nsys, s);
+    launch_plane<R>(false, b.lx, b.pvariant, ra, b.nsys, s);
   else
     launch_row_inv<R>(b.lx, ra, b.nsys, s);
 }
@@ -1218,6 +1235,54 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out) {
 template int tune_zpass<float>(const MvmBatch<float>&, hipStream_t, float*);
 template int tune_zpass<double>(const MvmBatch<double>&, hipStream_t, float*);
 
+// Autotuning of the plane kernels (batches with b.plane): time the forward
+// and inverse plane passes of each variant (plain product, every system
+// active) on the batch's own work buffer, x as input and y as output (all
+// overwritten; call before they hold live data); returns the fastest.
+template <typename R>
+int tune_plane(const MvmBatch<R>& b, const c128* x, c128* y, hipStream_t s, float* ms_out) {
+  if (ms_out)
+    for (int v = 0; v < kPlaneVariants; ++v) ms_out[v] = -1.0f;
+  if (b.nsys <= 0 || !b.plane) return 0;
+  if (!x || !y) throw std::runtime_error("tune_plane: missing vectors");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  {
+    ApiShared api;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      throw std::runtime_error("hipEventCreate failed");
+  }
+  MvmBatch<R> bb = b;
+  bb.status = nullptr;
+  const FuseArgs none{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+  float best = 1e30f;
+  int best_v = 0;
+  for (int v = 0; v < kPlaneVariants; ++v) {
+    bb.pvariant = v;
+    auto run = [&]() {
+      mvm_pass1<R>(bb, nullptr, none, x, false, s);
+      mvm_pass5<R>(bb, nullptr, none, x, y, s);
+    };
+    run();   // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3; ++r) run();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms_out) ms_out[v] = ms;
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  {
+    ApiShared api;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return best_v;
+}
+
 #define VIE_MVM_INST(R)                                                                                           \
   template void mvm<R>(const MvmBatch<R>&, const c128*, c128*, bool, hipStream_t, hipEvent_t*);                  \
   template void mvm_pass1<R>(const MvmBatch<R>&, const KBatch*, const FuseArgs&, const c128*, bool, hipStream_t); \
@@ -1226,6 +1291,8 @@ template int tune_zpass<double>(const MvmBatch<double>&, hipStream_t, float*);
 VIE_MVM_INST(float)
 VIE_MVM_INST(double)
 #undef VIE_MVM_INST
+template int tune_plane<float>(const MvmBatch<float>&, const c128*, c128*, hipStream_t, float*);
+template int tune_plane<double>(const MvmBatch<double>&, const c128*, c128*, hipStream_t, float*);
 
 int64_t mvm_row_tiles(int lx, int nz, int ny) {
   const int64_t rows = 3 * (int64_t)nz * ny;

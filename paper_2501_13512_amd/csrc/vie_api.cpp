@@ -220,6 +220,7 @@ struct vie_context {
   std::map<SpecKey, std::weak_ptr<Spectra>> cache;
   size_t reserved = 0;   // bytes reserved by requests admitted to the server
   std::map<std::array<int, 8>, std::pair<int, std::array<float, vie::kZPassVariants>>> ztune;
+  std::map<std::array<int, 8>, std::pair<int, std::array<float, vie::kPlaneVariants>>> ptune;
   std::unique_ptr<Server> server;
   std::mutex server_mu;
   double* far_scratch = nullptr;   // this device's copy of the far field's fixed scratch array
@@ -264,6 +265,7 @@ struct Group {
   DevBuf chi, work, vecs;
   DevBuf sys_origin;     // expanded blocks: box origin of each system (int4)
   int zvar[2] = {0, 0};  // tuned z-pass variant per precision ([0] FP64, [1] FP32)
+  int pvar[2] = {0, 0};  // tuned plane-kernel variant per precision
   c128* vec[8];  // B, X, R, RHAT, P, V, S, T
   int slot0;     // first entry in the problem's inner status/state arrays
   bool wg = false;  // small enough for the one-workgroup block solver
@@ -324,6 +326,8 @@ struct vie_problem {
   int64_t pstride = 0;
   int zvar[2] = {0, 0};
   float ztune_ms[2][vie::kZPassVariants] = {};
+  int pvar[2] = {0, 0};
+  float ptune_ms[2][vie::kPlaneVariants] = {};
   // inner systems of all groups: partials (per-system stride ipstride)
   DevBuf d_ipartials, d_ipartials2, d_intile;
   int64_t ipstride = 0;
@@ -484,6 +488,7 @@ MvmBatch<R> outer_batch(vie_problem& P, bool gated) {
   b.tw = tw_set<R>(P.ctx);
   b.zvariant = P.zvar[sizeof(R) == sizeof(float) ? 1 : 0];
   b.plane = vie::plane_supported(b.lx, b.ly) ? 1 : 0;
+  b.pvariant = P.pvar[sizeof(R) == sizeof(float) ? 1 : 0];
   return b;
 }
 
@@ -508,6 +513,7 @@ MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
   b.tw = tw_set<R>(P.ctx);
   b.zvariant = G.zvar[sizeof(R) == sizeof(float) ? 1 : 0];
   b.plane = vie::plane_supported(b.lx, b.ly) ? 1 : 0;
+  b.pvariant = G.pvar[sizeof(R) == sizeof(float) ? 1 : 0];
   return b;
 }
 
@@ -1609,6 +1615,30 @@ int cached_zvariant(vie_context* ctx, const MvmBatch<R>& b, hipStream_t s, float
   return it->second.first;
 }
 
+// Plane-kernel variant for a batch shape, tuned once per context, shape and
+// precision as the z pass; x and y: device vectors of the batch that hold
+// no data yet (clobbered).
+template <typename R>
+int cached_pvariant(vie_context* ctx, const MvmBatch<R>& b, const c128* x, c128* y, hipStream_t s, float* ms) {
+  const std::array<int, 8> key{(int)sizeof(R), b.nx, b.ny, b.nz, b.lx, b.ly, b.lz, b.nsys};
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->ptune.find(key);
+    if (it != ctx->ptune.end()) {
+      if (ms)
+        for (int v = 0; v < vie::kPlaneVariants; ++v) ms[v] = it->second.second[v];
+      return it->second.first;
+    }
+  }
+  std::array<float, vie::kPlaneVariants> t{};
+  const int v = vie::tune_plane<R>(b, x, y, s, t.data());
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->ptune.emplace(key, std::make_pair(v, t)).first;   // first tuning wins
+  if (ms)
+    for (int q = 0; q < vie::kPlaneVariants; ++q) ms[q] = it->second.second[q];
+  return it->second.first;
+}
+
 // inner_only: the blocks and their inner solves only (no full-grid operator:
 // no outer spectra, work buffer or Krylov vectors); used for the stacked
 // replica of preconditioned batches.
@@ -1761,6 +1791,8 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     for (auto& G : P->groups) {
       G.zvar[0] = cached_zvariant<double>(ctx, group_batch<double>(*P, G, false), s, nullptr);
       G.zvar[1] = cached_zvariant<float>(ctx, group_batch<float>(*P, G, false), s, nullptr);
+      G.pvar[0] = cached_pvariant<double>(ctx, group_batch<double>(*P, G, false), G.vec[0], G.vec[1], s, nullptr);
+      G.pvar[1] = cached_pvariant<float>(ctx, group_batch<float>(*P, G, false), G.vec[0], G.vec[1], s, nullptr);
     }
     if (P->groups.size() > 1) {
       ApiShared api;
@@ -1792,6 +1824,10 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
   if (!inner_only) {
     P->zvar[0] = cached_zvariant<double>(ctx, outer_batch<double>(*P, false), s, P->ztune_ms[0]);
     P->zvar[1] = cached_zvariant<float>(ctx, outer_batch<float>(*P, false), s, P->ztune_ms[1]);
+    P->pvar[0] = cached_pvariant<double>(ctx, outer_batch<double>(*P, false), P->vec[V_B], P->vec[V_TMP1], s,
+                                         P->ptune_ms[0]);
+    P->pvar[1] = cached_pvariant<float>(ctx, outer_batch<float>(*P, false), P->vec[V_B], P->vec[V_TMP1], s,
+                                        P->ptune_ms[1]);
   }
   hip_check(hipStreamSynchronize(s), "problem set-up");
   return P;
@@ -2119,6 +2155,46 @@ vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t vari
   });
 }
 
+vie_status vie_problem_set_plane(vie_problem* p, int32_t precision, int32_t variant) {
+  return guarded([&]() -> vie_status {
+    if (!p) fail(VIE_EINVAL, "problem is NULL");
+    if (precision != VIE_FP64 && precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
+    if (variant < -1 || variant >= vie::kPlaneVariants) fail(VIE_EINVAL, "plane-kernel variant out of range");
+    set_device(p->ctx);
+    {
+      ApiShared api;
+      hip_check(hipDeviceSynchronize(), "synchronise");
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+    const int q = precision == VIE_MIXED ? 1 : 0;
+    for (vie_problem* x : {p, p->replica.get()}) {
+      if (!x) continue;
+      if (variant >= 0) {
+        x->pvar[q] = variant;
+        for (auto& G : x->groups) G.pvar[q] = variant;
+      } else {
+        // the choices cached at set-up (tuned once per shape)
+        std::lock_guard<std::mutex> ck(x->ctx->mu);
+        auto tuned = [&](int sz, int nx, int ny, int nz, int lx, int ly, int lz, int nsys) {
+          auto it = x->ctx->ptune.find({sz, nx, ny, nz, lx, ly, lz, nsys});
+          return it == x->ctx->ptune.end() ? 0 : it->second.first;
+        };
+        const int sz = q == 1 ? (int)sizeof(float) : (int)sizeof(double);
+        if (x->spec) x->pvar[q] = tuned(sz, x->g.nx, x->g.ny, x->g.nz, x->lx, x->ly, x->lz, 1);
+        for (auto& G : x->groups) G.pvar[q] = tuned(sz, G.bx, G.by, G.bz, G.lx, G.ly, G.lz, G.nsys);
+      }
+      // captured inner steps hold the old kernels
+      ApiShared api;
+      for (auto& G : x->groups)
+        if (G.graph[q]) {
+          (void)hipGraphExecDestroy(G.graph[q]);
+          G.graph[q] = nullptr;
+        }
+    }
+    return VIE_OK;
+  });
+}
+
 vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info) {
   return guarded([&]() -> vie_status {
     if (!p || !info) fail(VIE_EINVAL, "problem and info are required");
@@ -2130,9 +2206,12 @@ vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info) {
     info->footprint_bytes = (int64_t)p->footprint;
     info->n_block_solver_groups = p->n_wg_groups;
     static_assert(vie::kZPassVariants == 5, "vie_problem_info holds 5 z-pass timings");
+    static_assert(vie::kPlaneVariants == 3, "vie_problem_info holds 3 plane-kernel timings");
     for (int q = 0; q < 2; ++q) {
       info->zpass_variant[q] = p->zvar[q];
       for (int v = 0; v < vie::kZPassVariants; ++v) info->zpass_tune_ms[q][v] = p->ztune_ms[q][v];
+      info->plane_variant[q] = p->pvar[q];
+      for (int v = 0; v < vie::kPlaneVariants; ++v) info->plane_tune_ms[q][v] = p->ptune_ms[q][v];
     }
     return VIE_OK;
   });
@@ -2156,6 +2235,9 @@ vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* bl
     d.footprint_bytes = (int64_t)plan_footprint(nullptr, pl, true);
     d.zpass_variant[0] = d.zpass_variant[1] = -1;
     for (auto& row : d.zpass_tune_ms)
+      for (auto& v : row) v = -1.0f;
+    d.plane_variant[0] = d.plane_variant[1] = -1;
+    for (auto& row : d.plane_tune_ms)
       for (auto& v : row) v = -1.0f;
     for (int32_t i = 0; i < groups_cap && i < (int32_t)pl.groups.size(); ++i) {
       const GroupPlan& gp = pl.groups[i];

@@ -55,7 +55,7 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
                 -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL", -8: "VIE_ETIMEDOUT"}
 
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
-               "vie_problem_create", "vie_problem_create_overlap", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass",
+               "vie_problem_create", "vie_problem_create_overlap", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass", "vie_problem_set_plane",
                "vie_plane_wave", "vie_plan",
                "vie_matvec", "vie_matvec_profile", "vie_group_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
                "vie_solve_batch",
@@ -96,7 +96,8 @@ class vie_problem_info(ctypes.Structure):
     _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("lz", ctypes.c_int32),
                 ("n_blocks", ctypes.c_int32), ("n_groups", ctypes.c_int32),
                 ("footprint_bytes", ctypes.c_int64), ("n_block_solver_groups", ctypes.c_int32),
-                ("zpass_variant", ctypes.c_int32 * 2), ("zpass_tune_ms", (ctypes.c_float * 5) * 2)]
+                ("zpass_variant", ctypes.c_int32 * 2), ("zpass_tune_ms", (ctypes.c_float * 5) * 2),
+                ("plane_variant", ctypes.c_int32 * 2), ("plane_tune_ms", (ctypes.c_float * 3) * 2)]
 
 
 class vie_group_plan(ctypes.Structure):
@@ -119,6 +120,7 @@ for _name, _args in {
     "vie_problem_destroy": [_vp],
     "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
     "vie_problem_set_zpass": [_vp, ctypes.c_int32, ctypes.c_int32],
+    "vie_problem_set_plane": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_plane_wave": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
     "vie_plan": [ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vie_problem_info),
                  _vp, ctypes.c_int32, _vp],
@@ -207,6 +209,10 @@ def vie_problem_get_info(p: int) -> vie_problem_info:
 
 def vie_problem_set_zpass(p: int, precision: int, variant: int) -> None:
     _check(_lib.vie_problem_set_zpass(p, int(precision), int(variant)), "vie_problem_set_zpass")
+
+
+def vie_problem_set_plane(p: int, precision: int, variant: int) -> None:
+    _check(_lib.vie_problem_set_plane(p, int(precision), int(variant)), "vie_problem_set_plane")
 
 
 def vie_plan(grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray], n_blocks: int, overlap: int = 0,

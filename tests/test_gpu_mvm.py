@@ -182,3 +182,99 @@ def test_pinned_zpass_preconditioned_solve(vie_ctx):
     finally:
         V.vie_problem_set_zpass(P.handle, V.VIE_FP64, -1)
         P.close()
+
+
+PSHAPES = [(6, 6, 6), (9, 8, 8), (5, 12, 12), (7, 16, 16), (4, 20, 20), (3, 30, 30)]   # x, y lengths 12 ... 64
+
+
+@pytest.mark.parametrize("prec", [V.VIE_FP64, V.VIE_MIXED])
+@pytest.mark.parametrize("shape", PSHAPES)
+def test_plane_variants_agree(vie_ctx, shape, prec):
+    """Every plane-kernel variant (pinned with vie_problem_set_plane) gives
+    the oracle's product on square x-y transforms of every plane length,
+    full-grid and block-diagonal, and the variants agree to rounding."""
+    seed = 7100 + shape[1]
+    case = W.random_tiny(seed, shape, fill=0.8, n_blocks=3)
+    g = op.Grid.from_case(case)
+    x = _rand(seed, case.shape)
+    want = op.FFTOperator(g)(x * g.mask)
+    want_b = _oracle_block_matvec(case, x * g.mask)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        xd = torch.from_numpy(x).cuda()
+        outs = {}
+        for v in range(3):
+            V.vie_problem_set_plane(P.handle, prec, v)
+            yd = torch.full_like(xd, complex("nan"))
+            V.vie_matvec(P.handle, prec, xd, yd)
+            bd = torch.full_like(xd, complex("nan"))
+            V.vie_block_matvec(P.handle, prec, xd, bd)
+            torch.cuda.synchronize()
+            outs[v] = (yd.cpu().numpy(), bd.cpu().numpy())
+            _assert_close(outs[v][0], want, g.mask, TOL[prec])
+            _assert_close(outs[v][1], want_b, g.mask, TOL[prec])
+        V.vie_problem_set_plane(P.handle, prec, -1)
+        assert P.info().plane_variant[1 if prec == V.VIE_MIXED else 0] in (0, 1, 2)
+        agree = 1e-14 if prec == V.VIE_FP64 else 1e-6
+        for v in (1, 2):
+            for k in range(2):
+                a, b = outs[v][k], outs[0][k]
+                assert np.abs(a - b).max() <= agree * np.abs(b).max(), (v, k)
+        with pytest.raises(V.VieError):
+            V.vie_problem_set_plane(P.handle, prec, 3)
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("prec", [V.VIE_FP64, V.VIE_MIXED])
+def test_plane_variants_metasurface_blocks(vie_ctx, prec):
+    """The metasurface's 64 pillar boxes (32 x 32 plane transforms, one
+    batch) and the slab box: block-diagonal product of every plane variant
+    against the oracle's block operators."""
+    case = W.metasurface()
+    x = _rand(12, case.shape) * (case.eps != 1)
+    want = _oracle_block_matvec(case, x)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        xd = torch.from_numpy(x).cuda()
+        for v in range(3):
+            V.vie_problem_set_plane(P.handle, prec, v)
+            bd = torch.full_like(xd, complex("nan"))
+            V.vie_block_matvec(P.handle, prec, xd, bd)
+            torch.cuda.synchronize()
+            _assert_close(bd.cpu().numpy(), want, case.eps != 1, TOL[prec])
+    finally:
+        V.vie_problem_set_plane(P.handle, prec, -1)
+        P.close()
+
+
+@pytest.mark.parametrize("prec", [V.VIE_FP64, V.VIE_MIXED])
+def test_pinned_plane_preconditioned_solve(vie_ctx, prec):
+    """Pinned plane variants inside the gated batched inner solves (the
+    BiCGSTAB updates and inner products fused into the plane kernels; blocks
+    that converge early are skipped) and the outer product of the 16^3 cube
+    (eight 8^3 blocks: 16 x 16 plane transforms): the same field as the
+    tuned kernels, to 1e-10 in FP64 at tol 1e-12; in mixed precision every
+    variant reaches tol 1e-9 through refinement and the fields agree to
+    1e-8."""
+    case = W.cube16()
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    tol, bar = (1e-12, 1e-10) if prec == V.VIE_FP64 else (1e-9, 1e-8)
+    try:
+        e = torch.from_numpy(V.vie_plane_wave(P.grid, case.kdir, case.pol)).cuda()
+        res = {}
+        for v in (-1, 0, 1, 2):
+            V.vie_problem_set_plane(P.handle, prec, v)
+            out = torch.empty_like(e)
+            st = V.vie_stats()
+            opts = V.make_opts(tol_outer=tol, tol_inner=1e-3, maxit_outer=2000, precision=prec, max_refine=5,
+                               flags=V.VIE_FLAG_NO_BLOCK_KERNEL)
+            assert V.vie_solve_device(P.handle, e, opts, out, None, st) == V.VIE_OK
+            torch.cuda.synchronize()
+            assert st.relres_true <= tol
+            res[v] = out.cpu().numpy()
+        for v in (0, 1, 2):
+            assert np.linalg.norm(res[v] - res[-1]) <= bar * np.linalg.norm(res[-1]), v
+    finally:
+        V.vie_problem_set_plane(P.handle, prec, -1)
+        P.close()
