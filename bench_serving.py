@@ -1,11 +1,16 @@
 """Batched-sweep and serving measurements with libvie's request server.
 
   python bench_serving.py sweep  [--n 64] [--slots 4]
+  python bench_serving.py fleet  [--n 64]
   python bench_serving.py stream [--rates 1,2,5,10,20,50] [--n 200] [--max-voxels N] [--slots 4]
 
 sweep: the solves of the batched sweep (workloads.sweep_case, mixed
 precision, block preconditioner, outer tol 1e-6, inner 1e-2) all submitted
-at once.  stream: a Poisson request stream (workloads.arrivals /
+at once.  fleet: the same solves as one batch per grid shape
+(vie_solve_many: every launch covers all problems of a shape, their blocks
+solved together), the shapes' batches on concurrent streams, problems set
+up from host arrays inside the timed region; against the same problems solved one by one on the GPU (mixed) and
+the plain FP64 path.  stream: a Poisson request stream (workloads.arrivals /
 serving_request) replayed in real time, one JSON line per rate; by default
 every request is served (grids up to 256x256x64); requests larger than
 --max-voxels are left out of the measured stream (stated in the output).
@@ -149,9 +154,89 @@ def measure(V, W, cases, arrive, slots, mode, rate, skipped, max_voxels):
     }
 
 
+def fleet(V, W, n):
+    """The sweep as one vie_solve_many call per grid shape."""
+    import torch
+    cases = [W.sweep_case(b) for b in range(n)]
+    shapes = {}
+    for i, c in enumerate(cases):
+        shapes.setdefault((c.nx, c.ny, c.nz), []).append(i)
+    ctx = V.vie_context_create(0)
+    opts = lambda c, prec: _opts(V, W, c, prec)   # noqa: E731
+    # warm-up: kernels and spectra of every shape class (one small batch each)
+    for idx in shapes.values():
+        sub = [cases[i] for i in idx[:2]]
+        Ps = [V.Problem(_grid(V, c), c.eps, c.block_id, c.n_blocks, ctx=ctx) for c in sub]
+        es = [torch.from_numpy(V.vie_plane_wave(P.grid, c.kdir, c.pol)).cuda() for P, c in zip(Ps, sub)]
+        ys = [torch.empty_like(e) for e in es]
+        V.vie_solve_many([P.handle for P in Ps], es, opts(sub[0], V.VIE_MIXED), ys)
+        for P in Ps:
+            P.close()
+    torch.cuda.synchronize()
+    out, per_shape = {}, {}
+
+    def run_shape(shape, idx):
+        # one thread and one stream per grid shape: the shapes' batches overlap
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            t1 = time.perf_counter()
+            sub = [cases[i] for i in idx]
+            Ps = [V.Problem(_grid(V, c), c.eps, c.block_id, c.n_blocks, ctx=ctx) for c in sub]
+            es = [torch.from_numpy(V.vie_plane_wave(P.grid, c.kdir, c.pol)).cuda() for P, c in zip(Ps, sub)]
+            ys = [torch.empty_like(e) for e in es]
+            st = (V.vie_stats * len(Ps))()
+            code = V.vie_solve_many([P.handle for P in Ps], es, opts(sub[0], V.VIE_MIXED), ys, stats=st,
+                                    stream=stream)
+            stream.synchronize()
+            dt = time.perf_counter() - t1
+            for k, i in enumerate(idx):
+                out[i] = (ys[k].cpu().numpy(), int(st[k].outer_iters), float(st[k].relres_true))
+            per_shape["x".join(map(str, shape))] = {
+                "problems": len(idx), "seconds": dt, "status": V.STATUS_NAMES.get(code, code),
+                "outer_iters": [int(st[k].outer_iters) for k in range(len(idx))]}
+            for P in Ps:
+                P.close()
+        print(f"fleet {shape}: {len(idx)} problems in {dt:.2f} s", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=run_shape, args=(shape, idx)) for shape, idx in shapes.items()]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    wall = time.perf_counter() - t0
+    # the same problems one by one (mixed, then plain FP64), set-up included
+    alone, fp64 = {}, []
+    t2 = time.perf_counter()
+    for i, c in enumerate(cases):
+        P = V.Problem(_grid(V, c), c.eps, c.block_id, c.n_blocks, ctx=ctx)
+        e = torch.from_numpy(V.vie_plane_wave(P.grid, c.kdir, c.pol)).cuda()
+        y = torch.empty_like(e)
+        st = V.vie_stats()
+        V.vie_solve_device(P.handle, e, opts(c, V.VIE_MIXED), y, None, st)
+        torch.cuda.synchronize()
+        alone[i] = y.cpu().numpy()
+        P.close()
+    t_alone = time.perf_counter() - t2
+    diffs = []
+    for i, c in enumerate(cases):
+        code, secs, e64 = fp64_alone(V, W, ctx, c)
+        fp64.append(secs)
+        diffs.append(float(np.linalg.norm(out[i][0] - e64) / np.linalg.norm(e64)))
+    V.vie_context_destroy(ctx)
+    return {"mode": "fleet", "n": n, "shapes": per_shape,
+            "batched_mixed": {"solves_per_s": n / wall, "seconds": wall},
+            "mixed_one_by_one": {"solves_per_s": n / t_alone, "seconds": t_alone},
+            "plain_fp64_one_by_one": {"solves_per_s": n / sum(fp64), "seconds": sum(fp64)},
+            "max_rel_field_diff_batched_vs_fp64": max(diffs),
+            "median_rel_field_diff_batched_vs_fp64": float(np.median(diffs)),
+            "max_rel_field_diff_batched_vs_alone": max(float(np.linalg.norm(out[i][0] - alone[i]) /
+                                                              np.linalg.norm(alone[i])) for i in range(n))}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["sweep", "stream"])
+    ap.add_argument("mode", choices=["sweep", "fleet", "stream"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--rates", default="1,2,5,10,20,50")
     ap.add_argument("--slots", type=int, default=4)
@@ -161,6 +246,9 @@ def main():
     import workloads as W
     from paper_2501_13512_amd import vie as V
 
+    if args.mode == "fleet":
+        print(json.dumps(fleet(V, W, args.n or 64)), flush=True)
+        return
     if args.mode == "sweep":
         n = args.n or 64
         cases = [W.sweep_case(b) for b in range(n)]

@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 13
+#define VIE_ABI_VERSION 14
 
 typedef enum {
   VIE_OK = 0,
@@ -383,6 +383,35 @@ vie_status vie_rcs(vie_problem* p, const void* pol_dev, int32_t n_dir, const dou
  * system's result and statistics are written.  nrhs in [1, 4096]. */
 vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, const vie_opts* opts,
                            void* e_tot_dev, void* pol_dev, vie_stats* stats, void* stream);
+
+/* Many independent problems of one grid shape solved as one batch (Sec.
+ * III-C, Table III: independent solves run in parallel; here the parallel
+ * axis is the problem).  The problems may differ in permittivity, block
+ * partition, spacing and wavelength, but not in nx, ny, nz or the FFT
+ * lengths (VIE_EINVAL), and belong to one context.  problems: n distinct
+ * handles; e_inc_dev[r], e_tot_dev[r], pol_dev[r] (pol_dev optional): device
+ * vectors of 3*nx*ny*nz complex of problem r, ordered on the stream; stats:
+ * NULL or n entries.  BiCGSTAB runs the n outer solves as one batch: every
+ * full-grid product (each system with its own 1/chi and its own spectra,
+ * read through a table), vector update and finalize launch covers all of
+ * them, and each stops on its own status.  With the preconditioner, each
+ * application solves the blocks of all problems together: the blocks are
+ * stacked along z, regrouped across problems by box shape, each with its
+ * own problem's spectra, all on the batched kernels (no one-workgroup block
+ * solver); a problem that has stopped contributes zero right-hand sides.
+ * The outer products use the kernel variants of problems[0] (pinned or
+ * tuned).  The FP64 true residual, mixed-mode refinement and the fields are
+ * then formed per problem as in vie_solve_device.  inner_iters_total and
+ * precond_applies are the batch's totals.  FGMRES and CGS, and n = 1, solve
+ * the problems one after another.  Batch storage (1/chi, 12 vectors and a
+ * work buffer per problem, the stacked blocks) is allocated for the call
+ * and counted against the context's budget while it runs (VIE_EBUSY beyond
+ * it).  Locks every problem for the call.  Returns the first error, else
+ * VIE_NOT_CONVERGED if any problem did not converge, else VIE_OK; every
+ * problem's result and statistics are written.  n in [1, 4096]. */
+vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* const* e_inc_dev,
+                          const vie_opts* opts, void* const* e_tot_dev, void* const* pol_dev, vie_stats* stats,
+                          void* stream);
 
 /* ------------------------------------------------------------------ serving
  * A request queue per context: independent solves (any grid, wavelength,

@@ -43,6 +43,7 @@ struct MvmBatch {
   int64_t sstride;         // elements between systems' spectra (0 = shared)
   const c128* chi_inv;     // [nsys][nz][ny][nx], 0 on voxels outside the system
   const cx<R>* spec;       // [6][lz/2+1][ly/2+1][lx/2+1] per system
+  const cx<R>* const* spec_tab;   // per-system spectra (device table; null: spec + sys sstride)
   cx<R>* work;
   const int* status;       // per system; null = always active
   const TwiddleSet<R>* tw; // host-side pointer table (values are device pointers)

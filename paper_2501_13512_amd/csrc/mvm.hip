@@ -667,6 +667,7 @@ struct ZArgs {
   int64_t wstride, sstride;
   cx<R>* work;
   const cx<R>* spec;
+  const cx<R>* const* spec_tab;   // per-system spectra (null: spec + sys sstride)
   const int* status;
   const cx<R>* tw;
 };
@@ -709,7 +710,7 @@ __global__ void __launch_bounds__((3 * ZGeo<R, LZ>::T * ZGeo<R, LZ>::ZP)) k_zcon
   // (fold x, fold y, fold z), reused for its mirrors
   const int64_t ox = lx / 2 + 1, oy = ly / 2 + 1;
   const int64_t oct = ox * oy * (LZ / 2 + 1);
-  const cx<R>* spec = a.spec + sys * a.sstride;
+  const cx<R>* spec = a.spec_tab ? a.spec_tab[sys] : a.spec + sys * a.sstride;
   constexpr int NFZ = nfold(LZ);
   for (int i = threadIdx.x; i < NFZ * ZP; i += 3 * T * ZP) {
     const int fz = i / ZP, pp = i - fz * ZP;
@@ -811,7 +812,7 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   const int c2 = tile * ZP + pp;
   const bool cvalid = c2 < cols;
   R sx = R(1), sy = R(1);
-  const cx<R>* const sp = a.spec + sys * a.sstride;
+  const cx<R>* const sp = a.spec_tab ? a.spec_tab[sys] : a.spec + sys * a.sstride;
   unsigned soff = 0;
   if (cvalid) {
     const int i2 = c2 / lx;
@@ -1113,6 +1114,7 @@ void mvm_mid(const MvmBatch<R>& b, hipStream_t s) {
   za.sstride = b.sstride;
   za.work = b.work;
   za.spec = b.spec;
+  za.spec_tab = b.spec_tab;
   za.status = b.status;
   za.tw = b.tw->table[b.lz];
   launch_zconv<R>(b.lz, za, b.nsys, s);
@@ -1170,6 +1172,7 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
     za.sstride = b.sstride;
     za.work = b.work;
     za.spec = b.spec;
+  za.spec_tab = b.spec_tab;
     za.status = b.status;
     za.tw = b.tw->table[b.lz];
     launch_zconv<R>(b.lz, za, b.nsys, s);
@@ -1210,6 +1213,7 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out) {
     za.sstride = b.sstride;
     za.work = b.work;
     za.spec = b.spec;
+  za.spec_tab = b.spec_tab;
     za.status = nullptr;
     za.tw = b.tw->table[b.lz];
     launch_zconv<R>(b.lz, za, b.nsys, s);   // warm-up

@@ -266,6 +266,11 @@ struct Group {
   DevBuf sys_origin;     // expanded blocks: box origin of each system (int4)
   int zvar[2] = {0, 0};  // tuned z-pass variant per precision ([0] FP64, [1] FP32)
   int pvar[2] = {0, 0};  // tuned plane-kernel variant per precision
+  // systems from problems with different spacing or wavelength: each
+  // system's spectra (kept alive here) and a device table of their addresses
+  // ([0, nsys) FP64, [nsys, 2 nsys) FP32); empty when all share `spec`
+  std::vector<std::shared_ptr<Spectra>> sys_spec;
+  DevBuf spec_tab;
   c128* vec[8];  // B, X, R, RHAT, P, V, S, T
   int slot0;     // first entry in the problem's inner status/state arrays
   bool wg = false;  // small enough for the one-workgroup block solver
@@ -313,6 +318,9 @@ struct ProblemPlan {
   int overlap = 0;
   std::vector<std::vector<uint8_t>> emask;
   std::vector<GroupPlan> groups;   // batched groups first, then block-solver groups
+  // blocks of several problems (vie_solve_many): dx, dy, dz, k0 of every
+  // block's own problem (empty: the plan's grid and k0 for every block)
+  std::vector<double> blk_phys;
 };
 
 struct vie_problem {
@@ -514,6 +522,8 @@ MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
   b.zvariant = G.zvar[sizeof(R) == sizeof(float) ? 1 : 0];
   b.plane = vie::plane_supported(b.lx, b.ly) ? 1 : 0;
   b.pvariant = G.pvar[sizeof(R) == sizeof(float) ? 1 : 0];
+  if (G.spec_tab.p)
+    b.spec_tab = G.spec_tab.as<const cx<R>*>() + (sizeof(R) == sizeof(float) ? G.nsys : 0);
   return b;
 }
 
@@ -1204,29 +1214,46 @@ KBatch batch_kbatch(vie_problem& P, int nrhs) {
   return k;
 }
 
-// BiCGSTAB of nrhs systems in one batch (x0 = 0): every launch covers all
+// The Krylov state of a batch of systems that share the full grid's shape
+// (right-hand sides of one problem, or several problems): vectors
+// kBatchVecs x [nsys][3 nv], per-system state and status, the replica that
+// holds the blocks of every system stacked along z (preconditioned solves)
+// and the problem whose outer progress ring (ring 0) the loop polls.
+struct BatchSet {
+  vie_problem& poll;
+  vie_problem* replica;
+  int nsys;
+  int64_t nv;
+  c128* vecs;
+  KBatch k;
+  int* status;
+  int* count;
+  c128* vec(int kind) const { return vecs + (int64_t)kind * nsys * 3 * nv; }
+};
+
+// BiCGSTAB of the batch's systems (x0 = 0): every launch covers all
 // systems, each stops on its own status (same per-system arithmetic as a
 // single solve).  Rhs in batch vector B, iterates in X.  With the
-// preconditioner, each application solves the blocks of all right-hand
-// sides together on the replica problem (R: outer products, RI: inner).
+// preconditioner, each application solves the blocks of all systems
+// together on the replica (R: outer products, RI: inner).
 template <typename R, typename RI = R>
-void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag, bool prec, double tol_in,
-                        int maxit_in, bool graphs, bool wg, hipStream_t s) {
-  const KBatch k = batch_kbatch(P, nrhs);
-  auto vec = [&](int kind) { return batch_vec(P, kind, nrhs); };
+void run_batch(const BatchSet& B, const MvmBatch<R>& m, double tol, int maxit, int lag, bool prec, double tol_in,
+               int maxit_in, bool graphs, bool wg, hipStream_t s) {
+  const KBatch& k = B.k;
+  const int nsys = B.nsys;
+  auto vec = [&](int kind) { return B.vec(kind); };
   vie::k_init(k, vec(BV_B), vec(BV_X), vec(BV_R), vec(BV_RHAT), nullptr, s);
   vie::k_finalize(k, vie::FIN_INIT, s, nullptr, tol, maxit);
-  const MvmBatch<R> m = batch_mvm<R>(P, nrhs);
   const StepVecs vv{vec(BV_X), vec(BV_R), vec(BV_RHAT), vec(BV_P), vec(BV_V), vec(BV_S), vec(BV_T)};
-  // y = K2^{-1} w for every right-hand side: to the stacked layout (systems
-  // that no longer iterate give zero right-hand sides, which the inner
-  // solves skip), one application on the replica, back
+  // y = K2^{-1} w for every system: to the stacked layout (systems that no
+  // longer iterate give zero right-hand sides, which the inner solves
+  // skip), one application on the replica, back
   auto apply = [&](const c128* w, c128* y) {
-    vie::batch_to_stacked(w, vec(BV_WI), nrhs, P.nv, P.mr_status.as<int>(), s);
-    precond_apply<RI>(*P.replica, vec(BV_WI), vec(BV_WO), tol_in, maxit_in, nullptr, lag, nullptr, 0, graphs, wg, s);
-    vie::stacked_to_batch(vec(BV_WO), y, nrhs, P.nv, s);
+    vie::batch_to_stacked(w, vec(BV_WI), nsys, B.nv, B.status, s);
+    precond_apply<RI>(*B.replica, vec(BV_WI), vec(BV_WO), tol_in, maxit_in, nullptr, lag, nullptr, 0, graphs, wg, s);
+    vie::stacked_to_batch(vec(BV_WO), y, nsys, B.nv, s);
   };
-  Poller poll(P, s, 0);
+  Poller poll(B.poll, s, 0);
   for (int it = 1; it <= maxit; ++it) {
     if (!prec) {
       fused_step<R>(m, k, vv, s);
@@ -1252,10 +1279,19 @@ void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag
       vie::k_update_xr(k, vec(BV_X), vec(BV_Y), vec(BV_Z), vec(BV_R), vec(BV_S), vec(BV_T), vec(BV_RHAT), s);
       vie::k_finalize(k, vie::FIN_XR, s);
     }
-    const long t = poll.push_count(P.mr_status.as<int>(), nrhs, P.mr_count.as<int>());
+    const long t = poll.push_count(B.status, nsys, B.count);
     if (t - lag >= 0 && poll.wait(t - lag) == 0) break;
   }
   hip_check(hipStreamSynchronize(s), "batch solve");
+}
+
+// nrhs right-hand sides of one problem in one batch.
+template <typename R, typename RI = R>
+void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag, bool prec, double tol_in,
+                        int maxit_in, bool graphs, bool wg, hipStream_t s) {
+  const BatchSet B{P, P.replica.get(), nrhs, P.nv, P.mr_vecs.as<c128>(), batch_kbatch(P, nrhs),
+                   P.mr_status.as<int>(), P.mr_count.as<int>()};
+  run_batch<R, RI>(B, batch_mvm<R>(P, nrhs), tol, maxit, lag, prec, tol_in, maxit_in, graphs, wg, s);
 }
 
 // The plan of nrhs copies of a problem stacked along z, with block ids
@@ -1298,6 +1334,19 @@ ProblemPlan stacked_plan(const ProblemPlan& pl, int nrhs) {
 std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& pl, hipStream_t s,
                                            bool inner_only = false);
 
+// Device memory of an inner-only problem built from plan sp (block
+// vectors, work buffers and state; spectra are the context's).
+size_t replica_bytes(const ProblemPlan& sp) {
+  size_t foot = 0;
+  for (const auto& gp : sp.groups) {
+    const size_t nsys = gp.blocks.size(), bnv = (size_t)gp.bx * gp.by * gp.bz;
+    foot += nsys * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
+            8 * nsys * 3 * bnv * sizeof(c128) + nsys * (sizeof(KState) + 2 * sizeof(int));
+  }
+  foot += (size_t)sp.nv * (sizeof(int32_t) + 4 * sizeof(int));   // block map
+  return foot;
+}
+
 // The replica problem for preconditioned batches of nrhs right-hand sides
 // (rebuilt when nrhs changes; counted in the problem's footprint).
 void ensure_replica(vie_problem& P, int nrhs, hipStream_t s) {
@@ -1314,13 +1363,7 @@ void ensure_replica(vie_problem& P, int nrhs, hipStream_t s) {
   }
   P.footprint -= std::min(P.footprint, old);
   const ProblemPlan sp = stacked_plan(*P.plan, nrhs);
-  size_t foot = 0;
-  for (const auto& gp : sp.groups) {
-    const size_t nsys = gp.blocks.size(), bnv = (size_t)gp.bx * gp.by * gp.bz;
-    foot += nsys * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
-            8 * nsys * 3 * bnv * sizeof(c128) + nsys * (sizeof(KState) + 2 * sizeof(int));
-  }
-  foot += (size_t)sp.nv * (sizeof(int32_t) + 4 * sizeof(int));   // block map
+  const size_t foot = replica_bytes(sp);
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->budget && ctx->used + ctx->reserved + foot > ctx->budget)
@@ -1337,6 +1380,84 @@ void ensure_replica(vie_problem& P, int nrhs, hipStream_t s) {
   P.replica_nrhs = nrhs;
   P.replica_bytes = foot;
   P.footprint += foot;
+}
+
+// Several problems of one grid shape in one batch (vie_solve_many): their
+// blocks stacked along z in problem order (block ids offset per problem),
+// regrouped across problems by box shape and FFT lengths, every block with
+// its own problem's spacing and k0 (its spectra); all groups batched.
+ProblemPlan fleet_plan(const std::vector<vie_problem*>& ps) {
+  const ProblemPlan& p0 = *ps[0]->plan;
+  ProblemPlan sp;
+  sp.g = p0.g;
+  sp.g.nz = p0.g.nz * (int)ps.size();
+  sp.nv = p0.nv * (int64_t)ps.size();
+  sp.k0 = p0.k0;
+  sp.lx = p0.lx;
+  sp.ly = p0.ly;
+  sp.lz = p0.lz;
+  sp.has_blocks = true;
+  sp.overlap = p0.overlap;
+  std::map<std::array<int, 6>, size_t> key_group;
+  int off = 0;
+  for (size_t r = 0; r < ps.size(); ++r) {
+    const ProblemPlan& pl = *ps[r]->plan;
+    const int nb = pl.n_blocks;
+    sp.chi.insert(sp.chi.end(), pl.chi.begin(), pl.chi.end());
+    for (int32_t b : pl.bid) sp.bid.push_back(b < 0 ? -1 : b + off);
+    for (int k = 0; k < nb; ++k) {
+      for (int a = 0; a < 3; ++a) {
+        sp.lo.push_back(pl.lo[3 * k + a] + (a == 2 ? (int)r * p0.g.nz : 0));
+        sp.hi.push_back(pl.hi[3 * k + a] + (a == 2 ? (int)r * p0.g.nz : 0));
+      }
+      sp.blk_phys.insert(sp.blk_phys.end(), {pl.g.dx, pl.g.dy, pl.g.dz, pl.k0});
+    }
+    sp.cnt.insert(sp.cnt.end(), pl.cnt.begin(), pl.cnt.end());
+    if (pl.overlap > 0) sp.emask.insert(sp.emask.end(), pl.emask.begin(), pl.emask.end());
+    for (const auto& gp : pl.groups) {
+      const std::array<int, 6> key{gp.lx, gp.ly, gp.lz, gp.bx, gp.by, gp.bz};
+      auto it = key_group.find(key);
+      if (it == key_group.end()) {
+        GroupPlan g2 = gp;
+        g2.blocks.clear();
+        g2.wg = false;
+        it = key_group.emplace(key, sp.groups.size()).first;
+        sp.groups.push_back(std::move(g2));
+      }
+      for (int k : gp.blocks) sp.groups[it->second].blocks.push_back(k + off);
+    }
+    off += nb;
+  }
+  sp.n_blocks = off;
+  return sp;
+}
+
+// The batch state of a vie_solve_many call: 1/chi of every problem,
+// per-problem spectrum tables, work buffer, vectors, Krylov state and the
+// replica; counted against the context's budget while it lives.
+struct Fleet {
+  vie_context* ctx;
+  size_t bytes = 0;
+  DevBuf chi, tab, work, vecs, state, status, partials, partials2, ntile, count;
+  std::unique_ptr<vie_problem> replica;
+  explicit Fleet(vie_context* c) : ctx(c) {}
+  ~Fleet() {
+    replica.reset();
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->used -= std::min(ctx->used, bytes);
+  }
+};
+
+template <typename R>
+MvmBatch<R> fleet_mvm(vie_problem& P0, Fleet& F, int n) {
+  MvmBatch<R> b = outer_batch<R>(P0, true);   // the first problem's shape and kernel variants
+  b.nsys = n;
+  b.cstride = P0.nv;
+  b.chi_inv = F.chi.as<c128>();
+  b.spec_tab = F.tab.as<const cx<R>*>() + (sizeof(R) == sizeof(float) ? n : 0);
+  b.work = F.work.as<cx<R>>();
+  b.status = F.status.as<int>();
+  return b;
 }
 
 // ------------------------------------------------------------------ problem set-up
@@ -1745,7 +1866,27 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
       gbox.push_back(int4{G.bx, G.by, G.bz, 0});
       upload(G.chi, gchi, s);
       if (pl.overlap > 0) upload(G.sys_origin, sorg, s);
-      G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0, s);
+      if (pl.blk_phys.empty()) {
+        G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0, s);
+      } else {
+        bool same = true;
+        for (int q = 0; q < G.nsys; ++q) {
+          const double* ph = &pl.blk_phys[4 * (size_t)G.blocks[q]];
+          G.sys_spec.push_back(get_spectra(ctx, G.lx, G.ly, G.lz, ph[0], ph[1], ph[2], ph[3], s));
+          same = same && G.sys_spec.back() == G.sys_spec.front();
+        }
+        G.spec = G.sys_spec.front();
+        if (same) {
+          G.sys_spec.clear();
+        } else {
+          std::vector<const void*> tab(2 * (size_t)G.nsys);
+          for (int q = 0; q < G.nsys; ++q) {
+            tab[q] = spec_ptr<double>(*G.sys_spec[q]);
+            tab[G.nsys + q] = spec_ptr<float>(*G.sys_spec[q]);
+          }
+          upload(G.spec_tab, tab, s);
+        }
+      }
       G.work.alloc((size_t)G.nsys * 3 * G.bz * G.ly * G.lx * sizeof(c128));
       G.work.zero(s);
       G.vecs.alloc(8 * (size_t)G.nsys * G.n * sizeof(c128));
@@ -2630,6 +2771,129 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
       if (stats) {
         stats[r].seconds += batch_s;
         stats[r].inner_iters_total += acc[0];   // the batch's totals (all right-hand sides)
+        stats[r].precond_applies += acc[1];
+      }
+    }
+    return worst;
+  });
+}
+
+vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* const* e_inc_dev,
+                          const vie_opts* opts, void* const* e_tot_dev, void* const* pol_dev, vie_stats* stats,
+                          void* stream) {
+  return guarded([&]() -> vie_status {
+    if (n < 1 || n > 4096) fail(VIE_EINVAL, "n must be in [1, 4096]");
+    if (!problems || !e_inc_dev || !e_tot_dev) fail(VIE_EINVAL, "problems, e_inc_dev and e_tot_dev are required");
+    std::vector<vie_problem*> ps(problems, problems + n);
+    for (int r = 0; r < n; ++r)
+      if (!ps[r] || !e_inc_dev[r] || !e_tot_dev[r]) fail(VIE_EINVAL, "a problem, e_inc or e_tot entry is NULL");
+    if (std::set<vie_problem*>(ps.begin(), ps.end()).size() != ps.size()) fail(VIE_EINVAL, "a problem appears twice");
+    vie_problem& P0 = *ps[0];
+    const bool prec = opts && opts->precondition != 0;
+    for (vie_problem* q : ps) {
+      if (q->ctx != P0.ctx) fail(VIE_EINVAL, "problems belong to different contexts");
+      if (q->g.nx != P0.g.nx || q->g.ny != P0.g.ny || q->g.nz != P0.g.nz || q->lx != P0.lx || q->ly != P0.ly ||
+          q->lz != P0.lz)
+        fail(VIE_EINVAL, "problems differ in grid shape or FFT lengths");
+      validate_opts(opts, !q->groups.empty());
+      if (prec && (!q->plan || q->plan->overlap != P0.plan->overlap))
+        fail(VIE_EINVAL, "preconditioned problems need their plans and one overlap");
+    }
+    // every problem's lock, in address order
+    std::vector<vie_problem*> order = ps;
+    std::sort(order.begin(), order.end());
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (vie_problem* q : order) locks.emplace_back(q->mu);
+    set_device(P0.ctx);
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    vie_status worst = VIE_OK;
+    auto keep = [&](vie_status st) {
+      if (worst >= 0 && (st < 0 || st > worst)) worst = st;
+    };
+    const int64_t nv = P0.nv, n3 = 3 * nv;
+    auto ein = [&](int r) { return (const c128*)e_inc_dev[r]; };
+    auto eout = [&](int r) { return (c128*)e_tot_dev[r]; };
+    auto pol = [&](int r) { return pol_dev ? (c128*)pol_dev[r] : nullptr; };
+    if (n == 1 || opts->solver != VIE_SOLVER_BICGSTAB) {
+      for (int r = 0; r < n; ++r) keep(solve_impl(ps[r], ein(r), opts, eout(r), pol(r), stats ? &stats[r] : nullptr, s));
+      return worst;
+    }
+    const bool graphs = (opts->flags & VIE_FLAG_NO_GRAPHS) == 0;
+    Fleet F(P0.ctx);
+    ProblemPlan fp;
+    if (prec) fp = fleet_plan(ps);
+    const size_t small = (size_t)n * (sizeof(KState) + 2 * sizeof(int) + 2 * (size_t)P0.pstride * sizeof(double)) +
+                         2 * (size_t)n * sizeof(void*) + sizeof(int);
+    const size_t bytes = (size_t)n * nv * sizeof(c128) + (size_t)n * 3 * P0.g.nz * P0.ly * P0.lx * sizeof(c128) +
+                         (size_t)kBatchVecs * n * n3 * sizeof(c128) + small + (prec ? replica_bytes(fp) : 0);
+    {
+      std::lock_guard<std::mutex> lk(P0.ctx->mu);
+      if (P0.ctx->budget && P0.ctx->used + P0.ctx->reserved + g_unfreed_bytes.load() + bytes > P0.ctx->budget)
+        fail(VIE_EBUSY, "the batch exceeds the context's HBM budget");
+      P0.ctx->used += bytes;
+      F.bytes = bytes;
+    }
+    F.chi.alloc((size_t)n * nv * sizeof(c128));
+    F.work.alloc((size_t)n * 3 * P0.g.nz * P0.ly * P0.lx * sizeof(c128));
+    F.vecs.alloc((size_t)kBatchVecs * n * n3 * sizeof(c128));
+    F.vecs.zero(s);
+    F.state.alloc((size_t)n * sizeof(KState));
+    F.status.alloc((size_t)n * sizeof(int));
+    F.partials.alloc((size_t)n * P0.pstride * sizeof(double));
+    F.partials2.alloc((size_t)n * P0.pstride * sizeof(double));
+    F.ntile.alloc((size_t)n * sizeof(int));
+    F.count.alloc(sizeof(int));
+    std::vector<const void*> tab(2 * (size_t)n);
+    for (int r = 0; r < n; ++r) {
+      hip_check(hipMemcpyAsync(F.chi.as<c128>() + r * nv, ps[r]->chi.p, nv * sizeof(c128), hipMemcpyDeviceToDevice, s),
+                "batch 1/chi");
+      tab[r] = spec_ptr<double>(*ps[r]->spec);
+      tab[n + r] = spec_ptr<float>(*ps[r]->spec);
+    }
+    upload(F.tab, tab, s);
+    if (prec) {
+      F.replica = build_problem(P0.ctx, fp, s, true);
+      hip_check(hipMemsetAsync(F.replica->d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
+    }
+    KBatch k{};
+    k.nsys = n;
+    k.n = n3;
+    k.status = F.status.as<int>();
+    k.st = F.state.as<KState>();
+    k.partials = F.partials.as<double>();
+    k.pstride = P0.pstride;
+    k.ntile = F.ntile.as<int>();
+    k.partials2 = F.partials2.as<double>();
+    const BatchSet B{P0, F.replica.get(), n, nv, F.vecs.as<c128>(), k, F.status.as<int>(), F.count.as<int>()};
+    for (int r = 0; r < n; ++r) vie::masked_copy(ein(r), ps[r]->chi.as<c128>(), B.vec(BV_B) + r * n3, nv, s);
+    const double ti = opts->tol_inner, to = opts->tol_outer;
+    const int mi = opts->maxit_inner, mo = opts->maxit_outer, lag = opts->poll_lag;
+    if (opts->precision == VIE_MIXED)
+      run_batch<float, float>(B, fleet_mvm<float>(P0, F, n), to, mo, lag, prec, ti, mi, graphs, false, s);
+    else if (opts->precision == VIE_MIXED_INNER)
+      run_batch<double, float>(B, fleet_mvm<double>(P0, F, n), to, mo, lag, prec, ti, mi, graphs, false, s);
+    else
+      run_batch<double, double>(B, fleet_mvm<double>(P0, F, n), to, mo, lag, prec, ti, mi, graphs, false, s);
+    int64_t acc[3] = {0, 0, 0};
+    if (prec) copy_out(acc, F.replica->d_acc.p, sizeof(acc), s, "acc");
+    std::vector<KState> st(n);
+    std::vector<int> status(n);
+    copy_out(st.data(), F.state.p, n * sizeof(KState), s, "batch state");
+    copy_out(status.data(), F.status.p, n * sizeof(int), s, "batch status");
+    const double batch_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    // per problem: true residual, refinement (mixed), fields, statistics
+    for (int r = 0; r < n; ++r) {
+      vie_problem& P = *ps[r];
+      hip_check(hipMemcpyAsync(P.vec[V_B], B.vec(BV_B) + r * n3, n3 * sizeof(c128), hipMemcpyDeviceToDevice, s),
+                "batch rhs");
+      hip_check(hipMemcpyAsync(P.vec[V_X], B.vec(BV_X) + r * n3, n3 * sizeof(c128), hipMemcpyDeviceToDevice, s),
+                "batch iterate");
+      const RunResult rr{st[r], status[r]};
+      keep(solve_impl(&P, nullptr, opts, eout(r), pol(r), stats ? &stats[r] : nullptr, s, &rr));
+      if (stats) {
+        stats[r].seconds += batch_s;
+        stats[r].inner_iters_total += acc[0];   // the batch's totals (all problems)
         stats[r].precond_applies += acc[1];
       }
     }

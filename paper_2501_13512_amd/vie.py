@@ -58,7 +58,7 @@ ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_c
                "vie_problem_create", "vie_problem_create_overlap", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass", "vie_problem_set_plane",
                "vie_plane_wave", "vie_plan",
                "vie_matvec", "vie_matvec_profile", "vie_group_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
-               "vie_solve_batch",
+               "vie_solve_batch", "vie_solve_many",
                "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
                "vie_total_field_box", "vie_far_field", "vie_far_field_noalloc", "vie_rcs")
 
@@ -134,6 +134,8 @@ for _name, _args in {
     "vie_solve_device": [_vp, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats), _vp],
     "vie_solve_batch": [_vp, ctypes.c_int32, _vp, ctypes.POINTER(vie_opts), _vp, _vp, ctypes.POINTER(vie_stats),
                         _vp],
+    "vie_solve_many": [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(vie_opts),
+                       ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(vie_stats), _vp],
     "vie_server_start": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_footprint": [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "vie_submit": [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(vie_opts), ctypes.POINTER(_vp)],
@@ -300,6 +302,19 @@ def vie_solve_batch(p: int, nrhs: int, e_inc, opts: vie_opts, e_tot, pol=None, s
     st = ctypes.cast(stats, ctypes.POINTER(vie_stats)) if stats is not None else None
     return _check(_lib.vie_solve_batch(p, int(nrhs), _dev(e_inc), ctypes.byref(opts), _dev(e_tot), _dev(pol), st,
                                        _stream(stream)), "vie_solve_batch", warn_ok=True)
+
+
+def vie_solve_many(problems, e_inc, opts: vie_opts, e_tot, pol=None, stats=None, stream=None) -> int:
+    """problems: n problem handles; e_inc, e_tot (and pol): n device buffers
+    (torch tensors or device addresses); stats: None or a ctypes array of n
+    vie_stats."""
+    n = len(problems)
+    arr = lambda xs: (_vp * n)(*[_dev(x) for x in xs])   # noqa: E731
+    hp = (_vp * n)(*problems)
+    st = ctypes.cast(stats, ctypes.POINTER(vie_stats)) if stats is not None else None
+    return _check(_lib.vie_solve_many(n, hp, arr(e_inc), ctypes.byref(opts), arr(e_tot),
+                                      arr(pol) if pol is not None else None, st, _stream(stream)),
+                  "vie_solve_many", warn_ok=True)
 
 
 def _host_problem_arrays(eps, block_id):

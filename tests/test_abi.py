@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 
 def test_abi_version():
-    assert V.vie_abi_version() == 13
+    assert V.vie_abi_version() == 14
 
 
 def _has_gpu():
