@@ -4,8 +4,11 @@ Calls only ``oracle/`` and ``workloads``.  Each run writes
 ``oracle_metasurface_<run>.json`` (settings, outer step count, residual
 history, inner step counts of every preconditioner application, refinement
 counts, timing) and ``oracle_metasurface_<run>_etot.npy``: E_tot at every
-scatterer voxel, complex128 [3, n] in the order of ``numpy.nonzero(mask)``
-over the [z, y, x] grid.
+scatterer voxel, [3, n] in the order of ``numpy.nonzero(mask)`` over the
+[z, y, x] grid; complex128 for ``tight`` (compared to 1e-10), complex64 for
+the others (compared at the 1e-5 level; ``shrink`` converts a complex128
+file).  The pad-4 runs' fields serve only the spread file and are not
+kept in the repository.
 
 Runs (the case is 128x128x32 at lambda/40, 64 pillar blocks + slab):
 
@@ -22,6 +25,7 @@ Runs (the case is 128x128x32 at lambda/40, 64 pillar blocks + slab):
                   inner 1e-2, at most 3 corrections);
 * ``mixed_pad4``  the same with lengths 2n + 4;
 * ``bench_fp64``  FP64 block-preconditioned at the benchmark's settings;
+* ``shrink``      rewrites the non-tight fields as complex64;
 * ``spread``      reads the stored fields and writes
                   ``oracle_metasurface_spread.json``: relative field
                   differences between the runs and the step counts side by
@@ -123,7 +127,8 @@ def run(name: str) -> dict:
         d.update(max_refine=3, refine_steps=sol.refine_steps, refine_iters=sol.refine_iters,
                  relres_true=sol.relres_true, true_history=sol.true_history)
     if spec.get("field", True):
-        np.save(path(name, "npy"), scatterer_values(g, sol.E_tot), allow_pickle=False)
+        f = scatterer_values(g, sol.E_tot)
+        np.save(path(name, "npy"), f if name == "tight" else f.astype(np.complex64), allow_pickle=False)
     return d
 
 
@@ -156,6 +161,15 @@ if __name__ == "__main__":
         workers = int(args[i + 1])
         del args[i:i + 2]
     for name in args:
+        if name == "shrink":
+            for run_name in RUNS:
+                f = path(run_name, "npy")
+                if run_name != "tight" and os.path.exists(f):
+                    a = np.load(f, allow_pickle=False)
+                    if a.dtype == np.complex128:
+                        np.save(f, a.astype(np.complex64), allow_pickle=False)
+                        print("shrunk", os.path.basename(f), flush=True)
+            continue
         if name == "spread":
             d = spread()
             with open(os.path.join(HERE, f"oracle_{CASE}_spread.json"), "w") as f:
