@@ -43,9 +43,11 @@ def _grid(V, c):
 
 
 def _opts(V, W, c, precision):
+    # at most one correction solve: a request whose main loop stops at its
+    # step cap does not spend three more caps on corrections
     pre = W.request_precondition(c)
     return V.make_opts(tol_outer=c.tol_outer, tol_inner=c.tol_inner, maxit_outer=c.maxit_outer,
-                       maxit_inner=c.maxit_inner, precondition=pre, precision=precision)
+                       maxit_inner=c.maxit_inner, precondition=pre, precision=precision, max_refine=1)
 
 
 def served(V, W, ctx, cases, arrive):
