@@ -167,3 +167,51 @@ def test_wait_timeout_keeps_ticket(ctx):
     assert code == V.VIE_NOT_CONVERGED
     assert st.outer_iters == 1500
     assert np.all(np.isfinite(e_tot))
+
+
+def test_served_request_memory_within_its_reservation():
+    """Admission by footprint does not undercount: on a fresh context
+    (nothing cached) one served metasurface request's device memory, sampled
+    every 2 ms while it runs, stays within what admission reserves for it:
+    the planned footprint with every spectrum and the set-up scratch
+    (vie_footprint on the fresh context) plus the request's own input and
+    output vectors; and it reaches at least half of the planned footprint
+    (the sampling sees the problem's persistent storage).  Runs without
+    graph capture, so the sampling thread's HIP calls cannot meet a
+    capture."""
+    import threading
+    import time
+    case = W.metasurface()
+    c0 = V.vie_context_create(0)
+    try:
+        nv = case.nx * case.ny * case.nz
+        plan = V.vie_footprint(c0, _grid(case), case.eps, case.block_id, case.n_blocks)
+        reserved = plan + 2 * 3 * nv * 16
+        opts = V.make_opts(tol_outer=1e-3, tol_inner=case.tol_inner, maxit_outer=200, precision=V.VIE_MIXED,
+                           flags=V.VIE_FLAG_NO_GRAPHS)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        V.vie_server_start(c0, 1, 4)
+        low = [free0]
+        done = threading.Event()
+
+        def sample():
+            while not done.is_set():
+                low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+                time.sleep(0.002)
+
+        th = threading.Thread(target=sample)
+        th.start()
+        try:
+            t = _submit(c0, case, opts)
+            code, _, st, _ = V.vie_wait(t, case.shape)
+        finally:
+            done.set()
+            th.join()
+        assert code in (V.VIE_OK, V.VIE_NOT_CONVERGED)
+        used = free0 - low[0]
+        slack = 64 << 20   # allocation granularity of the device allocator
+        assert used <= reserved + slack, (used, reserved)
+        assert used >= 0.5 * plan, (used, plan)
+    finally:
+        V.vie_context_destroy(c0)
