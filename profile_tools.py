@@ -148,6 +148,15 @@ def _per_queue(trace):
                    f"summed {sum(per.values()) / 1e6:.1f} ms")
         for n, ns in per.most_common(8):
             out.append(f"    {ns / 1e6:9.2f} ms {cnt[n]:8d} x {ns / cnt[n] / 1e3:7.2f} us  {n[:90]}")
+        # this queue's idle time between consecutive kernels, by kernel pair
+        pairs = collections.defaultdict(list)
+        for (s0, e0, n0), (s1, _, n1) in zip(t, t[1:]):
+            if s1 > e0:
+                pairs[(n0.split("(")[0][-40:], n1.split("(")[0][-40:])].append(s1 - e0)
+        for (a, b), g in sorted(pairs.items(), key=lambda kv: -sum(kv[1]))[:6]:
+            g.sort()
+            out.append(f"    idle {sum(g) / 1e6:8.2f} ms {len(g):7d} x median {g[len(g) // 2] / 1e3:7.2f} us  "
+                       f"after {a} -> {b}")
     return out
 
 
