@@ -580,8 +580,31 @@ def main():
         pm = mvm_profile(V, Q.handle, qi, oc.nx, oc.ny, oc.nz, V.VIE_MIXED, args.profile_reps)
         entry["mvm_mixed"] = {"ms": pm["ms"], "algorithmic_GBps": pm["algorithmic_GBps"],
                               "frac_of_hbm_peak": pm["algorithmic_GBps"] / HBM_PEAK_GBS, "dominant": pm["dominant"]}
-        others[name] = entry
         Q.close()
+        # the workload's own block partition (one block per sphere, the
+        # layer, the slab), capped: the outer residual stalls with the block
+        # preconditioner, in the oracle as well (its stored first steps)
+        if oc.n_blocks:
+            Qb = V.Problem(og, oc.eps, oc.block_id, oc.n_blocks, ctx=ctx)
+            cap = 30
+            for label, pv in (("preconditioned_mixed_capped", V.VIE_MIXED),
+                              ("preconditioned_fp64_capped", V.VIE_FP64)):
+                ob = V.make_opts(tol_outer=oc.tol_outer, tol_inner=oc.tol_inner, maxit_outer=cap,
+                                 maxit_inner=oc.maxit_inner, precondition=True, precision=pv, max_refine=0)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                try:
+                    cq = V.vie_solve_device(Qb.handle, qe, ob, qo, None, st)
+                except V.VieError as ex:   # a breakdown is a result of the run, not a failure of the bench
+                    cq = ex.code
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                entry[label] = {"outer_steps": st.outer_iters, "status": V.STATUS_NAMES.get(cq, cq),
+                                "relres_recursive": st.relres_recursive, "relres_true": st.relres_true,
+                                "seconds": dt, "ms_per_outer_step": 1e3 * dt / max(1, st.outer_iters),
+                                "inner_iters_total": st.inner_iters_total, "blocks": oc.n_blocks}
+            Qb.close()
+        others[name] = entry
         log(f"{name} done")
 
     # a short Poisson stream of the serving workload (every grid size of its
