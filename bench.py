@@ -118,6 +118,29 @@ def counters_for(kernel, workload, precision, lz):
     return None
 
 
+def group_traffic(dom_z, workload, precision, s_el):
+    """HBM traffic per launch of the dominant group's z pass over the solve's
+    launch mix: the counted bytes per launch with every system of the group
+    active (committed summary, `bench.py --traffic-probe` under two
+    rocprofv3 --pmc runs), scaled to the mix by the ratio of algorithmic
+    bytes (mix / all active).  None if no summary covers this kernel build."""
+    from profile_tools import kernel_hash
+    path = os.path.join(ROOT, "profiles", "mvm_hbm_traffic.json")
+    if not dom_z or not os.path.exists(path):
+        return None
+    lx, ly, lz = dom_z["fft"]
+    bz = dom_z["box"][2]
+    h = kernel_hash()
+    cands = [e for e in json.load(open(path)).get("entries", [])
+             if e.get("kernel", "").startswith("k_zconv_col") and e.get("workload") == workload
+             and e.get("precision") == precision and e.get("lz") == lz and e.get("source_hash") == h]
+    if not cands:
+        return None
+    e = max(cands, key=lambda c: c["dispatches"])   # the group's tuned variant runs most
+    full = dom_z["systems"] * 2 * 3 * bz * ly * lx * s_el + 6 * (lx // 2 + 1) * (ly // 2 + 1) * (lz // 2 + 1) * s_el
+    return e["bytes_per_launch"] * dom_z["bytes_per_launch"] / full
+
+
 def golden_error(case, e_tot):
     """Relative field difference at every scatterer voxel against the
     oracle's stored solves (tests/golden/): FP64 block-preconditioned at the
@@ -280,6 +303,9 @@ def main():
                     help="further workloads (comma-separated) reported beside the headline: solves without the block "
                          "preconditioner (it stalls on metal-sphere blocks), mixed and FP64, and their product's roofline; "
                          "'' for none")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only the dominant block group's product with every system active (10 repetitions), the "
+                         "full-grid product (5) and the 512 MiB calibration copy: the program for the counter runs")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also copy 512 MiB device to device three times (reference kernel for HBM counters)")
     ap.add_argument("--mvm-shapes", default="256x256x64",
@@ -303,6 +329,21 @@ def main():
     P = V.Problem(grid, case.eps, case.block_id, case.n_blocks, ctx=ctx)
     setup_s = time.perf_counter() - t0
     info = P.info()
+    if args.traffic_probe:
+        _, pg, _ = V.vie_plan(grid, case.eps, case.block_id, case.n_blocks)
+        batched = [(gi, g) for gi, g in enumerate(pg) if not g.one_workgroup]
+        gi, g = max(batched, key=lambda t: t[1].n_systems)
+        V.vie_group_profile(P.handle, prec, gi, g.n_systems, 10)
+        mvm_profile(V, P.handle, info, case.nx, case.ny, case.nz, prec, 5)
+        ca = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        cb = torch.empty_like(ca)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            cb.copy_(ca)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": case.name, "group": gi, "systems": g.n_systems,
+                          "fft": [g.lx, g.ly, g.lz]}), flush=True)
+        return
     e_inc = torch.from_numpy(V.vie_plane_wave(grid, case.kdir, case.pol)).cuda()
     e_tot = torch.empty_like(e_inc)
     maxit = case.maxit_outer if args.maxit_outer is None else args.maxit_outer
@@ -652,7 +693,9 @@ def main():
         "relres_true": stats[-1]["relres_true"],
         "mvm": mv,
         "roofline": ({"bound": "hbm", "achieved": dom_z["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": dom_z["achieved_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                      "frac": dom_z["achieved_GBps"] / HBM_PEAK_GBS,
+                      "traffic": group_traffic(dom_z, wl, "float" if prec == V.VIE_MIXED else "double",
+                                               8 if prec == V.VIE_MIXED else 16),
                       "kernel": f"z pass of the block group on the {dom_z['fft'][0]}x{dom_z['fft'][1]}x{dom_z['fft'][2]} "
                                 f"transform ({dom_z['systems']} systems, box {dom_z['box']}), {args.precision}; "
                                 f"k_zconv_col<{'float' if prec == V.VIE_MIXED else 'double'}, {dom_z['fft'][2]}, *>",
