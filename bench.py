@@ -50,21 +50,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def pass_bytes(nx, ny, nz, lx, ly, lz, s):
+def pass_bytes(nx, ny, nz, lx, ly, lz, s, rooftop=False):
     """Algorithmic bytes of the five passes of one product (s = bytes per
     complex element of the transform: 8 in complex64, 16 in complex128;
-    input and output vectors and 1/chi are complex128)."""
+    input and output vectors and 1/chi are complex128).  Rooftop
+    discretisation: one octant spectrum plus the three difference-symbol
+    tables instead of six octant spectra, and 1/chi per face (3 nv)."""
     nv = nx * ny * nz
     A = 3 * nz * ny * lx           # x-padded rows
     B = 3 * nz * ly * lx           # x,y-padded planes
-    oct_ = 6 * (lx // 2 + 1) * (ly // 2 + 1) * (lz // 2 + 1)
+    octv = (lx // 2 + 1) * (ly // 2 + 1) * (lz // 2 + 1)
+    oct_ = octv + lx + ly + lz if rooftop else 6 * octv
+    nchi = 3 * nv if rooftop else nv
     v = 16
     return [
         3 * nv * v + A * s,                        # x forward (pruned)
         A * s + B * s,                             # y forward (pruned)
         B * s + oct_ * s + B * s,                  # z fwd + spectral multiply + z inv
         B * s + A * s,                             # y inverse (cropped)
-        A * s + 3 * nv * v + nv * v + 3 * nv * v,  # x inverse + local term
+        A * s + 3 * nv * v + nchi * v + 3 * nv * v,  # x inverse + local term
     ]
 
 
@@ -79,7 +83,7 @@ def pass_names(zvar):
     return n
 
 
-def mvm_profile(V, handle, info, nx, ny, nz, prec, reps):
+def mvm_profile(V, handle, info, nx, ny, nz, prec, reps, rooftop=False):
     """Per-pass times of the full-grid product (HIP events on the launch
     stream) and their algorithmic bandwidth."""
     import torch
@@ -87,7 +91,7 @@ def mvm_profile(V, handle, info, nx, ny, nz, prec, reps):
     y = torch.empty_like(x)
     ms = V.vie_matvec_profile(handle, prec, x, y, reps)
     s_el = 8 if prec == V.VIE_MIXED else 16
-    pb = pass_bytes(nx, ny, nz, info.lx, info.ly, info.lz, s_el)
+    pb = pass_bytes(nx, ny, nz, info.lx, info.ly, info.lz, s_el, rooftop)
     q = 1 if prec == V.VIE_MIXED else 0
     zvar = int(info.zpass_variant[q])
     names = pass_names(zvar)
@@ -308,6 +312,8 @@ def main():
                          "full-grid product (5) and the 512 MiB calibration copy: the program for the counter runs")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also copy 512 MiB device to device three times (reference kernel for HBM counters)")
+    ap.add_argument("--no-rooftop", action="store_true",
+                    help="skip the rooftop-discretisation product and solve on the padded metasurface")
     ap.add_argument("--mvm-shapes", default="256x256x64",
                     help="extra grids (comma-separated NXxNYxNZ, '' for none) whose full-grid product is timed per pass")
     args = ap.parse_args()
@@ -571,6 +577,38 @@ def main():
             p["frac_of_hbm_peak"] = p["algorithmic_GBps"] / HBM_PEAK_GBS
         Q.close()
 
+    # the rooftop discretisation (face unknowns, one scalar spectrum) on the
+    # metasurface padded by a vacuum layer per side: its product beside the
+    # collocated product of the same grid, and a plain mixed-precision solve
+    roof = None
+    if not args.no_rooftop and args.maxit_outer is None:
+        rc = W.padded(W.metasurface())
+        rg = V.make_grid(rc.nx, rc.ny, rc.nz, rc.dx, rc.dy, rc.dz, rc.wavelength)
+        roof = {"workload": f"{rc.name} {rc.nx}x{rc.ny}x{rc.nz}, no blocks"}
+        for kind, flag in (("rooftop", True), ("collocated", False)):
+            Q = V.Problem(rg, rc.eps, ctx=ctx, rooftop=flag)
+            qi = Q.info()
+            roof[kind] = {p: mvm_profile(V, Q.handle, qi, rc.nx, rc.ny, rc.nz, pv, args.profile_reps, rooftop=flag)
+                          for p, pv in (("mixed", V.VIE_MIXED), ("fp64", V.VIE_FP64))}
+            roof[kind]["fft"] = [qi.lx, qi.ly, qi.lz]
+            if flag:
+                er = torch.from_numpy(V.vie_plane_wave_faces(rg, rc.kdir, rc.pol).reshape(-1)).cuda()
+                et = torch.empty_like(er)
+                ro = V.make_opts(tol_outer=2e-6, maxit_outer=3000, precondition=False, precision=V.VIE_MIXED,
+                                 max_refine=3)
+                V.vie_solve_device(Q.handle, er, ro, et, None, st)   # warm-up
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                cr = V.vie_solve_device(Q.handle, er, ro, et, None, st)
+                torch.cuda.synchronize()
+                tr = time.perf_counter() - t1
+                roof["plain_solve_mixed"] = {"solves_per_s": 1.0 / tr, "status": V.STATUS_NAMES.get(cr, cr),
+                                             "outer_steps": st.outer_iters, "refine_steps": st.refine_steps,
+                                             "refine_iters": st.refine_iters, "relres_true": st.relres_true,
+                                             "ms_per_outer_step": 1e3 * tr / max(1, st.outer_iters + st.refine_iters)}
+            Q.close()
+        log("rooftop product and solve done")
+
     # the inner tolerance of the block solves (the workload's 1e-2 is the
     # paper's softened value): one timed solve of the headline path per value
     sweep = {}
@@ -708,6 +746,7 @@ def main():
                               "achieved": dom["achieved"], "frac": dom["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
                               "valu_issue": valu},
         "mvm_other_grids": extra,
+        "rooftop": roof,
         "fp64_gpu_paths": compare,
         "solver_variants": variants,
         "inner_tol_sweep": sweep,

@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define VIE_ABI_VERSION 14
+#define VIE_ABI_VERSION 15
 
 typedef enum {
   VIE_OK = 0,
@@ -223,6 +223,31 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
  * larger FFT boxes per block. */
 vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, const double* eps_r,
                                       const int32_t* block_id, int32_t n_blocks, int32_t overlap, vie_problem** out);
+
+/* A problem in the rooftop discretisation of Sec. II-A, eq. (5) (rooftop
+ * basis functions, pulse testing; the scalar-potential and grad-div parts of
+ * eqs. (7)-(9)).  The unknowns are the normal components of P on the faces
+ * between cells: entry (c, z, y, x) of a 3*nx*ny*nz vector (component-major,
+ * x fastest, as for voxel vectors) is the face between cell (x, y, z) and its
+ * neighbour one step along axis c (x, y, z for c = 0, 1, 2).  The operator is
+ *   (A P)_f = P_f / chi_f - (T P)_f,
+ *   T P = k0^2 (g~ * P) + grad (g~ * div P),
+ * with g~ the scalar Green's function at the cell-centre separation (its
+ * mean over the sphere of the cell's volume at zero separation), * the
+ * discrete convolution times the cell volume, div the cell divergence of
+ * face values and grad the face gradient of cell values (both one-sided
+ * differences over one cell).  The face contrast chi_f = (1 - m) / m with m
+ * the mean of 1/eps_r over the face's two cells (continuity of the normal
+ * flux density).  Faces between two vacuum cells carry no unknown: the
+ * products and solves keep them 0.  The first and last cell layer of every
+ * axis must be vacuum (VIE_EINVAL otherwise).  eps_r as for
+ * vie_problem_create; no blocks.  vie_matvec, vie_matvec_profile,
+ * vie_solve and vie_solve_device (precondition 0; e_tot_out is then the
+ * field on every face, P_f / chi_f) accept it; the field post-processing
+ * (vie_total_field_box, vie_far_field*, vie_rcs), vie_solve_batch,
+ * vie_solve_many and z-pass variant 1 return VIE_EINVAL. */
+vie_status vie_problem_create_rooftop(vie_context* ctx, const vie_grid* grid, const double* eps_r,
+                                      vie_problem** out);
 vie_status vie_problem_destroy(vie_problem* p);
 vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info);
 
@@ -266,6 +291,12 @@ vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* bl
  * 1e-12, else VIE_EINVAL); pol: 3 complex (6 doubles); e_inc: 3*nx*ny*nz
  * complex written.  Host helper, no device needed. */
 vie_status vie_plane_wave(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc);
+
+/* The same wave for rooftop problems (vie_problem_create_rooftop): component
+ * c at the centre of the face between voxel (x, y, z) and its neighbour
+ * along axis c, i.e. half a cell further along that axis than the voxel
+ * centre.  Host helper, no device needed. */
+vie_status vie_plane_wave_faces(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc);
 
 /* y = A x on the device (the hot path's product; eqs. (2)-(4), (6)).
  * x_dev, y_dev: 3*nx*ny*nz complex double.  x is masked to the scatterer

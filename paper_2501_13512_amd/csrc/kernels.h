@@ -50,6 +50,10 @@ struct MvmBatch {
   int zvariant;            // z-pass kernel variant (see tune_zpass)
   int plane;               // 1: x and y transforms fused per z-plane (plane_supported(lx, ly))
   int pvariant;            // plane kernels: planes per workgroup variant (see tune_plane)
+  // 0: collocated voxels (spec: six octant spectra, 1/chi per voxel);
+  // 1: rooftop faces (spec: the scalar octant spectrum and difference
+  // symbols of green_spectrum_rooftop; 1/chi per face, [nsys][3][nz][ny][nx])
+  int rooftop;
 };
 
 // Square transforms small enough for the fused plane kernels.
@@ -120,6 +124,14 @@ int64_t mvm_row_tiles(int lx, int nz, int ny);
 // 6 lx ly lz c128.  Writes both precisions if the pointers are non-null.
 void green_spectra(int nx, int ny, int nz, int lx, int ly, int lz, double dx, double dy, double dz, double k0,
                    c128* scratch, c128* spec64, c64* spec32, const TwiddleSet<double>& tw, hipStream_t s);
+
+// Spectrum of the rooftop discretisation for one box shape: the octant of
+// FFT(k0^2 dV g~) (one component, ox oy oz elements) followed by the
+// difference-symbol tables b_x[lx], b_y[ly], b_z[lz] (see k_zconv_col).
+// `scratch` holds lx ly lz c128.  Writes both precisions if non-null.
+void green_spectrum_rooftop(int nx, int ny, int nz, int lx, int ly, int lz, double dx, double dy, double dz,
+                            double k0, c128* scratch, c128* spec64, c64* spec32, const TwiddleSet<double>& tw,
+                            hipStream_t s);
 
 }  // namespace vie
 
@@ -279,10 +291,14 @@ void record_inner(const int* gate, const KState* st, const int* slots, int nslot
                   int64_t hist_cap, hipStream_t s);
 // number of ACTIVE entries of status[0..n) into *out (device int)
 void count_active(const int* status, int n, int* out, hipStream_t s);
-// y = x * chi_inv (E_tot = P / chi on the scatterer, 0 in vacuum), batched
-void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int ncomp, hipStream_t s);
-// b = e * mask (mask: chi_inv != 0), 3 components of nv voxels
-void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s);
+// y = x * chi_inv (E_tot = P / chi on the scatterer, 0 in vacuum), batched;
+// element i uses chi_inv[i % cper] (cper 0: nv, one value per voxel; 3 nv:
+// one per face of the rooftop discretisation)
+void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int ncomp, hipStream_t s,
+                 int64_t cper = 0);
+// b = e * mask (mask: chi_inv != 0), 3 components of nv voxels; chi_inv
+// indexed as in total_field
+void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s, int64_t cper = 0);
 // r = b - a (c128, n elements) ; partial-free helper for refinement
 void sub_vec(const c128* b, const c128* a, c128* r, int64_t n, hipStream_t s);
 // Batch layout [nrhs][3][nv] <-> stacked layout [3][nrhs][nv] (the same

@@ -661,28 +661,32 @@ void count_active(const int* status, int n, int* out, hipStream_t s) {
   check_launch("count active");
 }
 
-__global__ void kk_total_field(const c128* P, const c128* chi, c128* e, int64_t nv, int ncomp) {
+__global__ void kk_total_field(const c128* P, const c128* chi, c128* e, int64_t nv, int ncomp, int64_t cper) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv * ncomp) return;
-  const c128 ci = chi[i % nv];
+  const c128 ci = chi[i % cper];
   e[i] = (ci.x == 0.0 && ci.y == 0.0) ? mk<double>(0.0, 0.0) : P[i] * ci;
 }
 
-void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int ncomp, hipStream_t s) {
+void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int ncomp, hipStream_t s, int64_t cper) {
   const int64_t n = nv * ncomp;
-  hipLaunchKernelGGL(kk_total_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, chi_inv, e, nv, ncomp);
+  if (cper <= 0) cper = nv;
+  hipLaunchKernelGGL(kk_total_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, chi_inv, e, nv, ncomp,
+                     cper);
   check_launch("total field");
 }
 
-__global__ void kk_masked_copy(const c128* e, const c128* chi, c128* b, int64_t nv) {
+__global__ void kk_masked_copy(const c128* e, const c128* chi, c128* b, int64_t nv, int64_t cper) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 3 * nv) return;
-  const c128 ci = chi[i % nv];
+  const c128 ci = chi[i % cper];
   b[i] = (ci.x == 0.0 && ci.y == 0.0) ? mk<double>(0.0, 0.0) : e[i];
 }
 
-void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s) {
-  hipLaunchKernelGGL(kk_masked_copy, dim3((unsigned)((3 * nv + 255) / 256)), dim3(256), 0, s, e, chi_inv, b, nv);
+void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s, int64_t cper) {
+  if (cper <= 0) cper = nv;
+  hipLaunchKernelGGL(kk_masked_copy, dim3((unsigned)((3 * nv + 255) / 256)), dim3(256), 0, s, e, chi_inv, b, nv,
+                     cper);
   check_launch("masked copy");
 }
 

@@ -78,6 +78,7 @@ struct RowArgs {
   const int* status;
   const cx<R>* tw;
   int mask_input;
+  int chi3;   // 1/chi per component ([3][nz][ny][nx]: rooftop faces) instead of per voxel
   double scale;
   // BiCGSTAB work fused into pass 1 (in_mode) and pass 5 (out_mode)
   int in_mode, out_mode;
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_fwd(Ro
   auto st = [&](int k, cx<R> v) { w[k] = v; };
   if (mode == 0) {
     const c128* xin = a.x + vrow;
-    const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
+    const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)(a.chi3 ? rr : zy) * a.nx;
     const bool msk = a.mask_input != 0;
     auto ld = [&](int n) -> cx<R> {
       if (n < nx) {
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__((Geo<R, L>::T * Geo<R, L>::ROWP)) k_row_inv_lo
   const int c = rr / (a.nz * a.ny), zy = rr - c * (a.nz * a.ny);
   const int z = zy / a.ny, yy = zy - z * a.ny;
   const int64_t vrow = sys * a.vstride + (int64_t)rr * a.nx;
-  const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)zy * a.nx;
+  const c128* chi = a.chi_inv + sys * a.cstride + (int64_t)(a.chi3 ? rr : zy) * a.nx;
   const cx<R>* w = a.work + sys * a.wstride + ((int64_t)(c * a.nz + z) * a.ly + yy) * a.lx;
   cx<R>* slot = lds + p * L;
   const int nx = a.nx;
@@ -328,7 +329,7 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_fwd(RowArgs<
       c128 v = a.x[v0 + e];
       if (msk) {
         const int q = e / pe;
-        const int z = (pl0 + q) % nz;
+        const int z = a.chi3 ? pl0 + q : (pl0 + q) % nz;
         const c128 ci = chi[(int64_t)z * pe + (e - q * pe)];
         if (ci.x == 0.0 && ci.y == 0.0) v = mk<double>(0.0, 0.0);
       }
@@ -476,7 +477,7 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_inv_local(Ro
       const int e = e0 + u * BT + (int)threadIdx.x;
       if (e < ne) {
         const int q = e / pe;
-        ci[u] = chi[(int64_t)((pl0 + q) % nz) * pe + (e - q * pe)];
+        ci[u] = chi[(int64_t)(a.chi3 ? pl0 + q : (pl0 + q) % nz) * pe + (e - q * pe)];
         xv[u] = a.x[v0 + e];
         if (mode == 1 || mode == 3) ov[u] = a.rhat[v0 + e];
         if (mode == 2 || mode == 4) ov[u] = a.s[v0 + e];
@@ -664,6 +665,7 @@ template <typename R>
 struct ZArgs {
   int nz, ly, lx;
   int variant;   // 0, 2, 3, 4: column sets (ZColGeo); 1: mirror columns
+  int rooftop;   // spectral multiply of the rooftop discretisation (column sets only)
   int64_t wstride, sstride;
   cx<R>* work;
   const cx<R>* spec;
@@ -763,7 +765,14 @@ __global__ void __launch_bounds__((3 * ZGeo<R, LZ>::T * ZGeo<R, LZ>::ZP)) k_zcon
   }
 }
 
-template <typename R, int LZ, int V>
+// K = 0: the collocated dyadic multiply (six octant spectra of the symmetric
+// tensor).  K = 1: the rooftop discretisation, whose spectral operator is
+// G'(q) (X_c - conj(b_c) sum_j b_j X_j) with G' = k0^2 dV FFT(g~) (one even
+// octant spectrum) and b_j = (1 - exp(-2 pi i q_j / L_j)) / (k0 d_j), the
+// symbol of the cell divergence of face values; -conj(b_c) is the symbol of
+// the face gradient of cell values.  The spectrum buffer holds the octant of
+// G' followed by the full-length tables b_x[lx], b_y[ly], b_z[lz].
+template <typename R, int LZ, int V, int K>
 __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>::ZP)) k_zconv_col(ZArgs<R> a) {
   using G = ZColGeo<R, LZ, V>;
   constexpr int T = G::TZ, ZP = G::ZP;
@@ -814,6 +823,8 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   R sx = R(1), sy = R(1);
   const cx<R>* const sp = a.spec_tab ? a.spec_tab[sys] : a.spec + sys * a.sstride;
   unsigned soff = 0;
+  cx<R> bx = czero<R>(), by = czero<R>();   // K = 1: difference symbols of the column
+  const unsigned oct32 = (unsigned)oct, fzs = (unsigned)(oy * ox);
   if (cvalid) {
     const int i2 = c2 / lx;
     const int qy = mirror_paired_row(i2, ly), qx = c2 - i2 * lx;
@@ -821,19 +832,31 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
     sx = qx <= hx ? R(1) : R(-1);
     sy = qy <= hy ? R(1) : R(-1);
     soff = (unsigned)(fy * ox + fx);
+    if constexpr (K == 1) {
+      bx = *elem(sp, oct32 + (unsigned)qx);
+      by = *elem(sp, oct32 + (unsigned)(lx + qy));
+    }
   }
-  const unsigned oct32 = (unsigned)oct, fzs = (unsigned)(oy * ox);
-  // spectrum values (xx, xy, xz, yy, yz, zz, parity signs of qx, qy applied)
+  constexpr int NS = K == 1 ? 3 : 6;
+  // K = 0: spectrum values (xx, xy, xz, yy, yz, zz, parity signs of qx, qy
+  // applied); K = 1: G'(fz), b_z(fz), b_z(LZ - fz)
   auto spec_at = [&](int fz, cx<R>* sv) {
     const unsigned o = soff + (unsigned)fz * fzs;
-    sv[0] = *elem(sp, o);
-    sv[1] = (sx * sy) * *elem(sp, oct32 + o);
-    sv[2] = sx * *elem(sp, 2 * oct32 + o);
-    sv[3] = *elem(sp, 3 * oct32 + o);
-    sv[4] = sy * *elem(sp, 4 * oct32 + o);
-    sv[5] = *elem(sp, 5 * oct32 + o);
+    if constexpr (K == 1) {
+      const unsigned bz0 = oct32 + (unsigned)(lx + ly);
+      sv[0] = *elem(sp, o);
+      sv[1] = *elem(sp, bz0 + (unsigned)fz);
+      sv[2] = *elem(sp, bz0 + (unsigned)(fz == 0 ? 0 : LZ - fz));
+    } else {
+      sv[0] = *elem(sp, o);
+      sv[1] = (sx * sy) * *elem(sp, oct32 + o);
+      sv[2] = sx * *elem(sp, 2 * oct32 + o);
+      sv[3] = *elem(sp, 3 * oct32 + o);
+      sv[4] = sy * *elem(sp, 4 * oct32 + o);
+      sv[5] = *elem(sp, 5 * oct32 + o);
+    }
   };
-  cx<R> pre[G::PF ? NF : 1][6];
+  cx<R> pre[G::PF ? NF : 1][NS];
   if constexpr (G::PF) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -853,13 +876,38 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
   fft_pencil<R, LZ, T, -1, false, true>(ldg, sts, slot, ZP, t, valid, a.tw);
 
   // Q(q) = S(q) X(q), S symmetric 3x3 from the octant with parity signs
-  if (cvalid) {
+  if constexpr (K == 1) if (cvalid) {
+    cx<R>* e0 = lds + pp;
+    const cx<R> cbx = conj(bx), cby = conj(by);
+    auto roof = [&](cx<R>* e, cx<R> gq, cx<R> bz) {
+      const cx<R> X = e[0], Y = e[LZ * ZP], Z = e[2 * LZ * ZP];
+      const cx<R> d = bx * X + by * Y + bz * Z;   // divergence
+      e[0] = gq * (X - cbx * d);
+      e[LZ * ZP] = gq * (Y - cby * d);
+      e[2 * LZ * ZP] = gq * (Z - conj(bz) * d);
+    };
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int fz = j0 + f * NFT;
+      if (fz > HZ) break;
+      cx<R> sl[NS];
+      const cx<R>* sv = sl;
+      if constexpr (G::PF)
+        sv = pre[f];
+      else
+        spec_at(fz, sl);
+      roof(e0 + fz * ZP, sv[0], sv[1]);
+      const int qz2 = LZ - fz;
+      if (fz > 0 && qz2 != fz) roof(e0 + qz2 * ZP, sv[0], sv[2]);
+    }
+  }
+  if constexpr (K == 0) if (cvalid) {
     cx<R>* e0 = lds + pp;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int fz = j0 + f * NFT;
       if (fz > HZ) break;
-      cx<R> sl[6];
+      cx<R> sl[NS];
       const cx<R>* sv = sl;
       if constexpr (G::PF)
         sv = pre[f];
@@ -967,7 +1015,10 @@ static void launch_zcol(const ZArgs<R>& a, int nsys, hipStream_t s) {
   using G = ZColGeo<R, L, V>;
   const int cols = a.ly * a.lx;
   const int blocks = ((cols + G::ZP - 1) / G::ZP) * nsys;
-  hipLaunchKernelGGL((k_zconv_col<R, L, V>), dim3(blocks), dim3(3 * G::TZ * G::ZP), 0, s, a);
+  if (a.rooftop)
+    hipLaunchKernelGGL((k_zconv_col<R, L, V, 1>), dim3(blocks), dim3(3 * G::TZ * G::ZP), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_zconv_col<R, L, V, 0>), dim3(blocks), dim3(3 * G::TZ * G::ZP), 0, s, a);
 }
 
 template <typename R>
@@ -977,6 +1028,7 @@ static void launch_zconv(int L, const ZArgs<R>& a, int nsys, hipStream_t s) {
 #define C(l)                                                                                      \
   case l: {                                                                                       \
     if (a.variant == 1) {                                                                         \
+      if (a.rooftop) throw std::runtime_error("z pass: no mirror-column variant for rooftop spectra"); \
       using G = ZGeo<R, l>;                                                                       \
       const int blocks = nfy * ((nfx + G::ZP - 1) / G::ZP) * nsys;                                \
       hipLaunchKernelGGL((k_zconv_mirror<R, l>), dim3(blocks), dim3(3 * G::T * G::ZP), 0, s, a);  \
@@ -1065,6 +1117,7 @@ static RowArgs<R> row_args(const MvmBatch<R>& b, const KBatch* k, const FuseArgs
   ra.status = b.status;
   ra.tw = b.tw->table[b.lx];
   ra.mask_input = mask_input ? 1 : 0;
+  ra.chi3 = b.rooftop;
   ra.scale = 1.0 / ((double)b.lx * (double)b.ly * (double)b.lz);
   ra.r = f.r;
   ra.p = f.p;
@@ -1115,6 +1168,7 @@ void mvm_mid(const MvmBatch<R>& b, hipStream_t s) {
   za.work = b.work;
   za.spec = b.spec;
   za.spec_tab = b.spec_tab;
+  za.rooftop = b.rooftop;
   za.status = b.status;
   za.tw = b.tw->table[b.lz];
   launch_zconv<R>(b.lz, za, b.nsys, s);
@@ -1172,7 +1226,8 @@ void mvm(const MvmBatch<R>& b, const c128* x, c128* y, bool mask_input, hipStrea
     za.sstride = b.sstride;
     za.work = b.work;
     za.spec = b.spec;
-  za.spec_tab = b.spec_tab;
+    za.spec_tab = b.spec_tab;
+    za.rooftop = b.rooftop;
     za.status = b.status;
     za.tw = b.tw->table[b.lz];
     launch_zconv<R>(b.lz, za, b.nsys, s);
@@ -1204,6 +1259,7 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out) {
   int best_v = 0;
   for (int v = 0; v < kZVariants; ++v) {
     if (v >= 2 && b.lz < 32) break;   // short columns: variants 0 and 1 only
+    if (v == 1 && b.rooftop) continue;   // column sets only
     ZArgs<R> za{};
     za.nz = b.nz;
     za.ly = b.ly;
@@ -1213,7 +1269,8 @@ int tune_zpass(const MvmBatch<R>& b, hipStream_t s, float* ms_out) {
     za.sstride = b.sstride;
     za.work = b.work;
     za.spec = b.spec;
-  za.spec_tab = b.spec_tab;
+    za.spec_tab = b.spec_tab;
+    za.rooftop = b.rooftop;
     za.status = nullptr;
     za.tw = b.tw->table[b.lz];
     launch_zconv<R>(b.lz, za, b.nsys, s);   // warm-up
@@ -1403,11 +1460,11 @@ __global__ void k_green_embed(c128* out, int nx, int ny, int nz, int lx, int ly,
   for (int c = 0; c < 6; ++c) out[c * npts + i] = mk<double>(t[c], ti[c]);
 }
 
-__global__ void k_extract_octant(const c128* full, c128* s64, c64* s32, int lx, int ly, int lz) {
+__global__ void k_extract_octant(const c128* full, c128* s64, c64* s32, int lx, int ly, int lz, int ncomp) {
   const int ox = lx / 2 + 1, oy = ly / 2 + 1, oz = lz / 2 + 1;
   const int64_t oct = (int64_t)ox * oy * oz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 6 * oct) return;
+  if (i >= ncomp * oct) return;
   const int c = (int)(i / oct);
   const int64_t r = i - c * oct;
   const int fx = (int)(r % ox), fy = (int)((r / ox) % oy), fz = (int)(r / ((int64_t)ox * oy));
@@ -1463,8 +1520,109 @@ void green_spectra(int nx, int ny, int nz, int lx, int ly, int lz, double dx, do
   launch_col<double, -1>(lz, ca, s);
   const int64_t oct = 6 * (int64_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1);
   hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, s, scratch, spec64, spec32,
-                     lx, ly, lz);
+                     lx, ly, lz, 6);
   check_launch("octant");
+}
+
+// Rooftop discretisation (Sec. II-A, eq. (5)): the scalar kernel
+// k0^2 dV g~(m), g~ the scalar Green's function at the centre separation for
+// m != 0 and its mean over the sphere of the cell's volume at m = 0,
+//   k0^2 dV g~(0) = (1 + j k0 a) exp(-j k0 a) - 1,  a = (3 dV / 4 pi)^(1/3)
+// (the radial integral of r exp(-j k0 r) from 0 to a).  Same slot layout as
+// k_green_embed, one component.
+__global__ void k_green_embed_scalar(c128* out, int nx, int ny, int nz, int lx, int ly, int lz, double dx, double dy,
+                                     double dz, double k0) {
+  const int64_t npts = (int64_t)lx * ly * lz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts) return;
+  const int sx = (int)(i % lx);
+  const int sy = (int)((i / lx) % ly);
+  const int sz = (int)(i / ((int64_t)lx * ly));
+  bool okx, oky, okz;
+  const int mx = slot_offset(sx, nx, lx, &okx);
+  const int my = slot_offset(sy, ny, ly, &oky);
+  const int mz = slot_offset(sz, nz, lz, &okz);
+  double re = 0.0, im = 0.0;
+  if (okx && oky && okz) {
+    const double dV = dx * dy * dz;
+    if (mx == 0 && my == 0 && mz == 0) {
+      const double x = k0 * cbrt(3.0 * dV / (4.0 * M_PI));
+      double sn, cs;
+      sincos(x, &sn, &cs);
+      re = cs + x * sn - 1.0;
+      im = x * cs - sn;
+    } else {
+      const double Rx = mx * dx, Ry = my * dy, Rz = mz * dz;
+      const double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+      double sn, cs;
+      sincos(k0 * R, &sn, &cs);
+      const double f = k0 * k0 * dV / (4.0 * M_PI * R);
+      re = f * cs;
+      im = -f * sn;
+    }
+  }
+  out[i] = mk<double>(re, im);
+}
+
+// b_j(q) = (1 - exp(-2 pi i q / L_j)) / (k0 d_j) for q in [0, L_j), the three
+// axes one after the other: 1 - cos t = 2 sin^2(t / 2) keeps the small
+// symbols accurate.
+__global__ void k_diff_symbols(c128* s64, c64* s32, int lx, int ly, int lz, double dx, double dy, double dz,
+                               double k0) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= lx + ly + lz) return;
+  int q = i, L = lx;
+  double d = dx;
+  if (q >= lx) {
+    q -= lx;
+    L = ly;
+    d = dy;
+    if (q >= ly) {
+      q -= ly;
+      L = lz;
+      d = dz;
+    }
+  }
+  double sh, ch, sf, cf;
+  sincospi((double)q / L, &sh, &ch);
+  sincospi(2.0 * q / L, &sf, &cf);
+  const c128 b = mk<double>(2.0 * sh * sh / (k0 * d), sf / (k0 * d));
+  if (s64) s64[i] = b;
+  if (s32) s32[i] = cvt<float>(b);
+}
+
+void green_spectrum_rooftop(int nx, int ny, int nz, int lx, int ly, int lz, double dx, double dy, double dz,
+                            double k0, c128* scratch, c128* spec64, c64* spec32, const TwiddleSet<double>& tw,
+                            hipStream_t s) {
+  const int64_t npts = (int64_t)lx * ly * lz;
+  hipLaunchKernelGGL(k_green_embed_scalar, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, scratch, nx, ny,
+                     nz, lx, ly, lz, dx, dy, dz, k0);
+  check_launch("rooftop embed");
+  launch_row_full(lx, scratch, (int64_t)ly * lz, tw.table[lx], s);
+  ColArgs<double> ca{};
+  ca.data = scratch;
+  ca.outer = lz;
+  ca.inner = lx;
+  ca.n_in = ly;
+  ca.n_out = ly;
+  ca.stride = 0;
+  ca.status = nullptr;
+  ca.tw = tw.table[ly];
+  ca.nsys = 1;
+  launch_col<double, -1>(ly, ca, s);
+  ca.outer = 1;
+  ca.inner = lx * ly;
+  ca.n_in = lz;
+  ca.n_out = lz;
+  ca.tw = tw.table[lz];
+  launch_col<double, -1>(lz, ca, s);
+  const int64_t oct = (int64_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1);
+  hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, s, scratch, spec64, spec32,
+                     lx, ly, lz, 1);
+  check_launch("rooftop octant");
+  hipLaunchKernelGGL(k_diff_symbols, dim3((unsigned)((lx + ly + lz + 255) / 256)), dim3(256), 0, s,
+                     spec64 ? spec64 + oct : nullptr, spec32 ? spec32 + oct : nullptr, lx, ly, lz, dx, dy, dz, k0);
+  check_launch("rooftop symbols");
 }
 
 }  // namespace vie

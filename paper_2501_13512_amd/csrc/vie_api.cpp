@@ -190,8 +190,9 @@ void cis_neg(long t, long L, double* c, double* s) {
 struct SpecKey {
   int lx, ly, lz;
   double dx, dy, dz, k0;
+  int kind;   // 0: collocated dyadic spectra, 1: rooftop scalar spectrum and symbols
   bool operator<(const SpecKey& o) const {
-    return std::tie(lx, ly, lz, dx, dy, dz, k0) < std::tie(o.lx, o.ly, o.lz, o.dx, o.dy, o.dz, o.k0);
+    return std::tie(lx, ly, lz, dx, dy, dz, k0, kind) < std::tie(o.lx, o.ly, o.lz, o.dx, o.dy, o.dz, o.k0, o.kind);
   }
 };
 
@@ -229,9 +230,14 @@ struct vie_context {
 
 namespace {
 
+int64_t spectra_elems(int lx, int ly, int lz, int kind) {
+  const int64_t oct = (int64_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1);
+  return kind == 1 ? oct + lx + ly + lz : 6 * oct;
+}
+
 std::shared_ptr<Spectra> get_spectra(vie_context* ctx, int lx, int ly, int lz, double dx, double dy, double dz,
-                                     double k0, hipStream_t s) {
-  SpecKey key{lx, ly, lz, dx, dy, dz, k0};
+                                     double k0, hipStream_t s, int kind = 0) {
+  SpecKey key{lx, ly, lz, dx, dy, dz, k0, kind};
   {
     std::lock_guard<std::mutex> g(ctx->mu);
     auto it = ctx->cache.find(key);
@@ -239,14 +245,18 @@ std::shared_ptr<Spectra> get_spectra(vie_context* ctx, int lx, int ly, int lz, d
       if (auto sp = it->second.lock()) return sp;
   }
   auto sp = std::make_shared<Spectra>();
-  const int64_t oct = 6 * (int64_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1);
-  sp->s64.alloc(oct * sizeof(c128));
-  sp->s32.alloc(oct * sizeof(c64));
-  DevBuf scratch(6 * (size_t)lx * ly * lz * sizeof(c128));
+  const int64_t ne = spectra_elems(lx, ly, lz, kind);
+  sp->s64.alloc(ne * sizeof(c128));
+  sp->s32.alloc(ne * sizeof(c64));
+  DevBuf scratch((kind == 1 ? 1 : 6) * (size_t)lx * ly * lz * sizeof(c128));
   // embed with the largest box the lengths support: a box of n <= (L+1)/2
   // voxels touches only offsets |m| <= n - 1, all of which are present.
-  vie::green_spectra((lx + 1) / 2, (ly + 1) / 2, (lz + 1) / 2, lx, ly, lz, dx, dy, dz, k0, scratch.as<c128>(),
-                     sp->s64.as<c128>(), sp->s32.as<c64>(), ctx->tws64, s);
+  if (kind == 1)
+    vie::green_spectrum_rooftop((lx + 1) / 2, (ly + 1) / 2, (lz + 1) / 2, lx, ly, lz, dx, dy, dz, k0,
+                                scratch.as<c128>(), sp->s64.as<c128>(), sp->s32.as<c64>(), ctx->tws64, s);
+  else
+    vie::green_spectra((lx + 1) / 2, (ly + 1) / 2, (lz + 1) / 2, lx, ly, lz, dx, dy, dz, k0, scratch.as<c128>(),
+                       sp->s64.as<c128>(), sp->s32.as<c64>(), ctx->tws64, s);
   hip_check(hipStreamSynchronize(s), "spectra");
   std::lock_guard<std::mutex> g(ctx->mu);
   auto& slot = ctx->cache[key];
@@ -306,7 +316,8 @@ struct ProblemPlan {
   int64_t nv = 0;
   int lx = 0, ly = 0, lz = 0;
   double k0 = 0;
-  std::vector<c128> chi;      // 1/chi, 0 on vacuum
+  std::vector<c128> chi;      // 1/chi, 0 on vacuum (rooftop: per face, [3][nz][ny][nx])
+  bool rooftop = false;       // staggered rooftop unknowns on cell faces (no blocks)
   bool has_blocks = false;
   int n_blocks = 0;
   std::vector<int32_t> bid;   // -1 on vacuum
@@ -327,6 +338,7 @@ struct vie_problem {
   vie_context* ctx = nullptr;
   vie_grid g{};
   int64_t nv = 0;
+  bool rooftop = false;   // rooftop discretisation: 1/chi per face (3 nv entries), scalar spectrum
   int lx = 0, ly = 0, lz = 0;
   double k0 = 0;
   std::shared_ptr<Spectra> spec;
@@ -486,7 +498,8 @@ MvmBatch<R> outer_batch(vie_problem& P, bool gated) {
   b.lz = P.lz;
   b.nsys = 1;
   b.vstride = 3 * P.nv;
-  b.cstride = P.nv;
+  b.cstride = P.rooftop ? 3 * P.nv : P.nv;
+  b.rooftop = P.rooftop ? 1 : 0;
   b.wstride = 3 * (int64_t)P.g.nz * P.ly * P.lx;
   b.sstride = 0;
   b.chi_inv = P.chi.as<c128>();
@@ -525,6 +538,14 @@ MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
   if (G.spec_tab.p)
     b.spec_tab = G.spec_tab.as<const cx<R>*>() + (sizeof(R) == sizeof(float) ? G.nsys : 0);
   return b;
+}
+
+// Entries of the problem's 1/chi per period: one per voxel, or one per face
+// (three per voxel) for the rooftop discretisation.
+int64_t chi_period(const vie_problem& P) { return P.rooftop ? 3 * P.nv : P.nv; }
+
+void collocated_only(const vie_problem* p, const char* what) {
+  if (p && p->rooftop) fail(VIE_EINVAL, std::string(what) + ": not available for rooftop problems");
 }
 
 KBatch outer_kbatch(vie_problem& P) {
@@ -1051,7 +1072,7 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
     hist_cap = stats->inner_hist_cap;
   }
   if (prec) hip_check(hipMemsetAsync(P.d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
-  if (!solved) vie::masked_copy(e_inc, P.chi.as<c128>(), v[V_B], P.nv, s);
+  if (!solved) vie::masked_copy(e_inc, P.chi.as<c128>(), v[V_B], P.nv, s, chi_period(P));
   RunResult rr;
   int refine = 0, refine_iters = 0;
   double relres_true = 0;
@@ -1092,7 +1113,7 @@ vie_status solve_impl(vie_problem* p, const c128* e_inc, const vie_opts* o, c128
       relres_true = true_relres(P, v[V_B], v[V_X], v[V_TMP1], v[V_TMP2], nb, s);
     }
   }
-  vie::total_field(v[V_X], P.chi.as<c128>(), e_tot, P.nv, 3, s);
+  vie::total_field(v[V_X], P.chi.as<c128>(), e_tot, P.nv, 3, s, chi_period(P));
   if (pol) hip_check(hipMemcpyAsync(pol, v[V_X], 3 * P.nv * sizeof(c128), hipMemcpyDeviceToDevice, s), "pol");
   int64_t acc[3] = {0, 0, 0};
   if (prec) hip_check(hipMemcpyAsync(acc, P.d_acc.p, sizeof(acc), hipMemcpyDeviceToHost, s), "acc");
@@ -1671,13 +1692,58 @@ ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* blo
   return pl;
 }
 
-size_t spectra_bytes(int lx, int ly, int lz) {
-  return 6 * (size_t)(lx / 2 + 1) * (ly / 2 + 1) * (lz / 2 + 1) * (sizeof(c128) + sizeof(c64));
+// Rooftop discretisation (Sec. II-A, eq. (5)): the unknowns are the normal
+// components of P on the faces between cells.  Face c + e_i / 2 (index c of
+// component i) joins cells c and c + e_i; the normal flux density is
+// continuous across it, so the face's field is D times the mean m of 1/eps
+// of the two cells, and P = D - E gives the face contrast chi_f = (1 - m) / m,
+// stored as 1/chi_f = m / (1 - m).  Faces between two vacuum cells, faces
+// past the grid's last layer and faces with m = 1 carry no unknown
+// (1/chi_f = 0).  The first and last cell layers of every axis must be
+// vacuum: every face with an unknown then lies inside the grid, and the
+// cell divergence and the face gradient need no boundary terms.
+ProblemPlan make_plan_rooftop(const vie_grid& g, const double* eps_r) {
+  ProblemPlan pl = make_plan(g, eps_r, nullptr, 0);   // sizes, finiteness, FFT lengths
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int64_t nv = pl.nv;
+  auto vac = [&](int64_t i) { return eps_r[2 * i] == 1.0 && eps_r[2 * i + 1] == 0.0; };
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const bool edge = x == 0 || y == 0 || z == 0 || x == nx - 1 || y == ny - 1 || z == nz - 1;
+        if (edge && !vac(((int64_t)z * ny + y) * nx + x))
+          fail(VIE_EINVAL, "rooftop problems need vacuum in the first and last cell layer of every axis");
+      }
+  auto inv_eps = [&](int64_t i) {
+    return vac(i) ? std::complex<double>(1.0, 0.0) : 1.0 / std::complex<double>(eps_r[2 * i], eps_r[2 * i + 1]);
+  };
+  std::vector<c128> chi(3 * (size_t)nv, mk<double>(0.0, 0.0));
+  const int64_t step[3] = {1, nx, (int64_t)nx * ny};
+  for (int c = 0; c < 3; ++c)
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int pos[3] = {x, y, z}, n[3] = {nx, ny, nz};
+          if (pos[c] == n[c] - 1) continue;
+          const int64_t i = ((int64_t)z * ny + y) * nx + x, j = i + step[c];
+          if (vac(i) && vac(j)) continue;
+          const std::complex<double> m = 0.5 * (inv_eps(i) + inv_eps(j));
+          if (m == 1.0) continue;
+          const std::complex<double> v = m / (1.0 - m);
+          chi[(size_t)c * nv + i] = mk<double>(v.real(), v.imag());
+        }
+  pl.chi = std::move(chi);
+  pl.rooftop = true;
+  return pl;
 }
 
-bool spectra_cached(vie_context* ctx, int lx, int ly, int lz, const vie_grid& g, double k0) {
+size_t spectra_bytes(int lx, int ly, int lz, int kind = 0) {
+  return (size_t)spectra_elems(lx, ly, lz, kind) * (sizeof(c128) + sizeof(c64));
+}
+
+bool spectra_cached(vie_context* ctx, int lx, int ly, int lz, const vie_grid& g, double k0, int kind = 0) {
   std::lock_guard<std::mutex> lk(ctx->mu);
-  auto it = ctx->cache.find(SpecKey{lx, ly, lz, g.dx, g.dy, g.dz, k0});
+  auto it = ctx->cache.find(SpecKey{lx, ly, lz, g.dx, g.dy, g.dz, k0, kind});
   return it != ctx->cache.end() && !it->second.expired();
 }
 
@@ -1688,15 +1754,16 @@ bool spectra_cached(vie_context* ctx, int lx, int ly, int lz, const vie_grid& g,
 size_t plan_footprint(vie_context* ctx, const ProblemPlan& pl, bool all_spectra = false) {
   const auto& g = pl.g;
   const size_t nv = (size_t)pl.nv;
-  size_t foot = nv * sizeof(c128)                                       // 1/chi
+  size_t foot = (pl.rooftop ? 3 : 1) * nv * sizeof(c128)                 // 1/chi
                 + 3 * (size_t)g.nz * pl.ly * pl.lx * sizeof(c128)       // work
                 + V_COUNT * 3 * nv * sizeof(c128)                       // Krylov vectors
                 + 2 * 4 * (size_t)std::max(vie::krylov_chunks(3 * (int64_t)nv), vie::mvm_row_tiles(pl.lx, g.nz, g.ny)) *
                       sizeof(double);   // two partial buffers
   std::set<std::tuple<int, int, int>> seen;
+  const int kind = pl.rooftop ? 1 : 0;
   auto spec = [&](int lx, int ly, int lz) {
-    if (seen.insert({lx, ly, lz}).second && (all_spectra || !spectra_cached(ctx, lx, ly, lz, g, pl.k0)))
-      foot += spectra_bytes(lx, ly, lz);
+    if (seen.insert({lx, ly, lz}).second && (all_spectra || !spectra_cached(ctx, lx, ly, lz, g, pl.k0, kind)))
+      foot += spectra_bytes(lx, ly, lz, kind);
   };
   spec(pl.lx, pl.ly, pl.lz);
   int64_t ipstride = 0, slots = 0;
@@ -1717,7 +1784,7 @@ size_t plan_footprint(vie_context* ctx, const ProblemPlan& pl, bool all_spectra 
 // precision, so every problem of that shape uses the same kernels.
 template <typename R>
 int cached_zvariant(vie_context* ctx, const MvmBatch<R>& b, hipStream_t s, float* ms) {
-  const std::array<int, 8> key{(int)sizeof(R), b.nx, b.ny, b.nz, b.lx, b.ly, b.lz, b.nsys};
+  const std::array<int, 8> key{(int)sizeof(R) + 64 * b.rooftop, b.nx, b.ny, b.nz, b.lx, b.ly, b.lz, b.nsys};
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto it = ctx->ztune.find(key);
@@ -1741,7 +1808,7 @@ int cached_zvariant(vie_context* ctx, const MvmBatch<R>& b, hipStream_t s, float
 // no data yet (clobbered).
 template <typename R>
 int cached_pvariant(vie_context* ctx, const MvmBatch<R>& b, const c128* x, c128* y, hipStream_t s, float* ms) {
-  const std::array<int, 8> key{(int)sizeof(R), b.nx, b.ny, b.nz, b.lx, b.ly, b.lz, b.nsys};
+  const std::array<int, 8> key{(int)sizeof(R) + 64 * b.rooftop, b.nx, b.ny, b.nz, b.lx, b.ly, b.lz, b.nsys};
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto it = ctx->ptune.find(key);
@@ -1776,8 +1843,9 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
   P->lz = pl.lz;
   P->k0 = pl.k0;
   P->overlap = pl.overlap;
+  P->rooftop = pl.rooftop;
   if (!inner_only) {
-    P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0, s);
+    P->spec = get_spectra(ctx, P->lx, P->ly, P->lz, g.dx, g.dy, g.dz, P->k0, s, pl.rooftop ? 1 : 0);
     upload(P->chi, pl.chi, s);
     P->work.alloc(3 * (size_t)g.nz * P->ly * P->lx * sizeof(c128));
     P->work.zero(s);
@@ -2192,14 +2260,16 @@ vie_status vie_context_destroy(vie_context* ctx) {
   });
 }
 
+// overlap < 0: the rooftop discretisation (no blocks)
 static vie_status problem_create(vie_context* ctx, const vie_grid* grid, const double* eps_r,
                                  const int32_t* block_id, int32_t n_blocks, int32_t overlap, vie_problem** out) {
   return guarded([&]() -> vie_status {
     if (!out) fail(VIE_EINVAL, "out is NULL");
     *out = nullptr;
     if (!ctx || !grid || !eps_r) fail(VIE_EINVAL, "ctx, grid and eps_r are required");
-    if (overlap < 0 || overlap > 256) fail(VIE_EINVAL, "overlap must be in [0, 256]");
-    ProblemPlan plan = make_plan(*grid, eps_r, block_id, n_blocks, block_id ? overlap : 0);
+    if (overlap < -1 || overlap > 256) fail(VIE_EINVAL, "overlap must be in [0, 256]");
+    ProblemPlan plan = overlap < 0 ? make_plan_rooftop(*grid, eps_r)
+                                   : make_plan(*grid, eps_r, block_id, n_blocks, block_id ? overlap : 0);
     set_device(ctx);
     const size_t foot = plan_footprint(ctx, plan);
     {
@@ -2229,7 +2299,16 @@ vie_status vie_problem_create(vie_context* ctx, const vie_grid* grid, const doub
 
 vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, const double* eps_r,
                                       const int32_t* block_id, int32_t n_blocks, int32_t overlap, vie_problem** out) {
+  if (overlap < 0) {
+    if (out) *out = nullptr;
+    return guarded([]() -> vie_status { fail(VIE_EINVAL, "overlap must be in [0, 256]"); });
+  }
   return problem_create(ctx, grid, eps_r, block_id, n_blocks, overlap, out);
+}
+
+vie_status vie_problem_create_rooftop(vie_context* ctx, const vie_grid* grid, const double* eps_r,
+                                      vie_problem** out) {
+  return problem_create(ctx, grid, eps_r, nullptr, 0, -1, out);
 }
 
 vie_status vie_problem_destroy(vie_problem* p) {
@@ -2260,6 +2339,7 @@ vie_status vie_problem_set_zpass(vie_problem* p, int32_t precision, int32_t vari
     if (!p) fail(VIE_EINVAL, "problem is NULL");
     if (precision != VIE_FP64 && precision != VIE_MIXED) fail(VIE_EINVAL, "unknown precision");
     if (variant < -1 || variant >= vie::kZPassVariants) fail(VIE_EINVAL, "z-pass variant out of range");
+    if (variant == 1 && p->rooftop) fail(VIE_EINVAL, "rooftop problems have no mirror-column z pass (variant 1)");
     set_device(p->ctx);
     {
       ApiShared api;
@@ -2394,7 +2474,10 @@ vie_status vie_plan(const vie_grid* grid, const double* eps_r, const int32_t* bl
   });
 }
 
-vie_status vie_plane_wave(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc) {
+// faces: component c sampled half a cell further along axis c (the face
+// centres of the rooftop unknowns)
+static vie_status plane_wave(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc,
+                             bool faces) {
   return guarded([&]() -> vie_status {
     if (!grid || !kdir || !pol || !e_inc) fail(VIE_EINVAL, "all arguments are required");
     const vie_grid g = *grid;
@@ -2412,17 +2495,26 @@ vie_status vie_plane_wave(const vie_grid* grid, const double kdir[3], const doub
         for (int x = 0; x < g.nx; ++x) {
           const double rx = (x - 0.5 * (g.nx - 1)) * g.dx, ry = (y - 0.5 * (g.ny - 1)) * g.dy,
                        rz = (z - 0.5 * (g.nz - 1)) * g.dz;
-          const double ph = -k0 * (kdir[0] * rx + kdir[1] * ry + kdir[2] * rz);
-          const std::complex<double> e = std::polar(1.0, ph);
           const int64_t v = ((int64_t)z * g.ny + y) * g.nx + x;
           for (int c = 0; c < 3; ++c) {
-            const std::complex<double> val = std::complex<double>(pol[2 * c], pol[2 * c + 1]) * e;
+            const double sx = faces && c == 0 ? 0.5 * g.dx : 0.0, sy = faces && c == 1 ? 0.5 * g.dy : 0.0,
+                         sz = faces && c == 2 ? 0.5 * g.dz : 0.0;
+            const double ph = -k0 * (kdir[0] * (rx + sx) + kdir[1] * (ry + sy) + kdir[2] * (rz + sz));
+            const std::complex<double> val = std::complex<double>(pol[2 * c], pol[2 * c + 1]) * std::polar(1.0, ph);
             e_inc[2 * (c * nv + v)] = val.real();
             e_inc[2 * (c * nv + v) + 1] = val.imag();
           }
         }
     return VIE_OK;
   });
+}
+
+vie_status vie_plane_wave(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc) {
+  return plane_wave(grid, kdir, pol, e_inc, false);
+}
+
+vie_status vie_plane_wave_faces(const vie_grid* grid, const double kdir[3], const double pol[6], double* e_inc) {
+  return plane_wave(grid, kdir, pol, e_inc, true);
 }
 
 vie_status vie_matvec(vie_problem* p, int32_t precision, const void* x_dev, void* y_dev, void* stream) {
@@ -2459,6 +2551,7 @@ vie_status vie_total_field_box(vie_problem* p, int32_t precision, const void* po
   return guarded([&]() -> vie_status {
     if (!p || !pol_dev || !e_inc_dev || !e_box_dev) fail(VIE_EINVAL, "problem, pol, e_inc and e_box are required");
     if (e_box_dev == pol_dev || e_box_dev == e_inc_dev) fail(VIE_EINVAL, "e_box must not overlap the inputs");
+    collocated_only(p, "vie_total_field_box");
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
     hipStream_t s = (hipStream_t)stream;
@@ -2476,6 +2569,7 @@ extern "C++" {
 static void far_field_host(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat,
                            std::vector<c128>& F, hipStream_t s) {
   if (!p || !pol_dev || !rhat) fail(VIE_EINVAL, "problem, pol and rhat are required");
+  collocated_only(p, "far field");
   if (n_dir < 1 || n_dir > 1000000) fail(VIE_EINVAL, "n_dir out of range");
   for (int32_t d = 0; d < n_dir; ++d) {
     const double* r = rhat + 3 * d;
@@ -2513,6 +2607,7 @@ vie_status vie_far_field_noalloc(vie_problem* p, const void* pol_dev, int32_t n_
                                  void* f_dev, void* stream) {
   return guarded([&]() -> vie_status {
     if (!p || !pol_dev || !rhat_dev || !f_dev) fail(VIE_EINVAL, "problem, pol, rhat and f are required");
+    collocated_only(p, "vie_far_field_noalloc");
     if (n_dir < 1) fail(VIE_EINVAL, "n_dir must be >= 1");
     const int64_t nchunk = vie::far_field_chunks(p->nv);
     if ((int64_t)n_dir * nchunk * 6 > vie::far_field_scratch_doubles())
@@ -2708,6 +2803,7 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
   return guarded([&]() -> vie_status {
     if (!p || !e_inc_dev || !e_tot_dev) fail(VIE_EINVAL, "problem, e_inc and e_tot are required");
     if (nrhs < 1 || nrhs > 4096) fail(VIE_EINVAL, "nrhs must be in [1, 4096]");
+    collocated_only(p, "vie_solve_batch");
     validate_opts(opts, !p->groups.empty());
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
@@ -2791,6 +2887,7 @@ vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* c
     vie_problem& P0 = *ps[0];
     const bool prec = opts && opts->precondition != 0;
     for (vie_problem* q : ps) {
+      collocated_only(q, "vie_solve_many");
       if (q->ctx != P0.ctx) fail(VIE_EINVAL, "problems belong to different contexts");
       if (q->g.nx != P0.g.nx || q->g.ny != P0.g.ny || q->g.nz != P0.g.nz || q->lx != P0.lx || q->ly != P0.ly ||
           q->lz != P0.lz)

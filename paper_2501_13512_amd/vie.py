@@ -55,8 +55,8 @@ STATUS_NAMES = {0: "VIE_OK", 1: "VIE_NOT_CONVERGED", -1: "VIE_EINVAL", -2: "VIE_
                 -4: "VIE_EBREAKDOWN", -5: "VIE_EBUSY", -6: "VIE_ECANCELLED", -7: "VIE_EINTERNAL", -8: "VIE_ETIMEDOUT"}
 
 ABI_SYMBOLS = ("vie_abi_version", "vie_last_error", "vie_context_create", "vie_context_destroy",
-               "vie_problem_create", "vie_problem_create_overlap", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass", "vie_problem_set_plane",
-               "vie_plane_wave", "vie_plan",
+               "vie_problem_create", "vie_problem_create_overlap", "vie_problem_create_rooftop", "vie_problem_destroy", "vie_problem_get_info", "vie_problem_set_zpass", "vie_problem_set_plane",
+               "vie_plane_wave", "vie_plane_wave_faces", "vie_plan",
                "vie_matvec", "vie_matvec_profile", "vie_group_profile", "vie_block_matvec", "vie_precond_apply", "vie_solve", "vie_solve_device",
                "vie_solve_batch", "vie_solve_many",
                "vie_server_start", "vie_footprint", "vie_submit", "vie_wait", "vie_cancel",
@@ -117,11 +117,13 @@ for _name, _args in {
     "vie_problem_create": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
     "vie_problem_create_overlap": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.POINTER(_vp)],
+    "vie_problem_create_rooftop": [_vp, ctypes.POINTER(vie_grid), _vp, ctypes.POINTER(_vp)],
     "vie_problem_destroy": [_vp],
     "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
     "vie_problem_set_zpass": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_problem_set_plane": [_vp, ctypes.c_int32, ctypes.c_int32],
     "vie_plane_wave": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
+    "vie_plane_wave_faces": [ctypes.POINTER(vie_grid), _vp, _vp, _vp],
     "vie_plan": [ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vie_problem_info),
                  _vp, ctypes.c_int32, _vp],
     "vie_matvec": [_vp, ctypes.c_int32, _vp, _vp, _vp],
@@ -199,6 +201,14 @@ def vie_problem_create_overlap(ctx: int, grid: vie_grid, eps_r: np.ndarray, bloc
     return out.value
 
 
+def vie_problem_create_rooftop(ctx: int, grid: vie_grid, eps_r: np.ndarray) -> int:
+    eps = np.ascontiguousarray(eps_r, dtype=np.complex128)
+    out = _vp()
+    _check(_lib.vie_problem_create_rooftop(ctx, ctypes.byref(grid), _np_ptr(eps), ctypes.byref(out)),
+           "vie_problem_create_rooftop")
+    return out.value
+
+
 def vie_problem_destroy(p: int) -> None:
     _check(_lib.vie_problem_destroy(p), "vie_problem_destroy")
 
@@ -236,6 +246,15 @@ def vie_plane_wave(grid: vie_grid, kdir: Sequence[float], pol: Sequence[complex]
     pl = np.ascontiguousarray(np.asarray(pol, dtype=np.complex128))
     out = np.empty((3, grid.nz, grid.ny, grid.nx), dtype=np.complex128)
     _check(_lib.vie_plane_wave(ctypes.byref(grid), _np_ptr(k), _np_ptr(pl), _np_ptr(out)), "vie_plane_wave")
+    return out
+
+
+def vie_plane_wave_faces(grid: vie_grid, kdir: Sequence[float], pol: Sequence[complex]) -> np.ndarray:
+    k = np.ascontiguousarray(kdir, dtype=np.float64)
+    pl = np.ascontiguousarray(np.asarray(pol, dtype=np.complex128))
+    out = np.empty((3, grid.nz, grid.ny, grid.nx), dtype=np.complex128)
+    _check(_lib.vie_plane_wave_faces(ctypes.byref(grid), _np_ptr(k), _np_ptr(pl), _np_ptr(out)),
+           "vie_plane_wave_faces")
     return out
 
 
@@ -408,11 +427,15 @@ class Problem:
     """Owns a context (optional) and a problem handle."""
 
     def __init__(self, grid: vie_grid, eps: np.ndarray, block_id: Optional[np.ndarray] = None, n_blocks: int = 0,
-                 ctx: Optional[int] = None, device: int = 0, overlap: int = 0):
+                 ctx: Optional[int] = None, device: int = 0, overlap: int = 0, rooftop: bool = False):
         self._own_ctx = ctx is None
         self.ctx = vie_context_create(device) if ctx is None else ctx
         self.grid = grid
-        if overlap and block_id is not None:
+        if rooftop:
+            if block_id is not None:
+                raise ValueError("rooftop problems take no blocks")
+            self.handle = vie_problem_create_rooftop(self.ctx, grid, eps)
+        elif overlap and block_id is not None:
             self.handle = vie_problem_create_overlap(self.ctx, grid, eps, block_id, n_blocks, overlap)
         else:
             self.handle = vie_problem_create(self.ctx, grid, eps, block_id, n_blocks)

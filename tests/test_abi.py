@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import operator as op, physics
+from oracle import operator as op, physics, rooftop
 from paper_2501_13512_amd import vie as V
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 
 def test_abi_version():
-    assert V.vie_abi_version() == 14
+    assert V.vie_abi_version() == 15
 
 
 def _has_gpu():
@@ -68,6 +68,19 @@ def test_plane_wave_matches_oracle(kdir, pol):
     want = physics.plane_wave(g, kdir, pol)
     got = V.vie_plane_wave(V.make_grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.wavelength),
                            kdir, pol)
+    assert np.abs(got - want).max() <= 1e-13
+
+
+@pytest.mark.parametrize("kdir,pol", [((0, 0, 1), (1, 0, 0)), ((0.6, 0, 0.8), (0.8, 0, -0.6)),
+                                      ((0, 1, 0), (0, 0, 1j))])
+def test_face_plane_wave_matches_rooftop_oracle(kdir, pol):
+    """The rooftop unknowns' incident field: component c at its face centre,
+    half a cell along axis c from the voxel centre."""
+    case = W.random_tiny(4, (5, 4, 7), spacing=(0.03, 0.05, 0.04), wavelength=0.7)
+    g = op.Grid.from_case(case)
+    want = rooftop.plane_wave(g, kdir, pol)
+    got = V.vie_plane_wave_faces(V.make_grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz,
+                                             case.wavelength), kdir, pol)
     assert np.abs(got - want).max() <= 1e-13
 
 

@@ -1,0 +1,200 @@
+"""GPU parity of the rooftop discretisation (Sec. II-A, eq. (5); the split
+of eqs. (7)-(9)) against the oracle's rooftop operator, element by element:
+products on random padded grids (plane-kernel and row-kernel shapes, short
+and long z columns, ragged sizes, every z-pass variant), the padded
+metasurface at full size, plain solves of a dielectric sphere, and the
+argument checks of the rooftop entry points.
+
+Products: max |GPU - oracle| / max |oracle| <= 1e-12 in FP64 and <= 1e-5
+in mixed mode (complex FP32 FFT), as for the collocated product; faces
+without an unknown are exactly zero.  Solves: the GPU and the oracle run
+BiCGSTAB to the same tolerance from x0 = 0; the solutions agree to a few
+times tol times the conditioning (bars stated per test)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import rooftop as rt, operator as op
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_2501_13512_amd import vie as V  # noqa: E402
+
+TOL = {V.VIE_FP64: 1e-12, V.VIE_MIXED: 1e-5}
+
+# interior shapes (nz, ny, nx); the grids are one vacuum layer larger per side
+SMALL = [(1, 1, 1), (2, 1, 3), (3, 5, 4), (6, 5, 4), (4, 7, 2)]
+MID = [(16, 16, 16), (12, 20, 33), (7, 48, 24), (40, 21, 13), (30, 14, 14), (9, 3, 100), (32, 64, 64)]
+
+
+def _case(seed, interior, fill=0.7):
+    return W.padded(W.random_tiny(seed, interior, fill=fill))
+
+
+def _grid(case):
+    return V.make_grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.wavelength)
+
+
+def _rand(seed, shape):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)
+
+
+def _matvec(P, x, prec):
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.full_like(xd, complex("nan"))
+    V.vie_matvec(P.handle, prec, xd, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def _assert_close(got, want, fmask, tol):
+    assert np.all(got[~fmask] == 0), "faces without an unknown must be zero"
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= tol, err
+
+
+def _check_product(ctx, case, seed, precs=(V.VIE_FP64, V.VIE_MIXED), variants=(None,)):
+    g = op.Grid.from_case(case)
+    fm = rt.face_mask(g)
+    x = _rand(seed, case.shape)
+    want = rt.RooftopFFT(g)(x)
+    P = V.Problem(_grid(case), case.eps, ctx=ctx, rooftop=True)
+    try:
+        for prec in precs:
+            for v in variants:
+                if v is not None:
+                    V.vie_problem_set_zpass(P.handle, prec, v)
+                print(f"rooftop product {case.name} prec {prec} variant {v}", flush=True)
+                _assert_close(_matvec(P, x, prec), want, fm, TOL[prec])
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("interior", SMALL)
+def test_rooftop_product_small(vie_ctx, interior):
+    seed = 5000 + sum(s * 31 ** i for i, s in enumerate(interior))
+    _check_product(vie_ctx, _case(seed, interior), seed)
+
+
+@pytest.mark.parametrize("interior", MID)
+def test_rooftop_product_ragged(vie_ctx, interior):
+    seed = 6000 + sum(s * 31 ** i for i, s in enumerate(interior))
+    _check_product(vie_ctx, _case(seed, interior, fill=0.6), seed)
+
+
+def test_rooftop_zpass_variants(vie_ctx):
+    """Every column-set z-pass variant (long columns: lz = 64 and 96) gives
+    the oracle's product; the mirror-column variant is refused."""
+    for interior in [(30, 14, 14), (40, 21, 13)]:
+        seed = 7000 + sum(interior)
+        _check_product(vie_ctx, _case(seed, interior, fill=0.6), seed, variants=(0, 2, 3, 4))
+    case = _case(1, (3, 3, 3))
+    P = V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
+    try:
+        with pytest.raises(V.VieError) as e:
+            V.vie_problem_set_zpass(P.handle, V.VIE_FP64, 1)
+        assert e.value.code == V.VIE_EINVAL
+        assert P.info().zpass_variant[0] != 1 and P.info().zpass_tune_ms[0][1] == -1
+    finally:
+        P.close()
+
+
+def test_rooftop_product_padded_metasurface_full_size(vie_ctx):
+    """The metasurface (8 x 8 pillars on a slab, 128 x 128 x 32 at lambda/40)
+    with one vacuum layer per side, 130 x 130 x 34: every face, both
+    precisions, in the launch configuration the product uses there."""
+    _check_product(vie_ctx, W.padded(W.metasurface()), 11)
+
+
+def test_rooftop_face_contrast_cases(vie_ctx):
+    """Faces whose mean of 1/eps is 1 (eps 2 next to eps 2/3) and faces
+    between vacuum cells carry no unknown; an all-vacuum grid gives 0."""
+    eps = np.ones((5, 5, 6), complex)
+    eps[2, 2, 2], eps[2, 2, 3] = 2.0, 2.0 / 3.0
+    eps[2, 1, 2] = 4.0 - 1.0j
+    case = W.Case("contrast", 6, 5, 5, 0.05, 0.05, 0.05, 1.0, eps, np.full(eps.shape, -1, np.int32), 0, 1e-8, 1e-2)
+    g = op.Grid.from_case(case)
+    fm = rt.face_mask(g)
+    assert not fm[0, 2, 2, 2]            # the m = 1 face
+    _check_product(vie_ctx, case, 3)
+    vac = W.Case("vacuum", 4, 4, 4, 0.1, 0.1, 0.1, 1.0, np.ones((4, 4, 4), complex),
+                 np.full((4, 4, 4), -1, np.int32), 0, 1e-8, 1e-2)
+    P = V.Problem(_grid(vac), vac.eps, ctx=vie_ctx, rooftop=True)
+    try:
+        assert np.all(_matvec(P, _rand(4, vac.shape), V.VIE_FP64) == 0)
+    finally:
+        P.close()
+
+
+def test_rooftop_argument_checks(vie_ctx):
+    """Non-vacuum boundary layers, blocks, preconditioning and the
+    collocated-only entry points are refused with VIE_EINVAL."""
+    case = W.random_tiny(9, (4, 4, 4), fill=1.0)
+    with pytest.raises(V.VieError) as e:
+        V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
+    assert e.value.code == V.VIE_EINVAL and "vacuum" in str(e.value)
+    case = _case(9, (4, 4, 4))
+    P = V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
+    try:
+        n = 3 * case.nvox
+        x = torch.zeros(n, dtype=torch.complex128, device="cuda")
+        y = torch.zeros_like(x)
+        st = V.vie_stats()
+        with pytest.raises(V.VieError) as e:
+            V.vie_solve_device(P.handle, x, V.make_opts(precondition=True), y, None, st)
+        assert e.value.code == V.VIE_EINVAL
+        with pytest.raises(V.VieError) as e:
+            V.vie_total_field_box(P.handle, V.VIE_FP64, x, x, y)
+        assert e.value.code == V.VIE_EINVAL
+        with pytest.raises(V.VieError) as e:
+            V.vie_far_field(P.handle, x, np.array([[0.0, 0.0, 1.0]]))
+        assert e.value.code == V.VIE_EINVAL
+        with pytest.raises(V.VieError) as e:
+            V.vie_solve_batch(P.handle, 1, x, V.make_opts(precondition=False), y)
+        assert e.value.code == V.VIE_EINVAL
+        with pytest.raises(V.VieError) as e:
+            V.vie_solve_many([P.handle], [x], V.make_opts(precondition=False), [y])
+        assert e.value.code == V.VIE_EINVAL
+    finally:
+        P.close()
+
+
+def _sphere():
+    return W.sphere(6, 30.0, 2.25, pad=1)      # 14^3 grid, k a = 2 pi / 5
+
+
+@pytest.mark.parametrize("prec,tol,bar", [(V.VIE_FP64, 1e-10, 1e-8), (V.VIE_MIXED, 1e-9, 1e-7)])
+def test_rooftop_sphere_solve_matches_oracle(vie_ctx, prec, tol, bar):
+    """Plain BiCGSTAB solve of the voxelised sphere (eps 2.25, radius 6 cells)
+    under x-polarised incidence along z: the GPU's face-centred plane wave
+    equals the oracle's, and the solution P and the face field P / chi_f
+    agree with the oracle's solve to `bar` (relative, max norm)."""
+    case = _sphere()
+    g = op.Grid.from_case(case)
+    e_or = rt.plane_wave(g)
+    e_gpu = V.vie_plane_wave_faces(_grid(case), (0.0, 0.0, 1.0), (1.0, 0.0, 0.0))
+    assert np.abs(e_gpu - e_or).max() <= 1e-13
+    P_or, info = rt.solve(g, e_or, 1e-12, 5000)
+    assert info.status == "converged"
+    P = V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
+    try:
+        ed = torch.from_numpy(e_gpu).cuda()
+        et = torch.zeros_like(ed)
+        pol = torch.zeros_like(ed)
+        st = V.vie_stats()
+        opts = V.make_opts(tol_outer=tol, maxit_outer=2000, precondition=False, precision=prec)
+        code = V.vie_solve_device(P.handle, ed, opts, et, pol, st)
+        torch.cuda.synchronize()
+        print(f"rooftop sphere solve prec {prec}: {st.outer_iters} steps, relres {st.relres_true:.2e}", flush=True)
+        assert code == V.VIE_OK and st.relres_true <= 2 * tol
+        Pg = pol.cpu().numpy()
+        fm = rt.face_mask(g)
+        assert np.all(Pg[~fm] == 0)
+        err = np.abs(Pg - P_or).max() / np.abs(P_or).max()
+        assert err <= bar, err
+        E_or = P_or * rt.face_chi_inv(g)
+        Eg = et.cpu().numpy()
+        assert np.abs(Eg - E_or).max() / np.abs(E_or).max() <= bar
+    finally:
+        P.close()

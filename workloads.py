@@ -39,7 +39,7 @@ import numpy as np
 
 __all__ = [
     "Case", "cube16", "metasurface", "plasmonic", "sweep_case", "sweep",
-    "sphere", "random_tiny", "mixed_partition", "plasmonic_small", "SERVING_GRIDS", "SERVING_RATES", "arrivals", "serving_request",
+    "sphere", "padded", "random_tiny", "mixed_partition", "plasmonic_small", "SERVING_GRIDS", "SERVING_RATES", "arrivals", "serving_request",
     "request_precondition", "CASES", "by_name",
 ]
 
@@ -265,6 +265,20 @@ def sphere(radius_vox: int, wavelength_vox: float, eps_r: complex,
     return Case(f"sphere_r{radius_vox}", n, n, n, 1.0, 1.0, 1.0, float(wavelength_vox),
                 eps, bid, 1, tol_outer=1e-10, tol_inner=1e-2, precision="fp64",
                 note=f"voxelised sphere radius {radius_vox} voxels, lambda {wavelength_vox} voxels, eps {eps_r}")
+
+
+def padded(case: Case, layers: int = 1) -> Case:
+    """``case`` with ``layers`` vacuum cells added on both sides of every axis
+    (the grid grows by ``2 layers`` per axis; same spacing and wavelength; no
+    blocks): the input of the rooftop discretisation, whose first and last
+    cell layers must be vacuum."""
+    L = int(layers)
+    eps = np.pad(case.eps, L, constant_values=1.0 + 0.0j).astype(np.complex128)
+    bid = np.full(eps.shape, -1, dtype=np.int32)
+    nz, ny, nx = eps.shape
+    return Case(f"{case.name}_pad{L}", nx, ny, nz, case.dx, case.dy, case.dz, case.wavelength, eps, bid, 0,
+                tol_outer=case.tol_outer, tol_inner=case.tol_inner, precision=case.precision,
+                note=f"{case.note}; {L} vacuum layer(s) on every side")
 
 
 def random_tiny(seed: int, shape: Tuple[int, int, int], fill: float = 0.7,
