@@ -262,6 +262,44 @@ def zpass_roofline(V, handle, grid_groups, block_group, hist, prec, lag, reps):
     return out
 
 
+def rooftop_measure(V, W, ctx, reps):
+    """The rooftop discretisation (face unknowns, one scalar spectrum) on the
+    metasurface padded by a vacuum layer per side: its product per pass
+    beside the collocated product of the same grid, both precisions, and a
+    plain mixed-precision solve (outer tol 2e-6)."""
+    import torch
+    rc = W.padded(W.metasurface())
+    rg = V.make_grid(rc.nx, rc.ny, rc.nz, rc.dx, rc.dy, rc.dz, rc.wavelength)
+    roof = {"workload": f"{rc.name} {rc.nx}x{rc.ny}x{rc.nz}, no blocks"}
+    st = V.vie_stats()
+    for kind, flag in (("rooftop", True), ("collocated", False)):
+        Q = V.Problem(rg, rc.eps, ctx=ctx, rooftop=flag)
+        qi = Q.info()
+        roof[kind] = {p: mvm_profile(V, Q.handle, qi, rc.nx, rc.ny, rc.nz, pv, reps, rooftop=flag)
+                      for p, pv in (("mixed", V.VIE_MIXED), ("fp64", V.VIE_FP64))}
+        roof[kind]["fft"] = [qi.lx, qi.ly, qi.lz]
+        if flag:
+            er = torch.from_numpy(V.vie_plane_wave_faces(rg, rc.kdir, rc.pol).reshape(-1)).cuda()
+            et = torch.empty_like(er)
+            ro = V.make_opts(tol_outer=2e-6, maxit_outer=3000, precondition=False, precision=V.VIE_MIXED,
+                             max_refine=3)
+            V.vie_solve_device(Q.handle, er, ro, et, None, st)   # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            cr = V.vie_solve_device(Q.handle, er, ro, et, None, st)
+            torch.cuda.synchronize()
+            tr = time.perf_counter() - t1
+            roof["plain_solve_mixed"] = {"solves_per_s": 1.0 / tr, "status": V.STATUS_NAMES.get(cr, cr),
+                                         "outer_steps": st.outer_iters, "refine_steps": st.refine_steps,
+                                         "refine_iters": st.refine_iters, "relres_true": st.relres_true,
+                                         "ms_per_outer_step": 1e3 * tr / max(1, st.outer_iters + st.refine_iters)}
+        Q.close()
+    for kind in ("rooftop", "collocated"):
+        for p in ("mixed", "fp64"):
+            roof[kind][p]["frac_of_hbm_peak"] = roof[kind][p]["algorithmic_GBps"] / HBM_PEAK_GBS
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +352,8 @@ def main():
                     help="also copy 512 MiB device to device three times (reference kernel for HBM counters)")
     ap.add_argument("--no-rooftop", action="store_true",
                     help="skip the rooftop-discretisation product and solve on the padded metasurface")
+    ap.add_argument("--rooftop-only", action="store_true",
+                    help="only the rooftop measurement (one JSON line with it), e.g. under a profiler")
     ap.add_argument("--mvm-shapes", default="256x256x64",
                     help="extra grids (comma-separated NXxNYxNZ, '' for none) whose full-grid product is timed per pass")
     args = ap.parse_args()
@@ -326,6 +366,12 @@ def main():
     import torch
     import workloads as W
     from paper_2501_13512_amd import vie as V
+
+    if args.rooftop_only:
+        ctx = V.vie_context_create(0)
+        print(json.dumps({"rooftop": rooftop_measure(V, W, ctx, args.profile_reps)}), flush=True)
+        V.vie_context_destroy(ctx)
+        return
 
     case = W.by_name(args.case)
     prec = V.VIE_MIXED if args.precision == "mixed" else V.VIE_FP64
@@ -577,36 +623,9 @@ def main():
             p["frac_of_hbm_peak"] = p["algorithmic_GBps"] / HBM_PEAK_GBS
         Q.close()
 
-    # the rooftop discretisation (face unknowns, one scalar spectrum) on the
-    # metasurface padded by a vacuum layer per side: its product beside the
-    # collocated product of the same grid, and a plain mixed-precision solve
     roof = None
     if not args.no_rooftop and args.maxit_outer is None:
-        rc = W.padded(W.metasurface())
-        rg = V.make_grid(rc.nx, rc.ny, rc.nz, rc.dx, rc.dy, rc.dz, rc.wavelength)
-        roof = {"workload": f"{rc.name} {rc.nx}x{rc.ny}x{rc.nz}, no blocks"}
-        for kind, flag in (("rooftop", True), ("collocated", False)):
-            Q = V.Problem(rg, rc.eps, ctx=ctx, rooftop=flag)
-            qi = Q.info()
-            roof[kind] = {p: mvm_profile(V, Q.handle, qi, rc.nx, rc.ny, rc.nz, pv, args.profile_reps, rooftop=flag)
-                          for p, pv in (("mixed", V.VIE_MIXED), ("fp64", V.VIE_FP64))}
-            roof[kind]["fft"] = [qi.lx, qi.ly, qi.lz]
-            if flag:
-                er = torch.from_numpy(V.vie_plane_wave_faces(rg, rc.kdir, rc.pol).reshape(-1)).cuda()
-                et = torch.empty_like(er)
-                ro = V.make_opts(tol_outer=2e-6, maxit_outer=3000, precondition=False, precision=V.VIE_MIXED,
-                                 max_refine=3)
-                V.vie_solve_device(Q.handle, er, ro, et, None, st)   # warm-up
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                cr = V.vie_solve_device(Q.handle, er, ro, et, None, st)
-                torch.cuda.synchronize()
-                tr = time.perf_counter() - t1
-                roof["plain_solve_mixed"] = {"solves_per_s": 1.0 / tr, "status": V.STATUS_NAMES.get(cr, cr),
-                                             "outer_steps": st.outer_iters, "refine_steps": st.refine_steps,
-                                             "refine_iters": st.refine_iters, "relres_true": st.relres_true,
-                                             "ms_per_outer_step": 1e3 * tr / max(1, st.outer_iters + st.refine_iters)}
-            Q.close()
+        roof = rooftop_measure(V, W, ctx, args.profile_reps)
         log("rooftop product and solve done")
 
     # the inner tolerance of the block solves (the workload's 1e-2 is the
