@@ -243,9 +243,10 @@ vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, co
  * axis must be vacuum (VIE_EINVAL otherwise).  eps_r as for
  * vie_problem_create; no blocks.  vie_matvec, vie_matvec_profile,
  * vie_solve and vie_solve_device (precondition 0; e_tot_out is then the
- * field on every face, P_f / chi_f) accept it; the field post-processing
- * (vie_total_field_box, vie_far_field*, vie_rcs), vie_solve_batch,
- * vie_solve_many and z-pass variant 1 return VIE_EINVAL. */
+ * field on every face, P_f / chi_f), vie_far_field, vie_far_field_noalloc
+ * and vie_rcs (each face unknown radiating from its face centre) accept it;
+ * vie_total_field_box, vie_solve_batch, vie_solve_many and z-pass variant 1
+ * return VIE_EINVAL. */
 vie_status vie_problem_create_rooftop(vie_context* ctx, const vie_grid* grid, const double* eps_r,
                                       vie_problem** out);
 vie_status vie_problem_destroy(vie_problem* p);
@@ -362,7 +363,9 @@ vie_status vie_total_field_box(vie_problem* p, int32_t precision, const void* po
                                void* e_box_dev, void* stream);
 
 /* Far field of the voxel currents, F(rhat) = (I - rhat rhat) sum_n P_n dV
- * exp(+j k0 rhat . r_n) (r_n: voxel centre relative to the grid centre), for
+ * exp(+j k0 rhat . r_n) (r_n: voxel centre relative to the grid centre; for
+ * rooftop problems component c of entry n is at its face centre, r_n plus
+ * d_c / 2 along axis c), for
  * n_dir unit directions rhat (host, 3 doubles each; |rhat| = 1 within 1e-12
  * else VIE_EINVAL).  f_out: host, 3*n_dir complex.  FP64; synchronises the
  * stream. */

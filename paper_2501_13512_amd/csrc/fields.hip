@@ -1,7 +1,10 @@
 // Far field of the voxel polarisation (the radiated field of Sec. II's
 // current distribution, as used for the RCS comparisons of Sec. III):
 //   F(rhat) = (I - rhat rhat) sum_n P_n dV exp(+j k0 rhat . r_n),
-// r_n the voxel centre relative to the grid centre.  Each workgroup sums a
+// r_n the voxel centre relative to the grid centre; for the face unknowns of
+// the rooftop discretisation (`faces`) component c of entry n sits half a
+// cell further along axis c, which multiplies its phase factor by the
+// direction's constant exp(+j k0 rhat_c d_c / 2).  Each workgroup sums a
 // chunk of voxels for one direction (FP64 phases and sums); a second kernel
 // adds the chunks of each direction in a fixed order (deterministic).
 #include <stdexcept>
@@ -24,9 +27,15 @@ static __device__ __align__(256) double scratch[kFarScratchDoubles];
 
 __global__ void __launch_bounds__(FF_T) k_far_partial(const c128* P, int nx, int ny, int nz, double dx, double dy,
                                                       double dz, double k0, const double* rhat, int nchunk,
-                                                      double* part) {
+                                                      double* part, int faces) {
   const int dir = blockIdx.x / nchunk, chunk = blockIdx.x - dir * nchunk;
   const double rx = rhat[3 * dir], ry = rhat[3 * dir + 1], rz = rhat[3 * dir + 2];
+  double hs[3] = {0.0, 0.0, 0.0}, hc[3] = {1.0, 1.0, 1.0};   // half-cell phase of each component
+  if (faces) {
+    sincos(0.5 * k0 * rx * dx, &hs[0], &hc[0]);
+    sincos(0.5 * k0 * ry * dy, &hs[1], &hc[1]);
+    sincos(0.5 * k0 * rz * dz, &hs[2], &hc[2]);
+  }
   const int64_t nv = (int64_t)nx * ny * nz;
   const double cx0 = 0.5 * (nx - 1), cy0 = 0.5 * (ny - 1), cz0 = 0.5 * (nz - 1);
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -42,8 +51,9 @@ __global__ void __launch_bounds__(FF_T) k_far_partial(const c128* P, int nx, int
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const c128 p = P[q * nv + v];
-      acc[2 * q] += p.x * c - p.y * s;
-      acc[2 * q + 1] += p.x * s + p.y * c;
+      const double cq = c * hc[q] - s * hs[q], sq = s * hc[q] + c * hs[q];
+      acc[2 * q] += p.x * cq - p.y * sq;
+      acc[2 * q + 1] += p.x * sq + p.y * cq;
     }
   }
   block_sum<6>(acc);
@@ -90,11 +100,11 @@ void* far_field_scratch_address() {
 }
 
 void far_field(const c128* P, int nx, int ny, int nz, double dx, double dy, double dz, double k0, const double* rhat,
-               int ndir, double* part, c128* F, hipStream_t s) {
+               int ndir, double* part, c128* F, hipStream_t s, bool faces) {
   if (ndir <= 0) return;
   const int64_t nchunk = far_field_chunks((int64_t)nx * ny * nz);
   hipLaunchKernelGGL(k_far_partial, dim3((unsigned)(ndir * nchunk)), dim3(FF_T), 0, s, P, nx, ny, nz, dx, dy, dz,
-                     k0, rhat, (int)nchunk, part);
+                     k0, rhat, (int)nchunk, part, faces ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw std::runtime_error(std::string("far field launch: ") + hipGetErrorString(e));
   hipLaunchKernelGGL(k_far_final, dim3(ndir), dim3(FF_T), 0, s, part, (int)nchunk, rhat, dx * dy * dz, F);

@@ -196,6 +196,8 @@ void block_solve(const BlockSolveArgs& a, int lx, int lz, hipStream_t s);
 // Far field F(rhat) = (I - rhat rhat) sum_n P_n dV exp(+j k0 rhat . r_n)
 // for ndir directions (rhat: device, 3 doubles each; F: device, 3 c128 each).
 // part: device scratch of 6 far_field_chunks(nx ny nz) doubles per direction.
+// faces: P holds rooftop face unknowns (component c at its face centre, half
+// a cell along axis c from the voxel centre).
 int64_t far_field_chunks(int64_t nv);
 // The far field's fixed scratch array (for the entry point that allocates
 // nothing): its capacity in doubles, and its address on the current device
@@ -203,7 +205,7 @@ int64_t far_field_chunks(int64_t nv);
 int64_t far_field_scratch_doubles();
 void* far_field_scratch_address();
 void far_field(const c128* P, int nx, int ny, int nz, double dx, double dy, double dz, double k0, const double* rhat,
-               int ndir, double* part, c128* F, hipStream_t s);
+               int ndir, double* part, c128* F, hipStream_t s, bool faces = false);
 
 // Flexible GMRES(m) of one system (the outer solve).  V: m+1 basis vectors,
 // Z: m preconditioned vectors (or null without preconditioner), each n c128;

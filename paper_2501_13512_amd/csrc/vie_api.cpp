@@ -2569,7 +2569,6 @@ extern "C++" {
 static void far_field_host(vie_problem* p, const void* pol_dev, int32_t n_dir, const double* rhat,
                            std::vector<c128>& F, hipStream_t s) {
   if (!p || !pol_dev || !rhat) fail(VIE_EINVAL, "problem, pol and rhat are required");
-  collocated_only(p, "far field");
   if (n_dir < 1 || n_dir > 1000000) fail(VIE_EINVAL, "n_dir out of range");
   for (int32_t d = 0; d < n_dir; ++d) {
     const double* r = rhat + 3 * d;
@@ -2584,7 +2583,7 @@ static void far_field_host(vie_problem* p, const void* pol_dev, int32_t n_dir, c
       dF(3 * (size_t)n_dir * sizeof(c128));
   hip_check(hipMemcpyAsync(dr.p, rhat, dr.bytes, hipMemcpyHostToDevice, s), "upload rhat");
   vie::far_field((const c128*)pol_dev, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, p->k0, dr.as<double>(), n_dir,
-                 part.as<double>(), dF.as<c128>(), s);
+                 part.as<double>(), dF.as<c128>(), s, p->rooftop);
   F.resize(3 * (size_t)n_dir);
   hip_check(hipMemcpyAsync(F.data(), dF.p, dF.bytes, hipMemcpyDeviceToHost, s), "download F");
   hip_check(hipStreamSynchronize(s), "far field");
@@ -2607,7 +2606,6 @@ vie_status vie_far_field_noalloc(vie_problem* p, const void* pol_dev, int32_t n_
                                  void* f_dev, void* stream) {
   return guarded([&]() -> vie_status {
     if (!p || !pol_dev || !rhat_dev || !f_dev) fail(VIE_EINVAL, "problem, pol, rhat and f are required");
-    collocated_only(p, "vie_far_field_noalloc");
     if (n_dir < 1) fail(VIE_EINVAL, "n_dir must be >= 1");
     const int64_t nchunk = vie::far_field_chunks(p->nv);
     if ((int64_t)n_dir * nchunk * 6 > vie::far_field_scratch_doubles())
@@ -2618,7 +2616,7 @@ vie_status vie_far_field_noalloc(vie_problem* p, const void* pol_dev, int32_t n_
     set_device(p->ctx);
     const vie_grid& g = p->g;
     vie::far_field((const c128*)pol_dev, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, p->k0, (const double*)rhat_dev, n_dir,
-                   p->ctx->far_scratch, (c128*)f_dev, (hipStream_t)stream);
+                   p->ctx->far_scratch, (c128*)f_dev, (hipStream_t)stream, p->rooftop);
     return VIE_OK;
   });
 }
