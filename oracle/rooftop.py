@@ -195,6 +195,68 @@ def dense_matrix(grid: Grid):
     return A, idx
 
 
+def face_owner(grid: Grid, block_id: np.ndarray) -> np.ndarray:
+    """Block of every face with an unknown, -1 elsewhere [3, nz, ny, nx].
+
+    Reading (eq. (10) partitions the unknowns; the paper's blocks are sets
+    of cells): the face between cell c and c + e_i belongs to the block of
+    c when c is a scatterer cell, else to the block of c + e_i.
+    """
+    fm = face_mask(grid)
+    owner = np.full(fm.shape, -1, dtype=np.int64)
+    for i, axis in ((0, 2), (1, 1), (2, 0)):
+        upper = np.roll(block_id, -1, axis=axis)   # block of c + e_i (the last layer has no faces)
+        own = np.where(grid.mask, block_id, upper)
+        owner[i] = np.where(fm[i], own, -1)
+    return owner
+
+
+class BlockPreconditioner:
+    """y = K2^{-1} w with K2 = blockdiag(A_1, ..., A_N) over the face
+    unknowns (eq. (10)): A_k = R_k A R_k^T, R_k keeping the faces block k
+    owns (``face_owner``).  Each block's system is solved by BiCGSTAB from
+    x0 = 0 to ``tol`` relative to its right-hand side (at most ``maxit``
+    steps), applying A_k as the full-grid product between two maskings."""
+
+    def __init__(self, grid: Grid, block_id: np.ndarray, n_blocks: int, tol: float, maxit: int):
+        self.op = RooftopFFT(grid)
+        self.tol, self.maxit = tol, maxit
+        owner = face_owner(grid, block_id)
+        self.blocks = [(k, owner == k) for k in range(n_blocks) if np.any(owner == k)]
+        self.inner_counts = []
+
+    def block_matvec(self, x: np.ndarray) -> np.ndarray:
+        """K2 x."""
+        y = np.zeros_like(x)
+        for _, fm in self.blocks:
+            y += fm * self.op(fm * x)
+        return y
+
+    def __call__(self, w: np.ndarray) -> np.ndarray:
+        y = np.zeros_like(w)
+        counts = []
+        for _, fm in self.blocks:
+            bk = w * fm
+            if not np.any(bk):
+                counts.append(0)
+                continue
+            yk, info = krylov.bicgstab(lambda x, fm=fm: fm * self.op(fm * x), bk, self.tol, self.maxit)
+            y += yk * fm
+            counts.append(info.iterations)
+        self.inner_counts.append(counts)
+        return y
+
+
+def solve_preconditioned(grid: Grid, e_inc: np.ndarray, block_id: np.ndarray, n_blocks: int, tol: float,
+                         maxit: int, tol_inner: float, maxit_inner: int):
+    """Right-preconditioned BiCGSTAB (Sec. II-B) with the rooftop block
+    preconditioner; returns (P, KrylovInfo, preconditioner)."""
+    M = BlockPreconditioner(grid, block_id, n_blocks, tol_inner, maxit_inner)
+    b = np.where(face_mask(grid), e_inc, 0.0)
+    P, info = krylov.bicgstab(M.op, b, tol, maxit, precond=M)
+    return P, info, M
+
+
 def face_positions(grid: Grid):
     """Face centres per component relative to the grid centre: 3 x (X, Y, Z)."""
     X, Y, Z = physics.voxel_positions(grid)

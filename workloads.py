@@ -269,14 +269,14 @@ def sphere(radius_vox: int, wavelength_vox: float, eps_r: complex,
 
 def padded(case: Case, layers: int = 1) -> Case:
     """``case`` with ``layers`` vacuum cells added on both sides of every axis
-    (the grid grows by ``2 layers`` per axis; same spacing and wavelength; no
-    blocks): the input of the rooftop discretisation, whose first and last
-    cell layers must be vacuum."""
+    (the grid grows by ``2 layers`` per axis; same spacing, wavelength and
+    block partition, -1 on the new cells): the input of the rooftop
+    discretisation, whose first and last cell layers must be vacuum."""
     L = int(layers)
     eps = np.pad(case.eps, L, constant_values=1.0 + 0.0j).astype(np.complex128)
-    bid = np.full(eps.shape, -1, dtype=np.int32)
+    bid = np.pad(case.block_id, L, constant_values=-1).astype(np.int32)
     nz, ny, nx = eps.shape
-    return Case(f"{case.name}_pad{L}", nx, ny, nz, case.dx, case.dy, case.dz, case.wavelength, eps, bid, 0,
+    return Case(f"{case.name}_pad{L}", nx, ny, nz, case.dx, case.dy, case.dz, case.wavelength, eps, bid, case.n_blocks,
                 tol_outer=case.tol_outer, tol_inner=case.tol_inner, precision=case.precision,
                 note=f"{case.note}; {L} vacuum layer(s) on every side")
 
