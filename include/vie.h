@@ -240,15 +240,21 @@ vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, co
  * the mean of 1/eps_r over the face's two cells (continuity of the normal
  * flux density).  Faces between two vacuum cells carry no unknown: the
  * products and solves keep them 0.  The first and last cell layer of every
- * axis must be vacuum (VIE_EINVAL otherwise).  eps_r as for
- * vie_problem_create; no blocks.  vie_matvec, vie_matvec_profile,
- * vie_solve and vie_solve_device (precondition 0; e_tot_out is then the
- * field on every face, P_f / chi_f), vie_far_field, vie_far_field_noalloc
- * and vie_rcs (each face unknown radiating from its face centre) accept it;
- * vie_total_field_box, vie_solve_batch, vie_solve_many and z-pass variant 1
- * return VIE_EINVAL. */
+ * axis must be vacuum (VIE_EINVAL otherwise).  eps_r, block_id and n_blocks
+ * as for vie_problem_create (block_id may be NULL).  Blocks (eq. (10)) are
+ * sets of cells; the face between cell c and c + e_i belongs to the block of
+ * c when c is a scatterer cell, else to the block of c + e_i, and block k's
+ * matrix is A restricted to the faces it owns (solved on its cells'
+ * bounding box grown by one cell per side).  vie_matvec,
+ * vie_matvec_profile, vie_block_matvec, vie_precond_apply, vie_group_profile,
+ * vie_solve and vie_solve_device (e_tot_out is then the field on every face,
+ * P_f / chi_f), vie_far_field, vie_far_field_noalloc and vie_rcs (each face
+ * unknown radiating from its face centre) accept it; vie_total_field_box,
+ * vie_solve_batch, vie_solve_many and z-pass variant 1 return VIE_EINVAL.
+ * Every block group runs on the batched multi-workgroup kernels
+ * (VIE_FLAG_NO_BLOCK_KERNEL has no effect). */
 vie_status vie_problem_create_rooftop(vie_context* ctx, const vie_grid* grid, const double* eps_r,
-                                      vie_problem** out);
+                                      const int32_t* block_id, int32_t n_blocks, vie_problem** out);
 vie_status vie_problem_destroy(vie_problem* p);
 vie_status vie_problem_get_info(const vie_problem* p, vie_problem_info* info);
 

@@ -227,13 +227,13 @@ class BlockPreconditioner:
 
     def block_matvec(self, x: np.ndarray) -> np.ndarray:
         """K2 x."""
-        y = np.zeros_like(x)
+        y = np.zeros(x.shape, dtype=np.complex128)
         for _, fm in self.blocks:
             y += fm * self.op(fm * x)
         return y
 
     def __call__(self, w: np.ndarray) -> np.ndarray:
-        y = np.zeros_like(w)
+        y = np.zeros(w.shape, dtype=np.complex128)
         counts = []
         for _, fm in self.blocks:
             bk = w * fm

@@ -327,9 +327,12 @@ struct BlockMap {
   const int4* block_origin; // [nblocks] (x, y, z, unused)
   const int4* gbox;         // [ngroups] (bx, by, bz, unused)
   int nx, ny, nz;
+  int faces;                // 1: rooftop face unknowns, block_id per face [3][nz][ny][nx]
 };
 // gvec_k[c][local] = w[c][v] for every scatterer voxel v (members only; the
-// other entries of the group vectors are left untouched, i.e. zero)
+// other entries of the group vectors are left untouched, i.e. zero); with
+// m.faces, per face: component c of entry v goes to the block owning that
+// face
 void block_gather(const BlockMap& m, const c128* w, c128* const* gdst, hipStream_t s);
 // y[c][v] = gsrc_k[c][local(v)] for scatterer voxels, 0 for vacuum
 void block_scatter(const BlockMap& m, c128* const* gsrc, c128* y, hipStream_t s);

@@ -786,9 +786,21 @@ __global__ void kk_gather(BlockMap m, const c128* w, c128* const* gdst) {
   const int64_t nv = (int64_t)m.nx * m.ny * m.nz;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
+  const int x = (int)(v % m.nx), y = (int)((v / m.nx) % m.ny), z = (int)(v / ((int64_t)m.nx * m.ny));
+  if (m.faces) {   // each component to the block owning its face
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = m.block_id[c * nv + v];
+      if (k < 0) continue;
+      int g, sysi;
+      int64_t bnv;
+      const int64_t loc = block_local(m, k, x, y, z, &g, &sysi, &bnv);
+      gdst[g][(int64_t)sysi * 3 * bnv + c * bnv + loc] = w[c * nv + v];
+    }
+    return;
+  }
   const int k = m.block_id[v];
   if (k < 0) return;
-  const int x = (int)(v % m.nx), y = (int)((v / m.nx) % m.ny), z = (int)(v / ((int64_t)m.nx * m.ny));
   int g, sysi;
   int64_t bnv;
   const int64_t loc = block_local(m, k, x, y, z, &g, &sysi, &bnv);
@@ -807,6 +819,22 @@ __global__ void kk_scatter(BlockMap m, c128* const* gsrc, c128* y) {
   const int64_t nv = (int64_t)m.nx * m.ny * m.nz;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
+  if (m.faces) {
+    const int x = (int)(v % m.nx), yy = (int)((v / m.nx) % m.ny), z = (int)(v / ((int64_t)m.nx * m.ny));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = m.block_id[c * nv + v];
+      c128 val = mk<double>(0.0, 0.0);
+      if (k >= 0) {
+        int g, sysi;
+        int64_t bnv;
+        const int64_t loc = block_local(m, k, x, yy, z, &g, &sysi, &bnv);
+        val = gsrc[g][(int64_t)sysi * 3 * bnv + c * bnv + loc];
+      }
+      y[c * nv + v] = val;
+    }
+    return;
+  }
   const int k = m.block_id[v];
   if (k < 0) {
 #pragma unroll

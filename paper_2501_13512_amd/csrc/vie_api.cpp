@@ -317,7 +317,8 @@ struct ProblemPlan {
   int lx = 0, ly = 0, lz = 0;
   double k0 = 0;
   std::vector<c128> chi;      // 1/chi, 0 on vacuum (rooftop: per face, [3][nz][ny][nx])
-  bool rooftop = false;       // staggered rooftop unknowns on cell faces (no blocks)
+  bool rooftop = false;       // staggered rooftop unknowns on cell faces
+  std::vector<int32_t> bid3;  // rooftop with blocks: block owning each face [3][nz][ny][nx], -1 none
   bool has_blocks = false;
   int n_blocks = 0;
   std::vector<int32_t> bid;   // -1 on vacuum
@@ -524,7 +525,8 @@ MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
   b.lz = G.lz;
   b.nsys = G.nsys;
   b.vstride = G.n;
-  b.cstride = G.bnv;
+  b.cstride = P.rooftop ? 3 * G.bnv : G.bnv;
+  b.rooftop = P.rooftop ? 1 : 0;
   b.wstride = 3 * (int64_t)G.bz * G.ly * G.lx;
   b.sstride = 0;
   b.chi_inv = G.chi.as<c128>();
@@ -1550,8 +1552,11 @@ void expand_blocks(ProblemPlan& pl, int m) {
   }
 }
 
+// rooftop: every block's box grows by one cell per side (the cells whose
+// faces and charges the block's face unknowns touch), and no group uses the
+// one-workgroup block solver (its kernels are collocated only).
 ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* block_id, int32_t n_blocks,
-                      int overlap = 0) {
+                      int overlap = 0, bool rooftop = false) {
   if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > 256 || g.ny > 256 || g.nz > 256)
     fail(VIE_EINVAL, "grid sizes must be in [1, 256]");
   if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !(g.wavelength > 0) || !is_finite(g.dx) || !is_finite(g.dy) ||
@@ -1611,6 +1616,15 @@ ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* blo
         }
       }
   if (overlap > 0) expand_blocks(pl, overlap);
+  if (rooftop) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < n_blocks; ++k)
+      if (cnt[k] > 0)
+        for (int a = 0; a < 3; ++a) {
+          lo[3 * k + a] = std::max(0, lo[3 * k + a] - 1);
+          hi[3 * k + a] = std::min(n[a] - 1, hi[3 * k + a] + 1);
+        }
+  }
   // group blocks by circulant lengths of their bounding boxes
   std::vector<GroupPlan> plans;
   {
@@ -1640,7 +1654,7 @@ ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* blo
     for (auto& gp : plans) {
       int bz = 1;
       for (int k : gp.blocks) bz = std::max(bz, hi[3 * k + 2] - lo[3 * k + 2] + 1);
-      gp.wg = vie::block_solver_supported(gp.lx, gp.ly, gp.lz, bz);
+      gp.wg = !rooftop && vie::block_solver_supported(gp.lx, gp.ly, gp.lz, bz);
       (gp.wg ? wg_plans : rest).push_back(std::move(gp));
     }
     plans = std::move(rest);
@@ -1702,8 +1716,9 @@ ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* blo
 // (1/chi_f = 0).  The first and last cell layers of every axis must be
 // vacuum: every face with an unknown then lies inside the grid, and the
 // cell divergence and the face gradient need no boundary terms.
-ProblemPlan make_plan_rooftop(const vie_grid& g, const double* eps_r) {
-  ProblemPlan pl = make_plan(g, eps_r, nullptr, 0);   // sizes, finiteness, FFT lengths
+ProblemPlan make_plan_rooftop(const vie_grid& g, const double* eps_r, const int32_t* block_id, int32_t n_blocks) {
+  // sizes, finiteness, FFT lengths, block ids and boxes
+  ProblemPlan pl = make_plan(g, eps_r, block_id, n_blocks, 0, true);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int64_t nv = pl.nv;
   auto vac = [&](int64_t i) { return eps_r[2 * i] == 1.0 && eps_r[2 * i + 1] == 0.0; };
@@ -1734,6 +1749,18 @@ ProblemPlan make_plan_rooftop(const vie_grid& g, const double* eps_r) {
         }
   pl.chi = std::move(chi);
   pl.rooftop = true;
+  if (pl.has_blocks) {
+    // a face belongs to the block of its lower cell when that cell is a
+    // scatterer cell, else to the block of its upper cell (eq. (10)
+    // partitions the unknowns; the blocks are sets of cells)
+    pl.bid3.assign(3 * (size_t)nv, -1);
+    for (int c = 0; c < 3; ++c)
+      for (int64_t i = 0; i < nv; ++i) {
+        const c128 f = pl.chi[(size_t)c * nv + i];
+        if (f.x == 0.0 && f.y == 0.0) continue;
+        pl.bid3[(size_t)c * nv + i] = pl.bid[i] >= 0 ? pl.bid[i] : pl.bid[i + step[c]];
+      }
+  }
   return pl;
 }
 
@@ -1769,7 +1796,7 @@ size_t plan_footprint(vie_context* ctx, const ProblemPlan& pl, bool all_spectra 
   int64_t ipstride = 0, slots = 0;
   for (const auto& gp : pl.groups) {
     const size_t nsys = gp.blocks.size(), bnv = (size_t)gp.bx * gp.by * gp.bz;
-    foot += nsys * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
+    foot += nsys * (pl.rooftop ? 3 : 1) * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
             8 * nsys * 3 * bnv * sizeof(c128);
     spec(gp.lx, gp.ly, gp.lz);
     ipstride = std::max<int64_t>(ipstride, 4 * std::max(vie::krylov_chunks(3 * (int64_t)bnv),
@@ -1908,7 +1935,8 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
       G.bnv = (int64_t)G.bx * G.by * G.bz;
       G.n = 3 * G.bnv;
       const int gi = (int)P->groups.size();
-      std::vector<c128> gchi((size_t)G.nsys * G.bnv, mk<double>(0.0, 0.0));
+      const int ncc = pl.rooftop ? 3 : 1;   // 1/chi entries per box voxel
+      std::vector<c128> gchi((size_t)G.nsys * ncc * G.bnv, mk<double>(0.0, 0.0));
       std::vector<int4> sorg(G.nsys);
       for (int q = 0; q < G.nsys; ++q) {
         const int k = G.blocks[q];
@@ -1928,14 +1956,21 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
               if (pl.overlap > 0)
                 in = X <= pl.hi[3 * k] && Y <= pl.hi[3 * k + 1] && Z <= pl.hi[3 * k + 2] &&
                      pl.emask[k][((size_t)z * ey + y) * ex + x] != 0;
-              if (in) gchi[(size_t)q * G.bnv + ((int64_t)z * G.by + y) * G.bx + x] = pl.chi[v];
+              const int64_t loc = ((int64_t)z * G.by + y) * G.bx + x;
+              if (pl.rooftop) {   // the faces block k owns
+                for (int c = 0; c < 3; ++c)
+                  if (pl.bid3[(size_t)c * nv + v] == k)
+                    gchi[((size_t)q * 3 + c) * G.bnv + loc] = pl.chi[(size_t)c * nv + v];
+              } else if (in) {
+                gchi[(size_t)q * G.bnv + loc] = pl.chi[v];
+              }
             }
       }
       gbox.push_back(int4{G.bx, G.by, G.bz, 0});
       upload(G.chi, gchi, s);
       if (pl.overlap > 0) upload(G.sys_origin, sorg, s);
       if (pl.blk_phys.empty()) {
-        G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0, s);
+        G.spec = get_spectra(ctx, G.lx, G.ly, G.lz, g.dx, g.dy, g.dz, P->k0, s, pl.rooftop ? 1 : 0);
       } else {
         bool same = true;
         for (int q = 0; q < G.nsys; ++q) {
@@ -1977,7 +2012,7 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     for (int k = 0; k < n_blocks; ++k)
       if (pl.cnt[k] > 0) slots.push_back(P->groups[block_group[k]].slot0 + block_sys[k]);
     P->n_nonempty = (int)slots.size();
-    upload(P->d_block_id, bid, s);
+    upload(P->d_block_id, pl.rooftop ? pl.bid3 : bid, s);
     upload(P->d_block_group, block_group, s);
     upload(P->d_block_sys, block_sys, s);
     upload(P->d_block_origin, origin, s);
@@ -2029,6 +2064,7 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
     m.nx = g.nx;
     m.ny = g.ny;
     m.nz = g.nz;
+    m.faces = pl.rooftop ? 1 : 0;
   }
   if (!inner_only) {
     P->zvar[0] = cached_zvariant<double>(ctx, outer_batch<double>(*P, false), s, P->ztune_ms[0]);
@@ -2268,7 +2304,7 @@ static vie_status problem_create(vie_context* ctx, const vie_grid* grid, const d
     *out = nullptr;
     if (!ctx || !grid || !eps_r) fail(VIE_EINVAL, "ctx, grid and eps_r are required");
     if (overlap < -1 || overlap > 256) fail(VIE_EINVAL, "overlap must be in [0, 256]");
-    ProblemPlan plan = overlap < 0 ? make_plan_rooftop(*grid, eps_r)
+    ProblemPlan plan = overlap < 0 ? make_plan_rooftop(*grid, eps_r, block_id, n_blocks)
                                    : make_plan(*grid, eps_r, block_id, n_blocks, block_id ? overlap : 0);
     set_device(ctx);
     const size_t foot = plan_footprint(ctx, plan);
@@ -2307,8 +2343,8 @@ vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, co
 }
 
 vie_status vie_problem_create_rooftop(vie_context* ctx, const vie_grid* grid, const double* eps_r,
-                                      vie_problem** out) {
-  return problem_create(ctx, grid, eps_r, nullptr, 0, -1, out);
+                                      const int32_t* block_id, int32_t n_blocks, vie_problem** out) {
+  return problem_create(ctx, grid, eps_r, block_id, n_blocks, -1, out);
 }
 
 vie_status vie_problem_destroy(vie_problem* p) {

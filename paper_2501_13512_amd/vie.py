@@ -117,7 +117,7 @@ for _name, _args in {
     "vie_problem_create": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
     "vie_problem_create_overlap": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.POINTER(_vp)],
-    "vie_problem_create_rooftop": [_vp, ctypes.POINTER(vie_grid), _vp, ctypes.POINTER(_vp)],
+    "vie_problem_create_rooftop": [_vp, ctypes.POINTER(vie_grid), _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
     "vie_problem_destroy": [_vp],
     "vie_problem_get_info": [_vp, ctypes.POINTER(vie_problem_info)],
     "vie_problem_set_zpass": [_vp, ctypes.c_int32, ctypes.c_int32],
@@ -201,11 +201,13 @@ def vie_problem_create_overlap(ctx: int, grid: vie_grid, eps_r: np.ndarray, bloc
     return out.value
 
 
-def vie_problem_create_rooftop(ctx: int, grid: vie_grid, eps_r: np.ndarray) -> int:
+def vie_problem_create_rooftop(ctx: int, grid: vie_grid, eps_r: np.ndarray, block_id: Optional[np.ndarray] = None,
+                               n_blocks: int = 0) -> int:
     eps = np.ascontiguousarray(eps_r, dtype=np.complex128)
+    bid = None if block_id is None else np.ascontiguousarray(block_id, dtype=np.int32)
     out = _vp()
-    _check(_lib.vie_problem_create_rooftop(ctx, ctypes.byref(grid), _np_ptr(eps), ctypes.byref(out)),
-           "vie_problem_create_rooftop")
+    _check(_lib.vie_problem_create_rooftop(ctx, ctypes.byref(grid), _np_ptr(eps), _np_ptr(bid), int(n_blocks),
+                                           ctypes.byref(out)), "vie_problem_create_rooftop")
     return out.value
 
 
@@ -432,9 +434,9 @@ class Problem:
         self.ctx = vie_context_create(device) if ctx is None else ctx
         self.grid = grid
         if rooftop:
-            if block_id is not None:
-                raise ValueError("rooftop problems take no blocks")
-            self.handle = vie_problem_create_rooftop(self.ctx, grid, eps)
+            if overlap:
+                raise ValueError("rooftop problems take no overlap")
+            self.handle = vie_problem_create_rooftop(self.ctx, grid, eps, block_id, n_blocks)
         elif overlap and block_id is not None:
             self.handle = vie_problem_create_overlap(self.ctx, grid, eps, block_id, n_blocks, overlap)
         else:

@@ -244,3 +244,123 @@ def test_rooftop_mie_comparison_on_gpu(vie_ctx, eps, r, tol_rcs):
     assert np.linalg.norm(sigma - rt.rcs_eplane(g, Pn, th)) / np.linalg.norm(sigma) <= 1e-10
     mie = physics.mie_rcs_eplane(eps, r, lam, th)
     assert np.linalg.norm(sigma - mie) / np.linalg.norm(mie) <= tol_rcs
+
+
+# ---------------------------------------------------------------- blocks (eq. (10))
+def _blocked_cases():
+    return [W.padded(W.random_tiny(41, (4, 5, 6), fill=0.8, n_blocks=3)),
+            W.padded(W.mixed_partition(0))]
+
+
+def _owner(case):
+    return rt.face_owner(op.Grid.from_case(case), case.block_id)
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_rooftop_block_matvec_matches_oracle(vie_ctx, which):
+    """K2 x (every block's matrix on the faces it owns) against the oracle's
+    block product, both precisions; the second case has two block box shapes
+    (two batched groups)."""
+    case = _blocked_cases()[which]
+    g = op.Grid.from_case(case)
+    M = rt.BlockPreconditioner(g, case.block_id, case.n_blocks, 1e-13, 500)
+    x = _rand(42 + which, case.shape) * rt.face_mask(g)
+    want = M.block_matvec(x)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
+    try:
+        assert P.info().n_block_solver_groups == 0
+        for prec in (V.VIE_FP64, V.VIE_MIXED):
+            xd = torch.from_numpy(x).cuda()
+            yd = torch.full_like(xd, complex("nan"))
+            V.vie_block_matvec(P.handle, prec, xd, yd)
+            _assert_close(yd.cpu().numpy(), want, rt.face_mask(g), TOL[prec])
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_rooftop_precond_apply_matches_oracle(vie_ctx, which):
+    """K2^{-1} w with tight inner solves: every block's system solved to
+    1e-12 on the GPU (FP64) against the oracle's at 1e-13 (both at the exact
+    block solutions, so the bar is set by conditioning, 1e-9)."""
+    case = _blocked_cases()[which]
+    g = op.Grid.from_case(case)
+    M = rt.BlockPreconditioner(g, case.block_id, case.n_blocks, 1e-13, 1000)
+    w = _rand(52 + which, case.shape) * rt.face_mask(g)
+    want = M(w)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
+    try:
+        wd = torch.from_numpy(w).cuda()
+        yd = torch.full_like(wd, complex("nan"))
+        V.vie_precond_apply(P.handle, V.VIE_FP64, 1e-12, 1000, wd, yd)
+        got = yd.cpu().numpy()
+    finally:
+        P.close()
+    _assert_close(got, want, rt.face_mask(g), 1e-9)
+
+
+@pytest.mark.parametrize("prec,tol,bar", [(V.VIE_FP64, 1e-10, 1e-8), (V.VIE_MIXED, 1e-9, 1e-7)])
+def test_rooftop_preconditioned_solve_matches_oracle(vie_ctx, prec, tol, bar):
+    """Block-preconditioned BiCGSTAB (inner tol 1e-3) on the two-shape
+    partition: the GPU solution equals the oracle's plain solve at 1e-12 (the
+    solution is unique; the inexact inner solves only change the path) and
+    the GPU needs fewer outer steps than the oracle's plain solve."""
+    case = W.padded(W.mixed_partition(0))
+    g = op.Grid.from_case(case)
+    e = rt.plane_wave(g)
+    P0, i0 = rt.solve(g, e, 1e-12, 3000)
+    assert i0.status == "converged"
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
+    try:
+        ed = torch.from_numpy(V.vie_plane_wave_faces(P.grid, case.kdir, case.pol)).cuda()
+        et = torch.empty_like(ed)
+        pol = torch.empty_like(ed)
+        st = V.vie_stats()
+        o = V.make_opts(tol_outer=tol, tol_inner=1e-3, maxit_outer=500, precondition=True, precision=prec)
+        assert V.vie_solve_device(P.handle, ed, o, et, pol, st) == V.VIE_OK
+        print(f"rooftop preconditioned solve prec {prec}: {st.outer_iters} steps (plain oracle {i0.iterations}), "
+              f"inner {st.inner_iters_total}", flush=True)
+        Pg = pol.cpu().numpy()
+    finally:
+        P.close()
+    assert np.abs(Pg - P0).max() <= bar * np.abs(P0).max()
+    assert st.outer_iters < i0.iterations
+
+
+def test_rooftop_padded_metasurface_blocks_full_size(vie_ctx):
+    """The padded metasurface with its 64 pillar blocks and the slab block:
+    K2 x for x on one pillar's faces and on the slab's faces equals the
+    oracle's full-grid product masked to that block; then a mixed
+    block-preconditioned solve (outer 2e-6, inner 1e-2) whose solution the
+    oracle's own product checks (||b - A P|| / ||b||, FP64)."""
+    case = W.padded(W.metasurface())
+    g = op.Grid.from_case(case)
+    owner = _owner(case)
+    A = rt.RooftopFFT(g)
+    x = _rand(61, case.shape)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
+    try:
+        for k in (0, 27, 64):
+            xk = x * (owner == k)
+            want = (owner == k) * A(xk)
+            xd = torch.from_numpy(xk).cuda()
+            yd = torch.full_like(xd, complex("nan"))
+            V.vie_block_matvec(P.handle, V.VIE_FP64, xd, yd)
+            print(f"padded metasurface block {k}: K2 x", flush=True)
+            _assert_close(yd.cpu().numpy(), want, rt.face_mask(g), 1e-12)
+        e = V.vie_plane_wave_faces(P.grid, case.kdir, case.pol)
+        ed = torch.from_numpy(e).cuda()
+        et = torch.empty_like(ed)
+        pol = torch.empty_like(ed)
+        st = V.vie_stats()
+        o = V.make_opts(tol_outer=2e-6, tol_inner=1e-2, maxit_outer=1000, precondition=True,
+                        precision=V.VIE_MIXED)
+        assert V.vie_solve_device(P.handle, ed, o, et, pol, st) == V.VIE_OK
+        print(f"padded metasurface preconditioned mixed solve: {st.outer_iters} steps, "
+              f"relres_true {st.relres_true:.2e}", flush=True)
+        Pg = pol.cpu().numpy()
+    finally:
+        P.close()
+    b = np.where(rt.face_mask(g), e, 0)
+    res = np.linalg.norm(b - A(Pg)) / np.linalg.norm(b)
+    assert res <= 3e-6, res
