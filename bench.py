@@ -265,15 +265,17 @@ def zpass_roofline(V, handle, grid_groups, block_group, hist, prec, lag, reps):
 def rooftop_measure(V, W, ctx, reps):
     """The rooftop discretisation (face unknowns, one scalar spectrum) on the
     metasurface padded by a vacuum layer per side: its product per pass
-    beside the collocated product of the same grid, both precisions, and a
-    plain mixed-precision solve (outer tol 2e-6)."""
+    beside the collocated product of the same grid, both precisions, and
+    mixed-precision solves (outer tol 2e-6): plain, and with the block
+    preconditioner over the 64 pillars and the slab (inner tol 1e-2)."""
     import torch
     rc = W.padded(W.metasurface())
     rg = V.make_grid(rc.nx, rc.ny, rc.nz, rc.dx, rc.dy, rc.dz, rc.wavelength)
-    roof = {"workload": f"{rc.name} {rc.nx}x{rc.ny}x{rc.nz}, no blocks"}
+    roof = {"workload": f"{rc.name} {rc.nx}x{rc.ny}x{rc.nz}, {rc.n_blocks} blocks (preconditioned solve)"}
     st = V.vie_stats()
     for kind, flag in (("rooftop", True), ("collocated", False)):
-        Q = V.Problem(rg, rc.eps, ctx=ctx, rooftop=flag)
+        Q = (V.Problem(rg, rc.eps, rc.block_id, rc.n_blocks, ctx=ctx, rooftop=True) if flag
+             else V.Problem(rg, rc.eps, ctx=ctx))
         qi = Q.info()
         roof[kind] = {p: mvm_profile(V, Q.handle, qi, rc.nx, rc.ny, rc.nz, pv, reps, rooftop=flag)
                       for p, pv in (("mixed", V.VIE_MIXED), ("fp64", V.VIE_FP64))}
@@ -281,18 +283,20 @@ def rooftop_measure(V, W, ctx, reps):
         if flag:
             er = torch.from_numpy(V.vie_plane_wave_faces(rg, rc.kdir, rc.pol).reshape(-1)).cuda()
             et = torch.empty_like(er)
-            ro = V.make_opts(tol_outer=2e-6, maxit_outer=3000, precondition=False, precision=V.VIE_MIXED,
-                             max_refine=3)
-            V.vie_solve_device(Q.handle, er, ro, et, None, st)   # warm-up
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            cr = V.vie_solve_device(Q.handle, er, ro, et, None, st)
-            torch.cuda.synchronize()
-            tr = time.perf_counter() - t1
-            roof["plain_solve_mixed"] = {"solves_per_s": 1.0 / tr, "status": V.STATUS_NAMES.get(cr, cr),
-                                         "outer_steps": st.outer_iters, "refine_steps": st.refine_steps,
-                                         "refine_iters": st.refine_iters, "relres_true": st.relres_true,
-                                         "ms_per_outer_step": 1e3 * tr / max(1, st.outer_iters + st.refine_iters)}
+            for label, pre in (("plain_solve_mixed", False), ("preconditioned_solve_mixed", True)):
+                ro = V.make_opts(tol_outer=2e-6, tol_inner=1e-2, maxit_outer=3000 if not pre else 1000,
+                                 precondition=pre, precision=V.VIE_MIXED, max_refine=3)
+                V.vie_solve_device(Q.handle, er, ro, et, None, st)   # warm-up
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                cr = V.vie_solve_device(Q.handle, er, ro, et, None, st)
+                torch.cuda.synchronize()
+                tr = time.perf_counter() - t1
+                roof[label] = {"solves_per_s": 1.0 / tr, "status": V.STATUS_NAMES.get(cr, cr),
+                               "outer_steps": st.outer_iters, "refine_steps": st.refine_steps,
+                               "refine_iters": st.refine_iters, "relres_true": st.relres_true,
+                               "inner_iters_total": st.inner_iters_total,
+                               "ms_per_outer_step": 1e3 * tr / max(1, st.outer_iters + st.refine_iters)}
         Q.close()
     for kind in ("rooftop", "collocated"):
         for p in ("mixed", "fp64"):

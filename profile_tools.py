@@ -175,9 +175,10 @@ def _per_kernel(rows):
 
 
 def _label(name):
-    m = re.search(r"k_zconv_col<(float|double), (\d+), (\d+)>", name)
-    if m:
-        return f"k_zconv_col<V{m.group(3)}>", m.group(1), int(m.group(2))
+    m = re.search(r"k_zconv_col<(float|double), (\d+), (\d+)(?:, (\d+))?>", name)
+    if m:   # the fourth template argument: 1 = rooftop spectral multiply
+        kind = ", rooftop" if m.group(4) == "1" else ""
+        return f"k_zconv_col<V{m.group(3)}{kind}>", m.group(1), int(m.group(2))
     m = re.search(r"k_zconv_mirror<(float|double), (\d+)>", name)
     if m:
         return "k_zconv_mirror", m.group(1), int(m.group(2))
