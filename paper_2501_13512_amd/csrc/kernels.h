@@ -298,6 +298,9 @@ void count_active(const int* status, int n, int* out, hipStream_t s);
 // one per face of the rooftop discretisation)
 void total_field(const c128* P, const c128* chi_inv, c128* e, int64_t nv, int ncomp, hipStream_t s,
                  int64_t cper = 0);
+// Rooftop face fields: component c of entries in the grid's last cell layer
+// along axis c set to 0 (those faces' second cell lies outside the grid)
+void zero_outer_faces(c128* e, int nx, int ny, int nz, hipStream_t s);
 // b = e * mask (mask: chi_inv != 0), 3 components of nv voxels; chi_inv
 // indexed as in total_field
 void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s, int64_t cper = 0);

@@ -683,6 +683,22 @@ __global__ void kk_masked_copy(const c128* e, const c128* chi, c128* b, int64_t 
   b[i] = (ci.x == 0.0 && ci.y == 0.0) ? mk<double>(0.0, 0.0) : e[i];
 }
 
+__global__ void kk_zero_outer_faces(c128* e, int nx, int ny, int nz) {
+  const int64_t nv = (int64_t)nx * ny * nz;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+  if (x == nx - 1) e[v] = mk<double>(0.0, 0.0);
+  if (y == ny - 1) e[nv + v] = mk<double>(0.0, 0.0);
+  if (z == nz - 1) e[2 * nv + v] = mk<double>(0.0, 0.0);
+}
+
+void zero_outer_faces(c128* e, int nx, int ny, int nz, hipStream_t s) {
+  const int64_t nv = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(kk_zero_outer_faces, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, e, nx, ny, nz);
+  check_launch("zero outer faces");
+}
+
 void masked_copy(const c128* e, const c128* chi_inv, c128* b, int64_t nv, hipStream_t s, int64_t cper) {
   if (cper <= 0) cper = nv;
   hipLaunchKernelGGL(kk_masked_copy, dim3((unsigned)((3 * nv + 255) / 256)), dim3(256), 0, s, e, chi_inv, b, nv,

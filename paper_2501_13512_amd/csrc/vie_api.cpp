@@ -2579,6 +2579,7 @@ static void total_field_box(vie_problem* p, const c128* pol, const c128* e_inc, 
   vie::mvm_pass1<R>(m, nullptr, none, pol, true, s);
   vie::mvm_mid<R>(m, s);
   vie::mvm_pass5<R>(m, nullptr, field, pol, e_box, s);
+  if (p->rooftop) vie::zero_outer_faces(e_box, p->g.nx, p->g.ny, p->g.nz, s);
 }
 }  // extern "C++"
 
@@ -2587,7 +2588,6 @@ vie_status vie_total_field_box(vie_problem* p, int32_t precision, const void* po
   return guarded([&]() -> vie_status {
     if (!p || !pol_dev || !e_inc_dev || !e_box_dev) fail(VIE_EINVAL, "problem, pol, e_inc and e_box are required");
     if (e_box_dev == pol_dev || e_box_dev == e_inc_dev) fail(VIE_EINVAL, "e_box must not overlap the inputs");
-    collocated_only(p, "vie_total_field_box");
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
     hipStream_t s = (hipStream_t)stream;
@@ -2837,8 +2837,9 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
   return guarded([&]() -> vie_status {
     if (!p || !e_inc_dev || !e_tot_dev) fail(VIE_EINVAL, "problem, e_inc and e_tot are required");
     if (nrhs < 1 || nrhs > 4096) fail(VIE_EINVAL, "nrhs must be in [1, 4096]");
-    collocated_only(p, "vie_solve_batch");
     validate_opts(opts, !p->groups.empty());
+    if (p->rooftop && opts->precondition && nrhs > 1 && opts->solver == VIE_SOLVER_BICGSTAB)
+      fail(VIE_EINVAL, "vie_solve_batch: preconditioned batches of rooftop problems are not available");
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
     auto t0 = std::chrono::steady_clock::now();
@@ -2869,7 +2870,7 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
       hip_check(hipMemsetAsync(P.replica->d_acc.p, 0, 3 * sizeof(int64_t), s), "acc");
     }
     for (int r = 0; r < nrhs; ++r)
-      vie::masked_copy(ein + r * n, P.chi.as<c128>(), batch_vec(P, BV_B, nrhs) + r * n, P.nv, s);
+      vie::masked_copy(ein + r * n, P.chi.as<c128>(), batch_vec(P, BV_B, nrhs) + r * n, P.nv, s, chi_period(P));
     const double ti = opts->tol_inner;
     const int mi = opts->maxit_inner, lag = opts->poll_lag;
     if (opts->precision == VIE_MIXED)

@@ -128,8 +128,8 @@ def test_rooftop_face_contrast_cases(vie_ctx):
 
 
 def test_rooftop_argument_checks(vie_ctx):
-    """Non-vacuum boundary layers, preconditioning and the collocated-only
-    entry points (total field in the box, batches) are refused with
+    """Non-vacuum boundary layers, preconditioning without blocks,
+    preconditioned batches and batches of problems are refused with
     VIE_EINVAL."""
     case = W.random_tiny(9, (4, 4, 4), fill=1.0)
     with pytest.raises(V.VieError) as e:
@@ -146,16 +146,80 @@ def test_rooftop_argument_checks(vie_ctx):
             V.vie_solve_device(P.handle, x, V.make_opts(precondition=True), y, None, st)
         assert e.value.code == V.VIE_EINVAL
         with pytest.raises(V.VieError) as e:
-            V.vie_total_field_box(P.handle, V.VIE_FP64, x, x, y)
-        assert e.value.code == V.VIE_EINVAL
-        with pytest.raises(V.VieError) as e:
-            V.vie_solve_batch(P.handle, 1, x, V.make_opts(precondition=False), y)
-        assert e.value.code == V.VIE_EINVAL
-        with pytest.raises(V.VieError) as e:
             V.vie_solve_many([P.handle], [x], V.make_opts(precondition=False), [y])
         assert e.value.code == V.VIE_EINVAL
     finally:
         P.close()
+    case = W.padded(W.random_tiny(9, (3, 3, 3), fill=1.0, n_blocks=2))
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
+    try:
+        x = torch.zeros(2 * 3 * case.nvox, dtype=torch.complex128, device="cuda")
+        y = torch.zeros_like(x)
+        with pytest.raises(V.VieError) as e:
+            V.vie_solve_batch(P.handle, 2, x, V.make_opts(precondition=True), y)
+        assert e.value.code == V.VIE_EINVAL
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(V.VIE_FP64, 1e-12), (V.VIE_MIXED, 1e-5)])
+def test_rooftop_total_field_box_matches_oracle(vie_ctx, prec, tol):
+    """E_inc + T P at every face centre of the box, vacuum faces included,
+    except the faces of the last cell layer along their own axis (their
+    second cell is outside the grid; 0 on output)."""
+    case = _case(71, (5, 6, 4), fill=0.7)
+    g = op.Grid.from_case(case)
+    fm = rt.face_mask(g)
+    Pf = _rand(72, case.shape) * fm
+    e = rt.plane_wave(g, (0.6, 0.0, 0.8), (0.8, 0.0, -0.6))
+    want = e + rt.RooftopFFT(g).scatter(Pf)
+    want[0, :, :, -1] = 0
+    want[1, :, -1, :] = 0
+    want[2, -1, :, :] = 0
+    P = V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
+    try:
+        out = torch.full((3,) + case.shape, complex("nan"), dtype=torch.complex128, device="cuda")
+        V.vie_total_field_box(P.handle, prec, torch.from_numpy(Pf).cuda(), torch.from_numpy(e).cuda(), out)
+        got = out.cpu().numpy()
+    finally:
+        P.close()
+    assert np.abs(got - want).max() / np.abs(want).max() <= tol
+
+
+@pytest.mark.parametrize("prec", [V.VIE_FP64, V.VIE_MIXED])
+def test_rooftop_plain_batch_equals_separate_solves(vie_ctx, prec):
+    """Three incident waves as one plain batch: bitwise the solves one by
+    one, and each at the oracle's solution."""
+    case = _sphere()
+    g = op.Grid.from_case(case)
+    waves = [((0.0, 0.0, 1.0), (1.0, 0.0, 0.0)), ((1.0, 0.0, 0.0), (0.0, 1.0, 0.0)),
+             ((0.6, 0.0, 0.8), (0.8, 0.0, -0.6))]
+    P = V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
+    try:
+        e = torch.from_numpy(np.stack([V.vie_plane_wave_faces(P.grid, k, p) for k, p in waves])).cuda()
+        opts = V.make_opts(tol_outer=1e-10, precondition=False, precision=prec, maxit_outer=2000)
+        want, iters = [], []
+        for r in range(3):
+            out = torch.empty_like(e[r])
+            pol = torch.empty_like(e[r])
+            st = V.vie_stats()
+            V.vie_solve_device(P.handle, e[r].contiguous(), opts, out, pol, st)
+            torch.cuda.synchronize()
+            want.append(pol.cpu().numpy())
+            iters.append(st.outer_iters)
+        out = torch.empty_like(e)
+        pol = torch.empty_like(e)
+        stats = (V.vie_stats * 3)()
+        assert V.vie_solve_batch(P.handle, 3, e, opts, out, pol, stats) == V.VIE_OK
+        torch.cuda.synchronize()
+        got = pol.cpu().numpy()
+    finally:
+        P.close()
+    assert [stats[r].outer_iters for r in range(3)] == iters
+    assert np.array_equal(got, np.stack(want))
+    for r, (k, p) in enumerate(waves):
+        ref, info = rt.solve(g, rt.plane_wave(g, k, p), 1e-12, 3000)
+        assert np.abs(got[r] - ref).max() <= 1e-7 * np.abs(ref).max()
 
 
 def _sphere():
