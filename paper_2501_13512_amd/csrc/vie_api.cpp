@@ -546,10 +546,6 @@ MvmBatch<R> group_batch(vie_problem& P, Group& G, bool gated) {
 // (three per voxel) for the rooftop discretisation.
 int64_t chi_period(const vie_problem& P) { return P.rooftop ? 3 * P.nv : P.nv; }
 
-void collocated_only(const vie_problem* p, const char* what) {
-  if (p && p->rooftop) fail(VIE_EINVAL, std::string(what) + ": not available for rooftop problems");
-}
-
 KBatch outer_kbatch(vie_problem& P) {
   KBatch k{};
   k.nsys = 1;
@@ -1475,7 +1471,7 @@ template <typename R>
 MvmBatch<R> fleet_mvm(vie_problem& P0, Fleet& F, int n) {
   MvmBatch<R> b = outer_batch<R>(P0, true);   // the first problem's shape and kernel variants
   b.nsys = n;
-  b.cstride = P0.nv;
+  b.cstride = chi_period(P0);
   b.chi_inv = F.chi.as<c128>();
   b.spec_tab = F.tab.as<const cx<R>*>() + (sizeof(R) == sizeof(float) ? n : 0);
   b.work = F.work.as<cx<R>>();
@@ -2922,7 +2918,9 @@ vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* c
     vie_problem& P0 = *ps[0];
     const bool prec = opts && opts->precondition != 0;
     for (vie_problem* q : ps) {
-      collocated_only(q, "vie_solve_many");
+      if (q->rooftop != P0.rooftop) fail(VIE_EINVAL, "vie_solve_many: rooftop and collocated problems mixed");
+      if (q->rooftop && prec && n > 1 && opts->solver == VIE_SOLVER_BICGSTAB)
+        fail(VIE_EINVAL, "vie_solve_many: preconditioned batches of rooftop problems are not available");
       if (q->ctx != P0.ctx) fail(VIE_EINVAL, "problems belong to different contexts");
       if (q->g.nx != P0.g.nx || q->g.ny != P0.g.ny || q->g.nz != P0.g.nz || q->lx != P0.lx || q->ly != P0.ly ||
           q->lz != P0.lz)
@@ -2957,7 +2955,8 @@ vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* c
     if (prec) fp = fleet_plan(ps);
     const size_t small = (size_t)n * (sizeof(KState) + 2 * sizeof(int) + 2 * (size_t)P0.pstride * sizeof(double)) +
                          2 * (size_t)n * sizeof(void*) + sizeof(int);
-    const size_t bytes = (size_t)n * nv * sizeof(c128) + (size_t)n * 3 * P0.g.nz * P0.ly * P0.lx * sizeof(c128) +
+    const int64_t cper = chi_period(P0);   // 1/chi entries per problem
+    const size_t bytes = (size_t)n * cper * sizeof(c128) + (size_t)n * 3 * P0.g.nz * P0.ly * P0.lx * sizeof(c128) +
                          (size_t)kBatchVecs * n * n3 * sizeof(c128) + small + (prec ? replica_bytes(fp) : 0);
     {
       std::lock_guard<std::mutex> lk(P0.ctx->mu);
@@ -2966,7 +2965,7 @@ vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* c
       P0.ctx->used += bytes;
       F.bytes = bytes;
     }
-    F.chi.alloc((size_t)n * nv * sizeof(c128));
+    F.chi.alloc((size_t)n * cper * sizeof(c128));
     F.work.alloc((size_t)n * 3 * P0.g.nz * P0.ly * P0.lx * sizeof(c128));
     F.vecs.alloc((size_t)kBatchVecs * n * n3 * sizeof(c128));
     F.vecs.zero(s);
@@ -2978,7 +2977,8 @@ vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* c
     F.count.alloc(sizeof(int));
     std::vector<const void*> tab(2 * (size_t)n);
     for (int r = 0; r < n; ++r) {
-      hip_check(hipMemcpyAsync(F.chi.as<c128>() + r * nv, ps[r]->chi.p, nv * sizeof(c128), hipMemcpyDeviceToDevice, s),
+      hip_check(hipMemcpyAsync(F.chi.as<c128>() + r * cper, ps[r]->chi.p, cper * sizeof(c128),
+                               hipMemcpyDeviceToDevice, s),
                 "batch 1/chi");
       tab[r] = spec_ptr<double>(*ps[r]->spec);
       tab[n + r] = spec_ptr<float>(*ps[r]->spec);
@@ -2998,7 +2998,8 @@ vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* c
     k.ntile = F.ntile.as<int>();
     k.partials2 = F.partials2.as<double>();
     const BatchSet B{P0, F.replica.get(), n, nv, F.vecs.as<c128>(), k, F.status.as<int>(), F.count.as<int>()};
-    for (int r = 0; r < n; ++r) vie::masked_copy(ein(r), ps[r]->chi.as<c128>(), B.vec(BV_B) + r * n3, nv, s);
+    for (int r = 0; r < n; ++r)
+      vie::masked_copy(ein(r), ps[r]->chi.as<c128>(), B.vec(BV_B) + r * n3, nv, s, chi_period(*ps[r]));
     const double ti = opts->tol_inner, to = opts->tol_outer;
     const int mi = opts->maxit_inner, mo = opts->maxit_outer, lag = opts->poll_lag;
     if (opts->precision == VIE_MIXED)

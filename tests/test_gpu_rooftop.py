@@ -129,8 +129,8 @@ def test_rooftop_face_contrast_cases(vie_ctx):
 
 def test_rooftop_argument_checks(vie_ctx):
     """Non-vacuum boundary layers, preconditioning without blocks,
-    preconditioned batches and batches of problems are refused with
-    VIE_EINVAL."""
+    preconditioned batches and batches mixing rooftop and collocated
+    problems are refused with VIE_EINVAL."""
     case = W.random_tiny(9, (4, 4, 4), fill=1.0)
     with pytest.raises(V.VieError) as e:
         V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
@@ -145,9 +145,14 @@ def test_rooftop_argument_checks(vie_ctx):
         with pytest.raises(V.VieError) as e:
             V.vie_solve_device(P.handle, x, V.make_opts(precondition=True), y, None, st)
         assert e.value.code == V.VIE_EINVAL
-        with pytest.raises(V.VieError) as e:
-            V.vie_solve_many([P.handle], [x], V.make_opts(precondition=False), [y])
-        assert e.value.code == V.VIE_EINVAL
+        cc = W.random_tiny(9, (6, 6, 6), fill=0.5)
+        C = V.Problem(_grid(cc), cc.eps, ctx=vie_ctx)
+        try:
+            with pytest.raises(V.VieError) as e:
+                V.vie_solve_many([P.handle, C.handle], [x, x], V.make_opts(precondition=False), [y, y])
+            assert e.value.code == V.VIE_EINVAL
+        finally:
+            C.close()
     finally:
         P.close()
     case = W.padded(W.random_tiny(9, (3, 3, 3), fill=1.0, n_blocks=2))
@@ -428,3 +433,38 @@ def test_rooftop_padded_metasurface_blocks_full_size(vie_ctx):
     b = np.where(rt.face_mask(g), e, 0)
     res = np.linalg.norm(b - A(Pg)) / np.linalg.norm(b)
     assert res <= 3e-6, res
+
+
+@pytest.mark.parametrize("prec", [V.VIE_FP64, V.VIE_MIXED])
+def test_rooftop_problems_in_one_batch(vie_ctx, prec):
+    """Three rooftop problems of one grid shape (different permittivities and
+    spacings) as one plain vie_solve_many batch: bitwise the solves alone,
+    each at the oracle's solution."""
+    cases = [_case(80 + i, (6, 6, 6), fill=0.6) for i in range(3)]
+    probs = [V.Problem(_grid(c), c.eps, ctx=vie_ctx, rooftop=True) for c in cases]
+    try:
+        es = [torch.from_numpy(V.vie_plane_wave_faces(p.grid, (0.0, 0.0, 1.0), (1.0, 0.0, 0.0))).cuda()
+              for p in probs]
+        opts = V.make_opts(tol_outer=1e-10, precondition=False, precision=prec, maxit_outer=2000)
+        want, iters = [], []
+        for p, e in zip(probs, es):
+            out, pol, st = torch.empty_like(e), torch.empty_like(e), V.vie_stats()
+            V.vie_solve_device(p.handle, e, opts, out, pol, st)
+            torch.cuda.synchronize()
+            want.append(pol.cpu().numpy())
+            iters.append(st.outer_iters)
+        outs = [torch.empty_like(e) for e in es]
+        pols = [torch.empty_like(e) for e in es]
+        stats = (V.vie_stats * 3)()
+        assert V.vie_solve_many([p.handle for p in probs], es, opts, outs, pols, stats) == V.VIE_OK
+        torch.cuda.synchronize()
+        got = [q.cpu().numpy() for q in pols]
+    finally:
+        for p in probs:
+            p.close()
+    assert [stats[r].outer_iters for r in range(3)] == iters
+    for r, c in enumerate(cases):
+        assert np.array_equal(got[r], want[r]), r
+        g = op.Grid.from_case(c)
+        ref, _ = rt.solve(g, rt.plane_wave(g), 1e-12, 3000)
+        assert np.abs(got[r] - ref).max() <= 1e-7 * np.abs(ref).max()
