@@ -174,6 +174,19 @@ def oracle_steps(case):
     return int(g["outer_iters"]) + int(g.get("refine_iters", 0)), int(g.get("refine_steps", 0))
 
 
+def cpu_rooftop_product(W):
+    """The oracle's rooftop product (FP64, scipy FFT on the host) on the
+    padded metasurface, one call, in seconds: the CPU figure beside the
+    rooftop product's GPU time."""
+    from oracle import operator as oop, rooftop as ort
+    rc = W.padded(W.metasurface())
+    A = ort.RooftopFFT(oop.Grid.from_case(rc))
+    x = np.random.default_rng(1).standard_normal((3,) + rc.shape) + 0j
+    t1 = time.perf_counter()
+    A(x)
+    return time.perf_counter() - t1
+
+
 def cpu_baseline(case, tol_outer, gpu_steps, sample_steps=3):
     """The CPU oracle on a bounded sample of the same workload, on every host
     core (scipy.fft workers; the oracle's inner products are plain numpy
@@ -301,6 +314,11 @@ def rooftop_measure(V, W, ctx, reps):
     for kind in ("rooftop", "collocated"):
         for p in ("mixed", "fp64"):
             roof[kind][p]["frac_of_hbm_peak"] = roof[kind][p]["algorithmic_GBps"] / HBM_PEAK_GBS
+    dm = roof["rooftop"]["mixed"]["dominant"]
+    roof["roofline"] = {"bound": "hbm", "achieved": dm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": dm["achieved"] / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": f"{dm['kernel']} (rooftop product, mixed, FFT {roof['rooftop']['fft']})",
+                        "bytes_per_launch": dm["bytes"], "ms": dm["ms"]}
     return roof
 
 
@@ -790,6 +808,8 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, case.tol_outer,
                                            stats[-1]["outer_iters"] + stats[-1]["refine_iters"], args.cpu_steps)
+        if roof is not None:
+            res["cpu_baseline"]["rooftop_product_s"] = cpu_rooftop_product(W)
         log("cpu baseline done")
     P.close()
     V.vie_context_destroy(ctx)
