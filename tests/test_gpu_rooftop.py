@@ -468,3 +468,26 @@ def test_rooftop_problems_in_one_batch(vie_ctx, prec):
         g = op.Grid.from_case(c)
         ref, _ = rt.solve(g, rt.plane_wave(g), 1e-12, 3000)
         assert np.abs(got[r] - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("solver,prec", [(V.VIE_SOLVER_FGMRES, V.VIE_FP64), (V.VIE_SOLVER_CGS, V.VIE_FP64),
+                                         (V.VIE_SOLVER_BICGSTAB, V.VIE_MIXED_INNER)])
+def test_rooftop_solver_variants_reach_the_oracle_solution(vie_ctx, solver, prec):
+    """Flexible GMRES(30), CGS and BiCGSTAB with FP32 inner solves, all with
+    the rooftop block preconditioner on the two-shape partition: each
+    solution equals the oracle's (unique) solution within 1e-8."""
+    case = W.padded(W.mixed_partition(0))
+    g = op.Grid.from_case(case)
+    P0, i0 = rt.solve(g, rt.plane_wave(g), 1e-12, 3000)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
+    try:
+        ed = torch.from_numpy(V.vie_plane_wave_faces(P.grid, case.kdir, case.pol)).cuda()
+        et, pol, st = torch.empty_like(ed), torch.empty_like(ed), V.vie_stats()
+        o = V.make_opts(tol_outer=1e-10, tol_inner=1e-3, maxit_outer=500, precondition=True, precision=prec,
+                        solver=solver, restart=30)
+        assert V.vie_solve_device(P.handle, ed, o, et, pol, st) == V.VIE_OK
+        print(f"rooftop solver {solver} prec {prec}: {st.outer_iters} steps", flush=True)
+        Pg = pol.cpu().numpy()
+    finally:
+        P.close()
+    assert np.abs(Pg - P0).max() <= 1e-8 * np.abs(P0).max()
