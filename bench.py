@@ -20,7 +20,7 @@ for every application; its duration at each active count is measured live
 with HIP events on the launch stream (vie_group_profile, the same kernel and
 grid as in the solves) and weighted by the launches of the timed solve.
 ``roofline_full_grid`` gives the full-grid product on a 256x256x64 grid
-(the survey's per-product byte model) beside it.  Extra fields: per-solve
+(the per-pass algorithmic byte model of ``pass_bytes``) beside it.  Extra fields: per-solve
 latency p50/p99, outer and inner step counts, the FP64 true residual, the
 field error at every scatterer voxel against the oracle's stored solves
 (case tolerance, and 1e-12), the FP64 GPU paths of the same workload
