@@ -248,13 +248,12 @@ vie_status vie_problem_create_overlap(vie_context* ctx, const vie_grid* grid, co
  * bounding box grown by one cell per side).  vie_matvec,
  * vie_matvec_profile, vie_block_matvec, vie_precond_apply, vie_group_profile,
  * vie_solve and vie_solve_device (e_tot_out is then the field on every face,
- * P_f / chi_f), vie_solve_batch (preconditioned batches of more than one
- * right-hand side excepted), vie_total_field_box (the field at every face
- * centre of the box; 0 on the faces of the last cell layer along their own
- * axis, whose second cell lies outside the grid), vie_far_field, vie_far_field_noalloc and vie_rcs (each
- * face unknown radiating from its face centre) and vie_solve_many (rooftop
- * problems only, plain batches) accept it; preconditioned BiCGSTAB batches of
- * right-hand sides or problems and z-pass variant 1 return VIE_EINVAL.
+ * P_f / chi_f), vie_solve_batch, vie_solve_many (a batch holds rooftop
+ * problems only), vie_total_field_box (the field at every face centre of the
+ * box; 0 on the faces of the last cell layer along their own axis, whose
+ * second cell lies outside the grid), vie_far_field, vie_far_field_noalloc
+ * and vie_rcs (each face unknown radiating from its face centre) accept it;
+ * z-pass variant 1 returns VIE_EINVAL.
  * Every block group runs on the batched multi-workgroup kernels
  * (VIE_FLAG_NO_BLOCK_KERNEL has no effect). */
 vie_status vie_problem_create_rooftop(vie_context* ctx, const vie_grid* grid, const double* eps_r,

@@ -1316,6 +1316,27 @@ void run_bicgstab_batch(vie_problem& P, int nrhs, double tol, int maxit, int lag
 // The plan of nrhs copies of a problem stacked along z, with block ids
 // offset per copy and the original shape groups (so every block is solved
 // with the same transform lengths and box as in the problem itself).
+// Rooftop plans stacked along z: the per-face 1/chi and owners are
+// component-major ([3][copies x nz][ny][nx], the layout batch_to_stacked
+// gives the vectors), copy r's block ids shifted by off[r].  Faces between
+// copies carry no unknown: every copy's first and last z layer is vacuum.
+void stack_faces(ProblemPlan& sp, const std::vector<const ProblemPlan*>& pls, const std::vector<int>& off) {
+  sp.rooftop = true;
+  sp.chi.clear();
+  sp.bid3.clear();
+  sp.chi.reserve(3 * (size_t)sp.nv);
+  sp.bid3.reserve(3 * (size_t)sp.nv);
+  for (int c = 0; c < 3; ++c)
+    for (size_t r = 0; r < pls.size(); ++r) {
+      const ProblemPlan& pl = *pls[r];
+      sp.chi.insert(sp.chi.end(), pl.chi.begin() + (size_t)c * pl.nv, pl.chi.begin() + (size_t)(c + 1) * pl.nv);
+      for (int64_t i = 0; i < pl.nv; ++i) {
+        const int32_t b = pl.bid3[(size_t)c * pl.nv + i];
+        sp.bid3.push_back(b < 0 ? -1 : b + off[r]);
+      }
+    }
+}
+
 ProblemPlan stacked_plan(const ProblemPlan& pl, int nrhs) {
   ProblemPlan sp;
   sp.g = pl.g;
@@ -1347,6 +1368,12 @@ ProblemPlan stacked_plan(const ProblemPlan& pl, int nrhs) {
       for (int k : gp.blocks) g2.blocks.push_back(k + r * nb);
     sp.groups.push_back(std::move(g2));
   }
+  if (pl.rooftop) {
+    std::vector<const ProblemPlan*> pls(nrhs, &pl);
+    std::vector<int> off(nrhs);
+    for (int r = 0; r < nrhs; ++r) off[r] = r * nb;
+    stack_faces(sp, pls, off);
+  }
   return sp;
 }
 
@@ -1359,7 +1386,7 @@ size_t replica_bytes(const ProblemPlan& sp) {
   size_t foot = 0;
   for (const auto& gp : sp.groups) {
     const size_t nsys = gp.blocks.size(), bnv = (size_t)gp.bx * gp.by * gp.bz;
-    foot += nsys * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
+    foot += nsys * (sp.rooftop ? 3 : 1) * bnv * sizeof(c128) + nsys * 3 * (size_t)gp.bz * gp.ly * gp.lx * sizeof(c128) +
             8 * nsys * 3 * bnv * sizeof(c128) + nsys * (sizeof(KState) + 2 * sizeof(int));
   }
   foot += (size_t)sp.nv * (sizeof(int32_t) + 4 * sizeof(int));   // block map
@@ -1448,6 +1475,17 @@ ProblemPlan fleet_plan(const std::vector<vie_problem*>& ps) {
     off += nb;
   }
   sp.n_blocks = off;
+  if (p0.rooftop) {
+    std::vector<const ProblemPlan*> pls;
+    std::vector<int> offs;
+    int o = 0;
+    for (vie_problem* q : ps) {
+      pls.push_back(q->plan.get());
+      offs.push_back(o);
+      o += q->plan->n_blocks;
+    }
+    stack_faces(sp, pls, offs);
+  }
   return sp;
 }
 
@@ -1971,7 +2009,7 @@ std::unique_ptr<vie_problem> build_problem(vie_context* ctx, const ProblemPlan& 
         bool same = true;
         for (int q = 0; q < G.nsys; ++q) {
           const double* ph = &pl.blk_phys[4 * (size_t)G.blocks[q]];
-          G.sys_spec.push_back(get_spectra(ctx, G.lx, G.ly, G.lz, ph[0], ph[1], ph[2], ph[3], s));
+          G.sys_spec.push_back(get_spectra(ctx, G.lx, G.ly, G.lz, ph[0], ph[1], ph[2], ph[3], s, pl.rooftop ? 1 : 0));
           same = same && G.sys_spec.back() == G.sys_spec.front();
         }
         G.spec = G.sys_spec.front();
@@ -2834,8 +2872,6 @@ vie_status vie_solve_batch(vie_problem* p, int32_t nrhs, const void* e_inc_dev, 
     if (!p || !e_inc_dev || !e_tot_dev) fail(VIE_EINVAL, "problem, e_inc and e_tot are required");
     if (nrhs < 1 || nrhs > 4096) fail(VIE_EINVAL, "nrhs must be in [1, 4096]");
     validate_opts(opts, !p->groups.empty());
-    if (p->rooftop && opts->precondition && nrhs > 1 && opts->solver == VIE_SOLVER_BICGSTAB)
-      fail(VIE_EINVAL, "vie_solve_batch: preconditioned batches of rooftop problems are not available");
     std::lock_guard<std::mutex> lk(p->mu);
     set_device(p->ctx);
     auto t0 = std::chrono::steady_clock::now();
@@ -2919,8 +2955,6 @@ vie_status vie_solve_many(int32_t n, vie_problem* const* problems, const void* c
     const bool prec = opts && opts->precondition != 0;
     for (vie_problem* q : ps) {
       if (q->rooftop != P0.rooftop) fail(VIE_EINVAL, "vie_solve_many: rooftop and collocated problems mixed");
-      if (q->rooftop && prec && n > 1 && opts->solver == VIE_SOLVER_BICGSTAB)
-        fail(VIE_EINVAL, "vie_solve_many: preconditioned batches of rooftop problems are not available");
       if (q->ctx != P0.ctx) fail(VIE_EINVAL, "problems belong to different contexts");
       if (q->g.nx != P0.g.nx || q->g.ny != P0.g.ny || q->g.nz != P0.g.nz || q->lx != P0.lx || q->ly != P0.ly ||
           q->lz != P0.lz)

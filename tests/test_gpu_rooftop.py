@@ -128,9 +128,9 @@ def test_rooftop_face_contrast_cases(vie_ctx):
 
 
 def test_rooftop_argument_checks(vie_ctx):
-    """Non-vacuum boundary layers, preconditioning without blocks,
-    preconditioned batches and batches mixing rooftop and collocated
-    problems are refused with VIE_EINVAL."""
+    """Non-vacuum boundary layers, preconditioning without blocks and
+    batches mixing rooftop and collocated problems are refused with
+    VIE_EINVAL."""
     case = W.random_tiny(9, (4, 4, 4), fill=1.0)
     with pytest.raises(V.VieError) as e:
         V.Problem(_grid(case), case.eps, ctx=vie_ctx, rooftop=True)
@@ -153,16 +153,6 @@ def test_rooftop_argument_checks(vie_ctx):
             assert e.value.code == V.VIE_EINVAL
         finally:
             C.close()
-    finally:
-        P.close()
-    case = W.padded(W.random_tiny(9, (3, 3, 3), fill=1.0, n_blocks=2))
-    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
-    try:
-        x = torch.zeros(2 * 3 * case.nvox, dtype=torch.complex128, device="cuda")
-        y = torch.zeros_like(x)
-        with pytest.raises(V.VieError) as e:
-            V.vie_solve_batch(P.handle, 2, x, V.make_opts(precondition=True), y)
-        assert e.value.code == V.VIE_EINVAL
     finally:
         P.close()
 
@@ -491,3 +481,52 @@ def test_rooftop_solver_variants_reach_the_oracle_solution(vie_ctx, solver, prec
     finally:
         P.close()
     assert np.abs(Pg - P0).max() <= 1e-8 * np.abs(P0).max()
+
+
+@pytest.mark.parametrize("prec,tol,bar", [(V.VIE_FP64, 1e-10, 1e-8), (V.VIE_MIXED, 1e-9, 1e-7)])
+def test_rooftop_preconditioned_batch_of_waves(vie_ctx, prec, tol, bar):
+    """Two incident waves as one block-preconditioned batch (the blocks of
+    both solved together on the stacked replica): each solution at the
+    oracle's."""
+    case = W.padded(W.mixed_partition(0))
+    g = op.Grid.from_case(case)
+    waves = [((0.0, 0.0, 1.0), (1.0, 0.0, 0.0)), ((0.6, 0.0, 0.8), (0.8, 0.0, -0.6))]
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx, rooftop=True)
+    try:
+        e = torch.from_numpy(np.stack([V.vie_plane_wave_faces(P.grid, k, p) for k, p in waves])).cuda()
+        out, pol, stats = torch.empty_like(e), torch.empty_like(e), (V.vie_stats * 2)()
+        o = V.make_opts(tol_outer=tol, tol_inner=1e-3, maxit_outer=500, precondition=True, precision=prec)
+        assert V.vie_solve_batch(P.handle, 2, e, o, out, pol, stats) == V.VIE_OK
+        torch.cuda.synchronize()
+        got = pol.cpu().numpy()
+    finally:
+        P.close()
+    for r, (k, p) in enumerate(waves):
+        ref, _ = rt.solve(g, rt.plane_wave(g, k, p), 1e-12, 3000)
+        assert np.abs(got[r] - ref).max() <= bar * np.abs(ref).max(), r
+        assert stats[r].precond_applies > 0
+
+
+def test_rooftop_preconditioned_problems_in_one_batch(vie_ctx):
+    """Three rooftop problems with blocks (different spacings: per-system
+    spectra) as one block-preconditioned vie_solve_many batch, FP64: each
+    solution at the oracle's."""
+    cases = [W.padded(W.random_tiny(90 + i, (5, 6, 6), fill=0.7, n_blocks=3)) for i in range(3)]
+    probs = [V.Problem(_grid(c), c.eps, c.block_id, c.n_blocks, ctx=vie_ctx, rooftop=True) for c in cases]
+    try:
+        es = [torch.from_numpy(V.vie_plane_wave_faces(p.grid, (0.0, 0.0, 1.0), (1.0, 0.0, 0.0))).cuda()
+              for p in probs]
+        outs = [torch.empty_like(e) for e in es]
+        pols = [torch.empty_like(e) for e in es]
+        stats = (V.vie_stats * 3)()
+        o = V.make_opts(tol_outer=1e-10, tol_inner=1e-3, maxit_outer=500, precondition=True, precision=V.VIE_FP64)
+        assert V.vie_solve_many([p.handle for p in probs], es, o, outs, pols, stats) == V.VIE_OK
+        torch.cuda.synchronize()
+        got = [q.cpu().numpy() for q in pols]
+    finally:
+        for p in probs:
+            p.close()
+    for r, c in enumerate(cases):
+        g = op.Grid.from_case(c)
+        ref, _ = rt.solve(g, rt.plane_wave(g), 1e-12, 3000)
+        assert np.abs(got[r] - ref).max() <= 1e-8 * np.abs(ref).max(), r
