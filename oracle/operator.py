@@ -135,6 +135,27 @@ def matvec_direct(grid: Grid, x: np.ndarray) -> np.ndarray:
     return out
 
 
+def apply_at(grid: Grid, src: np.ndarray, xs: np.ndarray, dst: np.ndarray) -> np.ndarray:
+    """(A x) at the voxels ``dst`` [S, 3] (z, y, x) for an x that is zero
+    except at the distinct voxels ``src`` [K, 3] (z, y, x), where it is
+    ``xs`` [K, 3] (components x, y, z): the definition's direct sum over the
+    K sources, for any grid size.  Returns [S, 3]."""
+    src = np.asarray(src, dtype=np.int64).reshape(-1, 3)
+    dst = np.asarray(dst, dtype=np.int64).reshape(-1, 3)
+    xs = np.asarray(xs, dtype=np.complex128).reshape(-1, 3)
+    eps_s = grid.eps[src[:, 0], src[:, 1], src[:, 2]]
+    xs = np.where((eps_s != 1.0)[:, None], xs, 0.0)            # x lives on S only
+    m = dst[:, None, :] - src[None, :, :]                       # [S, K, (z, y, x)]
+    T = offset_tensor(m[..., 2], m[..., 1], m[..., 0], grid.dx, grid.dy, grid.dz, grid.k0)
+    field = np.einsum("skab,kb->sa", T, xs)
+    same = np.all(m == 0, axis=-1)                              # dst s is source k
+    x_d = same.astype(np.complex128) @ xs
+    eps_d = grid.eps[dst[:, 0], dst[:, 1], dst[:, 2]]
+    on_s = eps_d != 1.0
+    chi_inv = np.where(on_s, 1.0 / np.where(on_s, eps_d - 1.0, 1.0), 0.0)
+    return np.where(on_s[:, None], x_d * chi_inv[:, None] - field, 0.0)
+
+
 class FFTOperator:
     """A applied with the FFT convolution (Sec. I, Toeplitz + FFT).
 

@@ -53,21 +53,70 @@ def check_grid(grid: Grid) -> None:
         raise ValueError("rooftop discretisation: the boundary cell layers must be vacuum")
 
 
+def _contrast(a, b):
+    """Face contrast from 1/eps of the face's two cells (0: no unknown)."""
+    m = 0.5 * (a + b)
+    both_vacuum = (a == 1.0) & (b == 1.0)
+    return np.where(both_vacuum, 0.0, (1.0 - m) / m)
+
+
 def face_chi(grid: Grid) -> np.ndarray:
     """chi_f of every face [3, nz, ny, nx] (0: no unknown): (1 - m) / m with
     m the mean of 1/eps over the face's two cells."""
     inv = np.where(grid.mask, 1.0 / np.where(grid.mask, grid.eps, 1.0), 1.0)
     out = np.zeros((3,) + inv.shape, dtype=np.complex128)
-
-    def chi_of(a, b):
-        m = 0.5 * (a + b)
-        both_vacuum = (a == 1.0) & (b == 1.0)
-        return np.where(both_vacuum, 0.0, (1.0 - m) / m)
-
-    out[0, :, :, :-1] = chi_of(inv[:, :, :-1], inv[:, :, 1:])
-    out[1, :, :-1, :] = chi_of(inv[:, :-1, :], inv[:, 1:, :])
-    out[2, :-1, :, :] = chi_of(inv[:-1, :, :], inv[1:, :, :])
+    out[0, :, :, :-1] = _contrast(inv[:, :, :-1], inv[:, :, 1:])
+    out[1, :, :-1, :] = _contrast(inv[:, :-1, :], inv[:, 1:, :])
+    out[2, :-1, :, :] = _contrast(inv[:-1, :, :], inv[1:, :, :])
     return out
+
+
+_STEP = np.array([[0, 0, 1], [0, 1, 0], [1, 0, 0]])   # (z, y, x) step along axis c = x, y, z
+
+
+def face_chi_at(grid: Grid, faces: np.ndarray) -> np.ndarray:
+    """chi_f at the faces [S, 4] (c, z, y, x), 0 where no unknown."""
+    faces = np.asarray(faces, dtype=np.int64).reshape(-1, 4)
+    c, cell = faces[:, 0], faces[:, 1:]
+    up = cell + _STEP[c]
+    inside = np.all(up < np.array([grid.nz, grid.ny, grid.nx]), axis=1)
+    up = np.where(inside[:, None], up, cell)
+    e1 = grid.eps[cell[:, 0], cell[:, 1], cell[:, 2]]
+    e2 = grid.eps[up[:, 0], up[:, 1], up[:, 2]]
+    return np.where(inside, _contrast(1.0 / e1, 1.0 / e2), 0.0)
+
+
+def apply_at(grid: Grid, src: np.ndarray, vals: np.ndarray, dst: np.ndarray) -> np.ndarray:
+    """(A P) at the faces ``dst`` [S, 4] (c, z, y, x) for a P that is zero
+    except at the distinct faces ``src`` [K, 4], where it is ``vals`` [K]:
+    the direct sums of T P = k0^2 (g~ * P) + grad (g~ * div P) over the K
+    sources and the cells their charges sit on, for any grid size."""
+    src = np.asarray(src, dtype=np.int64).reshape(-1, 4)
+    dst = np.asarray(dst, dtype=np.int64).reshape(-1, 4)
+    vals = np.where(face_chi_at(grid, src) != 0, np.asarray(vals, dtype=np.complex128), 0.0)
+    d = np.array([grid.dx, grid.dy, grid.dz])
+    k0, dV = grid.k0, grid.dV
+
+    def g(a, b):   # g~ between cells a [S, 3] and b [K, 3] (z, y, x)
+        m = a[:, None, :] - b[None, :, :]
+        return g_tilde(m[..., 2], m[..., 1], m[..., 0], grid.dx, grid.dy, grid.dz, k0)
+
+    # L^c: same-component convolution
+    lc = k0 ** 2 * dV * np.sum(np.where(dst[:, None, 0] == src[None, :, 0], g(dst[:, 1:], src[:, 1:]), 0.0)
+                               * vals[None, :], axis=1)
+    # cell charges of the rooftops: +P/d_c on the lower cell, -P/d_c on the upper
+    qcells = np.concatenate([src[:, 1:], src[:, 1:] + _STEP[src[:, 0]]])
+    q = np.concatenate([vals / d[src[:, 0]], -vals / d[src[:, 0]]])
+
+    def phi(cells):
+        return dV * np.sum(g(cells, qcells) * q[None, :], axis=1)
+
+    lq = (phi(dst[:, 1:] + _STEP[dst[:, 0]]) - phi(dst[:, 1:])) / d[dst[:, 0]]
+    same = np.all(dst[:, None, :] == src[None, :, :], axis=-1)
+    p_d = same.astype(np.complex128) @ vals
+    chi = face_chi_at(grid, dst)
+    chi_inv = np.where(chi != 0, 1.0 / np.where(chi != 0, chi, 1.0), 0.0)
+    return np.where(chi != 0, p_d * chi_inv - (lc + lq), 0.0)
 
 
 def face_mask(grid: Grid) -> np.ndarray:

@@ -140,3 +140,21 @@ def test_rooftop_preconditioned_solve():
     one = np.where(g.mask, 0, -1)
     _, i2, _ = rt.solve_preconditioned(g, e, one, 1, 1e-8, 50, 1e-13, 500)
     assert i2.status == "converged" and i2.iterations == 1
+
+
+def test_sparse_direct_evaluation_equals_the_fft_operator():
+    """rooftop.apply_at (direct sums over a sparse P, any grid size) equals
+    the FFT operator at sampled faces, sources and far faces alike."""
+    c = W.padded(W.random_tiny(5, (5, 6, 7), fill=0.7))
+    g = op.Grid.from_case(c)
+    rng = np.random.default_rng(1)
+    idx = np.argwhere(rt.face_mask(g))
+    src = idx[rng.choice(len(idx), 25, replace=False)]
+    vals = rng.standard_normal(25) + 1j * rng.standard_normal(25)
+    P = np.zeros((3,) + c.shape, complex)
+    P[tuple(src.T)] = vals
+    full = rt.RooftopFFT(g)(P)
+    dst = np.argwhere(np.ones((3,) + c.shape, bool))[rng.choice(3 * c.nvox, 60, replace=False)]
+    dst = np.concatenate([dst, src[:5]])
+    got = rt.apply_at(g, src, vals, dst)
+    assert np.abs(got - full[tuple(dst.T)]).max() <= 1e-13 * np.abs(full).max()
