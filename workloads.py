@@ -39,7 +39,7 @@ import numpy as np
 
 __all__ = [
     "Case", "cube16", "metasurface", "plasmonic", "sweep_case", "sweep",
-    "sphere", "padded", "random_tiny", "mixed_partition", "plasmonic_small", "SERVING_GRIDS", "SERVING_RATES", "arrivals", "serving_request",
+    "sphere", "padded", "random_large", "random_tiny", "mixed_partition", "plasmonic_small", "SERVING_GRIDS", "SERVING_RATES", "arrivals", "serving_request",
     "request_precondition", "CASES", "by_name",
 ]
 
@@ -279,6 +279,25 @@ def padded(case: Case, layers: int = 1) -> Case:
     return Case(f"{case.name}_pad{L}", nx, ny, nz, case.dx, case.dy, case.dz, case.wavelength, eps, bid, case.n_blocks,
                 tol_outer=case.tol_outer, tol_inner=case.tol_inner, precision=case.precision,
                 note=f"{case.note}; {L} vacuum layer(s) on every side")
+
+
+def random_large(seed: int, shape: Tuple[int, int, int] = (256, 256, 256), fill: float = 0.9,
+                 vacuum_shell: bool = False) -> Case:
+    """Random permittivity on a large grid (the largest the library takes by
+    default), no blocks: ``rng = default_rng(seed)``; mask ``rng.random(shape)
+    < fill``; eps ``rng.uniform(1.5, 4, shape) - 0.2j`` on the mask; spacing
+    lambda/40.  ``vacuum_shell``: the first and last cell layer of every axis
+    vacuum (rooftop inputs)."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    mask = rng.random(shape) < fill
+    if vacuum_shell:
+        mask[0], mask[-1], mask[:, 0], mask[:, -1], mask[:, :, 0], mask[:, :, -1] = (False,) * 6
+    eps = np.where(mask, rng.uniform(1.5, 4.0, shape) - 0.2j, 1.0 + 0.0j).astype(np.complex128)
+    d = 1.0 / 40.0
+    return Case(f"random_large{seed}_{nx}x{ny}x{nz}", nx, ny, nz, d, d, d, 1.0, eps,
+                np.full(shape, -1, dtype=np.int32), 0, tol_outer=1e-6, tol_inner=1e-2, precision="fp64",
+                note="random permittivity on a large grid")
 
 
 def random_tiny(seed: int, shape: Tuple[int, int, int], fill: float = 0.7,
