@@ -114,12 +114,16 @@ template <> struct Plan<12> { using type = Radices<4, 3>; };
 template <> struct Plan<16> { using type = Radices<16>; };
 template <> struct Plan<24> { using type = Radices<8, 3>; };
 template <> struct Plan<32> { using type = Radices<8, 4>; };
+template <> struct Plan<36> { using type = Radices<4, 3, 3>; };
 template <> struct Plan<48> { using type = Radices<16, 3>; };
 template <> struct Plan<64> { using type = Radices<8, 8>; };
+template <> struct Plan<72> { using type = Radices<8, 3, 3>; };
 template <> struct Plan<96> { using type = Radices<8, 4, 3>; };
 template <> struct Plan<128> { using type = Radices<16, 8>; };
+template <> struct Plan<144> { using type = Radices<16, 3, 3>; };
 template <> struct Plan<192> { using type = Radices<16, 4, 3>; };
 template <> struct Plan<256> { using type = Radices<16, 16>; };
+template <> struct Plan<288> { using type = Radices<8, 4, 3, 3>; };
 template <> struct Plan<384> { using type = Radices<16, 8, 3>; };
 template <> struct Plan<512> { using type = Radices<8, 8, 8>; };
 

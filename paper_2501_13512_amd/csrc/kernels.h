@@ -20,8 +20,12 @@ enum SysStatus : int {
 };
 
 // FFT lengths with compiled kernels (2^a 3^b, up to 512).
-constexpr int kFftLengths[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
-int smallest_fft_length(int min_len);   // smallest supported L >= min_len, or -1
+constexpr int kFftLengths[] = {1,  2,  3,  4,  6,   8,   12,  16,  24,  32,  36,
+                               48, 64, 72, 96, 128, 144, 192, 256, 288, 384, 512};
+// Smallest supported L >= min_len, or -1.  xy: an x or y length, which
+// skips 36 (no fused plane kernels for it; 48 keeps square boxes on the
+// plane kernels).
+int smallest_fft_length(int min_len, bool xy = false);
 
 // Twiddle tables exp(-2 pi i t / L), one per supported L, for one precision.
 template <typename R>

@@ -27,9 +27,9 @@
 
 namespace vie {
 
-int smallest_fft_length(int min_len) {
+int smallest_fft_length(int min_len, bool xy) {
   for (int L : kFftLengths)
-    if (L >= min_len) return L;
+    if (L >= min_len && !(xy && L == 36)) return L;
   return -1;
 }
 
@@ -941,8 +941,9 @@ __global__ void __launch_bounds__((3 * ZColGeo<R, LZ, V>::TZ * ZColGeo<R, LZ, V>
 }
 
 // ------------------------------------------------------------------ launchers
-#define VIE_L_CASES(F) \
-  F(1) F(2) F(3) F(4) F(6) F(8) F(12) F(16) F(24) F(32) F(48) F(64) F(96) F(128) F(192) F(256) F(384) F(512)
+#define VIE_L_CASES(F)                                                                                    \
+  F(1) F(2) F(3) F(4) F(6) F(8) F(12) F(16) F(24) F(32) F(36) F(48) F(64) F(72) F(96) F(128) F(144) F(192) F(256) \
+      F(288) F(384) F(512)
 
 [[noreturn]] static void bad_length(const char* what, int L) {
   throw std::runtime_error(std::string("unsupported FFT length for ") + what + ": " + std::to_string(L));

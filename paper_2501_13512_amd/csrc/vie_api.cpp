@@ -1614,8 +1614,8 @@ ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* blo
       pl.chi[i] = mk<double>(c.real(), c.imag());
     }
   }
-  pl.lx = vie::smallest_fft_length(2 * g.nx - 1);
-  pl.ly = vie::smallest_fft_length(2 * g.ny - 1);
+  pl.lx = vie::smallest_fft_length(2 * g.nx - 1, true);
+  pl.ly = vie::smallest_fft_length(2 * g.ny - 1, true);
   pl.lz = vie::smallest_fft_length(2 * g.nz - 1);
   if (pl.lx < 0 || pl.ly < 0 || pl.lz < 0) fail(VIE_EINVAL, "grid too large for the compiled FFT lengths");
   pl.k0 = 2.0 * M_PI / g.wavelength;
@@ -1667,7 +1667,7 @@ ProblemPlan make_plan(const vie_grid& g, const double* eps_r, const int32_t* blo
       if (cnt[k] == 0) continue;
       const int ex = hi[3 * k] - lo[3 * k] + 1, ey = hi[3 * k + 1] - lo[3 * k + 1] + 1,
                 ez = hi[3 * k + 2] - lo[3 * k + 2] + 1;
-      bylen[{vie::smallest_fft_length(2 * ex - 1), vie::smallest_fft_length(2 * ey - 1),
+      bylen[{vie::smallest_fft_length(2 * ex - 1, true), vie::smallest_fft_length(2 * ey - 1, true),
              vie::smallest_fft_length(2 * ez - 1)}]
           .push_back(k);
     }

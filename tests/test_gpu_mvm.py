@@ -17,7 +17,9 @@ from paper_2501_13512_amd import vie as V  # noqa: E402
 TOL = {V.VIE_FP64: 1e-12, V.VIE_MIXED: 1e-5}
 
 TINY = [(1, 1, 1), (2, 1, 1), (1, 3, 2), (3, 2, 5), (5, 5, 5), (6, 4, 3), (4, 6, 1)]
-MID = [(16, 16, 16), (17, 9, 5), (33, 20, 12), (24, 48, 7), (13, 21, 40), (64, 64, 32), (100, 3, 9)]
+MID = [(16, 16, 16), (17, 9, 5), (33, 20, 12), (24, 48, 7), (13, 21, 40), (64, 64, 32), (100, 3, 9),
+       # lengths 36 (z only), 72, 144 and 288
+       (18, 35, 10), (26, 9, 70), (34, 66, 12), (12, 8, 130), (130, 6, 6)]
 
 
 def _grid(case):

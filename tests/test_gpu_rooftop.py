@@ -24,7 +24,9 @@ TOL = {V.VIE_FP64: 1e-12, V.VIE_MIXED: 1e-5}
 
 # interior shapes (nz, ny, nx); the grids are one vacuum layer larger per side
 SMALL = [(1, 1, 1), (2, 1, 3), (3, 5, 4), (6, 5, 4), (4, 7, 2)]
-MID = [(16, 16, 16), (12, 20, 33), (7, 48, 24), (40, 21, 13), (30, 14, 14), (9, 3, 100), (32, 64, 64)]
+MID = [(16, 16, 16), (12, 20, 33), (7, 48, 24), (40, 21, 13), (30, 14, 14), (9, 3, 100), (32, 64, 64),
+       # lengths 36 (z only), 72, 144 and 288
+       (16, 33, 9), (24, 7, 68), (32, 10, 128)]
 
 
 def _case(seed, interior, fill=0.7):
