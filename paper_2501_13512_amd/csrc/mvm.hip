@@ -34,6 +34,11 @@ int smallest_fft_length(int min_len, bool xy) {
 }
 
 // ------------------------------------------------------------------ geometry
+constexpr int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p *= 2;
+  return p;
+}
 constexpr int pow2_floor(int v) {
   int p = 1;
   while (p * 2 <= v) p *= 2;
@@ -61,6 +66,14 @@ __device__ __forceinline__ bool sys_active(const int* status, int s) {
   return status == nullptr || status[s] == ST_ACTIVE;
 }
 
+// n / d by one multiply-high: m = ceil(2^32 / d) for d >= 2, m = 0 for d = 1.
+// With n = q d + r, n m / 2^32 = n / d + n (m - 2^32 / d) / 2^32 and the
+// second term is below n / 2^32, so the floor is q whenever n d < 2^32.
+// The plane kernels' element, row and plane indices stay far inside that
+// range (checked when they are launched).
+inline unsigned div_magic(int d) { return d <= 1 ? 0u : (unsigned)(((1ull << 32) + (unsigned)d - 1) / (unsigned)d); }
+__device__ __forceinline__ unsigned udiv_m(unsigned n, unsigned m) { return m ? __umulhi(n, m) : n; }
+
 template <typename R>
 __device__ __forceinline__ cx<R> czero() {
   return mk<R>(R(0), R(0));
@@ -79,6 +92,8 @@ struct RowArgs {
   const cx<R>* tw;
   int mask_input;
   int chi3;   // 1/chi per component ([3][nz][ny][nx]: rooftop faces) instead of per voxel
+  // division constants of the plane kernels (udiv_m): nx ny, nx, ny, nz
+  unsigned m_pe, m_nx, m_ny, m_nz;
   double scale;
   // BiCGSTAB work fused into pass 1 (in_mode) and pass 5 (out_mode)
   int in_mode, out_mode;
@@ -316,10 +331,11 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_fwd(RowArgs<
   const int padw = L - nx;
   for (int e = threadIdx.x; e < npl * ny * padw; e += BT) {
     const int row = e / padw, xx = nx + (e - row * padw);
-    lds[row / ny * L * LP + (row % ny) * LP + xx] = czero<R>();
+    const int q = (int)udiv_m((unsigned)row, a.m_ny);
+    lds[q * L * LP + (row - q * ny) * LP + xx] = czero<R>();
   }
   auto lds_at = [&](int e) -> cx<R>* {
-    const int q = e / pe, rem = e - q * pe, y = rem / nx;
+    const int q = (int)udiv_m((unsigned)e, a.m_pe), rem = e - q * pe, y = (int)udiv_m((unsigned)rem, a.m_nx);
     return lds + (q * L + y) * LP + (rem - y * nx);
   };
   if (mode == 0) {
@@ -328,8 +344,9 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_fwd(RowArgs<
     for (int e = threadIdx.x; e < ne; e += BT) {
       c128 v = a.x[v0 + e];
       if (msk) {
-        const int q = e / pe;
-        const int z = a.chi3 ? pl0 + q : (pl0 + q) % nz;
+        const int q = (int)udiv_m((unsigned)e, a.m_pe);
+        const int zq = pl0 + q;
+        const int z = a.chi3 ? zq : zq - nz * (int)udiv_m((unsigned)zq, a.m_nz);
         const c128 ci = chi[(int64_t)z * pe + (e - q * pe)];
         if (ci.x == 0.0 && ci.y == 0.0) v = mk<double>(0.0, 0.0);
       }
@@ -378,15 +395,19 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_fwd(RowArgs<
     }
   }
   __syncthreads();
-  // x transforms of the rows y < ny, in place
+  // x transforms of the rows y < ny, in place.  Consecutive lanes take
+  // consecutive rows (a row's threads are PP lanes apart), so the threads
+  // that a stage with fewer butterflies leaves idle form whole wavefronts,
+  // which skip it; the row stride LP keeps the lanes' LDS banks distinct.
   {
-    const int p = threadIdx.x / T, t = threadIdx.x - p * T;
+    const int p = threadIdx.x % PP, t = threadIdx.x / PP;
     const int nrows = npl * ny;
     for (int r0 = 0; r0 < nrows; r0 += PP) {
       const int row = r0 + p;
       const bool valid = p < PP && row < nrows;
       const int rr = valid ? row : 0;
-      cx<R>* slot = lds + (rr / ny * L + rr % ny) * LP;
+      const int rq = (int)udiv_m((unsigned)rr, a.m_ny);
+      cx<R>* slot = lds + (rq * L + (rr - rq * ny)) * LP;
       auto ld = [&](int n) -> cx<R> { return slot[n]; };
       auto st = [&](int k, cx<R> v) { slot[k] = v; };
       fft_pencil<R, L, T, -1, true, true>(ld, st, slot, 1, t, valid, a.tw);
@@ -448,15 +469,17 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_inv_local(Ro
       fft_pencil<R, L, T, +1, false, true>(ld, st, slot, LP, t, valid, a.tw);
     }
   }
-  // x inverse of the rows y < ny, in place, cropped to nx
+  // x inverse of the rows y < ny, in place, cropped to nx (lanes over rows
+  // as in the forward kernel)
   {
-    const int p = threadIdx.x / T, t = threadIdx.x - p * T;
+    const int p = threadIdx.x % PP, t = threadIdx.x / PP;
     const int nrows = npl * ny;
     for (int r0 = 0; r0 < nrows; r0 += PP) {
       const int row = r0 + p;
       const bool valid = p < PP && row < nrows;
       const int rr = valid ? row : 0;
-      cx<R>* slot = lds + (rr / ny * L + rr % ny) * LP;
+      const int rq = (int)udiv_m((unsigned)rr, a.m_ny);
+      cx<R>* slot = lds + (rq * L + (rr - rq * ny)) * LP;
       auto ld = [&](int n) -> cx<R> { return slot[n]; };
       auto st = [&](int k, cx<R> v) {
         if (k < nx) slot[k] = v;
@@ -476,8 +499,8 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_inv_local(Ro
     for (int u = 0; u < CH; ++u) {
       const int e = e0 + u * BT + (int)threadIdx.x;
       if (e < ne) {
-        const int q = e / pe;
-        ci[u] = chi[(int64_t)(a.chi3 ? pl0 + q : (pl0 + q) % nz) * pe + (e - q * pe)];
+        const int q = (int)udiv_m((unsigned)e, a.m_pe), zq = pl0 + q;
+        ci[u] = chi[(int64_t)(a.chi3 ? zq : zq - nz * (int)udiv_m((unsigned)zq, a.m_nz)) * pe + (e - q * pe)];
         xv[u] = a.x[v0 + e];
         if (mode == 1 || mode == 3) ov[u] = a.rhat[v0 + e];
         if (mode == 2 || mode == 4) ov[u] = a.s[v0 + e];
@@ -487,7 +510,7 @@ __global__ void __launch_bounds__((PlaneGeo<R, L, PV>::BT)) k_plane_inv_local(Ro
     for (int u = 0; u < CH; ++u) {
       const int e = e0 + u * BT + (int)threadIdx.x;
       if (e < ne) {
-        const int q = e / pe, rem = e - q * pe, y = rem / nx;
+        const int q = (int)udiv_m((unsigned)e, a.m_pe), rem = e - q * pe, y = (int)udiv_m((unsigned)rem, a.m_nx);
         const cx<R> qv = lds[(q * L + y) * LP + (rem - y * nx)];
         c128 out = mk<double>(0.0, 0.0);
         if (mode == 3)   // field at every voxel: E_inc + sum T P
@@ -636,13 +659,18 @@ __device__ __forceinline__ int mirror_paired_row(int i, int L) {
 // per column and component, PF: spectrum values loaded into registers
 // before the data (their latency overlaps the forward transform).
 //   0: wide tiles (up to 1024 threads), max_butterflies threads per column
-//   2: wide tiles, min_butterflies threads per column, prefetch
+//   2: wide tiles, min_butterflies rounded up to a power of two threads per
+//      column, prefetch (for L = 48: 4 threads, so a 16-column tile of the
+//      three components fills three whole wavefronts and each thread takes
+//      four radix-3 butterflies, where 3 threads leave a quarter of the
+//      third wavefront idle and take six butterflies, the last for one
+//      thread in three)
 //   3: one cache line of columns, min_butterflies threads, prefetch
 //   4: one cache line of columns, max_butterflies threads
 template <typename R, int LZ, int V>
 struct ZColGeo {
   static constexpr int T = PlanInfo<LZ>::max_butterflies;
-  static constexpr int TB = PlanInfo<LZ>::min_butterflies;
+  static constexpr int TB = V == 2 ? cmin(T, pow2_ceil(PlanInfo<LZ>::min_butterflies)) : PlanInfo<LZ>::min_butterflies;
   static constexpr int ES = (int)sizeof(cx<R>);
   static constexpr int LDS_ZP = cmax(1, (144 * 1024) / (3 * LZ * ES));
   static constexpr int LINE = cmax(1, pow2_floor(cmin(LDS_ZP, 128 / ES)));
@@ -1076,6 +1104,11 @@ static void launch_plane_pv(bool fwd, const RowArgs<R>& a, int nsys, hipStream_t
 template <typename R>
 static void launch_plane(bool fwd, int L, int pv, const RowArgs<R>& a, int nsys, hipStream_t s) {
   if (pv < 0 || pv >= kPlaneVariants) throw std::runtime_error("plane variant out of range");
+  // udiv_m's range: element indices below 16 nx ny planes' worth, row
+  // indices below 16 ny, plane indices below 3 nz
+  const uint64_t pe = (uint64_t)a.nx * (uint64_t)a.ny;
+  if (16 * pe * pe >= (1ull << 32) || 16 * (uint64_t)a.ny * a.ny >= (1ull << 32) || 3 * (uint64_t)a.nz * a.nz >= (1ull << 32))
+    throw std::runtime_error("plane pass: box too large for its index arithmetic");
   switch (L) {
 #define C(l)                                                 \
   case l: {                                                  \
@@ -1119,6 +1152,10 @@ static RowArgs<R> row_args(const MvmBatch<R>& b, const KBatch* k, const FuseArgs
   ra.tw = b.tw->table[b.lx];
   ra.mask_input = mask_input ? 1 : 0;
   ra.chi3 = b.rooftop;
+  ra.m_pe = div_magic(b.nx * b.ny);
+  ra.m_nx = div_magic(b.nx);
+  ra.m_ny = div_magic(b.ny);
+  ra.m_nz = div_magic(b.nz);
   ra.scale = 1.0 / ((double)b.lx * (double)b.ly * (double)b.lz);
   ra.r = f.r;
   ra.p = f.p;
