@@ -137,7 +137,11 @@ typedef enum {
 } vie_solver;
 
 /* vie_opts.flags: run the inner block iterations as individual kernel
- * launches instead of a captured HIP graph (same kernels, same results). */
+ * launches instead of a captured HIP graph (same kernels, same results).
+ * Without it, block groups whose products transform at least 2^21 points
+ * per inner step (systems x 3 x padded box) are launched one by one anyway
+ * (their steps outlast the host's launches, and a graph replay's start and
+ * end cost more); smaller groups replay the captured step. */
 #define VIE_FLAG_NO_GRAPHS 1
 /* vie_opts.flags: solve every block with the batched multi-workgroup
  * kernels, also blocks small enough for the one-workgroup block solver

@@ -288,6 +288,9 @@ void k_update_xr(const KBatch& k, c128* x, const c128* y, const c128* z, c128* r
 // The half-step test and omega (FIN_SOMEGA) formed in every workgroup of the
 // x, r update from the second product's partials; r's partials go to the
 // second buffer (the first is still being read by other workgroups).
+// ZS: z and s are one vector (the unpreconditioned steps of the inner
+// solves), loaded once.
+template <bool ZS>
 __global__ void __launch_bounds__(KT) kk_update_xr_fused(KBatch k, c128* x, const c128* y, const c128* z, c128* r,
                                                          const c128* sv, const c128* t, const c128* rhat) {
   const int64_t n = k.n;
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(KT) kk_update_xr_fused(KBatch k, c128* x, cons
         xv[j] = x[base + i];
         yv[j] = y[base + i];
         zv[j] = z[base + i];
-        sw[j] = sv[base + i];
+        if constexpr (!ZS) sw[j] = sv[base + i];
         tv[j] = t[base + i];
         hv[j] = rhat[base + i];
       }
@@ -355,7 +358,7 @@ __global__ void __launch_bounds__(KT) kk_update_xr_fused(KBatch k, c128* x, cons
       const int64_t i = i0 + (int64_t)(h * HE + j) * KT;
       if (i < n) {
         x[base + i] = xv[j] + alpha * yv[j] + omega * zv[j];
-        const c128 rv = sw[j] - omega * tv[j];
+        const c128 rv = (ZS ? zv[j] : sw[j]) - omega * tv[j];
         r[base + i] = rv;
         const c128 d = cdot1(hv[j], rv);
         acc[0] += d.x;
@@ -371,8 +374,12 @@ void k_update_xr_fused(const KBatch& k, c128* x, const c128* y, const c128* z, c
                        const c128* t, const c128* rhat, hipStream_t s) {
   if (!k.partials2) throw std::runtime_error("fused x, r update: no second partial buffer");
   const int64_t chunks = chunks_of(k.n);
-  hipLaunchKernelGGL(kk_update_xr_fused, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, y, z, r, sv, t,
-                     rhat);
+  if (z == sv)
+    hipLaunchKernelGGL(kk_update_xr_fused<true>, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, y, z, r,
+                       sv, t, rhat);
+  else
+    hipLaunchKernelGGL(kk_update_xr_fused<false>, dim3((unsigned)(chunks * k.nsys)), dim3(KT), 0, s, k, x, y, z, r,
+                       sv, t, rhat);
   check_launch("krylov xr (fused)");
 }
 

@@ -664,6 +664,18 @@ hipGraphExec_t group_graph(vie_problem& P, Group& G) {
   return ex;
 }
 
+// A captured step spares the host its launches, but each replay's start and
+// end cost the GPU more than the gaps between kernels launched one by one.
+// Groups whose products transform at least 2^21 points per step keep the GPU
+// busy long enough for the host to launch the step's kernels ahead of it, so
+// they launch them one by one (the metasurface's pillar and slab groups:
+// 2.27 against 2.36 s per mixed solve, same results); smaller groups replay
+// the captured step.
+constexpr int64_t kEagerStepPoints = int64_t(1) << 21;
+bool replay_step(const Group& G) {
+  return (int64_t)G.nsys * 3 * G.lx * G.ly * G.lz < kEagerStepPoints;
+}
+
 template <typename R>
 vie::BlockSolveArgs wg_args(vie_problem& P, Group& G, const int* gate, double tol, int maxit) {
   vie::BlockSolveArgs a{};
@@ -748,7 +760,8 @@ void precond_apply(vie_problem& P, const c128* w, c128* y, double tol, int maxit
     std::vector<Run> runs;
     for (size_t gi : bg) {
       hipStream_t gs = split ? P.branches.streams[gi] : s;
-      runs.push_back(Run{gi, gs, graphs ? group_graph<R>(P, P.groups[gi]) : nullptr, Poller(P, gs, 1 + (int)gi),
+      runs.push_back(Run{gi, gs, graphs && replay_step(P.groups[gi]) ? group_graph<R>(P, P.groups[gi]) : nullptr,
+                         Poller(P, gs, 1 + (int)gi),
                          true});
     }
     for (int it = 1; it <= maxit; ++it) {

@@ -161,6 +161,37 @@ def test_zpass_variants_agree(vie_ctx, shape, prec):
         P.close()
 
 
+@pytest.mark.parametrize("prec", [V.VIE_FP64, V.VIE_MIXED])
+@pytest.mark.parametrize("shape", ZSHAPES)
+def test_column_zpass_variants_bitwise(vie_ctx, shape, prec):
+    """The column-set z-pass variants (0, 2, 3, 4) differ only in which
+    thread takes which butterfly and which z fold of the multiply: their
+    full-grid and block-diagonal products are equal bit for bit, so the
+    autotuner's choice among them leaves iterates and step counts as they
+    are."""
+    seed = 7100 + shape[0]
+    case = W.random_tiny(seed, shape, fill=0.8, n_blocks=3)
+    x = _rand(seed, case.shape)
+    P = V.Problem(_grid(case), case.eps, case.block_id, case.n_blocks, ctx=vie_ctx)
+    try:
+        xd = torch.from_numpy(x).cuda()
+        outs = {}
+        for v in (0, 2, 3, 4):
+            V.vie_problem_set_zpass(P.handle, prec, v)
+            yd = torch.full_like(xd, complex("nan"))
+            V.vie_matvec(P.handle, prec, xd, yd)
+            bd = torch.full_like(xd, complex("nan"))
+            V.vie_block_matvec(P.handle, prec, xd, bd)
+            torch.cuda.synchronize()
+            outs[v] = (yd.cpu().numpy(), bd.cpu().numpy())
+        V.vie_problem_set_zpass(P.handle, prec, -1)
+        for v in (2, 3, 4):
+            for k in range(2):
+                assert np.array_equal(outs[v][k], outs[0][k]), (v, k)
+    finally:
+        P.close()
+
+
 def test_pinned_zpass_preconditioned_solve(vie_ctx):
     """Pinned z-pass variants inside gated batched inner solves (blocks that
     converge at different steps are skipped) and the outer product: same
