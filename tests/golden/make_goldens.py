@@ -36,6 +36,10 @@ Runs (the case is 128x128x32 at lambda/40, 64 pillar blocks + slab):
                   3e-2), capped at 3 outer steps: the residual after every
                   step and the inner step counts of every application
                   (``oracle_plasmonic_first.json``, no field).
+* ``plasmonic_small_tight``  the reduced plasmonic cell (48x48x32, 2x2
+                  spheres), FP64 without preconditioner to 1e-8: E_tot at
+                  every voxel of the cell, complex128
+                  (``oracle_plasmonic_small_tight_etot.npy``).
 
 BLAS is held to one thread so inner products are summed in a fixed order
 (the results do not depend on the machine's core count); ``--workers`` only
@@ -75,6 +79,8 @@ RUNS = {
     "mixed_pad4": dict(kind="mixed", prec=True, tol=BENCH_TOL, pad=4),
     "bench_fp64": dict(kind="fp64", prec=True, tol=BENCH_TOL, pad=0),
     "plasmonic_first": dict(kind="fp64", prec=True, tol=None, pad=0, maxit=3, case="plasmonic", field=False),
+    "plasmonic_small_tight": dict(kind="fp64", prec=False, tol=1e-8, maxit=20000, pad=0, case="plasmonic_small",
+                                  exact=True),
 }
 
 
@@ -128,7 +134,8 @@ def run(name: str) -> dict:
                  relres_true=sol.relres_true, true_history=sol.true_history)
     if spec.get("field", True):
         f = scatterer_values(g, sol.E_tot)
-        np.save(path(name, "npy"), f if name == "tight" else f.astype(np.complex64), allow_pickle=False)
+        exact = spec.get("exact", name == "tight")
+        np.save(path(name, "npy"), f if exact else f.astype(np.complex64), allow_pickle=False)
     return d
 
 

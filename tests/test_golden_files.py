@@ -51,3 +51,16 @@ def test_metasurface_reference_files_agree():
     assert ec.dtype == np.complex64
     assert sp["rel_field_diff"]["case|tight"] == pytest.approx(_rel(ec, et), rel=1e-3)
     assert 0 < sp["rel_field_diff"]["case|case_pad4"] < 1e-4
+
+
+def test_plasmonic_small_reference_file():
+    """The reduced plasmonic cell's plain FP64 oracle solve (the reference of
+    the GPU's flexible-GMRES block-preconditioned solves): converged to 1e-8,
+    E_tot at every voxel of the cell, complex128."""
+    case = W.plasmonic_small()
+    n_s = int(np.count_nonzero(case.eps != 1.0))
+    meta = json.load(open(os.path.join(HERE, "oracle_plasmonic_small_tight.json")))
+    assert meta["status"] == "converged" and meta["history"][-1] <= 1e-8 and not meta["precondition"]
+    e = np.load(os.path.join(HERE, "oracle_plasmonic_small_tight_etot.npy"), allow_pickle=False)
+    assert e.shape == (3, n_s) and e.dtype == np.complex128
+    assert np.isfinite(e).all() and np.linalg.norm(e) == pytest.approx(meta["etot_norm"], rel=1e-12)
